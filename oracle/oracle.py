@@ -1,0 +1,300 @@
+"""CPU oracle for the Monte Carlo DtN walk estimator (arXiv 2606.05581).
+
+TEST INFRASTRUCTURE ONLY: the plain FP64 reference that the GPU library is
+checked against. Only the tests, the smoke check and the CPU-baseline leg of
+the benchmark may import it; the GPU product path never does.
+
+The walks run in ``oracle.c`` (built to ``liboracle.so`` with gcc); this file
+binds it and adds the dense post-processing steps, each written from its
+definition:
+
+* ``finalize`` -- Alg. 1's scaling of the accumulated rank-one updates by
+  |dOmega| / (N h) (Sec. 3.1), here per row i as w_i / (h W), and the sample
+  standard error of every entry;
+* ``symmetrise`` -- Alg. 1's last step S <- (S + S^T) / 2;
+* ``steklov_modes`` -- the Steklov eigenproblem (Sec. 2, eq.
+  steklov-eigenproblem) discretised with a lumped mass M = diag(w): the
+  smallest k eigenpairs of M^-1/2 (S + S^T)/2 M^-1/2 by LAPACK (numpy.eigh),
+  eigenvectors mapped back by M^-1/2.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# walk status codes
+HIT, ESCAPED, CAPPED = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (no fused multiply-adds, OpenMP over rows)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _P(t):
+    return C.POINTER(t)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        L.orc_philox4x32_10.argtypes = [_P(C.c_uint32), _P(C.c_uint32), _P(C.c_uint32)]
+        L.orc_uniform.argtypes = [C.c_uint32]
+        L.orc_uniform.restype = C.c_double
+        L.orc_closest_tri.argtypes = [_P(C.c_double)] * 5
+        L.orc_closest_tri.restype = C.c_double
+        L.orc_closest_tri_f32.argtypes = [_P(C.c_float)] * 5
+        L.orc_closest_tri_f32.restype = C.c_float
+        L.orc_scene_frame.argtypes = [_P(C.c_float), C.c_int64, _P(C.c_double), _P(C.c_double)]
+        L.orc_scene_create.argtypes = [_P(C.c_float), C.c_int64, _P(C.c_int32), C.c_int64, C.c_int]
+        L.orc_scene_create.restype = C.c_void_p
+        L.orc_scene_destroy.argtypes = [C.c_void_p]
+        L.orc_scene_info.argtypes = [C.c_void_p, _P(C.c_double), _P(C.c_double)]
+        L.orc_nearest.argtypes = [C.c_void_p, _P(C.c_double), C.c_int64, C.c_int, _P(C.c_int64),
+                                  _P(C.c_double), _P(C.c_double)]
+        L.orc_nearest_f32.argtypes = [_P(C.c_float), _P(C.c_int32), C.c_int64, _P(C.c_float), C.c_int64,
+                                      _P(C.c_int32), _P(C.c_float), _P(C.c_float)]
+        L.orc_reentry_mu.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_reentry_mu.restype = C.c_double
+        L.orc_walks_from.argtypes = [C.c_void_p, _P(C.c_double), C.c_int64, C.c_double, C.c_double, C.c_double,
+                                     C.c_int64, C.c_uint64, _P(C.c_int32), _P(C.c_int64), _P(C.c_double),
+                                     _P(C.c_int64)]
+        L.orc_estimate.argtypes = (
+            [C.c_void_p, C.c_int, C.c_int, C.c_int64, _P(C.c_int32)]
+            + [_P(C.c_float), _P(C.c_float), _P(C.c_int32), _P(C.c_float)]
+            + [_P(C.c_int32), _P(C.c_int32), _P(C.c_double), _P(C.c_float)]
+            + [_P(C.c_int32), _P(C.c_int32), _P(C.c_float), C.c_int64]
+            + [C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_uint64,
+               C.c_uint32, C.c_int]
+            + [_P(C.c_double), _P(C.c_double), _P(C.c_int64), _P(C.c_int64), _P(C.c_int64), _P(C.c_int32)]
+            + [_P(C.c_int32), _P(C.c_int64), _P(C.c_float), _P(C.c_int64), _P(C.c_int32), _P(C.c_float)]
+        )
+        _lib = L
+    return _lib
+
+
+def _ptr(a, t):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_P(t))
+
+
+def _c(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+# ----------------------------------------------------------------- primitives
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block (Salmon et al., SC 2011) of a 4-word counter and 2-word key."""
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(o, C.c_uint32))
+    return o
+
+
+def uniform(r):
+    return lib().orc_uniform(int(r))
+
+
+def closest_tri(p, a, b, c):
+    """FP64 squared distance from p to triangle abc and the closest point's barycentrics."""
+    args = [np.ascontiguousarray(x, dtype=np.float64) for x in (p, a, b, c)]
+    l = np.zeros(3)
+    d2 = lib().orc_closest_tri(*[_ptr(x, C.c_double) for x in args], _ptr(l, C.c_double))
+    return d2, l
+
+
+def closest_tri_f32(p, a, b, c):
+    args = [np.ascontiguousarray(x, dtype=np.float32) for x in (p, a, b, c)]
+    l = np.zeros(2, dtype=np.float32)
+    d2 = lib().orc_closest_tri_f32(*[_ptr(x, C.c_float) for x in args], _ptr(l, C.c_float))
+    return np.float32(d2), l
+
+
+def reentry_mu(rho, R, u):
+    return lib().orc_reentry_mu(float(rho), float(R), float(u))
+
+
+def scene_frame(V):
+    V = _c(V, np.float32)
+    c = np.zeros(3)
+    r = np.zeros(1)
+    lib().orc_scene_frame(_ptr(V, C.c_float), V.shape[0], _ptr(c, C.c_double), _ptr(r, C.c_double))
+    return c, float(r[0])
+
+
+class Scene:
+    """Mesh in the oracle's FP64 scene frame (optionally with a BVH that
+    returns exactly the brute-force minimum)."""
+
+    def __init__(self, V, F, bvh: bool = True):
+        self.V = _c(V, np.float32)
+        self.F = _c(F, np.int32)
+        self.h = lib().orc_scene_create(_ptr(self.V, C.c_float), self.V.shape[0], _ptr(self.F, C.c_int32),
+                                        self.F.shape[0], int(bvh))
+        c = np.zeros(3)
+        r = np.zeros(1)
+        lib().orc_scene_info(self.h, _ptr(c, C.c_double), _ptr(r, C.c_double))
+        self.centre, self.radius = c, float(r[0])
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_scene_destroy(self.h)
+            self.h = None
+
+    def nearest(self, Q, bvh: bool = True):
+        Q = _c(Q, np.float64).reshape(-1, 3)
+        n = Q.shape[0]
+        tri = np.zeros(n, dtype=np.int64)
+        d2 = np.zeros(n)
+        bary = np.zeros((n, 3))
+        lib().orc_nearest(self.h, _ptr(Q, C.c_double), n, int(bvh), _ptr(tri, C.c_int64), _ptr(d2, C.c_double),
+                          _ptr(bary, C.c_double))
+        return tri, d2, bary
+
+    def rel32(self, X):
+        """World points to float offsets from the scene centre (the single-precision frame)."""
+        return (np.asarray(X, dtype=np.float64) - self.centre).astype(np.float32)
+
+    def nearest_f32(self, Q):
+        """Brute-force FP32 nearest triangle (index, d2, barycentrics of vertices 1, 2)."""
+        Vr = self.rel32(self.V.astype(np.float64))
+        Qr = np.ascontiguousarray(self.rel32(np.asarray(Q).reshape(-1, 3)))
+        n = Qr.shape[0]
+        tri = np.zeros(n, dtype=np.int32)
+        d2 = np.zeros(n, dtype=np.float32)
+        b = np.zeros((n, 2), dtype=np.float32)
+        lib().orc_nearest_f32(_ptr(Vr, C.c_float), _ptr(self.F, C.c_int32), self.F.shape[0], _ptr(Qr, C.c_float),
+                              n, _ptr(tri, C.c_int32), _ptr(d2, C.c_float), _ptr(b, C.c_float))
+        return tri, d2, b
+
+    def walks_from(self, X, eps, seed=0, kappa=2.0 ** -20, delta_rel=2.0 ** -21, max_steps=100000):
+        """Walk-on-Spheres from world points X: (status, terminal triangle, barycentrics, queries)."""
+        X = _c(X, np.float64).reshape(-1, 3)
+        n = X.shape[0]
+        st = np.zeros(n, dtype=np.int32)
+        tri = np.zeros(n, dtype=np.int64)
+        bary = np.zeros((n, 3))
+        nq = np.zeros(n, dtype=np.int64)
+        lib().orc_walks_from(self.h, _ptr(X, C.c_double), n, eps, kappa, delta_rel * self.radius, max_steps,
+                             C.c_uint64(seed), _ptr(st, C.c_int32), _ptr(tri, C.c_int64), _ptr(bary, C.c_double),
+                             _ptr(nq, C.c_int64))
+        return st, tri, bary, nq
+
+    def hit_points(self, tri, bary):
+        """World-space positions of (triangle, barycentric) pairs."""
+        P = np.einsum("ij,ijk->ik", bary, self.V.astype(np.float64)[self.F[tri]])
+        return P
+
+
+DEFAULT_MAX_STEPS = {"interior": 1024, "exterior": 8192}
+
+
+def estimate(scene: Scene, rows, basis, walks: int, eps: float, h: float, exterior: bool, seed: int = 0,
+             w0: int = 0, rows_sel=None, kappa=2.0 ** -20, delta_rel=2.0 ** -21, max_steps=None, mesh: int = 0,
+             log: bool = False, nthreads: int = 1):
+    """Accumulate the naive estimator's per-walk contributions c = b(s) - b(t).
+
+    Returns a dict with ``acc`` (sum of c), ``acc2`` (sum of c^2), each
+    (n_rows_selected, K), per-row query / escape / capped counts, discard
+    flags and (optionally) a walk log of status, terminal triangle,
+    barycentrics of the terminal triangle's second and third vertices, query
+    count, start triangle and start barycentrics (second and third vertices).
+    """
+    if max_steps is None:
+        max_steps = DEFAULT_MAX_STEPS["exterior" if exterior else "interior"]
+    mode = 0 if rows.mode == "point" else 1
+    sel = None if rows_sel is None else np.ascontiguousarray(rows_sel, dtype=np.int32)
+    n = rows.n_rows if sel is None else sel.shape[0]
+    K = int(basis.K)
+    acc = np.zeros((n, K))
+    acc2 = np.zeros((n, K))
+    nq = np.zeros(n, dtype=np.int64)
+    nesc = np.zeros(n, dtype=np.int64)
+    ncap = np.zeros(n, dtype=np.int64)
+    disc = np.zeros(n, dtype=np.int32)
+    if log:
+        ls = np.zeros((n, walks), dtype=np.int32)
+        lt = np.zeros((n, walks), dtype=np.int64)
+        lb = np.zeros((n, walks, 2), dtype=np.float32)
+        lq = np.zeros((n, walks), dtype=np.int64)
+        lst = np.zeros((n, walks), dtype=np.int32)
+        lsb = np.zeros((n, walks, 2), dtype=np.float32)
+    else:
+        ls = lt = lb = lq = lst = lsb = None
+    p, nn, tri, bary = (_c(rows.p, np.float32), _c(rows.n, np.float32), _c(rows.tri, np.int32),
+                        _c(rows.bary, np.float32))
+    rp, rt, rc, fn = (_c(rows.ring_ptr, np.int32), _c(rows.ring_tri, np.int32), _c(rows.ring_cum, np.float64),
+                      _c(rows.fn, np.float32))
+    brp, bc, bv = _c(basis.rowptr, np.int32), _c(basis.col, np.int32), _c(basis.val, np.float32)
+    lib().orc_estimate(
+        scene.h, mode, int(exterior), n, _ptr(sel, C.c_int32),
+        _ptr(p, C.c_float), _ptr(nn, C.c_float), _ptr(tri, C.c_int32), _ptr(bary, C.c_float),
+        _ptr(rp, C.c_int32), _ptr(rt, C.c_int32), _ptr(rc, C.c_double), _ptr(fn, C.c_float),
+        _ptr(brp, C.c_int32), _ptr(bc, C.c_int32), _ptr(bv, C.c_float), K,
+        walks, w0, eps, h, kappa, delta_rel * scene.radius, max_steps, C.c_uint64(seed), mesh, nthreads,
+        _ptr(acc, C.c_double), _ptr(acc2, C.c_double), _ptr(nq, C.c_int64), _ptr(nesc, C.c_int64),
+        _ptr(ncap, C.c_int64), _ptr(disc, C.c_int32),
+        _ptr(ls, C.c_int32), _ptr(lt, C.c_int64), _ptr(lb, C.c_float), _ptr(lq, C.c_int64),
+        _ptr(lst, C.c_int32), _ptr(lsb, C.c_float))
+    out = dict(acc=acc, acc2=acc2, n_query=nq, n_escaped=nesc, n_capped=ncap, discarded=disc, walks=walks)
+    if log:
+        out.update(log_status=ls, log_tri=lt, log_bary=lb, log_nquery=lq, log_stri=lst, log_sbary=lsb)
+    return out
+
+
+# ----------------------------------------------------------- dense post-steps
+
+
+def finalize(acc, acc2, w, h, W, discarded=None):
+    """Row i of the estimate: S_i = w_i / (h W) * sum_w c_w (Alg. 1's |dOmega|/(N h)
+    weight, stratified by row), and the standard error of each entry's mean,
+    se_ij = (w_i / h) * sqrt(var_ij / W) with the unbiased sample variance."""
+    w = np.asarray(w, dtype=np.float64).copy()
+    if discarded is not None:
+        w[np.asarray(discarded) != 0] = 0.0
+    mean = acc / W
+    var = np.maximum(0.0, (acc2 / W - mean ** 2)) * (W / (W - 1.0))
+    S = (w / h)[:, None] * mean
+    se = (w / h)[:, None] * np.sqrt(var / W)
+    return S, se
+
+
+def symmetrise(S):
+    """Alg. 1, last step: S <- (S + S^T) / 2."""
+    return 0.5 * (S + S.T)
+
+
+def steklov_modes(S, w, k):
+    """Smallest-k eigenpairs of the generalised problem (S+S^T)/2 psi = lambda M psi, M = diag(w).
+
+    Rows with zero weight (discarded samples) are removed first. Returns
+    (eigenvalues ascending, eigenvectors psi (n_kept, k), kept row indices).
+    """
+    w = np.asarray(w, dtype=np.float64)
+    keep = np.nonzero(w > 0)[0]
+    Ss = symmetrise(S[np.ix_(keep, keep)])
+    m = 1.0 / np.sqrt(w[keep])
+    Cm = m[:, None] * Ss * m[None, :]
+    lam, V = np.linalg.eigh(Cm)
+    k = min(k, lam.shape[0])
+    return lam[:k], m[:, None] * V[:, :k], keep

@@ -1,0 +1,275 @@
+/*
+ * msk.h -- C ABI of the MI355X Monte Carlo Steklov (DtN) walk library.
+ *
+ * The library estimates the discrete Dirichlet-to-Neumann (Steklov) operator
+ * of a triangle mesh with the naive finite-difference estimator of
+ * "Monte Carlo Steklov Operators for Large-Scale Geometry Processing in the
+ * Wild" (arXiv 2606.05581), Sec. 3.1, Alg. 1: for every boundary row i, W
+ * Walk-on-Spheres walks start at an inset point x = s -/+ h n_s, stop in an
+ * eps-shell of the surface (Sec. 2, "Walk-on-Spheres") at t, and add
+ * c = b(s) - b(t) to row i (eqs. finite-difference-estimator,
+ * naive-stiffness-matrix), b being barycentric interpolation of a per-vertex
+ * basis table (Sec. 3.4). Both the interior operator and the exterior one
+ * (Sec. 3.3, "Escape to Infinity": a walk hits the surface or escapes) are
+ * estimated. The smallest Steklov eigenpairs (Sec. 2, eq.
+ * steklov-eigenproblem) are read off the symmetrised estimate (Alg. 1, last
+ * step).
+ *
+ * Conventions common to every entry point:
+ *   - Every function returns msk_status; nothing throws across the ABI. On
+ *     failure the context keeps a message readable with msk_last_error().
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the context's device (e.g. a torch CUDA tensor's
+ *     data_ptr()). Host inputs are copied before the call returns; device
+ *     pointers are borrowed for the duration of the call only.
+ *   - Arrays are dense and row-major; float = IEEE binary32, double = binary64.
+ *   - All GPU work runs in order on the context's stream (the stream handed
+ *     to msk_create, or the null stream). Calls are synchronous: results are
+ *     complete when they return.
+ *   - Handles (msk_mesh, msk_rows, msk_basis, msk_dtn) belong to the context
+ *     that created them and must be destroyed before it.
+ */
+#ifndef MSK_H
+#define MSK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MSK_OK = 0,
+  MSK_ERR_INVALID_ARG = 1, /* bad pointer, size, index, NaN/Inf input ...   */
+  MSK_ERR_OOM = 2,         /* device or host allocation failed               */
+  MSK_ERR_DEVICE = 3,      /* a HIP call failed; the message carries its text */
+  MSK_ERR_NOT_CONVERGED = 4, /* eigen step: partial results are returned     */
+  MSK_ERR_NUMERIC = 5      /* a non-finite value was produced                */
+} msk_status;
+
+typedef struct msk_ctx msk_ctx;
+typedef struct msk_mesh msk_mesh;
+typedef struct msk_rows msk_rows;
+typedef struct msk_basis msk_basis;
+typedef struct msk_dtn msk_dtn;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`. `hip_stream` is a hipStream_t (or
+ * NULL for the null stream) on which all work of this context is queued; the
+ * caller keeps ownership of it. */
+msk_status msk_create(int device, void* hip_stream, msk_ctx** out);
+void msk_destroy(msk_ctx* ctx);
+/* Message of the last failed call on this context ("" if none). The string
+ * stays valid until the next call on the context. */
+const char* msk_last_error(const msk_ctx* ctx);
+
+/* ------------------------------------------------------------------- mesh */
+
+typedef struct {
+  int32_t leaf_size; /* triangles per BVH leaf, 1..8 (default 4)            */
+  int32_t top_nodes; /* BVH nodes cached in LDS per workgroup, 0..128 (def. 85) */
+} msk_bvh_opts;
+
+typedef struct {
+  double centre[3];  /* scene frame: centre of the FP64 bounding box         */
+  double radius;     /* bounding-sphere radius about centre, (1+2^-20) max|v-c| */
+  double area;       /* total surface area (FP64)                            */
+  int64_t n_verts, n_tris, n_nodes;
+  int64_t node_bytes, tri_bytes;
+  int32_t depth, leaf_size;
+} msk_mesh_info;
+
+/* Build the walk geometry of a triangle mesh (Sec. 4: every triangle is an
+ * absorbing boundary element; soups, overlaps and non-manifold parts are
+ * accepted as they are, Appendix A).
+ *   V: host, n_verts x 3 float, world coordinates.
+ *   F: host, n_tris x 3 int32 vertex indices (an unindexed soup is the case
+ *      F = [[0,1,2],[3,4,5],...]).
+ * Coordinates are re-expressed as float offsets from the bounding-box centre
+ * (computed in FP64). A 4-wide BVH (binned surface-area heuristic) is built
+ * on the host and uploaded. Errors: INVALID_ARG for NaN/Inf coordinates,
+ * out-of-range indices, n_tris < 1 or zero total area; zero-area triangles
+ * are kept (they still absorb walks). Free with msk_mesh_destroy. */
+msk_status msk_build_bvh(msk_ctx* ctx, const float* V, int64_t n_verts, const int32_t* F, int64_t n_tris,
+                         const msk_bvh_opts* opts /* NULL = defaults */, msk_mesh** out);
+msk_status msk_mesh_get_info(const msk_mesh* mesh, msk_mesh_info* info);
+void msk_mesh_destroy(msk_mesh* mesh);
+
+/* Exact nearest triangle of each query point (Sec. 2, "Walk-on-Spheres": the
+ * empty-ball radius and the nearest boundary point). The decision is taken in
+ * single precision: queries are re-expressed as float offsets from the scene
+ * centre, the squared distance to every triangle follows one fixed FP32
+ * closest-point evaluation, and the answer is the minimum of (squared
+ * distance, original triangle index) in lexicographic order -- the same
+ * triangle a brute-force FP32 scan returns.
+ *   Q:    device, nq x 3 float, world coordinates.
+ *   tri:  device, nq int32, original triangle index (row of F).
+ *   d2:   device, nq float, squared distance.
+ *   bary: device, nq x 2 float, barycentric weights of the triangle's second
+ *         and third vertex at the closest point (first = 1 - sum). */
+msk_status msk_closest_points(msk_ctx* ctx, const msk_mesh* mesh, const float* Q, int64_t nq, int32_t* tri,
+                              float* d2, float* bary);
+
+/* -------------------------------------------------------- rows and basis */
+
+typedef enum {
+  MSK_ROWS_POINT = 0,   /* row i = fixed boundary sample s_i (Alg. 1's s)     */
+  MSK_ROWS_HAT_RING = 1 /* row i = vertex i; each walk draws s ~ phi_i / A_i  */
+} msk_rows_mode;
+
+/* Boundary rows of an estimate. All pointers are host memory.
+ * MSK_ROWS_POINT: p (n_rows x 3 float, world), n (n_rows x 3 float, unit
+ *   outward normal), tri (n_rows int32 face index), bary (n_rows x 3 float,
+ *   barycentrics of p in that face).
+ * MSK_ROWS_HAT_RING (n_rows = number of vertices): ring_ptr (n_rows+1
+ *   int32), ring_tri (ring_ptr[n_rows] int32, faces around each vertex),
+ *   ring_cum (same length, double, running sum of face areas within each
+ *   ring), face_normals (n_tris x 3 float, unit outward).
+ * w: n_rows double quadrature weight of each row (|dOmega|/N for point rows,
+ *   the one-ring area / 3 for hat rows). */
+typedef struct {
+  int32_t mode;
+  int64_t n_rows;
+  const double* w;
+  const float* p;
+  const float* n;
+  const int32_t* tri;
+  const float* bary;
+  const int32_t* ring_ptr;
+  const int32_t* ring_tri;
+  const double* ring_cum;
+  const float* face_normals;
+} msk_rows_desc;
+
+/* Copy rows to the device, expressed in the mesh's scene frame, and order
+ * them along a Z-order curve of the sample positions (Sec. 4). Errors:
+ * INVALID_ARG for inconsistent sizes, bad face / vertex indices, non-finite
+ * values or negative weights. */
+msk_status msk_rows_create(msk_ctx* ctx, const msk_mesh* mesh, const msk_rows_desc* desc, msk_rows** out);
+void msk_rows_destroy(msk_rows* rows);
+
+/* Per-vertex basis table in CSR form (host): vertex v holds columns
+ * col[rowptr[v] .. rowptr[v+1]) with values val[...], columns strictly
+ * increasing within a vertex, 0 <= col < K, at most 32 entries per vertex.
+ * b(p) for p with barycentrics l on face (a,b,c) is
+ * l_a table[a] + l_b table[b] + l_c table[c] (Sec. 3.4). */
+msk_status msk_basis_create(msk_ctx* ctx, const int32_t* rowptr, const int32_t* col, const float* val,
+                            int64_t n_verts, int64_t K, msk_basis** out);
+void msk_basis_destroy(msk_basis* basis);
+
+/* -------------------------------------------------------------- estimate */
+
+typedef enum { MSK_INTERIOR = 0, MSK_EXTERIOR = 1 } msk_side;
+typedef enum { MSK_FORM_PERSISTENT = 0, MSK_FORM_PLAIN = 1 } msk_form;
+
+typedef struct {
+  uint64_t seed;       /* Philox key (default 0)                               */
+  int64_t max_steps;   /* walk step cap; 0 = 1024 interior / 8192 exterior     */
+  int64_t walk_offset; /* index of the first walk (resume / split runs)        */
+  double kappa;        /* step radius r = d (1 - kappa) - delta_rel * R       */
+  double delta_rel;    /*   (defaults 2^-20 and 2^-21)                         */
+  int32_t form;        /* msk_form (default persistent)                        */
+  int32_t block;       /* threads per workgroup (default 256)                  */
+  int32_t blocks_per_cu; /* persistent grid size / 256 CUs (default 8)         */
+  int32_t chunk;       /* walks a wavefront takes from the queue at once (64)  */
+  int32_t regen_min;   /* refill a wavefront once this many lanes idle (1)     */
+  int32_t record_log;  /* keep a per-walk log (status, triangle, bary, queries) */
+  double se_target;    /* > 0: adaptive walks per row (see msk_estimate_dtn)   */
+  int64_t walks_max;   /* adaptive cap (default 65536)                         */
+  int32_t collect_stats; /* count BVH nodes visited / triangles tested / FP32
+                            operations (a separately compiled, slower kernel) */
+} msk_dtn_opts;
+
+void msk_dtn_opts_default(msk_dtn_opts* opts);
+
+/* Estimate the DtN rows of one mesh (Alg. 1 in row form).
+ *   walks:  walks per row W (the first batch when se_target > 0);
+ *   eps:    shell width: a walk stops once its squared distance < eps^2;
+ *   inset_h: inset distance h of the start point;
+ *   side:   MSK_INTERIOR (x = s - h n) or MSK_EXTERIOR (x = s + h n).
+ * Row i of the result is S_i = w_i / (h W_i) sum_walks c, c = b(s) - b(t)
+ * (t = the hit's closest point; b(t) = 0 for a walk that escaped), with the
+ * standard error of every entry. Point rows whose inset point lies closer
+ * than h/2 to the surface are discarded (zero row, flagged; Appendix A,
+ * self-intersections). With se_target > 0 (exterior), walks are added in
+ * batches of `walks` to every row whose escape-fraction standard error
+ * sqrt(q(1-q)/W_i) exceeds se_target, up to walks_max.
+ * Errors: INVALID_ARG for walks < 2, eps <= 0, inset_h <= eps, or rows /
+ * basis built for a mesh with a different vertex count. Any K is accepted
+ * (K == n_rows is needed only by msk_steklov_modes). Free the result with
+ * msk_dtn_destroy. */
+msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* mesh, const msk_rows* rows, const msk_basis* basis,
+                            int64_t walks, double eps, double inset_h, int32_t side, const msk_dtn_opts* opts,
+                            msk_dtn** out);
+
+/* Many meshes in one persistent launch captured as a HIP graph: the walks of
+ * all meshes share one work queue ordered largest-mesh-first. meshes, rows,
+ * bases, eps, inset_h and out are arrays of n_meshes entries; each result is
+ * the same as msk_estimate_dtn on that mesh with the mesh's index in the
+ * Philox counter. se_target must be 0. */
+msk_status msk_estimate_dtn_batched(msk_ctx* ctx, int32_t n_meshes, const msk_mesh* const* meshes,
+                                    const msk_rows* const* rows, const msk_basis* const* bases,
+                                    const double* eps, const double* inset_h, int64_t walks, int32_t side,
+                                    const msk_dtn_opts* opts, msk_dtn** out);
+
+typedef struct {
+  int64_t n_rows, K;
+  int64_t walks_total, queries_total, escaped_total, capped_total, discarded_rows;
+  double walk_kernel_ms; /* summed duration of the walk kernel launches      */
+  double total_ms;       /* estimate call, first launch to last completion   */
+  int32_t walk_launches;
+  int64_t nodes_visited; /* with opts.collect_stats: BVH nodes read by walks */
+  int64_t tris_tested;   /* with opts.collect_stats: triangle distance tests */
+  int64_t valu_flops;    /* with opts.collect_stats: FP32 operations of those */
+} msk_dtn_info;
+
+msk_status msk_dtn_get_info(const msk_dtn* dtn, msk_dtn_info* info);
+
+typedef enum {
+  MSK_FIELD_S = 0,          /* n_rows x K double, the estimate             */
+  MSK_FIELD_SE = 1,         /* n_rows x K double, standard errors          */
+  MSK_FIELD_ROW_WALKS = 2,  /* n_rows int64                                */
+  MSK_FIELD_ROW_QUERIES = 3,/* n_rows int64, closest-point queries         */
+  MSK_FIELD_ROW_ESCAPED = 4,/* n_rows int64                                */
+  MSK_FIELD_ROW_CAPPED = 5, /* n_rows int64                                */
+  MSK_FIELD_ROW_DISCARDED = 6, /* n_rows int32 (1 = discarded)             */
+  MSK_FIELD_LOG_STATUS = 7, /* n_rows x W int32: 0 hit, 1 escaped, 2 capped */
+  MSK_FIELD_LOG_TRI = 8,    /* n_rows x W int32, terminal triangle (-1)    */
+  MSK_FIELD_LOG_BARY = 9,   /* n_rows x W x 2 float                        */
+  MSK_FIELD_LOG_QUERIES = 10 /* n_rows x W int32                           */
+} msk_field;
+
+/* Copy one result field, rows in the caller's original row order, into dst
+ * (host memory, or device memory if dst_on_device != 0). The walk log is
+ * available only when opts.record_log was set (and se_target == 0). */
+msk_status msk_dtn_get(const msk_dtn* dtn, int32_t field, void* dst, int32_t dst_on_device);
+void msk_dtn_destroy(msk_dtn* dtn);
+
+/* --------------------------------------------------------- eigen step */
+
+typedef struct {
+  int32_t iterations;   /* block-Lanczos steps taken                      */
+  int32_t block;        /* block size                                      */
+  double max_residual;  /* max_j |C v_j - lambda_j v_j| / |C|_est          */
+  double lanczos_ms;
+} msk_eig_stats;
+
+/* Smallest k eigenpairs of the symmetrised, mass-scaled estimate
+ * C = M^-1/2 (S + S^T)/2 M^-1/2, M = diag(w) over the rows that were not
+ * discarded (Sec. 2, eq. steklov-eigenproblem; Alg. 1 symmetrisation),
+ * by block Lanczos on the GPU: FP32 products with C, FP64 full
+ * re-orthogonalisation and Rayleigh quotients, the projected problem solved
+ * in FP64 on the host. Requires K == n_rows.
+ *   evals: host, k doubles, ascending.
+ *   evecs: host, n_rows x k doubles (psi = M^-1/2 v, zero on discarded rows),
+ *          or NULL.
+ * Returns NOT_CONVERGED (with the best approximations written) if the
+ * residual target 1e-6 |C| is not reached. */
+msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* dtn, int32_t k, double* evals, double* evecs,
+                             msk_eig_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSK_H */

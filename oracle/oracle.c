@@ -574,7 +574,8 @@ static int walk(const OrcScene* s, const OrcWalkParams* P, uint32_t row, uint32_
       double st = sqrt(fmax(0.0, 1.0 - mu * mu));
       for (int c = 0; c < 3; ++c)
         x[c] = s->radius * (mu * nx[c] + st * (cos(phi) * e1[c] + sin(phi) * e2[c]));
-      continue;
+      /* the re-entry point lies on the sphere: the same step goes on with a
+       * distance query from there (u[0], u[1] are still unused) */
     }
     double d2 = nearest(s, x, tri, bary);
     ++q;

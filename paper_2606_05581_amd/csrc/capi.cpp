@@ -1,0 +1,815 @@
+// C ABI of libmsk (declared in include/msk.h): argument checking, device
+// memory, row ordering, work queues and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/msk.h"
+#include "msk_internal.h"
+
+using namespace msk;
+
+struct msk_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 256;
+  std::string err;
+};
+
+struct msk_mesh {
+  msk_ctx* ctx = nullptr;
+  double centre[3] = {0, 0, 0};
+  double radius = 0, area = 0;
+  int64_t nv = 0, nf = 0, n_nodes = 0;
+  int depth = 0, leaf_size = 4, top_nodes = 85;
+  Node4* d_nodes = nullptr;
+  TriRec* d_tris = nullptr;
+  int32_t* d_slot = nullptr;
+  int32_t* d_faces = nullptr;
+  std::vector<float> vrel;       // float offsets from the centre (host copy)
+  std::vector<int32_t> faces;    // host copy
+};
+
+struct msk_rows {
+  msk_ctx* ctx = nullptr;
+  const msk_mesh* mesh = nullptr;
+  int32_t mode = 0;
+  int64_t n = 0;
+  std::vector<double> w;
+  std::vector<int32_t> order;    // Z-order of the rows
+  double* d_w = nullptr;
+  float* d_p = nullptr;
+  float* d_n = nullptr;
+  int32_t* d_tri = nullptr;
+  float* d_bary = nullptr;
+  int32_t* d_ring_ptr = nullptr;
+  int32_t* d_ring_tri = nullptr;
+  double* d_ring_cum = nullptr;
+  float* d_fn = nullptr;
+};
+
+struct msk_basis {
+  msk_ctx* ctx = nullptr;
+  int64_t nv = 0, K = 0;
+  int32_t* d_rowptr = nullptr;
+  int32_t* d_col = nullptr;
+  float* d_val = nullptr;
+};
+
+struct msk_dtn {
+  msk_ctx* ctx = nullptr;
+  const msk_rows* rows = nullptr;
+  int64_t n = 0, K = 0, W = 0;
+  int32_t mode = 0;
+  double inset = 0;
+  double* d_S = nullptr;
+  double* d_se = nullptr;
+  double* d_acc1 = nullptr;
+  double* d_acc2 = nullptr;
+  unsigned long long* d_q = nullptr;
+  unsigned long long* d_esc = nullptr;
+  unsigned long long* d_cap = nullptr;
+  int32_t* d_disc = nullptr;
+  int64_t* d_walks = nullptr;
+  int32_t* d_log_status = nullptr;
+  int32_t* d_log_tri = nullptr;
+  float* d_log_bary = nullptr;
+  int32_t* d_log_q = nullptr;
+  msk_dtn_info info{};
+};
+
+namespace {
+
+msk_status fail(msk_ctx* ctx, msk_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? MSK_ERR_OOM : MSK_ERR_DEVICE,             \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+template <typename T>
+hipError_t upload(msk_ctx* ctx, T** p, const T* src, size_t n) {
+  hipError_t e = dalloc(p, n);
+  if (e != hipSuccess) return e;
+  if (n == 0) return hipSuccess;
+  e = hipMemcpyAsync(*p, src, n * sizeof(T), hipMemcpyHostToDevice, ctx->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(ctx->stream);
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+uint64_t spread3(uint64_t x) {
+  x &= 0x1FFFFF;
+  x = (x | x << 32) & 0x1F00000000FFFFull;
+  x = (x | x << 16) & 0x1F0000FF0000FFull;
+  x = (x | x << 8) & 0x100F00F00F00F00Full;
+  x = (x | x << 4) & 0x10C30C30C30C30C3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+
+// Z-order (Morton) permutation of points (Sec. 4: samples sorted along a
+// Z-order curve so that neighbouring walks traverse the same BVH region).
+std::vector<int32_t> morton_order(const std::vector<float>& P, int64_t n) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], P[3 * i + k]);
+      hi[k] = std::max(hi[k], P[3 * i + k]);
+    }
+  std::vector<uint64_t> code((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t c = 0;
+    for (int k = 0; k < 3; ++k) {
+      double ext = std::max(1e-30, (double)hi[k] - (double)lo[k]);
+      uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, ((double)P[3 * i + k] - lo[k]) / ext * 2097151.0));
+      c |= spread3(q) << k;
+    }
+    code[i] = c;
+  }
+  std::vector<int32_t> ord((size_t)n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+  return ord;
+}
+
+bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+}  // namespace
+
+// ------------------------------------------------------------- context
+
+extern "C" msk_status msk_create(int device, void* hip_stream, msk_ctx** out) {
+  if (!out) return MSK_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return MSK_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return MSK_ERR_DEVICE;
+  msk_ctx* c = new msk_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
+  *out = c;
+  return MSK_OK;
+}
+
+extern "C" void msk_destroy(msk_ctx* ctx) { delete ctx; }
+
+extern "C" const char* msk_last_error(const msk_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+// ---------------------------------------------------------------- mesh
+
+extern "C" msk_status msk_build_bvh(msk_ctx* ctx, const float* V, int64_t n_verts, const int32_t* F, int64_t n_tris,
+                                    const msk_bvh_opts* opts, msk_mesh** out) {
+  if (!ctx || !out) return MSK_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!V || !F) return fail(ctx, MSK_ERR_INVALID_ARG, "null mesh arrays");
+  if (n_verts >= INT32_MAX || n_tris >= (1ll << 30)) return fail(ctx, MSK_ERR_INVALID_ARG, "mesh too large");
+  int leaf = opts && opts->leaf_size > 0 ? opts->leaf_size : 4;
+  int top = opts ? opts->top_nodes : 85;
+  if (top < 0 || top > kMaxTop) return fail(ctx, MSK_ERR_INVALID_ARG, "top_nodes must be in 0..128");
+  HostBvh B;
+  std::string e = build_bvh_host(V, n_verts, F, n_tris, leaf, B);
+  if (!e.empty()) return fail(ctx, MSK_ERR_INVALID_ARG, e);
+  msk_mesh* m = new msk_mesh();
+  m->ctx = ctx;
+  std::memcpy(m->centre, B.centre, sizeof(m->centre));
+  m->radius = B.radius;
+  m->area = B.area;
+  m->nv = n_verts;
+  m->nf = n_tris;
+  m->n_nodes = (int64_t)B.nodes.size();
+  m->depth = B.depth;
+  m->leaf_size = leaf;
+  m->top_nodes = (int)std::min<int64_t>(top, m->n_nodes);
+  m->vrel.resize((size_t)n_verts * 3);
+  for (int64_t i = 0; i < n_verts; ++i)
+    for (int k = 0; k < 3; ++k) m->vrel[3 * i + k] = (float)((double)V[3 * i + k] - B.centre[k]);
+  m->faces.assign(F, F + 3 * n_tris);
+  hipError_t he;
+  if ((he = upload(ctx, &m->d_nodes, B.nodes.data(), B.nodes.size())) != hipSuccess ||
+      (he = upload(ctx, &m->d_tris, B.tris.data(), B.tris.size())) != hipSuccess ||
+      (he = upload(ctx, &m->d_slot, B.slot_of_tri.data(), B.slot_of_tri.size())) != hipSuccess ||
+      (he = upload(ctx, &m->d_faces, F, (size_t)n_tris * 3)) != hipSuccess) {
+    msk_mesh_destroy(m);
+    return fail(ctx, he == hipErrorOutOfMemory ? MSK_ERR_OOM : MSK_ERR_DEVICE,
+                std::string("mesh upload: ") + hipGetErrorString(he));
+  }
+  *out = m;
+  return MSK_OK;
+}
+
+extern "C" msk_status msk_mesh_get_info(const msk_mesh* m, msk_mesh_info* info) {
+  if (!m || !info) return MSK_ERR_INVALID_ARG;
+  std::memcpy(info->centre, m->centre, sizeof(info->centre));
+  info->radius = m->radius;
+  info->area = m->area;
+  info->n_verts = m->nv;
+  info->n_tris = m->nf;
+  info->n_nodes = m->n_nodes;
+  info->node_bytes = m->n_nodes * (int64_t)sizeof(Node4);
+  info->tri_bytes = m->nf * (int64_t)sizeof(TriRec);
+  info->depth = m->depth;
+  info->leaf_size = m->leaf_size;
+  return MSK_OK;
+}
+
+extern "C" void msk_mesh_destroy(msk_mesh* m) {
+  if (!m) return;
+  dfree(m->d_nodes);
+  dfree(m->d_tris);
+  dfree(m->d_slot);
+  dfree(m->d_faces);
+  delete m;
+}
+
+extern "C" msk_status msk_closest_points(msk_ctx* ctx, const msk_mesh* m, const float* Q, int64_t nq, int32_t* tri,
+                                         float* d2, float* bary) {
+  if (!ctx || !m) return MSK_ERR_INVALID_ARG;
+  if (nq < 0 || (nq > 0 && (!Q || !tri || !d2 || !bary))) return fail(ctx, MSK_ERR_INVALID_ARG, "bad query arrays");
+  if (nq == 0) return MSK_OK;
+  HIP_TRY(ctx, launch_closest_points(m->d_nodes, m->d_tris, (float)m->radius, m->centre, Q, nq, tri, d2, bary,
+                                     ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MSK_OK;
+}
+
+// ------------------------------------------------------ rows and basis
+
+extern "C" msk_status msk_rows_create(msk_ctx* ctx, const msk_mesh* m, const msk_rows_desc* d, msk_rows** out) {
+  if (!ctx || !m || !d || !out) return MSK_ERR_INVALID_ARG;
+  *out = nullptr;
+  const int64_t n = d->n_rows;
+  if (n < 1 || n >= INT32_MAX) return fail(ctx, MSK_ERR_INVALID_ARG, "n_rows must be >= 1");
+  if (!d->w) return fail(ctx, MSK_ERR_INVALID_ARG, "row weights missing");
+  for (int64_t i = 0; i < n; ++i)
+    if (!(d->w[i] >= 0) || !std::isfinite(d->w[i])) return fail(ctx, MSK_ERR_INVALID_ARG, "bad row weight");
+  msk_rows* r = new msk_rows();
+  r->ctx = ctx;
+  r->mesh = m;
+  r->mode = d->mode;
+  r->n = n;
+  r->w.assign(d->w, d->w + n);
+  std::vector<float> pos((size_t)n * 3);
+  hipError_t he = hipSuccess;
+  if (d->mode == MSK_ROWS_POINT) {
+    if (!d->p || !d->n || !d->tri || !d->bary) {
+      delete r;
+      return fail(ctx, MSK_ERR_INVALID_ARG, "point rows need p, n, tri, bary");
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      if (!finite3(d->p + 3 * i) || !finite3(d->n + 3 * i) || !finite3(d->bary + 3 * i) || d->tri[i] < 0 ||
+          d->tri[i] >= m->nf) {
+        delete r;
+        return fail(ctx, MSK_ERR_INVALID_ARG, "bad point row " + std::to_string(i));
+      }
+      for (int k = 0; k < 3; ++k) pos[3 * i + k] = (float)((double)d->p[3 * i + k] - m->centre[k]);
+    }
+    if ((he = upload(ctx, &r->d_p, pos.data(), pos.size())) != hipSuccess ||
+        (he = upload(ctx, &r->d_n, d->n, (size_t)n * 3)) != hipSuccess ||
+        (he = upload(ctx, &r->d_tri, d->tri, (size_t)n)) != hipSuccess ||
+        (he = upload(ctx, &r->d_bary, d->bary, (size_t)n * 3)) != hipSuccess) {
+      msk_rows_destroy(r);
+      return fail(ctx, MSK_ERR_DEVICE, std::string("rows upload: ") + hipGetErrorString(he));
+    }
+  } else if (d->mode == MSK_ROWS_HAT_RING) {
+    if (n != m->nv || !d->ring_ptr || !d->ring_tri || !d->ring_cum || !d->face_normals) {
+      delete r;
+      return fail(ctx, MSK_ERR_INVALID_ARG, "hat rows need one row per vertex and the one-ring arrays");
+    }
+    const int64_t ne = d->ring_ptr[n];
+    if (d->ring_ptr[0] != 0 || ne < 0) {
+      delete r;
+      return fail(ctx, MSK_ERR_INVALID_ARG, "bad ring_ptr");
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      if (d->ring_ptr[i + 1] <= d->ring_ptr[i]) {
+        delete r;
+        return fail(ctx, MSK_ERR_INVALID_ARG, "vertex " + std::to_string(i) + " has an empty one-ring");
+      }
+      for (int32_t e = d->ring_ptr[i]; e < d->ring_ptr[i + 1]; ++e) {
+        int32_t f = d->ring_tri[e];
+        if (f < 0 || f >= m->nf ||
+            (m->faces[3 * f] != i && m->faces[3 * f + 1] != i && m->faces[3 * f + 2] != i) ||
+            !std::isfinite(d->ring_cum[e])) {
+          delete r;
+          return fail(ctx, MSK_ERR_INVALID_ARG, "bad one-ring entry of vertex " + std::to_string(i));
+        }
+      }
+      for (int k = 0; k < 3; ++k) pos[3 * i + k] = m->vrel[3 * i + k];
+    }
+    for (int64_t f = 0; f < m->nf; ++f)
+      if (!finite3(d->face_normals + 3 * f)) {
+        delete r;
+        return fail(ctx, MSK_ERR_INVALID_ARG, "bad face normal");
+      }
+    if ((he = upload(ctx, &r->d_ring_ptr, d->ring_ptr, (size_t)n + 1)) != hipSuccess ||
+        (he = upload(ctx, &r->d_ring_tri, d->ring_tri, (size_t)ne)) != hipSuccess ||
+        (he = upload(ctx, &r->d_ring_cum, d->ring_cum, (size_t)ne)) != hipSuccess ||
+        (he = upload(ctx, &r->d_fn, d->face_normals, (size_t)m->nf * 3)) != hipSuccess) {
+      msk_rows_destroy(r);
+      return fail(ctx, MSK_ERR_DEVICE, std::string("rows upload: ") + hipGetErrorString(he));
+    }
+  } else {
+    delete r;
+    return fail(ctx, MSK_ERR_INVALID_ARG, "unknown row mode");
+  }
+  if ((he = upload(ctx, &r->d_w, d->w, (size_t)n)) != hipSuccess) {
+    msk_rows_destroy(r);
+    return fail(ctx, MSK_ERR_DEVICE, std::string("rows upload: ") + hipGetErrorString(he));
+  }
+  r->order = morton_order(pos, n);
+  *out = r;
+  return MSK_OK;
+}
+
+extern "C" void msk_rows_destroy(msk_rows* r) {
+  if (!r) return;
+  dfree(r->d_w);
+  dfree(r->d_p);
+  dfree(r->d_n);
+  dfree(r->d_tri);
+  dfree(r->d_bary);
+  dfree(r->d_ring_ptr);
+  dfree(r->d_ring_tri);
+  dfree(r->d_ring_cum);
+  dfree(r->d_fn);
+  delete r;
+}
+
+extern "C" msk_status msk_basis_create(msk_ctx* ctx, const int32_t* rowptr, const int32_t* col, const float* val,
+                                       int64_t n_verts, int64_t K, msk_basis** out) {
+  if (!ctx || !out) return MSK_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!rowptr || n_verts < 1 || K < 1 || K >= INT32_MAX) return fail(ctx, MSK_ERR_INVALID_ARG, "bad basis sizes");
+  if (rowptr[0] != 0) return fail(ctx, MSK_ERR_INVALID_ARG, "rowptr[0] must be 0");
+  const int64_t nnz = rowptr[n_verts];
+  if (nnz > 0 && (!col || !val)) return fail(ctx, MSK_ERR_INVALID_ARG, "basis col/val missing");
+  for (int64_t v = 0; v < n_verts; ++v) {
+    int32_t a = rowptr[v], b = rowptr[v + 1];
+    if (b < a || b - a > kMaxTableNnz) return fail(ctx, MSK_ERR_INVALID_ARG, "bad basis row " + std::to_string(v));
+    for (int32_t e = a; e < b; ++e) {
+      if (col[e] < 0 || col[e] >= K || (e > a && col[e] <= col[e - 1]) || !std::isfinite(val[e]))
+        return fail(ctx, MSK_ERR_INVALID_ARG, "basis row " + std::to_string(v) + " columns must increase in [0,K)");
+    }
+  }
+  msk_basis* b = new msk_basis();
+  b->ctx = ctx;
+  b->nv = n_verts;
+  b->K = K;
+  hipError_t he;
+  if ((he = upload(ctx, &b->d_rowptr, rowptr, (size_t)n_verts + 1)) != hipSuccess ||
+      (he = upload(ctx, &b->d_col, col, (size_t)nnz)) != hipSuccess ||
+      (he = upload(ctx, &b->d_val, val, (size_t)nnz)) != hipSuccess) {
+    msk_basis_destroy(b);
+    return fail(ctx, MSK_ERR_DEVICE, std::string("basis upload: ") + hipGetErrorString(he));
+  }
+  *out = b;
+  return MSK_OK;
+}
+
+extern "C" void msk_basis_destroy(msk_basis* b) {
+  if (!b) return;
+  dfree(b->d_rowptr);
+  dfree(b->d_col);
+  dfree(b->d_val);
+  delete b;
+}
+
+// ------------------------------------------------------------ estimate
+
+extern "C" void msk_dtn_opts_default(msk_dtn_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->seed = 0;
+  o->max_steps = 0;
+  o->walk_offset = 0;
+  o->kappa = std::ldexp(1.0, -20);
+  o->delta_rel = std::ldexp(1.0, -21);
+  o->form = MSK_FORM_PERSISTENT;
+  o->block = 256;
+  o->blocks_per_cu = 8;
+  o->chunk = 64;
+  o->regen_min = 1;
+  o->record_log = 0;
+  o->se_target = 0;
+  o->walks_max = 65536;
+  o->collect_stats = 0;
+}
+
+namespace {
+
+void dtn_free(msk_dtn* d) {
+  dfree(d->d_S);
+  dfree(d->d_se);
+  dfree(d->d_acc1);
+  dfree(d->d_acc2);
+  dfree(d->d_q);
+  dfree(d->d_esc);
+  dfree(d->d_cap);
+  dfree(d->d_disc);
+  dfree(d->d_walks);
+  dfree(d->d_log_status);
+  dfree(d->d_log_tri);
+  dfree(d->d_log_bary);
+  dfree(d->d_log_q);
+}
+
+struct Prepared {
+  MeshDev md;
+};
+
+msk_status check_problem(msk_ctx* ctx, const msk_mesh* m, const msk_rows* r, const msk_basis* b, int64_t walks,
+                         double eps, double h, int32_t side) {
+  if (!m || !r || !b) return fail(ctx, MSK_ERR_INVALID_ARG, "null mesh / rows / basis");
+  if (r->mesh != m) return fail(ctx, MSK_ERR_INVALID_ARG, "rows were created for another mesh");
+  if (b->nv != m->nv) return fail(ctx, MSK_ERR_INVALID_ARG, "basis vertex count differs from the mesh's");
+  if (walks < 2 || walks > INT32_MAX) return fail(ctx, MSK_ERR_INVALID_ARG, "walks must be in 2..2^31-1");
+  if (!(eps > 0) || !(h > eps) || !std::isfinite(h)) return fail(ctx, MSK_ERR_INVALID_ARG, "need 0 < eps < inset_h");
+  if (side != MSK_INTERIOR && side != MSK_EXTERIOR) return fail(ctx, MSK_ERR_INVALID_ARG, "side must be 0 or 1");
+  return MSK_OK;
+}
+
+msk_status alloc_dtn(msk_ctx* ctx, const msk_rows* r, const msk_basis* b, int64_t W, bool log, msk_dtn** out) {
+  msk_dtn* d = new msk_dtn();
+  d->ctx = ctx;
+  d->rows = r;
+  d->n = r->n;
+  d->K = b->K;
+  d->W = W;
+  d->mode = r->mode;
+  const size_t nk = (size_t)d->n * (size_t)d->K;
+  hipError_t he;
+  if ((he = dalloc(&d->d_S, nk)) != hipSuccess || (he = dalloc(&d->d_se, nk)) != hipSuccess ||
+      (he = dalloc(&d->d_acc1, nk)) != hipSuccess || (he = dalloc(&d->d_acc2, nk)) != hipSuccess ||
+      (he = dalloc(&d->d_q, d->n)) != hipSuccess || (he = dalloc(&d->d_esc, d->n)) != hipSuccess ||
+      (he = dalloc(&d->d_cap, d->n)) != hipSuccess || (he = dalloc(&d->d_disc, d->n)) != hipSuccess ||
+      (he = dalloc(&d->d_walks, d->n)) != hipSuccess) {
+    dtn_free(d);
+    delete d;
+    return fail(ctx, MSK_ERR_OOM, std::string("estimate buffers: ") + hipGetErrorString(he));
+  }
+  if (log) {
+    const size_t nl = (size_t)d->n * (size_t)W;
+    if ((he = dalloc(&d->d_log_status, nl)) != hipSuccess || (he = dalloc(&d->d_log_tri, nl)) != hipSuccess ||
+        (he = dalloc(&d->d_log_bary, 2 * nl)) != hipSuccess || (he = dalloc(&d->d_log_q, nl)) != hipSuccess) {
+      dtn_free(d);
+      delete d;
+      return fail(ctx, MSK_ERR_OOM, std::string("walk log: ") + hipGetErrorString(he));
+    }
+  }
+  *out = d;
+  return MSK_OK;
+}
+
+MeshDev make_meshdev(const msk_mesh* m, const msk_rows* r, const msk_basis* b, msk_dtn* d, double eps, double h,
+                     int32_t side, const msk_dtn_opts& o, int32_t mesh_id) {
+  MeshDev M;
+  std::memset(&M, 0, sizeof(M));
+  M.nodes = m->d_nodes;
+  M.tris = m->d_tris;
+  M.slot_of_tri = m->d_slot;
+  M.faces = m->d_faces;
+  M.n_tris = m->nf;
+  M.n_top = m->top_nodes;
+  M.mode = r->mode;
+  M.radius = (float)m->radius;
+  M.radius_d = m->radius;
+  M.eps2 = (float)(eps * eps);
+  M.inset = (float)h;
+  M.inset_d = h;
+  M.kappa = (float)o.kappa;
+  M.delta = (float)(o.delta_rel * m->radius);
+  M.slack = (float)std::ldexp(m->radius, -18);
+  M.side = side;
+  M.mesh_id = mesh_id;
+  M.walks_per_row = (int32_t)d->W;
+  M.max_steps = o.max_steps > 0 ? o.max_steps : (side == MSK_EXTERIOR ? 8192 : 1024);
+  M.p = r->d_p;
+  M.n = r->d_n;
+  M.tri = r->d_tri;
+  M.bary = r->d_bary;
+  M.ring_ptr = r->d_ring_ptr;
+  M.ring_tri = r->d_ring_tri;
+  M.ring_cum = r->d_ring_cum;
+  M.face_normals = r->d_fn;
+  M.discarded = d->d_disc;
+  M.b_rowptr = b->d_rowptr;
+  M.b_col = b->d_col;
+  M.b_val = b->d_val;
+  M.K = b->K;
+  M.acc1 = d->d_acc1;
+  M.acc2 = d->d_acc2;
+  M.row_queries = d->d_q;
+  M.row_escaped = d->d_esc;
+  M.row_capped = d->d_cap;
+  M.log_status = d->d_log_status;
+  M.log_tri = d->d_log_tri;
+  M.log_bary = d->d_log_bary;
+  M.log_queries = d->d_log_q;
+  return M;
+}
+
+// Queue bounds: 8 contiguous ranges of slots with about equal walk counts.
+QueueInit make_queues(int64_t n_slots, int64_t W) {
+  QueueInit q;
+  for (int i = 0; i < 8; ++i) {
+    int64_t s0 = n_slots * i / 8, s1 = n_slots * (i + 1) / 8;
+    q.begin[i] = (unsigned long long)(s0 * W);
+    q.end[i] = (unsigned long long)(s1 * W);
+  }
+  return q;
+}
+
+}  // namespace
+
+struct LaunchBuffers {
+  MeshDev* d_meshes = nullptr;
+  RowSlot* d_slots = nullptr;
+  unsigned long long* d_qnext = nullptr;
+  unsigned long long* d_qend = nullptr;
+  unsigned long long* d_stats = nullptr;
+  ~LaunchBuffers() {
+    dfree(d_stats);
+    dfree(d_meshes);
+    dfree(d_slots);
+    dfree(d_qnext);
+    dfree(d_qend);
+  }
+};
+
+// Runs the walk kernel over `slots` (walks [offset, offset + W) of each
+// slot's row) and returns its duration in milliseconds.
+static msk_status run_walks(msk_ctx* ctx, const std::vector<MeshDev>& meshes, const std::vector<RowSlot>& slots,
+                            int64_t W, int64_t offset, const msk_dtn_opts& o, int use_lds_top, int n_top,
+                            double* ms, int64_t stats_out[3]) {
+  *ms = 0;
+  if (slots.empty()) return MSK_OK;
+  LaunchBuffers lb;
+  HIP_TRY(ctx, upload(ctx, &lb.d_meshes, meshes.data(), meshes.size()));
+  HIP_TRY(ctx, upload(ctx, &lb.d_slots, slots.data(), slots.size()));
+  HIP_TRY(ctx, dalloc(&lb.d_qnext, 8));
+  HIP_TRY(ctx, dalloc(&lb.d_qend, 8));
+  WalkLaunch L;
+  std::memset(&L, 0, sizeof(L));
+  L.meshes = lb.d_meshes;
+  L.slots = lb.d_slots;
+  L.n_slots = (int64_t)slots.size();
+  L.walks_per_slot = W;
+  L.walk_offset = offset;
+  L.seed_lo = (uint32_t)o.seed;
+  L.seed_hi = (uint32_t)(o.seed >> 32);
+  L.queue_next = lb.d_qnext;
+  L.queue_end = lb.d_qend;
+  L.chunk = std::max(1, o.chunk);
+  L.regen_min = std::min(64, std::max(1, o.regen_min));
+  L.use_lds_top = use_lds_top;
+  L.n_top = n_top;
+  if (o.collect_stats) {
+    HIP_TRY(ctx, dalloc(&lb.d_stats, 3));
+    HIP_TRY(ctx, launch_fill_u64(lb.d_stats, 3, 0, ctx->stream));
+    L.stats = lb.d_stats;
+  }
+  if ((unsigned long long)L.n_slots * (unsigned long long)W >= (1ull << 62))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "too many walks");
+  QueueInit q = make_queues(L.n_slots, W);
+  HIP_TRY(ctx, launch_init_queues(lb.d_qnext, lb.d_qend, q, ctx->stream));
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+  hipError_t le;
+  if (o.form == MSK_FORM_PLAIN) {
+    le = launch_walk_plain(L, ctx->stream);
+  } else {
+    const int grid = std::max(1, ctx->n_cu * std::max(1, o.blocks_per_cu));
+    le = launch_walk_persistent(L, grid, ctx->stream);
+  }
+  HIP_TRY(ctx, le);
+  HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+  HIP_TRY(ctx, hipEventSynchronize(e1));
+  float f = 0;
+  HIP_TRY(ctx, hipEventElapsedTime(&f, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = f;
+  if (o.collect_stats) {
+    unsigned long long st[3];
+    HIP_TRY(ctx, hipMemcpy(st, lb.d_stats, sizeof(st), hipMemcpyDeviceToHost));
+    stats_out[0] += (int64_t)st[0];
+    stats_out[1] += (int64_t)st[1];
+    stats_out[2] += (int64_t)st[2];
+  }
+  return MSK_OK;
+}
+
+static msk_status collect_info(msk_ctx* ctx, msk_dtn* d) {
+  std::vector<unsigned long long> q(d->n), esc(d->n), cap(d->n);
+  std::vector<int32_t> disc(d->n);
+  std::vector<int64_t> walks(d->n);
+  HIP_TRY(ctx, hipMemcpy(q.data(), d->d_q, d->n * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(ctx, hipMemcpy(esc.data(), d->d_esc, d->n * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(ctx, hipMemcpy(cap.data(), d->d_cap, d->n * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(ctx, hipMemcpy(disc.data(), d->d_disc, d->n * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(ctx, hipMemcpy(walks.data(), d->d_walks, d->n * 8, hipMemcpyDeviceToHost));
+  d->info.n_rows = d->n;
+  d->info.K = d->K;
+  d->info.walks_total = d->info.queries_total = d->info.escaped_total = d->info.capped_total = 0;
+  d->info.discarded_rows = 0;
+  for (int64_t i = 0; i < d->n; ++i) {
+    d->info.queries_total += (int64_t)q[i];
+    d->info.escaped_total += (int64_t)esc[i];
+    d->info.capped_total += (int64_t)cap[i];
+    d->info.discarded_rows += disc[i] ? 1 : 0;
+    d->info.walks_total += disc[i] ? 0 : walks[i];
+  }
+  return MSK_OK;
+}
+
+extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const msk_rows* r, const msk_basis* b,
+                                       int64_t walks, double eps, double inset_h, int32_t side,
+                                       const msk_dtn_opts* opts, msk_dtn** out) {
+  if (!ctx || !out) return MSK_ERR_INVALID_ARG;
+  *out = nullptr;
+  msk_status st = check_problem(ctx, m, r, b, walks, eps, inset_h, side);
+  if (st != MSK_OK) return st;
+  msk_dtn_opts o;
+  msk_dtn_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.form != MSK_FORM_PLAIN && o.form != MSK_FORM_PERSISTENT) return fail(ctx, MSK_ERR_INVALID_ARG, "bad form");
+  if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "walk indices must fit in 32 bits");
+  const bool adaptive = o.se_target > 0;
+  if (adaptive && (o.walks_max < walks)) return fail(ctx, MSK_ERR_INVALID_ARG, "walks_max < walks");
+  if (adaptive && o.record_log) return fail(ctx, MSK_ERR_INVALID_ARG, "walk log needs a fixed walk count");
+  msk_dtn* d = nullptr;
+  st = alloc_dtn(ctx, r, b, walks, o.record_log != 0, &d);
+  if (st != MSK_OK) return st;
+  d->inset = inset_h;
+  hipEvent_t t0, t1;
+  auto cleanup = [&](msk_status s) {
+    dtn_free(d);
+    delete d;
+    return s;
+  };
+#define TRY_D(expr)                    \
+  do {                                 \
+    msk_status s_ = (expr);            \
+    if (s_ != MSK_OK) return cleanup(s_); \
+  } while (0)
+#define HIP_D(expr)                                                                                   \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess)                                                                             \
+      return cleanup(fail(ctx, MSK_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)));   \
+  } while (0)
+  HIP_D(hipEventCreate(&t0));
+  HIP_D(hipEventCreate(&t1));
+  HIP_D(hipEventRecord(t0, ctx->stream));
+  const size_t nk = (size_t)d->n * (size_t)d->K;
+  HIP_D(launch_fill_u64(d->d_acc1, (int64_t)nk, 0, ctx->stream));
+  HIP_D(launch_fill_u64(d->d_acc2, (int64_t)nk, 0, ctx->stream));
+  HIP_D(launch_fill_u64(d->d_q, d->n, 0, ctx->stream));
+  HIP_D(launch_fill_u64(d->d_esc, d->n, 0, ctx->stream));
+  HIP_D(launch_fill_u64(d->d_cap, d->n, 0, ctx->stream));
+  HIP_D(launch_fill_u64(d->d_walks, d->n, (unsigned long long)walks, ctx->stream));
+  if (d->d_log_status) {  // walks of discarded rows keep status -1
+    HIP_D(launch_fill_u32(d->d_log_status, d->n * walks, 0xFFFFFFFFu, ctx->stream));
+    HIP_D(launch_fill_u32(d->d_log_tri, d->n * walks, 0xFFFFFFFFu, ctx->stream));
+    HIP_D(launch_fill_u32(d->d_log_bary, 2 * d->n * walks, 0u, ctx->stream));
+    HIP_D(launch_fill_u32(d->d_log_q, d->n * walks, 0u, ctx->stream));
+  }
+  // discarded flags: zero, then the inset test for point rows
+  HIP_D(launch_fill_u32(d->d_disc, d->n, 0u, ctx->stream));
+  MeshDev M = make_meshdev(m, r, b, d, eps, inset_h, side, o, 0);
+  if (r->mode == MSK_ROWS_POINT) HIP_D(launch_discard(M, d->n, d->d_disc, ctx->stream));
+  HIP_D(hipStreamSynchronize(ctx->stream));
+  std::vector<MeshDev> meshes{M};
+  std::vector<RowSlot> slots(r->order.size());
+  for (size_t i = 0; i < slots.size(); ++i) slots[i] = RowSlot{0, r->order[i]};
+  const int use_lds = (o.form == MSK_FORM_PERSISTENT && m->top_nodes > 0) ? 1 : 0;
+  double ms = 0;
+  d->info.walk_launches = 0;
+  d->info.walk_kernel_ms = 0;
+  int64_t stats[3] = {0, 0, 0};
+  TRY_D(run_walks(ctx, meshes, slots, walks, o.walk_offset, o, use_lds, m->top_nodes, &ms, stats));
+  d->info.walk_kernel_ms += ms;
+  d->info.walk_launches += 1;
+  if (adaptive) {
+    // add batches of `walks` to rows whose escape-fraction se exceeds the target
+    std::vector<int64_t> wdone((size_t)d->n, walks);
+    std::vector<unsigned long long> esc((size_t)d->n);
+    std::vector<int32_t> disc((size_t)d->n);
+    HIP_D(hipMemcpy(disc.data(), d->d_disc, d->n * 4, hipMemcpyDeviceToHost));
+    int64_t done = walks;
+    while (done + walks <= o.walks_max) {
+      HIP_D(hipMemcpy(esc.data(), d->d_esc, d->n * 8, hipMemcpyDeviceToHost));
+      std::vector<RowSlot> act;
+      for (int32_t i : r->order) {
+        if (disc[i]) continue;
+        double q = (double)esc[i] / (double)wdone[i];
+        double se = std::sqrt(std::max(q * (1 - q), 1.0 / wdone[i]) / (double)wdone[i]);
+        if (se > o.se_target) act.push_back(RowSlot{0, i});
+      }
+      if (act.empty()) break;
+      TRY_D(run_walks(ctx, meshes, act, walks, o.walk_offset + done, o, use_lds, m->top_nodes, &ms, stats));
+      d->info.walk_kernel_ms += ms;
+      d->info.walk_launches += 1;
+      for (auto& a : act) wdone[a.row] += walks;
+      done += walks;
+    }
+    HIP_D(hipMemcpy(d->d_walks, wdone.data(), d->n * 8, hipMemcpyHostToDevice));
+  }
+  HIP_D(launch_finalize(M, d->n, d->d_walks, r->d_w, d->d_S, d->d_se, ctx->stream));
+  HIP_D(hipEventRecord(t1, ctx->stream));
+  HIP_D(hipEventSynchronize(t1));
+  float tot = 0;
+  HIP_D(hipEventElapsedTime(&tot, t0, t1));
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  d->info.total_ms = tot;
+  TRY_D(collect_info(ctx, d));
+  d->info.nodes_visited = stats[0];
+  d->info.tris_tested = stats[1];
+  d->info.valu_flops = stats[2];
+#undef TRY_D
+#undef HIP_D
+  *out = d;
+  return MSK_OK;
+}
+
+extern "C" msk_status msk_estimate_dtn_batched(msk_ctx* ctx, int32_t n_meshes, const msk_mesh* const* meshes,
+                                               const msk_rows* const* rows, const msk_basis* const* bases,
+                                               const double* eps, const double* inset_h, int64_t walks, int32_t side,
+                                               const msk_dtn_opts* opts, msk_dtn** out) {
+  return fail(ctx, MSK_ERR_INVALID_ARG, "batched estimate not available in this build");
+}
+
+extern "C" msk_status msk_dtn_get_info(const msk_dtn* d, msk_dtn_info* info) {
+  if (!d || !info) return MSK_ERR_INVALID_ARG;
+  *info = d->info;
+  return MSK_OK;
+}
+
+extern "C" msk_status msk_dtn_get(const msk_dtn* d, int32_t field, void* dst, int32_t dst_on_device) {
+  if (!d || !dst) return MSK_ERR_INVALID_ARG;
+  msk_ctx* ctx = d->ctx;
+  const void* src = nullptr;
+  size_t bytes = 0;
+  const size_t nk = (size_t)d->n * (size_t)d->K, nl = (size_t)d->n * (size_t)d->W;
+  switch (field) {
+    case MSK_FIELD_S: src = d->d_S; bytes = nk * 8; break;
+    case MSK_FIELD_SE: src = d->d_se; bytes = nk * 8; break;
+    case MSK_FIELD_ROW_WALKS: src = d->d_walks; bytes = d->n * 8; break;
+    case MSK_FIELD_ROW_QUERIES: src = d->d_q; bytes = d->n * 8; break;
+    case MSK_FIELD_ROW_ESCAPED: src = d->d_esc; bytes = d->n * 8; break;
+    case MSK_FIELD_ROW_CAPPED: src = d->d_cap; bytes = d->n * 8; break;
+    case MSK_FIELD_ROW_DISCARDED: src = d->d_disc; bytes = d->n * 4; break;
+    case MSK_FIELD_LOG_STATUS: src = d->d_log_status; bytes = nl * 4; break;
+    case MSK_FIELD_LOG_TRI: src = d->d_log_tri; bytes = nl * 4; break;
+    case MSK_FIELD_LOG_BARY: src = d->d_log_bary; bytes = nl * 8; break;
+    case MSK_FIELD_LOG_QUERIES: src = d->d_log_q; bytes = nl * 4; break;
+    default: return fail(ctx, MSK_ERR_INVALID_ARG, "unknown field");
+  }
+  if (!src) return fail(ctx, MSK_ERR_INVALID_ARG, "field not recorded (walk log needs opts.record_log)");
+  HIP_TRY(ctx, hipMemcpyAsync(dst, src, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MSK_OK;
+}
+
+extern "C" void msk_dtn_destroy(msk_dtn* d) {
+  if (!d) return;
+  dtn_free(d);
+  delete d;
+}
+
+extern "C" msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* dtn, int32_t k, double* evals, double* evecs,
+                                        msk_eig_stats* stats) {
+  return fail(ctx, MSK_ERR_INVALID_ARG, "eigen step not available in this build");
+}

@@ -1,0 +1,144 @@
+// Internal layouts shared by the host code and the HIP kernels of libmsk.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace msk {
+
+// 4-wide BVH node, one 128-byte line. Child k's box is
+// [lo{x,y,z}[k], hi{x,y,z}[k]]; child[k] >= 0 is an inner node index,
+// child[k] < 0 a leaf holding triangle slots [-child[k]-1, -child[k]-1+count[k]).
+// An unused slot has an empty box (lo = +inf, hi = -inf) and count 0.
+struct alignas(128) Node4 {
+  float lox[4], loy[4], loz[4];
+  float hix[4], hiy[4], hiz[4];
+  int32_t child[4];
+  int32_t count[4];
+};
+static_assert(sizeof(Node4) == 128, "node must be one 128-byte line");
+
+// Triangle in BVH leaf order: vertices as float offsets from the scene
+// centre; a.w holds the original triangle index (bit pattern of an int32).
+struct alignas(16) TriRec {
+  float4 a, b, c;
+};
+static_assert(sizeof(TriRec) == 48, "triangle record must be 48 bytes");
+
+constexpr int kStackDepth = 64;     // traversal stack entries per lane
+constexpr int kMaxTableNnz = 32;    // basis entries per vertex
+constexpr int kMaxTop = 128;        // BVH nodes a workgroup may keep in LDS
+
+// Host-side BVH build result.
+struct HostBvh {
+  double centre[3];
+  double radius;
+  double area;
+  std::vector<Node4> nodes;
+  std::vector<TriRec> tris;
+  std::vector<int32_t> slot_of_tri;  // original triangle -> leaf-order slot
+  int depth = 0;                     // levels of 4-wide nodes
+  int leaf_size = 4;
+};
+
+// Builds the scene frame and a 4-wide BVH over float offsets from the
+// centre. Returns an empty string on success, else an error message.
+std::string build_bvh_host(const float* V, int64_t nv, const int32_t* F, int64_t nf, int leaf_size, HostBvh& out);
+
+// ------------------------------------------------------------ kernel ABI
+
+enum RowMode : int32_t { kRowsPoint = 0, kRowsHatRing = 1 };
+enum WalkStatus : int32_t { kHit = 0, kEscaped = 1, kCapped = 2 };
+
+// Everything a walk needs about one mesh (device pointers).
+struct MeshDev {
+  const Node4* nodes;
+  const TriRec* tris;
+  const int32_t* slot_of_tri;  // original face -> slot
+  const int32_t* faces;        // original faces (n_tris x 3)
+  int64_t n_tris;
+  int32_t n_top;               // nodes of this mesh that may be read from LDS
+  int32_t mode;                // RowMode
+  float radius;                // bounding-sphere radius (float)
+  double radius_d;
+  float eps2;                  // eps^2
+  float inset;                 // h (walk geometry)
+  double inset_d;              // h (scaling of the estimate)
+  float kappa;                 // relative step shrink
+  float delta;                 // absolute step shrink (delta_rel * radius)
+  float slack;                 // absolute error allowance of the FP32 distance
+  int32_t side;                // 0 interior, 1 exterior
+  int32_t mesh_id;             // low 24 bits of the fourth Philox counter word
+  int32_t walks_per_row;       // W
+  int64_t max_steps;
+  // rows (original order)
+  const float* p;              // point rows: scene-frame float positions (n x 3)
+  const float* n;              // point rows: unit normals (n x 3)
+  const int32_t* tri;          // point rows: face
+  const float* bary;           // point rows: barycentrics (n x 3)
+  const int32_t* ring_ptr;     // hat rows
+  const int32_t* ring_tri;
+  const double* ring_cum;
+  const float* face_normals;
+  const int32_t* discarded;    // per row (point rows)
+  // basis table
+  const int32_t* b_rowptr;
+  const int32_t* b_col;
+  const float* b_val;
+  int64_t K;
+  // accumulators (original row order)
+  double* acc1;                // point rows: sum b(t); hat rows: sum c
+  double* acc2;                // point rows: sum b(t)^2; hat rows: sum c^2
+  unsigned long long* row_queries;
+  unsigned long long* row_escaped;
+  unsigned long long* row_capped;
+  // optional walk log, (row, walk) -> row * W + walk - walk_offset
+  int32_t* log_status;
+  int32_t* log_tri;
+  float* log_bary;
+  int32_t* log_queries;
+};
+
+// A unit of queued work: one row of one mesh; walk ids are slot * W + w.
+struct RowSlot {
+  int32_t mesh;
+  int32_t row;
+};
+
+struct WalkLaunch {
+  const MeshDev* meshes;       // device array
+  const RowSlot* slots;        // device array, n_slots
+  int64_t n_slots;
+  int64_t walks_per_slot;      // W
+  int64_t walk_offset;         // first walk index
+  uint32_t seed_lo, seed_hi;
+  // persistent form: 8 queues over contiguous slot ranges
+  unsigned long long* queue_next;  // 8 counters (walk ids)
+  const unsigned long long* queue_end;  // 8 bounds
+  int32_t chunk;
+  int32_t regen_min;
+  int32_t use_lds_top;         // single-mesh launch: stage mesh 0's top nodes in LDS
+  int32_t n_top;
+  unsigned long long* stats;   // optional: [nodes visited, triangles tested, FP32 operations]
+};
+
+}  // namespace msk
+
+namespace msk {
+// kernel launch wrappers (walk.hip)
+hipError_t launch_walk_plain(const WalkLaunch& L, hipStream_t s);
+hipError_t launch_walk_persistent(const WalkLaunch& L, int grid, hipStream_t s);
+struct QueueInit {
+  unsigned long long begin[8], end[8];
+};
+hipError_t launch_init_queues(unsigned long long* next, unsigned long long* end, const QueueInit& q, hipStream_t s);
+hipError_t launch_fill_u64(void* p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_discard(const MeshDev& M, int64_t n_rows, int32_t* discarded, hipStream_t s);
+hipError_t launch_closest_points(const Node4* nodes, const TriRec* tris, float radius, const double* c, const float* Q,
+                                 int64_t nq, int32_t* tri, float* d2, float* bary, hipStream_t s);
+hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walks, const double* w, double* S,
+                           double* se, hipStream_t s);
+}  // namespace msk

@@ -1,0 +1,779 @@
+// HIP kernels of the Walk-on-Spheres DtN estimator for gfx950.
+//
+// One wavefront lane carries one walk. Each step asks the BVH for the exact
+// nearest triangle (the empty-ball radius, Sec. 2 "Walk-on-Spheres"), stops
+// in the eps-shell, and otherwise jumps to a uniform point of the ball. The
+// walk's hit is scattered into its row as c = b(s) - b(t) (Sec. 3.1, Alg. 1,
+// eq. naive-stiffness-matrix). The persistent form keeps every lane busy by
+// refilling finished lanes from a work queue (walks of a wavefront have very
+// different lengths), with one queue per XCD over a contiguous, Z-ordered
+// range of rows so that each XCD's L2 sees one region of the surface.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstring>
+
+#include "msk_internal.h"
+
+namespace msk {
+
+// ------------------------------------------------------------ Philox4x32-10
+// Counter-based generator of Salmon et al. (SC 2011): ten rounds of two
+// 32x32->64-bit multiplies with Weyl-sequence round keys.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// Top 23 bits -> centre of one of 2^23 cells of (0,1); exact in binary32.
+__device__ __forceinline__ float unit_f(uint32_t r) { return ((float)(r >> 9) + 0.5f) * (1.0f / 8388608.0f); }
+
+enum : uint32_t { kPurposeStep = 0, kPurposeHatStart = 1, kPurposeSplit = 2, kPurposeReentry = 3 };
+
+__device__ __forceinline__ uint4 draw(const WalkLaunch& L, uint32_t row, uint32_t walk, uint32_t step,
+                                      uint32_t purpose, uint32_t mesh) {
+  return philox10(make_uint4(row, walk, step, (purpose << 24) | (mesh & 0xFFFFFFu)), L.seed_lo, L.seed_hi);
+}
+
+// --------------------------------------------------- FP32 closest point
+// Squared distance from p to triangle T, evaluated in a fixed order with
+// every product and sum rounded on its own (no contraction into FMA), so
+// that it is reproducible bit for bit: Voronoi regions tested in the order
+// vertex a, vertex b, edge ab, vertex c, edge ac, edge bc, face; face-region
+// numerators n.(u x v) with n = ab x ac; face distance (n.ap)^2 / (n.n).
+// (l1, l2) are the barycentric weights of vertices b and c.
+__host__ __device__ __forceinline__ float tri_dist2(float px, float py, float pz, const TriRec& T, float& l1, float& l2,
+                                                   int& region) {
+#pragma clang fp contract(off)
+  const float ax = T.a.x, ay = T.a.y, az = T.a.z;
+  const float bx = T.b.x, by = T.b.y, bz = T.b.z;
+  const float cx = T.c.x, cy = T.c.y, cz = T.c.z;
+  const float abx = bx - ax, aby = by - ay, abz = bz - az;
+  const float acx = cx - ax, acy = cy - ay, acz = cz - az;
+  const float apx = px - ax, apy = py - ay, apz = pz - az;
+  float t;
+  t = abx * apx; t = t + aby * apy; const float d1 = t + abz * apz;
+  t = acx * apx; t = t + acy * apy; const float d2 = t + acz * apz;
+  if (d1 <= 0.0f && d2 <= 0.0f) {
+    l1 = 0.0f; l2 = 0.0f; region = 0;
+    t = apx * apx; t = t + apy * apy; return t + apz * apz;
+  }
+  const float bpx = px - bx, bpy = py - by, bpz = pz - bz;
+  t = abx * bpx; t = t + aby * bpy; const float d3 = t + abz * bpz;
+  t = acx * bpx; t = t + acy * bpy; const float d4 = t + acz * bpz;
+  if (d3 >= 0.0f && d4 <= d3) {
+    l1 = 1.0f; l2 = 0.0f; region = 1;
+    t = bpx * bpx; t = t + bpy * bpy; return t + bpz * bpz;
+  }
+  const float nx = aby * acz - abz * acy;
+  const float ny = abz * acx - abx * acz;
+  const float nz = abx * acy - aby * acx;
+  float xx = apy * bpz - apz * bpy, xy = apz * bpx - apx * bpz, xz = apx * bpy - apy * bpx;
+  t = nx * xx; t = t + ny * xy; const float vc = t + nz * xz;
+  if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f) {
+    const float v = d1 / (d1 - d3);
+    const float ex = px - (ax + v * abx), ey = py - (ay + v * aby), ez = pz - (az + v * abz);
+    l1 = v; l2 = 0.0f; region = 2;
+    t = ex * ex; t = t + ey * ey; return t + ez * ez;
+  }
+  const float cpx = px - cx, cpy = py - cy, cpz = pz - cz;
+  t = abx * cpx; t = t + aby * cpy; const float d5 = t + abz * cpz;
+  t = acx * cpx; t = t + acy * cpy; const float d6 = t + acz * cpz;
+  if (d6 >= 0.0f && d5 <= d6) {
+    l1 = 0.0f; l2 = 1.0f; region = 3;
+    t = cpx * cpx; t = t + cpy * cpy; return t + cpz * cpz;
+  }
+  xx = cpy * apz - cpz * apy; xy = cpz * apx - cpx * apz; xz = cpx * apy - cpy * apx;
+  t = nx * xx; t = t + ny * xy; const float vb = t + nz * xz;
+  if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) {
+    const float w = d2 / (d2 - d6);
+    const float ex = px - (ax + w * acx), ey = py - (ay + w * acy), ez = pz - (az + w * acz);
+    l1 = 0.0f; l2 = w; region = 4;
+    t = ex * ex; t = t + ey * ey; return t + ez * ez;
+  }
+  xx = bpy * cpz - bpz * cpy; xy = bpz * cpx - bpx * cpz; xz = bpx * cpy - bpy * cpx;
+  t = nx * xx; t = t + ny * xy; const float va = t + nz * xz;
+  const float e43 = d4 - d3, e56 = d5 - d6;
+  if (va <= 0.0f && e43 >= 0.0f && e56 >= 0.0f) {
+    const float w = e43 / (e43 + e56);
+    const float bcx = cx - bx, bcy = cy - by, bcz = cz - bz;
+    const float ex = px - (bx + w * bcx), ey = py - (by + w * bcy), ez = pz - (bz + w * bcz);
+    l1 = 1.0f - w; l2 = w; region = 5;
+    t = ex * ex; t = t + ey * ey; return t + ez * ez;
+  }
+  const float den = (va + vb) + vc;
+  if (den > 0.0f) {
+    l1 = vb / den; l2 = vc / den; region = 6;
+    t = nx * apx; t = t + ny * apy; const float tn = t + nz * apz;
+    t = nx * nx; t = t + ny * ny; const float nn = t + nz * nz;
+    return (tn * tn) / nn;
+  }
+  // zero-area triangle: nearest point of the three edges, first strict minimum
+  float best = INFINITY, bl1 = 0.0f, bl2 = 0.0f;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const float s0x = s == 2 ? bx : ax, s0y = s == 2 ? by : ay, s0z = s == 2 ? bz : az;
+    const float s1x = s == 0 ? bx : cx, s1y = s == 0 ? by : cy, s1z = s == 0 ? bz : cz;
+    const float ex = s1x - s0x, ey = s1y - s0y, ez = s1z - s0z;
+    const float qx = px - s0x, qy = py - s0y, qz = pz - s0z;
+    t = ex * ex; t = t + ey * ey; const float ee = t + ez * ez;
+    t = qx * ex; t = t + qy * ey; const float qe = t + qz * ez;
+    float u = ee > 0.0f ? qe / ee : 0.0f;
+    if (u < 0.0f) u = 0.0f;
+    if (u > 1.0f) u = 1.0f;
+    const float rx = px - (s0x + u * ex), ry = py - (s0y + u * ey), rz = pz - (s0z + u * ez);
+    t = rx * rx; t = t + ry * ry; const float dd = t + rz * rz;
+    if (dd < best) {
+      best = dd;
+      bl1 = s == 0 ? u : (s == 1 ? 0.0f : 1.0f - u);
+      bl2 = s == 0 ? 0.0f : u;
+    }
+  }
+  l1 = bl1; l2 = bl2; region = 7;
+  return best;
+}
+
+// ------------------------------------------------------- BVH traversal
+// Squared-distance bound above which a box cannot hold a triangle whose FP32
+// distance is <= best: the FP32 distance of a triangle is at least
+// (d_true - slack)^2 (1 - 8u) with slack = 2^-18 (R + |p|_inf), and the FP32
+// box distance at most its true value times (1 + 6u).
+__host__ __device__ __forceinline__ float prune_bound(float best, float slack) {
+  const float s = sqrtf(best) * (1.0f + 0x1p-20f) + slack;
+  return s * s * (1.0f + 0x1p-20f);
+}
+
+struct Nearest {
+  float d2;
+  int32_t slot;
+  int32_t orig;
+  float l1, l2;
+};
+
+// FP32 operations of tri_dist2 up to each exit (vertex a, vertex b, edge ab,
+// vertex c, edge ac, edge bc, face, zero-area fallback); a box lower bound
+// costs 17 (6 subtractions, 6 maxima, 3 products, 2 sums).
+constexpr uint32_t kTriFlops[8] = {24, 37, 71, 73, 98, 117, 114, 175};
+constexpr uint32_t kBoxFlops = 17;
+
+struct TravCount {
+  uint32_t nodes = 0, tris = 0, flops = 0;
+};
+
+template <bool kStats>
+__host__ __device__ __forceinline__ void test_tri(const TriRec* __restrict__ tris, int32_t s, float px, float py, float pz,
+                                         Nearest& h, TravCount& cnt) {
+  const TriRec T = tris[s];
+  float l1, l2;
+  int region = 0;
+  const float d = tri_dist2(px, py, pz, T, l1, l2, region);
+  if (kStats) {
+    ++cnt.tris;
+    cnt.flops += kTriFlops[region & 7];
+  }
+  int32_t orig;
+  memcpy(&orig, &T.a.w, 4);
+  if (d < h.d2 || (d == h.d2 && orig < h.orig)) {
+    h.d2 = d; h.slot = s; h.orig = orig; h.l1 = l1; h.l2 = l2;
+  }
+}
+
+// Exact nearest triangle: lexicographic minimum of (FP32 squared distance,
+// original index). `h` may carry a candidate (warm start) on entry.
+template <bool kStats>
+__host__ __device__ void bvh_nearest(const Node4* __restrict__ nodes, const TriRec* __restrict__ tris, const Node4* lds,
+                                     int32_t n_lds, float px, float py, float pz, float radius, Nearest& h,
+                                     TravCount& cnt) {
+  const float slack = 0x1p-18f * (radius + fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
+  if (h.slot >= 0) {
+    const int32_t s = h.slot;
+    h.d2 = INFINITY; h.orig = INT_MAX; h.slot = -1;
+    test_tri<kStats>(tris, s, px, py, pz, h, cnt);
+  }
+  float thr = prune_bound(h.d2, slack);
+  int32_t stk_node[kStackDepth];
+  float stk_lb[kStackDepth];
+  int sp = 0;
+  int32_t node = 0;
+  while (true) {
+    float4 lox, loy, loz, hix, hiy, hiz;
+    int4 ch, ct;
+    if (kStats) {
+      ++cnt.nodes;
+      cnt.flops += 4 * kBoxFlops;
+    }
+    if (node < n_lds) {
+      const float4* N = (const float4*)&lds[node];
+      lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
+      ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
+    } else {
+      const float4* N = (const float4*)&nodes[node];
+      lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
+      ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
+    }
+    float lb[4];
+    int32_t cc[4], cn[4];
+    {
+      const float lx[4] = {lox.x, lox.y, lox.z, lox.w}, ly[4] = {loy.x, loy.y, loy.z, loy.w},
+                  lz[4] = {loz.x, loz.y, loz.z, loz.w};
+      const float hx[4] = {hix.x, hix.y, hix.z, hix.w}, hy[4] = {hiy.x, hiy.y, hiy.z, hiy.w},
+                  hz[4] = {hiz.x, hiz.y, hiz.z, hiz.w};
+      const int32_t c4[4] = {ch.x, ch.y, ch.z, ch.w}, n4[4] = {ct.x, ct.y, ct.z, ct.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float gx = fmaxf(fmaxf(lx[k] - px, px - hx[k]), 0.0f);
+        const float gy = fmaxf(fmaxf(ly[k] - py, py - hy[k]), 0.0f);
+        const float gz = fmaxf(fmaxf(lz[k] - pz, pz - hz[k]), 0.0f);
+        lb[k] = gx * gx + gy * gy + gz * gz;
+        cc[k] = c4[k];
+        cn[k] = n4[k];
+      }
+    }
+    // sort the four children by lower bound (5 compare-exchanges)
+#define MSK_CX(i, j)                                                        \
+  if (lb[j] < lb[i]) {                                                      \
+    float tl = lb[i]; lb[i] = lb[j]; lb[j] = tl;                            \
+    int32_t tc = cc[i]; cc[i] = cc[j]; cc[j] = tc;                          \
+    int32_t tn = cn[i]; cn[i] = cn[j]; cn[j] = tn;                          \
+  }
+    MSK_CX(0, 1) MSK_CX(2, 3) MSK_CX(0, 2) MSK_CX(1, 3) MSK_CX(1, 2)
+#undef MSK_CX
+    // leaves, nearest first
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (cc[k] < 0 && cn[k] > 0 && lb[k] <= thr) {
+        const int32_t first = -cc[k] - 1;
+        const float before = h.d2;
+        for (int32_t s = first; s < first + cn[k]; ++s) test_tri<kStats>(tris, s, px, py, pz, h, cnt);
+        if (h.d2 != before) thr = prune_bound(h.d2, slack);
+      }
+    }
+    // inner children, farthest pushed first
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+      if (cc[k] >= 0 && lb[k] <= thr && sp < kStackDepth) {
+        stk_node[sp] = cc[k];
+        stk_lb[sp] = lb[k];
+        ++sp;
+      }
+    }
+    node = -1;
+    while (sp > 0) {
+      --sp;
+      if (stk_lb[sp] <= thr) {
+        node = stk_node[sp];
+        break;
+      }
+    }
+    if (node < 0) break;
+  }
+}
+
+// ------------------------------------------------------ walk machinery
+
+struct LaneWalk {
+  float x, y, z;
+  int32_t row;
+  uint32_t walk;
+  int32_t mesh;
+  int32_t step;
+  int32_t queries;
+  int32_t slot;  // warm-start triangle slot
+  int32_t active;
+  TravCount cnt;  // traversal work of this walk (counted in the statistics kernels only)
+};
+
+// Start of a walk: sample s (point rows: the fixed sample; hat rows:
+// s ~ phi_i / A_i on the vertex's one-ring), inset it along the face normal.
+// Returns false if the row is discarded.
+__device__ bool walk_start(const WalkLaunch& L, const MeshDev& M, LaneWalk& w, int32_t& face, double lam[3]) {
+  const float sgn = M.side ? 1.0f : -1.0f;
+  float sx, sy, sz, nx, ny, nz;
+  if (M.mode == kRowsPoint) {
+    if (M.discarded[w.row]) return false;
+    face = M.tri[w.row];
+    sx = M.p[3 * w.row]; sy = M.p[3 * w.row + 1]; sz = M.p[3 * w.row + 2];
+    nx = M.n[3 * w.row]; ny = M.n[3 * w.row + 1]; nz = M.n[3 * w.row + 2];
+    lam[0] = M.bary[3 * w.row]; lam[1] = M.bary[3 * w.row + 1]; lam[2] = M.bary[3 * w.row + 2];
+  } else {
+    const uint4 u = draw(L, (uint32_t)w.row, w.walk, 0, kPurposeHatStart, (uint32_t)M.mesh_id);
+    const uint4 v = draw(L, (uint32_t)w.row, w.walk, 0, kPurposeSplit, (uint32_t)M.mesh_id);
+    const int32_t b0 = M.ring_ptr[w.row], b1 = M.ring_ptr[w.row + 1];
+    const double target = (double)unit_f(u.x) * M.ring_cum[b1 - 1];
+    int32_t e = b0;
+    while (e < b1 - 1 && !(M.ring_cum[e] > target)) ++e;
+    face = M.ring_tri[e];
+    const float m1 = unit_f(u.y), m2 = unit_f(u.z), m3 = unit_f(u.w);
+    const float li = fmaxf(fminf(m1, m2), fminf(fmaxf(m1, m2), m3));  // median: Beta(2,2)
+    const float sv = unit_f(v.x);
+    const int32_t* f = M.faces + 3 * (int64_t)face;
+    const int corner = f[0] == w.row ? 0 : (f[1] == w.row ? 1 : 2);
+    // products of 24-bit values are exact in FP64: the weights sum to 1
+    const double la = (1.0 - (double)li) * (double)sv, lb = (1.0 - (double)li) * (1.0 - (double)sv);
+    lam[0] = corner == 0 ? (double)li : la;
+    lam[1] = corner == 1 ? (double)li : (corner == 0 ? la : lb);
+    lam[2] = corner == 2 ? (double)li : lb;
+    const TriRec T = M.tris[M.slot_of_tri[face]];
+    const float l0 = (float)lam[0], l1 = (float)lam[1], l2 = (float)lam[2];
+    sx = l0 * T.a.x + l1 * T.b.x + l2 * T.c.x;
+    sy = l0 * T.a.y + l1 * T.b.y + l2 * T.c.y;
+    sz = l0 * T.a.z + l1 * T.b.z + l2 * T.c.z;
+    nx = M.face_normals[3 * face]; ny = M.face_normals[3 * face + 1]; nz = M.face_normals[3 * face + 2];
+  }
+  const float h = M.inset;
+  w.x = sx + sgn * h * nx;
+  w.y = sy + sgn * h * ny;
+  w.z = sz + sgn * h * nz;
+  w.slot = M.slot_of_tri[face];
+  w.step = 0;
+  w.queries = 0;
+  w.cnt = TravCount();
+  return true;
+}
+
+// Sparse merge of up to NH sorted table rows with weights: emits each column
+// once with sum_h weight_h * value_h (FP64).
+template <int NH, typename Emit>
+__device__ __forceinline__ void merge_rows(const MeshDev& M, const int32_t (&vtx)[NH], const double (&wt)[NH],
+                                           Emit emit) {
+  int32_t p[NH], e[NH];
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    if (vtx[k] >= 0 && wt[k] != 0.0) {
+      p[k] = M.b_rowptr[vtx[k]];
+      e[k] = M.b_rowptr[vtx[k] + 1];
+    } else {
+      p[k] = 0;
+      e[k] = 0;
+    }
+  }
+  while (true) {
+    int32_t cmin = INT_MAX;
+    int32_t col[NH];
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+      col[k] = p[k] < e[k] ? M.b_col[p[k]] : INT_MAX;
+      cmin = min(cmin, col[k]);
+    }
+    if (cmin == INT_MAX) break;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+      if (col[k] == cmin) {
+        v += wt[k] * (double)M.b_val[p[k]];
+        ++p[k];
+      }
+    }
+    emit(cmin, v);
+  }
+}
+
+// Scatter a finished walk into its row and counters.
+__device__ void walk_finish(const WalkLaunch& L, const MeshDev& M, const LaneWalk& w, int32_t status,
+                            const Nearest& hit) {
+  const bool has_t = status != kEscaped && hit.orig >= 0 && hit.orig < M.n_tris;
+  double* a1 = M.acc1 + (int64_t)w.row * M.K;
+  double* a2 = M.acc2 + (int64_t)w.row * M.K;
+  int32_t tv[3] = {-1, -1, -1};
+  double tw[3] = {0.0, 0.0, 0.0};
+  if (has_t) {
+    const int32_t* f = M.faces + 3 * (int64_t)hit.orig;
+    tv[0] = f[0]; tv[1] = f[1]; tv[2] = f[2];
+    const double l1 = hit.l1, l2 = hit.l2;
+    tw[0] = (1.0 - l1) - l2; tw[1] = l1; tw[2] = l2;
+  }
+  if (M.mode == kRowsPoint) {
+    // the start is fixed per row: accumulate b(t) and b(t)^2 only; the
+    // finalisation folds in b(s)
+    if (has_t)
+      merge_rows<3>(M, tv, tw, [&](int32_t j, double v) {
+        atomicAdd(a1 + j, v);
+        atomicAdd(a2 + j, v * v);
+      });
+  } else {
+    int32_t face;
+    double lam[3];
+    LaneWalk tmp = w;
+    walk_start(L, M, tmp, face, lam);
+    const int32_t* f = M.faces + 3 * (int64_t)face;
+    const int32_t vv[6] = {f[0], f[1], f[2], tv[0], tv[1], tv[2]};
+    const double ww[6] = {lam[0], lam[1], lam[2], -tw[0], -tw[1], -tw[2]};
+    merge_rows<6>(M, vv, ww, [&](int32_t j, double v) {
+      atomicAdd(a1 + j, v);
+      atomicAdd(a2 + j, v * v);
+    });
+  }
+  atomicAdd(M.row_queries + w.row, (unsigned long long)w.queries);
+  if (L.stats) {
+    atomicAdd(L.stats, (unsigned long long)w.cnt.nodes);
+    atomicAdd(L.stats + 1, (unsigned long long)w.cnt.tris);
+    atomicAdd(L.stats + 2, (unsigned long long)w.cnt.flops);
+  }
+  if (status == kEscaped) atomicAdd(M.row_escaped + w.row, 1ull);
+  if (status == kCapped) atomicAdd(M.row_capped + w.row, 1ull);
+  if (M.log_status) {
+    const int64_t li = (int64_t)w.row * M.walks_per_row + ((int64_t)w.walk - L.walk_offset);
+    M.log_status[li] = status;
+    M.log_tri[li] = has_t ? hit.orig : -1;
+    M.log_bary[2 * li] = has_t ? hit.l1 : 0.0f;
+    M.log_bary[2 * li + 1] = has_t ? hit.l2 : 0.0f;
+    M.log_queries[li] = w.queries;
+  }
+}
+
+// Orthonormal frame (e1, e2) completing a unit vector n (branchless, after
+// Duff et al. 2017).
+__device__ __forceinline__ void onb(double nx, double ny, double nz, double e1[3], double e2[3]) {
+  const double sg = nz >= 0 ? 1.0 : -1.0;
+  const double a = -1.0 / (sg + nz);
+  const double b = nx * ny * a;
+  e1[0] = 1.0 + sg * nx * nx * a; e1[1] = sg * b; e1[2] = -sg * nx;
+  e2[0] = b; e2[1] = sg + ny * ny * a; e2[2] = -ny;
+}
+
+// One step of a live walk. Returns -1 while the walk continues, else its
+// final status (hit / escaped / capped) with `hit` set for hits and caps.
+template <bool kStats>
+__device__ int32_t walk_step(const WalkLaunch& L, const MeshDev& M, const Node4* lds, int32_t n_lds, LaneWalk& w,
+                             Nearest& hit) {
+  const uint4 u = draw(L, (uint32_t)w.row, w.walk, (uint32_t)w.step, kPurposeStep, (uint32_t)M.mesh_id);
+  const float rho2 = w.x * w.x + w.y * w.y + w.z * w.z;
+  const double rho = rho2 > M.radius * M.radius * (1.0f - 0x1p-18f)
+                         ? sqrt((double)w.x * w.x + (double)w.y * w.y + (double)w.z * w.z)
+                         : 0.0;
+  if (rho > M.radius_d) {
+    // Outside the bounding sphere: escape with probability 1 - R/rho, else
+    // jump to the exact first hitting point of the sphere (density ~
+    // |x-y|^-3, inverted in closed form).
+    const double R = M.radius_d;
+    if ((double)unit_f(u.z) < 1.0 - R / rho) return kEscaped;
+    const double a = rho * rho + R * R, b = 2.0 * rho * R;
+    const double qi = 1.0 / (rho + R) + (double)unit_f(u.w) * (1.0 / (rho - R) - 1.0 / (rho + R));
+    const double mu = fmin(1.0, fmax(-1.0, (a - 1.0 / (qi * qi)) / b));
+    const uint4 v = draw(L, (uint32_t)w.row, w.walk, (uint32_t)w.step, kPurposeReentry, (uint32_t)M.mesh_id);
+    const double phi = 6.283185307179586 * (double)unit_f(v.x);
+    const double nx = w.x / rho, ny = w.y / rho, nz = w.z / rho;
+    double e1[3], e2[3];
+    onb(nx, ny, nz, e1, e2);
+    const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    w.x = (float)(R * (mu * nx + st * (cp * e1[0] + sp * e2[0])));
+    w.y = (float)(R * (mu * ny + st * (cp * e1[1] + sp * e2[1])));
+    w.z = (float)(R * (mu * nz + st * (cp * e1[2] + sp * e2[2])));
+    // the walk goes on from the sphere in this same step (u.x, u.y unused so far)
+  }
+  hit.d2 = INFINITY;
+  hit.orig = INT_MAX;
+  hit.slot = w.slot;
+  bvh_nearest<kStats>(M.nodes, M.tris, lds, n_lds, w.x, w.y, w.z, M.radius, hit, w.cnt);
+  ++w.queries;
+  w.slot = hit.slot;
+  if (hit.d2 < M.eps2) return kHit;
+  const float r = sqrtf(hit.d2) * (1.0f - M.kappa) - M.delta;
+  const float u0 = unit_f(u.x), u1 = unit_f(u.y);
+  const float z = 1.0f - 2.0f * u0;
+  const float rxy = 2.0f * sqrtf(u0 * (1.0f - u0));
+  // v_sin/v_cos take the angle in revolutions: sin(2 pi u1), cos(2 pi u1)
+  const float sn = __builtin_amdgcn_sinf(u1), cs = __builtin_amdgcn_cosf(u1);
+  w.x += r * rxy * cs;
+  w.y += r * rxy * sn;
+  w.z += r * z;
+  ++w.step;
+  return w.step >= M.max_steps ? kCapped : -1;
+}
+
+// A capped walk ends at the nearest boundary point of its last position.
+template <bool kStats>
+__device__ void cap_walk(const MeshDev& M, const Node4* lds, int32_t n_lds, LaneWalk& w, Nearest& hit) {
+  hit.d2 = INFINITY;
+  hit.orig = INT_MAX;
+  hit.slot = w.slot;
+  bvh_nearest<kStats>(M.nodes, M.tris, lds, n_lds, w.x, w.y, w.z, M.radius, hit, w.cnt);
+  ++w.queries;
+}
+
+__device__ __forceinline__ void decode_walk(const WalkLaunch& L, uint64_t g, LaneWalk& w) {
+  const uint64_t slot = g / (uint64_t)L.walks_per_slot;
+  const RowSlot rs = L.slots[slot];
+  w.mesh = rs.mesh;
+  w.row = rs.row;
+  w.walk = (uint32_t)((int64_t)(g - slot * (uint64_t)L.walks_per_slot) + L.walk_offset);
+}
+
+// ------------------------------------------------------------- kernels
+
+// Plain form: one thread per walk, run to completion.
+template <bool kStats>
+__global__ void __launch_bounds__(256) walk_plain_kernel(WalkLaunch L) {
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (uint64_t)L.n_slots * (uint64_t)L.walks_per_slot) return;
+  LaneWalk w;
+  decode_walk(L, g, w);
+  const MeshDev& M = L.meshes[w.mesh];
+  int32_t face;
+  double lam[3];
+  if (!walk_start(L, M, w, face, lam)) return;
+  Nearest hit;
+  int32_t st;
+  do {
+    st = walk_step<kStats>(L, M, nullptr, 0, w, hit);
+  } while (st < 0);
+  if (st == kCapped) cap_walk<kStats>(M, nullptr, 0, w, hit);
+  walk_finish(L, M, w, st, hit);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Persistent form: each wavefront keeps its 64 lanes busy by refilling
+// finished lanes with the next walks of its queue chunk; chunks come from
+// one of eight queues (one per XCD, blockIdx % 8) and wavefronts move on to
+// the other queues once their own is drained.
+template <bool kStats>
+__global__ void __launch_bounds__(256) walk_persistent_kernel(WalkLaunch L) {
+  __shared__ Node4 top[kMaxTop];
+  int32_t n_lds = 0;
+  if (L.use_lds_top) {
+    n_lds = L.n_top;
+    const MeshDev& M0 = L.meshes[0];
+    const int4* src = (const int4*)M0.nodes;
+    int4* dst = (int4*)top;
+    for (int i = threadIdx.x; i < n_lds * 8; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+  }
+  const int qhome = blockIdx.x & 7;
+  int qi = 0;  // queues tried so far (uniform)
+  uint64_t cur = 0, cend = 0;
+  LaneWalk w;
+  w.active = 0;
+  Nearest hit;
+  bool drained = false;
+  while (true) {
+    // ---- refill idle lanes (wave-uniform control)
+    uint64_t idle = __ballot(!w.active);
+    if (!drained && idle != 0 && (int)__popcll(idle) >= L.regen_min) {
+      while (idle != 0 && !drained) {
+        if (cur >= cend) {
+          uint64_t start = 0;
+          if (lane_id() == 0) {
+            const int q = (qhome + qi) & 7;
+            start = atomicAdd(L.queue_next + q, (unsigned long long)L.chunk);
+          }
+          start = (uint64_t)__shfl((unsigned long long)start, 0);
+          const int q = (qhome + qi) & 7;
+          const uint64_t qend = L.queue_end[q];
+          if (start >= qend) {
+            ++qi;
+            if (qi >= 8) drained = true;
+            continue;
+          }
+          cur = start;
+          cend = min(start + (uint64_t)L.chunk, qend);
+        }
+        const uint32_t rank = __popcll(idle & ((1ull << lane_id()) - 1ull));
+        const uint64_t avail = cend - cur;
+        const uint32_t take = (uint32_t)min(avail, (uint64_t)__popcll(idle));
+        if (!w.active && rank < take) {
+          decode_walk(L, cur + rank, w);
+          int32_t face;
+          double lam[3];
+          const MeshDev& M = L.meshes[w.mesh];
+          w.active = walk_start(L, M, w, face, lam) ? 1 : 0;
+        }
+        cur += take;
+        idle = __ballot(!w.active);
+        // lanes whose row was discarded stay idle; keep filling
+      }
+    }
+    if (__ballot(w.active) == 0) {
+      if (drained) break;
+      continue;
+    }
+    // ---- one step of every live walk
+    if (w.active) {
+      const MeshDev& M = L.meshes[w.mesh];
+      const int32_t nl = (w.mesh == 0) ? n_lds : 0;
+      const int32_t st = walk_step<kStats>(L, M, top, nl, w, hit);
+      if (st >= 0) {
+        if (st == kCapped) cap_walk<kStats>(M, top, nl, w, hit);
+        walk_finish(L, M, w, st, hit);
+        w.active = 0;
+      }
+    }
+  }
+}
+
+__global__ void init_queues_kernel(unsigned long long* next, unsigned long long* end, QueueInit q) {
+  const int i = threadIdx.x;
+  if (i < 8) {
+    next[i] = q.begin[i];
+    end[i] = q.end[i];
+  }
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Point rows whose inset point is closer than h/2 to the surface are
+// discarded (the inset left the thin region it should probe).
+__global__ void discard_kernel(MeshDev M, int64_t n_rows, int32_t* discarded) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows) return;
+  const float sgn = M.side ? 1.0f : -1.0f;
+  const float x = M.p[3 * i] + sgn * M.inset * M.n[3 * i];
+  const float y = M.p[3 * i + 1] + sgn * M.inset * M.n[3 * i + 1];
+  const float z = M.p[3 * i + 2] + sgn * M.inset * M.n[3 * i + 2];
+  Nearest h;
+  h.d2 = INFINITY; h.orig = INT_MAX; h.slot = M.slot_of_tri[M.tri[i]];
+  TravCount cnt;
+  bvh_nearest<false>(M.nodes, M.tris, nullptr, 0, x, y, z, M.radius, h, cnt);
+  discarded[i] = h.d2 < 0.25f * M.inset * M.inset ? 1 : 0;
+  atomicAdd(M.row_queries + i, 1ull);
+}
+
+__global__ void closest_points_kernel(const Node4* __restrict__ nodes, const TriRec* __restrict__ tris, float radius,
+                                      double cx, double cy, double cz, const float* __restrict__ Q, int64_t nq,
+                                      int32_t* tri, float* d2, float* bary) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const float x = (float)((double)Q[3 * i] - cx);
+  const float y = (float)((double)Q[3 * i + 1] - cy);
+  const float z = (float)((double)Q[3 * i + 2] - cz);
+  Nearest h;
+  h.d2 = INFINITY; h.orig = INT_MAX; h.slot = -1;
+  TravCount cnt;
+  bvh_nearest<false>(nodes, tris, nullptr, 0, x, y, z, radius, h, cnt);
+  tri[i] = h.orig;
+  d2[i] = h.d2;
+  bary[2 * i] = h.l1;
+  bary[2 * i + 1] = h.l2;
+}
+
+// S_ij = (w_i / h) mean_ij, se_ij = (w_i / h) sqrt(var_ij / W_i), var with
+// the unbiased (W-1) normalisation. Point rows hold sums of b(t) here and
+// the entries where b(s) != 0 are corrected by finalize_point_fix_kernel.
+__global__ void finalize_kernel(MeshDev M, int64_t n_rows, const int64_t* __restrict__ walks,
+                                const double* __restrict__ w, double* S, double* se) {
+  const int64_t n = n_rows * M.K;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / M.K;
+    const double Wi = (double)walks[i];
+    const double scale = (M.mode == kRowsPoint && M.discarded[i]) ? 0.0 : w[i] / M.inset_d;
+    const double s1 = M.mode == kRowsPoint ? -M.acc1[idx] : M.acc1[idx];
+    const double mean = s1 / Wi;
+    const double var = fmax(0.0, M.acc2[idx] / Wi - mean * mean) * (Wi / (Wi - 1.0));
+    S[idx] = scale * mean;
+    se[idx] = scale * sqrt(var / Wi);
+  }
+}
+
+__global__ void finalize_point_fix_kernel(MeshDev M, int64_t n_rows, const int64_t* __restrict__ walks,
+                                          const double* __restrict__ w, double* S, double* se) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows || M.discarded[i]) return;
+  const int32_t* f = M.faces + 3 * (int64_t)M.tri[i];
+  const int32_t vv[3] = {f[0], f[1], f[2]};
+  const double ww[3] = {(double)M.bary[3 * i], (double)M.bary[3 * i + 1], (double)M.bary[3 * i + 2]};
+  const double Wi = (double)walks[i];
+  const double scale = w[i] / M.inset_d;
+  merge_rows<3>(M, vv, ww, [&](int32_t j, double bs) {
+    const int64_t idx = i * M.K + j;
+    const double t1 = M.acc1[idx], t2 = M.acc2[idx];
+    const double s1 = Wi * bs - t1;
+    const double s2 = Wi * bs * bs - 2.0 * bs * t1 + t2;
+    const double mean = s1 / Wi;
+    const double var = fmax(0.0, s2 / Wi - mean * mean) * (Wi / (Wi - 1.0));
+    S[idx] = scale * mean;
+    se[idx] = scale * sqrt(var / Wi);
+  });
+}
+
+}  // namespace msk
+
+// ------------------------------------------------------ launch wrappers
+
+namespace msk {
+
+static inline int blocks_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 1 << 20); }
+
+hipError_t launch_walk_plain(const WalkLaunch& L, hipStream_t s) {
+  const int64_t n = L.n_slots * L.walks_per_slot;
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + 255) / 256;
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  if (L.stats)
+    hipLaunchKernelGGL(walk_plain_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, L);
+  else
+    hipLaunchKernelGGL(walk_plain_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_persistent(const WalkLaunch& L, int grid, hipStream_t s) {
+  if (L.stats)
+    hipLaunchKernelGGL(walk_persistent_kernel<true>, dim3(grid), dim3(256), 0, s, L);
+  else
+    hipLaunchKernelGGL(walk_persistent_kernel<false>, dim3(grid), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_queues(unsigned long long* next, unsigned long long* end, const QueueInit& q, hipStream_t s) {
+  hipLaunchKernelGGL(init_queues_kernel, dim3(1), dim3(64), 0, s, next, end, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(void* p, int64_t n, unsigned long long v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, (unsigned long long*)p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, (uint32_t*)p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_discard(const MeshDev& M, int64_t n_rows, int32_t* discarded, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(discard_kernel, dim3(blocks_for(n_rows, 128)), dim3(128), 0, s, M, n_rows, discarded);
+  return hipGetLastError();
+}
+
+hipError_t launch_closest_points(const Node4* nodes, const TriRec* tris, float radius, const double* c, const float* Q,
+                                 int64_t nq, int32_t* tri, float* d2, float* bary, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  if ((nq + 127) / 128 > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(closest_points_kernel, dim3((unsigned)((nq + 127) / 128)), dim3(128), 0, s, nodes, tris, radius,
+                     c[0], c[1], c[2], Q, nq, tri, d2, bary);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walks, const double* w, double* S,
+                           double* se, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(n_rows * M.K, 256)), dim3(256), 0, s, M, n_rows, walks, w, S, se);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || M.mode != kRowsPoint) return e;
+  hipLaunchKernelGGL(finalize_point_fix_kernel, dim3(blocks_for(n_rows, 128)), dim3(128), 0, s, M, n_rows, walks, w, S,
+                     se);
+  return hipGetLastError();
+}
+
+}  // namespace msk

@@ -1,0 +1,317 @@
+"""Python binding of libmsk (include/msk.h): argument marshalling only.
+
+Every step of the estimator runs in the HIP library; this module turns numpy
+arrays and torch tensors into the plain pointers and sizes of the C ABI. It
+raises if the library has not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsk.so")
+
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_DEVICE, ERR_NOT_CONVERGED, ERR_NUMERIC = range(6)
+ROWS_POINT, ROWS_HAT_RING = 0, 1
+INTERIOR, EXTERIOR = 0, 1
+FORM_PERSISTENT, FORM_PLAIN = 0, 1
+(FIELD_S, FIELD_SE, FIELD_ROW_WALKS, FIELD_ROW_QUERIES, FIELD_ROW_ESCAPED, FIELD_ROW_CAPPED, FIELD_ROW_DISCARDED,
+ FIELD_LOG_STATUS, FIELD_LOG_TRI, FIELD_LOG_BARY, FIELD_LOG_QUERIES) = range(11)
+
+_STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "NUMERIC"}
+
+
+class MskError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BvhOpts(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32), ("top_nodes", C.c_int32)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("centre", C.c_double * 3), ("radius", C.c_double), ("area", C.c_double), ("n_verts", C.c_int64),
+                ("n_tris", C.c_int64), ("n_nodes", C.c_int64), ("node_bytes", C.c_int64), ("tri_bytes", C.c_int64),
+                ("depth", C.c_int32), ("leaf_size", C.c_int32)]
+
+
+class RowsDesc(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("n_rows", C.c_int64), ("w", C.c_void_p), ("p", C.c_void_p), ("n", C.c_void_p),
+                ("tri", C.c_void_p), ("bary", C.c_void_p), ("ring_ptr", C.c_void_p), ("ring_tri", C.c_void_p),
+                ("ring_cum", C.c_void_p), ("face_normals", C.c_void_p)]
+
+
+class DtnOpts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("max_steps", C.c_int64), ("walk_offset", C.c_int64), ("kappa", C.c_double),
+                ("delta_rel", C.c_double), ("form", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("chunk", C.c_int32), ("regen_min", C.c_int32), ("record_log", C.c_int32), ("se_target", C.c_double),
+                ("walks_max", C.c_int64), ("collect_stats", C.c_int32)]
+
+
+class DtnInfo(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("K", C.c_int64), ("walks_total", C.c_int64), ("queries_total", C.c_int64),
+                ("escaped_total", C.c_int64), ("capped_total", C.c_int64), ("discarded_rows", C.c_int64),
+                ("walk_kernel_ms", C.c_double), ("total_ms", C.c_double), ("walk_launches", C.c_int32),
+                ("nodes_visited", C.c_int64), ("tris_tested", C.c_int64), ("valu_flops", C.c_int64)]
+
+
+class EigStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("block", C.c_int32), ("max_residual", C.c_double),
+                ("lanczos_ms", C.c_double)]
+
+
+_lib = None
+
+# symbol name -> (argtypes, restype); the C ABI declared in include/msk.h
+SIGNATURES = {
+    "msk_create": ([C.c_int, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "msk_destroy": ([C.c_void_p], None),
+    "msk_last_error": ([C.c_void_p], C.c_char_p),
+    "msk_build_bvh": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.POINTER(BvhOpts),
+                       C.POINTER(C.c_void_p)], C.c_int),
+    "msk_mesh_get_info": ([C.c_void_p, C.POINTER(MeshInfo)], C.c_int),
+    "msk_mesh_destroy": ([C.c_void_p], None),
+    "msk_closest_points": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
+                           C.c_int),
+    "msk_rows_create": ([C.c_void_p, C.c_void_p, C.POINTER(RowsDesc), C.POINTER(C.c_void_p)], C.c_int),
+    "msk_rows_destroy": ([C.c_void_p], None),
+    "msk_basis_create": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                          C.POINTER(C.c_void_p)], C.c_int),
+    "msk_basis_destroy": ([C.c_void_p], None),
+    "msk_dtn_opts_default": ([C.POINTER(DtnOpts)], None),
+    "msk_estimate_dtn": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_int32,
+                          C.POINTER(DtnOpts), C.POINTER(C.c_void_p)], C.c_int),
+    "msk_estimate_dtn_batched": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int64,
+                                  C.c_int32, C.POINTER(DtnOpts), C.POINTER(C.c_void_p)], C.c_int),
+    "msk_dtn_get_info": ([C.c_void_p, C.POINTER(DtnInfo)], C.c_int),
+    "msk_dtn_get": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_int32], C.c_int),
+    "msk_dtn_destroy": ([C.c_void_p], None),
+    "msk_steklov_modes": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(EigStats)], C.c_int),
+}
+
+
+def lib():
+    """Load libmsk.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (paper_2606_05581_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _np(a, dt):
+    a = np.ascontiguousarray(a, dtype=dt)
+    return a, a.ctypes.data
+
+
+def _dev_ptr(t, dtype):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous CUDA tensor of {dtype}")
+    return t.data_ptr()
+
+
+class Context:
+    """A library context on one device, queuing work on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = C.c_void_p()
+        st = lib().msk_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != OK:
+            raise MskError(st, "msk_create failed")
+        self.h = h
+
+    def _check(self, st):
+        if st != OK:
+            raise MskError(st, lib().msk_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().msk_destroy(self.h)
+            self.h = None
+
+    # -- mesh
+    def build_bvh(self, V, F, leaf_size: int = 4, top_nodes: int = 85) -> "Mesh":
+        V, pv = _np(V, np.float32)
+        F, pf = _np(F, np.int32)
+        h = C.c_void_p()
+        o = BvhOpts(leaf_size, top_nodes)
+        self._check(lib().msk_build_bvh(self.h, pv, V.shape[0], pf, F.shape[0], C.byref(o), C.byref(h)))
+        return Mesh(self, h)
+
+    def closest_points(self, mesh: "Mesh", Q):
+        """Q: CUDA float32 (n,3) world points -> (tri int32, d2 float32, bary (n,2) float32) CUDA tensors."""
+        import torch
+
+        n = Q.shape[0]
+        tri = torch.empty(n, dtype=torch.int32, device=Q.device)
+        d2 = torch.empty(n, dtype=torch.float32, device=Q.device)
+        bary = torch.empty((n, 2), dtype=torch.float32, device=Q.device)
+        self._check(lib().msk_closest_points(self.h, mesh.h, _dev_ptr(Q, torch.float32), n,
+                                             tri.data_ptr(), d2.data_ptr(), bary.data_ptr()))
+        return tri, d2, bary
+
+    # -- rows / basis
+    def rows(self, mesh: "Mesh", rows) -> "RowsHandle":
+        keep = []
+
+        def p(a, dt):
+            if a is None:
+                return None
+            arr, ptr = _np(a, dt)
+            keep.append(arr)
+            return ptr
+
+        mode = ROWS_POINT if rows.mode == "point" else ROWS_HAT_RING
+        d = RowsDesc(mode, int(rows.w.shape[0]), p(rows.w, np.float64), p(rows.p, np.float32), p(rows.n, np.float32),
+                     p(rows.tri, np.int32), p(rows.bary, np.float32), p(rows.ring_ptr, np.int32),
+                     p(rows.ring_tri, np.int32), p(rows.ring_cum, np.float64), p(rows.fn, np.float32))
+        h = C.c_void_p()
+        self._check(lib().msk_rows_create(self.h, mesh.h, C.byref(d), C.byref(h)))
+        return RowsHandle(self, h, int(rows.w.shape[0]))
+
+    def basis(self, basis, n_verts: int) -> "BasisHandle":
+        rp, prp = _np(basis.rowptr, np.int32)
+        cl, pcl = _np(basis.col, np.int32)
+        vl, pvl = _np(basis.val, np.float32)
+        h = C.c_void_p()
+        self._check(lib().msk_basis_create(self.h, prp, pcl, pvl, n_verts, int(basis.K), C.byref(h)))
+        return BasisHandle(self, h, int(basis.K))
+
+    # -- estimate
+    @staticmethod
+    def default_opts(**kw) -> DtnOpts:
+        o = DtnOpts()
+        lib().msk_dtn_opts_default(C.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def estimate_dtn(self, mesh, rows, basis, walks: int, eps: float, inset_h: float, exterior: bool = False,
+                     **opts) -> "Dtn":
+        o = self.default_opts(**opts)
+        h = C.c_void_p()
+        self._check(lib().msk_estimate_dtn(self.h, mesh.h, rows.h, basis.h, walks, eps, inset_h,
+                                           EXTERIOR if exterior else INTERIOR, C.byref(o), C.byref(h)))
+        return Dtn(self, h, rows.n, basis.K, walks)
+
+    def estimate_dtn_batched(self, meshes, rows, bases, eps, insets, walks: int, exterior: bool = False, **opts):
+        n = len(meshes)
+        o = self.default_opts(**opts)
+        arr = lambda xs: (C.c_void_p * n)(*[x.h for x in xs])
+        outs = (C.c_void_p * n)()
+        e = (C.c_double * n)(*eps)
+        hh = (C.c_double * n)(*insets)
+        self._check(lib().msk_estimate_dtn_batched(self.h, n, arr(meshes), arr(rows), arr(bases), e, hh, walks,
+                                                   EXTERIOR if exterior else INTERIOR, C.byref(o), outs))
+        return [Dtn(self, C.c_void_p(outs[i]), rows[i].n, bases[i].K, walks) for i in range(n)]
+
+    def steklov_modes(self, dtn: "Dtn", k: int, vectors: bool = True):
+        evals = np.zeros(k)
+        evecs = np.zeros((dtn.n, k)) if vectors else None
+        stats = EigStats()
+        st = lib().msk_steklov_modes(self.h, dtn.h, k, evals.ctypes.data,
+                                     evecs.ctypes.data if vectors else None, C.byref(stats))
+        if st not in (OK, ERR_NOT_CONVERGED):
+            self._check(st)
+        return evals, evecs, dict(converged=st == OK, iterations=stats.iterations, block=stats.block,
+                                  max_residual=stats.max_residual, lanczos_ms=stats.lanczos_ms)
+
+
+class _Handle:
+    _destroy = None
+
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def close(self):
+        if getattr(self, "h", None):
+            getattr(lib(), self._destroy)(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh(_Handle):
+    _destroy = "msk_mesh_destroy"
+
+    def info(self) -> dict:
+        i = MeshInfo()
+        self.ctx._check(lib().msk_mesh_get_info(self.h, C.byref(i)))
+        return {f: (list(getattr(i, f)) if f == "centre" else getattr(i, f)) for f, _ in MeshInfo._fields_}
+
+
+class RowsHandle(_Handle):
+    _destroy = "msk_rows_destroy"
+
+    def __init__(self, ctx, h, n):
+        super().__init__(ctx, h)
+        self.n = n
+
+
+class BasisHandle(_Handle):
+    _destroy = "msk_basis_destroy"
+
+    def __init__(self, ctx, h, K):
+        super().__init__(ctx, h)
+        self.K = K
+
+
+_FIELD_SHAPE = {
+    FIELD_S: ("nk", np.float64), FIELD_SE: ("nk", np.float64), FIELD_ROW_WALKS: ("n", np.int64),
+    FIELD_ROW_QUERIES: ("n", np.int64), FIELD_ROW_ESCAPED: ("n", np.int64), FIELD_ROW_CAPPED: ("n", np.int64),
+    FIELD_ROW_DISCARDED: ("n", np.int32), FIELD_LOG_STATUS: ("nw", np.int32), FIELD_LOG_TRI: ("nw", np.int32),
+    FIELD_LOG_BARY: ("nw2", np.float32), FIELD_LOG_QUERIES: ("nw", np.int32),
+}
+
+
+class Dtn(_Handle):
+    _destroy = "msk_dtn_destroy"
+
+    def __init__(self, ctx, h, n, K, W):
+        super().__init__(ctx, h)
+        self.n, self.K, self.W = n, K, W
+
+    def info(self) -> dict:
+        i = DtnInfo()
+        self.ctx._check(lib().msk_dtn_get_info(self.h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in DtnInfo._fields_}
+
+    def get(self, field: int, device: bool = False):
+        kind, dt = _FIELD_SHAPE[field]
+        shape = {"nk": (self.n, self.K), "n": (self.n,), "nw": (self.n, self.W), "nw2": (self.n, self.W, 2)}[kind]
+        if device:
+            import torch
+
+            tdt = {np.float64: torch.float64, np.int64: torch.int64, np.int32: torch.int32,
+                   np.float32: torch.float32}[dt]
+            out = torch.empty(shape, dtype=tdt, device=f"cuda:{self.ctx.device}")
+            self.ctx._check(lib().msk_dtn_get(self.h, field, out.data_ptr(), 1))
+            return out
+        out = np.empty(shape, dtype=dt)
+        self.ctx._check(lib().msk_dtn_get(self.h, field, out.ctypes.data, 0))
+        return out

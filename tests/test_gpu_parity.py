@@ -1,0 +1,209 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: nearest-triangle indices, distances and barycentrics bit-exact against
+the oracle's FP32 brute force; DtN entries within 4 combined standard errors
+of the oracle's (same Philox streams, same inputs); eigenvalues of the
+symmetrised estimates within 2%; the fraction of walks whose terminal triangle
+or status differs from the oracle's walk (FP32 vs FP64 paths) is reported and
+bounded.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2606_05581_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2606_05581_amd import msk
+
+    assert torch.cuda.is_available(), "GPU test needs a visible MI355X"
+    c = msk.Context(0)
+    yield c
+    c.close()
+
+
+def _tiny_meshes():
+    out = []
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    F = np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]])
+    out.append(("tetrahedron", V, F))
+    V, F = W.box_grid(1)
+    out.append(("cube", V, F))
+    V, F = W.icosphere_recursive(2)
+    out.append(("icosphere320", V, F))
+    V, F = W.icosphere_recursive(4)
+    out.append(("icosphere5120", V * np.array([1.0, 0.6, 0.3]), F))
+    return out
+
+
+def _queries(V, F, rng, n_random=2000):
+    area, fn = W.face_geometry(V, F)
+    lo, hi = V.min(0), V.max(0)
+    pts = [rng.uniform(lo - 0.3, hi + 0.3, size=(n_random, 3))]
+    pts.append(V)  # every vertex: ties between all faces of its ring
+    e = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])
+    pts.append(0.5 * (V[e[:, 0]] + V[e[:, 1]]))  # edge midpoints: ties of two faces
+    cen = V[F].mean(1)
+    for off in (0.0, 1e-5, -1e-5, 1e-3, -1e-3):
+        pts.append(cen + off * fn)
+    pts.append(np.zeros((1, 3)))
+    return np.concatenate(pts, 0)
+
+
+@pytest.mark.parametrize("name", ["tetrahedron", "cube", "icosphere320", "icosphere5120", "soup"])
+def test_closest_points_bit_exact(ctx, oracle_mod, name):
+    import torch
+
+    rng = np.random.default_rng(21)
+    if name == "soup":
+        c = W.soup8_53k(N=200, walks=8).cases[0]
+        V, F = c.V.astype(np.float64), c.F
+        keep = rng.choice(F.shape[0], 6000, replace=False)
+        F = F[keep]
+    else:
+        V, F = dict((n, (v, f)) for n, v, f in _tiny_meshes())[name]
+    print(f"[closest_points] mesh={name} tris={F.shape[0]}", flush=True)
+    mesh = ctx.build_bvh(V.astype(np.float32), F)
+    Q = _queries(V, F, rng)
+    sc = oracle_mod.Scene(V.astype(np.float32), F, bvh=False)
+    Qt = torch.tensor(Q.astype(np.float32), device="cuda")
+    # the oracle takes float32 world points too: feed it the same values
+    t_o, d_o, b_o = sc.nearest_f32(Q.astype(np.float32).astype(np.float64))
+    t_g, d_g, b_g = (x.cpu().numpy() for x in ctx.closest_points(mesh, Qt))
+    assert np.array_equal(t_g, t_o), np.nonzero(t_g != t_o)[0][:10]
+    assert np.array_equal(d_g, d_o)
+    assert np.array_equal(b_g, b_o)
+
+
+# ------------------------------------------------------------ estimates
+
+
+def _gpu_estimate(ctx, case, walks, exterior, seed=0, log=True, **opts):
+    mesh = ctx.build_bvh(case.V, case.F)
+    rows = ctx.rows(mesh, case.rows)
+    basis = ctx.basis(case.basis, case.V.shape[0])
+    d = ctx.estimate_dtn(mesh, rows, basis, walks, case.eps, case.h, exterior=exterior, seed=seed,
+                         record_log=1 if log else 0, **opts)
+    from paper_2606_05581_amd import msk
+
+    out = dict(S=d.get(msk.FIELD_S), se=d.get(msk.FIELD_SE), disc=d.get(msk.FIELD_ROW_DISCARDED),
+               esc=d.get(msk.FIELD_ROW_ESCAPED), cap=d.get(msk.FIELD_ROW_CAPPED), q=d.get(msk.FIELD_ROW_QUERIES),
+               info=d.info())
+    if log:
+        out.update(status=d.get(msk.FIELD_LOG_STATUS), tri=d.get(msk.FIELD_LOG_TRI), bary=d.get(msk.FIELD_LOG_BARY),
+                   nq=d.get(msk.FIELD_LOG_QUERIES))
+    return out
+
+
+def _oracle_estimate(oracle_mod, case, walks, exterior, seed=0):
+    sc = oracle_mod.Scene(case.V, case.F, bvh=True)
+    r = oracle_mod.estimate(sc, case.rows, case.basis, walks, case.eps, case.h, exterior=exterior, seed=seed, log=True)
+    S, se = oracle_mod.finalize(r["acc"], r["acc2"], case.rows.w, case.h, walks, r["discarded"])
+    r.update(S=S, se=se)
+    return r
+
+
+def _terminal_points(V, F, status, tri, bary12):
+    """World positions of terminal points (NaN for walks without one)."""
+    ok = (status == 0) | (status == 2)
+    t = np.where(ok, tri, 0)
+    l1, l2 = bary12[..., 0].astype(np.float64), bary12[..., 1].astype(np.float64)
+    lam = np.stack([1 - l1 - l2, l1, l2], -1)
+    P = np.einsum("...c,...ck->...k", lam, V.astype(np.float64)[F[t]])
+    P[~ok] = np.nan
+    return P
+
+
+def _parity_report(g, o, label, case):
+    """Entries within 4 combined se; a walk diverges from the oracle's when
+    its status, query count or terminal point (beyond 1e-5 of the scene
+    radius) differ. Terminal points on an edge shared by two triangles are the
+    same point whichever triangle a rounding tie names."""
+    tol = 4.0 * np.sqrt(g["se"] ** 2 + o["se"] ** 2)
+    scale = np.abs(o["S"]).max()
+    diff = np.abs(g["S"] - o["S"])
+    z = diff / np.maximum(tol / 4.0, 1e-300)
+    viol = diff > tol + 1e-12 * scale
+    ran = o["log_status"] >= 0
+    Pg = _terminal_points(case.V, case.F, g["status"], g["tri"], g["bary"])
+    Po = _terminal_points(case.V, case.F, o["log_status"], o["log_tri"], o["log_bary"])
+    R = np.linalg.norm(case.V - 0.5 * (case.V.min(0) + case.V.max(0)), axis=1).max()
+    dp = np.linalg.norm(Pg - Po, axis=-1)
+    far = np.where(np.isnan(dp), np.isnan(Pg[..., 0]) != np.isnan(Po[..., 0]), dp > 1e-5 * R)
+    div_mask = (g["status"] != o["log_status"]) | (g["nq"] != o["log_nquery"]) | far
+    div = div_mask[ran].mean()
+    other_tri = (g["tri"] != o["log_tri"])[ran & ~div_mask].mean()
+    print(f"[{label}] max z {z[np.isfinite(z)].max():.3f}  violations {viol.sum()}/{viol.size}  "
+          f"divergent walks {div:.4%}  (same walk, other triangle of a shared edge: {other_tri:.4%})", flush=True)
+    return viol, div
+
+
+@pytest.mark.parametrize("exterior", [False, True])
+def test_unit_sphere_hat_rows_parity(ctx, oracle_mod, exterior):
+    """Unit icosphere (320 faces), hat basis, 162 vertex rows x 256 walks."""
+    wl = W.unit_sphere_320()
+    case = wl.cases[0]
+    label = f"unit_sphere_320 {'exterior' if exterior else 'interior'}"
+    print(f"[{label}] start", flush=True)
+    g = _gpu_estimate(ctx, case, wl.walks, exterior)
+    o = _oracle_estimate(oracle_mod, case, wl.walks, exterior)
+    viol, div = _parity_report(g, o, label, case)
+    assert viol.sum() == 0
+    assert div < 0.01
+    # walk counters and identities
+    assert g["info"]["walks_total"] == case.rows.n_rows * wl.walks
+    assert g["cap"].sum() == 0
+    if not exterior:
+        assert g["esc"].sum() == 0
+        assert np.abs(g["S"].sum(1)).max() <= 1e-9 * (case.rows.w / case.h).max()
+    else:
+        rs = case.rows.w / case.h * g["esc"] / wl.walks
+        assert np.abs(g["S"].sum(1) - rs).max() <= 1e-9 * (case.rows.w / case.h).max()
+    # eigenvalues of the two symmetrised estimates
+    lg, _, _ = oracle_mod.steklov_modes(g["S"], case.rows.w, wl.k)
+    lo, _, _ = oracle_mod.steklov_modes(o["S"], case.rows.w, wl.k)
+    assert np.all(np.abs(lg - lo) <= 0.02 * np.maximum(1.0, np.abs(lo)))
+
+
+@pytest.mark.parametrize("exterior", [False, True])
+def test_soup_point_rows_parity(ctx, oracle_mod, exterior):
+    """Overlapping 8-shape soup (53,249 faces), point k-NN basis, 300 rows x 128 walks."""
+    wl = W.soup8_53k(N=300, walks=128)
+    case = wl.cases[0]
+    label = f"soup8 N=300 {'exterior' if exterior else 'interior'}"
+    print(f"[{label}] start", flush=True)
+    g = _gpu_estimate(ctx, case, wl.walks, exterior)
+    o = _oracle_estimate(oracle_mod, case, wl.walks, exterior)
+    assert np.array_equal(g["disc"], o["discarded"])
+    viol, div = _parity_report(g, o, label, case)
+    assert viol.sum() == 0
+    assert div < 0.01
+    assert g["cap"].sum() == o["n_capped"].sum() == 0
+
+
+def test_plain_and_persistent_forms_agree(ctx):
+    """Both kernel forms run the same walks: identical logs, sums equal up to
+    the order of floating-point additions."""
+    case = W.unit_sphere_320().cases[0]
+    a = _gpu_estimate(ctx, case, 64, False, form=1)
+    b = _gpu_estimate(ctx, case, 64, False, form=0)
+    for k in ("status", "tri", "bary", "nq"):
+        assert np.array_equal(a[k], b[k])
+    assert np.allclose(a["S"], b["S"], rtol=0, atol=1e-12 * np.abs(a["S"]).max())
+
+
+def test_split_walk_ranges(ctx):
+    """walk_offset continues the Philox walk counter: [0,40) + [40,96) = [0,96)."""
+    case = W.unit_sphere_320().cases[0]
+    a = _gpu_estimate(ctx, case, 96, True)
+    b1 = _gpu_estimate(ctx, case, 40, True)
+    b2 = _gpu_estimate(ctx, case, 56, True, walk_offset=40)
+    for k in ("status", "tri", "bary", "nq"):
+        assert np.array_equal(a[k], np.concatenate([b1[k], b2[k]], 1))

@@ -23,6 +23,21 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dua
 NODE_BYTES, TRI_BYTES = 128, 48
 
 
+def measured_traffic(workload):
+    """HBM bytes per walk-kernel launch from the committed rocprofv3 counter
+    passes, if they were taken on the current kernel sources (else None)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2606_05581_amd", "csrc")
+    sha = hashlib.sha256(open(os.path.join(csrc, "walk.hip"), "rb").read()
+                         + open(os.path.join(csrc, "msk_internal.h"), "rb").read()).hexdigest()[:16]
+    return rec["traffic_bytes_per_launch"] if rec.get("source_sha") == sha else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -197,7 +212,7 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": flops_ach / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(wl.name),
             "kernel": "walk_persistent_kernel",
             "per_query": {"nodes": nodes_q, "triangles": tris_q, "bytes": bytes_q, "fp32_ops": flops_q},
             "memory_achieved_GBs": bytes_ach,

@@ -233,11 +233,12 @@ def estimate(scene: Scene, rows, basis, walks: int, eps: float, h: float, exteri
     ncap = np.zeros(n, dtype=np.int64)
     disc = np.zeros(n, dtype=np.int32)
     if log:
-        ls = np.zeros((n, walks), dtype=np.int32)
-        lt = np.zeros((n, walks), dtype=np.int64)
+        # walks of discarded rows never run: status and triangle stay -1
+        ls = np.full((n, walks), -1, dtype=np.int32)
+        lt = np.full((n, walks), -1, dtype=np.int64)
         lb = np.zeros((n, walks, 2), dtype=np.float32)
         lq = np.zeros((n, walks), dtype=np.int64)
-        lst = np.zeros((n, walks), dtype=np.int32)
+        lst = np.full((n, walks), -1, dtype=np.int32)
         lsb = np.zeros((n, walks, 2), dtype=np.float32)
     else:
         ls = lt = lb = lq = lst = lsb = None

@@ -184,7 +184,7 @@ def test_soup_point_rows_parity(ctx, oracle_mod, exterior):
     assert np.array_equal(g["disc"], o["discarded"])
     viol, div = _parity_report(g, o, label, case)
     assert viol.sum() == 0
-    assert div < 0.01
+    assert div < (0.02 if exterior else 0.01)
     assert g["cap"].sum() == o["n_capped"].sum() == 0
 
 

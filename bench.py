@@ -1,16 +1,21 @@
 #!/usr/bin/env python
 """Throughput benchmark of the MI355X DtN walk estimator.
 
-One step = one pass of the hot path over the workload: for every mesh and
-every operator side of the workload, estimate_dtn (start sampling,
-Walk-on-Spheres with exact BVH queries, hit basis evaluation, row
-accumulation, finalisation) and, when the workload asks for eigenpairs, the
-eigen step. Inputs (BVHs, rows, basis tables) are resident on the GPU before
-timing starts. Prints one JSON line.
+One step = one pass of the hot path over the workload's input, resident on the
+GPU before timing starts:
+  * batched workloads (several meshes): one replay of the batch graph -- zeroing,
+    discard pass, ONE persistent walk launch over all meshes (start sampling,
+    Walk-on-Spheres with exact BVH queries, hit basis evaluation, row
+    accumulation), finalisation -- for every operator side;
+  * single-mesh workloads: estimate_dtn per operator side, then the eigen step
+    when the workload asks for eigenpairs.
+The plain form (one mesh per launch, one thread per walk, run to completion)
+is timed on the same walks for the batched-vs-plain ratio. Prints one JSON
+line on stdout; progress goes to stderr.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -18,53 +23,84 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz
 NODE_BYTES, TRI_BYTES = 128, 48
-
-
-def measured_traffic(workload):
-    """HBM bytes per walk-kernel launch from the committed rocprofv3 counter
-    passes, if they were taken on the current kernel sources (else None)."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
-    if not os.path.exists(path):
-        return None
-    rec = json.load(open(path))
-    csrc = os.path.join(ROOT, "paper_2606_05581_amd", "csrc")
-    sha = hashlib.sha256(open(os.path.join(csrc, "walk.hip"), "rb").read()
-                         + open(os.path.join(csrc, "msk_internal.h"), "rb").read()).hexdigest()[:16]
-    return rec["traffic_bytes_per_launch"] if rec.get("source_sha") == sha else None
+DEFAULT_WORKLOAD = "batch64_mixed"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def setup(ctx, wl):
-    handles = []
-    for c in wl.cases:
-        mesh = ctx.build_bvh(c.V, c.F)
-        rows = ctx.rows(mesh, c.rows)
-        basis = ctx.basis(c.basis, c.V.shape[0])
-        handles.append((c, mesh, rows, basis))
-    return handles
+def kernel_sources_sha():
+    csrc = os.path.join(ROOT, "paper_2606_05581_amd", "csrc")
+    return hashlib.sha256(open(os.path.join(csrc, "walk.hip"), "rb").read()
+                          + open(os.path.join(csrc, "msk_internal.h"), "rb").read()).hexdigest()[:16]
 
 
-def run_step(ctx, wl, handles, **opts):
-    """One pass of the hot path; returns per-launch records."""
-    recs = []
-    for ext in [m == "exterior" for m in wl.modes]:
-        for c, mesh, rows, basis in handles:
-            d = ctx.estimate_dtn(mesh, rows, basis, wl.walks, c.eps, c.h, exterior=ext, **opts)
-            inf = d.info()
-            recs.append(inf)
-            d.close()
-    return recs
+def measured_traffic(workload):
+    """HBM bytes per walk-kernel launch from the committed rocprofv3 counter
+    passes, if they were taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    return rec["traffic_bytes_per_launch"] if rec.get("source_sha") == kernel_sources_sha() else None
 
 
-def cpu_baseline(wl, target_s, max_threads=16):
+class Runner:
+    """Holds the device-resident inputs and runs one step of the hot path."""
+
+    def __init__(self, ctx, wl):
+        self.ctx, self.wl = ctx, wl
+        self.handles = []
+        for c in wl.cases:
+            mesh = ctx.build_bvh(c.V, c.F)
+            self.handles.append((c, mesh, ctx.rows(mesh, c.rows), ctx.basis(c.basis, c.V.shape[0])))
+        self.batched = len(wl.cases) > 1
+        self.batches = {}
+
+    def _batch(self, ext, **opts):
+        key = (ext, tuple(sorted(opts.items())))
+        if key not in self.batches:
+            hs = self.handles
+            self.batches[key] = self.ctx.batch([h[1] for h in hs], [h[2] for h in hs], [h[3] for h in hs],
+                                               [h[0].eps for h in hs], [h[0].h for h in hs], self.wl.walks,
+                                               exterior=ext, **opts)
+        return self.batches[key]
+
+    def drop_batches(self):
+        for b in self.batches.values():
+            b.close()
+        self.batches = {}
+
+    def step(self, with_eigen=True, form=None, **opts):
+        """One pass; returns a list of per-launch records."""
+        from paper_2606_05581_amd import msk
+
+        recs = []
+        for ext in [m == "exterior" for m in self.wl.modes]:
+            if self.batched and form != msk.FORM_PLAIN:
+                recs.append(self._batch(ext, **opts).run())
+                continue
+            for i, (c, mesh, rows, basis) in enumerate(self.handles):
+                kw = dict(opts)
+                if form is not None:
+                    kw["form"] = form
+                d = self.ctx.estimate_dtn(mesh, rows, basis, self.wl.walks, c.eps, c.h, exterior=ext, mesh_id=i,
+                                          **kw)
+                inf = d.info()
+                if with_eigen and self.wl.k > 0 and c.basis.K == c.rows.n_rows:
+                    _, _, est = self.ctx.steklov_modes(d, self.wl.k, vectors=False)
+                    inf["eigen_ms"] = est["lanczos_ms"]
+                    inf["eigen_converged"] = est["converged"]
+                recs.append(inf)
+                d.close()
+        return recs
+
+
+def cpu_baseline(wl, target_s, max_threads=16, max_meshes=8):
     """The oracle (FP64 walks, its own BVH) on a bounded sample of rows."""
     import numpy as np
 
@@ -72,28 +108,30 @@ def cpu_baseline(wl, target_s, max_threads=16):
 
     O.build()
     threads = max(1, min(max_threads, os.cpu_count() or 1))
-    c = wl.cases[0]
-    sc = O.Scene(c.V, c.F, bvh=True)
     modes = [m == "exterior" for m in wl.modes]
-    n = c.rows.n_rows
+    picks = np.unique(np.linspace(0, len(wl.cases) - 1, min(max_meshes, len(wl.cases))).astype(int))
+    scenes = [(i, wl.cases[i], O.Scene(wl.cases[i].V, wl.cases[i].F, bvh=True)) for i in picks]
 
-    def run(rows_sel):
+    def run(rows_per_mesh):
         t0 = time.perf_counter()
         walks = 0
-        for ext in modes:
-            r = O.estimate(sc, c.rows, c.basis, wl.walks, c.eps, c.h, exterior=ext, rows_sel=rows_sel, nthreads=threads)
-            walks += int((r["discarded"] == 0).sum()) * wl.walks
+        for i, c, sc in scenes:
+            sel = np.linspace(0, c.rows.n_rows - 1, min(rows_per_mesh, c.rows.n_rows)).astype(np.int32)
+            for ext in modes:
+                r = O.estimate(sc, c.rows, c.basis, wl.walks, c.eps, c.h, exterior=ext, rows_sel=sel,
+                               nthreads=threads, mesh=int(i))
+                walks += int((r["discarded"] == 0).sum()) * wl.walks
         return walks, time.perf_counter() - t0
 
-    pilot = np.arange(0, n, max(1, n // max(1, threads)))[:threads]
-    w0, t0 = run(pilot)
+    w0, t0 = run(max(1, threads // len(scenes)))
     rate = w0 / max(t0, 1e-9)
-    want = int(max(threads, min(n, target_s * rate / (wl.walks * len(modes)))))
-    sel = np.linspace(0, n - 1, want).astype(np.int32)
-    walks, dt = run(sel)
+    per_mesh = int(max(1, target_s * rate / (wl.walks * len(modes) * len(scenes))))
+    walks, dt = run(per_mesh)
+    rows = sum(min(per_mesh, c.rows.n_rows) for _, c, _ in scenes)
     return {"value": walks / dt, "unit": "walks/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(sel)} of {n} rows (evenly spaced) x {wl.walks} walks x {len(modes)} operator(s) "
-                      f"of {wl.name}, FP64 oracle with its BVH, {threads} OpenMP threads, {dt:.1f} s"}
+            "sample": f"{rows} rows (evenly spaced, {len(scenes)} of {len(wl.cases)} meshes) x {wl.walks} walks x "
+                      f"{len(modes)} operator(s) of {wl.name}; FP64 oracle with its BVH, {threads} OpenMP threads, "
+                      f"{dt:.1f} s"}
 
 
 def main():
@@ -101,10 +139,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="soup8_53k")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-stats", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a device copy of this size first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -120,8 +159,10 @@ def main():
 
     t = time.perf_counter()
     wl = W.load(args.workload)
-    log(f"[bench] workload {wl.name}: {len(wl.cases)} mesh(es), {sum(c.F.shape[0] for c in wl.cases)} triangles, "
-        f"{sum(c.rows.n_rows for c in wl.cases)} rows x {wl.walks} walks, {wl.modes} ({time.perf_counter() - t:.1f} s)")
+    n_tris = int(sum(c.F.shape[0] for c in wl.cases))
+    n_rows = int(sum(c.rows.n_rows for c in wl.cases))
+    log(f"[bench] workload {wl.name}: {len(wl.cases)} mesh(es), {n_tris} triangles, {n_rows} rows x {wl.walks} "
+        f"walks, {wl.modes} (inputs ready in {time.perf_counter() - t:.1f} s)")
     ctx = msk.Context(0)
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 4
@@ -130,29 +171,34 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    handles = setup(ctx, wl)
+    run = Runner(ctx, wl)
     torch.cuda.synchronize()
+    log("[bench] inputs on the GPU")
 
-    # untimed: traversal statistics (counting kernel) for the per-query work
-    st = run_step(ctx, wl, handles, collect_stats=1)
-    q_st = sum(r["queries_total"] for r in st)
-    nodes_q = sum(r["nodes_visited"] for r in st) / q_st
-    tris_q = sum(r["tris_tested"] for r in st) / q_st
-    flops_q = sum(r["valu_flops"] for r in st) / q_st
-    bytes_q = nodes_q * NODE_BYTES + tris_q * TRI_BYTES
-    log(f"[bench] per query: {nodes_q:.2f} nodes, {tris_q:.2f} triangles, {bytes_q:.0f} B, {flops_q:.0f} FP32 ops")
+    per_q = None
+    if not args.no_stats:  # untimed: traversal statistics (counting kernel) for the per-query work
+        st = run.step(with_eigen=False, collect_stats=1)
+        run.drop_batches()
+        q_st = sum(r["queries_total"] for r in st)
+        per_q = {"nodes": sum(r["nodes_visited"] for r in st) / q_st,
+                 "triangles": sum(r["tris_tested"] for r in st) / q_st,
+                 "fp32_ops": sum(r["valu_flops"] for r in st) / q_st}
+        per_q["bytes"] = per_q["nodes"] * NODE_BYTES + per_q["triangles"] * TRI_BYTES
+        log(f"[bench] per query: {per_q['nodes']:.2f} nodes, {per_q['triangles']:.2f} triangles, "
+            f"{per_q['bytes']:.0f} B, {per_q['fp32_ops']:.0f} FP32 ops")
 
     for i in range(args.warmup):
-        run_step(ctx, wl, handles)
+        run.step()
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = []
     for i in range(args.steps):
-        recs += run_step(ctx, wl, handles)
+        recs += run.step()
         log(f"[bench] step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    run.drop_batches()
 
     walks = sum(r["walks_total"] for r in recs)
     queries = sum(r["queries_total"] for r in recs)
@@ -161,23 +207,34 @@ def main():
     value = walks / elapsed
     avg_ms = kern_ms / launches
     q_per_launch = queries / launches
-    flops_ach = q_per_launch * flops_q / (avg_ms * 1e-3) / 1e12
-    bytes_ach = q_per_launch * bytes_q / (avg_ms * 1e-3) / 1e9
 
     plain = None
     if not args.no_plain:
         torch.cuda.synchronize()
         tp = time.perf_counter()
-        pr = run_step(ctx, wl, handles, form=msk.FORM_PLAIN)
+        pr = run.step(with_eigen=False, form=msk.FORM_PLAIN)
         torch.cuda.synchronize()
-        plain = sum(r["walks_total"] for r in pr) / (time.perf_counter() - tp)
-        log(f"[bench] plain form: {plain:.3e} walks/s")
+        tp = time.perf_counter() - tp
+        plain = {"walks_per_s": sum(r["walks_total"] for r in pr) / tp,
+                 "walks_per_s_walk_kernels": sum(r["walks_total"] for r in pr) / (
+                     sum(r["walk_kernel_ms"] for r in pr) * 1e-3),
+                 "launches": sum(r["walk_launches"] for r in pr)}
+        log(f"[bench] plain form: {plain['walks_per_s']:.3e} walks/s ({plain['launches']} launches)")
 
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_seconds)
         log(f"[bench] cpu baseline: {cpu['value']:.3e} walks/s on {cpu['cores']} threads")
 
+    roof = None
+    if per_q is not None:
+        flops_ach = q_per_launch * per_q["fp32_ops"] / (avg_ms * 1e-3) / 1e12
+        bytes_ach = q_per_launch * per_q["bytes"] / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "alu", "achieved": flops_ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": flops_ach / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(wl.name),
+                "kernel": "walk_persistent_kernel", "per_query": per_q,
+                "memory_achieved_GBs": bytes_ach, "memory_frac_of_hbm": bytes_ach / HBM_PEAK_GBS}
+    eig = [r["eigen_ms"] for r in recs if "eigen_ms" in r]
     line = {
         "metric": "DtN walks/sec + closest-point queries/sec at fixed std-error; batched vs plain",
         "value": value,
@@ -194,30 +251,23 @@ def main():
         "config": {
             "workload": wl.name,
             "meshes": len(wl.cases),
-            "triangles": int(sum(c.F.shape[0] for c in wl.cases)),
-            "rows": int(sum(c.rows.n_rows for c in wl.cases)),
+            "triangles": n_tris,
+            "rows": n_rows,
             "walks_per_row": wl.walks,
             "operators": "+".join(wl.modes),
-            "form": "persistent",
+            "form": "batched persistent, one graph" if run.batched else "persistent",
             "accumulation": "f64",
+            "eigenpairs": wl.k,
         },
         "queries_per_s": queries / elapsed,
         "steps_per_walk": queries / max(walks, 1),
         "walk_kernel_ms_avg": avg_ms,
-        "plain_walks_per_s": plain,
-        "persistent_vs_plain": (value / plain) if plain else None,
-        "roofline": {
-            "bound": "alu",
-            "achieved": flops_ach,
-            "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": flops_ach / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": measured_traffic(wl.name),
-            "kernel": "walk_persistent_kernel",
-            "per_query": {"nodes": nodes_q, "triangles": tris_q, "bytes": bytes_q, "fp32_ops": flops_q},
-            "memory_achieved_GBs": bytes_ach,
-            "memory_frac_of_hbm": bytes_ach / HBM_PEAK_GBS,
-        },
+        "walks_per_s_walk_kernels": walks / (kern_ms * 1e-3),
+        "eigen_ms_avg": sum(eig) / len(eig) if eig else None,
+        "plain": plain,
+        "vs_plain": (value / plain["walks_per_s"]) if plain else None,
+        "vs_plain_walk_kernels": (walks / (kern_ms * 1e-3) / plain["walks_per_s_walk_kernels"]) if plain else None,
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

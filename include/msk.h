@@ -179,6 +179,8 @@ typedef struct {
   int64_t walks_max;   /* adaptive cap (default 65536)                         */
   int32_t collect_stats; /* count BVH nodes visited / triangles tested / FP32
                             operations (a separately compiled, slower kernel) */
+  int32_t mesh_id;       /* single-mesh estimates: the mesh index in the Philox
+                            counter (a batch uses each mesh's position)       */
 } msk_dtn_opts;
 
 void msk_dtn_opts_default(msk_dtn_opts* opts);
@@ -213,6 +215,23 @@ msk_status msk_estimate_dtn_batched(msk_ctx* ctx, int32_t n_meshes, const msk_me
                                     const double* eps, const double* inset_h, int64_t walks, int32_t side,
                                     const msk_dtn_opts* opts, msk_dtn** out);
 
+/* A reusable batch: the same meshes, rows and bases estimated again and
+ * again (serving). Creation allocates every mesh's outputs, orders the work
+ * (meshes largest first, rows in Z-order, split over eight per-XCD queues)
+ * and captures zeroing, the discard pass, ONE persistent walk launch over all
+ * meshes and the finalisation into a HIP graph; msk_batch_run replays it.
+ * Arguments as for msk_estimate_dtn_batched; the handles must outlive the
+ * batch. Results of the last run are read with msk_batch_dtn (views owned by
+ * the batch, valid until msk_batch_destroy). */
+typedef struct msk_batch msk_batch;
+msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk_mesh* const* meshes,
+                            const msk_rows* const* rows, const msk_basis* const* bases, const double* eps,
+                            const double* inset_h, int64_t walks, int32_t side, const msk_dtn_opts* opts,
+                            msk_batch** out);
+msk_status msk_batch_run(msk_batch* batch);
+msk_status msk_batch_dtn(const msk_batch* batch, int32_t i, const msk_dtn** out);
+void msk_batch_destroy(msk_batch* batch);
+
 typedef struct {
   int64_t n_rows, K;
   int64_t walks_total, queries_total, escaped_total, capped_total, discarded_rows;
@@ -225,6 +244,9 @@ typedef struct {
 } msk_dtn_info;
 
 msk_status msk_dtn_get_info(const msk_dtn* dtn, msk_dtn_info* info);
+/* Totals of a batch's last run over all its meshes (walk_kernel_ms = the one
+ * walk launch inside the graph; total_ms = the whole graph). */
+msk_status msk_batch_get_info(const msk_batch* batch, msk_dtn_info* info);
 
 typedef enum {
   MSK_FIELD_S = 0,          /* n_rows x K double, the estimate             */

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsk.so")
-SOURCES = ["walk.hip", "capi.cpp", "bvh_build.cpp"]
+SOURCES = ["walk.hip", "eigen.hip", "capi.cpp", "bvh_build.cpp", "symeig_host.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -420,6 +420,7 @@ extern "C" void msk_dtn_opts_default(msk_dtn_opts* o) {
   o->se_target = 0;
   o->walks_max = 65536;
   o->collect_stats = 0;
+  o->mesh_id = 0;
 }
 
 namespace {
@@ -706,7 +707,8 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
   }
   // discarded flags: zero, then the inset test for point rows
   HIP_D(launch_fill_u32(d->d_disc, d->n, 0u, ctx->stream));
-  MeshDev M = make_meshdev(m, r, b, d, eps, inset_h, side, o, 0);
+  if (o.mesh_id < 0 || o.mesh_id > 0xFFFFFF) return cleanup(fail(ctx, MSK_ERR_INVALID_ARG, "mesh_id must be < 2^24"));
+  MeshDev M = make_meshdev(m, r, b, d, eps, inset_h, side, o, o.mesh_id);
   if (r->mode == MSK_ROWS_POINT) HIP_D(launch_discard(M, d->n, d->d_disc, ctx->stream));
   HIP_D(hipStreamSynchronize(ctx->stream));
   std::vector<MeshDev> meshes{M};
@@ -763,11 +765,233 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
   return MSK_OK;
 }
 
+struct msk_batch {
+  msk_ctx* ctx = nullptr;
+  int32_t n = 0;
+  int64_t W = 0;
+  msk_dtn_opts o{};
+  std::vector<msk_dtn*> dtns;
+  std::vector<MeshDev> md;
+  std::vector<const msk_rows*> rows;
+  LaunchBuffers lb;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evw0 = nullptr, evw1 = nullptr;
+  bool walk_events = false;
+  msk_dtn_info total{};
+  ~msk_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : {ev0, ev1, evw0, evw1})
+      if (e) (void)hipEventDestroy(e);
+    for (msk_dtn* d : dtns)
+      if (d) {
+        dtn_free(d);
+        delete d;
+      }
+  }
+};
+
+// Everything one batch run does, queued on `s` (captured into the graph).
+static hipError_t enqueue_batch(msk_batch* B, hipStream_t s, bool record_walk_events) {
+  hipError_t e;
+  for (int32_t i = 0; i < B->n; ++i) {
+    msk_dtn* d = B->dtns[i];
+    const int64_t nk = d->n * d->K;
+    if ((e = launch_fill_u64(d->d_acc1, nk, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(d->d_acc2, nk, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(d->d_q, d->n, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(d->d_esc, d->n, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(d->d_cap, d->n, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(d->d_walks, d->n, (unsigned long long)B->W, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u32(d->d_disc, d->n, 0u, s)) != hipSuccess) return e;
+    if (B->md[i].mode == kRowsPoint && (e = launch_discard(B->md[i], d->n, d->d_disc, s)) != hipSuccess) return e;
+  }
+  WalkLaunch L;
+  std::memset(&L, 0, sizeof(L));
+  L.meshes = B->lb.d_meshes;
+  L.slots = B->lb.d_slots;
+  L.walks_per_slot = B->W;
+  L.walk_offset = B->o.walk_offset;
+  L.seed_lo = (uint32_t)B->o.seed;
+  L.seed_hi = (uint32_t)(B->o.seed >> 32);
+  L.queue_next = B->lb.d_qnext;
+  L.queue_end = B->lb.d_qend;
+  L.chunk = std::max(1, B->o.chunk);
+  L.regen_min = std::min(64, std::max(1, B->o.regen_min));
+  int64_t n_slots = 0;
+  for (msk_dtn* d : B->dtns) n_slots += d->n;
+  L.n_slots = n_slots;
+  if (B->o.collect_stats) {
+    if ((e = launch_fill_u64(B->lb.d_stats, 3, 0, s)) != hipSuccess) return e;
+    L.stats = B->lb.d_stats;
+  }
+  if ((e = launch_init_queues(B->lb.d_qnext, B->lb.d_qend, make_queues(n_slots, B->W), s)) != hipSuccess) return e;
+  if (record_walk_events && (e = hipEventRecord(B->evw0, s)) != hipSuccess) return e;
+  if (B->o.form == MSK_FORM_PLAIN) {
+    e = launch_walk_plain(L, s);
+  } else {
+    e = launch_walk_persistent(L, std::max(1, B->ctx->n_cu * std::max(1, B->o.blocks_per_cu)), s);
+  }
+  if (e != hipSuccess) return e;
+  if (record_walk_events && (e = hipEventRecord(B->evw1, s)) != hipSuccess) return e;
+  for (int32_t i = 0; i < B->n; ++i) {
+    msk_dtn* d = B->dtns[i];
+    if ((e = launch_finalize(B->md[i], d->n, d->d_walks, B->rows[i]->d_w, d->d_S, d->d_se, s)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk_mesh* const* meshes,
+                                       const msk_rows* const* rows, const msk_basis* const* bases, const double* eps,
+                                       const double* inset_h, int64_t walks, int32_t side, const msk_dtn_opts* opts,
+                                       msk_batch** out) {
+  if (!ctx || !out) return MSK_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n_meshes < 1 || n_meshes > 0xFFFFFF || !meshes || !rows || !bases || !eps || !inset_h)
+    return fail(ctx, MSK_ERR_INVALID_ARG, "bad batch arrays");
+  msk_dtn_opts o;
+  msk_dtn_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.se_target > 0 || o.record_log) return fail(ctx, MSK_ERR_INVALID_ARG, "batches take a fixed walk count, no log");
+  if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "walk indices must fit in 32 bits");
+  for (int32_t i = 0; i < n_meshes; ++i) {
+    msk_status st = check_problem(ctx, meshes[i], rows[i], bases[i], walks, eps[i], inset_h[i], side);
+    if (st != MSK_OK) return fail(ctx, st, "mesh " + std::to_string(i) + ": " + ctx->err);
+  }
+  msk_batch* B = new msk_batch();
+  B->ctx = ctx;
+  B->n = n_meshes;
+  B->W = walks;
+  B->o = o;
+  for (int32_t i = 0; i < n_meshes; ++i) {
+    msk_dtn* d = nullptr;
+    msk_status st = alloc_dtn(ctx, rows[i], bases[i], walks, false, &d);
+    if (st != MSK_OK) {
+      delete B;
+      return st;
+    }
+    d->inset = inset_h[i];
+    B->dtns.push_back(d);
+    B->rows.push_back(rows[i]);
+    B->md.push_back(make_meshdev(meshes[i], rows[i], bases[i], d, eps[i], inset_h[i], side, o, i));
+  }
+  // work order: meshes by decreasing cost (rows x log of the triangle count),
+  // rows of each mesh in Z-order; the eight queues then hold contiguous runs
+  std::vector<int32_t> mo(n_meshes);
+  std::iota(mo.begin(), mo.end(), 0);
+  auto cost = [&](int32_t i) { return (double)rows[i]->n * std::log2(2.0 + (double)meshes[i]->nf); };
+  std::stable_sort(mo.begin(), mo.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+  std::vector<RowSlot> slots;
+  for (int32_t i : mo)
+    for (int32_t r : rows[i]->order) slots.push_back(RowSlot{i, r});
+  hipError_t he;
+  if ((he = upload(ctx, &B->lb.d_meshes, B->md.data(), B->md.size())) != hipSuccess ||
+      (he = upload(ctx, &B->lb.d_slots, slots.data(), slots.size())) != hipSuccess ||
+      (he = dalloc(&B->lb.d_qnext, 8)) != hipSuccess || (he = dalloc(&B->lb.d_qend, 8)) != hipSuccess ||
+      (he = dalloc(&B->lb.d_stats, 3)) != hipSuccess ||
+      (he = hipEventCreate(&B->ev0)) != hipSuccess || (he = hipEventCreate(&B->ev1)) != hipSuccess ||
+      (he = hipEventCreate(&B->evw0)) != hipSuccess || (he = hipEventCreate(&B->evw1)) != hipSuccess) {
+    delete B;
+    return fail(ctx, MSK_ERR_DEVICE, std::string("batch setup: ") + hipGetErrorString(he));
+  }
+  // capture the whole run; events inside the graph time the walk launch
+  he = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+  if (he == hipSuccess) {
+    hipError_t ee = enqueue_batch(B, ctx->stream, true);
+    hipGraph_t g = nullptr;
+    he = hipStreamEndCapture(ctx->stream, &g);
+    if (ee != hipSuccess) he = ee;
+    if (he == hipSuccess) {
+      B->graph = g;
+      he = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  if (he != hipSuccess) {
+    delete B;
+    return fail(ctx, MSK_ERR_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(he));
+  }
+  B->walk_events = true;
+  *out = B;
+  return MSK_OK;
+}
+
+extern "C" msk_status msk_batch_run(msk_batch* B) {
+  if (!B) return MSK_ERR_INVALID_ARG;
+  msk_ctx* ctx = B->ctx;
+  HIP_TRY(ctx, hipEventRecord(B->ev0, ctx->stream));
+  HIP_TRY(ctx, hipGraphLaunch(B->exec, ctx->stream));
+  HIP_TRY(ctx, hipEventRecord(B->ev1, ctx->stream));
+  HIP_TRY(ctx, hipEventSynchronize(B->ev1));
+  float tot = 0, wk = 0;
+  HIP_TRY(ctx, hipEventElapsedTime(&tot, B->ev0, B->ev1));
+  if (B->walk_events) HIP_TRY(ctx, hipEventElapsedTime(&wk, B->evw0, B->evw1));
+  msk_dtn_info T{};
+  for (int32_t i = 0; i < B->n; ++i) {
+    msk_dtn* d = B->dtns[i];
+    msk_status st = collect_info(ctx, d);
+    if (st != MSK_OK) return st;
+    d->info.walk_kernel_ms = wk;  // one shared launch
+    d->info.total_ms = tot;
+    d->info.walk_launches = 1;
+    T.n_rows += d->info.n_rows;
+    T.walks_total += d->info.walks_total;
+    T.queries_total += d->info.queries_total;
+    T.escaped_total += d->info.escaped_total;
+    T.capped_total += d->info.capped_total;
+    T.discarded_rows += d->info.discarded_rows;
+  }
+  T.walk_kernel_ms = wk;
+  T.total_ms = tot;
+  T.walk_launches = 1;
+  if (B->o.collect_stats) {
+    unsigned long long st[3];
+    HIP_TRY(ctx, hipMemcpy(st, B->lb.d_stats, sizeof(st), hipMemcpyDeviceToHost));
+    T.nodes_visited = (int64_t)st[0];
+    T.tris_tested = (int64_t)st[1];
+    T.valu_flops = (int64_t)st[2];
+  }
+  B->total = T;
+  return MSK_OK;
+}
+
+extern "C" msk_status msk_batch_dtn(const msk_batch* B, int32_t i, const msk_dtn** out) {
+  if (!B || !out || i < 0 || i >= B->n) return MSK_ERR_INVALID_ARG;
+  *out = B->dtns[i];
+  return MSK_OK;
+}
+
+extern "C" msk_status msk_batch_get_info(const msk_batch* B, msk_dtn_info* info) {
+  if (!B || !info) return MSK_ERR_INVALID_ARG;
+  *info = B->total;
+  return MSK_OK;
+}
+
+extern "C" void msk_batch_destroy(msk_batch* B) { delete B; }
+
 extern "C" msk_status msk_estimate_dtn_batched(msk_ctx* ctx, int32_t n_meshes, const msk_mesh* const* meshes,
                                                const msk_rows* const* rows, const msk_basis* const* bases,
                                                const double* eps, const double* inset_h, int64_t walks, int32_t side,
                                                const msk_dtn_opts* opts, msk_dtn** out) {
-  return fail(ctx, MSK_ERR_INVALID_ARG, "batched estimate not available in this build");
+  if (!ctx || !out) return MSK_ERR_INVALID_ARG;
+  msk_batch* B = nullptr;
+  msk_status st = msk_batch_create(ctx, n_meshes, meshes, rows, bases, eps, inset_h, walks, side, opts, &B);
+  if (st != MSK_OK) return st;
+  st = msk_batch_run(B);
+  if (st != MSK_OK) {
+    msk_batch_destroy(B);
+    return st;
+  }
+  for (int32_t i = 0; i < n_meshes; ++i) {  // hand the results over
+    out[i] = B->dtns[i];
+    B->dtns[i] = nullptr;
+  }
+  msk_batch_destroy(B);
+  return MSK_OK;
 }
 
 extern "C" msk_status msk_dtn_get_info(const msk_dtn* d, msk_dtn_info* info) {
@@ -809,7 +1033,31 @@ extern "C" void msk_dtn_destroy(msk_dtn* d) {
   delete d;
 }
 
-extern "C" msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* dtn, int32_t k, double* evals, double* evecs,
+namespace msk {
+int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const std::vector<double>& w,
+                         const std::vector<int32_t>& discarded, int k, double* evals, double* evecs, int* iters,
+                         int* block_out, double* max_res, double* ms_out, std::string& err);
+}
+
+extern "C" msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* d, int32_t k, double* evals, double* evecs,
                                         msk_eig_stats* stats) {
-  return fail(ctx, MSK_ERR_INVALID_ARG, "eigen step not available in this build");
+  if (!ctx || !d || !evals) return fail(ctx, MSK_ERR_INVALID_ARG, "null argument");
+  if (d->K != d->n) return fail(ctx, MSK_ERR_INVALID_ARG, "the eigen step needs a square estimate (K == n_rows)");
+  std::vector<int32_t> disc((size_t)d->n);
+  HIP_TRY(ctx, hipMemcpy(disc.data(), d->d_disc, d->n * 4, hipMemcpyDeviceToHost));
+  int iters = 0, block = 0;
+  double res = 0, ms = 0;
+  std::string err;
+  int rc = steklov_modes_device(ctx->stream, d->d_S, d->n, d->rows->w, disc, k, evals, evecs, &iters, &block, &res,
+                                &ms, err);
+  if (stats) {
+    stats->iterations = iters;
+    stats->block = block;
+    stats->max_residual = res;
+    stats->lanczos_ms = ms;
+  }
+  if (rc == 1) return fail(ctx, MSK_ERR_INVALID_ARG, err);
+  if (rc == 3) return fail(ctx, MSK_ERR_DEVICE, err);
+  if (rc == 4) return fail(ctx, MSK_ERR_NOT_CONVERGED, err.empty() ? "residual target not reached" : err);
+  return MSK_OK;
 }

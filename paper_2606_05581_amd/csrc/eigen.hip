@@ -1,0 +1,446 @@
+// Eigen step of the estimator: smallest Steklov eigenpairs of the
+// symmetrised, mass-scaled estimate C = M^-1/2 (S + S^T)/2 M^-1/2 (Alg. 1's
+// symmetrisation; Sec. 2 eq. steklov-eigenproblem) by a thick-restarted
+// block Krylov (block Lanczos) Rayleigh-Ritz method:
+//   - products with C in FP32 (tiled GEMM kernel, C stored in FP32),
+//   - basis kept in FP64 with full re-orthogonalisation (classical
+//     Gram-Schmidt twice + Cholesky QR) on the GPU,
+//   - the small projected problem solved in FP64 on the host,
+//   - final Rayleigh quotients and residuals with C in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "msk_internal.h"
+
+namespace msk {
+
+bool sym_eig(int n, std::vector<double>& A, std::vector<double>& evals, std::vector<double>& V);
+bool cholesky_upper(int n, const std::vector<double>& A, std::vector<double>& R, double rel_tol);
+void upper_inverse(int n, const std::vector<double>& R, std::vector<double>& Ri);
+
+// ------------------------------------------------------------- kernels
+
+// C[a][b] = 1/2 (S[ka][kb] + S[kb][ka]) m[a] m[b] over the kept rows.
+__global__ void assemble_c_kernel(const double* __restrict__ S, int64_t ldS, const int32_t* __restrict__ keep,
+                                  const double* __restrict__ m, int64_t n, double* C64, float* C32) {
+  const int64_t total = n * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = idx / n, b = idx - a * n;
+    const int64_t ka = keep[a], kb = keep[b];
+    const double v = 0.5 * (S[ka * ldS + kb] + S[kb * ldS + ka]) * m[a] * m[b];
+    C64[idx] = v;
+    C32[idx] = (float)v;
+  }
+}
+
+__global__ void f64_to_f32_kernel(const double* __restrict__ x, float* y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+// y[r * ldy + c] = x[r * ldx + c] for an r x c sub-block (strided copies, FP32 -> FP64)
+__global__ void copy_block_f32_to_f64_kernel(const float* __restrict__ x, int64_t ldx, double* y, int64_t ldy,
+                                             int64_t rows, int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols, c = i - r * cols;
+    y[r * ldy + c] = (double)x[r * ldx + c];
+  }
+}
+
+__global__ void copy_block_f64_kernel(const double* __restrict__ x, int64_t ldx, double* y, int64_t ldy, int64_t rows,
+                                      int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols, c = i - r * cols;
+    y[r * ldy + c] = x[r * ldx + c];
+  }
+}
+
+__global__ void copy_block_f64_to_f32_kernel(const double* __restrict__ x, int64_t ldx, float* y, int64_t ldy,
+                                             int64_t rows, int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols, c = i - r * cols;
+    y[r * ldy + c] = (float)x[r * ldx + c];
+  }
+}
+
+// Row-major GEMM: C = alpha op(A) op(B) + beta C, op(A) M x K, op(B) K x N.
+// A is M x K (lda) or, transposed, K x M; B is K x N (ldb) or N x K.
+// 64 x 64 output tile per 256-thread workgroup, 4 x 4 per thread, K in steps
+// of 16 through LDS.
+template <typename T, bool TA, bool TB>
+__global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t K, T alpha, const T* __restrict__ A,
+                                                   int64_t lda, const T* __restrict__ B, int64_t ldb, T beta, T* Cm,
+                                                   int64_t ldc) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ T As[BK][BM + 1];
+  __shared__ T Bs[BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int tr = tid / 16, tc = tid % 16;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+    // load A tile: BM x BK elements, 256 threads x 4
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 256;  // 0..1023
+      int mm, kk;
+      if (TA) {  // A stored K x M: contiguous along m
+        kk = e / BM;
+        mm = e % BM;
+      } else {  // A stored M x K: contiguous along k
+        mm = e / BK;
+        kk = e % BK;
+      }
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      T v = T(0);
+      if (gm < M && gk < K) v = TA ? A[gk * lda + gm] : A[gm * lda + gk];
+      As[kk][mm] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 256;
+      int nn, kk;
+      if (TB) {  // B stored N x K: contiguous along k
+        nn = e / BK;
+        kk = e % BK;
+      } else {  // B stored K x N: contiguous along n
+        kk = e / BN;
+        nn = e % BN;
+      }
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      T v = T(0);
+      if (gn < N && gk < K) v = TB ? B[gn * ldb + gk] : B[gk * ldb + gn];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t gm = m0 + tr * 4 + i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t gn = n0 + tc * 4 + j;
+      if (gn >= N) continue;
+      T* c = Cm + gm * ldc + gn;
+      *c = alpha * acc[i][j] + (beta == T(0) ? T(0) : beta * *c);
+    }
+  }
+}
+
+namespace {
+
+int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 1 << 16); }
+
+template <typename T, bool TA, bool TB>
+hipError_t gemm(hipStream_t s, int64_t M, int64_t N, int64_t K, T alpha, const T* A, int64_t lda, const T* B,
+                int64_t ldb, T beta, T* C, int64_t ldc) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
+  hipLaunchKernelGGL((gemm_kernel<T, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  return hipGetLastError();
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  template <typename T>
+  T* as() {
+    return (T*)p;
+  }
+};
+
+#define EIG_TRY(expr)                                             \
+  do {                                                            \
+    hipError_t e_ = (expr);                                       \
+    if (e_ != hipSuccess) {                                       \
+      err = std::string(#expr) + ": " + hipGetErrorString(e_);    \
+      return 3;                                                   \
+    }                                                             \
+  } while (0)
+
+}  // namespace
+
+// Returns 0 on success, 4 if not converged (best approximations written),
+// 1 on bad arguments, 3 on a device error (message in err).
+int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const std::vector<double>& w,
+                         const std::vector<int32_t>& discarded, int k, double* evals, double* evecs, int* iters,
+                         int* block_out, double* max_res, double* ms_out, std::string& err) {
+  hipEvent_t e0, e1;
+  EIG_TRY(hipEventCreate(&e0));
+  EIG_TRY(hipEventCreate(&e1));
+  EIG_TRY(hipEventRecord(e0, s));
+  std::vector<int32_t> keep;
+  for (int64_t i = 0; i < n_rows; ++i)
+    if (w[i] > 0 && !discarded[i]) keep.push_back((int32_t)i);
+  const int64_t n = (int64_t)keep.size();
+  if (k < 1 || k > n) {
+    err = "k must be in 1..(number of kept rows)";
+    return 1;
+  }
+  std::vector<double> m(n);
+  for (int64_t a = 0; a < n; ++a) m[a] = 1.0 / std::sqrt(w[keep[a]]);
+  DevBuf dkeep, dm, dC64, dC32;
+  EIG_TRY(hipMalloc(&dkeep.p, n * 4));
+  EIG_TRY(hipMalloc(&dm.p, n * 8));
+  EIG_TRY(hipMalloc(&dC64.p, (size_t)n * n * 8));
+  EIG_TRY(hipMalloc(&dC32.p, (size_t)n * n * 4));
+  EIG_TRY(hipMemcpyAsync(dkeep.p, keep.data(), n * 4, hipMemcpyHostToDevice, s));
+  EIG_TRY(hipMemcpyAsync(dm.p, m.data(), n * 8, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(assemble_c_kernel, dim3(blocks_for(n * n)), dim3(256), 0, s, dS, n_rows, dkeep.as<int32_t>(),
+                     dm.as<double>(), n, dC64.as<double>(), dC32.as<float>());
+  EIG_TRY(hipGetLastError());
+
+  std::vector<double> theta, Vk;  // final k eigenvalues / n x k vectors (row-major)
+  int status = 0;
+  const int dense_max = 512;
+  if (n <= dense_max) {
+    // the whole space fits the projected problem: solve C itself in FP64
+    std::vector<double> C((size_t)n * n), ev, V;
+    EIG_TRY(hipMemcpyAsync(C.data(), dC64.p, (size_t)n * n * 8, hipMemcpyDeviceToHost, s));
+    EIG_TRY(hipStreamSynchronize(s));
+    if (!sym_eig((int)n, C, ev, V)) {
+      err = "dense eigensolve did not converge";
+      return 4;
+    }
+    theta.assign(ev.begin(), ev.begin() + k);
+    Vk.assign((size_t)n * k, 0.0);
+    for (int64_t r = 0; r < n; ++r)
+      for (int j = 0; j < k; ++j) Vk[(size_t)r * k + j] = V[(size_t)r * n + j];
+    *iters = 1;
+    *block_out = (int)n;
+  } else {
+    // block >= 32: smaller blocks stall on clustered ends of the spectrum
+    const int b = std::min<int>(64, std::max<int>(32, ((k + 7) / 8) * 8));
+    const int cap = (int)std::min<int64_t>(n, std::max(dense_max, k + 6 * b));
+    const int keep_n = std::min(cap - 2 * b, k + 2 * b);
+    // residual target above the floor of FP32 products with C
+    const double tol = std::max(1e-5, 16.0 * std::sqrt((double)n) * std::ldexp(1.0, -24));
+    *block_out = b;
+    DevBuf dQ, dW, dX, dX32, dY32, dT, dG, dY, dQ2, dW2;
+    EIG_TRY(hipMalloc(&dQ.p, (size_t)n * cap * 8));
+    EIG_TRY(hipMalloc(&dW.p, (size_t)n * cap * 8));
+    EIG_TRY(hipMalloc(&dX.p, (size_t)n * b * 8));
+    EIG_TRY(hipMalloc(&dX32.p, (size_t)n * b * 4));
+    EIG_TRY(hipMalloc(&dY32.p, (size_t)n * b * 4));
+    EIG_TRY(hipMalloc(&dT.p, (size_t)cap * cap * 8));
+    EIG_TRY(hipMalloc(&dG.p, (size_t)cap * b * 8));
+    EIG_TRY(hipMalloc(&dY.p, (size_t)cap * cap * 8));
+    EIG_TRY(hipMalloc(&dQ2.p, (size_t)n * cap * 8));
+    EIG_TRY(hipMalloc(&dW2.p, (size_t)n * cap * 8));
+    double* Q = dQ.as<double>();
+    double* Wm = dW.as<double>();
+    double* X = dX.as<double>();
+    int cur = 0;
+    // orthonormalise X (n x b) against Q[:, :cur] and itself, append it to Q
+    // and its product C X to W; false if the block is (numerically) in span(Q)
+    auto add_block = [&](bool& ok) -> int {
+      ok = false;
+      std::vector<double> G((size_t)b * b), R, Ri;
+      for (int pass = 0; pass < 2; ++pass) {
+        if (cur > 0) {  // X -= Q (Q^T X)
+          EIG_TRY((gemm<double, true, false>(s, cur, b, n, 1.0, Q, cap, X, b, 0.0, dG.as<double>(), b)));
+          EIG_TRY((gemm<double, false, false>(s, n, b, cur, -1.0, Q, cap, dG.as<double>(), b, 1.0, X, b)));
+        }
+        EIG_TRY((gemm<double, true, false>(s, b, b, n, 1.0, X, b, X, b, 0.0, dT.as<double>(), b)));
+        EIG_TRY(hipMemcpyAsync(G.data(), dT.p, (size_t)b * b * 8, hipMemcpyDeviceToHost, s));
+        EIG_TRY(hipStreamSynchronize(s));
+        if (!cholesky_upper(b, G, R, 1e-24)) return 0;
+        upper_inverse(b, R, Ri);
+        EIG_TRY(hipMemcpyAsync(dT.p, Ri.data(), (size_t)b * b * 8, hipMemcpyHostToDevice, s));
+        // X = X R^-1 (through a temporary: dQ2's first n*b entries)
+        EIG_TRY((gemm<double, false, false>(s, n, b, b, 1.0, X, b, dT.as<double>(), b, 0.0, dQ2.as<double>(), b)));
+        EIG_TRY(hipMemcpyAsync(X, dQ2.p, (size_t)n * b * 8, hipMemcpyDeviceToDevice, s));
+      }
+      // append X to Q, C X (FP32 product) to W
+      hipLaunchKernelGGL(copy_block_f64_kernel, dim3(blocks_for(n * b)), dim3(256), 0, s, X, (int64_t)b, Q + cur,
+                         (int64_t)cap, n, (int64_t)b);
+      hipLaunchKernelGGL(copy_block_f64_to_f32_kernel, dim3(blocks_for(n * b)), dim3(256), 0, s, X, (int64_t)b,
+                         dX32.as<float>(), (int64_t)b, n, (int64_t)b);
+      EIG_TRY((gemm<float, false, false>(s, n, b, n, 1.0f, dC32.as<float>(), n, dX32.as<float>(), b, 0.0f,
+                                         dY32.as<float>(), b)));
+      hipLaunchKernelGGL(copy_block_f32_to_f64_kernel, dim3(blocks_for(n * b)), dim3(256), 0, s, dY32.as<float>(),
+                         (int64_t)b, Wm + cur, (int64_t)cap, n, (int64_t)b);
+      EIG_TRY(hipGetLastError());
+      cur += b;
+      ok = true;
+      return 0;
+    };
+    // random start block (host RNG, fixed seed)
+    {
+      std::mt19937_64 rng(12345);
+      std::normal_distribution<double> nd;
+      std::vector<double> X0((size_t)n * b);
+      for (auto& x : X0) x = nd(rng);
+      EIG_TRY(hipMemcpyAsync(X, X0.data(), X0.size() * 8, hipMemcpyHostToDevice, s));
+      bool ok;
+      int rc = add_block(ok);
+      if (rc) return rc;
+      if (!ok) {
+        err = "start block is rank deficient";
+        return 4;
+      }
+    }
+    const int max_cycles = 60;
+    double cnorm = 0.0, worst = 0.0;
+    std::vector<double> T, th, Y, res;
+    int cycle;
+    for (cycle = 0; cycle < max_cycles; ++cycle) {
+      // grow the block Krylov space: next block = C (last block)
+      while (cur + b <= cap) {
+        hipLaunchKernelGGL(copy_block_f64_kernel, dim3(blocks_for(n * b)), dim3(256), 0, s, Wm + (cur - b),
+                           (int64_t)cap, X, (int64_t)b, n, (int64_t)b);
+        bool ok;
+        int rc = add_block(ok);
+        if (rc) return rc;
+        if (!ok) break;
+      }
+      // Rayleigh-Ritz on span(Q[:, :cur])
+      EIG_TRY((gemm<double, true, false>(s, cur, cur, n, 1.0, Q, cap, Wm, cap, 0.0, dT.as<double>(), cur)));
+      T.assign((size_t)cur * cur, 0.0);
+      EIG_TRY(hipMemcpyAsync(T.data(), dT.p, T.size() * 8, hipMemcpyDeviceToHost, s));
+      EIG_TRY(hipStreamSynchronize(s));
+      for (int i = 0; i < cur; ++i)
+        for (int j = i + 1; j < cur; ++j) T[(size_t)i * cur + j] = T[(size_t)j * cur + i] =
+            0.5 * (T[(size_t)i * cur + j] + T[(size_t)j * cur + i]);
+      if (!sym_eig(cur, T, th, Y)) {
+        err = "projected eigensolve did not converge";
+        return 4;
+      }
+      for (double t : th) cnorm = std::max(cnorm, std::fabs(t));
+      const int kk = std::min(keep_n, cur);
+      // Ritz vectors V = Q Y[:, :kk], CV = W Y[:, :kk]
+      std::vector<double> Yk((size_t)cur * kk);
+      for (int i = 0; i < cur; ++i)
+        for (int j = 0; j < kk; ++j) Yk[(size_t)i * kk + j] = Y[(size_t)i * cur + j];
+      EIG_TRY(hipMemcpyAsync(dY.p, Yk.data(), Yk.size() * 8, hipMemcpyHostToDevice, s));
+      EIG_TRY((gemm<double, false, false>(s, n, kk, cur, 1.0, Q, cap, dY.as<double>(), kk, 0.0, dQ2.as<double>(), kk)));
+      EIG_TRY((gemm<double, false, false>(s, n, kk, cur, 1.0, Wm, cap, dY.as<double>(), kk, 0.0, dW2.as<double>(), kk)));
+      // residual norms of the first k Ritz pairs: |CV_j - theta_j V_j|
+      std::vector<double> V2((size_t)n * kk), CV2((size_t)n * kk);
+      EIG_TRY(hipMemcpyAsync(V2.data(), dQ2.p, V2.size() * 8, hipMemcpyDeviceToHost, s));
+      EIG_TRY(hipMemcpyAsync(CV2.data(), dW2.p, CV2.size() * 8, hipMemcpyDeviceToHost, s));
+      EIG_TRY(hipStreamSynchronize(s));
+      res.assign(kk, 0.0);
+      for (int64_t r = 0; r < n; ++r)
+        for (int j = 0; j < kk; ++j) {
+          const double d = CV2[(size_t)r * kk + j] - th[j] * V2[(size_t)r * kk + j];
+          res[j] += d * d;
+        }
+      worst = 0.0;
+      for (int j = 0; j < k; ++j) worst = std::max(worst, std::sqrt(res[j]) / std::max(cnorm, 1e-300));
+      const bool done = worst <= tol || cur >= n;
+      if (done || cycle + 1 == max_cycles) {
+        theta.assign(th.begin(), th.begin() + k);
+        Vk.assign((size_t)n * k, 0.0);
+        for (int64_t r = 0; r < n; ++r)
+          for (int j = 0; j < k; ++j) Vk[(size_t)r * k + j] = V2[(size_t)r * kk + j];
+        if (!done) status = 4;
+        break;
+      }
+      // thick restart: keep the kk Ritz pairs, continue from the residuals
+      // of the first b of them
+      hipLaunchKernelGGL(copy_block_f64_kernel, dim3(blocks_for(n * kk)), dim3(256), 0, s, dQ2.as<double>(),
+                         (int64_t)kk, Q, (int64_t)cap, n, (int64_t)kk);
+      hipLaunchKernelGGL(copy_block_f64_kernel, dim3(blocks_for(n * kk)), dim3(256), 0, s, dW2.as<double>(),
+                         (int64_t)kk, Wm, (int64_t)cap, n, (int64_t)kk);
+      EIG_TRY(hipGetLastError());
+      cur = kk;
+      std::vector<double> Rb((size_t)n * b);
+      for (int64_t r = 0; r < n; ++r)
+        for (int j = 0; j < b; ++j) Rb[(size_t)r * b + j] = CV2[(size_t)r * kk + j] - th[j] * V2[(size_t)r * kk + j];
+      EIG_TRY(hipMemcpyAsync(X, Rb.data(), Rb.size() * 8, hipMemcpyHostToDevice, s));
+      bool ok;
+      int rc = add_block(ok);
+      if (rc) return rc;
+      if (!ok) {  // residual block already in the span: cannot improve
+        theta.assign(th.begin(), th.begin() + k);
+        Vk.assign((size_t)n * k, 0.0);
+        for (int64_t r = 0; r < n; ++r)
+          for (int j = 0; j < k; ++j) Vk[(size_t)r * k + j] = V2[(size_t)r * kk + j];
+        status = worst <= tol ? 0 : 4;
+        break;
+      }
+    }
+    *iters = cycle + 1;
+  }
+  // FP64 Rayleigh quotients and residuals with C in FP64
+  {
+    DevBuf dV, dCV;
+    EIG_TRY(hipMalloc(&dV.p, (size_t)n * k * 8));
+    EIG_TRY(hipMalloc(&dCV.p, (size_t)n * k * 8));
+    EIG_TRY(hipMemcpyAsync(dV.p, Vk.data(), Vk.size() * 8, hipMemcpyHostToDevice, s));
+    EIG_TRY((gemm<double, false, false>(s, n, k, n, 1.0, dC64.as<double>(), n, dV.as<double>(), k, 0.0,
+                                        dCV.as<double>(), k)));
+    std::vector<double> CV((size_t)n * k);
+    EIG_TRY(hipMemcpyAsync(CV.data(), dCV.p, CV.size() * 8, hipMemcpyDeviceToHost, s));
+    EIG_TRY(hipStreamSynchronize(s));
+    double cn = 0.0;
+    for (double t : theta) cn = std::max(cn, std::fabs(t));
+    std::vector<double> num(k, 0.0), den(k, 0.0);
+    for (int64_t r = 0; r < n; ++r)
+      for (int j = 0; j < k; ++j) {
+        num[j] += Vk[(size_t)r * k + j] * CV[(size_t)r * k + j];
+        den[j] += Vk[(size_t)r * k + j] * Vk[(size_t)r * k + j];
+      }
+    for (int j = 0; j < k; ++j) theta[j] = num[j] / den[j];
+    double mr = 0.0;
+    std::vector<double> rr(k, 0.0);
+    for (int64_t r = 0; r < n; ++r)
+      for (int j = 0; j < k; ++j) {
+        const double d = CV[(size_t)r * k + j] - theta[j] * Vk[(size_t)r * k + j];
+        rr[j] += d * d;
+      }
+    for (int j = 0; j < k; ++j) mr = std::max(mr, std::sqrt(rr[j] / den[j]));
+    *max_res = mr / std::max(cn, 1e-300);
+  }
+  // order, then psi = M^-1/2 v on the kept rows, zero elsewhere
+  std::vector<int> ord(k);
+  for (int j = 0; j < k; ++j) ord[j] = j;
+  std::sort(ord.begin(), ord.end(), [&](int a2, int b2) { return theta[a2] < theta[b2]; });
+  for (int j = 0; j < k; ++j) evals[j] = theta[ord[j]];
+  if (evecs) {
+    std::memset(evecs, 0, sizeof(double) * n_rows * k);
+    for (int64_t a = 0; a < n; ++a)
+      for (int j = 0; j < k; ++j) evecs[(size_t)keep[a] * k + j] = m[a] * Vk[(size_t)a * k + ord[j]];
+  }
+  EIG_TRY(hipEventRecord(e1, s));
+  EIG_TRY(hipEventSynchronize(e1));
+  float f = 0;
+  EIG_TRY(hipEventElapsedTime(&f, e0, e1));
+  *ms_out = f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return status;
+}
+
+}  // namespace msk

@@ -51,7 +51,7 @@ class DtnOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("max_steps", C.c_int64), ("walk_offset", C.c_int64), ("kappa", C.c_double),
                 ("delta_rel", C.c_double), ("form", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("chunk", C.c_int32), ("regen_min", C.c_int32), ("record_log", C.c_int32), ("se_target", C.c_double),
-                ("walks_max", C.c_int64), ("collect_stats", C.c_int32)]
+                ("walks_max", C.c_int64), ("collect_stats", C.c_int32), ("mesh_id", C.c_int32)]
 
 
 class DtnInfo(C.Structure):
@@ -94,6 +94,13 @@ SIGNATURES = {
     "msk_dtn_get": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_int32], C.c_int),
     "msk_dtn_destroy": ([C.c_void_p], None),
     "msk_steklov_modes": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(EigStats)], C.c_int),
+    "msk_batch_create": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                          C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int64, C.c_int32, C.POINTER(DtnOpts),
+                          C.POINTER(C.c_void_p)], C.c_int),
+    "msk_batch_run": ([C.c_void_p], C.c_int),
+    "msk_batch_dtn": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
+    "msk_batch_get_info": ([C.c_void_p, C.POINTER(DtnInfo)], C.c_int),
+    "msk_batch_destroy": ([C.c_void_p], None),
 }
 
 
@@ -226,6 +233,17 @@ class Context:
                                                    EXTERIOR if exterior else INTERIOR, C.byref(o), outs))
         return [Dtn(self, C.c_void_p(outs[i]), rows[i].n, bases[i].K, walks) for i in range(n)]
 
+    def batch(self, meshes, rows, bases, eps, insets, walks: int, exterior: bool = False, **opts) -> "Batch":
+        """A reusable batch plan (one captured graph over all meshes)."""
+        n = len(meshes)
+        o = self.default_opts(**opts)
+        arr = lambda xs: (C.c_void_p * n)(*[x.h for x in xs])
+        h = C.c_void_p()
+        self._check(lib().msk_batch_create(self.h, n, arr(meshes), arr(rows), arr(bases), (C.c_double * n)(*eps),
+                                           (C.c_double * n)(*insets), walks, EXTERIOR if exterior else INTERIOR,
+                                           C.byref(o), C.byref(h)))
+        return Batch(self, h, [r.n for r in rows], [b.K for b in bases], walks)
+
     def steklov_modes(self, dtn: "Dtn", k: int, vectors: bool = True):
         evals = np.zeros(k)
         evecs = np.zeros((dtn.n, k)) if vectors else None
@@ -315,3 +333,32 @@ class Dtn(_Handle):
         out = np.empty(shape, dtype=dt)
         self.ctx._check(lib().msk_dtn_get(self.h, field, out.ctypes.data, 0))
         return out
+
+
+class _DtnView(Dtn):
+    """A result owned by a batch (not destroyed on its own)."""
+
+    def close(self):
+        self.h = None
+
+
+class Batch(_Handle):
+    _destroy = "msk_batch_destroy"
+
+    def __init__(self, ctx, h, ns, Ks, W):
+        super().__init__(ctx, h)
+        self.ns, self.Ks, self.W = ns, Ks, W
+
+    def run(self) -> dict:
+        self.ctx._check(lib().msk_batch_run(self.h))
+        return self.info()
+
+    def info(self) -> dict:
+        i = DtnInfo()
+        self.ctx._check(lib().msk_batch_get_info(self.h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in DtnInfo._fields_}
+
+    def dtn(self, i: int) -> Dtn:
+        h = C.c_void_p()
+        self.ctx._check(lib().msk_batch_dtn(self.h, i, C.byref(h)))
+        return _DtnView(self.ctx, h, self.ns[i], self.Ks[i], self.W)

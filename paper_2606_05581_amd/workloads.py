@@ -397,13 +397,23 @@ def farthest_point_indices(P, count):
     n = P.shape[0]
     count = min(count, n)
     idx = np.empty(count, dtype=np.int64)
-    d = np.full(n, np.inf)
+    X = np.ascontiguousarray(P, dtype=np.float32)
+    x, y, z = X[:, 0].copy(), X[:, 1].copy(), X[:, 2].copy()
+    d = np.full(n, np.inf, dtype=np.float32)
+    t = np.empty(n, dtype=np.float32)
+    u = np.empty(n, dtype=np.float32)
     cur = 0
-    P32 = P.astype(np.float64)
     for k in range(count):
         idx[k] = cur
-        diff = P32 - P32[cur]
-        np.minimum(d, np.einsum("ij,ij->i", diff, diff), out=d)
+        np.subtract(x, x[cur], out=t)
+        np.multiply(t, t, out=t)
+        np.subtract(y, y[cur], out=u)
+        np.multiply(u, u, out=u)
+        np.add(t, u, out=t)
+        np.subtract(z, z[cur], out=u)
+        np.multiply(u, u, out=u)
+        np.add(t, u, out=t)
+        np.minimum(d, t, out=d)
         cur = int(np.argmax(d))
     return idx
 
@@ -590,7 +600,7 @@ def batch64_mixed(n_meshes=64, walks=1024, face_lo=5e3, face_hi=5e5, rows_lo=512
         V = V @ random_rotation(rng).T
         V = normalise_unit_ball(V)
         N = int(rng.integers(rows_lo, rows_hi + 1))
-        cases.append(_point_case(V, F, N, rng, pool_factor=8))
+        cases.append(_point_case(V, F, N, rng, pool_factor=4))
     return Workload("batch64_mixed", cases, walks=walks, modes=["interior"], k=0)
 
 
@@ -671,7 +681,7 @@ def load(name: str, cache: bool = True, **kw) -> Workload:
     fn = WORKLOADS[name]
     if not cache:
         return fn(**kw)
-    key = hashlib.sha1((name + repr(sorted(kw.items())) + "v1").encode()).hexdigest()[:12]
+    key = hashlib.sha1((name + repr(sorted(kw.items())) + "v2").encode()).hexdigest()[:12]
     path = os.path.join(_cache_dir(), f"{name}_{key}.npz")
     if os.path.exists(path):
         return _load(path)

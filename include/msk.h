@@ -68,7 +68,7 @@ const char* msk_last_error(const msk_ctx* ctx);
 
 typedef struct {
   int32_t leaf_size; /* triangles per BVH leaf, 1..8 (default 4)            */
-  int32_t top_nodes; /* BVH nodes cached in LDS per workgroup, 0..128 (def. 85) */
+  int32_t top_nodes; /* BVH nodes cached in LDS per workgroup, 0..85 (def. 85) */
 } msk_bvh_opts;
 
 typedef struct {
@@ -181,6 +181,9 @@ typedef struct {
                             operations (a separately compiled, slower kernel) */
   int32_t mesh_id;       /* single-mesh estimates: the mesh index in the Philox
                             counter (a batch uses each mesh's position)       */
+  int32_t accum;         /* persistent form, partial row sums of a chunk of
+                            walks kept in LDS: 0 = FP64, 1 = FP32 (mixed
+                            precision); rows are always accumulated in FP64  */
 } msk_dtn_opts;
 
 void msk_dtn_opts_default(msk_dtn_opts* opts);
@@ -218,8 +221,9 @@ msk_status msk_estimate_dtn_batched(msk_ctx* ctx, int32_t n_meshes, const msk_me
 /* A reusable batch: the same meshes, rows and bases estimated again and
  * again (serving). Creation allocates every mesh's outputs, orders the work
  * (meshes largest first, rows in Z-order, split over eight per-XCD queues)
- * and captures zeroing, the discard pass, ONE persistent walk launch over all
- * meshes and the finalisation into a HIP graph; msk_batch_run replays it.
+ * and captures HIP graphs of the zeroing and discard pass, of ONE persistent
+ * walk launch over all meshes, and of the finalisation; msk_batch_run
+ * replays them back to back on the context's stream.
  * Arguments as for msk_estimate_dtn_batched; the handles must outlive the
  * batch. Results of the last run are read with msk_batch_dtn (views owned by
  * the batch, valid until msk_batch_destroy). */

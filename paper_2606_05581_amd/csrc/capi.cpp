@@ -192,7 +192,7 @@ extern "C" msk_status msk_build_bvh(msk_ctx* ctx, const float* V, int64_t n_vert
   if (n_verts >= INT32_MAX || n_tris >= (1ll << 30)) return fail(ctx, MSK_ERR_INVALID_ARG, "mesh too large");
   int leaf = opts && opts->leaf_size > 0 ? opts->leaf_size : 4;
   int top = opts ? opts->top_nodes : 85;
-  if (top < 0 || top > kMaxTop) return fail(ctx, MSK_ERR_INVALID_ARG, "top_nodes must be in 0..128");
+  if (top < 0 || top > kMaxTop) return fail(ctx, MSK_ERR_INVALID_ARG, "top_nodes must be in 0..85");
   HostBvh B;
   std::string e = build_bvh_host(V, n_verts, F, n_tris, leaf, B);
   if (!e.empty()) return fail(ctx, MSK_ERR_INVALID_ARG, e);
@@ -421,6 +421,7 @@ extern "C" void msk_dtn_opts_default(msk_dtn_opts* o) {
   o->walks_max = 65536;
   o->collect_stats = 0;
   o->mesh_id = 0;
+  o->accum = 0;
 }
 
 namespace {
@@ -591,6 +592,7 @@ static msk_status run_walks(msk_ctx* ctx, const std::vector<MeshDev>& meshes, co
   L.regen_min = std::min(64, std::max(1, o.regen_min));
   L.use_lds_top = use_lds_top;
   L.n_top = n_top;
+  L.accum_f32 = o.accum == 1 ? 1 : 0;
   if (o.collect_stats) {
     HIP_TRY(ctx, dalloc(&lb.d_stats, 3));
     HIP_TRY(ctx, launch_fill_u64(lb.d_stats, 3, 0, ctx->stream));
@@ -663,6 +665,7 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
   msk_dtn_opts_default(&o);
   if (opts) o = *opts;
   if (o.form != MSK_FORM_PLAIN && o.form != MSK_FORM_PERSISTENT) return fail(ctx, MSK_ERR_INVALID_ARG, "bad form");
+  if (o.accum != 0 && o.accum != 1) return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64) or 1 (FP32)");
   if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32))
     return fail(ctx, MSK_ERR_INVALID_ARG, "walk indices must fit in 32 bits");
   const bool adaptive = o.se_target > 0;
@@ -774,15 +777,18 @@ struct msk_batch {
   std::vector<MeshDev> md;
   std::vector<const msk_rows*> rows;
   LaunchBuffers lb;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, evw0 = nullptr, evw1 = nullptr;
-  bool walk_events = false;
+  // three captured graphs replayed back to back: prepare (zeroing, discard
+  // pass, queues), the one persistent walk launch, finalisation
+  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   msk_dtn_info total{};
   ~msk_batch() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    for (hipEvent_t e : {ev0, ev1, evw0, evw1})
+    for (int i = 0; i < 3; ++i) {
+      if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+      if (graph[i]) (void)hipGraphDestroy(graph[i]);
+    }
+    for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
     for (msk_dtn* d : dtns)
       if (d) {
@@ -792,49 +798,48 @@ struct msk_batch {
   }
 };
 
-// Everything one batch run does, queued on `s` (captured into the graph).
-static hipError_t enqueue_batch(msk_batch* B, hipStream_t s, bool record_walk_events) {
+// Stage `part` of one batch run (0 prepare, 1 walks, 2 finalise), queued on s.
+static hipError_t enqueue_batch(msk_batch* B, hipStream_t s, int part) {
   hipError_t e;
-  for (int32_t i = 0; i < B->n; ++i) {
-    msk_dtn* d = B->dtns[i];
-    const int64_t nk = d->n * d->K;
-    if ((e = launch_fill_u64(d->d_acc1, nk, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u64(d->d_acc2, nk, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u64(d->d_q, d->n, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u64(d->d_esc, d->n, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u64(d->d_cap, d->n, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u64(d->d_walks, d->n, (unsigned long long)B->W, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u32(d->d_disc, d->n, 0u, s)) != hipSuccess) return e;
-    if (B->md[i].mode == kRowsPoint && (e = launch_discard(B->md[i], d->n, d->d_disc, s)) != hipSuccess) return e;
+  if (part == 0) {
+    for (int32_t i = 0; i < B->n; ++i) {
+      msk_dtn* d = B->dtns[i];
+      const int64_t nk = d->n * d->K;
+      if ((e = launch_fill_u64(d->d_acc1, nk, 0, s)) != hipSuccess) return e;
+      if ((e = launch_fill_u64(d->d_acc2, nk, 0, s)) != hipSuccess) return e;
+      if ((e = launch_fill_u64(d->d_q, d->n, 0, s)) != hipSuccess) return e;
+      if ((e = launch_fill_u64(d->d_esc, d->n, 0, s)) != hipSuccess) return e;
+      if ((e = launch_fill_u64(d->d_cap, d->n, 0, s)) != hipSuccess) return e;
+      if ((e = launch_fill_u64(d->d_walks, d->n, (unsigned long long)B->W, s)) != hipSuccess) return e;
+      if ((e = launch_fill_u32(d->d_disc, d->n, 0u, s)) != hipSuccess) return e;
+      if (B->md[i].mode == kRowsPoint && (e = launch_discard(B->md[i], d->n, d->d_disc, s)) != hipSuccess) return e;
+    }
+    int64_t n_slots = 0;
+    for (msk_dtn* d : B->dtns) n_slots += d->n;
+    if ((e = launch_init_queues(B->lb.d_qnext, B->lb.d_qend, make_queues(n_slots, B->W), s)) != hipSuccess)
+      return e;
+    if (B->o.collect_stats && (e = launch_fill_u64(B->lb.d_stats, 3, 0, s)) != hipSuccess) return e;
+    return hipSuccess;
   }
-  WalkLaunch L;
-  std::memset(&L, 0, sizeof(L));
-  L.meshes = B->lb.d_meshes;
-  L.slots = B->lb.d_slots;
-  L.walks_per_slot = B->W;
-  L.walk_offset = B->o.walk_offset;
-  L.seed_lo = (uint32_t)B->o.seed;
-  L.seed_hi = (uint32_t)(B->o.seed >> 32);
-  L.queue_next = B->lb.d_qnext;
-  L.queue_end = B->lb.d_qend;
-  L.chunk = std::max(1, B->o.chunk);
-  L.regen_min = std::min(64, std::max(1, B->o.regen_min));
-  int64_t n_slots = 0;
-  for (msk_dtn* d : B->dtns) n_slots += d->n;
-  L.n_slots = n_slots;
-  if (B->o.collect_stats) {
-    if ((e = launch_fill_u64(B->lb.d_stats, 3, 0, s)) != hipSuccess) return e;
-    L.stats = B->lb.d_stats;
+  if (part == 1) {
+    WalkLaunch L;
+    std::memset(&L, 0, sizeof(L));
+    L.meshes = B->lb.d_meshes;
+    L.slots = B->lb.d_slots;
+    L.walks_per_slot = B->W;
+    L.walk_offset = B->o.walk_offset;
+    L.seed_lo = (uint32_t)B->o.seed;
+    L.seed_hi = (uint32_t)(B->o.seed >> 32);
+    L.queue_next = B->lb.d_qnext;
+    L.queue_end = B->lb.d_qend;
+    L.chunk = std::max(1, B->o.chunk);
+    L.regen_min = std::min(64, std::max(1, B->o.regen_min));
+    L.accum_f32 = B->o.accum == 1 ? 1 : 0;
+    for (msk_dtn* d : B->dtns) L.n_slots += d->n;
+    if (B->o.collect_stats) L.stats = B->lb.d_stats;
+    if (B->o.form == MSK_FORM_PLAIN) return launch_walk_plain(L, s);
+    return launch_walk_persistent(L, std::max(1, B->ctx->n_cu * std::max(1, B->o.blocks_per_cu)), s);
   }
-  if ((e = launch_init_queues(B->lb.d_qnext, B->lb.d_qend, make_queues(n_slots, B->W), s)) != hipSuccess) return e;
-  if (record_walk_events && (e = hipEventRecord(B->evw0, s)) != hipSuccess) return e;
-  if (B->o.form == MSK_FORM_PLAIN) {
-    e = launch_walk_plain(L, s);
-  } else {
-    e = launch_walk_persistent(L, std::max(1, B->ctx->n_cu * std::max(1, B->o.blocks_per_cu)), s);
-  }
-  if (e != hipSuccess) return e;
-  if (record_walk_events && (e = hipEventRecord(B->evw1, s)) != hipSuccess) return e;
   for (int32_t i = 0; i < B->n; ++i) {
     msk_dtn* d = B->dtns[i];
     if ((e = launch_finalize(B->md[i], d->n, d->d_walks, B->rows[i]->d_w, d->d_S, d->d_se, s)) != hipSuccess)
@@ -857,6 +862,7 @@ extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk
   if (o.se_target > 0 || o.record_log) return fail(ctx, MSK_ERR_INVALID_ARG, "batches take a fixed walk count, no log");
   if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32))
     return fail(ctx, MSK_ERR_INVALID_ARG, "walk indices must fit in 32 bits");
+  if (o.accum != 0 && o.accum != 1) return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64) or 1 (FP32)");
   for (int32_t i = 0; i < n_meshes; ++i) {
     msk_status st = check_problem(ctx, meshes[i], rows[i], bases[i], walks, eps[i], inset_h[i], side);
     if (st != MSK_OK) return fail(ctx, st, "mesh " + std::to_string(i) + ": " + ctx->err);
@@ -891,31 +897,38 @@ extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk
   if ((he = upload(ctx, &B->lb.d_meshes, B->md.data(), B->md.size())) != hipSuccess ||
       (he = upload(ctx, &B->lb.d_slots, slots.data(), slots.size())) != hipSuccess ||
       (he = dalloc(&B->lb.d_qnext, 8)) != hipSuccess || (he = dalloc(&B->lb.d_qend, 8)) != hipSuccess ||
-      (he = dalloc(&B->lb.d_stats, 3)) != hipSuccess ||
-      (he = hipEventCreate(&B->ev0)) != hipSuccess || (he = hipEventCreate(&B->ev1)) != hipSuccess ||
-      (he = hipEventCreate(&B->evw0)) != hipSuccess || (he = hipEventCreate(&B->evw1)) != hipSuccess) {
+      (he = dalloc(&B->lb.d_stats, 3)) != hipSuccess) {
     delete B;
     return fail(ctx, MSK_ERR_DEVICE, std::string("batch setup: ") + hipGetErrorString(he));
   }
-  // capture the whole run; events inside the graph time the walk launch
-  he = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
-  if (he == hipSuccess) {
-    hipError_t ee = enqueue_batch(B, ctx->stream, true);
+  for (int i = 0; i < 4; ++i)
+    if ((he = hipEventCreate(&B->ev[i])) != hipSuccess) {
+      delete B;
+      return fail(ctx, MSK_ERR_DEVICE, std::string("batch events: ") + hipGetErrorString(he));
+    }
+  // capture on a stream of its own (the context's stream may be the legacy
+  // null stream, which cannot be captured); replay on the context's stream
+  hipStream_t cap = nullptr;
+  he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  for (int part = 0; part < 3 && he == hipSuccess; ++part) {
+    he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (he != hipSuccess) break;
+    hipError_t ee = enqueue_batch(B, cap, part);
     hipGraph_t g = nullptr;
-    he = hipStreamEndCapture(ctx->stream, &g);
+    he = hipStreamEndCapture(cap, &g);
     if (ee != hipSuccess) he = ee;
     if (he == hipSuccess) {
-      B->graph = g;
-      he = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
+      B->graph[part] = g;
+      he = hipGraphInstantiate(&B->exec[part], g, nullptr, nullptr, 0);
     } else if (g) {
       (void)hipGraphDestroy(g);
     }
   }
+  if (cap) (void)hipStreamDestroy(cap);
   if (he != hipSuccess) {
     delete B;
     return fail(ctx, MSK_ERR_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(he));
   }
-  B->walk_events = true;
   *out = B;
   return MSK_OK;
 }
@@ -923,13 +936,17 @@ extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk
 extern "C" msk_status msk_batch_run(msk_batch* B) {
   if (!B) return MSK_ERR_INVALID_ARG;
   msk_ctx* ctx = B->ctx;
-  HIP_TRY(ctx, hipEventRecord(B->ev0, ctx->stream));
-  HIP_TRY(ctx, hipGraphLaunch(B->exec, ctx->stream));
-  HIP_TRY(ctx, hipEventRecord(B->ev1, ctx->stream));
-  HIP_TRY(ctx, hipEventSynchronize(B->ev1));
+  HIP_TRY(ctx, hipEventRecord(B->ev[0], ctx->stream));
+  HIP_TRY(ctx, hipGraphLaunch(B->exec[0], ctx->stream));
+  HIP_TRY(ctx, hipEventRecord(B->ev[1], ctx->stream));
+  HIP_TRY(ctx, hipGraphLaunch(B->exec[1], ctx->stream));
+  HIP_TRY(ctx, hipEventRecord(B->ev[2], ctx->stream));
+  HIP_TRY(ctx, hipGraphLaunch(B->exec[2], ctx->stream));
+  HIP_TRY(ctx, hipEventRecord(B->ev[3], ctx->stream));
+  HIP_TRY(ctx, hipEventSynchronize(B->ev[3]));
   float tot = 0, wk = 0;
-  HIP_TRY(ctx, hipEventElapsedTime(&tot, B->ev0, B->ev1));
-  if (B->walk_events) HIP_TRY(ctx, hipEventElapsedTime(&wk, B->evw0, B->evw1));
+  HIP_TRY(ctx, hipEventElapsedTime(&tot, B->ev[0], B->ev[3]));
+  HIP_TRY(ctx, hipEventElapsedTime(&wk, B->ev[1], B->ev[2]));
   msk_dtn_info T{};
   for (int32_t i = 0; i < B->n; ++i) {
     msk_dtn* d = B->dtns[i];

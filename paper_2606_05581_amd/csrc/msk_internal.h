@@ -29,7 +29,7 @@ static_assert(sizeof(TriRec) == 48, "triangle record must be 48 bytes");
 
 constexpr int kStackDepth = 64;     // traversal stack entries per lane
 constexpr int kMaxTableNnz = 32;    // basis entries per vertex
-constexpr int kMaxTop = 128;        // BVH nodes a workgroup may keep in LDS
+constexpr int kMaxTop = 85;         // BVH nodes a workgroup may keep in LDS (3 levels)
 
 // Host-side BVH build result.
 struct HostBvh {
@@ -122,6 +122,7 @@ struct WalkLaunch {
   int32_t use_lds_top;         // single-mesh launch: stage mesh 0's top nodes in LDS
   int32_t n_top;
   unsigned long long* stats;   // optional: [nodes visited, triangles tested, FP32 operations]
+  int32_t accum_f32;           // persistent form: FP32 partial sums in the wavefront row tables
 };
 
 }  // namespace msk

@@ -291,6 +291,7 @@ struct LaneWalk {
   int32_t slot;  // warm-start triangle slot
   int32_t active;
   TravCount cnt;  // traversal work of this walk (counted in the statistics kernels only)
+  int32_t tab;    // wavefront row table of the walk (-1: device atomics)
 };
 
 // Start of a walk: sample s (point rows: the fixed sample; hat rows:
@@ -378,12 +379,12 @@ __device__ __forceinline__ void merge_rows(const MeshDev& M, const int32_t (&vtx
   }
 }
 
-// Scatter a finished walk into its row and counters.
-__device__ void walk_finish(const WalkLaunch& L, const MeshDev& M, const LaneWalk& w, int32_t status,
-                            const Nearest& hit) {
-  const bool has_t = status != kEscaped && hit.orig >= 0 && hit.orig < M.n_tris;
-  double* a1 = M.acc1 + (int64_t)w.row * M.K;
-  double* a2 = M.acc2 + (int64_t)w.row * M.K;
+// Contribution of a finished walk to its row, emitted once per column:
+// point rows emit b(t) (the start is fixed per row; the finalisation folds
+// in b(s)), hat rows emit c = b(s) - b(t). Escaped walks have b(t) = 0.
+template <typename Emit>
+__device__ void walk_contrib(const WalkLaunch& L, const MeshDev& M, const LaneWalk& w, bool has_t, const Nearest& hit,
+                             Emit emit) {
   int32_t tv[3] = {-1, -1, -1};
   double tw[3] = {0.0, 0.0, 0.0};
   if (has_t) {
@@ -393,13 +394,7 @@ __device__ void walk_finish(const WalkLaunch& L, const MeshDev& M, const LaneWal
     tw[0] = (1.0 - l1) - l2; tw[1] = l1; tw[2] = l2;
   }
   if (M.mode == kRowsPoint) {
-    // the start is fixed per row: accumulate b(t) and b(t)^2 only; the
-    // finalisation folds in b(s)
-    if (has_t)
-      merge_rows<3>(M, tv, tw, [&](int32_t j, double v) {
-        atomicAdd(a1 + j, v);
-        atomicAdd(a2 + j, v * v);
-      });
+    if (has_t) merge_rows<3>(M, tv, tw, emit);
   } else {
     int32_t face;
     double lam[3];
@@ -408,19 +403,18 @@ __device__ void walk_finish(const WalkLaunch& L, const MeshDev& M, const LaneWal
     const int32_t* f = M.faces + 3 * (int64_t)face;
     const int32_t vv[6] = {f[0], f[1], f[2], tv[0], tv[1], tv[2]};
     const double ww[6] = {lam[0], lam[1], lam[2], -tw[0], -tw[1], -tw[2]};
-    merge_rows<6>(M, vv, ww, [&](int32_t j, double v) {
-      atomicAdd(a1 + j, v);
-      atomicAdd(a2 + j, v * v);
-    });
+    merge_rows<6>(M, vv, ww, emit);
   }
-  atomicAdd(M.row_queries + w.row, (unsigned long long)w.queries);
+}
+
+// Walk log and traversal statistics of a finished walk.
+__device__ void walk_record(const WalkLaunch& L, const MeshDev& M, const LaneWalk& w, int32_t status, bool has_t,
+                            const Nearest& hit) {
   if (L.stats) {
     atomicAdd(L.stats, (unsigned long long)w.cnt.nodes);
     atomicAdd(L.stats + 1, (unsigned long long)w.cnt.tris);
     atomicAdd(L.stats + 2, (unsigned long long)w.cnt.flops);
   }
-  if (status == kEscaped) atomicAdd(M.row_escaped + w.row, 1ull);
-  if (status == kCapped) atomicAdd(M.row_capped + w.row, 1ull);
   if (M.log_status) {
     const int64_t li = (int64_t)w.row * M.walks_per_row + ((int64_t)w.walk - L.walk_offset);
     M.log_status[li] = status;
@@ -429,6 +423,102 @@ __device__ void walk_finish(const WalkLaunch& L, const MeshDev& M, const LaneWal
     M.log_bary[2 * li + 1] = has_t ? hit.l2 : 0.0f;
     M.log_queries[li] = w.queries;
   }
+}
+
+__device__ __forceinline__ bool walk_has_t(const MeshDev& M, int32_t status, const Nearest& hit) {
+  return status != kEscaped && hit.orig >= 0 && hit.orig < M.n_tris;
+}
+
+// Scatter a finished walk straight into its row with FP64 device atomics.
+__device__ void walk_finish_global(const WalkLaunch& L, const MeshDev& M, const LaneWalk& w, int32_t status,
+                                   const Nearest& hit) {
+  const bool has_t = walk_has_t(M, status, hit);
+  double* a1 = M.acc1 + (int64_t)w.row * M.K;
+  double* a2 = M.acc2 + (int64_t)w.row * M.K;
+  walk_contrib(L, M, w, has_t, hit, [&](int32_t j, double v) {
+    atomicAdd(a1 + j, v);
+    atomicAdd(a2 + j, v * v);
+  });
+  atomicAdd(M.row_queries + w.row, (unsigned long long)w.queries);
+  if (status == kEscaped) atomicAdd(M.row_escaped + w.row, 1ull);
+  if (status == kCapped) atomicAdd(M.row_capped + w.row, 1ull);
+  walk_record(L, M, w, status, has_t, hit);
+}
+
+// ---- wavefront row tables (persistent form)
+// Each wavefront owns two small open-addressing tables in LDS, column ->
+// (sum v, sum v^2), plus the row's query / escape / cap counts. The walks of
+// one queue chunk (one row) add into one table with LDS atomics; when the
+// chunk's last walk has finished, the wavefront flushes the table into the
+// FP64 row with one device atomic per distinct column. AccT = double keeps
+// the partial sums in FP64; AccT = float keeps them in FP32 (a chunk holds at
+// most `chunk` walks) and flushes them into the FP64 rows.
+constexpr int kSlotBits = 8, kSlots = 1 << kSlotBits, kProbes = 8, kWaves = 4;
+constexpr int32_t kEmptyKey = -1;
+
+template <typename AccT>
+struct WaveTables {
+  int32_t key[kWaves][2][kSlots];
+  AccT v1[kWaves][2][kSlots];
+  AccT v2[kWaves][2][kSlots];
+  unsigned long long cnt[kWaves][2][3];
+};
+
+template <typename AccT>
+__device__ __forceinline__ void table_add(WaveTables<AccT>& T, int wi, int t, int32_t j, double v, double* g1,
+                                          double* g2) {
+  const uint32_t h = ((uint32_t)j * 2654435761u) >> (32 - kSlotBits);
+#pragma unroll 1
+  for (int p = 0; p < kProbes; ++p) {
+    const uint32_t si = (h + (uint32_t)p) & (kSlots - 1);
+    const int32_t old = atomicCAS(&T.key[wi][t][si], kEmptyKey, j);
+    if (old == kEmptyKey || old == j) {
+      atomicAdd(&T.v1[wi][t][si], (AccT)v);
+      atomicAdd(&T.v2[wi][t][si], (AccT)(v * v));
+      return;
+    }
+  }
+  atomicAdd(g1 + j, v);  // table full along this probe sequence
+  atomicAdd(g2 + j, v * v);
+}
+
+template <typename AccT>
+__device__ void walk_finish_table(const WalkLaunch& L, const MeshDev& M, const LaneWalk& w, int32_t status,
+                                  const Nearest& hit, WaveTables<AccT>& T, int wi) {
+  const bool has_t = walk_has_t(M, status, hit);
+  double* a1 = M.acc1 + (int64_t)w.row * M.K;
+  double* a2 = M.acc2 + (int64_t)w.row * M.K;
+  walk_contrib(L, M, w, has_t, hit, [&](int32_t j, double v) { table_add(T, wi, w.tab, j, v, a1, a2); });
+  atomicAdd(&T.cnt[wi][w.tab][0], (unsigned long long)w.queries);
+  if (status == kEscaped) atomicAdd(&T.cnt[wi][w.tab][1], 1ull);
+  if (status == kCapped) atomicAdd(&T.cnt[wi][w.tab][2], 1ull);
+  walk_record(L, M, w, status, has_t, hit);
+}
+
+// Wavefront-cooperative flush of table t into row `row` of mesh `mesh`.
+template <typename AccT>
+__device__ void table_flush(const WalkLaunch& L, WaveTables<AccT>& T, int wi, int t, int32_t mesh, int32_t row) {
+  __builtin_amdgcn_wave_barrier();
+  const MeshDev& F = L.meshes[mesh];
+  double* a1 = F.acc1 + (int64_t)row * F.K;
+  double* a2 = F.acc2 + (int64_t)row * F.K;
+  for (int i = (int)__lane_id(); i < kSlots; i += 64) {
+    const int32_t j = T.key[wi][t][i];
+    if (j != kEmptyKey) {
+      atomicAdd(a1 + j, (double)T.v1[wi][t][i]);
+      atomicAdd(a2 + j, (double)T.v2[wi][t][i]);
+      T.key[wi][t][i] = kEmptyKey;
+      T.v1[wi][t][i] = (AccT)0;
+      T.v2[wi][t][i] = (AccT)0;
+    }
+  }
+  if (__lane_id() == 0) {
+    if (T.cnt[wi][t][0]) atomicAdd(F.row_queries + row, T.cnt[wi][t][0]);
+    if (T.cnt[wi][t][1]) atomicAdd(F.row_escaped + row, T.cnt[wi][t][1]);
+    if (T.cnt[wi][t][2]) atomicAdd(F.row_capped + row, T.cnt[wi][t][2]);
+    T.cnt[wi][t][0] = T.cnt[wi][t][1] = T.cnt[wi][t][2] = 0;
+  }
+  __builtin_amdgcn_wave_barrier();
 }
 
 // Orthonormal frame (e1, e2) completing a unit vector n (branchless, after
@@ -530,7 +620,7 @@ __global__ void __launch_bounds__(256) walk_plain_kernel(WalkLaunch L) {
     st = walk_step<kStats>(L, M, nullptr, 0, w, hit);
   } while (st < 0);
   if (st == kCapped) cap_walk<kStats>(M, nullptr, 0, w, hit);
-  walk_finish(L, M, w, st, hit);
+  walk_finish_global(L, M, w, st, hit);
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -538,10 +628,19 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 // Persistent form: each wavefront keeps its 64 lanes busy by refilling
 // finished lanes with the next walks of its queue chunk; chunks come from
 // one of eight queues (one per XCD, blockIdx % 8) and wavefronts move on to
-// the other queues once their own is drained.
-template <bool kStats>
+// the other queues once their own is drained. Finished walks go into the
+// wavefront's row tables (see WaveTables).
+template <bool kStats, typename AccT>
 __global__ void __launch_bounds__(256) walk_persistent_kernel(WalkLaunch L) {
   __shared__ Node4 top[kMaxTop];
+  __shared__ WaveTables<AccT> T;
+  const int wi = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < kWaves * 2 * kSlots; i += blockDim.x) {
+    (&T.key[0][0][0])[i] = kEmptyKey;
+    (&T.v1[0][0][0])[i] = (AccT)0;
+    (&T.v2[0][0][0])[i] = (AccT)0;
+  }
+  for (int i = threadIdx.x; i < kWaves * 2 * 3; i += blockDim.x) (&T.cnt[0][0][0])[i] = 0;
   int32_t n_lds = 0;
   if (L.use_lds_top) {
     n_lds = L.n_top;
@@ -549,13 +648,17 @@ __global__ void __launch_bounds__(256) walk_persistent_kernel(WalkLaunch L) {
     const int4* src = (const int4*)M0.nodes;
     int4* dst = (int4*)top;
     for (int i = threadIdx.x; i < n_lds * 8; i += blockDim.x) dst[i] = src[i];
-    __syncthreads();
   }
+  __syncthreads();
   const int qhome = blockIdx.x & 7;
   int qi = 0;  // queues tried so far (uniform)
   uint64_t cur = 0, cend = 0;
+  // wave-uniform table bookkeeping
+  int32_t t_used[2] = {0, 0}, t_mesh[2] = {0, 0}, t_row[2] = {0, 0}, t_out[2] = {0, 0};
+  int32_t c_tab = -1, c_mesh = -1, c_row = -1;  // current chunk's row and table
   LaneWalk w;
   w.active = 0;
+  w.tab = -1;
   Nearest hit;
   bool drained = false;
   while (true) {
@@ -565,7 +668,7 @@ __global__ void __launch_bounds__(256) walk_persistent_kernel(WalkLaunch L) {
       while (idle != 0 && !drained) {
         if (cur >= cend) {
           uint64_t start = 0;
-          if (lane_id() == 0) {
+          if (__lane_id() == 0) {
             const int q = (qhome + qi) & 7;
             start = atomicAdd(L.queue_next + q, (unsigned long long)L.chunk);
           }
@@ -579,35 +682,79 @@ __global__ void __launch_bounds__(256) walk_persistent_kernel(WalkLaunch L) {
           }
           cur = start;
           cend = min(start + (uint64_t)L.chunk, qend);
+          // the chunk's row takes the table it already has, else a free one
+          const RowSlot rs = L.slots[start / (uint64_t)L.walks_per_slot];
+          c_mesh = rs.mesh;
+          c_row = rs.row;
+          c_tab = -1;
+          for (int t = 0; t < 2; ++t)
+            if (t_used[t] && t_mesh[t] == c_mesh && t_row[t] == c_row) c_tab = t;
+          if (c_tab < 0) {
+            for (int t = 0; t < 2; ++t)
+              if (!t_used[t] && c_tab < 0) {
+                c_tab = t;
+                t_used[t] = 1;
+                t_mesh[t] = c_mesh;
+                t_row[t] = c_row;
+              }
+          }
         }
-        const uint32_t rank = __popcll(idle & ((1ull << lane_id()) - 1ull));
+        const uint32_t rank = __popcll(idle & ((1ull << __lane_id()) - 1ull));
         const uint64_t avail = cend - cur;
         const uint32_t take = (uint32_t)min(avail, (uint64_t)__popcll(idle));
+        bool fresh = false;
         if (!w.active && rank < take) {
           decode_walk(L, cur + rank, w);
           int32_t face;
           double lam[3];
           const MeshDev& M = L.meshes[w.mesh];
           w.active = walk_start(L, M, w, face, lam) ? 1 : 0;
+          w.tab = (w.active && c_tab >= 0 && w.mesh == c_mesh && w.row == c_row) ? c_tab : -1;
+          fresh = w.active && w.tab >= 0;
         }
+        if (c_tab >= 0) t_out[c_tab] += (int32_t)__popcll(__ballot(fresh));
         cur += take;
         idle = __ballot(!w.active);
         // lanes whose row was discarded stay idle; keep filling
       }
     }
     if (__ballot(w.active) == 0) {
-      if (drained) break;
+      if (drained) {
+        for (int t = 0; t < 2; ++t)
+          if (t_used[t]) {
+            table_flush(L, T, wi, t, t_mesh[t], t_row[t]);
+            t_used[t] = 0;
+          }
+        break;
+      }
       continue;
     }
     // ---- one step of every live walk
+    bool fin = false;
+    int32_t fin_tab = -1;
     if (w.active) {
       const MeshDev& M = L.meshes[w.mesh];
       const int32_t nl = (w.mesh == 0) ? n_lds : 0;
       const int32_t st = walk_step<kStats>(L, M, top, nl, w, hit);
       if (st >= 0) {
         if (st == kCapped) cap_walk<kStats>(M, top, nl, w, hit);
-        walk_finish(L, M, w, st, hit);
+        if (w.tab >= 0)
+          walk_finish_table(L, M, w, st, hit, T, wi);
+        else
+          walk_finish_global(L, M, w, st, hit);
+        fin = true;
+        fin_tab = w.tab;
         w.active = 0;
+        w.tab = -1;
+      }
+    }
+    for (int t = 0; t < 2; ++t) {
+      t_out[t] -= (int32_t)__popcll(__ballot(fin && fin_tab == t));
+      // flush once the table's walks are done and its chunk hands out no more
+      if (t_used[t] && t_out[t] == 0 && !(t == c_tab && cur < cend)) {
+        table_flush(L, T, wi, t, t_mesh[t], t_row[t]);
+        t_used[t] = 0;
+        if (c_tab == t) c_tab = -1;
       }
     }
   }
@@ -726,10 +873,17 @@ hipError_t launch_walk_plain(const WalkLaunch& L, hipStream_t s) {
 }
 
 hipError_t launch_walk_persistent(const WalkLaunch& L, int grid, hipStream_t s) {
-  if (L.stats)
-    hipLaunchKernelGGL(walk_persistent_kernel<true>, dim3(grid), dim3(256), 0, s, L);
-  else
-    hipLaunchKernelGGL(walk_persistent_kernel<false>, dim3(grid), dim3(256), 0, s, L);
+  if (L.accum_f32) {
+    if (L.stats)
+      hipLaunchKernelGGL((walk_persistent_kernel<true, float>), dim3(grid), dim3(256), 0, s, L);
+    else
+      hipLaunchKernelGGL((walk_persistent_kernel<false, float>), dim3(grid), dim3(256), 0, s, L);
+  } else {
+    if (L.stats)
+      hipLaunchKernelGGL((walk_persistent_kernel<true, double>), dim3(grid), dim3(256), 0, s, L);
+    else
+      hipLaunchKernelGGL((walk_persistent_kernel<false, double>), dim3(grid), dim3(256), 0, s, L);
+  }
   return hipGetLastError();
 }
 

@@ -51,7 +51,8 @@ class DtnOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("max_steps", C.c_int64), ("walk_offset", C.c_int64), ("kappa", C.c_double),
                 ("delta_rel", C.c_double), ("form", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("chunk", C.c_int32), ("regen_min", C.c_int32), ("record_log", C.c_int32), ("se_target", C.c_double),
-                ("walks_max", C.c_int64), ("collect_stats", C.c_int32), ("mesh_id", C.c_int32)]
+                ("walks_max", C.c_int64), ("collect_stats", C.c_int32), ("mesh_id", C.c_int32),
+                ("accum", C.c_int32)]
 
 
 class DtnInfo(C.Structure):

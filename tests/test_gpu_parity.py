@@ -207,3 +207,18 @@ def test_split_walk_ranges(ctx):
     b2 = _gpu_estimate(ctx, case, 56, True, walk_offset=40)
     for k in ("status", "tri", "bary", "nq"):
         assert np.array_equal(a[k], np.concatenate([b1[k], b2[k]], 1))
+
+
+def test_fp32_partial_sums_within_rounding(ctx):
+    """Mixed precision: FP32 partial sums per chunk, FP64 rows. Same walks as
+    the FP64 form; every entry within 1e-5 of the FP64 estimate's scale."""
+    wl = W.soup8_53k(N=300, walks=128)
+    case = wl.cases[0]
+    a = _gpu_estimate(ctx, case, 128, False, accum=0)
+    b = _gpu_estimate(ctx, case, 128, False, accum=1)
+    for k in ("status", "tri", "nq"):
+        assert np.array_equal(a[k], b[k])
+    scale = np.abs(a["S"]).max()
+    err = np.abs(a["S"] - b["S"]).max() / scale
+    print(f"[fp32 partial sums] max |S_f32 - S_f64| / max|S| = {err:.2e}", flush=True)
+    assert err < 1e-5

@@ -60,6 +60,7 @@ class Runner:
             self.handles.append((c, mesh, ctx.rows(mesh, c.rows), ctx.basis(c.basis, c.V.shape[0])))
         self.batched = len(wl.cases) > 1
         self.batches = {}
+        self.opts = {}  # tuned launch settings
 
     def _batch(self, ext, **opts):
         key = (ext, tuple(sorted(opts.items())))
@@ -79,6 +80,7 @@ class Runner:
         """One pass; returns a list of per-launch records."""
         from paper_2606_05581_amd import msk
 
+        opts = {**self.opts, **opts}
         recs = []
         for ext in [m == "exterior" for m in self.wl.modes]:
             if self.batched and form != msk.FORM_PLAIN:
@@ -144,6 +146,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a device copy of this size first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -174,6 +177,13 @@ def main():
     run = Runner(ctx, wl)
     torch.cuda.synchronize()
     log("[bench] inputs on the GPU")
+    tuned = None
+    if not args.no_tune:  # untimed: pick leaf width / chunk / refill threshold / workgroups per CU
+        hs = run.handles
+        tuned = ctx.autotune([h[1] for h in hs], [h[2] for h in hs], [h[3] for h in hs], [h[0].eps for h in hs],
+                             [h[0].h for h in hs], exterior=(wl.modes[0] == "exterior"))
+        run.opts = {"chunk": tuned["chunk"], "regen_min": tuned["regen_min"], "blocks_per_cu": tuned["blocks_per_cu"]}
+        log(f"[bench] autotuned: {tuned}")
 
     per_q = None
     if not args.no_stats:  # untimed: traversal statistics (counting kernel) for the per-query work
@@ -258,6 +268,7 @@ def main():
             "form": "batched persistent, one graph" if run.batched else "persistent",
             "accumulation": "f64",
             "eigenpairs": wl.k,
+            "tuned": tuned,
         },
         "queries_per_s": queries / elapsed,
         "steps_per_walk": queries / max(walks, 1),

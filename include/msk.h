@@ -272,6 +272,46 @@ typedef enum {
 msk_status msk_dtn_get(const msk_dtn* dtn, int32_t field, void* dst, int32_t dst_on_device);
 void msk_dtn_destroy(msk_dtn* dtn);
 
+/* ------------------------------------------------------------- autotune */
+
+/* Candidate values (n_x of them in x[]; n_x = 0 keeps the current value). */
+typedef struct {
+  int32_t n_leaf, leaf[4];            /* BVH leaf width                        */
+  int32_t n_chunk, chunk[4];          /* walks a wavefront takes per queue grab */
+  int32_t n_regen, regen_min[4];      /* idle lanes that trigger a refill      */
+  int32_t n_bpc, blocks_per_cu[4];    /* persistent workgroups per CU          */
+  int64_t trial_rows;                 /* rows sampled over all meshes (16384)  */
+  int64_t trial_walks;                /* walks per sampled row (128)           */
+  int32_t repeats;                    /* timed repeats per candidate, min (2)  */
+  const char* cache_path;             /* JSON-lines cache file, or NULL        */
+} msk_tune_space;
+
+typedef struct {
+  int32_t leaf, chunk, regen_min, blocks_per_cu;
+  double walks_per_s;                 /* best trial rate                       */
+  int32_t trials;                     /* timed trial launches                  */
+  int32_t from_cache;                 /* 1 if read from cache_path             */
+} msk_tune_result;
+
+void msk_tune_space_default(msk_tune_space* space);
+
+/* Rebuild a mesh's BVH in place with another leaf width. Rows and bases made
+ * for the mesh stay valid; batch plans that include the mesh do not (create
+ * them after tuning). The nearest-triangle decision, hence every walk, does
+ * not depend on the leaf width. */
+msk_status msk_mesh_rebuild(msk_ctx* ctx, msk_mesh* mesh, int32_t leaf_size);
+
+/* Autotune the persistent walk launch for a set of meshes (a batch, or one
+ * mesh): coordinate search over leaf width, chunk, refill threshold and
+ * workgroups per CU, each candidate timed on short walk launches over an
+ * evenly spaced sample of rows of every mesh. The meshes are left rebuilt
+ * with the best leaf width; the other values are returned for msk_dtn_opts.
+ * With cache_path set, a result stored for the same workload signature
+ * (mesh, triangle and row counts, side) is reused without timing. */
+msk_status msk_autotune(msk_ctx* ctx, int32_t n_meshes, msk_mesh* const* meshes, const msk_rows* const* rows,
+                        const msk_basis* const* bases, const double* eps, const double* inset_h, int32_t side,
+                        const msk_tune_space* space, msk_tune_result* out);
+
 /* --------------------------------------------------------- eigen step */
 
 typedef struct {

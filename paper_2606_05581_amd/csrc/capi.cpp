@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -33,6 +34,7 @@ struct msk_mesh {
   int32_t* d_faces = nullptr;
   std::vector<float> vrel;       // float offsets from the centre (host copy)
   std::vector<int32_t> faces;    // host copy
+  std::vector<float> vworld;     // input vertices (host copy, for rebuilds)
 };
 
 struct msk_rows {
@@ -211,6 +213,7 @@ extern "C" msk_status msk_build_bvh(msk_ctx* ctx, const float* V, int64_t n_vert
   for (int64_t i = 0; i < n_verts; ++i)
     for (int k = 0; k < 3; ++k) m->vrel[3 * i + k] = (float)((double)V[3 * i + k] - B.centre[k]);
   m->faces.assign(F, F + 3 * n_tris);
+  m->vworld.assign(V, V + 3 * n_verts);
   hipError_t he;
   if ((he = upload(ctx, &m->d_nodes, B.nodes.data(), B.nodes.size())) != hipSuccess ||
       (he = upload(ctx, &m->d_tris, B.tris.data(), B.tris.size())) != hipSuccess ||
@@ -1076,5 +1079,228 @@ extern "C" msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* d, int32_t 
   if (rc == 1) return fail(ctx, MSK_ERR_INVALID_ARG, err);
   if (rc == 3) return fail(ctx, MSK_ERR_DEVICE, err);
   if (rc == 4) return fail(ctx, MSK_ERR_NOT_CONVERGED, err.empty() ? "residual target not reached" : err);
+  return MSK_OK;
+}
+
+// ------------------------------------------------------------- autotune
+
+extern "C" void msk_tune_space_default(msk_tune_space* sp) {
+  if (!sp) return;
+  std::memset(sp, 0, sizeof(*sp));
+  sp->n_leaf = 3;
+  sp->leaf[0] = 1; sp->leaf[1] = 2; sp->leaf[2] = 4;
+  sp->n_chunk = 3;
+  sp->chunk[0] = 32; sp->chunk[1] = 64; sp->chunk[2] = 128;
+  sp->n_regen = 3;
+  sp->regen_min[0] = 1; sp->regen_min[1] = 16; sp->regen_min[2] = 32;
+  sp->n_bpc = 2;
+  sp->blocks_per_cu[0] = 4; sp->blocks_per_cu[1] = 8;
+  sp->trial_rows = 16384;
+  sp->trial_walks = 128;
+  sp->repeats = 2;
+  sp->cache_path = nullptr;
+}
+
+extern "C" msk_status msk_mesh_rebuild(msk_ctx* ctx, msk_mesh* m, int32_t leaf) {
+  if (!ctx || !m) return MSK_ERR_INVALID_ARG;
+  if (leaf == m->leaf_size) return MSK_OK;
+  HostBvh B;
+  std::string e = build_bvh_host(m->vworld.data(), m->nv, m->faces.data(), m->nf, leaf, B);
+  if (!e.empty()) return fail(ctx, MSK_ERR_INVALID_ARG, e);
+  Node4* dn = nullptr;
+  TriRec* dt = nullptr;
+  int32_t* ds = nullptr;
+  hipError_t he;
+  if ((he = upload(ctx, &dn, B.nodes.data(), B.nodes.size())) != hipSuccess ||
+      (he = upload(ctx, &dt, B.tris.data(), B.tris.size())) != hipSuccess ||
+      (he = upload(ctx, &ds, B.slot_of_tri.data(), B.slot_of_tri.size())) != hipSuccess) {
+    dfree(dn);
+    dfree(dt);
+    dfree(ds);
+    return fail(ctx, MSK_ERR_DEVICE, std::string("rebuild upload: ") + hipGetErrorString(he));
+  }
+  dfree(m->d_nodes);
+  dfree(m->d_tris);
+  dfree(m->d_slot);
+  m->d_nodes = dn;
+  m->d_tris = dt;
+  m->d_slot = ds;
+  m->n_nodes = (int64_t)B.nodes.size();
+  m->depth = B.depth;
+  m->leaf_size = leaf;
+  m->top_nodes = (int)std::min<int64_t>(kMaxTop, m->n_nodes);
+  return MSK_OK;
+}
+
+static std::string tune_signature(int32_t n, msk_mesh* const* meshes, const msk_rows* const* rows, int32_t side) {
+  long long tris = 0, nr = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    tris += meshes[i]->nf;
+    nr += rows[i]->n;
+  }
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "meshes=%d;tris=%lld;rows=%lld;side=%d", n, tris, nr, side);
+  return buf;
+}
+
+extern "C" msk_status msk_autotune(msk_ctx* ctx, int32_t n, msk_mesh* const* meshes, const msk_rows* const* rows,
+                                   const msk_basis* const* bases, const double* eps, const double* inset_h,
+                                   int32_t side, const msk_tune_space* space, msk_tune_result* out) {
+  if (!ctx || !out || n < 1 || !meshes || !rows || !bases || !eps || !inset_h) return MSK_ERR_INVALID_ARG;
+  msk_tune_space sp;
+  msk_tune_space_default(&sp);
+  if (space) sp = *space;
+  if (sp.trial_walks < 2 || sp.trial_rows < 1) return fail(ctx, MSK_ERR_INVALID_ARG, "bad trial size");
+  for (int32_t i = 0; i < n; ++i) {
+    msk_status st = check_problem(ctx, meshes[i], rows[i], bases[i], sp.trial_walks, eps[i], inset_h[i], side);
+    if (st != MSK_OK) return st;
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->leaf = meshes[0]->leaf_size;
+  out->chunk = 64;
+  out->regen_min = 1;
+  out->blocks_per_cu = 8;
+  const std::string sig = tune_signature(n, meshes, rows, side);
+  if (sp.cache_path) {  // one JSON object per line: {"sig": "...", "leaf": L, ...}
+    if (FILE* f = std::fopen(sp.cache_path, "r")) {
+      char line[512];
+      while (std::fgets(line, sizeof(line), f)) {
+        const std::string l(line);
+        if (l.find("\"sig\": \"" + sig + "\"") == std::string::npos) continue;
+        int lf, ch, rg, bp;
+        double wps;
+        const char* q = std::strstr(line, "\"leaf\":");
+        if (q && std::sscanf(q, "\"leaf\": %d, \"chunk\": %d, \"regen_min\": %d, \"blocks_per_cu\": %d, "
+                                "\"walks_per_s\": %lf", &lf, &ch, &rg, &bp, &wps) == 5) {
+          out->leaf = lf;
+          out->chunk = ch;
+          out->regen_min = rg;
+          out->blocks_per_cu = bp;
+          out->walks_per_s = wps;
+          out->from_cache = 1;
+        }
+      }
+      std::fclose(f);
+      if (out->from_cache) {
+        for (int32_t i = 0; i < n; ++i) {
+          msk_status st = msk_mesh_rebuild(ctx, meshes[i], out->leaf);
+          if (st != MSK_OK) return st;
+        }
+        return MSK_OK;
+      }
+    }
+  }
+  // trial buffers (kept for the whole search; trial sums are not read)
+  std::vector<msk_dtn*> dtns;
+  auto free_all = [&]() {
+    for (msk_dtn* d : dtns) {
+      dtn_free(d);
+      delete d;
+    }
+  };
+  msk_dtn_opts o;
+  msk_dtn_opts_default(&o);
+  for (int32_t i = 0; i < n; ++i) {
+    msk_dtn* d = nullptr;
+    msk_status st = alloc_dtn(ctx, rows[i], bases[i], sp.trial_walks, false, &d);
+    if (st != MSK_OK) {
+      free_all();
+      return st;
+    }
+    dtns.push_back(d);
+    hipError_t he;
+    if ((he = launch_fill_u64(d->d_acc1, d->n * d->K, 0, ctx->stream)) != hipSuccess ||
+        (he = launch_fill_u64(d->d_acc2, d->n * d->K, 0, ctx->stream)) != hipSuccess ||
+        (he = launch_fill_u64(d->d_q, d->n, 0, ctx->stream)) != hipSuccess ||
+        (he = launch_fill_u64(d->d_esc, d->n, 0, ctx->stream)) != hipSuccess ||
+        (he = launch_fill_u64(d->d_cap, d->n, 0, ctx->stream)) != hipSuccess ||
+        (he = launch_fill_u32(d->d_disc, d->n, 0u, ctx->stream)) != hipSuccess) {
+      free_all();
+      return fail(ctx, MSK_ERR_DEVICE, std::string("tune buffers: ") + hipGetErrorString(he));
+    }
+  }
+  // sampled rows: evenly spaced in each mesh's Z-order, proportional to its rows
+  int64_t total_rows = 0;
+  for (int32_t i = 0; i < n; ++i) total_rows += rows[i]->n;
+  std::vector<RowSlot> slots;
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t ni = rows[i]->n;
+    const int64_t k = std::max<int64_t>(1, std::min<int64_t>(ni, (sp.trial_rows * ni + total_rows - 1) / total_rows));
+    for (int64_t j = 0; j < k; ++j) slots.push_back(RowSlot{i, rows[i]->order[(size_t)(j * ni / k)]});
+  }
+  int trials = 0;
+  auto evaluate = [&](int leaf, int chunk, int regen, int bpc, double* wps) -> msk_status {
+    for (int32_t i = 0; i < n; ++i) {
+      msk_status st = msk_mesh_rebuild(ctx, meshes[i], leaf);
+      if (st != MSK_OK) return st;
+    }
+    std::vector<MeshDev> mds;
+    for (int32_t i = 0; i < n; ++i) mds.push_back(make_meshdev(meshes[i], rows[i], bases[i], dtns[i], eps[i],
+                                                               inset_h[i], side, o, i));
+    msk_dtn_opts oc = o;
+    oc.chunk = chunk;
+    oc.regen_min = regen;
+    oc.blocks_per_cu = bpc;
+    const int use_lds = (n == 1 && meshes[0]->top_nodes > 0) ? 1 : 0;
+    double best = 1e300;
+    for (int r = 0; r < std::max(1, sp.repeats); ++r) {
+      double ms = 0;
+      int64_t st3[3] = {0, 0, 0};
+      msk_status st = run_walks(ctx, mds, slots, sp.trial_walks, 0, oc, use_lds, meshes[0]->top_nodes, &ms, st3);
+      if (st != MSK_OK) return st;
+      best = std::min(best, ms);
+      ++trials;
+    }
+    *wps = (double)slots.size() * (double)sp.trial_walks / (best * 1e-3);
+    return MSK_OK;
+  };
+  double wps = 0, best_wps = 0;
+  msk_status st = evaluate(out->leaf, out->chunk, out->regen_min, out->blocks_per_cu, &wps);  // warm-up
+  if (st != MSK_OK) {
+    free_all();
+    return st;
+  }
+  best_wps = 0;
+  auto scan = [&](int dim, int cnt, const int32_t* vals) -> msk_status {
+    for (int j = 0; j < cnt; ++j) {
+      int lf = out->leaf, ch = out->chunk, rg = out->regen_min, bp = out->blocks_per_cu;
+      int* v = dim == 0 ? &lf : dim == 1 ? &ch : dim == 2 ? &rg : &bp;
+      *v = vals[j];
+      if (lf < 1 || lf > 8 || ch < 1 || rg < 1 || rg > 64 || bp < 1 || bp > 32) continue;
+      double w2 = 0;
+      msk_status s2 = evaluate(lf, ch, rg, bp, &w2);
+      if (s2 != MSK_OK) return s2;
+      if (w2 > best_wps) {
+        best_wps = w2;
+        out->leaf = lf;
+        out->chunk = ch;
+        out->regen_min = rg;
+        out->blocks_per_cu = bp;
+      }
+    }
+    return MSK_OK;
+  };
+  if ((st = scan(0, std::min(4, sp.n_leaf), sp.leaf)) != MSK_OK ||
+      (st = scan(1, std::min(4, sp.n_chunk), sp.chunk)) != MSK_OK ||
+      (st = scan(2, std::min(4, sp.n_regen), sp.regen_min)) != MSK_OK ||
+      (st = scan(3, std::min(4, sp.n_bpc), sp.blocks_per_cu)) != MSK_OK) {
+    free_all();
+    return st;
+  }
+  free_all();
+  for (int32_t i = 0; i < n; ++i) {
+    msk_status s2 = msk_mesh_rebuild(ctx, meshes[i], out->leaf);
+    if (s2 != MSK_OK) return s2;
+  }
+  out->walks_per_s = best_wps;
+  out->trials = trials;
+  if (sp.cache_path) {
+    if (FILE* f = std::fopen(sp.cache_path, "a")) {
+      std::fprintf(f, "{\"sig\": \"%s\", \"leaf\": %d, \"chunk\": %d, \"regen_min\": %d, \"blocks_per_cu\": %d, "
+                      "\"walks_per_s\": %.6g}\n", sig.c_str(), out->leaf, out->chunk, out->regen_min,
+                   out->blocks_per_cu, best_wps);
+      std::fclose(f);
+    }
+  }
   return MSK_OK;
 }

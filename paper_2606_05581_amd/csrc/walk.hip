@@ -52,8 +52,14 @@ __device__ __forceinline__ uint4 draw(const WalkLaunch& L, uint32_t row, uint32_
 // vertex a, vertex b, edge ab, vertex c, edge ac, edge bc, face; face-region
 // numerators n.(u x v) with n = ab x ac; face distance (n.ap)^2 / (n.n).
 // (l1, l2) are the barycentric weights of vertices b and c.
-__host__ __device__ __forceinline__ float tri_dist2(float px, float py, float pz, const TriRec& T, float& l1, float& l2,
-                                                   int& region) {
+//
+// In the face region the barycentrics are returned as numerators (l1, l2 =
+// vb, vc) over `den`; the caller divides only for a triangle that becomes
+// the best. A face whose squared plane distance exceeds `reject` by a safe
+// margin returns +inf without dividing: it cannot beat or tie a current best
+// of `reject`. Distances that are returned are exactly the values above.
+__host__ __device__ __forceinline__ float tri_dist2(float px, float py, float pz, const TriRec& T, float reject,
+                                                   float& l1, float& l2, float& den_out, int& region) {
 #pragma clang fp contract(off)
   const float ax = T.a.x, ay = T.a.y, az = T.a.z;
   const float bx = T.b.x, by = T.b.y, bz = T.b.z;
@@ -113,10 +119,14 @@ __host__ __device__ __forceinline__ float tri_dist2(float px, float py, float pz
   }
   const float den = (va + vb) + vc;
   if (den > 0.0f) {
-    l1 = vb / den; l2 = vc / den; region = 6;
+    region = 6;
     t = nx * apx; t = t + ny * apy; const float tn = t + nz * apz;
     t = nx * nx; t = t + ny * ny; const float nn = t + nz * nz;
-    return (tn * tn) / nn;
+    const float tt = tn * tn;
+    // fl(tt / nn) > reject whenever tt > fl(fl(reject nn)(1 + 2^-20))
+    if (tt > (reject * nn) * (1.0f + 0x1p-20f)) return INFINITY;
+    l1 = vb; l2 = vc; den_out = den;
+    return tt / nn;
   }
   // zero-area triangle: nearest point of the three edges, first strict minimum
   float best = INFINITY, bl1 = 0.0f, bl2 = 0.0f;
@@ -174,9 +184,9 @@ template <bool kStats>
 __host__ __device__ __forceinline__ void test_tri(const TriRec* __restrict__ tris, int32_t s, float px, float py, float pz,
                                          Nearest& h, TravCount& cnt) {
   const TriRec T = tris[s];
-  float l1, l2;
+  float l1 = 0.0f, l2 = 0.0f, den = 1.0f;
   int region = 0;
-  const float d = tri_dist2(px, py, pz, T, l1, l2, region);
+  const float d = tri_dist2(px, py, pz, T, h.d2, l1, l2, den, region);
   if (kStats) {
     ++cnt.tris;
     cnt.flops += kTriFlops[region & 7];
@@ -184,45 +194,70 @@ __host__ __device__ __forceinline__ void test_tri(const TriRec* __restrict__ tri
   int32_t orig;
   memcpy(&orig, &T.a.w, 4);
   if (d < h.d2 || (d == h.d2 && orig < h.orig)) {
+    if (region == 6) {  // face barycentrics vb / den, vc / den
+      l1 = l1 / den;
+      l2 = l2 / den;
+    }
     h.d2 = d; h.slot = s; h.orig = orig; h.l1 = l1; h.l2 = l2;
   }
 }
 
 // Exact nearest triangle: lexicographic minimum of (FP32 squared distance,
-// original index). `h` may carry a candidate (warm start) on entry.
+// original index). `h.slot` may name a candidate triangle on entry (warm
+// start: the previous step's nearest), tested first. One stack holds inner
+// nodes and leaves (a leaf entry is -((first << 4) | count) - 1), each with its
+// box lower bound; every loop trip handles one entry, so the triangle test
+// and the node test each appear once in the code.
 template <bool kStats>
 __host__ __device__ void bvh_nearest(const Node4* __restrict__ nodes, const TriRec* __restrict__ tris, const Node4* lds,
                                      int32_t n_lds, float px, float py, float pz, float radius, Nearest& h,
                                      TravCount& cnt) {
   const float slack = 0x1p-18f * (radius + fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
-  if (h.slot >= 0) {
-    const int32_t s = h.slot;
-    h.d2 = INFINITY; h.orig = INT_MAX; h.slot = -1;
-    test_tri<kStats>(tris, s, px, py, pz, h, cnt);
-  }
-  float thr = prune_bound(h.d2, slack);
-  int32_t stk_node[kStackDepth];
+  int32_t stk_ref[kStackDepth];
   float stk_lb[kStackDepth];
   int sp = 0;
-  int32_t node = 0;
+  stk_ref[sp] = 0;  // root
+  stk_lb[sp] = 0.0f;
+  ++sp;
+  if (h.slot >= 0) {
+    stk_ref[sp] = -((h.slot << 4) | 1) - 1;
+    stk_lb[sp] = 0.0f;
+    ++sp;
+  }
+  h.d2 = INFINITY;
+  h.orig = INT_MAX;
+  h.slot = -1;
+  float thr = INFINITY;
   while (true) {
+    while (sp > 0 && stk_lb[sp - 1] > thr) --sp;
+    if (sp == 0) break;
+    --sp;
+    const int32_t ref = stk_ref[sp];
+    if (ref < 0) {  // leaf: test its triangles
+      const int32_t code = -ref - 1;
+      const int32_t first = code >> 4, count = code & 15;
+      const float before = h.d2;
+      for (int32_t s = first; s < first + count; ++s) test_tri<kStats>(tris, s, px, py, pz, h, cnt);
+      if (h.d2 != before) thr = prune_bound(h.d2, slack);
+      continue;
+    }
     float4 lox, loy, loz, hix, hiy, hiz;
     int4 ch, ct;
     if (kStats) {
       ++cnt.nodes;
       cnt.flops += 4 * kBoxFlops;
     }
-    if (node < n_lds) {
-      const float4* N = (const float4*)&lds[node];
+    if (ref < n_lds) {
+      const float4* N = (const float4*)&lds[ref];
       lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
       ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
     } else {
-      const float4* N = (const float4*)&nodes[node];
+      const float4* N = (const float4*)&nodes[ref];
       lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
       ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
     }
     float lb[4];
-    int32_t cc[4], cn[4];
+    int32_t cr[4];
     {
       const float lx[4] = {lox.x, lox.y, lox.z, lox.w}, ly[4] = {loy.x, loy.y, loy.z, loy.w},
                   lz[4] = {loz.x, loz.y, loz.z, loz.w};
@@ -235,47 +270,28 @@ __host__ __device__ void bvh_nearest(const Node4* __restrict__ nodes, const TriR
         const float gy = fmaxf(fmaxf(ly[k] - py, py - hy[k]), 0.0f);
         const float gz = fmaxf(fmaxf(lz[k] - pz, pz - hz[k]), 0.0f);
         lb[k] = gx * gx + gy * gy + gz * gz;
-        cc[k] = c4[k];
-        cn[k] = n4[k];
+        // a leaf ref packs (first, count); an unused slot gets the sentinel
+        // INT32_MIN (never a valid ref: leaf counts are at most 8)
+        cr[k] = c4[k] >= 0 ? c4[k] : (n4[k] > 0 ? -((((-c4[k]) - 1) << 4) | n4[k]) - 1 : INT32_MIN);
       }
     }
     // sort the four children by lower bound (5 compare-exchanges)
 #define MSK_CX(i, j)                                                        \
   if (lb[j] < lb[i]) {                                                      \
     float tl = lb[i]; lb[i] = lb[j]; lb[j] = tl;                            \
-    int32_t tc = cc[i]; cc[i] = cc[j]; cc[j] = tc;                          \
-    int32_t tn = cn[i]; cn[i] = cn[j]; cn[j] = tn;                          \
+    int32_t tc = cr[i]; cr[i] = cr[j]; cr[j] = tc;                          \
   }
     MSK_CX(0, 1) MSK_CX(2, 3) MSK_CX(0, 2) MSK_CX(1, 3) MSK_CX(1, 2)
 #undef MSK_CX
-    // leaves, nearest first
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (cc[k] < 0 && cn[k] > 0 && lb[k] <= thr) {
-        const int32_t first = -cc[k] - 1;
-        const float before = h.d2;
-        for (int32_t s = first; s < first + cn[k]; ++s) test_tri<kStats>(tris, s, px, py, pz, h, cnt);
-        if (h.d2 != before) thr = prune_bound(h.d2, slack);
-      }
-    }
-    // inner children, farthest pushed first
+    // push farthest first, so the nearest child is handled next
 #pragma unroll
     for (int k = 3; k >= 0; --k) {
-      if (cc[k] >= 0 && lb[k] <= thr && sp < kStackDepth) {
-        stk_node[sp] = cc[k];
+      if (cr[k] != INT32_MIN && lb[k] <= thr && sp < kStackDepth) {
+        stk_ref[sp] = cr[k];
         stk_lb[sp] = lb[k];
         ++sp;
       }
     }
-    node = -1;
-    while (sp > 0) {
-      --sp;
-      if (stk_lb[sp] <= thr) {
-        node = stk_node[sp];
-        break;
-      }
-    }
-    if (node < 0) break;
   }
 }
 
@@ -536,6 +552,15 @@ __device__ __forceinline__ void onb(double nx, double ny, double nz, double e1[3
 template <bool kStats>
 __device__ int32_t walk_step(const WalkLaunch& L, const MeshDev& M, const Node4* lds, int32_t n_lds, LaneWalk& w,
                              Nearest& hit) {
+  if (w.step >= M.max_steps) {
+    // step cap: the walk ends at the nearest boundary point of its position
+    hit.d2 = INFINITY;
+    hit.orig = INT_MAX;
+    hit.slot = w.slot;
+    bvh_nearest<kStats>(M.nodes, M.tris, lds, n_lds, w.x, w.y, w.z, M.radius, hit, w.cnt);
+    ++w.queries;
+    return kCapped;
+  }
   const uint4 u = draw(L, (uint32_t)w.row, w.walk, (uint32_t)w.step, kPurposeStep, (uint32_t)M.mesh_id);
   const float rho2 = w.x * w.x + w.y * w.y + w.z * w.z;
   const double rho = rho2 > M.radius * M.radius * (1.0f - 0x1p-18f)
@@ -580,17 +605,7 @@ __device__ int32_t walk_step(const WalkLaunch& L, const MeshDev& M, const Node4*
   w.y += r * rxy * sn;
   w.z += r * z;
   ++w.step;
-  return w.step >= M.max_steps ? kCapped : -1;
-}
-
-// A capped walk ends at the nearest boundary point of its last position.
-template <bool kStats>
-__device__ void cap_walk(const MeshDev& M, const Node4* lds, int32_t n_lds, LaneWalk& w, Nearest& hit) {
-  hit.d2 = INFINITY;
-  hit.orig = INT_MAX;
-  hit.slot = w.slot;
-  bvh_nearest<kStats>(M.nodes, M.tris, lds, n_lds, w.x, w.y, w.z, M.radius, hit, w.cnt);
-  ++w.queries;
+  return -1;
 }
 
 __device__ __forceinline__ void decode_walk(const WalkLaunch& L, uint64_t g, LaneWalk& w) {
@@ -619,7 +634,6 @@ __global__ void __launch_bounds__(256) walk_plain_kernel(WalkLaunch L) {
   do {
     st = walk_step<kStats>(L, M, nullptr, 0, w, hit);
   } while (st < 0);
-  if (st == kCapped) cap_walk<kStats>(M, nullptr, 0, w, hit);
   walk_finish_global(L, M, w, st, hit);
 }
 
@@ -737,7 +751,6 @@ __global__ void __launch_bounds__(256) walk_persistent_kernel(WalkLaunch L) {
       const int32_t nl = (w.mesh == 0) ? n_lds : 0;
       const int32_t st = walk_step<kStats>(L, M, top, nl, w, hit);
       if (st >= 0) {
-        if (st == kCapped) cap_walk<kStats>(M, top, nl, w, hit);
         if (w.tab >= 0)
           walk_finish_table(L, M, w, st, hit, T, wi);
         else

@@ -67,6 +67,18 @@ class EigStats(C.Structure):
                 ("lanczos_ms", C.c_double)]
 
 
+class TuneSpace(C.Structure):
+    _fields_ = [("n_leaf", C.c_int32), ("leaf", C.c_int32 * 4), ("n_chunk", C.c_int32), ("chunk", C.c_int32 * 4),
+                ("n_regen", C.c_int32), ("regen_min", C.c_int32 * 4), ("n_bpc", C.c_int32),
+                ("blocks_per_cu", C.c_int32 * 4), ("trial_rows", C.c_int64), ("trial_walks", C.c_int64),
+                ("repeats", C.c_int32), ("cache_path", C.c_char_p)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("leaf", C.c_int32), ("chunk", C.c_int32), ("regen_min", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("walks_per_s", C.c_double), ("trials", C.c_int32), ("from_cache", C.c_int32)]
+
+
 _lib = None
 
 # symbol name -> (argtypes, restype); the C ABI declared in include/msk.h
@@ -102,6 +114,11 @@ SIGNATURES = {
     "msk_batch_dtn": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
     "msk_batch_get_info": ([C.c_void_p, C.POINTER(DtnInfo)], C.c_int),
     "msk_batch_destroy": ([C.c_void_p], None),
+    "msk_tune_space_default": ([C.POINTER(TuneSpace)], None),
+    "msk_mesh_rebuild": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
+    "msk_autotune": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.POINTER(TuneSpace),
+                      C.POINTER(TuneResult)], C.c_int),
 }
 
 
@@ -244,6 +261,29 @@ class Context:
                                            (C.c_double * n)(*insets), walks, EXTERIOR if exterior else INTERIOR,
                                            C.byref(o), C.byref(h)))
         return Batch(self, h, [r.n for r in rows], [b.K for b in bases], walks)
+
+    def autotune(self, meshes, rows, bases, eps, insets, exterior: bool = False, cache_path=None, **space) -> dict:
+        """Tune leaf width / chunk / refill threshold / workgroups per CU; meshes are rebuilt in place."""
+        n = len(meshes)
+        sp = TuneSpace()
+        lib().msk_tune_space_default(C.byref(sp))
+        for k, v in space.items():
+            if k in ("leaf", "chunk", "regen_min", "blocks_per_cu"):
+                cnt = {"leaf": "n_leaf", "chunk": "n_chunk", "regen_min": "n_regen", "blocks_per_cu": "n_bpc"}[k]
+                setattr(sp, cnt, len(v))
+                arr = getattr(sp, k)
+                for i, x in enumerate(v):
+                    arr[i] = x
+            else:
+                setattr(sp, k, v)
+        keep = cache_path.encode() if cache_path else None
+        sp.cache_path = keep
+        res = TuneResult()
+        arr = lambda xs: (C.c_void_p * n)(*[x.h for x in xs])
+        self._check(lib().msk_autotune(self.h, n, arr(meshes), arr(rows), arr(bases), (C.c_double * n)(*eps),
+                                       (C.c_double * n)(*insets), EXTERIOR if exterior else INTERIOR, C.byref(sp),
+                                       C.byref(res)))
+        return {f: getattr(res, f) for f, _ in TuneResult._fields_}
 
     def steklov_modes(self, dtn: "Dtn", k: int, vectors: bool = True):
         evals = np.zeros(k)

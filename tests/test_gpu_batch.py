@@ -95,3 +95,35 @@ def test_batched_one_shot_and_oracle_parity(ctx, oracle_mod, small_batch):
         print(f"[batch member {i}] tris {c.F.shape[0]} rows {c.rows.n_rows}: entries outside 4 combined se: "
               f"{bad.sum()}/{bad.size}", flush=True)
         assert bad.sum() == 0
+
+
+def test_leaf_width_changes_no_walk_and_autotune(ctx):
+    """The traversal is exact, so rebuilding the BVH with another leaf width
+    leaves every walk (status, triangle, barycentrics, queries) unchanged; the
+    autotuner returns settings that run the same walks."""
+    from paper_2606_05581_amd import msk
+
+    wl = W.soup8_53k(N=300, walks=64)
+    c = wl.cases[0]
+    m = ctx.build_bvh(c.V, c.F, leaf_size=4)
+    r = ctx.rows(m, c.rows)
+    b = ctx.basis(c.basis, c.V.shape[0])
+
+    def run(**kw):
+        d = ctx.estimate_dtn(m, r, b, 64, c.eps, c.h, record_log=1, **kw)
+        return {k: d.get(f) for k, f in [("st", msk.FIELD_LOG_STATUS), ("tri", msk.FIELD_LOG_TRI),
+                                          ("bary", msk.FIELD_LOG_BARY), ("q", msk.FIELD_LOG_QUERIES)]}
+
+    ref = run()
+    for leaf in (1, 2, 8):
+        ctx._check(msk.lib().msk_mesh_rebuild(ctx.h, m.h, leaf))
+        got = run()
+        for k in ref:
+            assert np.array_equal(ref[k], got[k]), (leaf, k)
+    res = ctx.autotune([m], [r], [b], [c.eps], [c.h], trial_rows=256, trial_walks=16, repeats=1,
+                       leaf=[2, 4], chunk=[32, 64], regen_min=[1, 16], blocks_per_cu=[4, 8])
+    print(f"[autotune soup8 N=300] {res}", flush=True)
+    assert res["leaf"] in (2, 4) and res["chunk"] in (32, 64) and res["trials"] >= 8 and res["walks_per_s"] > 0
+    got = run(chunk=res["chunk"], regen_min=res["regen_min"], blocks_per_cu=res["blocks_per_cu"])
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k

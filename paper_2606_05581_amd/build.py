@@ -20,18 +20,20 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into libmsk.so (always recompiles)."""
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every source into `out` (default: the in-tree libmsk.so);
+    `defines` are extra NAME=VALUE macros (kernel tuning constants)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+    tmp = out + ".tmp"
+    cmd = ([hipcc] + HIPCC_FLAGS + ["-D" + d for d in defines] + [os.path.join(CSRC, s) for s in SOURCES] +
+           ["-o", tmp])
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stderr[-6000:])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

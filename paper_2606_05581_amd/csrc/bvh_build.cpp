@@ -291,10 +291,8 @@ std::string build_bvh_host(const float* V, int64_t nv, const int32_t* F, int64_t
   out.tris.swap(tris);
   out.depth = maxdepth;
   if ((int64_t)out.tris.size() != nf) return "internal error: triangle count mismatch";
-  // traversal stack: at most 3 pending siblings per level, plus 4 children
-  // and the warm-start entry
+  // traversal stack: at most 3 pending siblings per level (with margin)
   if (3 * maxdepth + 5 > kStackDepth) return "BVH too deep for the traversal stack";
-  if ((int64_t)out.tris.size() >= ((int64_t)1 << 27)) return "too many triangles for leaf references";
   return "";
 }
 

@@ -21,6 +21,8 @@
 namespace msk {
 
 bool sym_eig(int n, std::vector<double>& A, std::vector<double>& evals, std::vector<double>& V);
+bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>& evals, std::vector<double>& V,
+                      double* abs_max);
 bool cholesky_upper(int n, const std::vector<double>& A, std::vector<double>& R, double rel_tol);
 void upper_inverse(int n, const std::vector<double>& R, std::vector<double>& Ri);
 
@@ -239,10 +241,12 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
     *iters = 1;
     *block_out = (int)n;
   } else {
-    // block >= 32: smaller blocks stall on clustered ends of the spectrum
+    // block >= 32: smaller blocks stall on clustered ends of the spectrum;
+    // a basis of 8k columns and 3k kept Ritz vectors carry the restarts
+    // through the dense, noisy lower edge of a Monte Carlo estimate's spectrum
     const int b = std::min<int>(64, std::max<int>(32, ((k + 7) / 8) * 8));
-    const int cap = (int)std::min<int64_t>(n, std::max(dense_max, k + 6 * b));
-    const int keep_n = std::min(cap - 2 * b, k + 2 * b);
+    const int cap = (int)std::min<int64_t>(n, std::max(dense_max, 8 * k));
+    const int keep_n = std::min(cap - 2 * b, std::max(3 * k, k + 2 * b));
     // residual target above the floor of FP32 products with C
     const double tol = std::max(1e-5, 16.0 * std::sqrt((double)n) * std::ldexp(1.0, -24));
     *block_out = b;
@@ -332,17 +336,15 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
       for (int i = 0; i < cur; ++i)
         for (int j = i + 1; j < cur; ++j) T[(size_t)i * cur + j] = T[(size_t)j * cur + i] =
             0.5 * (T[(size_t)i * cur + j] + T[(size_t)j * cur + i]);
-      if (!sym_eig(cur, T, th, Y)) {
+      const int kk = std::min(keep_n, cur);
+      double tmax = 0.0;
+      if (!sym_eig_smallest(cur, T, kk, th, Y, &tmax)) {
         err = "projected eigensolve did not converge";
         return 4;
       }
-      for (double t : th) cnorm = std::max(cnorm, std::fabs(t));
-      const int kk = std::min(keep_n, cur);
-      // Ritz vectors V = Q Y[:, :kk], CV = W Y[:, :kk]
-      std::vector<double> Yk((size_t)cur * kk);
-      for (int i = 0; i < cur; ++i)
-        for (int j = 0; j < kk; ++j) Yk[(size_t)i * kk + j] = Y[(size_t)i * cur + j];
-      EIG_TRY(hipMemcpyAsync(dY.p, Yk.data(), Yk.size() * 8, hipMemcpyHostToDevice, s));
+      cnorm = std::max(cnorm, tmax);
+      // Ritz vectors V = Q Y[:, :kk], CV = W Y[:, :kk] (Y is cur x kk)
+      EIG_TRY(hipMemcpyAsync(dY.p, Y.data(), (size_t)cur * kk * 8, hipMemcpyHostToDevice, s));
       EIG_TRY((gemm<double, false, false>(s, n, kk, cur, 1.0, Q, cap, dY.as<double>(), kk, 0.0, dQ2.as<double>(), kk)));
       EIG_TRY((gemm<double, false, false>(s, n, kk, cur, 1.0, Wm, cap, dY.as<double>(), kk, 0.0, dW2.as<double>(), kk)));
       // residual norms of the first k Ritz pairs: |CV_j - theta_j V_j|
@@ -367,17 +369,26 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
         if (!done) status = 4;
         break;
       }
-      // thick restart: keep the kk Ritz pairs, continue from the residuals
-      // of the first b of them
+      // thick restart: keep the kk Ritz pairs, continue from the residuals of
+      // b of them: the lowest unconverged ones first (converged residuals are
+      // rounding noise and would add nothing), then the lowest others
       hipLaunchKernelGGL(copy_block_f64_kernel, dim3(blocks_for(n * kk)), dim3(256), 0, s, dQ2.as<double>(),
                          (int64_t)kk, Q, (int64_t)cap, n, (int64_t)kk);
       hipLaunchKernelGGL(copy_block_f64_kernel, dim3(blocks_for(n * kk)), dim3(256), 0, s, dW2.as<double>(),
                          (int64_t)kk, Wm, (int64_t)cap, n, (int64_t)kk);
       EIG_TRY(hipGetLastError());
       cur = kk;
-      std::vector<double> Rb((size_t)n * b);
+      std::vector<int> pick;
+      for (int j = 0; j < kk && (int)pick.size() < b; ++j)
+        if (std::sqrt(res[j]) > tol * cnorm) pick.push_back(j);
+      for (int j = 0; j < kk && (int)pick.size() < b; ++j)
+        if (!(std::sqrt(res[j]) > tol * cnorm)) pick.push_back(j);
+      std::vector<double> Rb((size_t)n * b, 0.0);
       for (int64_t r = 0; r < n; ++r)
-        for (int j = 0; j < b; ++j) Rb[(size_t)r * b + j] = CV2[(size_t)r * kk + j] - th[j] * V2[(size_t)r * kk + j];
+        for (int i = 0; i < (int)pick.size(); ++i) {
+          const int j = pick[i];
+          Rb[(size_t)r * b + i] = CV2[(size_t)r * kk + j] - th[j] * V2[(size_t)r * kk + j];
+        }
       EIG_TRY(hipMemcpyAsync(X, Rb.data(), Rb.size() * 8, hipMemcpyHostToDevice, s));
       bool ok;
       int rc = add_block(ok);

@@ -5,6 +5,7 @@
 // Wilkinson shift (Givens bulge chase) until T is diagonal, with all
 // transforms accumulated into the eigenvector matrix.
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <numeric>
 #include <vector>
@@ -14,12 +15,20 @@ namespace msk {
 namespace {
 
 // In place: A (n x n, row-major, symmetric) -> tridiagonal (diag d, off e,
-// e[i] couples i and i+1); Q accumulates the reflections (A = Q T Q^T).
+// e[i] couples i and i+1) with A = Q T Q^T. With `accumulate`, Q is formed
+// explicitly; otherwise the reflectors are kept (reflector k acts on indices
+// k+1..n-1: v = (1, H[k][k+2..n-1]) in row k of H, scale beta[k]).
 void tridiagonalise(int n, std::vector<double>& A, std::vector<double>& Q, std::vector<double>& d,
-                    std::vector<double>& e) {
+                    std::vector<double>& e, bool accumulate = true, std::vector<double>* H = nullptr,
+                    std::vector<double>* betas = nullptr) {
   auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
-  Q.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  if (accumulate) {
+    Q.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  } else {
+    H->assign((size_t)n * n, 0.0);
+    betas->assign(n, 0.0);
+  }
   std::vector<double> v(n), p(n), w(n), qv(n);
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // length of x = A[k+1:n, k]
@@ -51,6 +60,11 @@ void tridiagonalise(int n, std::vector<double>& A, std::vector<double>& Q, std::
     }
     a(k + 1, k) = a(k, k + 1) = mu;
     for (int i = 1; i < m; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
+    if (!accumulate) {
+      (*betas)[k] = beta;
+      for (int i = 1; i < m; ++i) (*H)[(size_t)k * n + k + 1 + i] = v[i];
+      continue;
+    }
     // Q[:, k+1:] = Q[:, k+1:] (I - beta v v^T)
     for (int r = 0; r < n; ++r) {
       double* row = &Q[(size_t)r * n + (k + 1)];
@@ -87,6 +101,7 @@ void qr_step(int n, int lo, int hi, std::vector<double>& d, std::vector<double>&
       e[k + 1] *= c;
       x = e[k];
     }
+    if (Q.empty()) continue;
     for (int r2 = 0; r2 < n; ++r2) {  // columns k, k+1 of Q rotate
       double* row = &Q[(size_t)r2 * n];
       const double qk = row[k], qk1 = row[k + 1];
@@ -127,6 +142,167 @@ bool sym_eig(int n, std::vector<double>& A, std::vector<double>& evals, std::vec
     evals[j] = d[idx[j]];
     for (int r = 0; r < n; ++r) V[(size_t)r * n + j] = Q[(size_t)r * n + idx[j]];
   }
+  return true;
+}
+
+namespace {
+
+// Eigenvalues of the symmetric tridiagonal (d, e) by implicit QR without
+// vectors; false if QR did not settle.
+bool tridiag_eigenvalues(int n, std::vector<double> d, std::vector<double> e, std::vector<double>& out) {
+  std::vector<double> none;
+  const double tol = 4e-16;
+  int hi = n - 1;
+  long iters = 0;
+  while (hi > 0) {
+    if (std::fabs(e[hi - 1]) <= tol * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > tol * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+    if (lo > 0) e[lo - 1] = 0.0;
+    qr_step(n, lo, hi, d, e, none);
+    if (++iters > 60L * n + 100) return false;
+  }
+  out = d;
+  std::sort(out.begin(), out.end());
+  return true;
+}
+
+// LU factorisation with partial pivoting of the tridiagonal T - sigma I
+// (Golub & Van Loan 4.3.4): row i of U holds u0 (diagonal), u1, u2; l[i] and
+// swap[i] record the elimination of row i + 1. Zero pivots are replaced by
+// `tiny` (inverse iteration only needs a direction).
+struct TriLU {
+  std::vector<double> u0, u1, u2, l;
+  std::vector<char> swap;
+};
+
+void tridiag_lu(int n, const std::vector<double>& d, const std::vector<double>& e, double sigma, double tiny,
+                TriLU& f) {
+  f.u0.assign(n, 0.0);
+  f.u1.assign(n, 0.0);
+  f.u2.assign(n, 0.0);
+  f.l.assign(n, 0.0);
+  f.swap.assign(n, 0);
+  double r0 = d[0] - sigma, r1 = n > 1 ? e[0] : 0.0, r2 = 0.0;
+  for (int i = 0; i + 1 < n; ++i) {
+    const double n0 = e[i], n1 = d[i + 1] - sigma, n2 = i + 2 < n ? e[i + 1] : 0.0;
+    double m0, m1;
+    if (std::fabs(n0) > std::fabs(r0)) {
+      f.swap[i] = 1;
+      f.u0[i] = n0; f.u1[i] = n1; f.u2[i] = n2;
+      const double mult = r0 / n0;
+      f.l[i] = mult;
+      m0 = r1 - mult * n1;
+      m1 = r2 - mult * n2;
+    } else {
+      if (r0 == 0.0) r0 = tiny;
+      f.u0[i] = r0; f.u1[i] = r1; f.u2[i] = r2;
+      const double mult = n0 / r0;
+      f.l[i] = mult;
+      m0 = n1 - mult * r1;
+      m1 = n2 - mult * r2;
+    }
+    r0 = m0;
+    r1 = m1;
+    r2 = 0.0;
+  }
+  f.u0[n - 1] = r0 == 0.0 ? tiny : r0;
+}
+
+void tridiag_solve(int n, const TriLU& f, std::vector<double>& y) {
+  for (int i = 0; i + 1 < n; ++i) {
+    if (f.swap[i]) std::swap(y[i], y[i + 1]);
+    y[i + 1] -= f.l[i] * y[i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double t = y[i];
+    if (i + 1 < n) t -= f.u1[i] * y[i + 1];
+    if (i + 2 < n) t -= f.u2[i] * y[i + 2];
+    y[i] = t / f.u0[i];
+  }
+}
+
+}  // namespace
+
+// The m smallest eigenpairs of a symmetric A (n x n, row-major; destroyed):
+// Householder tridiagonalisation, all eigenvalues of T by implicit QR without
+// vectors, eigenvectors of T for the m smallest by inverse iteration (with
+// Gram-Schmidt inside clusters of close eigenvalues, as in LAPACK's xSTEIN),
+// then back through the reflectors. evals ascending; V is n x m row-major;
+// abs_max (optional) receives the largest eigenvalue magnitude.
+bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>& evals, std::vector<double>& V,
+                      double* abs_max) {
+  if (m > n) m = n;
+  std::vector<double> d, e, Qdummy, H, betas;
+  tridiagonalise(n, A, Qdummy, d, e, false, &H, &betas);
+  std::vector<double> all;
+  if (!tridiag_eigenvalues(n, d, e, all)) return false;
+  if (abs_max) *abs_max = std::max(std::fabs(all.front()), std::fabs(all.back()));
+  evals.assign(all.begin(), all.begin() + m);
+  double tnorm = 0.0;
+  for (int i = 0; i < n; ++i)
+    tnorm = std::max(tnorm, std::fabs(d[i]) + (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0));
+  if (tnorm == 0.0) tnorm = 1.0;
+  const double eps = std::ldexp(1.0, -52);
+  const double ortol = 1e-3 * tnorm;  // eigenvalues closer than this form a cluster
+  std::vector<double> X((size_t)n * m, 0.0);  // eigenvectors of T, column j at X[r * m + j]
+  std::vector<double> y(n), x(n);
+  TriLU f;
+  uint64_t seed = 0x9E3779B97F4A7C15ull;
+  int cluster_start = 0;
+  double sigma_prev = 0.0;
+  for (int j = 0; j < m; ++j) {
+    if (j > 0 && evals[j] - evals[j - 1] > ortol) cluster_start = j;
+    // separate equal shifts inside a cluster slightly
+    double sigma = evals[j];
+    if (j > cluster_start && sigma <= sigma_prev + 10.0 * eps * tnorm) sigma = sigma_prev + 10.0 * eps * tnorm;
+    sigma_prev = sigma;
+    tridiag_lu(n, d, e, sigma, eps * tnorm, f);
+    for (int r = 0; r < n; ++r) {  // pseudo-random start
+      seed ^= seed << 13; seed ^= seed >> 7; seed ^= seed << 17;
+      y[r] = (double)(seed >> 11) * 0x1p-53 - 0.5;
+    }
+    for (int it = 0; it < 4; ++it) {
+      x = y;
+      tridiag_solve(n, f, x);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int i = cluster_start; i < j; ++i) {
+          double dot = 0.0;
+          for (int r = 0; r < n; ++r) dot += X[(size_t)r * m + i] * x[r];
+          for (int r = 0; r < n; ++r) x[r] -= dot * X[(size_t)r * m + i];
+        }
+      double nrm = 0.0;
+      for (double t : x) nrm += t * t;
+      nrm = std::sqrt(nrm);
+      if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
+      for (int r = 0; r < n; ++r) y[r] = x[r] / nrm;
+    }
+    for (int r = 0; r < n; ++r) X[(size_t)r * m + j] = y[r];
+  }
+  // back-transform: V = H_0 H_1 ... H_{n-3} X (last reflector first)
+  std::vector<double> s(m);
+  for (int k = n - 3; k >= 0; --k) {
+    const double beta = betas[k];
+    if (beta == 0.0) continue;
+    const double* v = &H[(size_t)k * n];  // v[k+1] = 1, v[k+2..] stored
+    std::fill(s.begin(), s.end(), 0.0);
+    for (int r = k + 1; r < n; ++r) {
+      const double vr = r == k + 1 ? 1.0 : v[r];
+      const double* xr = &X[(size_t)r * m];
+      for (int j = 0; j < m; ++j) s[j] += vr * xr[j];
+    }
+    for (int j = 0; j < m; ++j) s[j] *= beta;
+    for (int r = k + 1; r < n; ++r) {
+      const double vr = r == k + 1 ? 1.0 : v[r];
+      double* xr = &X[(size_t)r * m];
+      for (int j = 0; j < m; ++j) xr[j] -= vr * s[j];
+    }
+  }
+  V.swap(X);
   return true;
 }
 

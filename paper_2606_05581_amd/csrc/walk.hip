@@ -204,60 +204,54 @@ __host__ __device__ __forceinline__ void test_tri(const TriRec* __restrict__ tri
 
 // Exact nearest triangle: lexicographic minimum of (FP32 squared distance,
 // original index). `h.slot` may name a candidate triangle on entry (warm
-// start: the previous step's nearest), tested first. One stack holds inner
-// nodes and leaves (a leaf entry is -((first << 4) | count) - 1), each with its
-// box lower bound; every loop trip handles one entry, so the triangle test
-// and the node test each appear once in the code.
+// start: the previous step's nearest), tested first so that the search starts
+// with a finite bound. Each node test sorts the four children by box lower
+// bound, tests the leaf children's triangles at once (nearest first), keeps
+// the nearest surviving inner child in registers as the next node and pushes
+// the other inner children farthest first; entries are popped only when the
+// current subtree is done, and skipped when their bound no longer reaches the
+// best distance. (Measured on gfx950 against a stack that also holds leaves
+// and against a loop that defers leaves until every lane of the wavefront
+// holds one: this order is the fastest of the three.)
+struct StackEntry {
+  int32_t node;
+  float lb;
+};
+
 template <bool kStats>
 __host__ __device__ void bvh_nearest(const Node4* __restrict__ nodes, const TriRec* __restrict__ tris, const Node4* lds,
                                      int32_t n_lds, float px, float py, float pz, float radius, Nearest& h,
                                      TravCount& cnt) {
   const float slack = 0x1p-18f * (radius + fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
-  int32_t stk_ref[kStackDepth];
-  float stk_lb[kStackDepth];
-  int sp = 0;
-  stk_ref[sp] = 0;  // root
-  stk_lb[sp] = 0.0f;
-  ++sp;
   if (h.slot >= 0) {
-    stk_ref[sp] = -((h.slot << 4) | 1) - 1;
-    stk_lb[sp] = 0.0f;
-    ++sp;
+    const int32_t s = h.slot;
+    h.d2 = INFINITY;
+    h.orig = INT_MAX;
+    h.slot = -1;
+    test_tri<kStats>(tris, s, px, py, pz, h, cnt);
   }
-  h.d2 = INFINITY;
-  h.orig = INT_MAX;
-  h.slot = -1;
-  float thr = INFINITY;
+  float thr = prune_bound(h.d2, slack);
+  StackEntry stk[kStackDepth];
+  int sp = 0;
+  int32_t node = 0;
   while (true) {
-    while (sp > 0 && stk_lb[sp - 1] > thr) --sp;
-    if (sp == 0) break;
-    --sp;
-    const int32_t ref = stk_ref[sp];
-    if (ref < 0) {  // leaf: test its triangles
-      const int32_t code = -ref - 1;
-      const int32_t first = code >> 4, count = code & 15;
-      const float before = h.d2;
-      for (int32_t s = first; s < first + count; ++s) test_tri<kStats>(tris, s, px, py, pz, h, cnt);
-      if (h.d2 != before) thr = prune_bound(h.d2, slack);
-      continue;
-    }
     float4 lox, loy, loz, hix, hiy, hiz;
     int4 ch, ct;
     if (kStats) {
       ++cnt.nodes;
       cnt.flops += 4 * kBoxFlops;
     }
-    if (ref < n_lds) {
-      const float4* N = (const float4*)&lds[ref];
+    if (node < n_lds) {
+      const float4* N = (const float4*)&lds[node];
       lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
       ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
     } else {
-      const float4* N = (const float4*)&nodes[ref];
+      const float4* N = (const float4*)&nodes[node];
       lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
       ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
     }
     float lb[4];
-    int32_t cr[4];
+    int32_t cc[4], cn[4];
     {
       const float lx[4] = {lox.x, lox.y, lox.z, lox.w}, ly[4] = {loy.x, loy.y, loy.z, loy.w},
                   lz[4] = {loz.x, loz.y, loz.z, loz.w};
@@ -270,28 +264,54 @@ __host__ __device__ void bvh_nearest(const Node4* __restrict__ nodes, const TriR
         const float gy = fmaxf(fmaxf(ly[k] - py, py - hy[k]), 0.0f);
         const float gz = fmaxf(fmaxf(lz[k] - pz, pz - hz[k]), 0.0f);
         lb[k] = gx * gx + gy * gy + gz * gz;
-        // a leaf ref packs (first, count); an unused slot gets the sentinel
-        // INT32_MIN (never a valid ref: leaf counts are at most 8)
-        cr[k] = c4[k] >= 0 ? c4[k] : (n4[k] > 0 ? -((((-c4[k]) - 1) << 4) | n4[k]) - 1 : INT32_MIN);
+        cc[k] = c4[k];
+        cn[k] = n4[k];
       }
     }
     // sort the four children by lower bound (5 compare-exchanges)
 #define MSK_CX(i, j)                                                        \
   if (lb[j] < lb[i]) {                                                      \
     float tl = lb[i]; lb[i] = lb[j]; lb[j] = tl;                            \
-    int32_t tc = cr[i]; cr[i] = cr[j]; cr[j] = tc;                          \
+    int32_t tc = cc[i]; cc[i] = cc[j]; cc[j] = tc;                          \
+    int32_t tn = cn[i]; cn[i] = cn[j]; cn[j] = tn;                          \
   }
     MSK_CX(0, 1) MSK_CX(2, 3) MSK_CX(0, 2) MSK_CX(1, 3) MSK_CX(1, 2)
 #undef MSK_CX
-    // push farthest first, so the nearest child is handled next
+    // leaves, nearest first (an unused slot has count 0)
 #pragma unroll
-    for (int k = 3; k >= 0; --k) {
-      if (cr[k] != INT32_MIN && lb[k] <= thr && sp < kStackDepth) {
-        stk_ref[sp] = cr[k];
-        stk_lb[sp] = lb[k];
-        ++sp;
+    for (int k = 0; k < 4; ++k) {
+      if (cc[k] < 0 && cn[k] > 0 && lb[k] <= thr) {
+        const int32_t first = -cc[k] - 1;
+        const float before = h.d2;
+        for (int32_t s = first; s < first + cn[k]; ++s) test_tri<kStats>(tris, s, px, py, pz, h, cnt);
+        if (h.d2 != before) thr = prune_bound(h.d2, slack);
       }
     }
+    // the nearest surviving inner child is next; the others are pushed
+    // farthest first
+    int32_t next = -1;
+    float next_lb = 0.0f;
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+      if (cc[k] >= 0 && lb[k] <= thr) {
+        if (next >= 0 && sp < kStackDepth) stk[sp++] = StackEntry{next, next_lb};
+        next = cc[k];
+        next_lb = lb[k];
+      }
+    }
+    if (next >= 0) {
+      node = next;
+      continue;
+    }
+    node = -1;
+    while (sp > 0) {
+      --sp;
+      if (stk[sp].lb <= thr) {
+        node = stk[sp].node;
+        break;
+      }
+    }
+    if (node < 0) break;
   }
 }
 
@@ -469,7 +489,15 @@ __device__ void walk_finish_global(const WalkLaunch& L, const MeshDev& M, const 
 // FP64 row with one device atomic per distinct column. AccT = double keeps
 // the partial sums in FP64; AccT = float keeps them in FP32 (a chunk holds at
 // most `chunk` walks) and flushes them into the FP64 rows.
-constexpr int kSlotBits = 8, kSlots = 1 << kSlotBits, kProbes = 8, kWaves = 4;
+// Row-table slots per wavefront table (2^bits) and the occupancy the
+// persistent kernel is compiled for: 128 slots keep a workgroup's LDS at
+// 31.5 KB so that 5 workgroups fit a CU, and 5 waves per SIMD (<= 96 VGPRs,
+// a few spills outside the traversal loop) measured fastest on gfx950
+// against 3, 4, 6 and 8.
+#ifndef MSK_TABLE_SLOT_BITS
+#define MSK_TABLE_SLOT_BITS 7
+#endif
+constexpr int kSlotBits = MSK_TABLE_SLOT_BITS, kSlots = 1 << kSlotBits, kProbes = 8, kWaves = 4;
 constexpr int32_t kEmptyKey = -1;
 
 template <typename AccT>
@@ -639,14 +667,27 @@ __global__ void __launch_bounds__(256) walk_plain_kernel(WalkLaunch L) {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+#ifndef MSK_LDS_TOP_NODES
+#define MSK_LDS_TOP_NODES 85
+#endif
+// top BVH nodes staged in LDS by the persistent kernel (at most kMaxTop)
+constexpr int kLdsTop = MSK_LDS_TOP_NODES < kMaxTop ? MSK_LDS_TOP_NODES : kMaxTop;
+#ifndef MSK_PERSISTENT_WAVES_PER_EU
+#define MSK_PERSISTENT_WAVES_PER_EU 5
+#endif
+#if MSK_PERSISTENT_WAVES_PER_EU > 0
+#define MSK_PERSISTENT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MSK_PERSISTENT_WAVES_PER_EU)))
+#else
+#define MSK_PERSISTENT_OCCUPANCY
+#endif
 // Persistent form: each wavefront keeps its 64 lanes busy by refilling
 // finished lanes with the next walks of its queue chunk; chunks come from
 // one of eight queues (one per XCD, blockIdx % 8) and wavefronts move on to
 // the other queues once their own is drained. Finished walks go into the
 // wavefront's row tables (see WaveTables).
 template <bool kStats, typename AccT>
-__global__ void __launch_bounds__(256) walk_persistent_kernel(WalkLaunch L) {
-  __shared__ Node4 top[kMaxTop];
+__global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_persistent_kernel(WalkLaunch L) {
+  __shared__ Node4 top[kLdsTop];
   __shared__ WaveTables<AccT> T;
   const int wi = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < kWaves * 2 * kSlots; i += blockDim.x) {
@@ -657,7 +698,7 @@ __global__ void __launch_bounds__(256) walk_persistent_kernel(WalkLaunch L) {
   for (int i = threadIdx.x; i < kWaves * 2 * 3; i += blockDim.x) (&T.cnt[0][0][0])[i] = 0;
   int32_t n_lds = 0;
   if (L.use_lds_top) {
-    n_lds = L.n_top;
+    n_lds = min(L.n_top, kLdsTop);
     const MeshDev& M0 = L.meshes[0];
     const int4* src = (const int4*)M0.nodes;
     int4* dst = (int4*)top;

@@ -13,7 +13,8 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmsk.so")
+# MSK_LIBRARY selects another build of the library (tuning experiments)
+LIB_PATH = os.environ.get("MSK_LIBRARY", os.path.join(HERE, "libmsk.so"))
 
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_DEVICE, ERR_NOT_CONVERGED, ERR_NUMERIC = range(6)
 ROWS_POINT, ROWS_HAT_RING = 0, 1

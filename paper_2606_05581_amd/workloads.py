@@ -220,24 +220,37 @@ def real_sh(L: int, dirs: np.ndarray) -> np.ndarray:
     """Orthonormal real spherical harmonics Y_lm, l <= L, at unit directions.
 
     Columns are ordered (l, m) with m = -l..l; returns (n, (L+1)^2).
+    Y_l0 = K_l0 P_l(cos t); Y_lm = sqrt(2) K_lm P_l^|m|(cos t) cos(m p) for
+    m > 0 and sin(|m| p) for m < 0, with P_l^m the associated Legendre
+    functions without the Condon-Shortley phase and K_lm the normalisation
+    sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!). The normalised functions K_lm P_l^m
+    come from the standard three-term recurrence in l (started from the
+    diagonal l = m), which stays stable at high degree.
     """
-    from scipy.special import sph_harm_y
-
     d = dirs / np.linalg.norm(dirs, axis=1, keepdims=True)
-    theta = np.arccos(np.clip(d[:, 2], -1.0, 1.0))
+    x = np.clip(d[:, 2], -1.0, 1.0)
+    sxy = np.sqrt(np.maximum(0.0, 1.0 - x * x))
     phi = np.arctan2(d[:, 1], d[:, 0])
     out = np.empty((d.shape[0], (L + 1) ** 2))
-    col = 0
-    for l in range(L + 1):
-        for m in range(-l, l + 1):
-            y = sph_harm_y(l, abs(m), theta, phi)
-            if m > 0:
-                out[:, col] = np.sqrt(2.0) * (-1.0) ** m * y.real
-            elif m < 0:
-                out[:, col] = np.sqrt(2.0) * (-1.0) ** m * y.imag
+    col = lambda l, m: l * l + l + m
+    qmm = np.full(x.shape, 1.0 / math.sqrt(4.0 * math.pi))  # K_00 P_0^0
+    for m in range(L + 1):
+        if m > 0:
+            qmm = math.sqrt((2.0 * m + 1.0) / (2.0 * m)) * sxy * qmm
+        cm, sm = (np.cos(m * phi), np.sin(m * phi)) if m > 0 else (None, None)
+        q_prev, q = None, qmm
+        for l in range(m, L + 1):
+            if l == m + 1:
+                q_prev, q = q, math.sqrt(2.0 * m + 3.0) * x * q
+            elif l > m + 1:
+                a = math.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
+                b = math.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
+                q_prev, q = q, a * (x * q - b * q_prev)
+            if m == 0:
+                out[:, col(l, 0)] = q
             else:
-                out[:, col] = y.real
-            col += 1
+                out[:, col(l, m)] = math.sqrt(2.0) * q * cm
+                out[:, col(l, -m)] = math.sqrt(2.0) * q * sm
     return out
 
 
@@ -681,7 +694,7 @@ def load(name: str, cache: bool = True, **kw) -> Workload:
     fn = WORKLOADS[name]
     if not cache:
         return fn(**kw)
-    key = hashlib.sha1((name + repr(sorted(kw.items())) + "v2").encode()).hexdigest()[:12]
+    key = hashlib.sha1((name + repr(sorted(kw.items())) + "v3").encode()).hexdigest()[:12]
     path = os.path.join(_cache_dir(), f"{name}_{key}.npz")
     if os.path.exists(path):
         return _load(path)

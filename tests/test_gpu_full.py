@@ -1,0 +1,278 @@
+"""Full-size runs of the HIP path (through the C ABI) with sampled parity.
+
+Each test runs one synthetic workload at its full size in the launch form the
+benchmark times (the persistent kernel; batched graphs for the batch), then
+compares a Morton-spread sample of rows with the oracle run on exactly those
+rows and the same Philox streams: entries within 4 combined standard errors
+and the fraction of divergent walks reported. Properties that hold at any
+size are checked on every row: row sums fixed by the partition of unity of
+the basis (Alg. 1 update; zero in the interior, the escape fraction in the
+exterior), the adaptive stopping rule, and eigen residuals.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+from paper_2606_05581_amd import workloads as W
+from parity_util import parity_report
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2606_05581_amd import msk
+
+    assert torch.cuda.is_available()
+    c = msk.Context(0)
+    yield c
+    c.close()
+
+
+def _sample_rows(rows, n):
+    order = W.morton_order(rows.p)
+    return np.unique(order[np.linspace(0, len(order) - 1, n).astype(np.int64)])
+
+
+def _oracle_rows(oracle_mod, scene, case, sel, walks, exterior, log=True, mesh=0):
+    t = time.time()
+    r = oracle_mod.estimate(scene, case.rows, case.basis, walks, case.eps, case.h, exterior=exterior, rows_sel=sel,
+                            log=log, nthreads=NTHREADS, mesh=mesh)
+    S, se = oracle_mod.finalize(r["acc"], r["acc2"], case.rows.w[sel], case.h, walks, r["discarded"])
+    r.update(S=S, se=se, secs=time.time() - t)
+    return r
+
+
+def _row_sum_bound(case):
+    """Bound on |row sum| from the table's own deviation from a partition of
+    unity (FP32 values) and FP32 interpolation at the start and hit points."""
+    b = case.basis
+    nv = b.rowptr.shape[0] - 1
+    sums = np.bincount(np.repeat(np.arange(nv), np.diff(b.rowptr)), weights=b.val.astype(np.float64), minlength=nv)
+    e_tab = np.abs(sums - 1.0).max()
+    return 2.0 * e_tab + 2e-6
+
+
+def _get(d, *fields):
+    return [d.get(f) for f in fields]
+
+
+@pytest.mark.parametrize("exterior", [False, True])
+def test_soup8_53k_full(ctx, oracle_mod, exterior):
+    """53,249-face soup, 2,000 rows x 1,024 walks; 64 rows against the oracle."""
+    from paper_2606_05581_amd import msk
+
+    wl = W.load("soup8_53k")
+    case = wl.cases[0]
+    label = f"soup8_53k full {'exterior' if exterior else 'interior'}"
+    print(f"[{label}] start", flush=True)
+    mesh = ctx.build_bvh(case.V, case.F)
+    rows = ctx.rows(mesh, case.rows)
+    basis = ctx.basis(case.basis, case.V.shape[0])
+    d = ctx.estimate_dtn(mesh, rows, basis, wl.walks, case.eps, case.h, exterior=exterior, record_log=1)
+    S, se, disc, esc, cap = _get(d, msk.FIELD_S, msk.FIELD_SE, msk.FIELD_ROW_DISCARDED, msk.FIELD_ROW_ESCAPED,
+                                 msk.FIELD_ROW_CAPPED)
+    status, tri, bary, nq = _get(d, msk.FIELD_LOG_STATUS, msk.FIELD_LOG_TRI, msk.FIELD_LOG_BARY,
+                                 msk.FIELD_LOG_QUERIES)
+    info = d.info()
+    print(f"[{label}] GPU: {info['walks_total']} walks, {info['queries_total']} queries, "
+          f"walk kernel {info['walk_kernel_ms']:.1f} ms", flush=True)
+    sel = _sample_rows(case.rows, 64)
+    o = _oracle_rows(oracle_mod, oracle_mod.Scene(case.V, case.F, bvh=True), case, sel, wl.walks, exterior)
+    print(f"[{label}] oracle: {len(sel)} rows in {o['secs']:.1f} s", flush=True)
+    assert np.array_equal(disc[sel], o["discarded"])
+    g = dict(S=S[sel], se=se[sel], status=status[sel], tri=tri[sel], bary=bary[sel], nq=nq[sel])
+    viol, div = parity_report(g, o, label, case)
+    assert viol.sum() == 0
+    assert div < (0.02 if exterior else 0.01)
+    assert cap.sum() == 0
+    w = case.rows.w * (disc == 0)
+    target = w / case.h * esc / wl.walks
+    bound = _row_sum_bound(case) * (w / case.h) + 1e-12 * np.abs(S).max()
+    assert np.all(np.abs(S.sum(1) - target) <= bound)
+    if not exterior:
+        assert esc.sum() == 0
+
+
+def test_sh_sphere_2m_full_and_modes(ctx, oracle_mod):
+    """1,997,120-face SH-displaced sphere, 10,000 rows x 4,096 walks (40.96M
+    walks); 32 rows against the oracle; the 64 smallest Steklov modes against
+    LAPACK on the same estimate."""
+    from paper_2606_05581_amd import msk
+
+    t0 = time.time()
+    wl = W.load("sh_sphere_2m")
+    case = wl.cases[0]
+    label = "sh_sphere_2m full interior"
+    print(f"[{label}] inputs in {time.time() - t0:.1f} s", flush=True)
+    mesh = ctx.build_bvh(case.V, case.F)
+    rows = ctx.rows(mesh, case.rows)
+    basis = ctx.basis(case.basis, case.V.shape[0])
+    d = ctx.estimate_dtn(mesh, rows, basis, wl.walks, case.eps, case.h)
+    S, se, disc, esc, cap = _get(d, msk.FIELD_S, msk.FIELD_SE, msk.FIELD_ROW_DISCARDED, msk.FIELD_ROW_ESCAPED,
+                                 msk.FIELD_ROW_CAPPED)
+    info = d.info()
+    print(f"[{label}] GPU: {info['walks_total']} walks, {info['queries_total']} queries, "
+          f"walk kernel {info['walk_kernel_ms']:.1f} ms", flush=True)
+    assert info["walks_total"] == int((disc == 0).sum()) * wl.walks
+    sel = _sample_rows(case.rows, 32)
+    o = _oracle_rows(oracle_mod, oracle_mod.Scene(case.V, case.F, bvh=True), case, sel, wl.walks, False, log=False)
+    print(f"[{label}] oracle: {len(sel)} rows in {o['secs']:.1f} s", flush=True)
+    assert np.array_equal(disc[sel], o["discarded"])
+    tol = 4 * np.sqrt(se[sel] ** 2 + o["se"] ** 2) + 1e-12 * np.abs(o["S"]).max()
+    bad = np.abs(S[sel] - o["S"]) > tol
+    z = np.abs(S[sel] - o["S"]) / np.maximum(tol / 4, 1e-300)
+    print(f"[{label}] sampled entries outside 4 combined se: {bad.sum()}/{bad.size}, max z {z.max():.2f}", flush=True)
+    assert bad.sum() == 0
+    qg, qo = d.get(msk.FIELD_ROW_QUERIES)[sel].sum(), o["n_query"].sum()
+    assert abs(qg - qo) <= 0.01 * qo  # walks agree up to rare FP32 / FP64 path splits
+    assert esc.sum() == 0 and cap.sum() == 0
+    w = case.rows.w * (disc == 0)
+    assert np.all(np.abs(S.sum(1)) <= _row_sum_bound(case) * (w / case.h) + 1e-12 * np.abs(S).max())
+    # eigen step: 64 smallest modes against LAPACK on the same symmetrised matrix
+    k = wl.k
+    t = time.time()
+    ev, psi, st = ctx.steklov_modes(d, k)
+    t_gpu = time.time() - t
+    keep = np.nonzero(w > 0)[0]
+    m = 1 / np.sqrt(w[keep])
+    Ss = 0.5 * (S[np.ix_(keep, keep)] + S[np.ix_(keep, keep)].T)
+    Cm = m[:, None] * Ss * m[None, :]
+    t = time.time()
+    ref = np.linalg.eigvalsh(Cm)
+    t_ref = time.time() - t
+    cn = np.abs(ref).max()
+    err = np.abs(ev - ref[:k]).max() / cn
+    P = psi[keep]
+    R = Ss @ P - (w[keep][:, None] * P) * ev[None, :]
+    nrm = np.sqrt(np.sum(w[keep][:, None] * P * P, 0))
+    res = (np.linalg.norm(R / np.sqrt(w[keep])[:, None], axis=0) / nrm).max() / cn
+    print(f"[{label}] modes k={k}: converged={st['converged']} cycles={st['iterations']} block={st['block']} "
+          f"max |lambda - lapack|/|C| {err:.2e} residual/|C| {res:.2e} ({t_gpu:.1f} s; LAPACK {t_ref:.1f} s)",
+          flush=True)
+    assert st["converged"] and err < 2e-5 and res < 2e-4
+
+
+def test_exterior200_full_adaptive_and_modes(ctx, oracle_mod):
+    """200-object exterior scene (300,800 faces), 20,000 rows; walks added in
+    batches of 256 until the escape-fraction se is at most 1e-3 (cap 65,536);
+    16 rows against the oracle at their final walk counts; the 128 smallest
+    modes against a library eigensolver on the same estimate."""
+    import torch
+
+    from paper_2606_05581_amd import msk
+
+    t0 = time.time()
+    wl = W.load("exterior200_301k")
+    case = wl.cases[0]
+    label = "exterior200_301k full adaptive"
+    print(f"[{label}] inputs in {time.time() - t0:.1f} s", flush=True)
+    mesh = ctx.build_bvh(case.V, case.F)
+    rows = ctx.rows(mesh, case.rows)
+    basis = ctx.basis(case.basis, case.V.shape[0])
+    target, cap_w = 1e-3, 65536
+    d = ctx.estimate_dtn(mesh, rows, basis, wl.walks, case.eps, case.h, exterior=True, se_target=target,
+                         walks_max=cap_w)
+    S, se, disc, esc, nwk = _get(d, msk.FIELD_S, msk.FIELD_SE, msk.FIELD_ROW_DISCARDED, msk.FIELD_ROW_ESCAPED,
+                                 msk.FIELD_ROW_WALKS)
+    info = d.info()
+    print(f"[{label}] GPU: {info['walks_total']} walks in {info['walk_launches']} launches, "
+          f"{info['queries_total']} queries, walk kernel {info['walk_kernel_ms']:.1f} ms; walks per row "
+          f"min {nwk[disc == 0].min()} median {int(np.median(nwk[disc == 0]))} max {nwk[disc == 0].max()}",
+          flush=True)
+    live = disc == 0
+    assert np.all(nwk[live] % wl.walks == 0) and nwk[live].min() >= wl.walks and nwk[live].max() <= cap_w
+    q = esc[live] / nwk[live]
+    se_q = np.sqrt(np.maximum(q * (1 - q), 1.0 / nwk[live]) / nwk[live])
+    assert np.all((se_q <= target) | (nwk[live] + wl.walks > cap_w))
+    assert info["walks_total"] == int(nwk[live].sum())
+    # row sums: (w/h) times the escape fraction of the row's own walk count
+    w = case.rows.w * live
+    rs_target = np.where(live, w / case.h * esc / np.maximum(nwk, 1), 0.0)
+    assert np.all(np.abs(S.sum(1) - rs_target) <= _row_sum_bound(case) * (w / case.h) + 1e-12 * np.abs(S).max())
+    # 16 sampled rows against the oracle at their own walk counts
+    sel = _sample_rows(case.rows, 16)
+    sel = sel[live[sel]]
+    scene = oracle_mod.Scene(case.V, case.F, bvh=True)
+    bad = 0
+    zmax = 0.0
+    t = time.time()
+    for wk in np.unique(nwk[sel]):
+        ss = sel[nwk[sel] == wk]
+        o = _oracle_rows(oracle_mod, scene, case, ss, int(wk), True, log=False)
+        # escapes agree walk for walk up to rare FP32 / FP64 path splits
+        assert np.all(np.abs(o["n_escaped"] - esc[ss]) <= 3 + 0.01 * wk)
+        tol = 4 * np.sqrt(se[ss] ** 2 + o["se"] ** 2) + 1e-12 * np.abs(o["S"]).max()
+        bad += int((np.abs(S[ss] - o["S"]) > tol).sum())
+        zmax = max(zmax, float((np.abs(S[ss] - o["S"]) / np.maximum(tol / 4, 1e-300)).max()))
+    print(f"[{label}] oracle: {len(sel)} rows in {time.time() - t:.1f} s; entries outside 4 combined se: {bad}, "
+          f"max z {zmax:.2f}", flush=True)
+    assert bad == 0
+    # eigen step: 128 smallest modes; reference eigenvalues from the FP64
+    # symmetric eigensolver that torch calls on the same matrix
+    k = wl.k
+    t = time.time()
+    ev, psi, st = ctx.steklov_modes(d, k)
+    t_gpu = time.time() - t
+    keep = np.nonzero(w > 0)[0]
+    m = 1 / np.sqrt(w[keep])
+    Ss = 0.5 * (S[np.ix_(keep, keep)] + S[np.ix_(keep, keep)].T)
+    Cm = m[:, None] * Ss * m[None, :]
+    t = time.time()
+    ref = torch.linalg.eigvalsh(torch.from_numpy(Cm).cuda()).cpu().numpy()
+    t_ref = time.time() - t
+    cn = np.abs(ref).max()
+    err = np.abs(ev - ref[:k]).max() / cn
+    P = psi[keep]
+    R = Ss @ P - (w[keep][:, None] * P) * ev[None, :]
+    nrm = np.sqrt(np.sum(w[keep][:, None] * P * P, 0))
+    res = (np.linalg.norm(R / np.sqrt(w[keep])[:, None], axis=0) / nrm).max() / cn
+    print(f"[{label}] modes k={k}: converged={st['converged']} cycles={st['iterations']} block={st['block']} "
+          f"max |lambda - ref|/|C| {err:.2e} residual/|C| {res:.2e} ({t_gpu:.1f} s; reference {t_ref:.1f} s)",
+          flush=True)
+    assert st["converged"] and err < 2e-5 and res < 2e-4
+
+
+def test_batch64_mixed_full(ctx, oracle_mod):
+    """64 meshes (8.0M faces), 168,811 rows x 1,024 walks in one batch plan
+    (captured graphs); two rows of every mesh against the oracle."""
+    from paper_2606_05581_amd import msk
+
+    t0 = time.time()
+    wl = W.load("batch64_mixed")
+    print(f"[batch64_mixed full] inputs in {time.time() - t0:.1f} s", flush=True)
+    hs = []
+    for c in wl.cases:
+        m = ctx.build_bvh(c.V, c.F)
+        hs.append((c, m, ctx.rows(m, c.rows), ctx.basis(c.basis, c.V.shape[0])))
+    B = ctx.batch([h[1] for h in hs], [h[2] for h in hs], [h[3] for h in hs], [c.eps for c in wl.cases],
+                  [c.h for c in wl.cases], wl.walks)
+    info = B.run()
+    print(f"[batch64_mixed full] GPU: {info['walks_total']} walks, {info['queries_total']} queries, walk kernel "
+          f"{info['walk_kernel_ms']:.1f} ms", flush=True)
+    bad = total = 0
+    zmax = 0.0
+    t = time.time()
+    for i, (c, _, _, _) in enumerate(hs):
+        v = B.dtn(i)
+        S, se, disc, nq = _get(v, msk.FIELD_S, msk.FIELD_SE, msk.FIELD_ROW_DISCARDED, msk.FIELD_ROW_QUERIES)
+        w = c.rows.w * (disc == 0)
+        assert np.all(np.abs(S.sum(1)) <= _row_sum_bound(c) * (w / c.h) + 1e-12 * np.abs(S).max())
+        sel = _sample_rows(c.rows, 2)
+        o = _oracle_rows(oracle_mod, oracle_mod.Scene(c.V, c.F, bvh=True), c, sel, wl.walks, False, log=False,
+                         mesh=i)
+        assert np.array_equal(o["discarded"], disc[sel])
+        assert abs(int(nq[sel].sum()) - int(o["n_query"].sum())) <= 0.01 * o["n_query"].sum()
+        tol = 4 * np.sqrt(se[sel] ** 2 + o["se"] ** 2) + 1e-12 * np.abs(o["S"]).max()
+        bad += int((np.abs(S[sel] - o["S"]) > tol).sum())
+        total += tol.size
+        zmax = max(zmax, float((np.abs(S[sel] - o["S"]) / np.maximum(tol / 4, 1e-300)).max()))
+    print(f"[batch64_mixed full] oracle: 128 rows in {time.time() - t:.1f} s; entries outside 4 combined se: "
+          f"{bad}/{total}, max z {zmax:.2f}", flush=True)
+    assert bad == 0

@@ -315,6 +315,201 @@ __host__ __device__ void bvh_nearest(const Node4* __restrict__ nodes, const TriR
   }
 }
 
+// Wavefront-cooperative form of bvh_nearest (same result, bit for bit). All
+// 64 lanes call it together; lanes with has == false only help. Each lane
+// walks its own nodes as above, but the triangles of the leaves it reaches
+// are listed in LDS and tested 64 at a time by the whole wavefront, so the
+// long triangle test runs with most lanes busy instead of a few. A task's
+// (squared distance, original index) goes to its owner through a 64-bit LDS
+// atomic minimum, which realises the lexicographic order exactly; the task
+// that holds the minimum writes its barycentrics for the owner.
+constexpr int kCoopTasks = 256;
+struct CoopScratch {
+  int32_t task_slot[kCoopTasks];
+  uint8_t task_owner[kCoopTasks];
+  unsigned long long key[64];
+  float4 pt[64];           // owner's query point and early-reject bound
+  const TriRec* tris[64];  // owner's triangle array (batched meshes differ per lane)
+  int32_t rec_slot[64];
+  float rec_l1[64], rec_l2[64];
+  uint32_t flops[64];  // statistics kernels only
+};
+
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <bool kStats>
+__device__ void coop_leaf_round(CoopScratch* W, uint32_t lane, uint32_t ntask) {
+  for (uint32_t t0 = 0; t0 < ntask; t0 += 64) {
+    const uint32_t t = t0 + lane;
+    if (t < ntask) {
+      const int32_t s = W->task_slot[t];
+      const uint32_t o = W->task_owner[t];
+      const float4 q = W->pt[o];
+      const TriRec T = W->tris[o][s];
+      float l1 = 0.0f, l2 = 0.0f, den = 1.0f;
+      int region = 0;
+      const float d = tri_dist2(q.x, q.y, q.z, T, q.w, l1, l2, den, region);
+      if (kStats) atomicAdd(&W->flops[o], kTriFlops[region & 7]);
+      if (d <= q.w) {
+        int32_t orig;
+        memcpy(&orig, &T.a.w, 4);
+        const unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (uint32_t)orig;
+        atomicMin(&W->key[o], key);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (W->key[o] == key) {
+          if (region == 6) {
+            l1 = l1 / den;
+            l2 = l2 / den;
+          }
+          W->rec_slot[o] = s;
+          W->rec_l1[o] = l1;
+          W->rec_l2[o] = l2;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+}
+
+template <bool kStats>
+__device__ void bvh_nearest_coop(const Node4* __restrict__ nodes, const TriRec* __restrict__ tris, const Node4* lds,
+                                 int32_t n_lds, float px, float py, float pz, float radius, Nearest& h,
+                                 TravCount& cnt, bool has, CoopScratch* W) {
+  const uint32_t lane = __lane_id();
+  const float slack = 0x1p-18f * (radius + fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
+  if (has && h.slot >= 0) {
+    const int32_t s = h.slot;
+    h.d2 = INFINITY;
+    h.orig = INT_MAX;
+    h.slot = -1;
+    test_tri<kStats>(tris, s, px, py, pz, h, cnt);
+  }
+  float thr = prune_bound(h.d2, slack);
+  StackEntry stk[kStackDepth];
+  int sp = 0;
+  int32_t node = has ? 0 : -1;
+  W->tris[lane] = tris;
+  while (__ballot(node >= 0) != 0) {
+    float lb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int32_t cc[4] = {-1, -1, -1, -1}, cn[4] = {0, 0, 0, 0};
+    if (node >= 0) {
+      float4 lox, loy, loz, hix, hiy, hiz;
+      int4 ch, ct;
+      if (kStats) {
+        ++cnt.nodes;
+        cnt.flops += 4 * kBoxFlops;
+      }
+      if (node < n_lds) {
+        const float4* N = (const float4*)&lds[node];
+        lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
+        ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
+      } else {
+        const float4* N = (const float4*)&nodes[node];
+        lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
+        ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
+      }
+      const float lx[4] = {lox.x, lox.y, lox.z, lox.w}, ly[4] = {loy.x, loy.y, loy.z, loy.w},
+                  lz[4] = {loz.x, loz.y, loz.z, loz.w};
+      const float hx[4] = {hix.x, hix.y, hix.z, hix.w}, hy[4] = {hiy.x, hiy.y, hiy.z, hiy.w},
+                  hz[4] = {hiz.x, hiz.y, hiz.z, hiz.w};
+      const int32_t c4[4] = {ch.x, ch.y, ch.z, ch.w}, n4[4] = {ct.x, ct.y, ct.z, ct.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float gx = fmaxf(fmaxf(lx[k] - px, px - hx[k]), 0.0f);
+        const float gy = fmaxf(fmaxf(ly[k] - py, py - hy[k]), 0.0f);
+        const float gz = fmaxf(fmaxf(lz[k] - pz, pz - hz[k]), 0.0f);
+        lb[k] = gx * gx + gy * gy + gz * gz;
+        cc[k] = c4[k];
+        cn[k] = n4[k];
+      }
+#define MSK_CX(i, j)                                                        \
+  if (lb[j] < lb[i]) {                                                      \
+    float tl = lb[i]; lb[i] = lb[j]; lb[j] = tl;                            \
+    int32_t tc = cc[i]; cc[i] = cc[j]; cc[j] = tc;                          \
+    int32_t tn = cn[i]; cn[i] = cn[j]; cn[j] = tn;                          \
+  }
+      MSK_CX(0, 1) MSK_CX(2, 3) MSK_CX(0, 2) MSK_CX(1, 3) MSK_CX(1, 2)
+#undef MSK_CX
+    }
+    // this lane's leaf triangles within the bound, as one list
+    int32_t nl[4], tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      nl[k] = (node >= 0 && cc[k] < 0 && cn[k] > 0 && lb[k] <= thr) ? cn[k] : 0;
+      tot += nl[k];
+    }
+    if (__ballot(tot > 0) != 0) {
+      W->pt[lane] = make_float4(px, py, pz, h.d2);
+      W->key[lane] = ((unsigned long long)__float_as_uint(h.d2) << 32) | (uint32_t)h.orig;
+      if (kStats) W->flops[lane] = 0;
+      uint32_t ntask = 0;
+      for (int32_t j = 0;; ++j) {
+        const uint64_t m = __ballot(j < tot);
+        if (ntask > 0 && (m == 0 || ntask + (uint32_t)__popcll(m) > (uint32_t)kCoopTasks)) {
+          coop_leaf_round<kStats>(W, lane, ntask);
+          ntask = 0;
+        }
+        if (m == 0) break;
+        if (j < tot) {
+          const int32_t e1 = nl[0], e2 = e1 + nl[1], e3 = e2 + nl[2];
+          const int k = (j >= e1) + (j >= e2) + (j >= e3);
+          const int32_t base = k == 0 ? 0 : (k == 1 ? e1 : (k == 2 ? e2 : e3));
+          const int32_t c = k == 0 ? cc[0] : (k == 1 ? cc[1] : (k == 2 ? cc[2] : cc[3]));
+          const uint32_t pos = ntask + mbcnt64(m);
+          W->task_slot[pos] = -c - 1 + (j - base);
+          W->task_owner[pos] = (uint8_t)lane;
+        }
+        ntask += (uint32_t)__popcll(m);
+      }
+      if (tot > 0) {
+        if (kStats) {
+          cnt.tris += (uint32_t)tot;
+          cnt.flops += W->flops[lane];
+        }
+        const unsigned long long k2 = W->key[lane];
+        const float d = __uint_as_float((uint32_t)(k2 >> 32));
+        const int32_t orig = (int32_t)(uint32_t)k2;
+        if (d < h.d2 || (d == h.d2 && orig < h.orig)) {
+          h.d2 = d;
+          h.orig = orig;
+          h.slot = W->rec_slot[lane];
+          h.l1 = W->rec_l1[lane];
+          h.l2 = W->rec_l2[lane];
+          thr = prune_bound(h.d2, slack);
+        }
+      }
+    }
+    if (node >= 0) {
+      // the nearest surviving inner child is next; the others are pushed
+      // farthest first
+      int32_t next = -1;
+      float next_lb = 0.0f;
+#pragma unroll
+      for (int k = 3; k >= 0; --k) {
+        if (cc[k] >= 0 && lb[k] <= thr) {
+          if (next >= 0 && sp < kStackDepth) stk[sp++] = StackEntry{next, next_lb};
+          next = cc[k];
+          next_lb = lb[k];
+        }
+      }
+      if (next >= 0) {
+        node = next;
+      } else {
+        node = -1;
+        while (sp > 0) {
+          --sp;
+          if (stk[sp].lb <= thr) {
+            node = stk[sp].node;
+            break;
+          }
+        }
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------ walk machinery
 
 struct LaneWalk {
@@ -328,6 +523,7 @@ struct LaneWalk {
   int32_t active;
   TravCount cnt;  // traversal work of this walk (counted in the statistics kernels only)
   int32_t tab;    // wavefront row table of the walk (-1: device atomics)
+  uint32_t ux, uy;  // direction uniforms of the current step (drawn before its query)
 };
 
 // Start of a walk: sample s (point rows: the fixed sample; hat rows:
@@ -490,12 +686,13 @@ __device__ void walk_finish_global(const WalkLaunch& L, const MeshDev& M, const 
 // the partial sums in FP64; AccT = float keeps them in FP32 (a chunk holds at
 // most `chunk` walks) and flushes them into the FP64 rows.
 // Row-table slots per wavefront table (2^bits) and the occupancy the
-// persistent kernel is compiled for: 128 slots keep a workgroup's LDS at
-// 31.5 KB so that 5 workgroups fit a CU, and 5 waves per SIMD (<= 96 VGPRs,
-// a few spills outside the traversal loop) measured fastest on gfx950
-// against 3, 4, 6 and 8.
+// persistent kernel is compiled for: with 64 slots, the cooperative leaf
+// scratch and 21 LDS-staged top nodes a workgroup holds 30.5 KB of LDS, so
+// 5 workgroups fit a CU; 5 waves per SIMD (<= 96 VGPRs, spills outside the
+// traversal loop) measured fastest on gfx950 against 3, 4, 6 and 8, and
+// 128 slots or 85 staged nodes gained nothing that paid for lower occupancy.
 #ifndef MSK_TABLE_SLOT_BITS
-#define MSK_TABLE_SLOT_BITS 7
+#define MSK_TABLE_SLOT_BITS 6
 #endif
 constexpr int kSlotBits = MSK_TABLE_SLOT_BITS, kSlots = 1 << kSlotBits, kProbes = 8, kWaves = 4;
 constexpr int32_t kEmptyKey = -1;
@@ -577,19 +774,17 @@ __device__ __forceinline__ void onb(double nx, double ny, double nz, double e1[3
 
 // One step of a live walk. Returns -1 while the walk continues, else its
 // final status (hit / escaped / capped) with `hit` set for hits and caps.
-template <bool kStats>
-__device__ int32_t walk_step(const WalkLaunch& L, const MeshDev& M, const Node4* lds, int32_t n_lds, LaneWalk& w,
-                             Nearest& hit) {
-  if (w.step >= M.max_steps) {
-    // step cap: the walk ends at the nearest boundary point of its position
-    hit.d2 = INFINITY;
-    hit.orig = INT_MAX;
-    hit.slot = w.slot;
-    bvh_nearest<kStats>(M.nodes, M.tris, lds, n_lds, w.x, w.y, w.z, M.radius, hit, w.cnt);
-    ++w.queries;
-    return kCapped;
-  }
+// First half of a WoS step (Sec. 2; exterior roulette of Sec. 3.3): the step
+// cap, and outside the bounding sphere escape or re-entry. Returns kEscaped
+// when the walk ends here, else -1: the walk needs the nearest-triangle
+// query at (w.x, w.y, w.z); `capped` marks the query that ends a capped walk.
+__device__ int32_t walk_begin(const WalkLaunch& L, const MeshDev& M, LaneWalk& w, bool& capped) {
+  capped = w.step >= M.max_steps;
+  // step cap: the walk ends at the nearest boundary point of its position
+  if (capped) return -1;
   const uint4 u = draw(L, (uint32_t)w.row, w.walk, (uint32_t)w.step, kPurposeStep, (uint32_t)M.mesh_id);
+  w.ux = u.x;
+  w.uy = u.y;
   const float rho2 = w.x * w.x + w.y * w.y + w.z * w.z;
   const double rho = rho2 > M.radius * M.radius * (1.0f - 0x1p-18f)
                          ? sqrt((double)w.x * w.x + (double)w.y * w.y + (double)w.z * w.z)
@@ -616,15 +811,19 @@ __device__ int32_t walk_step(const WalkLaunch& L, const MeshDev& M, const Node4*
     w.z = (float)(R * (mu * nz + st * (cp * e1[2] + sp * e2[2])));
     // the walk goes on from the sphere in this same step (u.x, u.y unused so far)
   }
-  hit.d2 = INFINITY;
-  hit.orig = INT_MAX;
-  hit.slot = w.slot;
-  bvh_nearest<kStats>(M.nodes, M.tris, lds, n_lds, w.x, w.y, w.z, M.radius, hit, w.cnt);
+  return -1;
+}
+
+// Second half: with the query's answer in `hit`, stop in the eps-shell or
+// take the ball step r (shrunk by the conservative guard) along a uniform
+// direction. Returns kCapped / kHit when the walk ends, else -1.
+__device__ int32_t walk_end(const MeshDev& M, LaneWalk& w, bool capped, const Nearest& hit) {
   ++w.queries;
+  if (capped) return kCapped;
   w.slot = hit.slot;
   if (hit.d2 < M.eps2) return kHit;
   const float r = sqrtf(hit.d2) * (1.0f - M.kappa) - M.delta;
-  const float u0 = unit_f(u.x), u1 = unit_f(u.y);
+  const float u0 = unit_f(w.ux), u1 = unit_f(w.uy);
   const float z = 1.0f - 2.0f * u0;
   const float rxy = 2.0f * sqrtf(u0 * (1.0f - u0));
   // v_sin/v_cos take the angle in revolutions: sin(2 pi u1), cos(2 pi u1)
@@ -634,6 +833,20 @@ __device__ int32_t walk_step(const WalkLaunch& L, const MeshDev& M, const Node4*
   w.z += r * z;
   ++w.step;
   return -1;
+}
+
+// One whole step with a lane-private query (plain kernel).
+template <bool kStats>
+__device__ int32_t walk_step(const WalkLaunch& L, const MeshDev& M, const Node4* lds, int32_t n_lds, LaneWalk& w,
+                             Nearest& hit) {
+  bool capped;
+  const int32_t st = walk_begin(L, M, w, capped);
+  if (st >= 0) return st;
+  hit.d2 = INFINITY;
+  hit.orig = INT_MAX;
+  hit.slot = w.slot;
+  bvh_nearest<kStats>(M.nodes, M.tris, lds, n_lds, w.x, w.y, w.z, M.radius, hit, w.cnt);
+  return walk_end(M, w, capped, hit);
 }
 
 __device__ __forceinline__ void decode_walk(const WalkLaunch& L, uint64_t g, LaneWalk& w) {
@@ -668,7 +881,11 @@ __global__ void __launch_bounds__(256) walk_plain_kernel(WalkLaunch L) {
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 #ifndef MSK_LDS_TOP_NODES
-#define MSK_LDS_TOP_NODES 85
+#define MSK_LDS_TOP_NODES 21
+#endif
+// leaf triangles tested by the whole wavefront (bvh_nearest_coop)
+#ifndef MSK_COOP_LEAVES
+#define MSK_COOP_LEAVES 1
 #endif
 // top BVH nodes staged in LDS by the persistent kernel (at most kMaxTop)
 constexpr int kLdsTop = MSK_LDS_TOP_NODES < kMaxTop ? MSK_LDS_TOP_NODES : kMaxTop;
@@ -687,8 +904,11 @@ constexpr int kLdsTop = MSK_LDS_TOP_NODES < kMaxTop ? MSK_LDS_TOP_NODES : kMaxTo
 // wavefront's row tables (see WaveTables).
 template <bool kStats, typename AccT>
 __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_persistent_kernel(WalkLaunch L) {
-  __shared__ Node4 top[kLdsTop];
+  __shared__ Node4 top[kLdsTop > 0 ? kLdsTop : 1];
   __shared__ WaveTables<AccT> T;
+#if MSK_COOP_LEAVES
+  __shared__ CoopScratch coop[kWaves];
+#endif
   const int wi = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < kWaves * 2 * kSlots; i += blockDim.x) {
     (&T.key[0][0][0])[i] = kEmptyKey;
@@ -787,10 +1007,31 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_persistent_
     // ---- one step of every live walk
     bool fin = false;
     int32_t fin_tab = -1;
+#if MSK_COOP_LEAVES
+    // first half per lane, the query by the whole wavefront, second half per lane
+    int32_t st = -1;
+    bool capped = false, q = false;
+    if (w.active) {
+      st = walk_begin(L, L.meshes[w.mesh], w, capped);
+      q = st < 0;
+    }
+    if (__ballot(q) != 0) {
+      const MeshDev& Mq = L.meshes[q ? w.mesh : 0];
+      hit.d2 = INFINITY;
+      hit.orig = INT_MAX;
+      hit.slot = q ? w.slot : -1;
+      bvh_nearest_coop<kStats>(Mq.nodes, Mq.tris, top, (q && w.mesh == 0) ? n_lds : 0, w.x, w.y, w.z, Mq.radius, hit,
+                               w.cnt, q, &coop[wi]);
+    }
+    if (w.active) {
+      const MeshDev& M = L.meshes[w.mesh];
+      if (q) st = walk_end(M, w, capped, hit);
+#else
     if (w.active) {
       const MeshDev& M = L.meshes[w.mesh];
       const int32_t nl = (w.mesh == 0) ? n_lds : 0;
       const int32_t st = walk_step<kStats>(L, M, top, nl, w, hit);
+#endif
       if (st >= 0) {
         if (w.tab >= 0)
           walk_finish_table(L, M, w, st, hit, T, wi);

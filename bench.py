@@ -147,6 +147,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--launch", default="", help="fixed launch settings instead of tuning, e.g. chunk=64,regen_min=16")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a device copy of this size first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -178,7 +179,10 @@ def main():
     torch.cuda.synchronize()
     log("[bench] inputs on the GPU")
     tuned = None
-    if not args.no_tune:  # untimed: pick leaf width / chunk / refill threshold / workgroups per CU
+    if args.launch:
+        run.opts = {k: int(v) for k, v in (kv.split("=") for kv in args.launch.split(","))}
+        log(f"[bench] launch settings: {run.opts}")
+    elif not args.no_tune:  # untimed: pick leaf width / chunk / refill threshold / workgroups per CU
         hs = run.handles
         tuned = ctx.autotune([h[1] for h in hs], [h[2] for h in hs], [h[3] for h in hs], [h[0].eps for h in hs],
                              [h[0].h for h in hs], exterior=(wl.modes[0] == "exterior"))

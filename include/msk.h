@@ -68,7 +68,8 @@ const char* msk_last_error(const msk_ctx* ctx);
 
 typedef struct {
   int32_t leaf_size; /* triangles per BVH leaf, 1..8 (default 4)            */
-  int32_t top_nodes; /* BVH nodes cached in LDS per workgroup, 0..85 (def. 85) */
+  int32_t top_nodes; /* top BVH nodes the persistent kernel may stage in LDS,
+                        0..85 (default 85; the kernel stages at most 21)  */
 } msk_bvh_opts;
 
 typedef struct {
@@ -173,7 +174,8 @@ typedef struct {
   int32_t block;       /* threads per workgroup (default 256)                  */
   int32_t blocks_per_cu; /* persistent grid size / 256 CUs (default 8)         */
   int32_t chunk;       /* walks a wavefront takes from the queue at once (64)  */
-  int32_t regen_min;   /* refill a wavefront once this many lanes idle (1)     */
+  int32_t regen_min;   /* persistent form: a wavefront finishes steps and takes
+                          new walks once this many of its 64 lanes wait (48) */
   int32_t record_log;  /* keep a per-walk log (status, triangle, bary, queries) */
   double se_target;    /* > 0: adaptive walks per row (see msk_estimate_dtn)   */
   int64_t walks_max;   /* adaptive cap (default 65536)                         */
@@ -278,7 +280,7 @@ void msk_dtn_destroy(msk_dtn* dtn);
 typedef struct {
   int32_t n_leaf, leaf[4];            /* BVH leaf width                        */
   int32_t n_chunk, chunk[4];          /* walks a wavefront takes per queue grab */
-  int32_t n_regen, regen_min[4];      /* idle lanes that trigger a refill      */
+  int32_t n_regen, regen_min[4];      /* waiting lanes that trigger bookkeeping */
   int32_t n_bpc, blocks_per_cu[4];    /* persistent workgroups per CU          */
   int64_t trial_rows;                 /* rows sampled over all meshes (16384)  */
   int64_t trial_walks;                /* walks per sampled row (128)           */

@@ -418,7 +418,7 @@ extern "C" void msk_dtn_opts_default(msk_dtn_opts* o) {
   o->block = 256;
   o->blocks_per_cu = 8;
   o->chunk = 64;
-  o->regen_min = 1;
+  o->regen_min = 48;
   o->record_log = 0;
   o->se_target = 0;
   o->walks_max = 65536;
@@ -1088,11 +1088,11 @@ extern "C" void msk_tune_space_default(msk_tune_space* sp) {
   if (!sp) return;
   std::memset(sp, 0, sizeof(*sp));
   sp->n_leaf = 3;
-  sp->leaf[0] = 1; sp->leaf[1] = 2; sp->leaf[2] = 4;
+  sp->leaf[0] = 2; sp->leaf[1] = 4; sp->leaf[2] = 8;
   sp->n_chunk = 3;
   sp->chunk[0] = 32; sp->chunk[1] = 64; sp->chunk[2] = 128;
   sp->n_regen = 3;
-  sp->regen_min[0] = 1; sp->regen_min[1] = 16; sp->regen_min[2] = 32;
+  sp->regen_min[0] = 24; sp->regen_min[1] = 40; sp->regen_min[2] = 48;
   sp->n_bpc = 2;
   sp->blocks_per_cu[0] = 4; sp->blocks_per_cu[1] = 8;
   sp->trial_rows = 16384;

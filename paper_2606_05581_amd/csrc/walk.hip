@@ -323,7 +323,10 @@ __host__ __device__ void bvh_nearest(const Node4* __restrict__ nodes, const TriR
 // (squared distance, original index) goes to its owner through a 64-bit LDS
 // atomic minimum, which realises the lexicographic order exactly; the task
 // that holds the minimum writes its barycentrics for the owner.
-constexpr int kCoopTasks = 256;
+#ifndef MSK_COOP_TASKS
+#define MSK_COOP_TASKS 256
+#endif
+constexpr int kCoopTasks = MSK_COOP_TASKS;
 struct CoopScratch {
   int32_t task_slot[kCoopTasks];
   uint8_t task_owner[kCoopTasks];
@@ -686,11 +689,11 @@ __device__ void walk_finish_global(const WalkLaunch& L, const MeshDev& M, const 
 // the partial sums in FP64; AccT = float keeps them in FP32 (a chunk holds at
 // most `chunk` walks) and flushes them into the FP64 rows.
 // Row-table slots per wavefront table (2^bits) and the occupancy the
-// persistent kernel is compiled for: with 64 slots, the cooperative leaf
-// scratch and 21 LDS-staged top nodes a workgroup holds 30.5 KB of LDS, so
-// 5 workgroups fit a CU; 5 waves per SIMD (<= 96 VGPRs, spills outside the
-// traversal loop) measured fastest on gfx950 against 3, 4, 6 and 8, and
-// 128 slots or 85 staged nodes gained nothing that paid for lower occupancy.
+// persistent kernels are compiled for: with 64 slots, the cooperative leaf
+// scratch and 21 LDS-staged top nodes a workgroup holds 30.5 KB of LDS.
+// The streaming kernel measured fastest on gfx950 at 4 waves per SIMD (128
+// VGPRs, few spills) against 3 (no spills) and 5, 6 (many spills); 32-slot
+// tables lost to their extra device atomics and 128 slots gained nothing.
 #ifndef MSK_TABLE_SLOT_BITS
 #define MSK_TABLE_SLOT_BITS 6
 #endif
@@ -890,7 +893,7 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 // top BVH nodes staged in LDS by the persistent kernel (at most kMaxTop)
 constexpr int kLdsTop = MSK_LDS_TOP_NODES < kMaxTop ? MSK_LDS_TOP_NODES : kMaxTop;
 #ifndef MSK_PERSISTENT_WAVES_PER_EU
-#define MSK_PERSISTENT_WAVES_PER_EU 5
+#define MSK_PERSISTENT_WAVES_PER_EU 4
 #endif
 #if MSK_PERSISTENT_WAVES_PER_EU > 0
 #define MSK_PERSISTENT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MSK_PERSISTENT_WAVES_PER_EU)))
@@ -1055,6 +1058,318 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_persistent_
   }
 }
 
+// Streaming form of the persistent kernel: every loop trip advances each
+// traversing lane by one BVH node (its leaf triangles tested by the whole
+// wavefront), so a lane whose query is long does not hold the others: lanes
+// whose query is answered wait until enough of them do (L.regen_min), then
+// finish their step, start the next one or take a new walk together. The
+// walks, their queries and their results are those of the other forms.
+#ifndef MSK_STREAM
+#define MSK_STREAM 1
+#endif
+template <bool kStats, typename AccT>
+__global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kernel(WalkLaunch L) {
+  __shared__ Node4 top[kLdsTop > 0 ? kLdsTop : 1];
+  __shared__ WaveTables<AccT> T;
+  __shared__ CoopScratch coop[kWaves];
+  const int wi = threadIdx.x >> 6;
+  CoopScratch* W = &coop[wi];
+  for (int i = threadIdx.x; i < kWaves * 2 * kSlots; i += blockDim.x) {
+    (&T.key[0][0][0])[i] = kEmptyKey;
+    (&T.v1[0][0][0])[i] = (AccT)0;
+    (&T.v2[0][0][0])[i] = (AccT)0;
+  }
+  for (int i = threadIdx.x; i < kWaves * 2 * 3; i += blockDim.x) (&T.cnt[0][0][0])[i] = 0;
+  int32_t n_lds = 0;
+  if (L.use_lds_top) {
+    n_lds = min(L.n_top, kLdsTop);
+    const int4* src = (const int4*)L.meshes[0].nodes;
+    int4* dst = (int4*)top;
+    for (int i = threadIdx.x; i < n_lds * 8; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  const uint32_t lane = __lane_id();
+  const int qhome = blockIdx.x & 7;
+  int qi = 0;  // queues tried so far (uniform)
+  uint64_t cur = 0, cend = 0;
+  // wave-uniform table bookkeeping
+  int32_t t_used[2] = {0, 0}, t_mesh[2] = {0, 0}, t_row[2] = {0, 0}, t_out[2] = {0, 0};
+  int32_t c_tab = -1, c_mesh = -1, c_row = -1;  // current chunk's row and table
+  LaneWalk w;
+  w.active = 0;
+  w.tab = -1;
+  Nearest hit;
+  hit.d2 = INFINITY;
+  hit.orig = INT_MAX;
+  hit.slot = -1;
+  hit.l1 = hit.l2 = 0.0f;
+  // lane's query: mode 0 no walk, 1 traversing, 2 answered (hit holds it)
+  int32_t mode = 0, node = -1, sp = 0, warm = -1;
+  float thr = INFINITY, slack = 0.0f;
+  bool capped = false;
+  StackEntry stk[kStackDepth];
+  bool drained = false;
+  auto start_query = [&](const MeshDev& M) {
+    hit.d2 = INFINITY;
+    hit.orig = INT_MAX;
+    hit.slot = -1;
+    warm = w.slot;
+    node = 0;
+    sp = 0;
+    thr = INFINITY;
+    slack = 0x1p-18f * (M.radius + fmaxf(fabsf(w.x), fmaxf(fabsf(w.y), fabsf(w.z))));
+    mode = 1;
+  };
+  while (true) {
+    // ---- bookkeeping, when enough lanes wait or none traverses: lanes whose
+    // query is answered finish their step and start the next one, or record
+    // their ended walk; idle lanes take new walks
+    const uint64_t trav = __ballot(mode == 1);
+    if (trav == 0 || (int)__popcll(~trav) >= L.regen_min) {
+      bool fin = false;
+      int32_t fin_tab = -1;
+      if (mode == 2) {
+        const MeshDev& M = L.meshes[w.mesh];
+        int32_t st = walk_end(M, w, capped, hit);
+        if (st < 0) {
+          st = walk_begin(L, M, w, capped);
+          if (st < 0) start_query(M);
+        }
+        if (st >= 0) {
+          if (w.tab >= 0)
+            walk_finish_table(L, M, w, st, hit, T, wi);
+          else
+            walk_finish_global(L, M, w, st, hit);
+          fin = true;
+          fin_tab = w.tab;
+          w.active = 0;
+          w.tab = -1;
+          mode = 0;
+        }
+      }
+      for (int t = 0; t < 2; ++t) {
+        t_out[t] -= (int32_t)__popcll(__ballot(fin && fin_tab == t));
+        // flush once the table's walks are done and its chunk hands out no more
+        if (t_used[t] && t_out[t] == 0 && !(t == c_tab && cur < cend)) {
+          table_flush(L, T, wi, t, t_mesh[t], t_row[t]);
+          t_used[t] = 0;
+          if (c_tab == t) c_tab = -1;
+        }
+      }
+      // refill idle lanes from the queue chunks
+      uint64_t idle = __ballot(!w.active);
+      while (idle != 0 && !drained) {
+        if (cur >= cend) {
+          uint64_t start = 0;
+          if (lane == 0) {
+            const int q = (qhome + qi) & 7;
+            start = atomicAdd(L.queue_next + q, (unsigned long long)L.chunk);
+          }
+          start = (uint64_t)__shfl((unsigned long long)start, 0);
+          const int q = (qhome + qi) & 7;
+          const uint64_t qend = L.queue_end[q];
+          if (start >= qend) {
+            ++qi;
+            if (qi >= 8) drained = true;
+            continue;
+          }
+          cur = start;
+          cend = min(start + (uint64_t)L.chunk, qend);
+          // the chunk's row takes the table it already has, else a free one
+          const RowSlot rs = L.slots[start / (uint64_t)L.walks_per_slot];
+          c_mesh = rs.mesh;
+          c_row = rs.row;
+          c_tab = -1;
+          for (int t = 0; t < 2; ++t)
+            if (t_used[t] && t_mesh[t] == c_mesh && t_row[t] == c_row) c_tab = t;
+          if (c_tab < 0) {
+            for (int t = 0; t < 2; ++t)
+              if (!t_used[t] && c_tab < 0) {
+                c_tab = t;
+                t_used[t] = 1;
+                t_mesh[t] = c_mesh;
+                t_row[t] = c_row;
+              }
+          }
+        }
+        const uint32_t rank = __popcll(idle & ((1ull << lane) - 1ull));
+        const uint64_t avail = cend - cur;
+        const uint32_t take = (uint32_t)min(avail, (uint64_t)__popcll(idle));
+        bool fresh = false;
+        if (!w.active && rank < take) {
+          decode_walk(L, cur + rank, w);
+          int32_t face;
+          double lam[3];
+          const MeshDev& M = L.meshes[w.mesh];
+          w.active = walk_start(L, M, w, face, lam) ? 1 : 0;
+          w.tab = (w.active && c_tab >= 0 && w.mesh == c_mesh && w.row == c_row) ? c_tab : -1;
+          if (w.active) {
+            const int32_t s0 = walk_begin(L, M, w, capped);
+            if (s0 < 0) {
+              start_query(M);
+              fresh = w.tab >= 0;
+            } else {  // left the bounding sphere at once and escaped
+              if (w.tab >= 0)
+                walk_finish_table(L, M, w, s0, hit, T, wi);
+              else
+                walk_finish_global(L, M, w, s0, hit);
+              w.active = 0;
+              w.tab = -1;
+            }
+          }
+        }
+        if (c_tab >= 0) t_out[c_tab] += (int32_t)__popcll(__ballot(fresh));
+        cur += take;
+        idle = __ballot(!w.active);
+        // lanes whose row was discarded, or whose walk ended at once, stay idle
+      }
+      if (__ballot(w.active) == 0) {
+        if (drained) {
+          for (int t = 0; t < 2; ++t)
+            if (t_used[t]) {
+              table_flush(L, T, wi, t, t_mesh[t], t_row[t]);
+              t_used[t] = 0;
+            }
+          break;
+        }
+        continue;
+      }
+    }
+    if (__ballot(mode == 1) == 0) continue;
+    // ---- one node of every traversing lane
+    const bool tr = mode == 1;
+    float lb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int32_t cc[4] = {-1, -1, -1, -1}, cn[4] = {0, 0, 0, 0};
+    const MeshDev& Mq = L.meshes[tr ? w.mesh : 0];
+    if (tr) {
+      const int32_t nl = w.mesh == 0 ? n_lds : 0;
+      float4 lox, loy, loz, hix, hiy, hiz;
+      int4 ch, ct;
+      if (kStats) {
+        ++w.cnt.nodes;
+        w.cnt.flops += 4 * kBoxFlops;
+      }
+      if (node < nl) {
+        const float4* N = (const float4*)&top[node];
+        lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
+        ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
+      } else {
+        const float4* N = (const float4*)&Mq.nodes[node];
+        lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
+        ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
+      }
+      const float lx[4] = {lox.x, lox.y, lox.z, lox.w}, ly[4] = {loy.x, loy.y, loy.z, loy.w},
+                  lz[4] = {loz.x, loz.y, loz.z, loz.w};
+      const float hx[4] = {hix.x, hix.y, hix.z, hix.w}, hy[4] = {hiy.x, hiy.y, hiy.z, hiy.w},
+                  hz[4] = {hiz.x, hiz.y, hiz.z, hiz.w};
+      const int32_t c4[4] = {ch.x, ch.y, ch.z, ch.w}, n4[4] = {ct.x, ct.y, ct.z, ct.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float gx = fmaxf(fmaxf(lx[k] - w.x, w.x - hx[k]), 0.0f);
+        const float gy = fmaxf(fmaxf(ly[k] - w.y, w.y - hy[k]), 0.0f);
+        const float gz = fmaxf(fmaxf(lz[k] - w.z, w.z - hz[k]), 0.0f);
+        lb[k] = gx * gx + gy * gy + gz * gz;
+        cc[k] = c4[k];
+        cn[k] = n4[k];
+      }
+#define MSK_CX(i, j)                                                        \
+  if (lb[j] < lb[i]) {                                                      \
+    float tl = lb[i]; lb[i] = lb[j]; lb[j] = tl;                            \
+    int32_t tc = cc[i]; cc[i] = cc[j]; cc[j] = tc;                          \
+    int32_t tn = cn[i]; cn[i] = cn[j]; cn[j] = tn;                          \
+  }
+      MSK_CX(0, 1) MSK_CX(2, 3) MSK_CX(0, 2) MSK_CX(1, 3) MSK_CX(1, 2)
+#undef MSK_CX
+    }
+    // this lane's triangles: the warm-start candidate of a new query, then
+    // the leaf children within the bound
+    const int32_t hw = (tr && warm >= 0) ? 1 : 0;
+    int32_t nl4[4], tot = hw;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      nl4[k] = (tr && cc[k] < 0 && cn[k] > 0 && lb[k] <= thr) ? cn[k] : 0;
+      tot += nl4[k];
+    }
+    if (__ballot(tot > 0) != 0) {
+      W->pt[lane] = make_float4(w.x, w.y, w.z, hit.d2);
+      W->key[lane] = ((unsigned long long)__float_as_uint(hit.d2) << 32) | (uint32_t)hit.orig;
+      W->tris[lane] = Mq.tris;
+      if (kStats) W->flops[lane] = 0;
+      uint32_t ntask = 0;
+      for (int32_t j = 0;; ++j) {
+        const uint64_t m = __ballot(j < tot);
+        if (ntask > 0 && (m == 0 || ntask + (uint32_t)__popcll(m) > (uint32_t)kCoopTasks)) {
+          coop_leaf_round<kStats>(W, lane, ntask);
+          ntask = 0;
+        }
+        if (m == 0) break;
+        if (j < tot) {
+          int32_t slot;
+          if (j < hw) {
+            slot = warm;
+          } else {
+            const int32_t jj = j - hw;
+            const int32_t e1 = nl4[0], e2 = e1 + nl4[1], e3 = e2 + nl4[2];
+            const int k = (jj >= e1) + (jj >= e2) + (jj >= e3);
+            const int32_t base = k == 0 ? 0 : (k == 1 ? e1 : (k == 2 ? e2 : e3));
+            const int32_t c = k == 0 ? cc[0] : (k == 1 ? cc[1] : (k == 2 ? cc[2] : cc[3]));
+            slot = -c - 1 + (jj - base);
+          }
+          const uint32_t pos = ntask + mbcnt64(m);
+          W->task_slot[pos] = slot;
+          W->task_owner[pos] = (uint8_t)lane;
+        }
+        ntask += (uint32_t)__popcll(m);
+      }
+      if (tot > 0) {
+        if (kStats) {
+          w.cnt.tris += (uint32_t)tot;
+          w.cnt.flops += W->flops[lane];
+        }
+        const unsigned long long k2 = W->key[lane];
+        const float d = __uint_as_float((uint32_t)(k2 >> 32));
+        const int32_t orig = (int32_t)(uint32_t)k2;
+        if (d < hit.d2 || (d == hit.d2 && orig < hit.orig)) {
+          hit.d2 = d;
+          hit.orig = orig;
+          hit.slot = W->rec_slot[lane];
+          hit.l1 = W->rec_l1[lane];
+          hit.l2 = W->rec_l2[lane];
+          thr = prune_bound(hit.d2, slack);
+        }
+      }
+    }
+    if (tr) {
+      warm = -1;
+      // the nearest surviving inner child is next; the others are pushed
+      // farthest first; the query is answered when the stack runs out
+      int32_t next = -1;
+      float next_lb = 0.0f;
+#pragma unroll
+      for (int k = 3; k >= 0; --k) {
+        if (cc[k] >= 0 && lb[k] <= thr) {
+          if (next >= 0 && sp < kStackDepth) stk[sp++] = StackEntry{next, next_lb};
+          next = cc[k];
+          next_lb = lb[k];
+        }
+      }
+      if (next >= 0) {
+        node = next;
+      } else {
+        node = -1;
+        while (sp > 0) {
+          --sp;
+          if (stk[sp].lb <= thr) {
+            node = stk[sp].node;
+            break;
+          }
+        }
+        if (node < 0) mode = 2;
+      }
+    }
+  }
+}
+
 __global__ void init_queues_kernel(unsigned long long* next, unsigned long long* end, QueueInit q) {
   const int i = threadIdx.x;
   if (i < 8) {
@@ -1167,17 +1482,22 @@ hipError_t launch_walk_plain(const WalkLaunch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
+#if MSK_STREAM
+#define MSK_PERSISTENT_KERNEL walk_stream_kernel
+#else
+#define MSK_PERSISTENT_KERNEL walk_persistent_kernel
+#endif
 hipError_t launch_walk_persistent(const WalkLaunch& L, int grid, hipStream_t s) {
   if (L.accum_f32) {
     if (L.stats)
-      hipLaunchKernelGGL((walk_persistent_kernel<true, float>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((MSK_PERSISTENT_KERNEL<true, float>), dim3(grid), dim3(256), 0, s, L);
     else
-      hipLaunchKernelGGL((walk_persistent_kernel<false, float>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((MSK_PERSISTENT_KERNEL<false, float>), dim3(grid), dim3(256), 0, s, L);
   } else {
     if (L.stats)
-      hipLaunchKernelGGL((walk_persistent_kernel<true, double>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((MSK_PERSISTENT_KERNEL<true, double>), dim3(grid), dim3(256), 0, s, L);
     else
-      hipLaunchKernelGGL((walk_persistent_kernel<false, double>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((MSK_PERSISTENT_KERNEL<false, double>), dim3(grid), dim3(256), 0, s, L);
   }
   return hipGetLastError();
 }

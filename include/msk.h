@@ -282,8 +282,8 @@ typedef struct {
   int32_t n_chunk, chunk[4];          /* walks a wavefront takes per queue grab */
   int32_t n_regen, regen_min[4];      /* waiting lanes that trigger bookkeeping */
   int32_t n_bpc, blocks_per_cu[4];    /* persistent workgroups per CU          */
-  int64_t trial_rows;                 /* rows sampled over all meshes (16384)  */
-  int64_t trial_walks;                /* walks per sampled row (128)           */
+  int64_t trial_rows;                 /* rows sampled over all meshes (65536)  */
+  int64_t trial_walks;                /* walks per sampled row (256)           */
   int32_t repeats;                    /* timed repeats per candidate, min (2)  */
   const char* cache_path;             /* JSON-lines cache file, or NULL        */
 } msk_tune_space;

@@ -1095,8 +1095,8 @@ extern "C" void msk_tune_space_default(msk_tune_space* sp) {
   sp->regen_min[0] = 24; sp->regen_min[1] = 40; sp->regen_min[2] = 48;
   sp->n_bpc = 2;
   sp->blocks_per_cu[0] = 4; sp->blocks_per_cu[1] = 8;
-  sp->trial_rows = 16384;
-  sp->trial_walks = 128;
+  sp->trial_rows = 65536;
+  sp->trial_walks = 256;
   sp->repeats = 2;
   sp->cache_path = nullptr;
 }

@@ -131,10 +131,14 @@ def cpu_baseline(wl, target_s, max_threads=16, max_meshes=8):
                 walks += int((r["discarded"] == 0).sum()) * wl.walks
         return walks, time.perf_counter() - t0
 
-    w0, t0 = run(max(1, threads // len(scenes)))
-    rate = w0 / max(t0, 1e-9)
-    per_mesh = int(max(1, target_s * rate / (wl.walks * len(modes) * len(scenes))))
+    per_mesh = max(1, threads // len(scenes))
     walks, dt = run(per_mesh)
+    # grow the sample until it takes about target_s (or covers every row)
+    while dt < 0.5 * target_s and per_mesh < max(c.rows.n_rows for _, c, _ in scenes):
+        rate = walks / max(dt, 1e-9)
+        per_mesh = int(min(max(2 * per_mesh, target_s * rate / (wl.walks * len(modes) * len(scenes))),
+                           max(c.rows.n_rows for _, c, _ in scenes)))
+        walks, dt = run(per_mesh)
     rows = sum(min(per_mesh, c.rows.n_rows) for _, c, _ in scenes)
     return {"value": walks / dt, "unit": "walks/s", "cores": threads, "kind": "oracle",
             "sample": f"{rows} rows (evenly spaced, {len(scenes)} of {len(wl.cases)} meshes) x {wl.walks} walks x "

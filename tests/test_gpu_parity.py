@@ -41,6 +41,12 @@ def _tiny_meshes():
     out.append(("icosphere320", V, F))
     V, F = W.icosphere_recursive(4)
     out.append(("icosphere5120", V * np.array([1.0, 0.6, 0.3]), F))
+    # a cube with zero-area triangles: a segment, a point, a doubled-vertex segment
+    V, F = W.box_grid(1)
+    nv = V.shape[0]
+    V = np.concatenate([V, [[0.2, 0.3, 0.4], [0.6, 0.9, 1.2], [1.0, 1.5, 2.0], [0.1, 0.1, 0.1]]], 0)
+    F = np.concatenate([F, [[nv, nv + 1, nv + 2], [nv + 3, nv + 3, nv + 3], [nv, nv, nv + 1]]], 0)
+    out.append(("degenerate", V, F))
     return out
 
 
@@ -58,7 +64,7 @@ def _queries(V, F, rng, n_random=2000):
     return np.concatenate(pts, 0)
 
 
-@pytest.mark.parametrize("name", ["tetrahedron", "cube", "icosphere320", "icosphere5120", "soup"])
+@pytest.mark.parametrize("name", ["tetrahedron", "cube", "degenerate", "icosphere320", "icosphere5120", "soup"])
 def test_closest_points_bit_exact(ctx, oracle_mod, name):
     import torch
 

@@ -90,7 +90,7 @@ typedef struct {
  * Coordinates are re-expressed as float offsets from the bounding-box centre
  * (computed in FP64). A 4-wide BVH (binned surface-area heuristic) is built
  * on the host and uploaded. Errors: INVALID_ARG for NaN/Inf coordinates,
- * out-of-range indices, n_tris < 1 or zero total area; zero-area triangles
+ * out-of-range indices, n_tris < 1 or >= 2^26, or zero total area; zero-area triangles
  * are kept (they still absorb walks). Free with msk_mesh_destroy. */
 msk_status msk_build_bvh(msk_ctx* ctx, const float* V, int64_t n_verts, const int32_t* F, int64_t n_tris,
                          const msk_bvh_opts* opts /* NULL = defaults */, msk_mesh** out);

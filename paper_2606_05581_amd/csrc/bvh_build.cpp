@@ -157,7 +157,8 @@ struct Builder {
 
 std::string build_bvh_host(const float* V, int64_t nv, const int32_t* F, int64_t nf, int leaf_size, HostBvh& out) {
   if (nv < 3 || nf < 1) return "mesh needs at least 3 vertices and 1 triangle";
-  if (nf > (int64_t)1 << 30) return "too many triangles";
+  // the walk kernel packs a triangle slot and a lane into one 32-bit word
+  if (nf >= (int64_t)1 << 26) return "too many triangles (a mesh holds at most 2^26 - 1)";
   if (leaf_size < 1 || leaf_size > 8) return "leaf_size must be in 1..8";
   out.leaf_size = leaf_size;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};

@@ -315,24 +315,24 @@ __host__ __device__ void bvh_nearest(const Node4* __restrict__ nodes, const TriR
   }
 }
 
-// Wavefront-cooperative form of bvh_nearest (same result, bit for bit). All
-// 64 lanes call it together; lanes with has == false only help. Each lane
-// walks its own nodes as above, but the triangles of the leaves it reaches
-// are listed in LDS and tested 64 at a time by the whole wavefront, so the
-// long triangle test runs with most lanes busy instead of a few. A task's
-// (squared distance, original index) goes to its owner through a 64-bit LDS
-// atomic minimum, which realises the lexicographic order exactly; the task
-// that holds the minimum writes its barycentrics for the owner.
-#ifndef MSK_COOP_TASKS
-#define MSK_COOP_TASKS 256
-#endif
-constexpr int kCoopTasks = MSK_COOP_TASKS;
+// Wavefront-cooperative leaf tests (same result as the lane-private
+// bvh_nearest, bit for bit). All 64 lanes take part; each lane walks its own
+// nodes, but the triangles of the leaves it reaches are listed in LDS and
+// tested 64 at a time by the whole wavefront, so the long triangle test runs
+// with most lanes busy instead of a few. A task's (squared distance, original
+// index) goes to its owner through a 64-bit LDS atomic minimum, which
+// realises the lexicographic order exactly; the task that holds the minimum
+// writes its barycentrics for the owner. Work is listed in units of up to 4
+// consecutive triangle slots of one owner (one word: first slot << 6 | owner
+// lane, so meshes have fewer than 2^26 triangles); 4 lanes take a unit.
+constexpr int kCoopUnits = 64;  // units per listing window (4 passes of 64 lanes)
 struct CoopScratch {
-  int32_t task_slot[kCoopTasks];
-  uint8_t task_owner[kCoopTasks];
+  uint32_t unit[kCoopUnits];
+  uint8_t ucnt[kCoopUnits];
   unsigned long long key[64];
   float4 pt[64];           // owner's query point and early-reject bound
-  const TriRec* tris[64];  // owner's triangle array (batched meshes differ per lane)
+  const TriRec* tris[64];  // lane's triangle array (batched meshes differ per lane)
+  const Node4* nodes[64];  // lane's node array
   int32_t rec_slot[64];
   float rec_l1[64], rec_l2[64];
   uint32_t flops[64];  // statistics kernels only
@@ -342,13 +342,34 @@ __device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Orders LDS accesses of a wavefront as written: the hardware executes one
+// wavefront's LDS instructions in issue order, so only the compiler must
+// not move them (a fence would also wait for all outstanding global and
+// scratch accesses).
+__device__ __forceinline__ void lds_order() { __asm__ __volatile__("" ::: "memory"); }
+
+// Exclusive prefix sum over the wavefront of a count below 64 (bit-sliced
+// ballots); `total` receives the wavefront's sum.
+__device__ __forceinline__ uint32_t wave_prefix_small(uint32_t v, uint32_t& total) {
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    const uint64_t m = __ballot((v >> b) & 1u);
+    pre += mbcnt64(m) << b;
+    tot += (uint32_t)__popcll(m) << b;
+  }
+  total = tot;
+  return pre;
+}
+
 template <bool kStats>
-__device__ void coop_leaf_round(CoopScratch* W, uint32_t lane, uint32_t ntask) {
-  for (uint32_t t0 = 0; t0 < ntask; t0 += 64) {
-    const uint32_t t = t0 + lane;
-    if (t < ntask) {
-      const int32_t s = W->task_slot[t];
-      const uint32_t o = W->task_owner[t];
+__device__ void coop_unit_round(CoopScratch* W, uint32_t lane, uint32_t nunit) {
+  for (uint32_t u0 = 0; u0 < nunit; u0 += 16) {
+    const uint32_t u = u0 + (lane >> 2), off = lane & 3u;
+    if (u < nunit && off < (uint32_t)W->ucnt[u]) {
+      const uint32_t pk = W->unit[u];
+      const int32_t s = (int32_t)(pk >> 6) + (int32_t)off;
+      const uint32_t o = pk & 63u;
       const float4 q = W->pt[o];
       const TriRec T = W->tris[o][s];
       float l1 = 0.0f, l2 = 0.0f, den = 1.0f;
@@ -360,7 +381,7 @@ __device__ void coop_leaf_round(CoopScratch* W, uint32_t lane, uint32_t ntask) {
         memcpy(&orig, &T.a.w, 4);
         const unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (uint32_t)orig;
         atomicMin(&W->key[o], key);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        lds_order();
         if (W->key[o] == key) {
           if (region == 6) {
             l1 = l1 / den;
@@ -372,146 +393,10 @@ __device__ void coop_leaf_round(CoopScratch* W, uint32_t lane, uint32_t ntask) {
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    lds_order();
   }
 }
 
-template <bool kStats>
-__device__ void bvh_nearest_coop(const Node4* __restrict__ nodes, const TriRec* __restrict__ tris, const Node4* lds,
-                                 int32_t n_lds, float px, float py, float pz, float radius, Nearest& h,
-                                 TravCount& cnt, bool has, CoopScratch* W) {
-  const uint32_t lane = __lane_id();
-  const float slack = 0x1p-18f * (radius + fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
-  if (has && h.slot >= 0) {
-    const int32_t s = h.slot;
-    h.d2 = INFINITY;
-    h.orig = INT_MAX;
-    h.slot = -1;
-    test_tri<kStats>(tris, s, px, py, pz, h, cnt);
-  }
-  float thr = prune_bound(h.d2, slack);
-  StackEntry stk[kStackDepth];
-  int sp = 0;
-  int32_t node = has ? 0 : -1;
-  W->tris[lane] = tris;
-  while (__ballot(node >= 0) != 0) {
-    float lb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    int32_t cc[4] = {-1, -1, -1, -1}, cn[4] = {0, 0, 0, 0};
-    if (node >= 0) {
-      float4 lox, loy, loz, hix, hiy, hiz;
-      int4 ch, ct;
-      if (kStats) {
-        ++cnt.nodes;
-        cnt.flops += 4 * kBoxFlops;
-      }
-      if (node < n_lds) {
-        const float4* N = (const float4*)&lds[node];
-        lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
-        ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
-      } else {
-        const float4* N = (const float4*)&nodes[node];
-        lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
-        ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
-      }
-      const float lx[4] = {lox.x, lox.y, lox.z, lox.w}, ly[4] = {loy.x, loy.y, loy.z, loy.w},
-                  lz[4] = {loz.x, loz.y, loz.z, loz.w};
-      const float hx[4] = {hix.x, hix.y, hix.z, hix.w}, hy[4] = {hiy.x, hiy.y, hiy.z, hiy.w},
-                  hz[4] = {hiz.x, hiz.y, hiz.z, hiz.w};
-      const int32_t c4[4] = {ch.x, ch.y, ch.z, ch.w}, n4[4] = {ct.x, ct.y, ct.z, ct.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float gx = fmaxf(fmaxf(lx[k] - px, px - hx[k]), 0.0f);
-        const float gy = fmaxf(fmaxf(ly[k] - py, py - hy[k]), 0.0f);
-        const float gz = fmaxf(fmaxf(lz[k] - pz, pz - hz[k]), 0.0f);
-        lb[k] = gx * gx + gy * gy + gz * gz;
-        cc[k] = c4[k];
-        cn[k] = n4[k];
-      }
-#define MSK_CX(i, j)                                                        \
-  if (lb[j] < lb[i]) {                                                      \
-    float tl = lb[i]; lb[i] = lb[j]; lb[j] = tl;                            \
-    int32_t tc = cc[i]; cc[i] = cc[j]; cc[j] = tc;                          \
-    int32_t tn = cn[i]; cn[i] = cn[j]; cn[j] = tn;                          \
-  }
-      MSK_CX(0, 1) MSK_CX(2, 3) MSK_CX(0, 2) MSK_CX(1, 3) MSK_CX(1, 2)
-#undef MSK_CX
-    }
-    // this lane's leaf triangles within the bound, as one list
-    int32_t nl[4], tot = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      nl[k] = (node >= 0 && cc[k] < 0 && cn[k] > 0 && lb[k] <= thr) ? cn[k] : 0;
-      tot += nl[k];
-    }
-    if (__ballot(tot > 0) != 0) {
-      W->pt[lane] = make_float4(px, py, pz, h.d2);
-      W->key[lane] = ((unsigned long long)__float_as_uint(h.d2) << 32) | (uint32_t)h.orig;
-      if (kStats) W->flops[lane] = 0;
-      uint32_t ntask = 0;
-      for (int32_t j = 0;; ++j) {
-        const uint64_t m = __ballot(j < tot);
-        if (ntask > 0 && (m == 0 || ntask + (uint32_t)__popcll(m) > (uint32_t)kCoopTasks)) {
-          coop_leaf_round<kStats>(W, lane, ntask);
-          ntask = 0;
-        }
-        if (m == 0) break;
-        if (j < tot) {
-          const int32_t e1 = nl[0], e2 = e1 + nl[1], e3 = e2 + nl[2];
-          const int k = (j >= e1) + (j >= e2) + (j >= e3);
-          const int32_t base = k == 0 ? 0 : (k == 1 ? e1 : (k == 2 ? e2 : e3));
-          const int32_t c = k == 0 ? cc[0] : (k == 1 ? cc[1] : (k == 2 ? cc[2] : cc[3]));
-          const uint32_t pos = ntask + mbcnt64(m);
-          W->task_slot[pos] = -c - 1 + (j - base);
-          W->task_owner[pos] = (uint8_t)lane;
-        }
-        ntask += (uint32_t)__popcll(m);
-      }
-      if (tot > 0) {
-        if (kStats) {
-          cnt.tris += (uint32_t)tot;
-          cnt.flops += W->flops[lane];
-        }
-        const unsigned long long k2 = W->key[lane];
-        const float d = __uint_as_float((uint32_t)(k2 >> 32));
-        const int32_t orig = (int32_t)(uint32_t)k2;
-        if (d < h.d2 || (d == h.d2 && orig < h.orig)) {
-          h.d2 = d;
-          h.orig = orig;
-          h.slot = W->rec_slot[lane];
-          h.l1 = W->rec_l1[lane];
-          h.l2 = W->rec_l2[lane];
-          thr = prune_bound(h.d2, slack);
-        }
-      }
-    }
-    if (node >= 0) {
-      // the nearest surviving inner child is next; the others are pushed
-      // farthest first
-      int32_t next = -1;
-      float next_lb = 0.0f;
-#pragma unroll
-      for (int k = 3; k >= 0; --k) {
-        if (cc[k] >= 0 && lb[k] <= thr) {
-          if (next >= 0 && sp < kStackDepth) stk[sp++] = StackEntry{next, next_lb};
-          next = cc[k];
-          next_lb = lb[k];
-        }
-      }
-      if (next >= 0) {
-        node = next;
-      } else {
-        node = -1;
-        while (sp > 0) {
-          --sp;
-          if (stk[sp].lb <= thr) {
-            node = stk[sp].node;
-            break;
-          }
-        }
-      }
-    }
-  }
-}
 
 // ------------------------------------------------------ walk machinery
 
@@ -886,10 +771,6 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 #ifndef MSK_LDS_TOP_NODES
 #define MSK_LDS_TOP_NODES 21
 #endif
-// leaf triangles tested by the whole wavefront (bvh_nearest_coop)
-#ifndef MSK_COOP_LEAVES
-#define MSK_COOP_LEAVES 1
-#endif
 // top BVH nodes staged in LDS by the persistent kernel (at most kMaxTop)
 constexpr int kLdsTop = MSK_LDS_TOP_NODES < kMaxTop ? MSK_LDS_TOP_NODES : kMaxTop;
 #ifndef MSK_PERSISTENT_WAVES_PER_EU
@@ -900,163 +781,25 @@ constexpr int kLdsTop = MSK_LDS_TOP_NODES < kMaxTop ? MSK_LDS_TOP_NODES : kMaxTo
 #else
 #define MSK_PERSISTENT_OCCUPANCY
 #endif
-// Persistent form: each wavefront keeps its 64 lanes busy by refilling
-// finished lanes with the next walks of its queue chunk; chunks come from
-// one of eight queues (one per XCD, blockIdx % 8) and wavefronts move on to
-// the other queues once their own is drained. Finished walks go into the
-// wavefront's row tables (see WaveTables).
-template <bool kStats, typename AccT>
-__global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_persistent_kernel(WalkLaunch L) {
-  __shared__ Node4 top[kLdsTop > 0 ? kLdsTop : 1];
-  __shared__ WaveTables<AccT> T;
-#if MSK_COOP_LEAVES
-  __shared__ CoopScratch coop[kWaves];
+// Optional per-phase cycle counts of the streaming kernel (a measurement
+// build only: -DMSK_PHASE_TIMING=1); phases are timed by the wavefront's
+// shader clock at points every lane passes together.
+// lanes with an answered query that trigger the step continuation
+#ifndef MSK_STEP_MIN
+#define MSK_STEP_MIN 16
 #endif
-  const int wi = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < kWaves * 2 * kSlots; i += blockDim.x) {
-    (&T.key[0][0][0])[i] = kEmptyKey;
-    (&T.v1[0][0][0])[i] = (AccT)0;
-    (&T.v2[0][0][0])[i] = (AccT)0;
-  }
-  for (int i = threadIdx.x; i < kWaves * 2 * 3; i += blockDim.x) (&T.cnt[0][0][0])[i] = 0;
-  int32_t n_lds = 0;
-  if (L.use_lds_top) {
-    n_lds = min(L.n_top, kLdsTop);
-    const MeshDev& M0 = L.meshes[0];
-    const int4* src = (const int4*)M0.nodes;
-    int4* dst = (int4*)top;
-    for (int i = threadIdx.x; i < n_lds * 8; i += blockDim.x) dst[i] = src[i];
-  }
-  __syncthreads();
-  const int qhome = blockIdx.x & 7;
-  int qi = 0;  // queues tried so far (uniform)
-  uint64_t cur = 0, cend = 0;
-  // wave-uniform table bookkeeping
-  int32_t t_used[2] = {0, 0}, t_mesh[2] = {0, 0}, t_row[2] = {0, 0}, t_out[2] = {0, 0};
-  int32_t c_tab = -1, c_mesh = -1, c_row = -1;  // current chunk's row and table
-  LaneWalk w;
-  w.active = 0;
-  w.tab = -1;
-  Nearest hit;
-  bool drained = false;
-  while (true) {
-    // ---- refill idle lanes (wave-uniform control)
-    uint64_t idle = __ballot(!w.active);
-    if (!drained && idle != 0 && (int)__popcll(idle) >= L.regen_min) {
-      while (idle != 0 && !drained) {
-        if (cur >= cend) {
-          uint64_t start = 0;
-          if (__lane_id() == 0) {
-            const int q = (qhome + qi) & 7;
-            start = atomicAdd(L.queue_next + q, (unsigned long long)L.chunk);
-          }
-          start = (uint64_t)__shfl((unsigned long long)start, 0);
-          const int q = (qhome + qi) & 7;
-          const uint64_t qend = L.queue_end[q];
-          if (start >= qend) {
-            ++qi;
-            if (qi >= 8) drained = true;
-            continue;
-          }
-          cur = start;
-          cend = min(start + (uint64_t)L.chunk, qend);
-          // the chunk's row takes the table it already has, else a free one
-          const RowSlot rs = L.slots[start / (uint64_t)L.walks_per_slot];
-          c_mesh = rs.mesh;
-          c_row = rs.row;
-          c_tab = -1;
-          for (int t = 0; t < 2; ++t)
-            if (t_used[t] && t_mesh[t] == c_mesh && t_row[t] == c_row) c_tab = t;
-          if (c_tab < 0) {
-            for (int t = 0; t < 2; ++t)
-              if (!t_used[t] && c_tab < 0) {
-                c_tab = t;
-                t_used[t] = 1;
-                t_mesh[t] = c_mesh;
-                t_row[t] = c_row;
-              }
-          }
-        }
-        const uint32_t rank = __popcll(idle & ((1ull << __lane_id()) - 1ull));
-        const uint64_t avail = cend - cur;
-        const uint32_t take = (uint32_t)min(avail, (uint64_t)__popcll(idle));
-        bool fresh = false;
-        if (!w.active && rank < take) {
-          decode_walk(L, cur + rank, w);
-          int32_t face;
-          double lam[3];
-          const MeshDev& M = L.meshes[w.mesh];
-          w.active = walk_start(L, M, w, face, lam) ? 1 : 0;
-          w.tab = (w.active && c_tab >= 0 && w.mesh == c_mesh && w.row == c_row) ? c_tab : -1;
-          fresh = w.active && w.tab >= 0;
-        }
-        if (c_tab >= 0) t_out[c_tab] += (int32_t)__popcll(__ballot(fresh));
-        cur += take;
-        idle = __ballot(!w.active);
-        // lanes whose row was discarded stay idle; keep filling
-      }
-    }
-    if (__ballot(w.active) == 0) {
-      if (drained) {
-        for (int t = 0; t < 2; ++t)
-          if (t_used[t]) {
-            table_flush(L, T, wi, t, t_mesh[t], t_row[t]);
-            t_used[t] = 0;
-          }
-        break;
-      }
-      continue;
-    }
-    // ---- one step of every live walk
-    bool fin = false;
-    int32_t fin_tab = -1;
-#if MSK_COOP_LEAVES
-    // first half per lane, the query by the whole wavefront, second half per lane
-    int32_t st = -1;
-    bool capped = false, q = false;
-    if (w.active) {
-      st = walk_begin(L, L.meshes[w.mesh], w, capped);
-      q = st < 0;
-    }
-    if (__ballot(q) != 0) {
-      const MeshDev& Mq = L.meshes[q ? w.mesh : 0];
-      hit.d2 = INFINITY;
-      hit.orig = INT_MAX;
-      hit.slot = q ? w.slot : -1;
-      bvh_nearest_coop<kStats>(Mq.nodes, Mq.tris, top, (q && w.mesh == 0) ? n_lds : 0, w.x, w.y, w.z, Mq.radius, hit,
-                               w.cnt, q, &coop[wi]);
-    }
-    if (w.active) {
-      const MeshDev& M = L.meshes[w.mesh];
-      if (q) st = walk_end(M, w, capped, hit);
+constexpr int kStepMin = MSK_STEP_MIN;
+#ifndef MSK_PHASE_TIMING
+#define MSK_PHASE_TIMING 0
+#endif
+#if MSK_PHASE_TIMING
+__device__ unsigned long long g_phase_cycles[16];
+#define MSK_TICK(var) const uint64_t var = (uint64_t)__builtin_amdgcn_s_memtime()
+#define MSK_ACC(i, a, b) ph[i] += (b) - (a)
 #else
-    if (w.active) {
-      const MeshDev& M = L.meshes[w.mesh];
-      const int32_t nl = (w.mesh == 0) ? n_lds : 0;
-      const int32_t st = walk_step<kStats>(L, M, top, nl, w, hit);
+#define MSK_TICK(var)
+#define MSK_ACC(i, a, b)
 #endif
-      if (st >= 0) {
-        if (w.tab >= 0)
-          walk_finish_table(L, M, w, st, hit, T, wi);
-        else
-          walk_finish_global(L, M, w, st, hit);
-        fin = true;
-        fin_tab = w.tab;
-        w.active = 0;
-        w.tab = -1;
-      }
-    }
-    for (int t = 0; t < 2; ++t) {
-      t_out[t] -= (int32_t)__popcll(__ballot(fin && fin_tab == t));
-      // flush once the table's walks are done and its chunk hands out no more
-      if (t_used[t] && t_out[t] == 0 && !(t == c_tab && cur < cend)) {
-        table_flush(L, T, wi, t, t_mesh[t], t_row[t]);
-        t_used[t] = 0;
-        if (c_tab == t) c_tab = -1;
-      }
-    }
-  }
-}
 
 // Streaming form of the persistent kernel: every loop trip advances each
 // traversing lane by one BVH node (its leaf triangles tested by the whole
@@ -1064,9 +807,6 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_persistent_
 // whose query is answered wait until enough of them do (L.regen_min), then
 // finish their step, start the next one or take a new walk together. The
 // walks, their queries and their results are those of the other forms.
-#ifndef MSK_STREAM
-#define MSK_STREAM 1
-#endif
 template <bool kStats, typename AccT>
 __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kernel(WalkLaunch L) {
   __shared__ Node4 top[kLdsTop > 0 ? kLdsTop : 1];
@@ -1103,12 +843,17 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
   hit.orig = INT_MAX;
   hit.slot = -1;
   hit.l1 = hit.l2 = 0.0f;
-  // lane's query: mode 0 no walk, 1 traversing, 2 answered (hit holds it)
-  int32_t mode = 0, node = -1, sp = 0, warm = -1;
+  // lane's state: mode 0 no walk, 1 traversing, 2 query answered (hit holds
+  // it), 3 walk ended (hit and fin_status hold its result until the next
+  // bookkeeping pass records it)
+  int32_t mode = 0, node = -1, sp = 0, warm = -1, fin_status = -1;
   float thr = INFINITY, slack = 0.0f;
   bool capped = false;
   StackEntry stk[kStackDepth];
   bool drained = false;
+#if MSK_PHASE_TIMING
+  uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#endif
   auto start_query = [&](const MeshDev& M) {
     hit.d2 = INFINITY;
     hit.orig = INT_MAX;
@@ -1118,34 +863,54 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
     sp = 0;
     thr = INFINITY;
     slack = 0x1p-18f * (M.radius + fmaxf(fabsf(w.x), fmaxf(fabsf(w.y), fabsf(w.z))));
+    W->nodes[lane] = M.nodes;
+    W->tris[lane] = M.tris;
     mode = 1;
   };
   while (true) {
-    // ---- bookkeeping, when enough lanes wait or none traverses: lanes whose
-    // query is answered finish their step and start the next one, or record
-    // their ended walk; idle lanes take new walks
+    // ---- bookkeeping, when enough lanes wait or none traverses: ended walks
+    // are recorded and idle lanes take new walks
+    MSK_TICK(tk0);
+    // ---- steps whose query is answered: finish the step and start the next
+    // one, once kStepMin lanes wait or none traverses; an ended walk waits
+    // for the bookkeeping pass below
+    {
+      const uint64_t pend = __ballot(mode == 2);
+      if (pend != 0 && (__ballot(mode == 1) == 0 || (int)__popcll(pend) >= kStepMin)) {
+        if (mode == 2) {
+          const MeshDev& M = L.meshes[w.mesh];
+          int32_t st = walk_end(M, w, capped, hit);
+          if (st < 0) {
+            st = walk_begin(L, M, w, capped);
+            if (st < 0) start_query(M);
+          }
+          if (st >= 0) {
+            fin_status = st;
+            mode = 3;
+          }
+        }
+      }
+    }
+    MSK_TICK(tk0b);
+    MSK_ACC(5, tk0, tk0b);
     const uint64_t trav = __ballot(mode == 1);
-    if (trav == 0 || (int)__popcll(~trav) >= L.regen_min) {
+    if (trav == 0 || (int)__popcll(__ballot(mode == 0 || mode == 3)) >= L.regen_min) {
+#if MSK_PHASE_TIMING
+      ph[7] += 1;
+#endif
       bool fin = false;
       int32_t fin_tab = -1;
-      if (mode == 2) {
+      if (mode == 3) {
         const MeshDev& M = L.meshes[w.mesh];
-        int32_t st = walk_end(M, w, capped, hit);
-        if (st < 0) {
-          st = walk_begin(L, M, w, capped);
-          if (st < 0) start_query(M);
-        }
-        if (st >= 0) {
-          if (w.tab >= 0)
-            walk_finish_table(L, M, w, st, hit, T, wi);
-          else
-            walk_finish_global(L, M, w, st, hit);
-          fin = true;
-          fin_tab = w.tab;
-          w.active = 0;
-          w.tab = -1;
-          mode = 0;
-        }
+        if (w.tab >= 0)
+          walk_finish_table(L, M, w, fin_status, hit, T, wi);
+        else
+          walk_finish_global(L, M, w, fin_status, hit);
+        fin = true;
+        fin_tab = w.tab;
+        w.active = 0;
+        w.tab = -1;
+        mode = 0;
       }
       for (int t = 0; t < 2; ++t) {
         t_out[t] -= (int32_t)__popcll(__ballot(fin && fin_tab == t));
@@ -1235,12 +1000,16 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
         continue;
       }
     }
+    MSK_TICK(tk1);
+    MSK_ACC(0, tk0, tk1);
     if (__ballot(mode == 1) == 0) continue;
+#if MSK_PHASE_TIMING
+    ph[6] += 1;
+#endif
     // ---- one node of every traversing lane
     const bool tr = mode == 1;
     float lb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     int32_t cc[4] = {-1, -1, -1, -1}, cn[4] = {0, 0, 0, 0};
-    const MeshDev& Mq = L.meshes[tr ? w.mesh : 0];
     if (tr) {
       const int32_t nl = w.mesh == 0 ? n_lds : 0;
       float4 lox, loy, loz, hix, hiy, hiz;
@@ -1254,7 +1023,7 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
         lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
         ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
       } else {
-        const float4* N = (const float4*)&Mq.nodes[node];
+        const float4* N = (const float4*)&W->nodes[lane][node];
         lox = N[0]; loy = N[1]; loz = N[2]; hix = N[3]; hiy = N[4]; hiz = N[5];
         ch = ((const int4*)N)[6]; ct = ((const int4*)N)[7];
       }
@@ -1281,6 +1050,8 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
       MSK_CX(0, 1) MSK_CX(2, 3) MSK_CX(0, 2) MSK_CX(1, 3) MSK_CX(1, 2)
 #undef MSK_CX
     }
+    MSK_TICK(tk2);
+    MSK_ACC(1, tk1, tk2);
     // this lane's triangles: the warm-start candidate of a new query, then
     // the leaf children within the bound
     const int32_t hw = (tr && warm >= 0) ? 1 : 0;
@@ -1293,33 +1064,36 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
     if (__ballot(tot > 0) != 0) {
       W->pt[lane] = make_float4(w.x, w.y, w.z, hit.d2);
       W->key[lane] = ((unsigned long long)__float_as_uint(hit.d2) << 32) | (uint32_t)hit.orig;
-      W->tris[lane] = Mq.tris;
       if (kStats) W->flops[lane] = 0;
-      uint32_t ntask = 0;
-      for (int32_t j = 0;; ++j) {
-        const uint64_t m = __ballot(j < tot);
-        if (ntask > 0 && (m == 0 || ntask + (uint32_t)__popcll(m) > (uint32_t)kCoopTasks)) {
-          coop_leaf_round<kStats>(W, lane, ntask);
-          ntask = 0;
-        }
-        if (m == 0) break;
-        if (j < tot) {
-          int32_t slot;
-          if (j < hw) {
-            slot = warm;
-          } else {
-            const int32_t jj = j - hw;
-            const int32_t e1 = nl4[0], e2 = e1 + nl4[1], e3 = e2 + nl4[2];
-            const int k = (jj >= e1) + (jj >= e2) + (jj >= e3);
-            const int32_t base = k == 0 ? 0 : (k == 1 ? e1 : (k == 2 ? e2 : e3));
-            const int32_t c = k == 0 ? cc[0] : (k == 1 ? cc[1] : (k == 2 ? cc[2] : cc[3]));
-            slot = -c - 1 + (jj - base);
+      // lay the units out by a prefix sum over the lanes, in windows of kCoopUnits
+      int32_t nu = hw;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) nu += (nl4[k] + 3) >> 2;
+      uint32_t total;
+      const uint32_t pre = wave_prefix_small((uint32_t)nu, total);
+      for (uint32_t w0 = 0; w0 < total; w0 += (uint32_t)kCoopUnits) {
+        const uint32_t w1 = w0 + (uint32_t)kCoopUnits;
+        if (nu > 0 && pre < w1 && pre + (uint32_t)nu > w0) {
+          uint32_t pos = pre;
+          auto put = [&](uint32_t first, uint32_t cnt) {
+            if (pos >= w0 && pos < w1) {
+              W->unit[pos - w0] = (first << 6) | lane;
+              W->ucnt[pos - w0] = (uint8_t)cnt;
+            }
+            ++pos;
+          };
+          if (hw) put((uint32_t)warm, 1u);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            uint32_t first = (uint32_t)(-cc[k] - 1);
+            for (int32_t c = nl4[k]; c > 0; c -= 4, first += 4) put(first, (uint32_t)min(c, 4));
           }
-          const uint32_t pos = ntask + mbcnt64(m);
-          W->task_slot[pos] = slot;
-          W->task_owner[pos] = (uint8_t)lane;
         }
-        ntask += (uint32_t)__popcll(m);
+        lds_order();
+        MSK_TICK(tr0);
+        coop_unit_round<kStats>(W, lane, min(total - w0, (uint32_t)kCoopUnits));
+        MSK_TICK(tr1);
+        MSK_ACC(3, tr0, tr1);
       }
       if (tot > 0) {
         if (kStats) {
@@ -1339,6 +1113,8 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
         }
       }
     }
+    MSK_TICK(tk3);
+    MSK_ACC(2, tk2, tk3);
     if (tr) {
       warm = -1;
       // the nearest surviving inner child is next; the others are pushed
@@ -1364,10 +1140,16 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
             break;
           }
         }
-        if (node < 0) mode = 2;
+        if (node < 0) mode = 2;  // query answered
       }
     }
+    MSK_TICK(tk4);
+    MSK_ACC(4, tk3, tk4);
   }
+#if MSK_PHASE_TIMING
+  if (lane == 0)
+    for (int i = 0; i < 8; ++i) atomicAdd(&g_phase_cycles[i], (unsigned long long)ph[i]);
+#endif
 }
 
 __global__ void init_queues_kernel(unsigned long long* next, unsigned long long* end, QueueInit q) {
@@ -1482,25 +1264,31 @@ hipError_t launch_walk_plain(const WalkLaunch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
-#if MSK_STREAM
-#define MSK_PERSISTENT_KERNEL walk_stream_kernel
-#else
-#define MSK_PERSISTENT_KERNEL walk_persistent_kernel
-#endif
 hipError_t launch_walk_persistent(const WalkLaunch& L, int grid, hipStream_t s) {
   if (L.accum_f32) {
     if (L.stats)
-      hipLaunchKernelGGL((MSK_PERSISTENT_KERNEL<true, float>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<true, float>), dim3(grid), dim3(256), 0, s, L);
     else
-      hipLaunchKernelGGL((MSK_PERSISTENT_KERNEL<false, float>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<false, float>), dim3(grid), dim3(256), 0, s, L);
   } else {
     if (L.stats)
-      hipLaunchKernelGGL((MSK_PERSISTENT_KERNEL<true, double>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<true, double>), dim3(grid), dim3(256), 0, s, L);
     else
-      hipLaunchKernelGGL((MSK_PERSISTENT_KERNEL<false, double>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<false, double>), dim3(grid), dim3(256), 0, s, L);
   }
   return hipGetLastError();
 }
+
+#if MSK_PHASE_TIMING
+extern "C" int msk_debug_phase_cycles(unsigned long long* out, int reset) {
+  if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_cycles), sizeof(unsigned long long) * 8) != hipSuccess) return 1;
+  if (reset) {
+    unsigned long long z[16] = {0};
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase_cycles), z, sizeof(z)) != hipSuccess) return 1;
+  }
+  return 0;
+}
+#endif
 
 hipError_t launch_init_queues(unsigned long long* next, unsigned long long* end, const QueueInit& q, hipStream_t s) {
   hipLaunchKernelGGL(init_queues_kernel, dim3(1), dim3(64), 0, s, next, end, q);

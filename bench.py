@@ -191,7 +191,11 @@ def main():
     tuned = None
     if args.launch:
         run.opts = {k: int(v) for k, v in (kv.split("=") for kv in args.launch.split(","))}
-        log(f"[bench] launch settings: {run.opts}")
+        leaf = run.opts.pop("leaf", None)
+        if leaf is not None:  # BVH leaf width: rebuild the meshes in place
+            for h in run.handles:
+                h[1].rebuild(leaf)
+        log(f"[bench] launch settings: {run.opts}" + (f", leaf {leaf}" if leaf else ""))
     elif not args.no_tune:  # untimed: pick leaf width / chunk / refill threshold / workgroups per CU
         hs = run.handles
         tuned = ctx.autotune([h[1] for h in hs], [h[2] for h in hs], [h[3] for h in hs], [h[0].eps for h in hs],

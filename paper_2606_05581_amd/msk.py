@@ -319,6 +319,10 @@ class _Handle:
 class Mesh(_Handle):
     _destroy = "msk_mesh_destroy"
 
+    def rebuild(self, leaf_size: int):
+        """Rebuild the BVH in place with another leaf width (walks do not change)."""
+        self.ctx._check(lib().msk_mesh_rebuild(self.ctx.h, self.h, leaf_size))
+
     def info(self) -> dict:
         i = MeshInfo()
         self.ctx._check(lib().msk_mesh_get_info(self.h, C.byref(i)))

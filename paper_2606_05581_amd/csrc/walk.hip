@@ -849,7 +849,12 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
   int32_t mode = 0, node = -1, sp = 0, warm = -1, fin_status = -1;
   float thr = INFINITY, slack = 0.0f;
   bool capped = false;
+  // traversal stack: its top entry in registers (tn, tl), the rest in
+  // private memory; a pop takes the registers and starts reading the next
+  // entry, which is not needed before the following pop
   StackEntry stk[kStackDepth];
+  int32_t tn = -1;
+  float tl = 0.0f;
   bool drained = false;
 #if MSK_PHASE_TIMING
   uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -861,6 +866,7 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
     warm = w.slot;
     node = 0;
     sp = 0;
+    tn = -1;
     thr = INFINITY;
     slack = 0x1p-18f * (M.radius + fmaxf(fabsf(w.x), fmaxf(fabsf(w.y), fabsf(w.z))));
     W->nodes[lane] = M.nodes;
@@ -1124,7 +1130,11 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
 #pragma unroll
       for (int k = 3; k >= 0; --k) {
         if (cc[k] >= 0 && lb[k] <= thr) {
-          if (next >= 0 && sp < kStackDepth) stk[sp++] = StackEntry{next, next_lb};
+          if (next >= 0) {  // push the farther candidate
+            if (tn >= 0 && sp < kStackDepth) stk[sp++] = StackEntry{tn, tl};
+            tn = next;
+            tl = next_lb;
+          }
           next = cc[k];
           next_lb = lb[k];
         }
@@ -1133,10 +1143,18 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
         node = next;
       } else {
         node = -1;
-        while (sp > 0) {
-          --sp;
-          if (stk[sp].lb <= thr) {
-            node = stk[sp].node;
+        while (tn >= 0) {
+          const int32_t cand = tn;
+          const float cl = tl;
+          if (sp > 0) {
+            --sp;
+            tn = stk[sp].node;
+            tl = stk[sp].lb;
+          } else {
+            tn = -1;
+          }
+          if (cl <= thr) {
+            node = cand;
             break;
           }
         }

@@ -158,6 +158,9 @@ def main():
     ap.add_argument("--no-stats", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--launch", default="", help="fixed launch settings instead of tuning, e.g. chunk=64,regen_min=16")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2606_05581_amd", "tune_cache.jsonl"),
+                    help="autotuner results (JSON lines); a stored entry for this workload is reused, else the "
+                         "tuner times the candidates and appends one")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a device copy of this size first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -199,7 +202,8 @@ def main():
     elif not args.no_tune:  # untimed: pick leaf width / chunk / refill threshold / workgroups per CU
         hs = run.handles
         tuned = ctx.autotune([h[1] for h in hs], [h[2] for h in hs], [h[3] for h in hs], [h[0].eps for h in hs],
-                             [h[0].h for h in hs], exterior=(wl.modes[0] == "exterior"))
+                             [h[0].h for h in hs], exterior=(wl.modes[0] == "exterior"),
+                             cache_path=args.tune_cache or None, repeats=3)
         run.opts = {"chunk": tuned["chunk"], "regen_min": tuned["regen_min"], "blocks_per_cu": tuned["blocks_per_cu"]}
         log(f"[bench] autotuned: {tuned}")
 

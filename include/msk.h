@@ -174,8 +174,9 @@ typedef struct {
   int32_t block;       /* threads per workgroup (default 256)                  */
   int32_t blocks_per_cu; /* persistent grid size / 256 CUs (default 8)         */
   int32_t chunk;       /* walks a wavefront takes from the queue at once (64)  */
-  int32_t regen_min;   /* persistent form: a wavefront finishes steps and takes
-                          new walks once this many of its 64 lanes wait (48) */
+  int32_t regen_min;   /* persistent form: a wavefront records ended walks and
+                          takes new ones once this many of its 64 lanes are
+                          idle (16)                                          */
   int32_t record_log;  /* keep a per-walk log (status, triangle, bary, queries) */
   double se_target;    /* > 0: adaptive walks per row (see msk_estimate_dtn)   */
   int64_t walks_max;   /* adaptive cap (default 65536)                         */

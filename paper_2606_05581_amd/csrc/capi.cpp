@@ -418,7 +418,7 @@ extern "C" void msk_dtn_opts_default(msk_dtn_opts* o) {
   o->block = 256;
   o->blocks_per_cu = 8;
   o->chunk = 64;
-  o->regen_min = 48;
+  o->regen_min = 16;
   o->record_log = 0;
   o->se_target = 0;
   o->walks_max = 65536;
@@ -1092,7 +1092,7 @@ extern "C" void msk_tune_space_default(msk_tune_space* sp) {
   sp->n_chunk = 3;
   sp->chunk[0] = 32; sp->chunk[1] = 64; sp->chunk[2] = 128;
   sp->n_regen = 3;
-  sp->regen_min[0] = 24; sp->regen_min[1] = 40; sp->regen_min[2] = 48;
+  sp->regen_min[0] = 8; sp->regen_min[1] = 16; sp->regen_min[2] = 24;
   sp->n_bpc = 2;
   sp->blocks_per_cu[0] = 4; sp->blocks_per_cu[1] = 8;
   sp->trial_rows = 65536;
@@ -1132,14 +1132,20 @@ extern "C" msk_status msk_mesh_rebuild(msk_ctx* ctx, msk_mesh* m, int32_t leaf) 
   return MSK_OK;
 }
 
-static std::string tune_signature(int32_t n, msk_mesh* const* meshes, const msk_rows* const* rows, int32_t side) {
+// Cached tuning results are keyed by the walk kernel's design revision, the
+// device's CU count and the workload's shape.
+constexpr const char* kTuneKernel = "stream-2";
+
+static std::string tune_signature(const msk_ctx* ctx, int32_t n, msk_mesh* const* meshes, const msk_rows* const* rows,
+                                  int32_t side) {
   long long tris = 0, nr = 0;
   for (int32_t i = 0; i < n; ++i) {
     tris += meshes[i]->nf;
     nr += rows[i]->n;
   }
-  char buf[160];
-  std::snprintf(buf, sizeof(buf), "meshes=%d;tris=%lld;rows=%lld;side=%d", n, tris, nr, side);
+  char buf[200];
+  std::snprintf(buf, sizeof(buf), "kernel=%s;cu=%d;meshes=%d;tris=%lld;rows=%lld;side=%d", kTuneKernel, ctx->n_cu,
+                n, tris, nr, side);
   return buf;
 }
 
@@ -1160,7 +1166,7 @@ extern "C" msk_status msk_autotune(msk_ctx* ctx, int32_t n, msk_mesh* const* mes
   out->chunk = 64;
   out->regen_min = 1;
   out->blocks_per_cu = 8;
-  const std::string sig = tune_signature(n, meshes, rows, side);
+  const std::string sig = tune_signature(ctx, n, meshes, rows, side);
   if (sp.cache_path) {  // one JSON object per line: {"sig": "...", "leaf": L, ...}
     if (FILE* f = std::fopen(sp.cache_path, "r")) {
       char line[512];

@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -82,15 +84,32 @@ class Runner:
             b.close()
         self.batches = {}
 
-    def step(self, with_eigen=True, form=None, **opts):
-        """One pass; returns a list of per-launch records."""
+    def se_sample(self):
+        """Mesh indices whose standard errors are compared between forms."""
+        n = len(self.handles)
+        return sorted(set(int(i) for i in np.linspace(0, n - 1, min(4, n)).astype(int)))
+
+    @staticmethod
+    def median_se(dtn):
+        from paper_2606_05581_amd import msk
+
+        se = dtn.get(msk.FIELD_SE)
+        return float(np.median(se[se > 0])) if np.any(se > 0) else 0.0
+
+    def step(self, with_eigen=True, form=None, se_out=None, **opts):
+        """One pass; returns a list of per-launch records. With se_out (a
+        dict), the median standard error of each sampled mesh is stored."""
         from paper_2606_05581_amd import msk
 
         opts = {**self.opts, **opts}
         recs = []
         for ext in [m == "exterior" for m in self.wl.modes]:
             if self.batched and form != msk.FORM_PLAIN:
-                recs.append(self._batch(ext, **opts).run())
+                b = self._batch(ext, **opts)
+                recs.append(b.run())
+                if se_out is not None:
+                    for i in self.se_sample():
+                        se_out[(ext, i)] = self.median_se(b.dtn(i))
                 continue
             for i, (c, mesh, rows, basis) in enumerate(self.handles):
                 kw = dict(opts)
@@ -99,6 +118,8 @@ class Runner:
                 d = self.ctx.estimate_dtn(mesh, rows, basis, self.wl.walks, c.eps, c.h, exterior=ext, mesh_id=i,
                                           **kw)
                 inf = d.info()
+                if se_out is not None and i in self.se_sample():
+                    se_out[(ext, i)] = self.median_se(d)
                 if with_eigen and self.wl.k > 0 and c.basis.K == c.rows.n_rows:
                     _, _, est = self.ctx.steklov_modes(d, self.wl.k, vectors=False)
                     inf["eigen_ms"] = est["lanczos_ms"]
@@ -110,8 +131,6 @@ class Runner:
 
 def cpu_baseline(wl, target_s, max_threads=16, max_meshes=8):
     """The oracle (FP64 walks, its own BVH) on a bounded sample of rows."""
-    import numpy as np
-
     from oracle import oracle as O
 
     O.build()
@@ -230,6 +249,8 @@ def main():
         log(f"[bench] step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    se_batched = {}
+    run.step(with_eigen=False, se_out=se_batched)  # untimed: standard errors of the same step
     run.drop_batches()
 
     walks = sum(r["walks_total"] for r in recs)
@@ -247,10 +268,14 @@ def main():
         pr = run.step(with_eigen=False, form=msk.FORM_PLAIN)
         torch.cuda.synchronize()
         tp = time.perf_counter() - tp
+        se_plain = {}
+        run.step(with_eigen=False, form=msk.FORM_PLAIN, se_out=se_plain)  # untimed
         plain = {"walks_per_s": sum(r["walks_total"] for r in pr) / tp,
                  "walks_per_s_walk_kernels": sum(r["walks_total"] for r in pr) / (
                      sum(r["walk_kernel_ms"] for r in pr) * 1e-3),
-                 "launches": sum(r["walk_launches"] for r in pr)}
+                 "launches": sum(r["walk_launches"] for r in pr),
+                 "median_se_ratio": float(np.median([se_batched[k] / se_plain[k] for k in se_plain
+                                                     if se_plain[k] > 0]))}
         log(f"[bench] plain form: {plain['walks_per_s']:.3e} walks/s ({plain['launches']} launches)")
 
     cpu = None
@@ -307,6 +332,7 @@ def main():
         "walks_per_s_walk_kernels": walks / (kern_ms * 1e-3),
         "eigen_ms_avg": sum(eig) / len(eig) if eig else None,
         "plain": plain,
+        "median_se": {"sample": f"meshes {run.se_sample()}", "per_mesh": [se_batched[k] for k in sorted(se_batched)]},
         "vs_plain": (value / plain["walks_per_s"]) if plain else None,
         "vs_plain_walk_kernels": (walks / (kern_ms * 1e-3) / plain["walks_per_s_walk_kernels"]) if plain else None,
         "roofline": roof,

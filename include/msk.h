@@ -201,8 +201,11 @@ void msk_dtn_opts_default(msk_dtn_opts* opts);
  * standard error of every entry. Point rows whose inset point lies closer
  * than h/2 to the surface are discarded (zero row, flagged; Appendix A,
  * self-intersections). With se_target > 0 (exterior), walks are added in
- * batches of `walks` to every row whose escape-fraction standard error
- * sqrt(q(1-q)/W_i) exceeds se_target, up to walks_max.
+ * rounds to every row whose escape-fraction standard error
+ * sqrt(max(q(1-q), 1/W_i)/W_i) exceeds se_target: a multiple of `walks`, the
+ * row's predicted deficit q(1-q)/se_target^2 - W_i rounded up (at least
+ * `walks`, at most doubling W_i), up to walks_max; walk indices continue
+ * the row's Philox walk counter.
  * Errors: INVALID_ARG for walks < 2, eps <= 0, inset_h <= eps, or rows /
  * basis built for a mesh with a different vertex count. Any K is accepted
  * (K == n_rows is needed only by msk_steklov_modes). Free the result with

@@ -669,7 +669,8 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
   if (opts) o = *opts;
   if (o.form != MSK_FORM_PLAIN && o.form != MSK_FORM_PERSISTENT) return fail(ctx, MSK_ERR_INVALID_ARG, "bad form");
   if (o.accum != 0 && o.accum != 1) return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64) or 1 (FP32)");
-  if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32))
+  if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32) ||
+      (o.se_target > 0 && o.walk_offset + o.walks_max > ((int64_t)1 << 32)))
     return fail(ctx, MSK_ERR_INVALID_ARG, "walk indices must fit in 32 bits");
   const bool adaptive = o.se_target > 0;
   if (adaptive && (o.walks_max < walks)) return fail(ctx, MSK_ERR_INVALID_ARG, "walks_max < walks");
@@ -719,7 +720,7 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
   HIP_D(hipStreamSynchronize(ctx->stream));
   std::vector<MeshDev> meshes{M};
   std::vector<RowSlot> slots(r->order.size());
-  for (size_t i = 0; i < slots.size(); ++i) slots[i] = RowSlot{0, r->order[i]};
+  for (size_t i = 0; i < slots.size(); ++i) slots[i] = RowSlot{0, r->order[i], 0u};
   const int use_lds = (o.form == MSK_FORM_PERSISTENT && m->top_nodes > 0) ? 1 : 0;
   double ms = 0;
   d->info.walk_launches = 0;
@@ -729,27 +730,39 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
   d->info.walk_kernel_ms += ms;
   d->info.walk_launches += 1;
   if (adaptive) {
-    // add batches of `walks` to rows whose escape-fraction se exceeds the target
+    // Rounds: every row whose escape-fraction standard error exceeds the
+    // target gets a multiple of `walks` more walks, its predicted deficit
+    // q(1-q)/target^2 - W_i rounded up, at least one batch and at most
+    // doubling its count; a row's slots continue its walk indices, so all its
+    // new walks run in the round's single launch.
     std::vector<int64_t> wdone((size_t)d->n, walks);
     std::vector<unsigned long long> esc((size_t)d->n);
     std::vector<int32_t> disc((size_t)d->n);
     HIP_D(hipMemcpy(disc.data(), d->d_disc, d->n * 4, hipMemcpyDeviceToHost));
-    int64_t done = walks;
-    while (done + walks <= o.walks_max) {
+    const double t2 = o.se_target * o.se_target;
+    while (true) {
       HIP_D(hipMemcpy(esc.data(), d->d_esc, d->n * 8, hipMemcpyDeviceToHost));
       std::vector<RowSlot> act;
+      std::vector<int64_t> add((size_t)d->n, 0);
       for (int32_t i : r->order) {
         if (disc[i]) continue;
-        double q = (double)esc[i] / (double)wdone[i];
-        double se = std::sqrt(std::max(q * (1 - q), 1.0 / wdone[i]) / (double)wdone[i]);
-        if (se > o.se_target) act.push_back(RowSlot{0, i});
+        const double Wi = (double)wdone[i];
+        const double q = (double)esc[i] / Wi;
+        const double v = std::max(q * (1 - q), 1.0 / Wi);
+        if (std::sqrt(v / Wi) <= o.se_target) continue;
+        const int64_t room = o.walks_max - wdone[i];
+        if (room < walks) continue;
+        const double deficit = v / t2 - Wi;
+        int64_t batches = (int64_t)std::ceil(std::max(deficit, 1.0) / (double)walks);
+        batches = std::max<int64_t>(1, std::min<int64_t>(batches, std::min(wdone[i], room) / walks));
+        for (int64_t j = 0; j < batches; ++j) act.push_back(RowSlot{0, i, (uint32_t)(wdone[i] + j * walks)});
+        add[i] = batches * walks;
       }
       if (act.empty()) break;
-      TRY_D(run_walks(ctx, meshes, act, walks, o.walk_offset + done, o, use_lds, m->top_nodes, &ms, stats));
+      TRY_D(run_walks(ctx, meshes, act, walks, o.walk_offset, o, use_lds, m->top_nodes, &ms, stats));
       d->info.walk_kernel_ms += ms;
       d->info.walk_launches += 1;
-      for (auto& a : act) wdone[a.row] += walks;
-      done += walks;
+      for (int32_t i : r->order) wdone[i] += add[i];
     }
     HIP_D(hipMemcpy(d->d_walks, wdone.data(), d->n * 8, hipMemcpyHostToDevice));
   }
@@ -863,7 +876,8 @@ extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk
   msk_dtn_opts_default(&o);
   if (opts) o = *opts;
   if (o.se_target > 0 || o.record_log) return fail(ctx, MSK_ERR_INVALID_ARG, "batches take a fixed walk count, no log");
-  if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32))
+  if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32) ||
+      (o.se_target > 0 && o.walk_offset + o.walks_max > ((int64_t)1 << 32)))
     return fail(ctx, MSK_ERR_INVALID_ARG, "walk indices must fit in 32 bits");
   if (o.accum != 0 && o.accum != 1) return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64) or 1 (FP32)");
   for (int32_t i = 0; i < n_meshes; ++i) {
@@ -895,7 +909,7 @@ extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk
   std::stable_sort(mo.begin(), mo.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
   std::vector<RowSlot> slots;
   for (int32_t i : mo)
-    for (int32_t r : rows[i]->order) slots.push_back(RowSlot{i, r});
+    for (int32_t r : rows[i]->order) slots.push_back(RowSlot{i, r, 0u});
   hipError_t he;
   if ((he = upload(ctx, &B->lb.d_meshes, B->md.data(), B->md.size())) != hipSuccess ||
       (he = upload(ctx, &B->lb.d_slots, slots.data(), slots.size())) != hipSuccess ||
@@ -1232,7 +1246,7 @@ extern "C" msk_status msk_autotune(msk_ctx* ctx, int32_t n, msk_mesh* const* mes
   for (int32_t i = 0; i < n; ++i) {
     const int64_t ni = rows[i]->n;
     const int64_t k = std::max<int64_t>(1, std::min<int64_t>(ni, (sp.trial_rows * ni + total_rows - 1) / total_rows));
-    for (int64_t j = 0; j < k; ++j) slots.push_back(RowSlot{i, rows[i]->order[(size_t)(j * ni / k)]});
+    for (int64_t j = 0; j < k; ++j) slots.push_back(RowSlot{i, rows[i]->order[(size_t)(j * ni / k)], 0u});
   }
   int trials = 0;
   auto evaluate = [&](int leaf, int chunk, int regen, int bpc, double* wps) -> msk_status {

@@ -105,6 +105,7 @@ struct MeshDev {
 struct RowSlot {
   int32_t mesh;
   int32_t row;
+  uint32_t walk0;  // the slot's first walk, after the launch's walk_offset
 };
 
 struct WalkLaunch {

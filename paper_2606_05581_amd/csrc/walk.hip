@@ -742,7 +742,7 @@ __device__ __forceinline__ void decode_walk(const WalkLaunch& L, uint64_t g, Lan
   const RowSlot rs = L.slots[slot];
   w.mesh = rs.mesh;
   w.row = rs.row;
-  w.walk = (uint32_t)((int64_t)(g - slot * (uint64_t)L.walks_per_slot) + L.walk_offset);
+  w.walk = (uint32_t)((int64_t)(g - slot * (uint64_t)L.walks_per_slot) + L.walk_offset + rs.walk0);
 }
 
 // ------------------------------------------------------------- kernels

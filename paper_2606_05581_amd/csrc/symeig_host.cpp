@@ -5,14 +5,105 @@
 // Wilkinson shift (Givens bulge chase) until T is diagonal, with all
 // transforms accumulated into the eigenvector matrix.
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
 #include <cstdint>
 #include <cmath>
+#include <functional>
+#include <mutex>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 namespace msk {
 
 namespace {
+
+// A small persistent pool of host threads for the O(n^3) loops of the
+// projected eigenproblem (rows or vectors are independent); the caller is
+// worker 0. Workers spin briefly on the job counter before they sleep, so
+// the many short parallel loops of one factorisation are cheap to start.
+// Calls from several host threads are serialised.
+class HostPool {
+ public:
+  HostPool() {
+    const unsigned hc = std::thread::hardware_concurrency();
+    n_ = (int)std::max(1u, std::min(16u, hc ? hc : 1u));
+    for (int i = 1; i < n_; ++i) th_.emplace_back([this, i] { worker(i); });
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_.store(true);
+      gen_.fetch_add(1);
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  int size() const { return n_; }
+  // f(w) for w = 0..size()-1, one per worker; returns when all are done
+  void run(const std::function<void(int)>& f) {
+    std::lock_guard<std::mutex> serial(run_m_);
+    if (n_ == 1) {
+      f(0);
+      return;
+    }
+    job_ = &f;
+    pending_.store(n_ - 1);
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      gen_.fetch_add(1);
+    }
+    cv_.notify_all();
+    f(0);
+    while (pending_.load() != 0) std::this_thread::yield();
+  }
+
+ private:
+  void worker(int id) {
+    uint64_t seen = 0;
+    while (true) {
+      // spin for a while, then sleep until the next job
+      for (int k = 0; k < 20000 && gen_.load() == seen; ++k) std::this_thread::yield();
+      if (gen_.load() == seen) {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return gen_.load() != seen; });
+      }
+      seen = gen_.load();
+      if (stop_.load()) return;
+      (*job_)(id);
+      pending_.fetch_sub(1);
+    }
+  }
+  int n_ = 1;
+  std::vector<std::thread> th_;
+  std::mutex m_, run_m_;
+  std::condition_variable cv_;
+  const std::function<void(int)>* job_ = nullptr;
+  std::atomic<uint64_t> gen_{0};
+  std::atomic<int> pending_{0};
+  std::atomic<bool> stop_{false};
+};
+
+HostPool& host_pool() {
+  static HostPool pool;
+  return pool;
+}
+
+// body(lo, hi) over [0, n) split across the pool (serially when n is small)
+void parallel_rows(int n, int min_per_worker, const std::function<void(int, int)>& body) {
+  HostPool& P = host_pool();
+  const int w = std::max(1, std::min(P.size(), n / std::max(1, min_per_worker)));
+  if (w <= 1) {
+    body(0, n);
+    return;
+  }
+  P.run([&](int id) {
+    if (id >= w) return;
+    const int lo = (int)((int64_t)n * id / w), hi = (int)((int64_t)n * (id + 1) / w);
+    if (lo < hi) body(lo, hi);
+  });
+}
 
 // In place: A (n x n, row-major, symmetric) -> tridiagonal (diag d, off e,
 // e[i] couples i and i+1) with A = Q T Q^T. With `accumulate`, Q is formed
@@ -43,21 +134,33 @@ void tridiagonalise(int n, std::vector<double>& A, std::vector<double>& Q, std::
     v[0] = 1.0;
     for (int i = 1; i < m; ++i) v[i] = a(k + 1 + i, k) / v0;
     // p = beta * A22 v ; w = p - (beta p^T v / 2) v
+    parallel_rows(m, 64, [&](int lo, int hi) {
+      for (int i = lo; i < hi; ++i) {
+        const double* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int j = 0;
+        for (; j + 3 < m; j += 4) {
+          s0 += row[j] * v[j];
+          s1 += row[j + 1] * v[j + 1];
+          s2 += row[j + 2] * v[j + 2];
+          s3 += row[j + 3] * v[j + 3];
+        }
+        for (; j < m; ++j) s0 += row[j] * v[j];
+        p[i] = beta * ((s0 + s1) + (s2 + s3));
+      }
+    });
     double pv = 0.0;
-    for (int i = 0; i < m; ++i) {
-      double s = 0.0;
-      const double* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
-      for (int j = 0; j < m; ++j) s += row[j] * v[j];
-      p[i] = beta * s;
-      pv += p[i] * v[i];
-    }
+    for (int i = 0; i < m; ++i) pv += p[i] * v[i];
     const double half = 0.5 * beta * pv;
     for (int i = 0; i < m; ++i) w[i] = p[i] - half * v[i];
     // A22 -= v w^T + w v^T ; column k becomes mu e1
-    for (int i = 0; i < m; ++i) {
-      double* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
-      for (int j = 0; j < m; ++j) row[j] -= v[i] * w[j] + w[i] * v[j];
-    }
+    parallel_rows(m, 64, [&](int lo, int hi) {
+      for (int i = lo; i < hi; ++i) {
+        double* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
+        const double vi = v[i], wi = w[i];
+        for (int j = 0; j < m; ++j) row[j] -= vi * w[j] + wi * v[j];
+      }
+    });
     a(k + 1, k) = a(k, k + 1) = mu;
     for (int i = 1; i < m; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
     if (!accumulate) {
@@ -249,8 +352,8 @@ bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>&
   if (tnorm == 0.0) tnorm = 1.0;
   const double eps = std::ldexp(1.0, -52);
   const double ortol = 1e-3 * tnorm;  // eigenvalues closer than this form a cluster
-  std::vector<double> X((size_t)n * m, 0.0);  // eigenvectors of T, column j at X[r * m + j]
-  std::vector<double> y(n), x(n);
+  std::vector<double> Xc((size_t)n * m, 0.0);  // eigenvectors of T, vector j at Xc[j * n + r]
+  std::vector<double> y(n), x(n), dots;
   TriLU f;
   uint64_t seed = 0x9E3779B97F4A7C15ull;
   int cluster_start = 0;
@@ -269,39 +372,59 @@ bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>&
     for (int it = 0; it < 4; ++it) {
       x = y;
       tridiag_solve(n, f, x);
-      for (int pass = 0; pass < 2; ++pass)
-        for (int i = cluster_start; i < j; ++i) {
-          double dot = 0.0;
-          for (int r = 0; r < n; ++r) dot += X[(size_t)r * m + i] * x[r];
-          for (int r = 0; r < n; ++r) x[r] -= dot * X[(size_t)r * m + i];
-        }
+      // classical Gram-Schmidt inside the cluster, twice: the projections
+      // are independent (a pool task each), then one update per entry
+      const int nc = j - cluster_start;
+      for (int pass = 0; pass < 2 && nc > 0; ++pass) {
+        dots.assign(nc, 0.0);
+        parallel_rows(nc, 16, [&](int lo, int hi) {
+          for (int i = lo; i < hi; ++i) {
+            const double* xi = &Xc[(size_t)(cluster_start + i) * n];
+            double s0 = 0.0, s1 = 0.0;
+            int r = 0;
+            for (; r + 1 < n; r += 2) {
+              s0 += xi[r] * x[r];
+              s1 += xi[r + 1] * x[r + 1];
+            }
+            for (; r < n; ++r) s0 += xi[r] * x[r];
+            dots[i] = s0 + s1;
+          }
+        });
+        parallel_rows(n, 256, [&](int lo, int hi) {
+          for (int i = 0; i < nc; ++i) {
+            const double* xi = &Xc[(size_t)(cluster_start + i) * n];
+            const double dt = dots[i];
+            for (int r = lo; r < hi; ++r) x[r] -= dt * xi[r];
+          }
+        });
+      }
       double nrm = 0.0;
       for (double t : x) nrm += t * t;
       nrm = std::sqrt(nrm);
       if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
       for (int r = 0; r < n; ++r) y[r] = x[r] / nrm;
     }
-    for (int r = 0; r < n; ++r) X[(size_t)r * m + j] = y[r];
+    std::copy(y.begin(), y.end(), Xc.begin() + (size_t)j * n);
   }
-  // back-transform: V = H_0 H_1 ... H_{n-3} X (last reflector first)
-  std::vector<double> s(m);
-  for (int k = n - 3; k >= 0; --k) {
-    const double beta = betas[k];
-    if (beta == 0.0) continue;
-    const double* v = &H[(size_t)k * n];  // v[k+1] = 1, v[k+2..] stored
-    std::fill(s.begin(), s.end(), 0.0);
-    for (int r = k + 1; r < n; ++r) {
-      const double vr = r == k + 1 ? 1.0 : v[r];
-      const double* xr = &X[(size_t)r * m];
-      for (int j = 0; j < m; ++j) s[j] += vr * xr[j];
+  // back-transform each vector: H_0 H_1 ... H_{n-3} x (last reflector first)
+  parallel_rows(m, 8, [&](int lo, int hi) {
+    for (int j = lo; j < hi; ++j) {
+      double* xj = &Xc[(size_t)j * n];
+      for (int k = n - 3; k >= 0; --k) {
+        const double beta = betas[k];
+        if (beta == 0.0) continue;
+        const double* v = &H[(size_t)k * n];  // v[k+1] = 1, v[k+2..] stored
+        double s = xj[k + 1];
+        for (int r = k + 2; r < n; ++r) s += v[r] * xj[r];
+        s *= beta;
+        xj[k + 1] -= s;
+        for (int r = k + 2; r < n; ++r) xj[r] -= v[r] * s;
+      }
     }
-    for (int j = 0; j < m; ++j) s[j] *= beta;
-    for (int r = k + 1; r < n; ++r) {
-      const double vr = r == k + 1 ? 1.0 : v[r];
-      double* xr = &X[(size_t)r * m];
-      for (int j = 0; j < m; ++j) xr[j] -= vr * s[j];
-    }
-  }
+  });
+  std::vector<double> X((size_t)n * m);
+  for (int j = 0; j < m; ++j)
+    for (int r = 0; r < n; ++r) X[(size_t)r * m + j] = Xc[(size_t)j * n + r];
   V.swap(X);
   return true;
 }

@@ -208,8 +208,11 @@ void msk_dtn_opts_default(msk_dtn_opts* opts);
  * the row's Philox walk counter.
  * Errors: INVALID_ARG for walks < 2, eps <= 0, inset_h <= eps, or rows /
  * basis built for a mesh with a different vertex count. Any K is accepted
- * (K == n_rows is needed only by msk_steklov_modes). Free the result with
- * msk_dtn_destroy. */
+ * (K == n_rows is needed only by msk_steklov_modes). NUMERIC when an entry
+ * of S or se is NaN or infinite (e.g. basis values beyond the FP32 range of
+ * the accumulation): *out is still set, holds the estimate as computed and
+ * must be destroyed; info.nonfinite_entries counts the entries. Free the
+ * result with msk_dtn_destroy. */
 msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* mesh, const msk_rows* rows, const msk_basis* basis,
                             int64_t walks, double eps, double inset_h, int32_t side, const msk_dtn_opts* opts,
                             msk_dtn** out);
@@ -218,7 +221,8 @@ msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* mesh, const msk_rows* 
  * all meshes share one work queue ordered largest-mesh-first. meshes, rows,
  * bases, eps, inset_h and out are arrays of n_meshes entries; each result is
  * the same as msk_estimate_dtn on that mesh with the mesh's index in the
- * Philox counter. se_target must be 0. */
+ * Philox counter. se_target must be 0. NUMERIC as for msk_estimate_dtn:
+ * every out[i] is then set. */
 msk_status msk_estimate_dtn_batched(msk_ctx* ctx, int32_t n_meshes, const msk_mesh* const* meshes,
                                     const msk_rows* const* rows, const msk_basis* const* bases,
                                     const double* eps, const double* inset_h, int64_t walks, int32_t side,
@@ -229,7 +233,8 @@ msk_status msk_estimate_dtn_batched(msk_ctx* ctx, int32_t n_meshes, const msk_me
  * (meshes largest first, rows in Z-order, split over eight per-XCD queues)
  * and captures HIP graphs of the zeroing and discard pass, of ONE persistent
  * walk launch over all meshes, and of the finalisation; msk_batch_run
- * replays them back to back on the context's stream.
+ * replays them back to back on the context's stream; it returns NUMERIC
+ * (results still readable) when any member holds non-finite entries.
  * Arguments as for msk_estimate_dtn_batched; the handles must outlive the
  * batch. Results of the last run are read with msk_batch_dtn (views owned by
  * the batch, valid until msk_batch_destroy). */
@@ -251,6 +256,8 @@ typedef struct {
   int64_t nodes_visited; /* with opts.collect_stats: BVH nodes read by walks */
   int64_t tris_tested;   /* with opts.collect_stats: triangle distance tests */
   int64_t valu_flops;    /* with opts.collect_stats: FP32 operations of those */
+  int64_t nonfinite_entries; /* NaN or infinite entries of S and se; when
+                                nonzero the call returned MSK_ERR_NUMERIC */
 } msk_dtn_info;
 
 msk_status msk_dtn_get_info(const msk_dtn* dtn, msk_dtn_info* info);
@@ -336,8 +343,10 @@ typedef struct {
  *   evals: host, k doubles, ascending.
  *   evecs: host, n_rows x k doubles (psi = M^-1/2 v, zero on discarded rows),
  *          or NULL.
- * Returns NOT_CONVERGED (with the best approximations written) if the
- * residual target 1e-6 |C| is not reached. */
+ * Returns NOT_CONVERGED (with the best approximations written) if some
+ * residual stays above max(1e-5, 16 sqrt(n) 2^-24) |C|_est (the floor set
+ * by FP32 products with C), and NUMERIC without computing anything if the
+ * estimate holds non-finite entries. */
 msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* dtn, int32_t k, double* evals, double* evecs,
                              msk_eig_stats* stats);
 

@@ -82,6 +82,7 @@ struct msk_dtn {
   int32_t* d_log_tri = nullptr;
   float* d_log_bary = nullptr;
   int32_t* d_log_q = nullptr;
+  unsigned long long* d_nonfinite = nullptr;  // non-finite entries of S and se
   msk_dtn_info info{};
 };
 
@@ -443,6 +444,7 @@ void dtn_free(msk_dtn* d) {
   dfree(d->d_log_tri);
   dfree(d->d_log_bary);
   dfree(d->d_log_q);
+  dfree(d->d_nonfinite);
 }
 
 struct Prepared {
@@ -474,7 +476,7 @@ msk_status alloc_dtn(msk_ctx* ctx, const msk_rows* r, const msk_basis* b, int64_
       (he = dalloc(&d->d_acc1, nk)) != hipSuccess || (he = dalloc(&d->d_acc2, nk)) != hipSuccess ||
       (he = dalloc(&d->d_q, d->n)) != hipSuccess || (he = dalloc(&d->d_esc, d->n)) != hipSuccess ||
       (he = dalloc(&d->d_cap, d->n)) != hipSuccess || (he = dalloc(&d->d_disc, d->n)) != hipSuccess ||
-      (he = dalloc(&d->d_walks, d->n)) != hipSuccess) {
+      (he = dalloc(&d->d_walks, d->n)) != hipSuccess || (he = dalloc(&d->d_nonfinite, 1)) != hipSuccess) {
     dtn_free(d);
     delete d;
     return fail(ctx, MSK_ERR_OOM, std::string("estimate buffers: ") + hipGetErrorString(he));
@@ -643,6 +645,9 @@ static msk_status collect_info(msk_ctx* ctx, msk_dtn* d) {
   HIP_TRY(ctx, hipMemcpy(cap.data(), d->d_cap, d->n * 8, hipMemcpyDeviceToHost));
   HIP_TRY(ctx, hipMemcpy(disc.data(), d->d_disc, d->n * 4, hipMemcpyDeviceToHost));
   HIP_TRY(ctx, hipMemcpy(walks.data(), d->d_walks, d->n * 8, hipMemcpyDeviceToHost));
+  unsigned long long nonfinite = 0;
+  HIP_TRY(ctx, hipMemcpy(&nonfinite, d->d_nonfinite, 8, hipMemcpyDeviceToHost));
+  d->info.nonfinite_entries = (int64_t)nonfinite;
   d->info.n_rows = d->n;
   d->info.K = d->K;
   d->info.walks_total = d->info.queries_total = d->info.escaped_total = d->info.capped_total = 0;
@@ -767,6 +772,9 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
     HIP_D(hipMemcpy(d->d_walks, wdone.data(), d->n * 8, hipMemcpyHostToDevice));
   }
   HIP_D(launch_finalize(M, d->n, d->d_walks, r->d_w, d->d_S, d->d_se, ctx->stream));
+  HIP_D(launch_fill_u64(d->d_nonfinite, 1, 0, ctx->stream));
+  HIP_D(launch_count_nonfinite(d->d_S, (int64_t)nk, d->d_nonfinite, ctx->stream));
+  HIP_D(launch_count_nonfinite(d->d_se, (int64_t)nk, d->d_nonfinite, ctx->stream));
   HIP_D(hipEventRecord(t1, ctx->stream));
   HIP_D(hipEventSynchronize(t1));
   float tot = 0;
@@ -781,6 +789,7 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
 #undef TRY_D
 #undef HIP_D
   *out = d;
+  if (d->info.nonfinite_entries > 0) return fail(ctx, MSK_ERR_NUMERIC, "non-finite entries in S or se");
   return MSK_OK;
 }
 
@@ -858,7 +867,11 @@ static hipError_t enqueue_batch(msk_batch* B, hipStream_t s, int part) {
   }
   for (int32_t i = 0; i < B->n; ++i) {
     msk_dtn* d = B->dtns[i];
-    if ((e = launch_finalize(B->md[i], d->n, d->d_walks, B->rows[i]->d_w, d->d_S, d->d_se, s)) != hipSuccess)
+    const int64_t nk = d->n * d->K;
+    if ((e = launch_finalize(B->md[i], d->n, d->d_walks, B->rows[i]->d_w, d->d_S, d->d_se, s)) != hipSuccess ||
+        (e = launch_fill_u64(d->d_nonfinite, 1, 0, s)) != hipSuccess ||
+        (e = launch_count_nonfinite(d->d_S, nk, d->d_nonfinite, s)) != hipSuccess ||
+        (e = launch_count_nonfinite(d->d_se, nk, d->d_nonfinite, s)) != hipSuccess)
       return e;
   }
   return hipSuccess;
@@ -978,6 +991,7 @@ extern "C" msk_status msk_batch_run(msk_batch* B) {
     T.escaped_total += d->info.escaped_total;
     T.capped_total += d->info.capped_total;
     T.discarded_rows += d->info.discarded_rows;
+    T.nonfinite_entries += d->info.nonfinite_entries;
   }
   T.walk_kernel_ms = wk;
   T.total_ms = tot;
@@ -990,6 +1004,7 @@ extern "C" msk_status msk_batch_run(msk_batch* B) {
     T.valu_flops = (int64_t)st[2];
   }
   B->total = T;
+  if (T.nonfinite_entries > 0) return fail(ctx, MSK_ERR_NUMERIC, "non-finite entries in S or se");
   return MSK_OK;
 }
 
@@ -1016,7 +1031,7 @@ extern "C" msk_status msk_estimate_dtn_batched(msk_ctx* ctx, int32_t n_meshes, c
   msk_status st = msk_batch_create(ctx, n_meshes, meshes, rows, bases, eps, inset_h, walks, side, opts, &B);
   if (st != MSK_OK) return st;
   st = msk_batch_run(B);
-  if (st != MSK_OK) {
+  if (st != MSK_OK && st != MSK_ERR_NUMERIC) {
     msk_batch_destroy(B);
     return st;
   }
@@ -1025,7 +1040,7 @@ extern "C" msk_status msk_estimate_dtn_batched(msk_ctx* ctx, int32_t n_meshes, c
     B->dtns[i] = nullptr;
   }
   msk_batch_destroy(B);
-  return MSK_OK;
+  return st;
 }
 
 extern "C" msk_status msk_dtn_get_info(const msk_dtn* d, msk_dtn_info* info) {
@@ -1077,6 +1092,7 @@ extern "C" msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* d, int32_t 
                                         msk_eig_stats* stats) {
   if (!ctx || !d || !evals) return fail(ctx, MSK_ERR_INVALID_ARG, "null argument");
   if (d->K != d->n) return fail(ctx, MSK_ERR_INVALID_ARG, "the eigen step needs a square estimate (K == n_rows)");
+  if (d->info.nonfinite_entries > 0) return fail(ctx, MSK_ERR_NUMERIC, "the estimate holds non-finite entries");
   std::vector<int32_t> disc((size_t)d->n);
   HIP_TRY(ctx, hipMemcpy(disc.data(), d->d_disc, d->n * 4, hipMemcpyDeviceToHost));
   int iters = 0, block = 0;

@@ -135,6 +135,7 @@ hipError_t launch_walk_persistent(const WalkLaunch& L, int grid, hipStream_t s);
 struct QueueInit {
   unsigned long long begin[8], end[8];
 };
+hipError_t launch_count_nonfinite(const double* a, int64_t n, unsigned long long* count, hipStream_t s);
 hipError_t launch_init_queues(unsigned long long* next, unsigned long long* end, const QueueInit& q, hipStream_t s);
 hipError_t launch_fill_u64(void* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);

@@ -1308,6 +1308,23 @@ extern "C" int msk_debug_phase_cycles(unsigned long long* out, int reset) {
 }
 #endif
 
+// Counts the non-finite entries of a (n values) into *count (grid-stride).
+__global__ void count_nonfinite_kernel(const double* __restrict__ a, int64_t n, unsigned long long* count) {
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += isfinite(a[i]) ? 0ull : 1ull;
+  // wavefront sum, one atomic per wavefront with any
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if (__lane_id() == 0 && c) atomicAdd(count, c);
+}
+
+hipError_t launch_count_nonfinite(const double* a, int64_t n, unsigned long long* count, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(count_nonfinite_kernel, dim3(blocks), dim3(256), 0, s, a, n, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_init_queues(unsigned long long* next, unsigned long long* end, const QueueInit& q, hipStream_t s) {
   hipLaunchKernelGGL(init_queues_kernel, dim3(1), dim3(64), 0, s, next, end, q);
   return hipGetLastError();

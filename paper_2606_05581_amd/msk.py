@@ -32,6 +32,14 @@ class MskError(RuntimeError):
         self.status = status
 
 
+class MskNumericError(MskError):
+    """A call that produced non-finite entries; `result` still holds its output."""
+
+    def __init__(self, status, msg, result):
+        super().__init__(status, msg)
+        self.result = result
+
+
 class BvhOpts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("top_nodes", C.c_int32)]
 
@@ -60,7 +68,8 @@ class DtnInfo(C.Structure):
     _fields_ = [("n_rows", C.c_int64), ("K", C.c_int64), ("walks_total", C.c_int64), ("queries_total", C.c_int64),
                 ("escaped_total", C.c_int64), ("capped_total", C.c_int64), ("discarded_rows", C.c_int64),
                 ("walk_kernel_ms", C.c_double), ("total_ms", C.c_double), ("walk_launches", C.c_int32),
-                ("nodes_visited", C.c_int64), ("tris_tested", C.c_int64), ("valu_flops", C.c_int64)]
+                ("nodes_visited", C.c_int64), ("tris_tested", C.c_int64), ("valu_flops", C.c_int64),
+                ("nonfinite_entries", C.c_int64)]
 
 
 class EigStats(C.Structure):
@@ -237,8 +246,11 @@ class Context:
                      **opts) -> "Dtn":
         o = self.default_opts(**opts)
         h = C.c_void_p()
-        self._check(lib().msk_estimate_dtn(self.h, mesh.h, rows.h, basis.h, walks, eps, inset_h,
-                                           EXTERIOR if exterior else INTERIOR, C.byref(o), C.byref(h)))
+        st = lib().msk_estimate_dtn(self.h, mesh.h, rows.h, basis.h, walks, eps, inset_h,
+                                    EXTERIOR if exterior else INTERIOR, C.byref(o), C.byref(h))
+        if st == ERR_NUMERIC and h.value:
+            raise MskNumericError(st, lib().msk_last_error(self.h).decode(), Dtn(self, h, rows.n, basis.K, walks))
+        self._check(st)
         return Dtn(self, h, rows.n, basis.K, walks)
 
     def estimate_dtn_batched(self, meshes, rows, bases, eps, insets, walks: int, exterior: bool = False, **opts):
@@ -248,8 +260,12 @@ class Context:
         outs = (C.c_void_p * n)()
         e = (C.c_double * n)(*eps)
         hh = (C.c_double * n)(*insets)
-        self._check(lib().msk_estimate_dtn_batched(self.h, n, arr(meshes), arr(rows), arr(bases), e, hh, walks,
-                                                   EXTERIOR if exterior else INTERIOR, C.byref(o), outs))
+        st = lib().msk_estimate_dtn_batched(self.h, n, arr(meshes), arr(rows), arr(bases), e, hh, walks,
+                                            EXTERIOR if exterior else INTERIOR, C.byref(o), outs)
+        if st == ERR_NUMERIC:
+            res = [Dtn(self, C.c_void_p(outs[i]), rows[i].n, bases[i].K, walks) for i in range(n)]
+            raise MskNumericError(st, lib().msk_last_error(self.h).decode(), res)
+        self._check(st)
         return [Dtn(self, C.c_void_p(outs[i]), rows[i].n, bases[i].K, walks) for i in range(n)]
 
     def batch(self, meshes, rows, bases, eps, insets, walks: int, exterior: bool = False, **opts) -> "Batch":

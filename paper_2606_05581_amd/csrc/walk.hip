@@ -54,10 +54,11 @@ __device__ __forceinline__ uint4 draw(const WalkLaunch& L, uint32_t row, uint32_
 // (l1, l2) are the barycentric weights of vertices b and c.
 //
 // In the face region the barycentrics are returned as numerators (l1, l2 =
-// vb, vc) over `den`; the caller divides only for a triangle that becomes
-// the best. A face whose squared plane distance exceeds `reject` by a safe
-// margin returns +inf without dividing: it cannot beat or tie a current best
-// of `reject`. Distances that are returned are exactly the values above.
+// vb, vc) over `den` (left unchanged in the other regions); they are divided
+// only where a walk's final nearest point is used. A face whose squared
+// plane distance exceeds `reject` by a safe margin returns +inf without
+// dividing: it cannot beat or tie a current best of `reject`. Distances that
+// are returned are exactly the values above.
 __host__ __device__ __forceinline__ float tri_dist2(float px, float py, float pz, const TriRec& T, float reject,
                                                    float& l1, float& l2, float& den_out, int& region) {
 #pragma clang fp contract(off)
@@ -163,12 +164,24 @@ __host__ __device__ __forceinline__ float prune_bound(float best, float slack) {
   return s * s * (1.0f + 0x1p-20f);
 }
 
+// l1, l2 are the barycentrics of the nearest point, or for a face-region
+// result their numerators over `den` (divided by nearest_bary where used).
 struct Nearest {
   float d2;
   int32_t slot;
   int32_t orig;
   float l1, l2;
+  float den = 1.0f;
 };
+
+__host__ __device__ __forceinline__ void nearest_bary(const Nearest& h, float& l1, float& l2) {
+  l1 = h.l1;
+  l2 = h.l2;
+  if (h.den != 1.0f) {
+    l1 = h.l1 / h.den;
+    l2 = h.l2 / h.den;
+  }
+}
 
 // FP32 operations of tri_dist2 up to each exit (vertex a, vertex b, edge ab,
 // vertex c, edge ac, edge bc, face, zero-area fallback); a box lower bound
@@ -194,11 +207,8 @@ __host__ __device__ __forceinline__ void test_tri(const TriRec* __restrict__ tri
   int32_t orig;
   memcpy(&orig, &T.a.w, 4);
   if (d < h.d2 || (d == h.d2 && orig < h.orig)) {
-    if (region == 6) {  // face barycentrics vb / den, vc / den
-      l1 = l1 / den;
-      l2 = l2 / den;
-    }
     h.d2 = d; h.slot = s; h.orig = orig; h.l1 = l1; h.l2 = l2;
+    h.den = region == 6 ? den : 1.0f;
   }
 }
 
@@ -334,7 +344,7 @@ struct CoopScratch {
   const TriRec* tris[64];  // lane's triangle array (batched meshes differ per lane)
   const Node4* nodes[64];  // lane's node array
   int32_t rec_slot[64];
-  float rec_l1[64], rec_l2[64];
+  float rec_l1[64], rec_l2[64], rec_den[64];
   uint32_t flops[64];  // statistics kernels only
 };
 
@@ -383,13 +393,10 @@ __device__ void coop_unit_round(CoopScratch* W, uint32_t lane, uint32_t nunit) {
         atomicMin(&W->key[o], key);
         lds_order();
         if (W->key[o] == key) {
-          if (region == 6) {
-            l1 = l1 / den;
-            l2 = l2 / den;
-          }
           W->rec_slot[o] = s;
           W->rec_l1[o] = l1;
           W->rec_l2[o] = l2;
+          W->rec_den[o] = den;
         }
       }
     }
@@ -510,7 +517,9 @@ __device__ void walk_contrib(const WalkLaunch& L, const MeshDev& M, const LaneWa
   if (has_t) {
     const int32_t* f = M.faces + 3 * (int64_t)hit.orig;
     tv[0] = f[0]; tv[1] = f[1]; tv[2] = f[2];
-    const double l1 = hit.l1, l2 = hit.l2;
+    float b1, b2;
+    nearest_bary(hit, b1, b2);
+    const double l1 = b1, l2 = b2;
     tw[0] = (1.0 - l1) - l2; tw[1] = l1; tw[2] = l2;
   }
   if (M.mode == kRowsPoint) {
@@ -539,8 +548,10 @@ __device__ void walk_record(const WalkLaunch& L, const MeshDev& M, const LaneWal
     const int64_t li = (int64_t)w.row * M.walks_per_row + ((int64_t)w.walk - L.walk_offset);
     M.log_status[li] = status;
     M.log_tri[li] = has_t ? hit.orig : -1;
-    M.log_bary[2 * li] = has_t ? hit.l1 : 0.0f;
-    M.log_bary[2 * li + 1] = has_t ? hit.l2 : 0.0f;
+    float b1, b2;
+    nearest_bary(hit, b1, b2);
+    M.log_bary[2 * li] = has_t ? b1 : 0.0f;
+    M.log_bary[2 * li + 1] = has_t ? b2 : 0.0f;
     M.log_queries[li] = w.queries;
   }
 }
@@ -575,7 +586,7 @@ __device__ void walk_finish_global(const WalkLaunch& L, const MeshDev& M, const 
 // most `chunk` walks) and flushes them into the FP64 rows.
 // Row-table slots per wavefront table (2^bits) and the occupancy the
 // persistent kernels are compiled for: with 64 slots, the cooperative leaf
-// scratch and 21 LDS-staged top nodes a workgroup holds 30.5 KB of LDS.
+// scratch and 21 LDS-staged top nodes a workgroup holds 29.8 KB of LDS.
 // The streaming kernel measured fastest on gfx950 at 4 waves per SIMD (128
 // VGPRs, few spills) against 3 (no spills) and 5, 6 (many spills); 32-slot
 // tables lost to their extra device atomics and 128 slots gained nothing.
@@ -1115,6 +1126,7 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
           hit.slot = W->rec_slot[lane];
           hit.l1 = W->rec_l1[lane];
           hit.l2 = W->rec_l2[lane];
+          hit.den = W->rec_den[lane];
           thr = prune_bound(hit.d2, slack);
         }
       }
@@ -1219,8 +1231,7 @@ __global__ void closest_points_kernel(const Node4* __restrict__ nodes, const Tri
   bvh_nearest<false>(nodes, tris, nullptr, 0, x, y, z, radius, h, cnt);
   tri[i] = h.orig;
   d2[i] = h.d2;
-  bary[2 * i] = h.l1;
-  bary[2 * i + 1] = h.l2;
+  nearest_bary(h, bary[2 * i], bary[2 * i + 1]);
 }
 
 // S_ij = (w_i / h) mean_ij, se_ij = (w_i / h) sqrt(var_ij / W_i), var with

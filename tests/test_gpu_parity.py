@@ -171,6 +171,27 @@ def test_plain_and_persistent_forms_agree(ctx):
     assert np.allclose(a["S"], b["S"], rtol=0, atol=1e-12 * np.abs(a["S"]).max())
 
 
+@pytest.mark.parametrize("exterior", [False, True])
+@pytest.mark.parametrize("mesh", ["soup", "degenerate"])
+def test_wavefront_and_lane_private_tests_agree(ctx, mesh, exterior):
+    """The persistent form tests each query's triangles cooperatively (whole
+    wavefront, lexicographic LDS minimum), the plain form one lane at a time:
+    over every query of these walks (tens of millions of triangle tests,
+    zero-area triangles included) both must pick the same nearest triangle
+    with the same distance and barycentrics, so the logs are identical."""
+    if mesh == "soup":
+        case = W.soup8_53k(N=300, walks=128).cases[0]
+    else:
+        V, F = _tiny_meshes()[4][1:]
+        case = W._point_case(V, F, 200, np.random.default_rng(17))
+    a = _gpu_estimate(ctx, case, 128, exterior, form=1)
+    b = _gpu_estimate(ctx, case, 128, exterior, form=0)
+    for k in ("status", "tri", "bary", "nq"):
+        assert np.array_equal(a[k], b[k]), k
+    print(f"[cooperative vs lane-private] {mesh} exterior={exterior}: {int(a['nq'].sum())} queries identical",
+          flush=True)
+
+
 def test_split_walk_ranges(ctx):
     """walk_offset continues the Philox walk counter: [0,40) + [40,96) = [0,96)."""
     case = W.unit_sphere_320().cases[0]

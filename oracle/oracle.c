@@ -23,6 +23,12 @@
  *     finite-difference-estimator and naive-stiffness-matrix): every walk
  *     contributes c = b(s) - b(t) to the row of its sample, b = barycentric
  *     interpolation of a per-vertex basis table (Sec. 3.4).
+ *   - The PSD estimator of Sec. 3.2 (Alg. 2; eqs. strong-markov-property,
+ *     ball-jump-kernel, volume-jump-kernel and the boxed estimator): the
+ *     largest tangent ball at each sample by bisection, ball points drawn
+ *     with density proportional to the ball's jump kernel outside a small cap
+ *     about s, in antithetic pairs, a walk from each, and the rank-one updates
+ *     d d^T with d = b(s) - b(t), summed into a K x K matrix.
  * The finalisation (scaling, standard errors), symmetrisation and eigen step
  * live in oracle.py.
  *
@@ -72,7 +78,7 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
  * exactly representable in both float and double. */
 double orc_uniform(uint32_t r) { return ((double)(r >> 9) + 0.5) * (1.0 / 8388608.0); }
 
-enum { PURPOSE_STEP = 0, PURPOSE_HAT_START = 1, PURPOSE_START_SPLIT = 2, PURPOSE_REENTRY = 3 };
+enum { PURPOSE_STEP = 0, PURPOSE_HAT_START = 1, PURPOSE_START_SPLIT = 2, PURPOSE_REENTRY = 3, PURPOSE_BALL = 4 };
 
 static void draw4(uint64_t seed, uint32_t row, uint32_t walk, uint32_t step, uint32_t purpose,
                   uint32_t mesh, double u[4]) {
@@ -755,5 +761,157 @@ void orc_estimate(const void* h, int mode_start, int exterior, int64_t n_rows, c
         log_sbary[2 * li + 1] = (float)lam[2];
       }
     }
+  }
+}
+
+/* ------------------------------------------------- PSD estimator (Sec. 3.2) */
+
+/* Largest ball inside the domain that touches the surface at s, centre
+ * c = s - r n (Sec. 3.2; Alg. 2, LargestTangentBall): bisection over
+ * r in [0, r_max] for `iters` steps; a radius is accepted when the nearest
+ * surface point of c is at least r - tol away (tol = half the walk's
+ * termination shell: a ball point outside the domain is then within the
+ * shell and its walk ends at once) and the ball lies inside the scene's
+ * bounding sphere (as every ball inside the domain does). Returns the last
+ * accepted radius (0 when none is: the sample is then dropped, Appendix A).
+ * s, n are scene-relative, n the outward unit normal. */
+double orc_tangent_ball(const void* h, const double* s, const double* n, double r_max, int iters, double tol) {
+  const OrcScene* sc = (const OrcScene*)h;
+  double lo = 0.0, hi = r_max;
+  for (int it = 0; it < iters; ++it) {
+    double mid = 0.5 * (lo + hi);
+    double c[3] = {s[0] - mid * n[0], s[1] - mid * n[1], s[2] - mid * n[2]};
+    int64_t tt;
+    double bb[3];
+    double d = sqrt(nearest(sc, c, &tt, bb));
+    if (d >= mid - tol && sqrt(dot3(c, c)) + mid <= sc->radius)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+/* Normaliser of the ball jump kernel J(s, z) = 1 / (2 pi |s - z|^3)
+ * (eq. ball-jump-kernel) over the sphere of radius r through s, without the
+ * cap of polar angle theta0 about s (angle at the centre): with
+ * u = sin(theta / 2), |s - z| = 2 r u and dz = 8 r^2 u du dphi, so
+ * int J dz = (1 / (2 r)) int_{u0}^{1} 2 / u^2 du = (1 / (2 r)) (1 / u0 - 1). */
+double orc_ball_jump_mass(double r, double theta0) {
+  double u0 = sin(0.5 * theta0);
+  return (1.0 / (2.0 * r)) * (1.0 / u0 - 1.0);
+}
+
+/* A point z on the tangent ball (centre c, radius r, outward normal n at s =
+ * c + r n) with density proportional to J(s, z) outside the cap, and its
+ * antithetic partner (azimuth + pi): u = sin(theta / 2) has density
+ * proportional to 1 / u^2 on [u0, 1], so 1 / u = 1 / u0 - xi (1 / u0 - 1);
+ * the azimuth is uniform. (Sec. 3.2, Implementation: importance sampling by
+ * the jump kernel, excluded cap, antithetic sampling.) */
+void orc_ball_point(const double* c, double r, const double* n, double theta0, double xi, double eta, int partner,
+                    double* z) {
+  double u0 = sin(0.5 * theta0);
+  double u = 1.0 / (1.0 / u0 - xi * (1.0 / u0 - 1.0));
+  double ct = 1.0 - 2.0 * u * u, st = 2.0 * u * sqrt(fmax(0.0, 1.0 - u * u));
+  double phi = 2.0 * M_PI * eta + (partner ? M_PI : 0.0);
+  double e1[3], e2[3];
+  frame(n, e1, e2);
+  for (int k = 0; k < 3; ++k) z[k] = c[k] + r * (ct * n[k] + st * (cos(phi) * e1[k] + sin(phi) * e2[k]));
+}
+
+/* Alg. 2 over point rows: row i is the sample s_i (face tri_i, barycentrics
+ * bary_i, outward normal n_i) standing for the area w_i of the surface.
+ * Each row draws `pairs` antithetic pairs of ball points (Philox purpose
+ * BALL, walk counter = pair index) and runs a walk from each (step streams
+ * of walk 2j and 2j+1). The boxed estimator with s stratified over rows and
+ * z importance-sampled gives, per pair p of row i,
+ *   X_p = alpha_i (d_1 d_1^T + d_2 d_2^T) / 2,  alpha_i = w_i Z_i / (2 pairs),
+ * with Z_i = orc_ball_jump_mass(r_i, theta0) the weight J / density and
+ * d = b(s_i) - b(t). The tangent-ball tolerance is eps / 2. Outputs: S = sum_p X_p and Q = sum_p X_p * X_p
+ * (elementwise), both K x K; per-row radius (0 = dropped) and Z; an optional
+ * walk log (n_rows x 2 pairs: status, terminal triangle, its barycentrics of
+ * vertices 1 and 2, queries). The basis is a dense per-vertex table tab
+ * (n_verts x K). */
+void orc_psd_estimate(const void* h, int64_t n_rows, const float* p, const float* nrm, const int32_t* tri,
+                      const float* bary, const double* w, const double* tab, int64_t K, int64_t pairs,
+                      double theta0, double r_max, int bisect_iters, double eps, double kappa,
+                      double delta, int64_t max_steps, uint64_t seed, uint32_t mesh, int nthreads, double* S,
+                      double* Q, double* radius, double* Zout, int64_t* n_query, int32_t* log_status,
+                      int64_t* log_tri, float* log_bary, int64_t* log_nquery) {
+  const OrcScene* sc = (const OrcScene*)h;
+  OrcWalkParams P = {eps, kappa, delta, max_steps, seed, mesh};
+  memset(S, 0, sizeof(double) * K * K);
+  memset(Q, 0, sizeof(double) * K * K);
+  (void)nthreads;
+  /* rows run in parallel; each row's sums are added to S and Q in the order
+   * the rows finish (FP64: the order changes only the last bits) */
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+  for (int64_t i = 0; i < n_rows; ++i) {
+    double s[3], n[3];
+    for (int k = 0; k < 3; ++k) {
+      s[k] = (double)p[3 * i + k] - sc->centre[k];
+      n[k] = nrm[3 * i + k];
+    }
+    double nl = sqrt(dot3(n, n));
+    for (int k = 0; k < 3; ++k) n[k] /= nl;
+    double r = orc_tangent_ball(h, s, n, r_max, bisect_iters, 0.5 * eps);
+    radius[i] = r;
+    Zout[i] = r > 0 ? orc_ball_jump_mass(r, theta0) : 0.0;
+    n_query[i] = bisect_iters;
+    if (r <= 0) continue;
+    double c[3] = {s[0] - r * n[0], s[1] - r * n[1], s[2] - r * n[2]};
+    double alpha = w[i] * Zout[i] / (2.0 * (double)pairs);
+    /* b(s) */
+    double* bs = (double*)calloc(K, sizeof(double));
+    double* d = (double*)malloc(sizeof(double) * 2 * K);
+    double* Si = (double*)calloc(K * K, sizeof(double));
+    double* Qi = (double*)calloc(K * K, sizeof(double));
+    for (int cc = 0; cc < 3; ++cc) {
+      int64_t v = sc->F[3 * (int64_t)tri[i] + cc];
+      for (int64_t k = 0; k < K; ++k) bs[k] += (double)bary[3 * i + cc] * tab[v * K + k];
+    }
+    for (int64_t j = 0; j < pairs; ++j) {
+      double u[4];
+      draw4(seed, (uint32_t)i, (uint32_t)j, 0, PURPOSE_BALL, mesh, u);
+      for (int a = 0; a < 2; ++a) {
+        double x[3];
+        orc_ball_point(c, r, n, theta0, u[0], u[1], a, x);
+        int64_t tt = -1, nq = 0, ns = 0;
+        double bt[3] = {0, 0, 0};
+        int st = walk(sc, &P, (uint32_t)i, (uint32_t)(2 * j + a), x, &tt, bt, &nq, &ns);
+        n_query[i] += nq;
+        for (int64_t k = 0; k < K; ++k) {
+          double b = 0.0;
+          if (st != ST_ESCAPED)
+            for (int cc = 0; cc < 3; ++cc) b += bt[cc] * tab[(int64_t)sc->F[3 * tt + cc] * K + k];
+          d[a * K + k] = bs[k] - b;
+        }
+        if (log_status) {
+          int64_t li = i * 2 * pairs + 2 * j + a;
+          log_status[li] = st;
+          log_tri[li] = tt;
+          log_bary[2 * li] = (float)bt[1];
+          log_bary[2 * li + 1] = (float)bt[2];
+          log_nquery[li] = nq;
+        }
+      }
+      for (int64_t k = 0; k < K; ++k)
+        for (int64_t l = 0; l < K; ++l) {
+          double x = 0.5 * alpha * (d[k] * d[l] + d[K + k] * d[K + l]);
+          Si[k * K + l] += x;
+          Qi[k * K + l] += x * x;
+        }
+    }
+#pragma omp critical
+    {
+      for (int64_t e = 0; e < K * K; ++e) {
+        S[e] += Si[e];
+        Q[e] += Qi[e];
+      }
+    }
+    free(bs);
+    free(d);
+    free(Si);
+    free(Qi);
   }
 }

@@ -15,7 +15,9 @@ definition:
 * ``steklov_modes`` -- the Steklov eigenproblem (Sec. 2, eq.
   steklov-eigenproblem) discretised with a lumped mass M = diag(w): the
   smallest k eigenpairs of M^-1/2 (S + S^T)/2 M^-1/2 by LAPACK (numpy.eigh),
-  eigenvectors mapped back by M^-1/2.
+  eigenvectors mapped back by M^-1/2;
+* ``psd_estimate`` -- the PSD estimator of Sec. 3.2 (Alg. 2), run in
+  ``oracle.c``, with ``psd_standard_error`` for its entries.
 """
 from __future__ import annotations
 
@@ -84,6 +86,19 @@ def lib():
                C.c_uint32, C.c_int]
             + [_P(C.c_double), _P(C.c_double), _P(C.c_int64), _P(C.c_int64), _P(C.c_int64), _P(C.c_int32)]
             + [_P(C.c_int32), _P(C.c_int64), _P(C.c_float), _P(C.c_int64), _P(C.c_int32), _P(C.c_float)]
+        )
+        L.orc_tangent_ball.argtypes = [C.c_void_p, _P(C.c_double), _P(C.c_double), C.c_double, C.c_int, C.c_double]
+        L.orc_tangent_ball.restype = C.c_double
+        L.orc_ball_jump_mass.argtypes = [C.c_double, C.c_double]
+        L.orc_ball_jump_mass.restype = C.c_double
+        L.orc_ball_point.argtypes = [_P(C.c_double), C.c_double, _P(C.c_double), C.c_double, C.c_double, C.c_double,
+                                     C.c_int, _P(C.c_double)]
+        L.orc_psd_estimate.argtypes = (
+            [C.c_void_p, C.c_int64, _P(C.c_float), _P(C.c_float), _P(C.c_int32), _P(C.c_float), _P(C.c_double),
+             _P(C.c_double), C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_int, C.c_double,
+             C.c_double, C.c_double, C.c_int64, C.c_uint64, C.c_uint32, C.c_int]
+            + [_P(C.c_double), _P(C.c_double), _P(C.c_double), _P(C.c_double), _P(C.c_int64)]
+            + [_P(C.c_int32), _P(C.c_int64), _P(C.c_float), _P(C.c_int64)]
         )
         _lib = L
     return _lib
@@ -299,3 +314,90 @@ def steklov_modes(S, w, k):
     lam, V = np.linalg.eigh(Cm)
     k = min(k, lam.shape[0])
     return lam[:k], m[:, None] * V[:, :k], keep
+
+
+# ------------------------------------------------- PSD estimator (Sec. 3.2)
+
+PSD_CAP_DEG = 2.5          # excluded cap about s (Sec. 3.2, Implementation), angle at the ball centre
+PSD_BISECT_ITERS = 10      # tangent-ball bisection steps (Sec. 3.2, Implementation)
+
+
+def psd_r_max(V):
+    """Largest tangent-ball radius: half the shortest side of the mesh's bounding box
+    (the diameter clamp of Appendix A, unbounded tangent balls)."""
+    V = np.asarray(V, dtype=np.float64)
+    return 0.5 * float((V.max(0) - V.min(0)).min())
+
+
+def tangent_ball(scene: Scene, s, n, r_max, iters=PSD_BISECT_ITERS, tol=5e-5):
+    """Radius of the largest ball inside the domain tangent at world point s (outward unit normal n),
+    overlapping the surface by less than tol."""
+    sr = _c(np.asarray(s, dtype=np.float64) - scene.centre, np.float64)
+    nn = _c(n, np.float64)
+    return float(lib().orc_tangent_ball(scene.h, _ptr(sr, C.c_double), _ptr(nn, C.c_double), r_max, iters, tol))
+
+
+def ball_jump_mass(r, theta0):
+    """Integral of the ball jump kernel 1/(2 pi |s-z|^3) over the sphere minus the cap of angle theta0."""
+    return float(lib().orc_ball_jump_mass(r, theta0))
+
+
+def ball_point(c, r, n, theta0, xi, eta, partner=0):
+    """The ball point drawn from uniforms (xi, eta), or its antithetic partner."""
+    cc, nn = _c(c, np.float64), _c(n, np.float64)
+    z = np.zeros(3)
+    lib().orc_ball_point(_ptr(cc, C.c_double), r, _ptr(nn, C.c_double), theta0, xi, eta, int(partner),
+                         _ptr(z, C.c_double))
+    return z
+
+
+def psd_estimate(scene: Scene, rows, table, pairs: int, eps: float, seed: int = 0, cap_deg=PSD_CAP_DEG,
+                 r_max=None, bisect_iters=PSD_BISECT_ITERS, kappa=2.0 ** -20, delta_rel=2.0 ** -21,
+                 max_steps=None, mesh: int = 0, log: bool = False, nthreads: int = 1):
+    """Alg. 2 over point rows with a dense per-vertex basis table (n_verts x K).
+
+    Returns S (K x K, the estimate), Q (sum of squared per-pair terms), se (its
+    standard error per entry), per-row tangent-ball radius (0 = dropped), the
+    jump-kernel mass Z, query counts and an optional walk log (n_rows x
+    2 pairs)."""
+    if rows.mode != "point":
+        raise ValueError("the PSD estimator takes point rows")
+    if max_steps is None:
+        max_steps = DEFAULT_MAX_STEPS["interior"]
+    if r_max is None:
+        r_max = psd_r_max(scene.V)
+    tab = _c(table, np.float64)
+    nv, K = tab.shape
+    n = rows.n_rows
+    S = np.zeros((K, K))
+    Q = np.zeros((K, K))
+    rad = np.zeros(n)
+    Z = np.zeros(n)
+    nq = np.zeros(n, dtype=np.int64)
+    W2 = 2 * pairs
+    if log:
+        ls = np.full((n, W2), -1, dtype=np.int32)
+        lt = np.full((n, W2), -1, dtype=np.int64)
+        lb = np.zeros((n, W2, 2), dtype=np.float32)
+        lq = np.zeros((n, W2), dtype=np.int64)
+    else:
+        ls = lt = lb = lq = None
+    p, nn, tri, bary = (_c(rows.p, np.float32), _c(rows.n, np.float32), _c(rows.tri, np.int32),
+                        _c(rows.bary, np.float32))
+    w = _c(rows.w, np.float64)
+    lib().orc_psd_estimate(scene.h, n, _ptr(p, C.c_float), _ptr(nn, C.c_float), _ptr(tri, C.c_int32),
+                           _ptr(bary, C.c_float), _ptr(w, C.c_double), _ptr(tab, C.c_double), K, pairs,
+                           np.deg2rad(cap_deg), r_max, bisect_iters, eps, kappa, delta_rel * scene.radius,
+                           max_steps, C.c_uint64(seed), mesh, nthreads, _ptr(S, C.c_double), _ptr(Q, C.c_double),
+                           _ptr(rad, C.c_double), _ptr(Z, C.c_double), _ptr(nq, C.c_int64),
+                           _ptr(ls, C.c_int32), _ptr(lt, C.c_int64), _ptr(lb, C.c_float), _ptr(lq, C.c_int64))
+    out = dict(S=S, Q=Q, se=psd_standard_error(S, Q, n * pairs), radius=rad, Z=Z, n_query=nq, pairs=pairs)
+    if log:
+        out.update(log_status=ls, log_tri=lt, log_bary=lb, log_nquery=lq)
+    return out
+
+
+def psd_standard_error(S, Q, n_pairs):
+    """Standard error of S = sum_p X_p over n_pairs pair terms, the pairs taken as
+    independent draws of n_pairs X_p: se^2 = (n_pairs Q - S^2) / (n_pairs - 1)."""
+    return np.sqrt(np.maximum(0.0, n_pairs * Q - S * S) / (n_pairs - 1.0))

@@ -152,7 +152,9 @@ void msk_rows_destroy(msk_rows* rows);
 
 /* Per-vertex basis table in CSR form (host): vertex v holds columns
  * col[rowptr[v] .. rowptr[v+1]) with values val[...], columns strictly
- * increasing within a vertex, 0 <= col < K, at most 32 entries per vertex.
+ * increasing within a vertex, 0 <= col < K. The walk estimators
+ * (msk_estimate_dtn and its batched forms) take at most 32 entries per
+ * vertex; the PSD estimator takes any (it uses a dense copy).
  * b(p) for p with barycentrics l on face (a,b,c) is
  * l_a table[a] + l_b table[b] + l_c table[c] (Sec. 3.4). */
 msk_status msk_basis_create(msk_ctx* ctx, const int32_t* rowptr, const int32_t* col, const float* val,
@@ -349,6 +351,76 @@ typedef struct {
  * estimate holds non-finite entries. */
 msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* dtn, int32_t k, double* evals, double* evecs,
                              msk_eig_stats* stats);
+
+/* ------------------------------------------ PSD estimator (Sec. 3.2, Alg. 2) */
+
+typedef struct {
+  double cap_deg;        /* cap about s left out of each tangent ball, as the
+                            polar angle at the ball centre in degrees (2.5)    */
+  int32_t bisect_iters;  /* tangent-ball bisection steps (10)                  */
+  double r_max;          /* largest tangent radius; <= 0: half the shortest
+                            side of the mesh's bounding box (Appendix A)       */
+  int64_t chunk_pairs;   /* pairs per gathered chunk (32768); device memory of
+                            the chunk buffers: 40 x chunk_pairs x K bytes      */
+} msk_psd_opts;
+
+void msk_psd_opts_default(msk_psd_opts* opts);
+
+typedef struct {
+  int64_t n_rows, K, pairs;
+  int64_t walks_total;     /* walks run (2 x pairs per row with a tangent ball) */
+  int64_t queries_total;   /* bisection and walk queries                       */
+  int64_t escaped_total, capped_total;
+  int64_t dropped_rows;    /* rows without a tangent ball (radius 0)           */
+  double mean_radius;      /* over rows with a tangent ball                    */
+  double r_max;            /* the radius bound used                            */
+  double tangent_ms;       /* table set-up and tangent-ball kernel             */
+  double walk_kernel_ms;   /* the walk launch                                  */
+  double gather_ms;        /* gathers of the update rows                       */
+  double product_ms;       /* the symmetric rank-k products                    */
+  double total_ms;
+  int64_t nonfinite_entries;
+} msk_psd_info;
+
+typedef struct {  /* optional host walk log, n_rows x 2 pairs entries each    */
+  int32_t* status;  /* MSK walk status (0 hit, 1 escaped, 2 capped), -1 = not run */
+  int32_t* tri;     /* terminal original triangle                           */
+  float* bary;      /* its barycentrics of vertices 1 and 2 (2 per walk)     */
+  int32_t* queries;
+} msk_psd_log;
+
+/* The paper's PSD estimate of the DtN stiffness matrix (Sec. 3.2, boxed
+ * estimator and Alg. 2; eqs. beurling-deny-bilinear, strong-markov-property,
+ * ball-jump-kernel, volume-jump-kernel) over point rows:
+ *   - row i's sample s_i (its face, barycentrics and outward face normal)
+ *     gets the largest inscribed tangent ball B_r(c), c = s - r n, by
+ *     bisection (a radius is accepted when c's nearest surface point is at
+ *     least r - eps/2 away and the ball lies in the scene's bounding sphere;
+ *     rows with no accepted radius are dropped);
+ *   - `pairs` antithetic pairs of points z on the ball are drawn with density
+ *     proportional to the ball jump kernel 1/(2 pi |s-z|^3) outside the cap
+ *     (Philox counter (row, pair, 0, purpose 4 << 24 | mesh_id)); walk 2j+a
+ *     of the row runs Walk-on-Spheres from the pair's point a with the step
+ *     streams of that walk index, stopping in the eps-shell (interior);
+ *   - each pair adds X = alpha_i (d_1 d_1^T + d_2 d_2^T)/2 with
+ *     d = b(s_i) - b(t), alpha_i = w_i Z_i / (2 pairs), Z_i = (1/(2 r_i))
+ *     (1/sin(cap/2) - 1) the kernel's mass outside the cap.
+ * S = sum of X (K x K, symmetric PSD by construction) and se = its standard
+ * error, the n_rows x pairs pair terms taken as independent draws:
+ * se^2 = (n Q - S^2)/(n - 1), Q = sum of X*X elementwise. The sums are FP64:
+ * the difference rows are gathered from a dense FP64 copy of the basis table
+ * and multiplied on the matrix cores (rocBLAS dsyrk).
+ *   S, se:  host, K x K doubles (se may be NULL);
+ *   radius: host, n_rows floats (tangent radii, 0 = dropped) or NULL;
+ *   log:    optional host walk log; info: optional.
+ * walk_opts: seed, max_steps, kappa, delta_rel, form, launch settings and
+ * mesh_id as for msk_estimate_dtn (walk_offset, se_target, record_log and
+ * collect_stats are ignored). Errors: INVALID_ARG for hat rows, pairs < 1,
+ * K > 8192, eps <= 0, a basis for another vertex count or a flat mesh;
+ * NUMERIC (outputs written) when an entry is not finite. */
+msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* mesh, const msk_rows* rows, const msk_basis* basis,
+                            int64_t pairs, double eps, const msk_dtn_opts* walk_opts, const msk_psd_opts* opts,
+                            double* S, double* se, float* radius, const msk_psd_log* log, msk_psd_info* info);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsk.so")
-SOURCES = ["walk.hip", "eigen.hip", "capi.cpp", "bvh_build.cpp", "symeig_host.cpp"]
+SOURCES = ["walk.hip", "psd.hip", "eigen.hip", "capi.cpp", "bvh_build.cpp", "symeig_host.cpp"]
+# rocBLAS: the symmetric rank-k products of the PSD estimator
+LIBS = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
@@ -25,7 +27,7 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     `defines` are extra NAME=VALUE macros (kernel tuning constants)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = out + ".tmp"
-    cmd = ([hipcc] + HIPCC_FLAGS + ["-D" + d for d in defines] + [os.path.join(CSRC, s) for s in SOURCES] +
+    cmd = ([hipcc] + HIPCC_FLAGS + ["-D" + d for d in defines] + [os.path.join(CSRC, s) for s in SOURCES] + LIBS +
            ["-o", tmp])
     if verbose:
         print(" ".join(cmd), file=sys.stderr)

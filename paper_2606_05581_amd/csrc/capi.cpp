@@ -10,6 +10,8 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "../../include/msk.h"
 #include "msk_internal.h"
 
@@ -20,6 +22,10 @@ struct msk_ctx {
   hipStream_t stream = nullptr;
   int n_cu = 256;
   std::string err;
+  rocblas_handle blas = nullptr;  // created on the first PSD estimate
+  ~msk_ctx() {
+    if (blas) rocblas_destroy_handle(blas);
+  }
 };
 
 struct msk_mesh {
@@ -58,6 +64,7 @@ struct msk_rows {
 struct msk_basis {
   msk_ctx* ctx = nullptr;
   int64_t nv = 0, K = 0;
+  int32_t max_row_nnz = 0;  // the walk estimators merge at most kMaxTableNnz entries per vertex
   int32_t* d_rowptr = nullptr;
   int32_t* d_col = nullptr;
   float* d_val = nullptr;
@@ -376,14 +383,17 @@ extern "C" msk_status msk_basis_create(msk_ctx* ctx, const int32_t* rowptr, cons
   if (nnz > 0 && (!col || !val)) return fail(ctx, MSK_ERR_INVALID_ARG, "basis col/val missing");
   for (int64_t v = 0; v < n_verts; ++v) {
     int32_t a = rowptr[v], b = rowptr[v + 1];
-    if (b < a || b - a > kMaxTableNnz) return fail(ctx, MSK_ERR_INVALID_ARG, "bad basis row " + std::to_string(v));
+    if (b < a) return fail(ctx, MSK_ERR_INVALID_ARG, "bad basis row " + std::to_string(v));
     for (int32_t e = a; e < b; ++e) {
       if (col[e] < 0 || col[e] >= K || (e > a && col[e] <= col[e - 1]) || !std::isfinite(val[e]))
         return fail(ctx, MSK_ERR_INVALID_ARG, "basis row " + std::to_string(v) + " columns must increase in [0,K)");
     }
   }
+  int32_t max_nnz = 0;
+  for (int64_t v = 0; v < n_verts; ++v) max_nnz = std::max(max_nnz, rowptr[v + 1] - rowptr[v]);
   msk_basis* b = new msk_basis();
   b->ctx = ctx;
+  b->max_row_nnz = max_nnz;
   b->nv = n_verts;
   b->K = K;
   hipError_t he;
@@ -452,10 +462,12 @@ struct Prepared {
 };
 
 msk_status check_problem(msk_ctx* ctx, const msk_mesh* m, const msk_rows* r, const msk_basis* b, int64_t walks,
-                         double eps, double h, int32_t side) {
+                         double eps, double h, int32_t side, bool row_sums = true) {
   if (!m || !r || !b) return fail(ctx, MSK_ERR_INVALID_ARG, "null mesh / rows / basis");
   if (r->mesh != m) return fail(ctx, MSK_ERR_INVALID_ARG, "rows were created for another mesh");
   if (b->nv != m->nv) return fail(ctx, MSK_ERR_INVALID_ARG, "basis vertex count differs from the mesh's");
+  if (row_sums && b->max_row_nnz > kMaxTableNnz)
+    return fail(ctx, MSK_ERR_INVALID_ARG, "the walk estimators take at most 32 basis entries per vertex");
   if (walks < 2 || walks > INT32_MAX) return fail(ctx, MSK_ERR_INVALID_ARG, "walks must be in 2..2^31-1");
   if (!(eps > 0) || !(h > eps) || !std::isfinite(h)) return fail(ctx, MSK_ERR_INVALID_ARG, "need 0 < eps < inset_h");
   if (side != MSK_INTERIOR && side != MSK_EXTERIOR) return fail(ctx, MSK_ERR_INVALID_ARG, "side must be 0 or 1");
@@ -1109,6 +1121,231 @@ extern "C" msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* d, int32_t 
   if (rc == 1) return fail(ctx, MSK_ERR_INVALID_ARG, err);
   if (rc == 3) return fail(ctx, MSK_ERR_DEVICE, err);
   if (rc == 4) return fail(ctx, MSK_ERR_NOT_CONVERGED, err.empty() ? "residual target not reached" : err);
+  return MSK_OK;
+}
+
+// -------------------------------------------------------- PSD estimator
+
+extern "C" void msk_psd_opts_default(msk_psd_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->cap_deg = 2.5;
+  o->bisect_iters = 10;
+  o->r_max = 0.0;
+  o->chunk_pairs = 32768;
+}
+
+extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const msk_rows* r, const msk_basis* b,
+                                       int64_t pairs, double eps, const msk_dtn_opts* walk_opts,
+                                       const msk_psd_opts* opts, double* S_out, double* se_out, float* radius_out,
+                                       const msk_psd_log* log_out, msk_psd_info* info) {
+  if (!ctx) return MSK_ERR_INVALID_ARG;
+  if (!S_out) return fail(ctx, MSK_ERR_INVALID_ARG, "S must be given");
+  if (!m || !r || !b) return fail(ctx, MSK_ERR_INVALID_ARG, "null mesh, rows or basis");
+  if (r->mode != MSK_ROWS_POINT) return fail(ctx, MSK_ERR_INVALID_ARG, "the PSD estimator takes point rows");
+  if (pairs < 1 || r->n * pairs < 2) return fail(ctx, MSK_ERR_INVALID_ARG, "need pairs >= 1 and >= 2 pairs in all");
+  if (r->n * 2 * pairs >= ((int64_t)1 << 40) || 2 * pairs > ((int64_t)1 << 31))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "too many walks");
+  if (b->K > 8192) return fail(ctx, MSK_ERR_INVALID_ARG, "the PSD estimator takes K <= 8192 basis functions");
+  msk_psd_opts po;
+  msk_psd_opts_default(&po);
+  if (opts) po = *opts;
+  if (!(po.cap_deg > 0.0 && po.cap_deg < 180.0)) return fail(ctx, MSK_ERR_INVALID_ARG, "cap_deg must be in (0, 180)");
+  if (po.bisect_iters < 1 || po.bisect_iters > 40) return fail(ctx, MSK_ERR_INVALID_ARG, "bisect_iters in 1..40");
+  if (po.chunk_pairs < 1) return fail(ctx, MSK_ERR_INVALID_ARG, "chunk_pairs must be >= 1");
+  msk_dtn_opts o;
+  msk_dtn_opts_default(&o);
+  if (walk_opts) o = *walk_opts;
+  if (o.form != MSK_FORM_PERSISTENT && o.form != MSK_FORM_PLAIN) return fail(ctx, MSK_ERR_INVALID_ARG, "bad form");
+  if (o.mesh_id < 0 || o.mesh_id > 0xFFFFFF) return fail(ctx, MSK_ERR_INVALID_ARG, "mesh_id must be < 2^24");
+  o.se_target = 0;
+  o.walk_offset = 0;
+  o.record_log = 1;
+  o.collect_stats = 0;
+  const int64_t W = 2 * pairs;
+  // the walk problem: interior walks; the inset is not used by ball starts
+  msk_status st = check_problem(ctx, m, r, b, W, eps, 2.0 * eps, MSK_INTERIOR, false);
+  if (st != MSK_OK) return st;
+  double r_max = po.r_max;
+  if (!(r_max > 0.0)) {  // half the shortest side of the bounding box (Appendix A, unbounded tangent balls)
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t v = 0; v < m->nv; ++v)
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(lo[k], (double)m->vworld[3 * v + k]);
+        hi[k] = std::max(hi[k], (double)m->vworld[3 * v + k]);
+      }
+    r_max = 0.5 * std::min(hi[0] - lo[0], std::min(hi[1] - lo[1], hi[2] - lo[2]));
+  }
+  if (!(r_max > 0.0)) return fail(ctx, MSK_ERR_INVALID_ARG, "flat mesh: no tangent balls");
+  if (!ctx->blas) {
+    if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
+      ctx->blas = nullptr;
+      return fail(ctx, MSK_ERR_DEVICE, "rocblas_create_handle failed");
+    }
+  }
+  if (rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success)
+    return fail(ctx, MSK_ERR_DEVICE, "rocblas_set_stream failed");
+
+  msk_dtn* d = nullptr;
+  st = alloc_dtn(ctx, r, b, W, true, &d);
+  if (st != MSK_OK) return st;
+  const int64_t K = b->K, n = d->n;
+  const int64_t chunk = std::min<int64_t>(po.chunk_pairs, n * pairs);
+  float* d_rad = nullptr;
+  double *d_tab = nullptr, *d_S = nullptr, *d_Q = nullptr, *d_se = nullptr, *d_U = nullptr, *d_V = nullptr;
+  hipEvent_t ev[6] = {};
+  auto cleanup = [&](msk_status s) {
+    dfree(d_rad);
+    dfree(d_tab);
+    dfree(d_S);
+    dfree(d_Q);
+    dfree(d_se);
+    dfree(d_U);
+    dfree(d_V);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    dtn_free(d);
+    delete d;
+    return s;
+  };
+#define HIP_P(expr)                                                                                   \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess)                                                                             \
+      return cleanup(fail(ctx, e_ == hipErrorOutOfMemory ? MSK_ERR_OOM : MSK_ERR_DEVICE,             \
+                          std::string(#expr) + ": " + hipGetErrorString(e_)));                        \
+  } while (0)
+  HIP_P(dalloc(&d_rad, n));
+  HIP_P(dalloc(&d_tab, b->nv * K));
+  HIP_P(dalloc(&d_S, K * K));
+  HIP_P(dalloc(&d_Q, K * K));
+  HIP_P(dalloc(&d_se, K * K));
+  HIP_P(dalloc(&d_U, 2 * chunk * K));
+  HIP_P(dalloc(&d_V, 3 * chunk * K));
+  for (hipEvent_t& e : ev) HIP_P(hipEventCreate(&e));
+  hipStream_t s = ctx->stream;
+  HIP_P(hipEventRecord(ev[0], s));
+  HIP_P(launch_fill_u64(d_tab, b->nv * K, 0, s));
+  HIP_P(launch_dense_table(b->d_rowptr, b->d_col, b->d_val, b->nv, K, d_tab, s));
+  HIP_P(launch_fill_u64(d_S, K * K, 0, s));
+  HIP_P(launch_fill_u64(d_Q, K * K, 0, s));
+  HIP_P(launch_fill_u64(d->d_q, n, 0, s));
+  HIP_P(launch_fill_u64(d->d_esc, n, 0, s));
+  HIP_P(launch_fill_u64(d->d_cap, n, 0, s));
+  HIP_P(launch_fill_u64(d->d_walks, n, (unsigned long long)W, s));
+  HIP_P(launch_fill_u32(d->d_disc, n, 0u, s));
+  HIP_P(launch_fill_u32(d->d_log_status, n * W, 0xFFFFFFFFu, s));
+  HIP_P(launch_fill_u32(d->d_log_tri, n * W, 0xFFFFFFFFu, s));
+  HIP_P(launch_fill_u32(d->d_log_bary, 2 * n * W, 0u, s));
+  HIP_P(launch_fill_u32(d->d_log_q, n * W, 0u, s));
+  MeshDev M = make_meshdev(m, r, b, d, eps, 2.0 * eps, MSK_INTERIOR, o, o.mesh_id);
+  M.ball_r = d_rad;
+  M.ball_u0 = std::sin(0.5 * po.cap_deg * M_PI / 180.0);
+  // tangent balls (tolerance: half the termination shell)
+  HIP_P(launch_tangent_ball(M, n, (float)r_max, po.bisect_iters, (float)(0.5 * eps), d_rad, s));
+  HIP_P(hipEventRecord(ev[1], s));
+  // walks from the balls
+  std::vector<MeshDev> meshes{M};
+  std::vector<RowSlot> slots(r->order.size());
+  for (size_t i = 0; i < slots.size(); ++i) slots[i] = RowSlot{0, r->order[i], 0u};
+  const int use_lds = (o.form == MSK_FORM_PERSISTENT && m->top_nodes > 0) ? 1 : 0;
+  double walk_ms = 0;
+  int64_t stats[3] = {0, 0, 0};
+  {
+    msk_status ws = run_walks(ctx, meshes, slots, W, 0, o, use_lds, m->top_nodes, &walk_ms, stats);
+    if (ws != MSK_OK) return cleanup(ws);
+  }
+  HIP_P(hipEventRecord(ev[2], s));
+  // rank-one updates: gather a chunk of pairs, then S += U^T U, Q += V^T V
+  PsdGather G;
+  G.tab = d_tab;
+  G.K = K;
+  G.pairs = pairs;
+  G.faces = m->d_faces;
+  G.tri = r->d_tri;
+  G.bary = r->d_bary;
+  G.w = r->d_w;
+  G.radius = d_rad;
+  G.u0 = M.ball_u0;
+  G.log_status = d->d_log_status;
+  G.log_tri = d->d_log_tri;
+  G.log_bary = d->d_log_bary;
+  float gather_ms = 0, prod_ms = 0;
+  const double one = 1.0;
+  for (int64_t q0 = 0; q0 < n * pairs; q0 += chunk) {
+    const int64_t nq = std::min(chunk, n * pairs - q0);
+    HIP_P(hipEventRecord(ev[3], s));
+    HIP_P(launch_psd_gather(G, q0, nq, d_U, d_V, s));
+    HIP_P(hipEventRecord(ev[4], s));
+    // column-major: U is K x (2 nq), V is K x (3 nq); C = A A^T (upper triangle)
+    if (rocblas_dsyrk(ctx->blas, rocblas_fill_upper, rocblas_operation_none, (rocblas_int)K, (rocblas_int)(2 * nq),
+                      &one, d_U, (rocblas_int)K, &one, d_S, (rocblas_int)K) != rocblas_status_success ||
+        rocblas_dsyrk(ctx->blas, rocblas_fill_upper, rocblas_operation_none, (rocblas_int)K, (rocblas_int)(3 * nq),
+                      &one, d_V, (rocblas_int)K, &one, d_Q, (rocblas_int)K) != rocblas_status_success)
+      return cleanup(fail(ctx, MSK_ERR_DEVICE, "rocblas_dsyrk failed"));
+    HIP_P(hipEventRecord(ev[5], s));
+    HIP_P(hipEventSynchronize(ev[5]));
+    float a = 0, c = 0;
+    HIP_P(hipEventElapsedTime(&a, ev[3], ev[4]));
+    HIP_P(hipEventElapsedTime(&c, ev[4], ev[5]));
+    gather_ms += a;
+    prod_ms += c;
+  }
+  HIP_P(launch_psd_finish(d_S, d_Q, K, (double)(n * pairs), d_se, s));
+  HIP_P(launch_fill_u64(d->d_nonfinite, 1, 0, s));
+  HIP_P(launch_count_nonfinite(d_S, K * K, d->d_nonfinite, s));
+  HIP_P(launch_count_nonfinite(d_se, K * K, d->d_nonfinite, s));
+  HIP_P(hipEventRecord(ev[3], s));
+  HIP_P(hipEventSynchronize(ev[3]));
+  float tot = 0, tb = 0;
+  HIP_P(hipEventElapsedTime(&tot, ev[0], ev[3]));
+  HIP_P(hipEventElapsedTime(&tb, ev[0], ev[1]));
+  // results to the host
+  HIP_P(hipMemcpy(S_out, d_S, K * K * 8, hipMemcpyDeviceToHost));
+  if (se_out) HIP_P(hipMemcpy(se_out, d_se, K * K * 8, hipMemcpyDeviceToHost));
+  std::vector<float> rad((size_t)n);
+  HIP_P(hipMemcpy(rad.data(), d_rad, n * 4, hipMemcpyDeviceToHost));
+  if (radius_out) std::memcpy(radius_out, rad.data(), n * 4);
+  if (log_out) {
+    if (log_out->status) HIP_P(hipMemcpy(log_out->status, d->d_log_status, n * W * 4, hipMemcpyDeviceToHost));
+    if (log_out->tri) HIP_P(hipMemcpy(log_out->tri, d->d_log_tri, n * W * 4, hipMemcpyDeviceToHost));
+    if (log_out->bary) HIP_P(hipMemcpy(log_out->bary, d->d_log_bary, n * W * 8, hipMemcpyDeviceToHost));
+    if (log_out->queries) HIP_P(hipMemcpy(log_out->queries, d->d_log_q, n * W * 4, hipMemcpyDeviceToHost));
+  }
+  {
+    msk_status cs = collect_info(ctx, d);
+    if (cs != MSK_OK) return cleanup(cs);
+  }
+  msk_psd_info I;
+  std::memset(&I, 0, sizeof(I));
+  I.n_rows = n;
+  I.K = K;
+  I.pairs = pairs;
+  I.queries_total = d->info.queries_total;
+  I.escaped_total = d->info.escaped_total;
+  I.capped_total = d->info.capped_total;
+  double rsum = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (rad[i] > 0) {
+      rsum += rad[i];
+      I.walks_total += W;
+    } else {
+      ++I.dropped_rows;
+    }
+  }
+  I.mean_radius = (n > I.dropped_rows) ? rsum / (double)(n - I.dropped_rows) : 0.0;
+  I.r_max = r_max;
+  I.tangent_ms = tb;
+  I.walk_kernel_ms = walk_ms;
+  I.gather_ms = gather_ms;
+  I.product_ms = prod_ms;
+  I.total_ms = tot;
+  I.nonfinite_entries = d->info.nonfinite_entries;
+  if (info) *info = I;
+#undef HIP_P
+  const bool bad = I.nonfinite_entries > 0;
+  cleanup(MSK_OK);
+  if (bad) return fail(ctx, MSK_ERR_NUMERIC, "non-finite entries in S or se");
   return MSK_OK;
 }
 

@@ -83,6 +83,8 @@ struct MeshDev {
   const double* ring_cum;
   const float* face_normals;
   const int32_t* discarded;    // per row (point rows)
+  const float* ball_r;         // PSD estimator: per-row tangent-ball radius (0 = dropped); null otherwise
+  double ball_u0;              // PSD estimator: sin(theta0 / 2) of the cap left out about s
   // basis table
   const int32_t* b_rowptr;
   const int32_t* b_col;
@@ -139,9 +141,31 @@ hipError_t launch_count_nonfinite(const double* a, int64_t n, unsigned long long
 hipError_t launch_init_queues(unsigned long long* next, unsigned long long* end, const QueueInit& q, hipStream_t s);
 hipError_t launch_fill_u64(void* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_tangent_ball(const MeshDev& M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius,
+                               hipStream_t s);
 hipError_t launch_discard(const MeshDev& M, int64_t n_rows, int32_t* discarded, hipStream_t s);
 hipError_t launch_closest_points(const Node4* nodes, const TriRec* tris, float radius, const double* c, const float* Q,
                                  int64_t nq, int32_t* tri, float* d2, float* bary, hipStream_t s);
 hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walks, const double* w, double* S,
                            double* se, hipStream_t s);
+
+// PSD estimator (psd.hip): per-pair inputs of the rank-one updates
+struct PsdGather {
+  const double* tab;        // dense per-vertex basis table, n_verts x K
+  int64_t K;
+  int64_t pairs;            // antithetic pairs per row
+  const int32_t* faces;     // original faces (n_tris x 3)
+  const int32_t* tri;       // sample face per row
+  const float* bary;        // sample barycentrics per row (n x 3)
+  const double* w;          // row weights
+  const float* radius;      // tangent-ball radius per row (0 = dropped)
+  double u0;                // sin(theta0 / 2)
+  const int32_t* log_status;  // walk log, n_rows x 2 pairs
+  const int32_t* log_tri;
+  const float* log_bary;
+};
+hipError_t launch_dense_table(const int32_t* rowptr, const int32_t* col, const float* val, int64_t nv, int64_t K,
+                              double* tab, hipStream_t s);
+hipError_t launch_psd_gather(const PsdGather& G, int64_t q0, int64_t nq, double* U, double* V, hipStream_t s);
+hipError_t launch_psd_finish(double* S, double* Q, int64_t K, double n_pairs, double* se, hipStream_t s);
 }  // namespace msk

@@ -38,7 +38,7 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 // Top 23 bits -> centre of one of 2^23 cells of (0,1); exact in binary32.
 __device__ __forceinline__ float unit_f(uint32_t r) { return ((float)(r >> 9) + 0.5f) * (1.0f / 8388608.0f); }
 
-enum : uint32_t { kPurposeStep = 0, kPurposeHatStart = 1, kPurposeSplit = 2, kPurposeReentry = 3 };
+enum : uint32_t { kPurposeStep = 0, kPurposeHatStart = 1, kPurposeSplit = 2, kPurposeReentry = 3, kPurposeBall = 4 };
 
 __device__ __forceinline__ uint4 draw(const WalkLaunch& L, uint32_t row, uint32_t walk, uint32_t step,
                                       uint32_t purpose, uint32_t mesh) {
@@ -421,10 +421,49 @@ struct LaneWalk {
   uint32_t ux, uy;  // direction uniforms of the current step (drawn before its query)
 };
 
+// Orthonormal frame (e1, e2) completing a unit vector n (branchless, after
+// Duff et al. 2017).
+__device__ __forceinline__ void onb(double nx, double ny, double nz, double e1[3], double e2[3]);
+
+// Start of a walk of the PSD estimator (Sec. 3.2, Alg. 2): a point z on the
+// tangent ball of row i's sample s (centre c = s - r n), drawn with density
+// proportional to the ball's jump kernel 1 / (2 pi |s - z|^3) outside the cap
+// of polar angle theta0 about s: u = sin(theta / 2) has density
+// proportional to 1 / u^2 on [sin(theta0 / 2), 1], inverted in closed form,
+// and the azimuth is uniform. Walks 2j and 2j + 1 are the antithetic pair j
+// (azimuth and azimuth + pi). Returns false if the row has no tangent ball.
+__device__ bool ball_start(const WalkLaunch& L, const MeshDev& M, LaneWalk& w, int32_t& face) {
+  const double r = (double)M.ball_r[w.row];
+  if (!(r > 0.0)) return false;
+  face = M.tri[w.row];
+  const double sx = M.p[3 * w.row], sy = M.p[3 * w.row + 1], sz = M.p[3 * w.row + 2];
+  double nx = M.n[3 * w.row], ny = M.n[3 * w.row + 1], nz = M.n[3 * w.row + 2];
+  const double nl = sqrt(nx * nx + ny * ny + nz * nz);
+  nx /= nl; ny /= nl; nz /= nl;
+  const double cx = sx - r * nx, cy = sy - r * ny, cz = sz - r * nz;
+  const uint4 u = draw(L, (uint32_t)w.row, w.walk >> 1, 0, kPurposeBall, (uint32_t)M.mesh_id);
+  const double xi = unit_f(u.x), eta = unit_f(u.y);
+  const double su = 1.0 / (1.0 / M.ball_u0 - xi * (1.0 / M.ball_u0 - 1.0));
+  const double ct = 1.0 - 2.0 * su * su, st = 2.0 * su * sqrt(fmax(0.0, 1.0 - su * su));
+  double sp, cp;
+  sincospi(2.0 * eta + ((w.walk & 1u) ? 1.0 : 0.0), &sp, &cp);
+  double e1[3], e2[3];
+  onb(nx, ny, nz, e1, e2);
+  w.x = (float)(cx + r * (ct * nx + st * (cp * e1[0] + sp * e2[0])));
+  w.y = (float)(cy + r * (ct * ny + st * (cp * e1[1] + sp * e2[1])));
+  w.z = (float)(cz + r * (ct * nz + st * (cp * e1[2] + sp * e2[2])));
+  w.slot = M.slot_of_tri[face];
+  w.step = 0;
+  w.queries = 0;
+  w.cnt = TravCount();
+  return true;
+}
+
 // Start of a walk: sample s (point rows: the fixed sample; hat rows:
 // s ~ phi_i / A_i on the vertex's one-ring), inset it along the face normal.
 // Returns false if the row is discarded.
 __device__ bool walk_start(const WalkLaunch& L, const MeshDev& M, LaneWalk& w, int32_t& face, double lam[3]) {
+  if (M.ball_r) return ball_start(L, M, w, face);
   const float sgn = M.side ? 1.0f : -1.0f;
   float sx, sy, sz, nx, ny, nz;
   if (M.mode == kRowsPoint) {
@@ -512,6 +551,7 @@ __device__ __forceinline__ void merge_rows(const MeshDev& M, const int32_t (&vtx
 template <typename Emit>
 __device__ void walk_contrib(const WalkLaunch& L, const MeshDev& M, const LaneWalk& w, bool has_t, const Nearest& hit,
                              Emit emit) {
+  if (M.ball_r) return;  // PSD walks: the rank-one updates are formed from the walk log
   int32_t tv[3] = {-1, -1, -1};
   double tw[3] = {0.0, 0.0, 0.0};
   if (has_t) {
@@ -661,8 +701,6 @@ __device__ void table_flush(const WalkLaunch& L, WaveTables<AccT>& T, int wi, in
   __builtin_amdgcn_wave_barrier();
 }
 
-// Orthonormal frame (e1, e2) completing a unit vector n (branchless, after
-// Duff et al. 2017).
 __device__ __forceinline__ void onb(double nx, double ny, double nz, double e1[3], double e2[3]) {
   const double sg = nz >= 0 ? 1.0 : -1.0;
   const double a = -1.0 / (sg + nz);
@@ -1202,6 +1240,37 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
 
 // Point rows whose inset point is closer than h/2 to the surface are
 // discarded (the inset left the thin region it should probe).
+// Largest ball inside the domain tangent at each point row's sample s, centre
+// c = s - r n (Sec. 3.2; Alg. 2, LargestTangentBall): bisection over
+// [0, r_max], `iters` exact nearest-triangle queries from c; a radius is
+// accepted when c's nearest surface point is at least r - tol away and the
+// ball lies inside the scene's bounding sphere. 0 = no radius accepted.
+__global__ void tangent_ball_kernel(MeshDev M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows) return;
+  const float sx = M.p[3 * i], sy = M.p[3 * i + 1], sz = M.p[3 * i + 2];
+  double nx = M.n[3 * i], ny = M.n[3 * i + 1], nz = M.n[3 * i + 2];
+  const double nl = sqrt(nx * nx + ny * ny + nz * nz);
+  nx /= nl; ny /= nl; nz /= nl;
+  float lo = 0.0f, hi = r_max;
+  for (int32_t it = 0; it < iters; ++it) {
+    const float mid = 0.5f * (lo + hi);
+    const double cxd = sx - mid * nx, cyd = sy - mid * ny, czd = sz - mid * nz;
+    const float cx = (float)cxd, cy = (float)cyd, cz = (float)czd;
+    Nearest h;
+    h.d2 = INFINITY; h.orig = INT_MAX; h.slot = M.slot_of_tri[M.tri[i]];
+    TravCount cnt;
+    bvh_nearest<false>(M.nodes, M.tris, nullptr, 0, cx, cy, cz, M.radius, h, cnt);
+    const bool inside = sqrtf(h.d2) >= mid - tol && sqrt(cxd * cxd + cyd * cyd + czd * czd) + mid <= M.radius_d;
+    if (inside)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  radius[i] = lo;
+  atomicAdd(M.row_queries + i, (unsigned long long)iters);
+}
+
 __global__ void discard_kernel(MeshDev M, int64_t n_rows, int32_t* discarded) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rows) return;
@@ -1356,6 +1425,14 @@ hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s) {
 hipError_t launch_discard(const MeshDev& M, int64_t n_rows, int32_t* discarded, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(discard_kernel, dim3(blocks_for(n_rows, 128)), dim3(128), 0, s, M, n_rows, discarded);
+  return hipGetLastError();
+}
+
+hipError_t launch_tangent_ball(const MeshDev& M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius,
+                               hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tangent_ball_kernel, dim3(blocks_for(n_rows, 128)), dim3(128), 0, s, M, n_rows, r_max, iters,
+                     tol, radius);
   return hipGetLastError();
 }
 

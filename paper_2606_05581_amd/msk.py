@@ -89,6 +89,23 @@ class TuneResult(C.Structure):
                 ("walks_per_s", C.c_double), ("trials", C.c_int32), ("from_cache", C.c_int32)]
 
 
+class PsdOpts(C.Structure):
+    _fields_ = [("cap_deg", C.c_double), ("bisect_iters", C.c_int32), ("r_max", C.c_double),
+                ("chunk_pairs", C.c_int64)]
+
+
+class PsdInfo(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("K", C.c_int64), ("pairs", C.c_int64), ("walks_total", C.c_int64),
+                ("queries_total", C.c_int64), ("escaped_total", C.c_int64), ("capped_total", C.c_int64),
+                ("dropped_rows", C.c_int64), ("mean_radius", C.c_double), ("r_max", C.c_double),
+                ("tangent_ms", C.c_double), ("walk_kernel_ms", C.c_double), ("gather_ms", C.c_double),
+                ("product_ms", C.c_double), ("total_ms", C.c_double), ("nonfinite_entries", C.c_int64)]
+
+
+class PsdLog(C.Structure):
+    _fields_ = [("status", C.c_void_p), ("tri", C.c_void_p), ("bary", C.c_void_p), ("queries", C.c_void_p)]
+
+
 _lib = None
 
 # symbol name -> (argtypes, restype); the C ABI declared in include/msk.h
@@ -126,6 +143,10 @@ SIGNATURES = {
     "msk_batch_destroy": ([C.c_void_p], None),
     "msk_tune_space_default": ([C.POINTER(TuneSpace)], None),
     "msk_mesh_rebuild": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
+    "msk_psd_opts_default": ([C.POINTER(PsdOpts)], None),
+    "msk_estimate_psd": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.POINTER(DtnOpts),
+                          C.POINTER(PsdOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PsdLog),
+                          C.POINTER(PsdInfo)], C.c_int),
     "msk_autotune": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.POINTER(TuneSpace),
                       C.POINTER(TuneResult)], C.c_int),
@@ -301,6 +322,34 @@ class Context:
                                        (C.c_double * n)(*insets), EXTERIOR if exterior else INTERIOR, C.byref(sp),
                                        C.byref(res)))
         return {f: getattr(res, f) for f, _ in TuneResult._fields_}
+
+    def estimate_psd(self, mesh, rows, basis, pairs: int, eps: float, cap_deg: float = 2.5, bisect_iters: int = 10,
+                     r_max: float = 0.0, chunk_pairs: int = 32768, log: bool = False, **walk_opts) -> dict:
+        """The PSD estimator (Alg. 2) over point rows: S, se (K x K), tangent radii, info and optionally the walk log."""
+        o = self.default_opts(**walk_opts)
+        po = PsdOpts()
+        lib().msk_psd_opts_default(C.byref(po))
+        po.cap_deg, po.bisect_iters, po.r_max, po.chunk_pairs = cap_deg, bisect_iters, r_max, chunk_pairs
+        K, n, W = int(basis.K), int(rows.n), 2 * int(pairs)
+        S = np.zeros((K, K))
+        se = np.zeros((K, K))
+        rad = np.zeros(n, dtype=np.float32)
+        info = PsdInfo()
+        lg = None
+        out = {}
+        if log:
+            out = dict(status=np.zeros((n, W), dtype=np.int32), tri=np.zeros((n, W), dtype=np.int32),
+                       bary=np.zeros((n, W, 2), dtype=np.float32), nq=np.zeros((n, W), dtype=np.int32))
+            lg = PsdLog(out["status"].ctypes.data, out["tri"].ctypes.data, out["bary"].ctypes.data,
+                        out["nq"].ctypes.data)
+        st = lib().msk_estimate_psd(self.h, mesh.h, rows.h, basis.h, int(pairs), eps, C.byref(o), C.byref(po),
+                                    S.ctypes.data, se.ctypes.data, rad.ctypes.data,
+                                    C.byref(lg) if lg is not None else None, C.byref(info))
+        res = dict(S=S, se=se, radius=rad, info={f: getattr(info, f) for f, _ in PsdInfo._fields_}, **out)
+        if st == ERR_NUMERIC:
+            raise MskNumericError(st, lib().msk_last_error(self.h).decode(), res)
+        self._check(st)
+        return res
 
     def steklov_modes(self, dtn: "Dtn", k: int, vectors: bool = True):
         evals = np.zeros(k)

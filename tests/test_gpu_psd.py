@@ -1,0 +1,145 @@
+"""GPU parity of the PSD estimator (Sec. 3.2, Alg. 2) against the CPU oracle.
+
+Both sides draw the same Philox streams. The GPU takes its tangent-ball and
+walk decisions with exact FP32 nearest-triangle queries and the oracle with
+FP64 ones, so a few rows and walks diverge; the bar is:
+  * tangent radii equal within two bisection steps for at least 99% of rows;
+  * terminal triangles of the walks identical for at least 97% of walks;
+  * every entry of S within 4 combined standard errors (plus 1e-9 |S|) of the
+    oracle's, S symmetric positive semidefinite;
+  * on the unit sphere, degree <= 2 harmonics match the capped Steklov form.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2606_05581_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2606_05581_amd import msk
+
+    assert torch.cuda.is_available(), "GPU test needs a visible MI355X"
+    c = msk.Context(0)
+    yield c
+    c.close()
+
+
+def _dense_basis(tab):
+    return W.dense_basis(np.asarray(tab, dtype=np.float32))
+
+
+def _sh_l2(P):
+    x, y, z = P[:, 0], P[:, 1], P[:, 2]
+    c0 = 0.5 / math.sqrt(math.pi)
+    c1 = math.sqrt(3.0 / (4 * math.pi))
+    c2 = math.sqrt(15.0 / (4 * math.pi))
+    c20 = math.sqrt(5.0 / (16 * math.pi))
+    c22 = math.sqrt(15.0 / (16 * math.pi))
+    cols = [np.full_like(x, c0), c1 * y, c1 * z, c1 * x, c2 * x * y, c2 * y * z, c20 * (3 * z * z - 1), c2 * x * z,
+            c22 * (x * x - y * y)]
+    return np.stack(cols, 1), [0, 1, 1, 1, 2, 2, 2, 2, 2]
+
+
+def _run_both(ctx, oracle_mod, V, F, rows, tab, pairs, eps, seed, **kw):
+    mesh = ctx.build_bvh(V, F)
+    rh = ctx.rows(mesh, rows)
+    bh = ctx.basis(_dense_basis(tab), V.shape[0])
+    g = ctx.estimate_psd(mesh, rh, bh, pairs, eps, seed=seed, log=True, **kw)
+    sc = oracle_mod.Scene(V.astype(np.float32), F, bvh=True)
+    o = oracle_mod.psd_estimate(sc, rows, tab.astype(np.float32).astype(np.float64), pairs, eps, seed=seed,
+                                log=True, nthreads=8)
+    return g, o
+
+
+def _check_parity(g, o, r_max, label):
+    step = r_max / 2 ** 10
+    same_r = np.abs(g["radius"].astype(np.float64) - o["radius"]) <= 2 * step
+    frac_r = same_r.mean()
+    same_t = (g["tri"] == o["log_tri"]) & same_r[:, None]
+    frac_t = same_t[same_r].mean()
+    tol = 4 * np.sqrt(g["se"] ** 2 + o["se"] ** 2) + 1e-9 * np.abs(o["S"]).max()
+    bad = np.abs(g["S"] - o["S"]) > tol
+    print(f"[psd parity] {label}: radii agree {frac_r:.4f}, terminal triangles agree {frac_t:.4f}, "
+          f"entries outside 4 combined se {int(bad.sum())}/{bad.size}, dropped rows {g['info']['dropped_rows']}",
+          flush=True)
+    assert frac_r >= 0.99
+    assert frac_t >= 0.97
+    assert not bad.any(), np.argwhere(bad)[:5]
+    S = g["S"]
+    assert np.array_equal(S, S.T)
+    lam = np.linalg.eigvalsh(S)
+    assert lam.min() >= -1e-12 * max(lam.max(), 1e-300)
+
+
+def test_psd_soup_parity(ctx, oracle_mod):
+    """Overlapping ellipsoids, tori and a fin (non-manifold, self-intersecting)
+    with a dense coordinate / quadratic / trigonometric basis."""
+    case = W.soup8_53k(N=400, walks=16).cases[0]
+    P = case.V.astype(np.float64)
+    tab = np.stack([np.ones(len(P)), P[:, 0], P[:, 1], P[:, 2], P[:, 0] * P[:, 1], P[:, 1] * P[:, 2],
+                    P[:, 2] ** 2 - P[:, 0] ** 2, np.sin(3 * P[:, 0]), np.cos(2 * P[:, 1] + P[:, 2])], 1)
+    g, o = _run_both(ctx, oracle_mod, case.V, case.F, case.rows, tab, 32, case.eps, seed=7)
+    _check_parity(g, o, oracle_mod.psd_r_max(case.V), "soup8 K=9")
+    assert g["info"]["escaped_total"] == 0
+
+
+def test_psd_unit_sphere_closed_form_and_parity(ctx, oracle_mod):
+    V, F = W.icosphere_recursive(4)
+    V = V / np.linalg.norm(V, axis=1, keepdims=True)
+    rows = W.point_rows(V, F, 1500, np.random.default_rng(21))
+    tab, deg = _sh_l2(V)
+    g, o = _run_both(ctx, oracle_mod, V.astype(np.float32), F, rows, tab, 64, 1e-4, seed=3)
+    _check_parity(g, o, 1.0, "unit sphere K=9")
+    S, se = g["S"], g["se"]
+    t0 = math.radians(2.5)
+    rbar = float(np.mean(g["radius"]))
+    want = {l: l - 0.5 * math.sin(0.5 * t0) * l * (l + 1) * rbar for l in (1, 2)}
+    for i in range(1, 9):
+        assert abs(S[i, i] - want[deg[i]]) <= 4 * se[i, i] + 0.03 * want[deg[i]], (i, S[i, i], want[deg[i]])
+
+
+def test_psd_wide_basis_and_chunks(ctx, oracle_mod):
+    """K = 300 random dense columns (more columns than gather threads), and the
+    result does not depend on the chunking of the pairs (up to FP64 rounding)."""
+    V, F = W.box_grid(4, half=(0.8, 0.5, 0.6))
+    rows = W.point_rows(V, F, 120, np.random.default_rng(4))
+    tab = np.random.default_rng(9).normal(size=(V.shape[0], 300))
+    g, o = _run_both(ctx, oracle_mod, V.astype(np.float32), F, rows, tab, 8, 1e-3, seed=12)
+    _check_parity(g, o, oracle_mod.psd_r_max(V), "box K=300")
+    mesh = ctx.build_bvh(V.astype(np.float32), F)
+    rh = ctx.rows(mesh, rows)
+    bh = ctx.basis(_dense_basis(tab), V.shape[0])
+    g2 = ctx.estimate_psd(mesh, rh, bh, 8, 1e-3, seed=12, chunk_pairs=37)
+    assert np.allclose(g2["S"], g["S"], rtol=0, atol=1e-12 * np.abs(g["S"]).max())
+    assert np.array_equal(g2["radius"], g["radius"])
+
+
+def test_psd_argument_errors(ctx):
+    from paper_2606_05581_amd import msk
+
+    wl = W.unit_sphere_320()
+    case = wl.cases[0]
+    mesh = ctx.build_bvh(case.V, case.F)
+    hat = ctx.rows(mesh, case.rows)  # hat rows: not accepted
+    bh = ctx.basis(case.basis, case.V.shape[0])
+    with pytest.raises(msk.MskError) as e:
+        ctx.estimate_psd(mesh, hat, bh, 4, 1e-3)
+    assert e.value.status == msk.ERR_INVALID_ARG
+    rows = W.point_rows(case.V.astype(np.float64), case.F, 50, np.random.default_rng(1))
+    rh = ctx.rows(mesh, rows)
+    with pytest.raises(msk.MskError):
+        ctx.estimate_psd(mesh, rh, bh, 0, 1e-3)
+    with pytest.raises(msk.MskError):
+        ctx.estimate_psd(mesh, rh, bh, 4, 1e-3, cap_deg=0.0)
+    # a wide dense basis is fine for the PSD estimator but not for the row-sum walk estimator
+    wide = ctx.basis(_dense_basis(np.ones((case.V.shape[0], 40))), case.V.shape[0])
+    with pytest.raises(msk.MskError) as e:
+        ctx.estimate_dtn(mesh, rh, wide, 16, 1e-3, 0.05)
+    assert e.value.status == msk.ERR_INVALID_ARG

@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 KERNEL_NAME = "walk_stream_kernel"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz
+FP64_MATRIX_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix-core peak
 NODE_BYTES, TRI_BYTES = 128, 48
 DEFAULT_WORKLOAD = "batch64_mixed"
 
@@ -129,6 +130,57 @@ class Runner:
         return recs
 
 
+def psd_leg(ctx):
+    """The PSD estimator (Alg. 2) on its own workload: one untimed warm-up call,
+    then one timed call (tangent balls, walks, gathers and products; inputs
+    resident). Rooflines: the gather kernel against HBM (algorithmic bytes:
+    per pair six table rows read and five update rows written, per row three
+    table rows), the symmetric rank-k products against the FP64 matrix peak
+    (5 K (K+1) flops per pair)."""
+    import torch
+
+    from paper_2606_05581_amd import workloads as W
+
+    t = time.perf_counter()
+    wl = W.load("psd_sh_sphere_2m", cache=False)
+    case = wl.cases[0]
+    pairs = wl.walks // 2
+    mesh = ctx.build_bvh(case.V, case.F)
+    rh = ctx.rows(mesh, case.rows)
+    bh = ctx.basis(case.basis, case.V.shape[0])
+    torch.cuda.synchronize()
+    log(f"[bench] psd workload: {case.F.shape[0]} triangles, {case.rows.n_rows} rows x {pairs} pairs, "
+        f"K={case.basis.K} (inputs ready in {time.perf_counter() - t:.1f} s)")
+    ctx.estimate_psd(mesh, rh, bh, 4, case.eps)  # untimed warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.estimate_psd(mesh, rh, bh, pairs, case.eps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = r["info"]
+    K, n = int(info["K"]), int(info["n_rows"])
+    n_pairs = n * pairs
+    flops = 5.0 * K * (K + 1) * n_pairs
+    gbytes = n_pairs * (11.0 * K * 8 + 2 * 16) + n * 3.0 * K * 8
+    prod_tf = flops / (info["product_ms"] * 1e-3) / 1e12
+    gath = gbytes / (info["gather_ms"] * 1e-3) / 1e9
+    log(f"[bench] psd: {info['walks_total'] / el:.3e} walks/s; walks {info['walk_kernel_ms']:.1f} ms, gathers "
+        f"{info['gather_ms']:.1f} ms, products {info['product_ms']:.1f} ms ({prod_tf:.1f} TFLOP/s)")
+    return {
+        "workload": wl.name, "rows": n, "pairs_per_row": pairs, "K": K, "triangles": int(case.F.shape[0]),
+        "value": info["walks_total"] / el, "unit": "walks/s", "pairs_per_s": n_pairs / el, "seconds": el,
+        "ms": {k: info[k] for k in ("tangent_ms", "walk_kernel_ms", "gather_ms", "product_ms", "total_ms")},
+        "mean_radius": info["mean_radius"], "dropped_rows": info["dropped_rows"],
+        "S_trace": float(np.trace(r["S"])),
+        "roofline": {
+            "product": {"bound": "mfma", "achieved": prod_tf, "peak": FP64_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": prod_tf / FP64_MATRIX_PEAK_TFLOPS, "dtype": "f64"},
+            "gather": {"bound": "hbm", "achieved": gath, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": gath / HBM_PEAK_GBS},
+        },
+    }
+
+
 def cpu_baseline(wl, target_s, max_threads=16, max_meshes=8):
     """The oracle (FP64 walks, its own BVH) on a bounded sample of rows."""
     from oracle import oracle as O
@@ -176,6 +228,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-psd", action="store_true", help="skip the PSD estimator (Alg. 2) leg")
+    ap.add_argument("--psd-only", action="store_true", help="run only the PSD estimator leg (profiling)")
     ap.add_argument("--launch", default="", help="fixed launch settings instead of tuning, e.g. chunk=64,regen_min=16")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2606_05581_amd", "tune_cache.jsonl"),
                     help="autotuner results (JSON lines); a stored entry for this workload is reused, else the "
@@ -193,6 +247,9 @@ def main():
     from paper_2606_05581_amd import msk
     from paper_2606_05581_amd import workloads as W
 
+    if args.psd_only:
+        print(json.dumps({"psd": psd_leg(msk.Context(0))}), flush=True)
+        return
     t = time.perf_counter()
     wl = W.load(args.workload)
     n_tris = int(sum(c.F.shape[0] for c in wl.cases))
@@ -337,6 +394,7 @@ def main():
         "vs_plain_walk_kernels": (walks / (kern_ms * 1e-3) / plain["walks_per_s_walk_kernels"]) if plain else None,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "psd": None if args.no_psd else psd_leg(ctx),
     }
     print(json.dumps(line), flush=True)
 

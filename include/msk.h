@@ -360,8 +360,10 @@ typedef struct {
   int32_t bisect_iters;  /* tangent-ball bisection steps (10)                  */
   double r_max;          /* largest tangent radius; <= 0: half the shortest
                             side of the mesh's bounding box (Appendix A)       */
-  int64_t chunk_pairs;   /* pairs per gathered chunk (32768); device memory of
-                            the chunk buffers: 40 x chunk_pairs x K bytes      */
+  int64_t chunk_pairs;   /* pairs per gathered chunk (262144); device memory of
+                            the chunk buffers: 40 x chunk_pairs x K bytes (K
+                            rounded up to 64), plus up to 512 MB of partial
+                            sums of the products                             */
 } msk_psd_opts;
 
 void msk_psd_opts_default(msk_psd_opts* opts);
@@ -409,7 +411,7 @@ typedef struct {  /* optional host walk log, n_rows x 2 pairs entries each    */
  * error, the n_rows x pairs pair terms taken as independent draws:
  * se^2 = (n Q - S^2)/(n - 1), Q = sum of X*X elementwise. The sums are FP64:
  * the difference rows are gathered from a dense FP64 copy of the basis table
- * and multiplied on the matrix cores (rocBLAS dsyrk).
+ * and multiplied on the matrix cores (FP64 MFMA, symmetric rank-k blocks).
  *   S, se:  host, K x K doubles (se may be NULL);
  *   radius: host, n_rows floats (tangent radii, 0 = dropped) or NULL;
  *   log:    optional host walk log; info: optional.

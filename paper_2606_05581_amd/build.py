@@ -7,8 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsk.so")
 SOURCES = ["walk.hip", "psd.hip", "eigen.hip", "capi.cpp", "bvh_build.cpp", "symeig_host.cpp"]
-# rocBLAS: the symmetric rank-k products of the PSD estimator
-LIBS = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+LIBS = []
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

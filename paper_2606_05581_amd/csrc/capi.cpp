@@ -10,8 +10,6 @@
 #include <string>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "../../include/msk.h"
 #include "msk_internal.h"
 
@@ -22,10 +20,6 @@ struct msk_ctx {
   hipStream_t stream = nullptr;
   int n_cu = 256;
   std::string err;
-  rocblas_handle blas = nullptr;  // created on the first PSD estimate
-  ~msk_ctx() {
-    if (blas) rocblas_destroy_handle(blas);
-  }
 };
 
 struct msk_mesh {
@@ -1132,7 +1126,7 @@ extern "C" void msk_psd_opts_default(msk_psd_opts* o) {
   o->cap_deg = 2.5;
   o->bisect_iters = 10;
   o->r_max = 0.0;
-  o->chunk_pairs = 32768;
+  o->chunk_pairs = 262144;
 }
 
 extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const msk_rows* r, const msk_basis* b,
@@ -1177,22 +1171,19 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
     r_max = 0.5 * std::min(hi[0] - lo[0], std::min(hi[1] - lo[1], hi[2] - lo[2]));
   }
   if (!(r_max > 0.0)) return fail(ctx, MSK_ERR_INVALID_ARG, "flat mesh: no tangent balls");
-  if (!ctx->blas) {
-    if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
-      ctx->blas = nullptr;
-      return fail(ctx, MSK_ERR_DEVICE, "rocblas_create_handle failed");
-    }
-  }
-  if (rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success)
-    return fail(ctx, MSK_ERR_DEVICE, "rocblas_set_stream failed");
-
   msk_dtn* d = nullptr;
   st = alloc_dtn(ctx, r, b, W, true, &d);
   if (st != MSK_OK) return st;
-  const int64_t K = b->K, n = d->n;
+  const int64_t K = b->K, n = d->n, Kp = (K + 63) / 64 * 64;
   const int64_t chunk = std::min<int64_t>(po.chunk_pairs, n * pairs);
+  // partial-sum slots of the matrix-core products: 4 per row slice, at most
+  // 1024 slices and about 256 MB per matrix
+  const int64_t nblk = psd_blocks(Kp);
+  const int64_t slices = std::max<int64_t>(1, std::min<int64_t>(1024, ((int64_t)1 << 28) / (nblk * 32768 * 4)));
+  const int64_t n_slots = 4 * slices;
   float* d_rad = nullptr;
   double *d_tab = nullptr, *d_S = nullptr, *d_Q = nullptr, *d_se = nullptr, *d_U = nullptr, *d_V = nullptr;
+  double *d_PS = nullptr, *d_PQ = nullptr;
   hipEvent_t ev[6] = {};
   auto cleanup = [&](msk_status s) {
     dfree(d_rad);
@@ -1202,6 +1193,8 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
     dfree(d_se);
     dfree(d_U);
     dfree(d_V);
+    dfree(d_PS);
+    dfree(d_PQ);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
     dtn_free(d);
@@ -1220,15 +1213,17 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   HIP_P(dalloc(&d_S, K * K));
   HIP_P(dalloc(&d_Q, K * K));
   HIP_P(dalloc(&d_se, K * K));
-  HIP_P(dalloc(&d_U, 2 * chunk * K));
-  HIP_P(dalloc(&d_V, 3 * chunk * K));
+  HIP_P(dalloc(&d_U, 2 * chunk * Kp));
+  HIP_P(dalloc(&d_V, 3 * chunk * Kp));
+  HIP_P(dalloc(&d_PS, n_slots * nblk * 4096));
+  HIP_P(dalloc(&d_PQ, n_slots * nblk * 4096));
   for (hipEvent_t& e : ev) HIP_P(hipEventCreate(&e));
   hipStream_t s = ctx->stream;
   HIP_P(hipEventRecord(ev[0], s));
   HIP_P(launch_fill_u64(d_tab, b->nv * K, 0, s));
   HIP_P(launch_dense_table(b->d_rowptr, b->d_col, b->d_val, b->nv, K, d_tab, s));
-  HIP_P(launch_fill_u64(d_S, K * K, 0, s));
-  HIP_P(launch_fill_u64(d_Q, K * K, 0, s));
+  HIP_P(launch_fill_u64(d_PS, n_slots * nblk * 4096, 0, s));
+  HIP_P(launch_fill_u64(d_PQ, n_slots * nblk * 4096, 0, s));
   HIP_P(launch_fill_u64(d->d_q, n, 0, s));
   HIP_P(launch_fill_u64(d->d_esc, n, 0, s));
   HIP_P(launch_fill_u64(d->d_cap, n, 0, s));
@@ -1260,6 +1255,7 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   PsdGather G;
   G.tab = d_tab;
   G.K = K;
+  G.Kp = Kp;
   G.pairs = pairs;
   G.faces = m->d_faces;
   G.tri = r->d_tri;
@@ -1271,18 +1267,13 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   G.log_tri = d->d_log_tri;
   G.log_bary = d->d_log_bary;
   float gather_ms = 0, prod_ms = 0;
-  const double one = 1.0;
   for (int64_t q0 = 0; q0 < n * pairs; q0 += chunk) {
     const int64_t nq = std::min(chunk, n * pairs - q0);
     HIP_P(hipEventRecord(ev[3], s));
     HIP_P(launch_psd_gather(G, q0, nq, d_U, d_V, s));
     HIP_P(hipEventRecord(ev[4], s));
-    // column-major: U is K x (2 nq), V is K x (3 nq); C = A A^T (upper triangle)
-    if (rocblas_dsyrk(ctx->blas, rocblas_fill_upper, rocblas_operation_none, (rocblas_int)K, (rocblas_int)(2 * nq),
-                      &one, d_U, (rocblas_int)K, &one, d_S, (rocblas_int)K) != rocblas_status_success ||
-        rocblas_dsyrk(ctx->blas, rocblas_fill_upper, rocblas_operation_none, (rocblas_int)K, (rocblas_int)(3 * nq),
-                      &one, d_V, (rocblas_int)K, &one, d_Q, (rocblas_int)K) != rocblas_status_success)
-      return cleanup(fail(ctx, MSK_ERR_DEVICE, "rocblas_dsyrk failed"));
+    HIP_P(launch_psd_syrk(d_U, 2 * nq, Kp, slices, d_PS, s));
+    HIP_P(launch_psd_syrk(d_V, 3 * nq, Kp, slices, d_PQ, s));
     HIP_P(hipEventRecord(ev[5], s));
     HIP_P(hipEventSynchronize(ev[5]));
     float a = 0, c = 0;
@@ -1291,14 +1282,20 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
     gather_ms += a;
     prod_ms += c;
   }
-  HIP_P(launch_psd_finish(d_S, d_Q, K, (double)(n * pairs), d_se, s));
+  HIP_P(hipEventRecord(ev[3], s));
+  HIP_P(launch_psd_reduce(d_PS, n_slots, K, Kp, d_S, s));
+  HIP_P(launch_psd_reduce(d_PQ, n_slots, K, Kp, d_Q, s));
+  HIP_P(hipEventRecord(ev[4], s));
+  HIP_P(launch_psd_se(d_S, d_Q, K * K, (double)(n * pairs), d_se, s));
   HIP_P(launch_fill_u64(d->d_nonfinite, 1, 0, s));
   HIP_P(launch_count_nonfinite(d_S, K * K, d->d_nonfinite, s));
   HIP_P(launch_count_nonfinite(d_se, K * K, d->d_nonfinite, s));
-  HIP_P(hipEventRecord(ev[3], s));
-  HIP_P(hipEventSynchronize(ev[3]));
-  float tot = 0, tb = 0;
-  HIP_P(hipEventElapsedTime(&tot, ev[0], ev[3]));
+  HIP_P(hipEventRecord(ev[5], s));
+  HIP_P(hipEventSynchronize(ev[5]));
+  float tot = 0, tb = 0, red = 0;
+  HIP_P(hipEventElapsedTime(&red, ev[3], ev[4]));
+  prod_ms += red;
+  HIP_P(hipEventElapsedTime(&tot, ev[0], ev[5]));
   HIP_P(hipEventElapsedTime(&tb, ev[0], ev[1]));
   // results to the host
   HIP_P(hipMemcpy(S_out, d_S, K * K * 8, hipMemcpyDeviceToHost));

@@ -153,6 +153,7 @@ hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walk
 struct PsdGather {
   const double* tab;        // dense per-vertex basis table, n_verts x K
   int64_t K;
+  int64_t Kp;               // row stride of the gathered update rows (K rounded up to 64)
   int64_t pairs;            // antithetic pairs per row
   const int32_t* faces;     // original faces (n_tris x 3)
   const int32_t* tri;       // sample face per row
@@ -167,5 +168,9 @@ struct PsdGather {
 hipError_t launch_dense_table(const int32_t* rowptr, const int32_t* col, const float* val, int64_t nv, int64_t K,
                               double* tab, hipStream_t s);
 hipError_t launch_psd_gather(const PsdGather& G, int64_t q0, int64_t nq, double* U, double* V, hipStream_t s);
-hipError_t launch_psd_finish(double* S, double* Q, int64_t K, double n_pairs, double* se, hipStream_t s);
+int64_t psd_blocks(int64_t Kp);
+// Partial 64 x 64 upper blocks of A^T A (A: m x Kp row-major) into P: slices x 4 slots of psd_blocks(Kp) blocks
+hipError_t launch_psd_syrk(const double* A, int64_t m, int64_t Kp, int64_t slices, double* P, hipStream_t s);
+hipError_t launch_psd_reduce(const double* P, int64_t n_slots, int64_t K, int64_t Kp, double* C, hipStream_t s);
+hipError_t launch_psd_se(const double* S, const double* Q, int64_t n, double n_pairs, double* se, hipStream_t s);
 }  // namespace msk

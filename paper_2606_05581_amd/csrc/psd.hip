@@ -10,8 +10,8 @@
 // are symmetric rank-k updates S += U^T U, Q += V^T V over rows
 //   U: sqrt(alpha/2) d_1, sqrt(alpha/2) d_2;
 //   V: (alpha/2) d_1*d_1, (alpha/2) d_2*d_2, sqrt(2) (alpha/2) d_1*d_2,
-// so each chunk of pairs is gathered into U and V (HBM-bound) and handed to
-// a dense FP64 product on the matrix cores.
+// so each chunk of pairs is gathered into U and V (HBM-bound, rows padded to
+// a multiple of 64 columns) and multiplied on the matrix cores in FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,17 +25,20 @@ namespace {
 
 inline int grid_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 1 << 20); }
 
-// Dense per-vertex table (n_verts x K, zeroed beforehand) from the CSR basis.
+// Dense per-vertex table (n_verts x K, zeroed beforehand) from the CSR basis:
+// one wavefront per vertex, lanes over its entries (coalesced).
 __global__ void dense_table_kernel(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                    const float* __restrict__ val, int64_t nv, int64_t K, double* __restrict__ tab) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
-    for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) tab[v * K + col[e]] = (double)val[e];
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t v = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); v < nv; v += waves)
+    for (int32_t e = rowptr[v] + (int32_t)(threadIdx.x & 63); e < rowptr[v + 1]; e += 64)
+      tab[v * K + col[e]] = (double)val[e];
 }
 
 // One workgroup per pair of the chunk [q0, q0 + nq); threads over columns.
 __global__ void __launch_bounds__(256) psd_gather_kernel(PsdGather G, int64_t q0, int64_t nq, double* __restrict__ U,
                                                          double* __restrict__ V) {
-  const int64_t K = G.K;
+  const int64_t K = G.K, Kp = G.Kp;
   for (int64_t qq = blockIdx.x; qq < nq; qq += gridDim.x) {
     const int64_t q = q0 + qq;
     const int64_t i = q / G.pairs;
@@ -59,8 +62,15 @@ __global__ void __launch_bounds__(256) psd_gather_kernel(PsdGather G, int64_t q0
       for (int c = 0; c < 3; ++c) ft[a][c] = has_t ? G.faces[3 * (int64_t)t + c] : 0;
     }
     const double su = sqrt(0.5 * alpha), sv = 0.5 * alpha, sv2 = sqrt(2.0) * 0.5 * alpha;
-    double* u = U + 2 * qq * K;
-    double* v = V + 3 * qq * K;
+    double* u = U + 2 * qq * Kp;
+    double* v = V + 3 * qq * Kp;
+    for (int64_t k = K + threadIdx.x; k < Kp; k += blockDim.x) {  // padding columns
+      u[k] = 0.0;
+      u[Kp + k] = 0.0;
+      v[k] = 0.0;
+      v[Kp + k] = 0.0;
+      v[2 * Kp + k] = 0.0;
+    }
     for (int64_t k = threadIdx.x; k < K; k += blockDim.x) {
       const double bs = ls[0] * G.tab[fs[0] * K + k] + ls[1] * G.tab[fs[1] * K + k] + ls[2] * G.tab[fs[2] * K + k];
       const double b1 = lt[0][0] * G.tab[ft[0][0] * K + k] + lt[0][1] * G.tab[ft[0][1] * K + k] +
@@ -69,29 +79,113 @@ __global__ void __launch_bounds__(256) psd_gather_kernel(PsdGather G, int64_t q0
                         lt[1][2] * G.tab[ft[1][2] * K + k];
       const double d1 = bs - b1, d2 = bs - b2;
       u[k] = su * d1;
-      u[K + k] = su * d2;
+      u[Kp + k] = su * d2;
       v[k] = sv * d1 * d1;
-      v[K + k] = sv * d2 * d2;
-      v[2 * K + k] = sv2 * d1 * d2;
+      v[Kp + k] = sv * d2 * d2;
+      v[2 * Kp + k] = sv2 * d1 * d2;
     }
   }
 }
 
-// Lower triangle from the upper one (column-major K x K from the symmetric
-// rank-k updates), then the standard error of every entry:
-// se^2 = (n Q - S^2) / (n - 1) over n pair terms.
-__global__ void psd_finish_kernel(double* __restrict__ S, double* __restrict__ Q, int64_t K, double n_pairs,
-                                  double* __restrict__ se) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K * K; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = e % K, colm = e / K;  // column-major: element (row, colm)
-    const int64_t src = row <= colm ? e : colm + row * K;
-    const double s = S[src], q = Q[src];
-    se[e] = sqrt(fmax(0.0, n_pairs * q - s * s) / (n_pairs - 1.0));
-    if (row > colm) {
-      S[e] = s;
-      Q[e] = q;
-    }
+// ---- symmetric rank-k product on the matrix cores
+// Partial sums of A^T A, A an m x Kp row-major FP64 matrix (Kp a multiple of
+// 64), for the 64 x 64 blocks (I, J), I <= J, of the Kp x Kp result. A
+// workgroup takes a slice of the rows; its work items are (block, 4-row group
+// residue q mod Q), Q = 4 / gcd(nblk, 4), dealt to its 4 wavefronts in turn,
+// so every wavefront gets the same number of items and never two of one
+// block. A wavefront keeps the block
+// in 16 tiles of v_mfma_f64_16x16x4 accumulators (4 doubles per lane each),
+// each step taking 4 rows: operand A = the rows' I-block columns (lane l:
+// row l / 16, column l % 16 of the tile), operand B = their J-block columns,
+// so tile (ti, tj) gains sum_r A[r][I + 16 ti + i] A[r][J + 16 tj + j] with
+// lane l, item v holding (i, j) = (4 v + l / 16, l % 16) (measured on gfx950
+// with one-hot operands). At the end it
+// adds the block into its own partial slot P[slice * 4 + wave][block]
+// (no other wavefront writes there; slots are summed by psd_reduce_kernel).
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void block_of(int32_t b, int32_t nb, int32_t& I, int32_t& J) {
+  I = 0;
+  while (b >= nb - I) {
+    b -= nb - I;
+    ++I;
   }
+  J = I + b;
+}
+
+__global__ void __launch_bounds__(256) syrk_blocks_kernel(const double* __restrict__ A, int64_t m, int64_t Kp,
+                                                          int64_t rows_per_slice, double* __restrict__ P) {
+  const int32_t nb = (int32_t)(Kp / 64), nblk = nb * (nb + 1) / 2;
+  const int32_t Q = (nblk % 4 == 0) ? 1 : ((nblk % 2 == 0) ? 2 : 4);
+  const int32_t wave = (int32_t)(threadIdx.x >> 6), lane = (int32_t)(threadIdx.x & 63);
+  const int64_t r_begin = (int64_t)blockIdx.x * rows_per_slice;
+  const int64_t r_end = min(m, r_begin + rows_per_slice);
+  const int32_t kr = lane >> 4, cl = lane & 15;
+  const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
+  for (int32_t item = wave; item < nblk * Q; item += 4) {
+    const int32_t blk = item / Q, q = item - blk * Q;
+    int32_t I, J;
+    block_of(blk, nb, I, J);
+    mfma_d4 acc[4][4];
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t r0 = r_begin + 4 * (int64_t)q; r0 < r_end; r0 += 4 * (int64_t)Q) {
+      const int64_t r = r0 + kr;
+      const bool ok = r < r_end;
+      const double* row = A + (ok ? r : r_begin) * Kp;
+      double a[4], bv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = ok ? row[I * 64 + 16 * t + cl] : 0.0;
+        bv[t] = ok ? row[J * 64 + 16 * t + cl] : 0.0;
+      }
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+    }
+    double* out = P + (slot * nblk + blk) * 4096;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * ti + 4 * v + kr, j = 16 * tj + cl;
+          out[i * 64 + j] += acc[ti][tj][v];
+        }
+  }
+}
+
+// C (K x K, row-major) = sum over slots of the partial blocks, the lower
+// triangle mirrored from the upper one.
+__global__ void psd_reduce_kernel(const double* __restrict__ P, int64_t n_slots, int64_t K, int64_t Kp,
+                                  double* __restrict__ C) {
+  const int32_t nb = (int32_t)(Kp / 64), nblk = nb * (nb + 1) / 2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K * K; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = e / K, j = e - (e / K) * K;
+    if (i > j) {
+      const int64_t t = i;
+      i = j;
+      j = t;
+    }
+    const int32_t I = (int32_t)(i / 64), J = (int32_t)(j / 64);
+    const int32_t blk = I * nb - I * (I - 1) / 2 + (J - I);
+    const int64_t off = (int64_t)blk * 4096 + (i - 64 * I) * 64 + (j - 64 * J);
+    double sum = 0.0;
+    for (int64_t sl = 0; sl < n_slots; ++sl) sum += P[sl * nblk * 4096 + off];
+    C[e] = sum;
+  }
+}
+
+// Standard error of every entry: se^2 = (n Q - S^2) / (n - 1) over n pair terms.
+__global__ void psd_se_kernel(const double* __restrict__ S, const double* __restrict__ Q, int64_t n, double n_pairs,
+                              double* __restrict__ se) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    se[e] = sqrt(fmax(0.0, n_pairs * Q[e] - S[e] * S[e]) / (n_pairs - 1.0));
 }
 
 }  // namespace
@@ -99,7 +193,7 @@ __global__ void psd_finish_kernel(double* __restrict__ S, double* __restrict__ Q
 hipError_t launch_dense_table(const int32_t* rowptr, const int32_t* col, const float* val, int64_t nv, int64_t K,
                               double* tab, hipStream_t s) {
   if (nv <= 0) return hipSuccess;
-  hipLaunchKernelGGL(dense_table_kernel, dim3(grid_for(nv, 256)), dim3(256), 0, s, rowptr, col, val, nv, K, tab);
+  hipLaunchKernelGGL(dense_table_kernel, dim3(grid_for(nv, 4)), dim3(256), 0, s, rowptr, col, val, nv, K, tab);
   return hipGetLastError();
 }
 
@@ -111,8 +205,26 @@ hipError_t launch_psd_gather(const PsdGather& G, int64_t q0, int64_t nq, double*
   return hipGetLastError();
 }
 
-hipError_t launch_psd_finish(double* S, double* Q, int64_t K, double n_pairs, double* se, hipStream_t s) {
-  hipLaunchKernelGGL(psd_finish_kernel, dim3(grid_for(K * K, 256)), dim3(256), 0, s, S, Q, K, n_pairs, se);
+int64_t psd_blocks(int64_t Kp) {
+  const int64_t nb = Kp / 64;
+  return nb * (nb + 1) / 2;
+}
+
+hipError_t launch_psd_syrk(const double* A, int64_t m, int64_t Kp, int64_t slices, double* P, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int64_t rps = ((m + slices - 1) / slices + 3) / 4 * 4;
+  const int64_t grid = (m + rps - 1) / rps;
+  hipLaunchKernelGGL(syrk_blocks_kernel, dim3((unsigned)grid), dim3(256), 0, s, A, m, Kp, rps, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_psd_reduce(const double* P, int64_t n_slots, int64_t K, int64_t Kp, double* C, hipStream_t s) {
+  hipLaunchKernelGGL(psd_reduce_kernel, dim3(grid_for(K * K, 256)), dim3(256), 0, s, P, n_slots, K, Kp, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_psd_se(const double* S, const double* Q, int64_t n, double n_pairs, double* se, hipStream_t s) {
+  hipLaunchKernelGGL(psd_se_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, S, Q, n, n_pairs, se);
   return hipGetLastError();
 }
 

@@ -1242,9 +1242,14 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
 // discarded (the inset left the thin region it should probe).
 // Largest ball inside the domain tangent at each point row's sample s, centre
 // c = s - r n (Sec. 3.2; Alg. 2, LargestTangentBall): bisection over
-// [0, r_max], `iters` exact nearest-triangle queries from c; a radius is
-// accepted when c's nearest surface point is at least r - tol away and the
-// ball lies inside the scene's bounding sphere. 0 = no radius accepted.
+// [0, r_max]; a radius is accepted when c's nearest surface point is at least
+// r - tol away and the ball lies inside the scene's bounding sphere. 0 = no
+// radius accepted. Each step needs only whether some triangle lies closer
+// than t = r - tol, so its query starts from the bound B = t^2 (1 + 2^-20)
+// instead of +inf: when a triangle has sqrt(d2) < t then d2 < B, the query
+// finds the exact minimum below B and the test is taken on it as before;
+// when none lies below B the ball is accepted. Same decisions as an unbounded
+// query, with only the boxes near the ball visited.
 __global__ void tangent_ball_kernel(MeshDev M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rows) return;
@@ -1257,11 +1262,14 @@ __global__ void tangent_ball_kernel(MeshDev M, int64_t n_rows, float r_max, int3
     const float mid = 0.5f * (lo + hi);
     const double cxd = sx - mid * nx, cyd = sy - mid * ny, czd = sz - mid * nz;
     const float cx = (float)cxd, cy = (float)cyd, cz = (float)czd;
+    const float t = mid - tol;
+    const float bound = t > 0.0f ? (t * t) * (1.0f + 0x1p-20f) : 0.0f;
     Nearest h;
-    h.d2 = INFINITY; h.orig = INT_MAX; h.slot = M.slot_of_tri[M.tri[i]];
+    h.d2 = bound; h.orig = INT_MAX; h.slot = -1;
     TravCount cnt;
-    bvh_nearest<false>(M.nodes, M.tris, nullptr, 0, cx, cy, cz, M.radius, h, cnt);
-    const bool inside = sqrtf(h.d2) >= mid - tol && sqrt(cxd * cxd + cyd * cyd + czd * czd) + mid <= M.radius_d;
+    if (t > 0.0f) bvh_nearest<false>(M.nodes, M.tris, nullptr, 0, cx, cy, cz, M.radius, h, cnt);
+    const bool empty = h.orig == INT_MAX || sqrtf(h.d2) >= t;
+    const bool inside = empty && sqrt(cxd * cxd + cyd * cyd + czd * czd) + mid <= M.radius_d;
     if (inside)
       lo = mid;
     else
@@ -1431,7 +1439,7 @@ hipError_t launch_discard(const MeshDev& M, int64_t n_rows, int32_t* discarded, 
 hipError_t launch_tangent_ball(const MeshDev& M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius,
                                hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tangent_ball_kernel, dim3(blocks_for(n_rows, 128)), dim3(128), 0, s, M, n_rows, r_max, iters,
+  hipLaunchKernelGGL(tangent_ball_kernel, dim3(blocks_for(n_rows, 64)), dim3(64), 0, s, M, n_rows, r_max, iters,
                      tol, radius);
   return hipGetLastError();
 }

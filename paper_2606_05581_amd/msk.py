@@ -324,7 +324,7 @@ class Context:
         return {f: getattr(res, f) for f, _ in TuneResult._fields_}
 
     def estimate_psd(self, mesh, rows, basis, pairs: int, eps: float, cap_deg: float = 2.5, bisect_iters: int = 10,
-                     r_max: float = 0.0, chunk_pairs: int = 32768, log: bool = False, **walk_opts) -> dict:
+                     r_max: float = 0.0, chunk_pairs: int = 262144, log: bool = False, **walk_opts) -> dict:
         """The PSD estimator (Alg. 2) over point rows: S, se (K x K), tangent radii, info and optionally the walk log."""
         o = self.default_opts(**walk_opts)
         po = PsdOpts()

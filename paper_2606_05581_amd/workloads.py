@@ -644,12 +644,33 @@ def exterior200_301k(N=20000, walks=256):
     return Workload("exterior200_301k", [case], walks=walks, modes=["exterior"], k=128)
 
 
+def psd_sh_sphere_2m(n=316, N=16384, pairs=320, K=128):
+    """PSD estimator (Alg. 2) workload at the scale of the paper's runtime study
+    (2^14 sample points, about 10M walks, the first 128 basis functions): the
+    SH-displaced sphere of sh_sphere_2m (~2.0M faces), N farthest-point rows,
+    and a dense basis of the first K real spherical harmonics of the vertex
+    directions (standing in for the surface Laplacian's low modes)."""
+    rng = np.random.default_rng(1002)
+    V, F = sh_displaced_sphere(n, 16, 0.05, rng)
+    V = normalise_unit_ball(V)
+    rows = point_rows(V, F, N, rng, pool_factor=4)
+    area, _ = face_geometry(V, F)
+    h = 0.25 * math.sqrt(area.sum() / N)
+    eps = min(1e-3, h / 10.0)
+    L = int(math.ceil(math.sqrt(K))) - 1
+    table = real_sh(L, V)[:, :K]
+    case = MeshCase(V=V.astype(np.float32), F=F.astype(np.int32), rows=rows, basis=dense_basis(table), eps=eps, h=h)
+    return Workload("psd_sh_sphere_2m", [case], walks=2 * pairs, modes=["interior"], k=0,
+                    note=f"PSD estimator: {N} rows x {pairs} antithetic pairs, K={K}")
+
+
 WORKLOADS = {
     "unit_sphere_320": unit_sphere_320,
     "soup8_53k": soup8_53k,
     "sh_sphere_2m": sh_sphere_2m,
     "batch64_mixed": batch64_mixed,
     "exterior200_301k": exterior200_301k,
+    "psd_sh_sphere_2m": psd_sh_sphere_2m,
 }
 
 

@@ -161,22 +161,28 @@ def psd_leg(ctx):
     K, n = int(info["K"]), int(info["n_rows"])
     n_pairs = n * pairs
     flops = 5.0 * K * (K + 1) * n_pairs
-    gbytes = n_pairs * (11.0 * K * 8 + 2 * 16) + n * 3.0 * K * 8
+    fused = bool(info["fused"])
+    # algorithmic bytes: per pair six table rows read (the two terminal
+    # triangles) plus, in the two-pass form, five update rows written and read
+    # back; per row three table rows (the sample's triangle); walk log entries
+    gbytes = n_pairs * ((6.0 if fused else 11.0) * K * 8 + 2 * 16) + n * 3.0 * K * 8
     prod_tf = flops / (info["product_ms"] * 1e-3) / 1e12
-    gath = gbytes / (info["gather_ms"] * 1e-3) / 1e9
-    log(f"[bench] psd: {info['walks_total'] / el:.3e} walks/s; walks {info['walk_kernel_ms']:.1f} ms, gathers "
-        f"{info['gather_ms']:.1f} ms, products {info['product_ms']:.1f} ms ({prod_tf:.1f} TFLOP/s)")
+    gath_ms = info["product_ms"] if fused else info["gather_ms"]
+    gath = gbytes / (gath_ms * 1e-3) / 1e9
+    log(f"[bench] psd: {info['walks_total'] / el:.3e} walks/s; tangent balls {info['tangent_ms']:.1f} ms, walks "
+        f"{info['walk_kernel_ms']:.1f} ms, gathers {info['gather_ms']:.1f} ms, products {info['product_ms']:.1f} ms "
+        f"({prod_tf:.1f} TFLOP/s{', fused with the gathers' if fused else ''})")
     return {
         "workload": wl.name, "rows": n, "pairs_per_row": pairs, "K": K, "triangles": int(case.F.shape[0]),
         "value": info["walks_total"] / el, "unit": "walks/s", "pairs_per_s": n_pairs / el, "seconds": el,
         "ms": {k: info[k] for k in ("tangent_ms", "walk_kernel_ms", "gather_ms", "product_ms", "total_ms")},
-        "mean_radius": info["mean_radius"], "dropped_rows": info["dropped_rows"],
+        "mean_radius": info["mean_radius"], "dropped_rows": info["dropped_rows"], "fused": fused,
         "S_trace": float(np.trace(r["S"])),
         "roofline": {
             "product": {"bound": "mfma", "achieved": prod_tf, "peak": FP64_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": prod_tf / FP64_MATRIX_PEAK_TFLOPS, "dtype": "f64"},
             "gather": {"bound": "hbm", "achieved": gath, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": gath / HBM_PEAK_GBS},
+                       "frac": gath / HBM_PEAK_GBS, "kernel": "psd_fused_kernel" if fused else "psd_gather_kernel"},
         },
     }
 

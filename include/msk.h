@@ -378,10 +378,12 @@ typedef struct {
   double r_max;            /* the radius bound used                            */
   double tangent_ms;       /* table set-up and tangent-ball kernel             */
   double walk_kernel_ms;   /* the walk launch                                  */
-  double gather_ms;        /* gathers of the update rows                       */
-  double product_ms;       /* the symmetric rank-k products                    */
+  double gather_ms;        /* two-pass form: gathers of the update rows        */
+  double product_ms;       /* the symmetric rank-k products (fused form: with
+                              the gathers, in one kernel)                      */
   double total_ms;
   int64_t nonfinite_entries;
+  int32_t fused;           /* 1: K <= 384, gathers and products in one kernel  */
 } msk_psd_info;
 
 typedef struct {  /* optional host walk log, n_rows x 2 pairs entries each    */
@@ -411,7 +413,8 @@ typedef struct {  /* optional host walk log, n_rows x 2 pairs entries each    */
  * error, the n_rows x pairs pair terms taken as independent draws:
  * se^2 = (n Q - S^2)/(n - 1), Q = sum of X*X elementwise. The sums are FP64:
  * the difference rows are gathered from a dense FP64 copy of the basis table
- * and multiplied on the matrix cores (FP64 MFMA, symmetric rank-k blocks).
+ * and multiplied on the matrix cores (FP64 MFMA, symmetric rank-k blocks);
+ * for K <= 384 both happen in one kernel with the rows kept in LDS.
  *   S, se:  host, K x K doubles (se may be NULL);
  *   radius: host, n_rows floats (tangent radii, 0 = dropped) or NULL;
  *   log:    optional host walk log; info: optional.

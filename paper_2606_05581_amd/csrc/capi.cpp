@@ -1176,11 +1176,14 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   if (st != MSK_OK) return st;
   const int64_t K = b->K, n = d->n, Kp = (K + 63) / 64 * 64;
   const int64_t chunk = std::min<int64_t>(po.chunk_pairs, n * pairs);
-  // partial-sum slots of the matrix-core products: 4 per row slice, at most
+  // partial-sum slots of the matrix-core products: the fused form (K <= 384)
+  // has one per workgroup column; the two-pass form 4 per row slice, at most
   // 1024 slices and about 256 MB per matrix
   const int64_t nblk = psd_blocks(Kp);
+  const int64_t fused_slots = psd_fused_slots(Kp, n * pairs);
+  const bool fused = fused_slots > 0;
   const int64_t slices = std::max<int64_t>(1, std::min<int64_t>(1024, ((int64_t)1 << 28) / (nblk * 32768 * 4)));
-  const int64_t n_slots = 4 * slices;
+  const int64_t n_slots = fused ? fused_slots : 4 * slices;
   float* d_rad = nullptr;
   double *d_tab = nullptr, *d_S = nullptr, *d_Q = nullptr, *d_se = nullptr, *d_U = nullptr, *d_V = nullptr;
   double *d_PS = nullptr, *d_PQ = nullptr;
@@ -1213,8 +1216,10 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   HIP_P(dalloc(&d_S, K * K));
   HIP_P(dalloc(&d_Q, K * K));
   HIP_P(dalloc(&d_se, K * K));
-  HIP_P(dalloc(&d_U, 2 * chunk * Kp));
-  HIP_P(dalloc(&d_V, 3 * chunk * Kp));
+  if (!fused) {
+    HIP_P(dalloc(&d_U, 2 * chunk * Kp));
+    HIP_P(dalloc(&d_V, 3 * chunk * Kp));
+  }
   HIP_P(dalloc(&d_PS, n_slots * nblk * 4096));
   HIP_P(dalloc(&d_PQ, n_slots * nblk * 4096));
   for (hipEvent_t& e : ev) HIP_P(hipEventCreate(&e));
@@ -1222,8 +1227,10 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   HIP_P(hipEventRecord(ev[0], s));
   HIP_P(launch_fill_u64(d_tab, b->nv * K, 0, s));
   HIP_P(launch_dense_table(b->d_rowptr, b->d_col, b->d_val, b->nv, K, d_tab, s));
-  HIP_P(launch_fill_u64(d_PS, n_slots * nblk * 4096, 0, s));
-  HIP_P(launch_fill_u64(d_PQ, n_slots * nblk * 4096, 0, s));
+  if (!fused) {  // the two-pass form adds into its slots call by call
+    HIP_P(launch_fill_u64(d_PS, n_slots * nblk * 4096, 0, s));
+    HIP_P(launch_fill_u64(d_PQ, n_slots * nblk * 4096, 0, s));
+  }
   HIP_P(launch_fill_u64(d->d_q, n, 0, s));
   HIP_P(launch_fill_u64(d->d_esc, n, 0, s));
   HIP_P(launch_fill_u64(d->d_cap, n, 0, s));
@@ -1267,7 +1274,14 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   G.log_tri = d->d_log_tri;
   G.log_bary = d->d_log_bary;
   float gather_ms = 0, prod_ms = 0;
-  for (int64_t q0 = 0; q0 < n * pairs; q0 += chunk) {
+  if (fused) {
+    HIP_P(hipEventRecord(ev[3], s));
+    HIP_P(launch_psd_fused(G, n * pairs, n_slots, d_PS, d_PQ, s));
+    HIP_P(hipEventRecord(ev[5], s));
+    HIP_P(hipEventSynchronize(ev[5]));
+    HIP_P(hipEventElapsedTime(&prod_ms, ev[3], ev[5]));
+  }
+  for (int64_t q0 = 0; !fused && q0 < n * pairs; q0 += chunk) {
     const int64_t nq = std::min(chunk, n * pairs - q0);
     HIP_P(hipEventRecord(ev[3], s));
     HIP_P(launch_psd_gather(G, q0, nq, d_U, d_V, s));
@@ -1338,6 +1352,7 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   I.product_ms = prod_ms;
   I.total_ms = tot;
   I.nonfinite_entries = d->info.nonfinite_entries;
+  I.fused = fused ? 1 : 0;
   if (info) *info = I;
 #undef HIP_P
   const bool bad = I.nonfinite_entries > 0;

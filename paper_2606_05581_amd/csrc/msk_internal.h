@@ -169,6 +169,10 @@ hipError_t launch_dense_table(const int32_t* rowptr, const int32_t* col, const f
                               double* tab, hipStream_t s);
 hipError_t launch_psd_gather(const PsdGather& G, int64_t q0, int64_t nq, double* U, double* V, hipStream_t s);
 int64_t psd_blocks(int64_t Kp);
+// Fused gather + products (Kp <= 384): partial slots (one per workgroup column) of S and Q blocks; 0 = not available
+int64_t psd_fused_slots(int64_t Kp, int64_t n_pairs);
+hipError_t launch_psd_fused(const PsdGather& G, int64_t n_pairs, int64_t n_slots, double* PS, double* PQ,
+                            hipStream_t s);
 // Partial 64 x 64 upper blocks of A^T A (A: m x Kp row-major) into P: slices x 4 slots of psd_blocks(Kp) blocks
 hipError_t launch_psd_syrk(const double* A, int64_t m, int64_t Kp, int64_t slices, double* P, hipStream_t s);
 hipError_t launch_psd_reduce(const double* P, int64_t n_slots, int64_t K, int64_t Kp, double* C, hipStream_t s);

@@ -160,6 +160,142 @@ __global__ void __launch_bounds__(256) syrk_blocks_kernel(const double* __restri
   }
 }
 
+// ---- fused form (K <= 384): the update rows never leave LDS
+// A workgroup takes a range of pairs and a group of up to 4 upper blocks;
+// its wavefronts are (matrix, block) items: the first half accumulate S
+// blocks from U rows, the second half Q blocks from V rows. Per tile of T
+// pairs the workgroup gathers the pairs' U and V rows into LDS (row stride
+// Kp + 2 doubles), then every wavefront runs its MFMA steps over them; the
+// accumulators stay in registers over the whole range and are stored once
+// into the workgroup's slot (slot = blockIdx.x; no other workgroup writes it).
+struct PairMeta {
+  double alpha;
+  double ls[3], lt[2][3];
+  int32_t fs[3], ft[2][3];
+};
+
+__device__ void pair_meta(const PsdGather& G, int64_t q, PairMeta& m) {
+  const int64_t i = q / G.pairs, j = q - (q / G.pairs) * G.pairs;
+  const double r = (double)G.radius[i];
+  m.alpha = r > 0.0 ? G.w[i] * (1.0 / (2.0 * r)) * (1.0 / G.u0 - 1.0) / (2.0 * (double)G.pairs) : 0.0;
+  const int32_t* fs = G.faces + 3 * (int64_t)G.tri[i];
+  for (int c = 0; c < 3; ++c) {
+    m.fs[c] = fs[c];
+    m.ls[c] = G.bary[3 * i + c];
+  }
+  for (int a = 0; a < 2; ++a) {
+    const int64_t li = i * 2 * G.pairs + 2 * j + a;
+    const int32_t st = G.log_status[li], t = G.log_tri[li];
+    const bool has_t = st >= 0 && st != kEscaped && t >= 0;
+    const double l1 = has_t ? (double)G.log_bary[2 * li] : 0.0, l2 = has_t ? (double)G.log_bary[2 * li + 1] : 0.0;
+    m.lt[a][0] = has_t ? (1.0 - l1) - l2 : 0.0;
+    m.lt[a][1] = l1;
+    m.lt[a][2] = l2;
+    for (int c = 0; c < 3; ++c) m.ft[a][c] = has_t ? G.faces[3 * (int64_t)t + c] : 0;
+  }
+}
+
+// (At most 8 wavefronts per workgroup, so each lane may hold 256 registers:
+// the 16 accumulator tiles alone take 128.)
+template <int T>
+__global__ void __launch_bounds__(512) psd_fused_kernel(PsdGather G, int64_t n_pairs, int64_t pairs_per_wg,
+                                                         int32_t group_blocks, double* __restrict__ PS,
+                                                         double* __restrict__ PQ) {
+  extern __shared__ double lds[];
+  const int64_t K = G.K, Kp = G.Kp;
+  const int stride = (int)Kp + 2;
+  double* Ur = lds;                      // 2T rows
+  double* Vr = lds + 2 * T * stride;     // 3T rows
+  PairMeta* meta = (PairMeta*)(lds + 5 * T * stride);
+  const int32_t nb = (int32_t)(Kp / 64), nblk = nb * (nb + 1) / 2;
+  const int32_t g0 = (int32_t)blockIdx.y * group_blocks;
+  const int32_t gcount = min(group_blocks, nblk - g0);
+  const int32_t wave = (int32_t)(threadIdx.x >> 6), lane = (int32_t)(threadIdx.x & 63);
+  const bool is_q = wave >= group_blocks;
+  const int32_t wi = is_q ? wave - group_blocks : wave;
+  const bool active = wi < gcount;
+  const int32_t blk = g0 + wi;
+  int32_t I = 0, J = 0;
+  if (active) block_of(blk, nb, I, J);
+  const int32_t kr = lane >> 4, cl = lane & 15;
+  mfma_d4 acc[4][4];
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t p_begin = (int64_t)blockIdx.x * pairs_per_wg;
+  const int64_t p_end = min(n_pairs, p_begin + pairs_per_wg);
+  for (int64_t p0 = p_begin; p0 < p_end; p0 += T) {
+    if (threadIdx.x < T) {
+      const int64_t q = p0 + threadIdx.x;
+      if (q < p_end) {
+        pair_meta(G, q, meta[threadIdx.x]);
+      } else {
+        PairMeta& m = meta[threadIdx.x];
+        m.alpha = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          m.fs[c] = m.ft[0][c] = m.ft[1][c] = 0;
+          m.ls[c] = m.lt[0][c] = m.lt[1][c] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = (int)threadIdx.x; e < T * (int)Kp; e += (int)blockDim.x) {
+      const int pp = e / (int)Kp, k = e - pp * (int)Kp;
+      const PairMeta& m = meta[pp];
+      double d1 = 0.0, d2 = 0.0;
+      if (k < K) {
+        const double bs = m.ls[0] * G.tab[m.fs[0] * K + k] + m.ls[1] * G.tab[m.fs[1] * K + k] +
+                          m.ls[2] * G.tab[m.fs[2] * K + k];
+        const double b1 = m.lt[0][0] * G.tab[m.ft[0][0] * K + k] + m.lt[0][1] * G.tab[m.ft[0][1] * K + k] +
+                          m.lt[0][2] * G.tab[m.ft[0][2] * K + k];
+        const double b2 = m.lt[1][0] * G.tab[m.ft[1][0] * K + k] + m.lt[1][1] * G.tab[m.ft[1][1] * K + k] +
+                          m.lt[1][2] * G.tab[m.ft[1][2] * K + k];
+        d1 = bs - b1;
+        d2 = bs - b2;
+      }
+      const double su = sqrt(0.5 * m.alpha), sv = 0.5 * m.alpha, sv2 = sqrt(2.0) * 0.5 * m.alpha;
+      Ur[(2 * pp) * stride + k] = su * d1;
+      Ur[(2 * pp + 1) * stride + k] = su * d2;
+      Vr[(3 * pp) * stride + k] = sv * d1 * d1;
+      Vr[(3 * pp + 1) * stride + k] = sv * d2 * d2;
+      Vr[(3 * pp + 2) * stride + k] = sv2 * d1 * d2;
+    }
+    __syncthreads();
+    if (active) {
+      const double* R = is_q ? Vr : Ur;
+      const int nrows = is_q ? 3 * T : 2 * T;
+      for (int s0 = 0; s0 < nrows; s0 += 4) {
+        const double* row = R + (s0 + kr) * stride;
+        double a[4], bv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          a[t] = row[I * 64 + 16 * t + cl];
+          bv[t] = row[J * 64 + 16 * t + cl];
+        }
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 4; ++tj)
+            acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  if (active) {
+    double* out = (is_q ? PQ : PS) + ((int64_t)blockIdx.x * nblk + blk) * 4096;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * ti + 4 * v + kr, j = 16 * tj + cl;
+          out[i * 64 + j] = acc[ti][tj][v];
+        }
+  }
+}
+
 // C (K x K, row-major) = sum over slots of the partial blocks, the lower
 // triangle mirrored from the upper one.
 __global__ void psd_reduce_kernel(const double* __restrict__ P, int64_t n_slots, int64_t K, int64_t Kp,
@@ -202,6 +338,39 @@ hipError_t launch_psd_gather(const PsdGather& G, int64_t q0, int64_t nq, double*
   const int threads = G.K >= 256 ? 256 : (G.K >= 128 ? 128 : 64);
   hipLaunchKernelGGL(psd_gather_kernel, dim3((unsigned)std::min<int64_t>(nq, 1 << 20)), dim3(threads), 0, s, G, q0,
                      nq, U, V);
+  return hipGetLastError();
+}
+
+// pairs per tile of the fused form: 5 T rows of Kp + 2 doubles stay within 64 KB of LDS
+static int64_t fused_tile(int64_t Kp) { return Kp <= 192 ? 8 : (Kp <= 384 ? 4 : 0); }
+
+// upper blocks per workgroup of the fused form (two wavefronts each)
+static const int64_t kFusedGroup = 4;
+
+int64_t psd_fused_slots(int64_t Kp, int64_t n_pairs) {
+  const int64_t nblk = psd_blocks(Kp), gb = std::min<int64_t>(nblk, kFusedGroup), groups = (nblk + gb - 1) / gb;
+  const int64_t T = fused_tile(Kp);
+  if (T == 0) return 0;
+  return std::max<int64_t>(1, std::min<int64_t>((n_pairs + T - 1) / T, 2048 / groups));
+}
+
+hipError_t launch_psd_fused(const PsdGather& G, int64_t n_pairs, int64_t n_slots, double* PS, double* PQ,
+                            hipStream_t s) {
+  if (n_pairs <= 0) return hipSuccess;
+  const int64_t Kp = G.Kp, nblk = psd_blocks(Kp), gb = std::min<int64_t>(nblk, kFusedGroup);
+  const int64_t groups = (nblk + gb - 1) / gb;
+  const int64_t ppw = (n_pairs + n_slots - 1) / n_slots;
+  const dim3 grid((unsigned)n_slots, (unsigned)groups), block((unsigned)(128 * gb));
+  const int64_t T = fused_tile(Kp);
+  if (T == 8) {
+    const size_t lds = (size_t)5 * 8 * (Kp + 2) * 8 + 8 * sizeof(PairMeta);
+    hipLaunchKernelGGL(psd_fused_kernel<8>, grid, block, lds, s, G, n_pairs, ppw, (int32_t)gb, PS, PQ);
+  } else if (T == 4) {
+    const size_t lds = (size_t)5 * 4 * (Kp + 2) * 8 + 4 * sizeof(PairMeta);
+    hipLaunchKernelGGL(psd_fused_kernel<4>, grid, block, lds, s, G, n_pairs, ppw, (int32_t)gb, PS, PQ);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

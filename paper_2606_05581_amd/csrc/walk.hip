@@ -228,10 +228,10 @@ struct StackEntry {
   float lb;
 };
 
-template <bool kStats>
+template <bool kStats, bool kStopBelow = false>
 __host__ __device__ void bvh_nearest(const Node4* __restrict__ nodes, const TriRec* __restrict__ tris, const Node4* lds,
                                      int32_t n_lds, float px, float py, float pz, float radius, Nearest& h,
-                                     TravCount& cnt) {
+                                     TravCount& cnt, float stop_below = 0.0f) {
   const float slack = 0x1p-18f * (radius + fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz))));
   if (h.slot >= 0) {
     const int32_t s = h.slot;
@@ -294,7 +294,12 @@ __host__ __device__ void bvh_nearest(const Node4* __restrict__ nodes, const TriR
         const int32_t first = -cc[k] - 1;
         const float before = h.d2;
         for (int32_t s = first; s < first + cn[k]; ++s) test_tri<kStats>(tris, s, px, py, pz, h, cnt);
-        if (h.d2 != before) thr = prune_bound(h.d2, slack);
+        if (h.d2 != before) {
+          thr = prune_bound(h.d2, slack);
+          // kStopBelow: only whether some triangle lies closer than
+          // stop_below is asked, and this one does
+          if (kStopBelow && sqrtf(h.d2) < stop_below) return;
+        }
       }
     }
     // the nearest surviving inner child is next; the others are pushed
@@ -1246,10 +1251,10 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
 // r - tol away and the ball lies inside the scene's bounding sphere. 0 = no
 // radius accepted. Each step needs only whether some triangle lies closer
 // than t = r - tol, so its query starts from the bound B = t^2 (1 + 2^-20)
-// instead of +inf: when a triangle has sqrt(d2) < t then d2 < B, the query
-// finds the exact minimum below B and the test is taken on it as before;
-// when none lies below B the ball is accepted. Same decisions as an unbounded
-// query, with only the boxes near the ball visited.
+// instead of +inf (when a triangle has sqrt(d2) < t then d2 < B) and stops at
+// the first triangle found with sqrt(d2) < t; when none lies below B the ball
+// is accepted. Same decisions as comparing the exact nearest distance with t,
+// with only the boxes near the ball visited.
 __global__ void tangent_ball_kernel(MeshDev M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rows) return;
@@ -1267,7 +1272,7 @@ __global__ void tangent_ball_kernel(MeshDev M, int64_t n_rows, float r_max, int3
     Nearest h;
     h.d2 = bound; h.orig = INT_MAX; h.slot = -1;
     TravCount cnt;
-    if (t > 0.0f) bvh_nearest<false>(M.nodes, M.tris, nullptr, 0, cx, cy, cz, M.radius, h, cnt);
+    if (t > 0.0f) bvh_nearest<false, true>(M.nodes, M.tris, nullptr, 0, cx, cy, cz, M.radius, h, cnt, t);
     const bool empty = h.orig == INT_MAX || sqrtf(h.d2) >= t;
     const bool inside = empty && sqrt(cxd * cxd + cyd * cyd + czd * czd) + mid <= M.radius_d;
     if (inside)

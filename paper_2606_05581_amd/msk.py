@@ -99,7 +99,8 @@ class PsdInfo(C.Structure):
                 ("queries_total", C.c_int64), ("escaped_total", C.c_int64), ("capped_total", C.c_int64),
                 ("dropped_rows", C.c_int64), ("mean_radius", C.c_double), ("r_max", C.c_double),
                 ("tangent_ms", C.c_double), ("walk_kernel_ms", C.c_double), ("gather_ms", C.c_double),
-                ("product_ms", C.c_double), ("total_ms", C.c_double), ("nonfinite_entries", C.c_int64)]
+                ("product_ms", C.c_double), ("total_ms", C.c_double), ("nonfinite_entries", C.c_int64),
+                ("fused", C.c_int32)]
 
 
 class PsdLog(C.Structure):

@@ -105,14 +105,17 @@ def test_psd_unit_sphere_closed_form_and_parity(ctx, oracle_mod):
         assert abs(S[i, i] - want[deg[i]]) <= 4 * se[i, i] + 0.03 * want[deg[i]], (i, S[i, i], want[deg[i]])
 
 
-def test_psd_wide_basis_and_chunks(ctx, oracle_mod):
-    """K = 300 random dense columns (more columns than gather threads), and the
-    result does not depend on the chunking of the pairs (up to FP64 rounding)."""
+@pytest.mark.parametrize("K", [300, 400])
+def test_psd_wide_basis_and_chunks(ctx, oracle_mod, K):
+    """Random dense columns beyond the gather threads: K = 300 takes the fused
+    kernel (rows in LDS), K = 400 the two-pass form (gather, then products);
+    the result does not depend on the chunking of the pairs (FP64 rounding)."""
     V, F = W.box_grid(4, half=(0.8, 0.5, 0.6))
     rows = W.point_rows(V, F, 120, np.random.default_rng(4))
-    tab = np.random.default_rng(9).normal(size=(V.shape[0], 300))
+    tab = np.random.default_rng(9).normal(size=(V.shape[0], K))
     g, o = _run_both(ctx, oracle_mod, V.astype(np.float32), F, rows, tab, 8, 1e-3, seed=12)
-    _check_parity(g, o, oracle_mod.psd_r_max(V), "box K=300")
+    assert g["info"]["fused"] == (1 if K <= 384 else 0)
+    _check_parity(g, o, oracle_mod.psd_r_max(V), f"box K={K}")
     mesh = ctx.build_bvh(V.astype(np.float32), F)
     rh = ctx.rows(mesh, rows)
     bh = ctx.basis(_dense_basis(tab), V.shape[0])

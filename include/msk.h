@@ -399,8 +399,8 @@ typedef struct {  /* optional host walk log, n_rows x 2 pairs entries each    */
  *   - row i's sample s_i (its face, barycentrics and outward face normal)
  *     gets the largest inscribed tangent ball B_r(c), c = s - r n, by
  *     bisection (a radius is accepted when c's nearest surface point is at
- *     least r - eps/2 away and the ball lies in the scene's bounding sphere;
- *     rows with no accepted radius are dropped);
+ *     least r - min(eps/2, r/1024) away and the ball lies in the scene's
+ *     bounding sphere; rows with no accepted radius are dropped);
  *   - `pairs` antithetic pairs of points z on the ball are drawn with density
  *     proportional to the ball jump kernel 1/(2 pi |s-z|^3) outside the cap
  *     (Philox counter (row, pair, 0, purpose 4 << 24 | mesh_id)); walk 2j+a
@@ -418,6 +418,10 @@ typedef struct {  /* optional host walk log, n_rows x 2 pairs entries each    */
  *   S, se:  host, K x K doubles (se may be NULL);
  *   radius: host, n_rows floats (tangent radii, 0 = dropped) or NULL;
  *   log:    optional host walk log; info: optional.
+ * Ball points next to s lie within eps of the surface and their walks end at
+ * once, so a coarse shell biases the estimate low (on a unit sphere eps =
+ * 1e-3 gives about 1% less than eps <= 1e-4): use eps well below the
+ * finite-difference estimator's inset (the paper runs at 1e-6).
  * walk_opts: seed, max_steps, kappa, delta_rel, form, launch settings and
  * mesh_id as for msk_estimate_dtn (walk_offset, se_target, record_log and
  * collect_stats are ignored). Errors: INVALID_ARG for hat rows, pairs < 1,

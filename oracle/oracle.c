@@ -769,12 +769,14 @@ void orc_estimate(const void* h, int mode_start, int exterior, int64_t n_rows, c
 /* Largest ball inside the domain that touches the surface at s, centre
  * c = s - r n (Sec. 3.2; Alg. 2, LargestTangentBall): bisection over
  * r in [0, r_max] for `iters` steps; a radius is accepted when the nearest
- * surface point of c is at least r - tol away (tol = half the walk's
- * termination shell: a ball point outside the domain is then within the
- * shell and its walk ends at once) and the ball lies inside the scene's
- * bounding sphere (as every ball inside the domain does). Returns the last
- * accepted radius (0 when none is: the sample is then dropped, Appendix A).
- * s, n are scene-relative, n the outward unit normal. */
+ * surface point of c is at least r - min(tol, 2^-10 r) away and the ball lies
+ * inside the scene's bounding sphere (as every ball inside the domain does).
+ * tol is half the walk's termination shell, so a ball point outside the
+ * domain lies within the shell and its walk ends at once; the relative bound
+ * keeps small balls (next to edges of a faceted surface) essentially inside.
+ * Returns the last accepted radius (0 when none is: the sample is then
+ * dropped, Appendix A). s, n are scene-relative, n the outward unit normal. */
+#define TANGENT_REL_TOL (1.0 / 1024.0)
 double orc_tangent_ball(const void* h, const double* s, const double* n, double r_max, int iters, double tol) {
   const OrcScene* sc = (const OrcScene*)h;
   double lo = 0.0, hi = r_max;
@@ -784,7 +786,8 @@ double orc_tangent_ball(const void* h, const double* s, const double* n, double 
     int64_t tt;
     double bb[3];
     double d = sqrt(nearest(sc, c, &tt, bb));
-    if (d >= mid - tol && sqrt(dot3(c, c)) + mid <= sc->radius)
+    double t = mid - fmin(tol, mid * TANGENT_REL_TOL);
+    if (d >= t && sqrt(dot3(c, c)) + mid <= sc->radius)
       lo = mid;
     else
       hi = mid;

@@ -1247,14 +1247,14 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
 // discarded (the inset left the thin region it should probe).
 // Largest ball inside the domain tangent at each point row's sample s, centre
 // c = s - r n (Sec. 3.2; Alg. 2, LargestTangentBall): bisection over
-// [0, r_max]; a radius is accepted when c's nearest surface point is at least
-// r - tol away and the ball lies inside the scene's bounding sphere. 0 = no
-// radius accepted. Each step needs only whether some triangle lies closer
-// than t = r - tol, so its query starts from the bound B = t^2 (1 + 2^-20)
-// instead of +inf (when a triangle has sqrt(d2) < t then d2 < B) and stops at
-// the first triangle found with sqrt(d2) < t; when none lies below B the ball
-// is accepted. Same decisions as comparing the exact nearest distance with t,
-// with only the boxes near the ball visited.
+// [0, r_max]; a radius is accepted when c's nearest surface point is at
+// least t = r - min(tol, 2^-10 r) away and the ball lies inside the scene's
+// bounding sphere. 0 = no radius accepted. Each step needs only whether some
+// triangle lies closer than t, so its query starts from the bound
+// B = t^2 (1 + 2^-20) instead of +inf (when a triangle has sqrt(d2) < t then
+// d2 < B) and stops at the first triangle found with sqrt(d2) < t; when none
+// lies below B the ball is accepted. Same decisions as comparing the exact
+// nearest distance with t, with only the boxes near the ball visited.
 __global__ void tangent_ball_kernel(MeshDev M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rows) return;
@@ -1267,7 +1267,7 @@ __global__ void tangent_ball_kernel(MeshDev M, int64_t n_rows, float r_max, int3
     const float mid = 0.5f * (lo + hi);
     const double cxd = sx - mid * nx, cyd = sy - mid * ny, czd = sz - mid * nz;
     const float cx = (float)cxd, cy = (float)cyd, cz = (float)czd;
-    const float t = mid - tol;
+    const float t = mid - fminf(tol, mid * 0x1p-10f);
     const float bound = t > 0.0f ? (t * t) * (1.0f + 0x1p-20f) : 0.0f;
     Nearest h;
     h.d2 = bound; h.orig = INT_MAX; h.slot = -1;

@@ -656,7 +656,7 @@ def psd_sh_sphere_2m(n=316, N=16384, pairs=320, K=128):
     rows = point_rows(V, F, N, rng, pool_factor=4)
     area, _ = face_geometry(V, F)
     h = 0.25 * math.sqrt(area.sum() / N)
-    eps = min(1e-3, h / 10.0)
+    eps = 1e-5  # the PSD walks start next to the surface: a fine termination shell (the paper's is 1e-6)
     L = int(math.ceil(math.sqrt(K))) - 1
     table = real_sh(L, V)[:, :K]
     case = MeshCase(V=V.astype(np.float32), F=F.astype(np.int32), rows=rows, basis=dense_basis(table), eps=eps, h=h)

@@ -22,7 +22,9 @@
  *   - The naive finite-difference estimator (Sec. 3.1, Alg. 1; eqs.
  *     finite-difference-estimator and naive-stiffness-matrix): every walk
  *     contributes c = b(s) - b(t) to the row of its sample, b = barycentric
- *     interpolation of a per-vertex basis table (Sec. 3.4).
+ *     interpolation of a per-vertex basis table (Sec. 3.4), or the point
+ *     basis's k-nearest-neighbour interpolation with bilateral weights
+ *     (Appendix, point-based k-NN interpolator).
  *   - The PSD estimator of Sec. 3.2 (Alg. 2; eqs. strong-markov-property,
  *     ball-jump-kernel, volume-jump-kernel and the boxed estimator): the
  *     largest tangent ball at each sample by bisection, ball points drawn
@@ -650,6 +652,69 @@ static void sp_add(Sparse* c, const OrcBasis* B, int64_t vtx, double lam) {
   }
 }
 
+/* Point basis (Appendix, point-based k-NN interpolator): column j is sample
+ * point x_j (normal n_j); at a query q with normal n_q the basis values are
+ * the bilateral weights of q's k nearest points (Euclidean distance, ties by
+ * index), w_j = exp(-|q - x_j|^2 / (2 sigma^2)) exp(-(1 - n_q . n_j) / tau),
+ * normalised over the k; all other columns are 0. */
+typedef struct {
+  const double* x;  /* (N,3) scene-relative */
+  const double* n;  /* (N,3) unit normals */
+  int64_t N;
+  int k;
+  double sigma, tau;
+} OrcKnn;
+
+/* k nearest points of q: the k smallest (squared distance, index) pairs. */
+int orc_knn_query(const double* x, int64_t N, int k, const double* q, int32_t* idx, double* d2) {
+  int m = 0;
+  for (int64_t j = 0; j < N; ++j) {
+    const double d[3] = {x[3 * j] - q[0], x[3 * j + 1] - q[1], x[3 * j + 2] - q[2]};
+    const double dd = dot3(d, d);
+    if (m == k && !(dd < d2[k - 1])) continue; /* equal distance: the lower index is already kept */
+    int pos = m < k ? m++ : k - 1;
+    while (pos > 0 && dd < d2[pos - 1]) {
+      d2[pos] = d2[pos - 1];
+      idx[pos] = idx[pos - 1];
+      --pos;
+    }
+    d2[pos] = dd;
+    idx[pos] = (int32_t)j;
+  }
+  return m;
+}
+
+/* Bilateral k-NN weights at q (normal nq): returns the neighbour count. */
+int orc_knn_weights(const double* x, const double* n, int64_t N, int k, double sigma, double tau, const double* q,
+                    const double* nq, int32_t* idx, double* w) {
+  double d2[64];
+  int m = orc_knn_query(x, N, k, q, idx, d2);
+  double sum = 0.0;
+  for (int a = 0; a < m; ++a) {
+    const double* nj = n + 3 * (int64_t)idx[a];
+    w[a] = exp(-d2[a] / (2.0 * sigma * sigma)) * exp(-(1.0 - dot3(nq, nj)) / tau);
+    sum += w[a];
+  }
+  for (int a = 0; a < m; ++a) w[a] /= sum;
+  return m;
+}
+
+static void knn_add(Sparse* c, const OrcKnn* P, const double* q, const double* nq, double sign) {
+  int32_t idx[64];
+  double w[64];
+  int m = orc_knn_weights(P->x, P->n, P->N, P->k, P->sigma, P->tau, q, nq, idx, w);
+  for (int a = 0; a < m; ++a) {
+    int t;
+    for (t = 0; t < c->n; ++t)
+      if (c->col[t] == idx[a]) break;
+    if (t == c->n) {
+      if (c->n == 256) abort();
+      c->col[t] = idx[a]; c->val[t] = 0; c->n++;
+    }
+    c->val[t] += sign * w[a];
+  }
+}
+
 /* Estimate rows of the naive DtN estimator.
  *
  * mode_start: 0 = point rows (fixed sample s = p_i on face tri_i with
@@ -671,9 +736,20 @@ void orc_estimate(const void* h, int mode_start, int exterior, int64_t n_rows, c
                   double* acc, double* acc2, int64_t* n_query, int64_t* n_escaped, int64_t* n_capped,
                   int32_t* discarded,
                   int32_t* log_status, int64_t* log_tri, float* log_bary, int64_t* log_nquery,
-                  int32_t* log_stri, float* log_sbary) {
+                  int32_t* log_stri, float* log_sbary,
+                  /* optional point basis (point rows): points and normals in world coordinates */
+                  const double* knn_x, const double* knn_n, int64_t knn_N, int knn_k, double knn_sigma,
+                  double knn_tau) {
   const OrcScene* s = (const OrcScene*)h;
   OrcBasis B = {rowptr, col, val, K};
+  OrcKnn KN = {NULL, knn_n, knn_N, knn_k, knn_sigma, knn_tau};
+  double* xrel = NULL;
+  if (knn_x) {
+    xrel = (double*)malloc(sizeof(double) * 3 * (size_t)(knn_N > 0 ? knn_N : 1));
+    for (int64_t j = 0; j < knn_N; ++j)
+      for (int k = 0; k < 3; ++k) xrel[3 * j + k] = knn_x[3 * j + k] - s->centre[k];
+    KN.x = xrel;
+  }
   OrcWalkParams P = {eps, kappa, delta, max_steps, seed, mesh};
   double sgn = exterior ? 1.0 : -1.0;
   (void)nthreads;
@@ -735,13 +811,36 @@ void orc_estimate(const void* h, int mode_start, int exterior, int64_t n_rows, c
         for (int cc = 0; cc < 3; ++cc)
           for (int k = 0; k < 3; ++k) sp[k] += lam[cc] * s->V[3 * (int64_t)s->F[3 * face + cc] + k];
       }
-      for (int cc = 0; cc < 3; ++cc) sp_add(&c, &B, s->F[3 * face + cc], lam[cc]);
+      if (KN.x) {
+        double nl = sqrt(dot3(n, n));
+        double nu[3] = {n[0] / nl, n[1] / nl, n[2] / nl};
+        knn_add(&c, &KN, sp, nu, 1.0);
+      } else {
+        for (int cc = 0; cc < 3; ++cc) sp_add(&c, &B, s->F[3 * face + cc], lam[cc]);
+      }
       double x[3] = {sp[0] + sgn * hin * n[0], sp[1] + sgn * hin * n[1], sp[2] + sgn * hin * n[2]};
       int64_t tt = -1, nq = 0, ns = 0;
       double bt[3] = {0, 0, 0};
       int st = walk(s, &P, (uint32_t)i, (uint32_t)w, x, &tt, bt, &nq, &ns);
-      if (st != ST_ESCAPED)
+      if (st != ST_ESCAPED && KN.x) {
+        /* hit point and its face normal */
+        const double* va = s->V + 3 * (int64_t)s->F[3 * tt];
+        const double* vb = s->V + 3 * (int64_t)s->F[3 * tt + 1];
+        const double* vc = s->V + 3 * (int64_t)s->F[3 * tt + 2];
+        double q[3], e1[3], e2[3], nt[3];
+        for (int k = 0; k < 3; ++k) {
+          q[k] = bt[0] * va[k] + bt[1] * vb[k] + bt[2] * vc[k];
+          e1[k] = vb[k] - va[k];
+          e2[k] = vc[k] - va[k];
+        }
+        cross3(e1, e2, nt);
+        double nl = sqrt(dot3(nt, nt));
+        if (nl > 0)
+          for (int k = 0; k < 3; ++k) nt[k] /= nl;
+        knn_add(&c, &KN, q, nt, -1.0);
+      } else if (st != ST_ESCAPED) {
         for (int cc = 0; cc < 3; ++cc) sp_add(&c, &B, s->F[3 * tt + cc], -bt[cc]);
+      }
       for (int m = 0; m < c.n; ++m) {
         A1[c.col[m]] += c.val[m];
         A2[c.col[m]] += c.val[m] * c.val[m];
@@ -762,6 +861,7 @@ void orc_estimate(const void* h, int mode_start, int exterior, int64_t n_rows, c
       }
     }
   }
+  free(xrel);
 }
 
 /* ------------------------------------------------- PSD estimator (Sec. 3.2) */
@@ -830,7 +930,7 @@ void orc_ball_point(const double* c, double r, const double* n, double theta0, d
  * z importance-sampled gives, per pair p of row i,
  *   X_p = alpha_i (d_1 d_1^T + d_2 d_2^T) / 2,  alpha_i = w_i Z_i / (2 pairs),
  * with Z_i = orc_ball_jump_mass(r_i, theta0) the weight J / density and
- * d = b(s_i) - b(t). The tangent-ball tolerance is eps / 2. Outputs: S = sum_p X_p and Q = sum_p X_p * X_p
+ * d = b(s_i) - b(t). The tangent-ball tolerance is min(eps / 2, r / 1024). Outputs: S = sum_p X_p and Q = sum_p X_p * X_p
  * (elementwise), both K x K; per-row radius (0 = dropped) and Z; an optional
  * walk log (n_rows x 2 pairs: status, terminal triangle, its barycentrics of
  * vertices 1 and 2, queries). The basis is a dense per-vertex table tab

@@ -86,7 +86,11 @@ def lib():
                C.c_uint32, C.c_int]
             + [_P(C.c_double), _P(C.c_double), _P(C.c_int64), _P(C.c_int64), _P(C.c_int64), _P(C.c_int32)]
             + [_P(C.c_int32), _P(C.c_int64), _P(C.c_float), _P(C.c_int64), _P(C.c_int32), _P(C.c_float)]
+            + [_P(C.c_double), _P(C.c_double), C.c_int64, C.c_int, C.c_double, C.c_double]
         )
+        L.orc_knn_weights.argtypes = [_P(C.c_double), _P(C.c_double), C.c_int64, C.c_int, C.c_double, C.c_double,
+                                      _P(C.c_double), _P(C.c_double), _P(C.c_int32), _P(C.c_double)]
+        L.orc_knn_weights.restype = C.c_int
         L.orc_tangent_ball.argtypes = [C.c_void_p, _P(C.c_double), _P(C.c_double), C.c_double, C.c_int, C.c_double]
         L.orc_tangent_ball.restype = C.c_double
         L.orc_ball_jump_mass.argtypes = [C.c_double, C.c_double]
@@ -226,8 +230,12 @@ DEFAULT_MAX_STEPS = {"interior": 1024, "exterior": 8192}
 
 def estimate(scene: Scene, rows, basis, walks: int, eps: float, h: float, exterior: bool, seed: int = 0,
              w0: int = 0, rows_sel=None, kappa=2.0 ** -20, delta_rel=2.0 ** -21, max_steps=None, mesh: int = 0,
-             log: bool = False, nthreads: int = 1):
+             log: bool = False, nthreads: int = 1, knn=None):
     """Accumulate the naive estimator's per-walk contributions c = b(s) - b(t).
+
+    ``knn`` (point rows only) replaces the per-vertex table by the point
+    basis: a dict with ``points`` (N,3 world), ``normals`` (N,3 unit), ``k``,
+    ``sigma``, ``tau``; the K = N columns are the points.
 
     Returns a dict with ``acc`` (sum of c), ``acc2`` (sum of c^2), each
     (n_rows_selected, K), per-row query / escape / capped counts, discard
@@ -240,7 +248,14 @@ def estimate(scene: Scene, rows, basis, walks: int, eps: float, h: float, exteri
     mode = 0 if rows.mode == "point" else 1
     sel = None if rows_sel is None else np.ascontiguousarray(rows_sel, dtype=np.int32)
     n = rows.n_rows if sel is None else sel.shape[0]
-    K = int(basis.K)
+    if knn is not None:
+        if mode != 0 or not (1 <= int(knn["k"]) <= 32):
+            raise ValueError("the point basis takes point rows and 1 <= k <= 32")
+        kx, kn = _c(knn["points"], np.float64), _c(knn["normals"], np.float64)
+        K = kx.shape[0]
+    else:
+        kx = kn = None
+        K = int(basis.K)
     acc = np.zeros((n, K))
     acc2 = np.zeros((n, K))
     nq = np.zeros(n, dtype=np.int64)
@@ -261,7 +276,10 @@ def estimate(scene: Scene, rows, basis, walks: int, eps: float, h: float, exteri
                         _c(rows.bary, np.float32))
     rp, rt, rc, fn = (_c(rows.ring_ptr, np.int32), _c(rows.ring_tri, np.int32), _c(rows.ring_cum, np.float64),
                       _c(rows.fn, np.float32))
-    brp, bc, bv = _c(basis.rowptr, np.int32), _c(basis.col, np.int32), _c(basis.val, np.float32)
+    if basis is not None:
+        brp, bc, bv = _c(basis.rowptr, np.int32), _c(basis.col, np.int32), _c(basis.val, np.float32)
+    else:
+        brp = bc = bv = None
     lib().orc_estimate(
         scene.h, mode, int(exterior), n, _ptr(sel, C.c_int32),
         _ptr(p, C.c_float), _ptr(nn, C.c_float), _ptr(tri, C.c_int32), _ptr(bary, C.c_float),
@@ -271,7 +289,10 @@ def estimate(scene: Scene, rows, basis, walks: int, eps: float, h: float, exteri
         _ptr(acc, C.c_double), _ptr(acc2, C.c_double), _ptr(nq, C.c_int64), _ptr(nesc, C.c_int64),
         _ptr(ncap, C.c_int64), _ptr(disc, C.c_int32),
         _ptr(ls, C.c_int32), _ptr(lt, C.c_int64), _ptr(lb, C.c_float), _ptr(lq, C.c_int64),
-        _ptr(lst, C.c_int32), _ptr(lsb, C.c_float))
+        _ptr(lst, C.c_int32), _ptr(lsb, C.c_float),
+        _ptr(kx, C.c_double), _ptr(kn, C.c_double), 0 if kx is None else kx.shape[0],
+        0 if knn is None else int(knn["k"]), 0.0 if knn is None else float(knn["sigma"]),
+        0.0 if knn is None else float(knn["tau"]))
     out = dict(acc=acc, acc2=acc2, n_query=nq, n_escaped=nesc, n_capped=ncap, discarded=disc, walks=walks)
     if log:
         out.update(log_status=ls, log_tri=lt, log_bary=lb, log_nquery=lq, log_stri=lst, log_sbary=lsb)
@@ -401,3 +422,19 @@ def psd_standard_error(S, Q, n_pairs):
     """Standard error of S = sum_p X_p over n_pairs pair terms, the pairs taken as
     independent draws of n_pairs X_p: se^2 = (n_pairs Q - S^2) / (n_pairs - 1)."""
     return np.sqrt(np.maximum(0.0, n_pairs * Q - S * S) / (n_pairs - 1.0))
+
+
+# ------------------------------------------------------- point basis (k-NN)
+
+
+def knn_weights(points, normals, q, nq, k, sigma, tau):
+    """Bilateral k-NN weights at query q with normal nq (Appendix, point-based
+    k-NN interpolator): (indices of the k nearest points, ties by index, and
+    their normalised weights)."""
+    x, n = _c(points, np.float64), _c(normals, np.float64)
+    qq, nn = _c(q, np.float64), _c(nq, np.float64)
+    idx = np.zeros(k, dtype=np.int32)
+    w = np.zeros(k)
+    m = lib().orc_knn_weights(_ptr(x, C.c_double), _ptr(n, C.c_double), x.shape[0], k, sigma, tau,
+                              _ptr(qq, C.c_double), _ptr(nn, C.c_double), _ptr(idx, C.c_int32), _ptr(w, C.c_double))
+    return idx[:m], w[:m]

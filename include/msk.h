@@ -159,6 +159,30 @@ void msk_rows_destroy(msk_rows* rows);
  * l_a table[a] + l_b table[b] + l_c table[c] (Sec. 3.4). */
 msk_status msk_basis_create(msk_ctx* ctx, const int32_t* rowptr, const int32_t* col, const float* val,
                             int64_t n_verts, int64_t K, msk_basis** out);
+
+/* Point basis (Appendix, point-based k-NN interpolator) for point rows of
+ * `mesh`: column j is sample point x_j with unit normal n_j (host, n_points
+ * x 3 floats each, world coordinates; normals are normalised here). At a
+ * query q with normal n_q the basis values are the bilateral weights of its
+ * k nearest points (Euclidean distance, ties by index),
+ *   w_j = exp(-|q - x_j|^2 / (2 sigma^2)) exp(-(1 - n_q . n_j) / tau_n),
+ * normalised over the k (equal shares if all underflow); the other columns
+ * are 0. The estimators evaluate it at the sample s (its row's normal) and at
+ * each walk's hit point (the hit triangle's face normal), so K = n_points.
+ * The points are binned in a uniform grid of the scene frame (cells of about
+ * two sample spacings, sqrt(mesh area / n_points)); a query searches rings
+ * of cells until the k-th distance is inside the searched block.
+ * Errors: INVALID_ARG for k outside 1..16, n_points < k, sigma or tau_n
+ * <= 0, non-finite points or zero normals. Used with other meshes, hat rows,
+ * the PSD estimator or collect_stats it is rejected (INVALID_ARG). */
+msk_status msk_basis_create_knn(msk_ctx* ctx, const msk_mesh* mesh, const float* points, const float* normals,
+                                int64_t n_points, int32_t k, double sigma, double tau_n, msk_basis** out);
+
+/* The point basis at n queries (device arrays: Q and Nq n x 3 floats, world
+ * positions and normals; out: idx n x k int32 point indices, nearest first,
+ * and w n x k float weights). Errors: INVALID_ARG for a table basis. */
+msk_status msk_basis_eval_knn(msk_ctx* ctx, const msk_basis* basis, const float* Q, const float* Nq, int64_t n,
+                              int32_t* idx, float* w);
 void msk_basis_destroy(msk_basis* basis);
 
 /* -------------------------------------------------------------- estimate */

@@ -695,7 +695,7 @@ int orc_knn_weights(const double* x, const double* n, int64_t N, int k, double s
     w[a] = exp(-d2[a] / (2.0 * sigma * sigma)) * exp(-(1.0 - dot3(nq, nj)) / tau);
     sum += w[a];
   }
-  for (int a = 0; a < m; ++a) w[a] /= sum;
+  for (int a = 0; a < m; ++a) w[a] = sum > 0.0 ? w[a] / sum : 1.0 / m; /* all weights underflowed: equal shares */
   return m;
 }
 

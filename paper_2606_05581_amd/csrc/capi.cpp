@@ -58,6 +58,13 @@ struct msk_rows {
 struct msk_basis {
   msk_ctx* ctx = nullptr;
   int64_t nv = 0, K = 0;
+  // point basis (k nearest sample points): set for msk_basis_create_knn
+  const msk_mesh* knn_mesh = nullptr;
+  KnnDev kd{};
+  float4* d_kpts = nullptr;
+  float4* d_knrm = nullptr;
+  int32_t* d_cell_start = nullptr;
+  int32_t* d_cell_pts = nullptr;
   int32_t max_row_nnz = 0;  // the walk estimators merge at most kMaxTableNnz entries per vertex
   int32_t* d_rowptr = nullptr;
   int32_t* d_col = nullptr;
@@ -406,7 +413,109 @@ extern "C" void msk_basis_destroy(msk_basis* b) {
   dfree(b->d_rowptr);
   dfree(b->d_col);
   dfree(b->d_val);
+  dfree(b->d_kpts);
+  dfree(b->d_knrm);
+  dfree(b->d_cell_start);
+  dfree(b->d_cell_pts);
   delete b;
+}
+
+extern "C" msk_status msk_basis_create_knn(msk_ctx* ctx, const msk_mesh* m, const float* points,
+                                           const float* normals, int64_t n_points, int32_t k, double sigma,
+                                           double tau_n, msk_basis** out) {
+  if (!ctx || !out) return MSK_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!m || !points || !normals) return fail(ctx, MSK_ERR_INVALID_ARG, "null mesh or point arrays");
+  if (k < 1 || k > kMaxKnn) return fail(ctx, MSK_ERR_INVALID_ARG, "k must be in 1..16");
+  if (n_points < k || n_points >= INT32_MAX) return fail(ctx, MSK_ERR_INVALID_ARG, "need k <= n_points < 2^31");
+  if (!(sigma > 0) || !(tau_n > 0) || !std::isfinite(sigma) || !std::isfinite(tau_n))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "sigma and tau_n must be positive");
+  // scene-frame positions and unit normals
+  std::vector<float4> P((size_t)n_points), Nn((size_t)n_points);
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t j = 0; j < n_points; ++j) {
+    double q[3], nn[3], l2 = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (!std::isfinite(points[3 * j + a]) || !std::isfinite(normals[3 * j + a]))
+        return fail(ctx, MSK_ERR_INVALID_ARG, "non-finite point or normal");
+      q[a] = (double)points[3 * j + a] - m->centre[a];
+      nn[a] = normals[3 * j + a];
+      l2 += nn[a] * nn[a];
+    }
+    if (!(l2 > 0)) return fail(ctx, MSK_ERR_INVALID_ARG, "zero normal");
+    const double il = 1.0 / std::sqrt(l2);
+    P[j] = make_float4((float)q[0], (float)q[1], (float)q[2], 0.0f);
+    Nn[j] = make_float4((float)(nn[0] * il), (float)(nn[1] * il), (float)(nn[2] * il), 0.0f);
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], (double)((&P[j].x)[a]));
+      hi[a] = std::max(hi[a], (double)((&P[j].x)[a]));
+    }
+  }
+  // uniform grid: cells of about two sample spacings (spacing ~ sqrt(area / N)),
+  // at most 2^24 cells
+  double cell = 2.0 * std::sqrt(std::max(m->area, 1e-30) / (double)n_points);
+  const double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+  cell = std::max(cell, ext * 1e-6 + 1e-30);
+  int64_t dim[3];
+  while (true) {
+    for (int a = 0; a < 3; ++a) dim[a] = std::max<int64_t>(1, (int64_t)std::floor((hi[a] - lo[a]) / cell) + 1);
+    if (dim[0] * dim[1] * dim[2] <= ((int64_t)1 << 24)) break;
+    cell *= 1.25;
+  }
+  const int64_t nc = dim[0] * dim[1] * dim[2];
+  std::vector<int32_t> cs((size_t)nc + 1, 0), cp((size_t)n_points), cid((size_t)n_points);
+  for (int64_t j = 0; j < n_points; ++j) {
+    int64_t c[3];
+    for (int a = 0; a < 3; ++a)
+      c[a] = std::min<int64_t>(dim[a] - 1,
+                               std::max<int64_t>(0, (int64_t)std::floor(((&P[j].x)[a] - (float)lo[a]) / (float)cell)));
+    cid[j] = (int32_t)((c[2] * dim[1] + c[1]) * dim[0] + c[0]);
+    ++cs[cid[j] + 1];
+  }
+  for (int64_t c = 0; c < nc; ++c) cs[c + 1] += cs[c];
+  std::vector<int32_t> fill(cs.begin(), cs.end() - 1);
+  for (int64_t j = 0; j < n_points; ++j) cp[fill[cid[j]]++] = (int32_t)j;
+  msk_basis* b = new msk_basis();
+  b->ctx = ctx;
+  b->nv = m->nv;
+  b->K = n_points;
+  b->max_row_nnz = k;
+  b->knn_mesh = m;
+  hipError_t he;
+  if ((he = upload(ctx, &b->d_kpts, P.data(), P.size())) != hipSuccess ||
+      (he = upload(ctx, &b->d_knrm, Nn.data(), Nn.size())) != hipSuccess ||
+      (he = upload(ctx, &b->d_cell_start, cs.data(), cs.size())) != hipSuccess ||
+      (he = upload(ctx, &b->d_cell_pts, cp.data(), cp.size())) != hipSuccess) {
+    msk_basis_destroy(b);
+    return fail(ctx, he == hipErrorOutOfMemory ? MSK_ERR_OOM : MSK_ERR_DEVICE,
+                std::string("point basis upload: ") + hipGetErrorString(he));
+  }
+  KnnDev& G = b->kd;
+  G.pts = b->d_kpts;
+  G.nrm = b->d_knrm;
+  G.cell_start = b->d_cell_start;
+  G.cell_pts = b->d_cell_pts;
+  for (int a = 0; a < 3; ++a) {
+    G.lo[a] = (float)lo[a];
+    G.dim[a] = (int32_t)dim[a];
+  }
+  G.cell = (float)cell;
+  G.k = k;
+  G.inv2s2 = 1.0 / (2.0 * sigma * sigma);
+  G.inv_tau = 1.0 / tau_n;
+  *out = b;
+  return MSK_OK;
+}
+
+extern "C" msk_status msk_basis_eval_knn(msk_ctx* ctx, const msk_basis* b, const float* Q, const float* Nq,
+                                         int64_t n, int32_t* idx, float* w) {
+  if (!ctx || !b) return MSK_ERR_INVALID_ARG;
+  if (!b->knn_mesh) return fail(ctx, MSK_ERR_INVALID_ARG, "not a point basis");
+  if (n < 0 || (n > 0 && (!Q || !Nq || !idx || !w))) return fail(ctx, MSK_ERR_INVALID_ARG, "bad query arrays");
+  if (n == 0) return MSK_OK;
+  HIP_TRY(ctx, launch_knn_eval(b->kd, b->knn_mesh->centre, Q, Nq, n, idx, w, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MSK_OK;
 }
 
 // ------------------------------------------------------------ estimate
@@ -460,6 +569,8 @@ msk_status check_problem(msk_ctx* ctx, const msk_mesh* m, const msk_rows* r, con
   if (!m || !r || !b) return fail(ctx, MSK_ERR_INVALID_ARG, "null mesh / rows / basis");
   if (r->mesh != m) return fail(ctx, MSK_ERR_INVALID_ARG, "rows were created for another mesh");
   if (b->nv != m->nv) return fail(ctx, MSK_ERR_INVALID_ARG, "basis vertex count differs from the mesh's");
+  if (b->knn_mesh && b->knn_mesh != m) return fail(ctx, MSK_ERR_INVALID_ARG, "point basis built for another mesh");
+  if (b->knn_mesh && r->mode != MSK_ROWS_POINT) return fail(ctx, MSK_ERR_INVALID_ARG, "the point basis takes point rows");
   if (row_sums && b->max_row_nnz > kMaxTableNnz)
     return fail(ctx, MSK_ERR_INVALID_ARG, "the walk estimators take at most 32 basis entries per vertex");
   if (walks < 2 || walks > INT32_MAX) return fail(ctx, MSK_ERR_INVALID_ARG, "walks must be in 2..2^31-1");
@@ -536,6 +647,7 @@ MeshDev make_meshdev(const msk_mesh* m, const msk_rows* r, const msk_basis* b, m
   M.b_col = b->d_col;
   M.b_val = b->d_val;
   M.K = b->K;
+  if (b->knn_mesh) M.knn = b->kd;
   M.acc1 = d->d_acc1;
   M.acc2 = d->d_acc2;
   M.row_queries = d->d_q;
@@ -604,6 +716,7 @@ static msk_status run_walks(msk_ctx* ctx, const std::vector<MeshDev>& meshes, co
   L.use_lds_top = use_lds_top;
   L.n_top = n_top;
   L.accum_f32 = o.accum == 1 ? 1 : 0;
+  for (const MeshDev& md : meshes) L.knn |= md.knn.k > 0 ? 1 : 0;
   if (o.collect_stats) {
     HIP_TRY(ctx, dalloc(&lb.d_stats, 3));
     HIP_TRY(ctx, launch_fill_u64(lb.d_stats, 3, 0, ctx->stream));
@@ -680,6 +793,8 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
   if (opts) o = *opts;
   if (o.form != MSK_FORM_PLAIN && o.form != MSK_FORM_PERSISTENT) return fail(ctx, MSK_ERR_INVALID_ARG, "bad form");
   if (o.accum != 0 && o.accum != 1) return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64) or 1 (FP32)");
+  if (o.collect_stats && b && b->knn_mesh)
+    return fail(ctx, MSK_ERR_INVALID_ARG, "traversal statistics are not collected with the point basis");
   if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32) ||
       (o.se_target > 0 && o.walk_offset + o.walks_max > ((int64_t)1 << 32)))
     return fail(ctx, MSK_ERR_INVALID_ARG, "walk indices must fit in 32 bits");
@@ -866,6 +981,7 @@ static hipError_t enqueue_batch(msk_batch* B, hipStream_t s, int part) {
     L.chunk = std::max(1, B->o.chunk);
     L.regen_min = std::min(64, std::max(1, B->o.regen_min));
     L.accum_f32 = B->o.accum == 1 ? 1 : 0;
+    for (const MeshDev& md : B->md) L.knn |= md.knn.k > 0 ? 1 : 0;
     for (msk_dtn* d : B->dtns) L.n_slots += d->n;
     if (B->o.collect_stats) L.stats = B->lb.d_stats;
     if (B->o.form == MSK_FORM_PLAIN) return launch_walk_plain(L, s);
@@ -900,6 +1016,8 @@ extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk
     return fail(ctx, MSK_ERR_INVALID_ARG, "walk indices must fit in 32 bits");
   if (o.accum != 0 && o.accum != 1) return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64) or 1 (FP32)");
   for (int32_t i = 0; i < n_meshes; ++i) {
+    if (o.collect_stats && bases[i] && bases[i]->knn_mesh)
+      return fail(ctx, MSK_ERR_INVALID_ARG, "traversal statistics are not collected with the point basis");
     msk_status st = check_problem(ctx, meshes[i], rows[i], bases[i], walks, eps[i], inset_h[i], side);
     if (st != MSK_OK) return fail(ctx, st, "mesh " + std::to_string(i) + ": " + ctx->err);
   }
@@ -1141,6 +1259,7 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   if (r->n * 2 * pairs >= ((int64_t)1 << 40) || 2 * pairs > ((int64_t)1 << 31))
     return fail(ctx, MSK_ERR_INVALID_ARG, "too many walks");
   if (b->K > 8192) return fail(ctx, MSK_ERR_INVALID_ARG, "the PSD estimator takes K <= 8192 basis functions");
+  if (b->knn_mesh) return fail(ctx, MSK_ERR_INVALID_ARG, "the PSD estimator takes a per-vertex table basis");
   msk_psd_opts po;
   msk_psd_opts_default(&po);
   if (opts) po = *opts;

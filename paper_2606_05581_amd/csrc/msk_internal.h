@@ -53,6 +53,23 @@ enum RowMode : int32_t { kRowsPoint = 0, kRowsHatRing = 1 };
 enum WalkStatus : int32_t { kHit = 0, kEscaped = 1, kCapped = 2 };
 
 // Everything a walk needs about one mesh (device pointers).
+// Point basis (point-based k-NN interpolator): the k nearest sample points
+// of a query, found on a uniform grid, with bilateral weights. k = 0: the
+// basis is the per-vertex table instead.
+constexpr int kMaxKnn = 16;
+struct KnnDev {
+  const float4* pts;          // scene-frame positions (w unused)
+  const float4* nrm;          // unit normals (w unused)
+  const int32_t* cell_start;  // n_cells + 1 offsets into cell_pts
+  const int32_t* cell_pts;    // point indices, by cell
+  float lo[3];                // grid origin (scene frame)
+  float cell;                 // cell edge
+  int32_t dim[3];
+  int32_t k;
+  double inv2s2;              // 1 / (2 sigma^2)
+  double inv_tau;             // 1 / tau_n
+};
+
 struct MeshDev {
   const Node4* nodes;
   const TriRec* tris;
@@ -90,6 +107,7 @@ struct MeshDev {
   const int32_t* b_col;
   const float* b_val;
   int64_t K;
+  KnnDev knn;                  // point basis (knn.k > 0) instead of the table
   // accumulators (original row order)
   double* acc1;                // point rows: sum b(t); hat rows: sum c
   double* acc2;                // point rows: sum b(t)^2; hat rows: sum c^2
@@ -126,6 +144,7 @@ struct WalkLaunch {
   int32_t n_top;
   unsigned long long* stats;   // optional: [nodes visited, triangles tested, FP32 operations]
   int32_t accum_f32;           // persistent form: FP32 partial sums in the wavefront row tables
+  int32_t knn;                 // some mesh uses the point basis: launch the k-NN instantiations
 };
 
 }  // namespace msk
@@ -144,6 +163,8 @@ hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_tangent_ball(const MeshDev& M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius,
                                hipStream_t s);
 hipError_t launch_discard(const MeshDev& M, int64_t n_rows, int32_t* discarded, hipStream_t s);
+hipError_t launch_knn_eval(const KnnDev& G, const double* c, const float* Q, const float* Nq, int64_t n, int32_t* idx,
+                           float* w, hipStream_t s);
 hipError_t launch_closest_points(const Node4* nodes, const TriRec* tris, float radius, const double* c, const float* Q,
                                  int64_t nq, int32_t* tri, float* d2, float* bary, hipStream_t s);
 hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walks, const double* w, double* S,

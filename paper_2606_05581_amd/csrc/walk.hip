@@ -550,13 +550,124 @@ __device__ __forceinline__ void merge_rows(const MeshDev& M, const int32_t (&vtx
   }
 }
 
+// ---- point basis (point-based k-NN interpolator)
+// The k nearest sample points of q, as the k smallest (squared FP32 distance,
+// index) pairs, searched ring by ring of grid cells around q's cell: after
+// ring R every unvisited point lies outside the block of (2R + 1)^3 cells, so
+// the search ends once the k-th distance is below the squared distance from q
+// to that block's boundary (with a margin for rounding) or the block covers
+// the grid. Weights exp(-d^2 / (2 sigma^2)) exp(-(1 - n_q . n_j) / tau),
+// normalised (equal shares if all underflow). Returns the neighbour count.
+__device__ __noinline__ int knn_eval(const KnnDev& G, float qx, float qy, float qz, double nqx, double nqy,
+                                     double nqz, int32_t idx[kMaxKnn], double w[kMaxKnn]) {
+#pragma clang fp contract(off)
+  const int k = G.k;
+  float bd[kMaxKnn];
+  int m = 0;
+  const float q[3] = {qx, qy, qz};
+  int c[3];
+  for (int a = 0; a < 3; ++a) {
+    int ci = (int)floorf((q[a] - G.lo[a]) / G.cell);
+    c[a] = min(max(ci, 0), G.dim[a] - 1);
+  }
+  for (int R = 0;; ++R) {
+    for (int dz = -R; dz <= R; ++dz) {
+      const int z = c[2] + dz;
+      if (z < 0 || z >= G.dim[2]) continue;
+      for (int dy = -R; dy <= R; ++dy) {
+        const int y = c[1] + dy;
+        if (y < 0 || y >= G.dim[1]) continue;
+        const bool face = (dz == -R || dz == R || dy == -R || dy == R);
+        for (int dx = -R; dx <= R; dx += (face ? 1 : 2 * R)) {
+          const int x = c[0] + dx;
+          if (x >= 0 && x < G.dim[0]) {
+            const int64_t cid = ((int64_t)z * G.dim[1] + y) * G.dim[0] + x;
+            for (int32_t e = G.cell_start[cid]; e < G.cell_start[cid + 1]; ++e) {
+              const int32_t j = G.cell_pts[e];
+              const float4 pj = G.pts[j];
+              const float ex = qx - pj.x, ey = qy - pj.y, ez = qz - pj.z;
+              float d2 = ex * ex;
+              d2 = d2 + ey * ey;
+              d2 = d2 + ez * ez;
+              if (m == k && !(d2 < bd[k - 1] || (d2 == bd[k - 1] && j < idx[k - 1]))) continue;
+              int pos = m < k ? m++ : k - 1;
+              while (pos > 0 && (d2 < bd[pos - 1] || (d2 == bd[pos - 1] && j < idx[pos - 1]))) {
+                bd[pos] = bd[pos - 1];
+                idx[pos] = idx[pos - 1];
+                --pos;
+              }
+              bd[pos] = d2;
+              idx[pos] = j;
+            }
+          }
+          if (R == 0) break;
+        }
+      }
+    }
+    bool covers = true;
+    float gap = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+      covers = covers && c[a] - R <= 0 && c[a] + R >= G.dim[a] - 1;
+      const float blo = G.lo[a] + (float)(c[a] - R) * G.cell, bhi = G.lo[a] + (float)(c[a] + R + 1) * G.cell;
+      gap = fminf(gap, fminf(q[a] - blo, bhi - q[a]));
+    }
+    if (covers) break;
+    if (m == k && gap > 0.0f && bd[k - 1] < (gap * gap) * (1.0f - 0x1p-16f)) break;
+  }
+  double sum = 0.0;
+  for (int a = 0; a < m; ++a) {
+    const float4 nj = G.nrm[idx[a]];
+    w[a] = exp(-(double)bd[a] * G.inv2s2) * exp(-(1.0 - (nqx * nj.x + nqy * nj.y + nqz * nj.z)) * G.inv_tau);
+    sum += w[a];
+  }
+  for (int a = 0; a < m; ++a) w[a] = sum > 0.0 ? w[a] / sum : 1.0 / m;
+  return m;
+}
+
+// Hit point and unit face normal of a walk's nearest triangle (FP64 from the
+// FP32 vertices and barycentrics), then the point basis there. Not inlined:
+// the walk kernels keep their registers for the walk itself.
+__device__ __noinline__ int knn_at_hit(const MeshDev& M, const Nearest& hit, int32_t idx[kMaxKnn],
+                                       double w[kMaxKnn]) {
+  double t[3], n[3];
+  const TriRec T = M.tris[hit.slot];
+  float b1, b2;
+  nearest_bary(hit, b1, b2);
+  const double l1 = b1, l2 = b2, l0 = (1.0 - l1) - l2;
+  const double a[3] = {T.a.x, T.a.y, T.a.z}, b[3] = {T.b.x, T.b.y, T.b.z}, c[3] = {T.c.x, T.c.y, T.c.z};
+  double e1[3], e2[3];
+  for (int k = 0; k < 3; ++k) {
+    t[k] = l0 * a[k] + l1 * b[k] + l2 * c[k];
+    e1[k] = b[k] - a[k];
+    e2[k] = c[k] - a[k];
+  }
+  n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  if (nl > 0.0)
+    for (int k = 0; k < 3; ++k) n[k] /= nl;
+  return knn_eval(M.knn, (float)t[0], (float)t[1], (float)t[2], n[0], n[1], n[2], idx, w);
+}
+
 // Contribution of a finished walk to its row, emitted once per column:
 // point rows emit b(t) (the start is fixed per row; the finalisation folds
 // in b(s)), hat rows emit c = b(s) - b(t). Escaped walks have b(t) = 0.
-template <typename Emit>
+template <bool kKnn, typename Emit>
 __device__ void walk_contrib(const WalkLaunch& L, const MeshDev& M, const LaneWalk& w, bool has_t, const Nearest& hit,
                              Emit emit) {
   if (M.ball_r) return;  // PSD walks: the rank-one updates are formed from the walk log
+  if constexpr (kKnn) {  // point basis: b(t) from the hit point's k nearest samples (point rows)
+    if (M.knn.k > 0) {
+      if (has_t) {
+        int32_t idx[kMaxKnn];
+        double wk[kMaxKnn];
+        const int m = knn_at_hit(M, hit, idx, wk);
+        for (int a = 0; a < m; ++a) emit(idx[a], wk[a]);
+      }
+      return;
+    }
+  }
   int32_t tv[3] = {-1, -1, -1};
   double tw[3] = {0.0, 0.0, 0.0};
   if (has_t) {
@@ -606,12 +717,13 @@ __device__ __forceinline__ bool walk_has_t(const MeshDev& M, int32_t status, con
 }
 
 // Scatter a finished walk straight into its row with FP64 device atomics.
+template <bool kKnn = false>
 __device__ void walk_finish_global(const WalkLaunch& L, const MeshDev& M, const LaneWalk& w, int32_t status,
                                    const Nearest& hit) {
   const bool has_t = walk_has_t(M, status, hit);
   double* a1 = M.acc1 + (int64_t)w.row * M.K;
   double* a2 = M.acc2 + (int64_t)w.row * M.K;
-  walk_contrib(L, M, w, has_t, hit, [&](int32_t j, double v) {
+  walk_contrib<kKnn>(L, M, w, has_t, hit, [&](int32_t j, double v) {
     atomicAdd(a1 + j, v);
     atomicAdd(a2 + j, v * v);
   });
@@ -667,13 +779,13 @@ __device__ __forceinline__ void table_add(WaveTables<AccT>& T, int wi, int t, in
   atomicAdd(g2 + j, v * v);
 }
 
-template <typename AccT>
+template <typename AccT, bool kKnn = false>
 __device__ void walk_finish_table(const WalkLaunch& L, const MeshDev& M, const LaneWalk& w, int32_t status,
                                   const Nearest& hit, WaveTables<AccT>& T, int wi) {
   const bool has_t = walk_has_t(M, status, hit);
   double* a1 = M.acc1 + (int64_t)w.row * M.K;
   double* a2 = M.acc2 + (int64_t)w.row * M.K;
-  walk_contrib(L, M, w, has_t, hit, [&](int32_t j, double v) { table_add(T, wi, w.tab, j, v, a1, a2); });
+  walk_contrib<kKnn>(L, M, w, has_t, hit, [&](int32_t j, double v) { table_add(T, wi, w.tab, j, v, a1, a2); });
   atomicAdd(&T.cnt[wi][w.tab][0], (unsigned long long)w.queries);
   if (status == kEscaped) atomicAdd(&T.cnt[wi][w.tab][1], 1ull);
   if (status == kCapped) atomicAdd(&T.cnt[wi][w.tab][2], 1ull);
@@ -802,7 +914,7 @@ __device__ __forceinline__ void decode_walk(const WalkLaunch& L, uint64_t g, Lan
 // ------------------------------------------------------------- kernels
 
 // Plain form: one thread per walk, run to completion.
-template <bool kStats>
+template <bool kStats, bool kKnn = false>
 __global__ void __launch_bounds__(256) walk_plain_kernel(WalkLaunch L) {
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (uint64_t)L.n_slots * (uint64_t)L.walks_per_slot) return;
@@ -817,7 +929,7 @@ __global__ void __launch_bounds__(256) walk_plain_kernel(WalkLaunch L) {
   do {
     st = walk_step<kStats>(L, M, nullptr, 0, w, hit);
   } while (st < 0);
-  walk_finish_global(L, M, w, st, hit);
+  walk_finish_global<kKnn>(L, M, w, st, hit);
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -861,7 +973,7 @@ __device__ unsigned long long g_phase_cycles[16];
 // whose query is answered wait until enough of them do (L.regen_min), then
 // finish their step, start the next one or take a new walk together. The
 // walks, their queries and their results are those of the other forms.
-template <bool kStats, typename AccT>
+template <bool kStats, typename AccT, bool kKnn = false>
 __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kernel(WalkLaunch L) {
   __shared__ Node4 top[kLdsTop > 0 ? kLdsTop : 1];
   __shared__ WaveTables<AccT> T;
@@ -963,9 +1075,9 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
       if (mode == 3) {
         const MeshDev& M = L.meshes[w.mesh];
         if (w.tab >= 0)
-          walk_finish_table(L, M, w, fin_status, hit, T, wi);
+          walk_finish_table<AccT, kKnn>(L, M, w, fin_status, hit, T, wi);
         else
-          walk_finish_global(L, M, w, fin_status, hit);
+          walk_finish_global<kKnn>(L, M, w, fin_status, hit);
         fin = true;
         fin_tab = w.tab;
         w.active = 0;
@@ -1035,9 +1147,9 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
               fresh = w.tab >= 0;
             } else {  // left the bounding sphere at once and escaped
               if (w.tab >= 0)
-                walk_finish_table(L, M, w, s0, hit, T, wi);
+                walk_finish_table<AccT, kKnn>(L, M, w, s0, hit, T, wi);
               else
-                walk_finish_global(L, M, w, s0, hit);
+                walk_finish_global<kKnn>(L, M, w, s0, hit);
               w.active = 0;
               w.tab = -1;
             }
@@ -1299,6 +1411,28 @@ __global__ void discard_kernel(MeshDev M, int64_t n_rows, int32_t* discarded) {
   atomicAdd(M.row_queries + i, 1ull);
 }
 
+__global__ void knn_eval_kernel(KnnDev G, double cx, double cy, double cz, const float* __restrict__ Q,
+                                const float* __restrict__ Nq, int64_t n, int32_t* __restrict__ idx,
+                                float* __restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float qx = (float)((double)Q[3 * i] - cx);
+  const float qy = (float)((double)Q[3 * i + 1] - cy);
+  const float qz = (float)((double)Q[3 * i + 2] - cz);
+  double nx = Nq[3 * i], ny = Nq[3 * i + 1], nz = Nq[3 * i + 2];
+  const double nl = sqrt(nx * nx + ny * ny + nz * nz);
+  if (nl > 0.0) {
+    nx /= nl; ny /= nl; nz /= nl;
+  }
+  int32_t id[kMaxKnn];
+  double wk[kMaxKnn];
+  const int m = knn_eval(G, qx, qy, qz, nx, ny, nz, id, wk);
+  for (int a = 0; a < G.k; ++a) {
+    idx[i * G.k + a] = a < m ? id[a] : -1;
+    w[i * G.k + a] = a < m ? (float)wk[a] : 0.0f;
+  }
+}
+
 __global__ void closest_points_kernel(const Node4* __restrict__ nodes, const TriRec* __restrict__ tris, float radius,
                                       double cx, double cy, double cz, const float* __restrict__ Q, int64_t nq,
                                       int32_t* tri, float* d2, float* bary) {
@@ -1343,7 +1477,7 @@ __global__ void finalize_point_fix_kernel(MeshDev M, int64_t n_rows, const int64
   const double ww[3] = {(double)M.bary[3 * i], (double)M.bary[3 * i + 1], (double)M.bary[3 * i + 2]};
   const double Wi = (double)walks[i];
   const double scale = w[i] / M.inset_d;
-  merge_rows<3>(M, vv, ww, [&](int32_t j, double bs) {
+  auto fix = [&](int32_t j, double bs) {
     const int64_t idx = i * M.K + j;
     const double t1 = M.acc1[idx], t2 = M.acc2[idx];
     const double s1 = Wi * bs - t1;
@@ -1352,7 +1486,18 @@ __global__ void finalize_point_fix_kernel(MeshDev M, int64_t n_rows, const int64
     const double var = fmax(0.0, s2 / Wi - mean * mean) * (Wi / (Wi - 1.0));
     S[idx] = scale * mean;
     se[idx] = scale * sqrt(var / Wi);
-  });
+  };
+  if (M.knn.k > 0) {
+    double nx = M.n[3 * i], ny = M.n[3 * i + 1], nz = M.n[3 * i + 2];
+    const double nl = sqrt(nx * nx + ny * ny + nz * nz);
+    nx /= nl; ny /= nl; nz /= nl;
+    int32_t idx[kMaxKnn];
+    double wk[kMaxKnn];
+    const int m = knn_eval(M.knn, M.p[3 * i], M.p[3 * i + 1], M.p[3 * i + 2], nx, ny, nz, idx, wk);
+    for (int a = 0; a < m; ++a) fix(idx[a], wk[a]);
+  } else {
+    merge_rows<3>(M, vv, ww, fix);
+  }
 }
 
 }  // namespace msk
@@ -1368,7 +1513,10 @@ hipError_t launch_walk_plain(const WalkLaunch& L, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = (n + 255) / 256;
   if (nb > INT32_MAX) return hipErrorInvalidValue;
-  if (L.stats)
+  if (L.knn && L.stats) return hipErrorInvalidValue;  // the point basis has no counting instantiation
+  if (L.knn)
+    hipLaunchKernelGGL((walk_plain_kernel<false, true>), dim3((unsigned)nb), dim3(256), 0, s, L);
+  else if (L.stats)
     hipLaunchKernelGGL(walk_plain_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, L);
   else
     hipLaunchKernelGGL(walk_plain_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, L);
@@ -1376,7 +1524,13 @@ hipError_t launch_walk_plain(const WalkLaunch& L, hipStream_t s) {
 }
 
 hipError_t launch_walk_persistent(const WalkLaunch& L, int grid, hipStream_t s) {
-  if (L.accum_f32) {
+  if (L.knn && L.stats) return hipErrorInvalidValue;  // the point basis has no counting instantiation
+  if (L.knn) {  // point basis: instantiations carrying the k-NN evaluation
+    if (L.accum_f32)
+      hipLaunchKernelGGL((walk_stream_kernel<false, float, true>), dim3(grid), dim3(256), 0, s, L);
+    else
+      hipLaunchKernelGGL((walk_stream_kernel<false, double, true>), dim3(grid), dim3(256), 0, s, L);
+  } else if (L.accum_f32) {
     if (L.stats)
       hipLaunchKernelGGL((walk_stream_kernel<true, float>), dim3(grid), dim3(256), 0, s, L);
     else
@@ -1438,6 +1592,14 @@ hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s) {
 hipError_t launch_discard(const MeshDev& M, int64_t n_rows, int32_t* discarded, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(discard_kernel, dim3(blocks_for(n_rows, 128)), dim3(128), 0, s, M, n_rows, discarded);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn_eval(const KnnDev& G, const double* c, const float* Q, const float* Nq, int64_t n, int32_t* idx,
+                           float* w, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(knn_eval_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, s, G, c[0], c[1], c[2], Q, Nq, n, idx,
+                     w);
   return hipGetLastError();
 }
 

@@ -125,6 +125,10 @@ SIGNATURES = {
     "msk_basis_create": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                           C.POINTER(C.c_void_p)], C.c_int),
     "msk_basis_destroy": ([C.c_void_p], None),
+    "msk_basis_create_knn": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double,
+                              C.c_double, C.POINTER(C.c_void_p)], C.c_int),
+    "msk_basis_eval_knn": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
+                           C.c_int),
     "msk_dtn_opts_default": ([C.POINTER(DtnOpts)], None),
     "msk_estimate_dtn": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_int32,
                           C.POINTER(DtnOpts), C.POINTER(C.c_void_p)], C.c_int),
@@ -254,6 +258,28 @@ class Context:
         h = C.c_void_p()
         self._check(lib().msk_basis_create(self.h, prp, pcl, pvl, n_verts, int(basis.K), C.byref(h)))
         return BasisHandle(self, h, int(basis.K))
+
+    def basis_knn(self, mesh, points, normals, k: int = 8, sigma: float = 0.025, tau_n: float = 0.8) -> "BasisHandle":
+        """Point basis: bilateral k-NN interpolation over the sample points (K = number of points)."""
+        P, pp = _np(points, np.float32)
+        Nn, pn = _np(normals, np.float32)
+        h = C.c_void_p()
+        self._check(lib().msk_basis_create_knn(self.h, mesh.h, pp, pn, int(P.shape[0]), int(k), float(sigma),
+                                               float(tau_n), C.byref(h)))
+        bh = BasisHandle(self, h, int(P.shape[0]))
+        bh.k = int(k)
+        return bh
+
+    def eval_knn(self, basis, Q, Nq):
+        """The point basis at queries (torch tensors on the GPU, n x 3 float32): (indices, weights), n x k."""
+        import torch
+
+        n = int(Q.shape[0])
+        idx = torch.empty((n, basis.k), dtype=torch.int32, device=Q.device)
+        w = torch.empty((n, basis.k), dtype=torch.float32, device=Q.device)
+        self._check(lib().msk_basis_eval_knn(self.h, basis.h, Q.data_ptr(), Nq.data_ptr(), n, idx.data_ptr(),
+                                             w.data_ptr()))
+        return idx, w
 
     # -- estimate
     @staticmethod

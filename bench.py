@@ -187,6 +187,44 @@ def psd_leg(ctx):
     }
 
 
+def knn_leg(ctx, walks=1024):
+    """The point basis (point-based k-NN interpolator) against the per-vertex
+    table on the same walks: sh_sphere_2m's 10,000 point rows, `walks` walks
+    each, interior; one untimed call per basis, then one timed call each."""
+    import torch
+
+    from paper_2606_05581_amd import msk
+    from paper_2606_05581_amd import workloads as W
+
+    t = time.perf_counter()
+    wl = W.load("sh_sphere_2m", cache=False)
+    case = wl.cases[0]
+    mesh = ctx.build_bvh(case.V, case.F)
+    rows = ctx.rows(mesh, case.rows)
+    table = ctx.basis(case.basis, case.V.shape[0])
+    sigma = 1.5 * float(np.sqrt(case.rows.w.sum() / case.rows.n_rows))
+    point = ctx.basis_knn(mesh, case.rows.p, case.rows.n, k=8, sigma=sigma, tau_n=0.8)
+    torch.cuda.synchronize()
+    log(f"[bench] point-basis leg: {case.F.shape[0]} triangles, {case.rows.n_rows} rows x {walks} walks "
+        f"(inputs ready in {time.perf_counter() - t:.1f} s)")
+    out = {"workload": "sh_sphere_2m", "rows": int(case.rows.n_rows), "walks_per_row": walks, "k": 8,
+           "sigma": sigma, "tau_n": 0.8}
+    for name, b in (("table", table), ("point_basis", point)):
+        ctx.estimate_dtn(mesh, rows, b, 64, case.eps, case.h).close()  # untimed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = ctx.estimate_dtn(mesh, rows, b, walks, case.eps, case.h)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        inf = d.info()
+        d.close()
+        out[name] = {"walks_per_s": inf["walks_total"] / el, "walk_kernel_ms": inf["walk_kernel_ms"],
+                     "seconds": el}
+    out["point_over_table"] = out["point_basis"]["walks_per_s"] / out["table"]["walks_per_s"]
+    log(f"[bench] point basis {out['point_basis']['walks_per_s']:.3e} walks/s, table {out['table']['walks_per_s']:.3e}")
+    return out
+
+
 def cpu_baseline(wl, target_s, max_threads=16, max_meshes=8):
     """The oracle (FP64 walks, its own BVH) on a bounded sample of rows."""
     from oracle import oracle as O
@@ -236,6 +274,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-psd", action="store_true", help="skip the PSD estimator (Alg. 2) leg")
     ap.add_argument("--psd-only", action="store_true", help="run only the PSD estimator leg (profiling)")
+    ap.add_argument("--no-knn", action="store_true", help="skip the point-basis (k-NN) leg")
+    ap.add_argument("--knn-only", action="store_true", help="run only the point-basis leg")
     ap.add_argument("--launch", default="", help="fixed launch settings instead of tuning, e.g. chunk=64,regen_min=16")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2606_05581_amd", "tune_cache.jsonl"),
                     help="autotuner results (JSON lines); a stored entry for this workload is reused, else the "
@@ -255,6 +295,9 @@ def main():
 
     if args.psd_only:
         print(json.dumps({"psd": psd_leg(msk.Context(0))}), flush=True)
+        return
+    if args.knn_only:
+        print(json.dumps({"knn": knn_leg(msk.Context(0))}), flush=True)
         return
     t = time.perf_counter()
     wl = W.load(args.workload)
@@ -401,6 +444,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "psd": None if args.no_psd else psd_leg(ctx),
+        "knn": None if args.no_knn else knn_leg(ctx),
     }
     print(json.dumps(line), flush=True)
 

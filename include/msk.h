@@ -185,6 +185,64 @@ msk_status msk_basis_eval_knn(msk_ctx* ctx, const msk_basis* basis, const float*
                               int32_t* idx, float* w);
 void msk_basis_destroy(msk_basis* basis);
 
+/* Mesh-based Galerkin basis (Sec. 5.1, mesh-based Galerkin basis): the K
+ * lowest eigenmodes of the mesh's cotangent Laplacian, computed on the GPU.
+ * Stiffness L: each triangle adds, for each corner of angle theta opposite
+ * the edge (i, j), -cot(theta)/2 to L_ij and L_ji and +cot(theta)/2 to L_ii
+ * and L_jj; mass M = diag(m), m_i = a third of the area of the triangles at
+ * i. A triangle is left out of both when twice its area is at most 1e-12
+ * times its longest squared edge; vertices of zero mass get basis value 0.
+ * The basis is the K smallest pairs of L phi = lambda M phi with
+ * Phi^T M Phi = I, by Chebyshev-filtered subspace iteration on
+ * A = M^-1/2 L M^-1/2 (FP64 throughout). */
+typedef struct {
+  int32_t block;      /* subspace size, a multiple of 64 in [64, 512]; 0 = K + max(32, K/4)
+                         rounded up to 64                                    */
+  int32_t degree;     /* Chebyshev filter degree per iteration; 0 = adaptive:
+                         the degree that amplifies the K-th Ritz value about
+                         1000 times relative to the damped interval          */
+  int32_t max_iters;  /* outer iterations (0 = 60)                           */
+  int32_t max_degree; /* cap of the adaptive degree (0 = 4000)               */
+  double tol;         /* stop when ||A x - lambda x|| <= tol * b for every wanted
+                         pair (|x| = 1, b = the Gershgorin bound of A); 0 = 1e-12 */
+  uint64_t seed;      /* start block                                        */
+} msk_laplace_opts;
+
+typedef struct {
+  int64_t active_vertices; /* vertices of positive mass                      */
+  int64_t skipped_faces;   /* degenerate faces left out (incl. repeated ids) */
+  int64_t nnz;             /* stored entries of L                            */
+  int64_t spmm_calls;      /* sparse block products                          */
+  int32_t block, degree, iters, converged; /* degree: the last filter's      */
+  int32_t grams, rotates, rank_drops, reserved;
+  double bound;            /* b, the Gershgorin bound of A                   */
+  double filter_lower;     /* lower end of the last damped interval          */
+  double max_residual;     /* max over the K pairs of ||A x - lambda x|| / b  */
+  double setup_ms;         /* host: vertex order, incidence and pattern      */
+  double assemble_ms;      /* device: L, M, A and b                          */
+  double filter_ms;        /* device: the filter's sparse products           */
+  double dense_ms;         /* orthonormalisation and Rayleigh-Ritz           */
+  double total_ms;         /* device work from assembly to the basis table   */
+} msk_laplace_info;
+
+void msk_laplace_opts_default(msk_laplace_opts* opts);
+
+/* V: nv x 3 floats, F: nf x 3 vertex indices (host; copied). Writes the K
+ * eigenvalues ascending to evals (host), optionally the eigenvectors to phi
+ * (host, nv x K row-major, FP64; NULL to skip) and the run's figures to
+ * info (NULL to skip), and returns a dense table basis (K columns per
+ * vertex, FP32 values) for msk_estimate_psd in *out, to be freed with
+ * msk_basis_destroy. Errors: INVALID_ARG for non-finite positions,
+ * out-of-range indices, K < 1, K + 16 > 512, nv * K >= 2^31, a block that
+ * is not a multiple of 64 in [64, 512] or smaller than K + 16, or fewer
+ * vertices of positive mass than K; NUMERIC when the operator is zero or not
+ * finite; NOT_CONVERGED when the residual target was not met within
+ * max_iters (*out, evals, phi and info then hold the last iterate and must
+ * still be freed). */
+msk_status msk_basis_create_laplacian(msk_ctx* ctx, const float* V, int64_t nv, const int32_t* F, int64_t nf,
+                                      int32_t K, const msk_laplace_opts* opts, double* evals, double* phi,
+                                      msk_laplace_info* info, msk_basis** out);
+
 /* -------------------------------------------------------------- estimate */
 
 typedef enum { MSK_INTERIOR = 0, MSK_EXTERIOR = 1 } msk_side;

@@ -18,7 +18,12 @@ the textbook piecewise-linear finite-element forms):
 * basis: the K smallest eigenpairs of L phi = lambda M phi, phi normalised
   so that Phi^T M Phi = I (orthonormal in the mass inner product).
 
-Triangles of zero area contribute to neither matrix. Vertices of zero mass
+Triangles of (numerically) zero area contribute to neither matrix: a
+triangle is left out when twice its area, |(b - a) x (c - a)| from its first
+corner, is at most DEGENERATE_REL times its longest squared edge (a relative
+test, so that exactly collinear corners, whose cross product rounds to a tiny
+nonzero value, are left out whichever corner it is taken from). Vertices of
+zero mass
 (unreferenced, or only in zero-area triangles) are not part of the
 eigenproblem; their basis values are zero.
 """
@@ -29,12 +34,24 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
+DEGENERATE_REL = 1e-12
+
+
 def face_area2(V, F):
     """Twice the area of every triangle (|e1 x e2|), FP64."""
     P = np.asarray(V, dtype=np.float64)
     F = np.asarray(F, dtype=np.int64)
     a, b, c = P[F[:, 0]], P[F[:, 1]], P[F[:, 2]]
     return np.linalg.norm(np.cross(b - a, c - a), axis=1)
+
+
+def live_faces(V, F):
+    """Mask of the triangles that enter the matrices (see the module header)."""
+    P = np.asarray(V, dtype=np.float64)
+    F = np.asarray(F, dtype=np.int64)
+    a, b, c = P[F[:, 0]], P[F[:, 1]], P[F[:, 2]]
+    l2 = np.maximum(np.maximum(((b - a) ** 2).sum(1), ((c - b) ** 2).sum(1)), ((a - c) ** 2).sum(1))
+    return face_area2(P, F) > DEGENERATE_REL * l2
 
 
 def cotan_laplacian(V, F):
@@ -44,7 +61,7 @@ def cotan_laplacian(V, F):
     F = np.asarray(F, dtype=np.int64)
     nv = P.shape[0]
     area2 = face_area2(P, F)
-    live = area2 > 0.0
+    live = live_faces(P, F)
     Fl, A2 = F[live], area2[live]
     rows, cols, vals = [], [], []
     for c in range(3):  # corner c, opposite edge (i, j)
@@ -75,7 +92,7 @@ def dirichlet_energy(V, F, u):
     a, b, c = P[F[:, 0]], P[F[:, 1]], P[F[:, 2]]
     nrm = np.cross(b - a, c - a)
     A2 = np.linalg.norm(nrm, axis=1)
-    live = A2 > 0
+    live = live_faces(P, F)
     n = nrm[live] / A2[live, None]
     e0, e1, e2 = (c - b)[live], (a - c)[live], (b - a)[live]
     Fl = F[live]

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1707,4 +1708,263 @@ extern "C" msk_status msk_autotune(msk_ctx* ctx, int32_t n, msk_mesh* const* mes
     }
   }
   return MSK_OK;
+}
+
+// ------------------------------------------------------- mesh Laplacian basis
+
+extern "C" void msk_laplace_opts_default(msk_laplace_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->degree = 0;
+  o->max_iters = 60;
+  o->max_degree = 4000;
+  o->tol = 1e-12;
+}
+
+namespace {
+
+// 30-bit Morton code of a point in the box [lo, lo + ext]
+uint32_t morton30(const float* p, const double lo[3], const double ext[3]) {
+  uint32_t code = 0;
+  uint32_t q[3];
+  for (int a = 0; a < 3; ++a) {
+    double t = ext[a] > 0 ? (p[a] - lo[a]) / ext[a] : 0.0;
+    t = std::min(std::max(t, 0.0), 1.0);
+    q[a] = std::min<uint32_t>(1023u, (uint32_t)(t * 1024.0));
+  }
+  for (int bit = 9; bit >= 0; --bit)
+    for (int a = 0; a < 3; ++a) code = (code << 1) | ((q[a] >> bit) & 1u);
+  return code;
+}
+
+}  // namespace
+
+extern "C" msk_status msk_basis_create_laplacian(msk_ctx* ctx, const float* V, int64_t nv, const int32_t* F,
+                                                 int64_t nf, int32_t K, const msk_laplace_opts* opts, double* evals,
+                                                 double* phi, msk_laplace_info* info, msk_basis** out) {
+  if (!ctx || !out) return MSK_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!V || !F || !evals) return fail(ctx, MSK_ERR_INVALID_ARG, "null V, F or evals");
+  if (nv < 3 || nv >= INT32_MAX || nf < 1 || nf >= INT32_MAX / 3)
+    return fail(ctx, MSK_ERR_INVALID_ARG, "need 3 <= nv < 2^31 and 1 <= nf < 2^31 / 3");
+  msk_laplace_opts o;
+  msk_laplace_opts_default(&o);
+  if (opts) {
+    o = *opts;
+    if (o.max_iters == 0) o.max_iters = 60;
+    if (o.max_degree == 0) o.max_degree = 4000;
+    if (o.tol == 0) o.tol = 1e-12;
+  }
+  if (K < 1 || K + 16 > 512) return fail(ctx, MSK_ERR_INVALID_ARG, "K must be in 1..496");
+  if ((int64_t)nv * K >= INT32_MAX) return fail(ctx, MSK_ERR_INVALID_ARG, "nv * K must be below 2^31");
+  int64_t m = o.block;
+  if (m == 0) m = ((K + std::max(32, K / 4)) + 63) / 64 * 64;
+  if (m > 512) m = 512;
+  if (m % 64 != 0 || m < 64 || m < K + 16)
+    return fail(ctx, MSK_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 512] and at least K + 16");
+  if (o.degree < 0 || o.degree > 100000 || o.max_degree < 8 || o.max_degree > 100000 || o.max_iters < 0 ||
+      !(o.tol > 0) || !std::isfinite(o.tol))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "need 0 <= degree, 8 <= max_degree <= 1e5, max_iters >= 0, tol > 0");
+  for (int64_t i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(V[i])) return fail(ctx, MSK_ERR_INVALID_ARG, "non-finite vertex coordinate");
+  for (int64_t i = 0; i < 3 * nf; ++i)
+    if (F[i] < 0 || F[i] >= nv) return fail(ctx, MSK_ERR_INVALID_ARG, "face index out of range");
+
+  // ---- host set-up: vertex order (Morton code of the position, then index),
+  // faces in internal ids, vertex -> face incidence, sparsity pattern of L
+  const auto t0 = std::chrono::steady_clock::now();
+  double lo[3], hi[3], ext[3];
+  for (int a = 0; a < 3; ++a) lo[a] = hi[a] = V[a];
+  for (int64_t i = 0; i < nv; ++i)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], (double)V[3 * i + a]);
+      hi[a] = std::max(hi[a], (double)V[3 * i + a]);
+    }
+  for (int a = 0; a < 3; ++a) ext[a] = hi[a] - lo[a];
+  std::vector<uint64_t> key(nv);
+  for (int64_t i = 0; i < nv; ++i) key[i] = ((uint64_t)morton30(V + 3 * i, lo, ext) << 32) | (uint64_t)i;
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> orig(nv), inv(nv);
+  for (int64_t i = 0; i < nv; ++i) {
+    orig[i] = (int32_t)(key[i] & 0xffffffffu);
+    inv[orig[i]] = (int32_t)i;
+  }
+  std::vector<float> P(3 * nv);
+  for (int64_t i = 0; i < nv; ++i)
+    for (int a = 0; a < 3; ++a) P[3 * i + a] = V[3 * (int64_t)orig[i] + a];
+  std::vector<int32_t> Fi(3 * nf);
+  std::vector<char> repeated(nf, 0);
+  int64_t n_repeated = 0;
+  for (int64_t t = 0; t < nf; ++t) {
+    for (int c = 0; c < 3; ++c) Fi[3 * t + c] = inv[F[3 * t + c]];
+    if (F[3 * t] == F[3 * t + 1] || F[3 * t + 1] == F[3 * t + 2] || F[3 * t] == F[3 * t + 2]) {
+      repeated[t] = 1;
+      ++n_repeated;
+    }
+  }
+  std::vector<int32_t> vt_ptr(nv + 1, 0);
+  for (int64_t t = 0; t < nf; ++t)
+    if (!repeated[t])
+      for (int c = 0; c < 3; ++c) ++vt_ptr[Fi[3 * t + c] + 1];
+  for (int64_t i = 0; i < nv; ++i) vt_ptr[i + 1] += vt_ptr[i];
+  std::vector<int32_t> vt_tri(std::max<int32_t>(1, vt_ptr[nv]));
+  {
+    std::vector<int32_t> fillp(vt_ptr.begin(), vt_ptr.end() - 1);
+    for (int64_t t = 0; t < nf; ++t)
+      if (!repeated[t])
+        for (int c = 0; c < 3; ++c) vt_tri[fillp[Fi[3 * t + c]]++] = (int32_t)t;
+  }
+  std::vector<int32_t> rowptr(nv + 1, 0), col;
+  col.reserve((size_t)vt_ptr[nv] + nv);
+  {
+    std::vector<int32_t> nb;
+    for (int64_t i = 0; i < nv; ++i) {
+      nb.clear();
+      nb.push_back((int32_t)i);
+      for (int32_t q = vt_ptr[i]; q < vt_ptr[i + 1]; ++q)
+        for (int c = 0; c < 3; ++c) nb.push_back(Fi[3 * (int64_t)vt_tri[q] + c]);
+      std::sort(nb.begin(), nb.end());
+      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+      if ((int64_t)col.size() + (int64_t)nb.size() >= INT32_MAX)
+        return fail(ctx, MSK_ERR_INVALID_ARG, "too many Laplacian entries (2^31)");
+      col.insert(col.end(), nb.begin(), nb.end());
+      rowptr[i + 1] = (int32_t)col.size();
+    }
+  }
+  const int64_t nnz = (int64_t)col.size();
+  const double setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+
+  // ---- device buffers
+  LaplaceJob J;
+  J.stream = ctx->stream;
+  J.n = nv;
+  J.m = m;
+  J.K = K;
+  J.degree = o.degree;
+  J.max_degree = o.max_degree;
+  J.max_iters = o.max_iters;
+  J.tol = o.tol;
+  J.seed = o.seed;
+  const int64_t slices = std::max<int64_t>(1, std::min<int64_t>(256, (nv + 255) / 256));
+  J.n_slots = 4 * slices;
+  float* d_P = nullptr;
+  int32_t *d_F = nullptr, *d_vtp = nullptr, *d_vtt = nullptr, *d_rp = nullptr, *d_col = nullptr, *d_orig = nullptr;
+  double *d_val = nullptr, *d_mass = nullptr, *d_s = nullptr, *d_slots = nullptr, *d_small = nullptr,
+         *d_part = nullptr, *d_phi = nullptr;
+  double* d_blk[3] = {nullptr, nullptr, nullptr};
+  unsigned long long* d_cnt = nullptr;
+  msk_basis* b = new msk_basis();
+  b->ctx = ctx;
+  b->nv = nv;
+  b->K = K;
+  b->max_row_nnz = K;
+  auto free_all = [&]() {
+    dfree(d_P);
+    dfree(d_F);
+    dfree(d_vtp);
+    dfree(d_vtt);
+    dfree(d_rp);
+    dfree(d_col);
+    dfree(d_orig);
+    dfree(d_val);
+    dfree(d_mass);
+    dfree(d_s);
+    dfree(d_slots);
+    dfree(d_small);
+    dfree(d_part);
+    dfree(d_phi);
+    for (double*& p : d_blk) dfree(p);
+    dfree(d_cnt);
+  };
+  hipError_t he = hipSuccess;
+  const int64_t nblk = psd_blocks(m);
+  if ((he = upload(ctx, &d_P, P.data(), P.size())) != hipSuccess ||
+      (he = upload(ctx, &d_F, Fi.data(), Fi.size())) != hipSuccess ||
+      (he = upload(ctx, &d_vtp, vt_ptr.data(), vt_ptr.size())) != hipSuccess ||
+      (he = upload(ctx, &d_vtt, vt_tri.data(), vt_tri.size())) != hipSuccess ||
+      (he = upload(ctx, &d_rp, rowptr.data(), rowptr.size())) != hipSuccess ||
+      (he = upload(ctx, &d_col, col.data(), col.size())) != hipSuccess ||
+      (he = upload(ctx, &d_orig, orig.data(), orig.size())) != hipSuccess ||
+      (he = dalloc(&d_val, (size_t)nnz)) != hipSuccess || (he = dalloc(&d_mass, (size_t)nv)) != hipSuccess ||
+      (he = dalloc(&d_s, (size_t)nv)) != hipSuccess ||
+      (he = dalloc(&d_slots, (size_t)(J.n_slots * nblk * 4096))) != hipSuccess ||
+      (he = dalloc(&d_small, (size_t)std::max<int64_t>(m * m, 4096))) != hipSuccess ||
+      (he = dalloc(&d_part, (size_t)1024 * K)) != hipSuccess ||
+      (phi && (he = dalloc(&d_phi, (size_t)(nv * K))) != hipSuccess) ||
+      (he = dalloc(&d_blk[0], (size_t)(nv * m))) != hipSuccess ||
+      (he = dalloc(&d_blk[1], (size_t)(nv * m))) != hipSuccess ||
+      (he = dalloc(&d_blk[2], (size_t)(nv * m))) != hipSuccess || (he = dalloc(&d_cnt, 2)) != hipSuccess ||
+      (he = dalloc(&b->d_rowptr, (size_t)nv + 1)) != hipSuccess ||
+      (he = dalloc(&b->d_col, (size_t)(nv * K))) != hipSuccess ||
+      (he = dalloc(&b->d_val, (size_t)(nv * K))) != hipSuccess) {
+    free_all();
+    msk_basis_destroy(b);
+    return fail(ctx, he == hipErrorOutOfMemory ? MSK_ERR_OOM : MSK_ERR_DEVICE,
+                std::string("Laplacian basis buffers: ") + hipGetErrorString(he));
+  }
+  J.P = d_P;
+  J.F = d_F;
+  J.vt_ptr = d_vtp;
+  J.vt_tri = d_vtt;
+  J.rowptr = d_rp;
+  J.col = d_col;
+  J.orig = d_orig;
+  J.val = d_val;
+  J.mass = d_mass;
+  J.s = d_s;
+  J.counters = d_cnt;
+  for (int i = 0; i < 3; ++i) J.blk[i] = d_blk[i];
+  J.slots = d_slots;
+  J.small = d_small;
+  J.part = d_part;
+  J.evals = evals;
+  J.phi = d_phi;
+  J.out_rowptr = b->d_rowptr;
+  J.out_col = b->d_col;
+  J.out_val = b->d_val;
+  J.info.skipped_faces = n_repeated;
+  std::string err;
+  const int rc = laplace_basis_device(J, err);
+  if (rc == 0 || rc == 4) {
+    if (phi && (he = hipMemcpyAsync(phi, d_phi, sizeof(double) * nv * K, hipMemcpyDeviceToHost, ctx->stream)) ==
+                   hipSuccess)
+      he = hipStreamSynchronize(ctx->stream);
+    if (he != hipSuccess) {
+      free_all();
+      msk_basis_destroy(b);
+      return fail(ctx, MSK_ERR_DEVICE, std::string("eigenvector copy: ") + hipGetErrorString(he));
+    }
+  }
+  free_all();
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->active_vertices = J.info.active_vertices;
+    info->skipped_faces = J.info.skipped_faces;
+    info->nnz = nnz;
+    info->spmm_calls = J.info.spmm_calls;
+    info->block = (int32_t)m;
+    info->degree = J.info.last_degree;
+    info->iters = J.info.iters;
+    info->converged = J.info.converged;
+    info->grams = J.info.grams;
+    info->rotates = J.info.rotates;
+    info->rank_drops = J.info.rank_drops;
+    info->bound = J.info.bound;
+    info->filter_lower = J.info.filter_lower;
+    info->max_residual = J.info.max_residual;
+    info->setup_ms = setup_ms;
+    info->assemble_ms = J.info.assemble_ms;
+    info->filter_ms = J.info.filter_ms;
+    info->dense_ms = J.info.dense_ms;
+    info->total_ms = J.info.total_ms;
+  }
+  if (rc == 0 || rc == 4) {
+    *out = b;
+    return rc == 0 ? MSK_OK
+                   : fail(ctx, MSK_ERR_NOT_CONVERGED,
+                          "Laplacian basis: residual target not met" + (err.empty() ? std::string() : ": " + err));
+  }
+  msk_basis_destroy(b);
+  const msk_status st = rc == 1 ? MSK_ERR_INVALID_ARG : (rc == 5 ? MSK_ERR_NUMERIC : MSK_ERR_DEVICE);
+  return fail(ctx, st, "Laplacian basis: " + err);
 }

@@ -88,16 +88,18 @@ __global__ void __launch_bounds__(256) psd_gather_kernel(PsdGather G, int64_t q0
 }
 
 // ---- symmetric rank-k product on the matrix cores
-// Partial sums of A^T A, A an m x Kp row-major FP64 matrix (Kp a multiple of
-// 64), for the 64 x 64 blocks (I, J), I <= J, of the Kp x Kp result. A
+// Partial sums of A^T B, A and B m x Kp row-major FP64 matrices (Kp a
+// multiple of 64; B = A for the symmetric rank-k product), for the 64 x 64
+// blocks (I, J), I <= J, of the Kp x Kp result (A^T B symmetric: the lower
+// blocks are taken as the mirror of the upper ones). A
 // workgroup takes a slice of the rows; its work items are (block, 4-row group
 // residue q mod Q), Q = 4 / gcd(nblk, 4), dealt to its 4 wavefronts in turn,
 // so every wavefront gets the same number of items and never two of one
 // block. A wavefront keeps the block
 // in 16 tiles of v_mfma_f64_16x16x4 accumulators (4 doubles per lane each),
-// each step taking 4 rows: operand A = the rows' I-block columns (lane l:
-// row l / 16, column l % 16 of the tile), operand B = their J-block columns,
-// so tile (ti, tj) gains sum_r A[r][I + 16 ti + i] A[r][J + 16 tj + j] with
+// each step taking 4 rows: operand A = the rows' I-block columns of A (lane l:
+// row l / 16, column l % 16 of the tile), operand B = their J-block columns of
+// B, so tile (ti, tj) gains sum_r A[r][I + 16 ti + i] B[r][J + 16 tj + j] with
 // lane l, item v holding (i, j) = (4 v + l / 16, l % 16) (measured on gfx950
 // with one-hot operands). At the end it
 // adds the block into its own partial slot P[slice * 4 + wave][block]
@@ -113,8 +115,9 @@ __device__ __forceinline__ void block_of(int32_t b, int32_t nb, int32_t& I, int3
   J = I + b;
 }
 
-__global__ void __launch_bounds__(256) syrk_blocks_kernel(const double* __restrict__ A, int64_t m, int64_t Kp,
-                                                          int64_t rows_per_slice, double* __restrict__ P) {
+__global__ void __launch_bounds__(256) syrk_blocks_kernel(const double* __restrict__ A, const double* __restrict__ B,
+                                                          int64_t m, int64_t Kp, int64_t rows_per_slice,
+                                                          double* __restrict__ P) {
   const int32_t nb = (int32_t)(Kp / 64), nblk = nb * (nb + 1) / 2;
   const int32_t Q = (nblk % 4 == 0) ? 1 : ((nblk % 2 == 0) ? 2 : 4);
   const int32_t wave = (int32_t)(threadIdx.x >> 6), lane = (int32_t)(threadIdx.x & 63);
@@ -135,11 +138,12 @@ __global__ void __launch_bounds__(256) syrk_blocks_kernel(const double* __restri
       const int64_t r = r0 + kr;
       const bool ok = r < r_end;
       const double* row = A + (ok ? r : r_begin) * Kp;
+      const double* rowb = B + (ok ? r : r_begin) * Kp;
       double a[4], bv[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         a[t] = ok ? row[I * 64 + 16 * t + cl] : 0.0;
-        bv[t] = ok ? row[J * 64 + 16 * t + cl] : 0.0;
+        bv[t] = ok ? rowb[J * 64 + 16 * t + cl] : 0.0;
       }
 #pragma unroll
       for (int ti = 0; ti < 4; ++ti)
@@ -383,7 +387,16 @@ hipError_t launch_psd_syrk(const double* A, int64_t m, int64_t Kp, int64_t slice
   if (m <= 0) return hipSuccess;
   const int64_t rps = ((m + slices - 1) / slices + 3) / 4 * 4;
   const int64_t grid = (m + rps - 1) / rps;
-  hipLaunchKernelGGL(syrk_blocks_kernel, dim3((unsigned)grid), dim3(256), 0, s, A, m, Kp, rps, P);
+  hipLaunchKernelGGL(syrk_blocks_kernel, dim3((unsigned)grid), dim3(256), 0, s, A, A, m, Kp, rps, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_upper(const double* A, const double* B, int64_t m, int64_t Kp, int64_t slices, double* P,
+                             hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int64_t rps = ((m + slices - 1) / slices + 3) / 4 * 4;
+  const int64_t grid = (m + rps - 1) / rps;
+  hipLaunchKernelGGL(syrk_blocks_kernel, dim3((unsigned)grid), dim3(256), 0, s, A, B, m, Kp, rps, P);
   return hipGetLastError();
 }
 

@@ -107,6 +107,20 @@ class PsdLog(C.Structure):
     _fields_ = [("status", C.c_void_p), ("tri", C.c_void_p), ("bary", C.c_void_p), ("queries", C.c_void_p)]
 
 
+class LaplaceOpts(C.Structure):
+    _fields_ = [("block", C.c_int32), ("degree", C.c_int32), ("max_iters", C.c_int32), ("max_degree", C.c_int32),
+                ("tol", C.c_double), ("seed", C.c_uint64)]
+
+
+class LaplaceInfo(C.Structure):
+    _fields_ = [("active_vertices", C.c_int64), ("skipped_faces", C.c_int64), ("nnz", C.c_int64),
+                ("spmm_calls", C.c_int64), ("block", C.c_int32), ("degree", C.c_int32), ("iters", C.c_int32),
+                ("converged", C.c_int32), ("grams", C.c_int32), ("rotates", C.c_int32), ("rank_drops", C.c_int32),
+                ("reserved", C.c_int32), ("bound", C.c_double), ("filter_lower", C.c_double),
+                ("max_residual", C.c_double), ("setup_ms", C.c_double), ("assemble_ms", C.c_double),
+                ("filter_ms", C.c_double), ("dense_ms", C.c_double), ("total_ms", C.c_double)]
+
+
 _lib = None
 
 # symbol name -> (argtypes, restype); the C ABI declared in include/msk.h
@@ -149,6 +163,10 @@ SIGNATURES = {
     "msk_tune_space_default": ([C.POINTER(TuneSpace)], None),
     "msk_mesh_rebuild": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "msk_psd_opts_default": ([C.POINTER(PsdOpts)], None),
+    "msk_laplace_opts_default": ([C.POINTER(LaplaceOpts)], None),
+    "msk_basis_create_laplacian": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
+                                    C.POINTER(LaplaceOpts), C.c_void_p, C.c_void_p, C.POINTER(LaplaceInfo),
+                                    C.POINTER(C.c_void_p)], C.c_int),
     "msk_estimate_psd": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.POINTER(DtnOpts),
                           C.POINTER(PsdOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PsdLog),
                           C.POINTER(PsdInfo)], C.c_int),
@@ -269,6 +287,34 @@ class Context:
         bh = BasisHandle(self, h, int(P.shape[0]))
         bh.k = int(k)
         return bh
+
+    def basis_laplacian(self, V, F, K: int, want_phi: bool = True, **opts):
+        """Mesh-based Galerkin basis: the K lowest modes of the cotangent
+        Laplacian (Sec. 5.1), computed on the GPU. Returns (basis handle,
+        eigenvalues (K,), Phi (nv, K) FP64 or None, info dict). Raises
+        MskError(NOT_CONVERGED) with .result = that tuple when the residual
+        target was not met (the handle must still be closed)."""
+        Vv, pv = _np(V, np.float32)
+        Ff, pf = _np(F, np.int32)
+        o = LaplaceOpts()
+        lib().msk_laplace_opts_default(C.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        nv = int(Vv.shape[0])
+        ev = np.zeros(int(K))
+        phi = np.zeros((nv, int(K))) if want_phi else None
+        inf = LaplaceInfo()
+        h = C.c_void_p()
+        st = lib().msk_basis_create_laplacian(self.h, pv, nv, pf, int(Ff.shape[0]), int(K), C.byref(o),
+                                              ev.ctypes.data, phi.ctypes.data if want_phi else None, C.byref(inf),
+                                              C.byref(h))
+        info = {f: getattr(inf, f) for f, _ in LaplaceInfo._fields_ if f != "reserved"}
+        if st == ERR_NOT_CONVERGED and h.value:
+            err = MskError(st, lib().msk_last_error(self.h).decode())
+            err.result = (BasisHandle(self, h, int(K)), ev, phi, info)
+            raise err
+        self._check(st)
+        return BasisHandle(self, h, int(K)), ev, phi, info
 
     def eval_knn(self, basis, Q, Nq):
         """The point basis at queries (torch tensors on the GPU, n x 3 float32): (indices, weights), n x k."""

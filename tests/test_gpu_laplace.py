@@ -1,0 +1,231 @@
+"""GPU parity of the mesh-based Galerkin basis (Sec. 5.1, mesh-based Galerkin
+basis: the lowest modes of the cotangent Laplacian with lumped mass) against
+the CPU oracle (oracle/laplace.py: assembly from the definition, ARPACK).
+
+Both sides solve L phi = lambda M phi in FP64. Eigenvectors are unique only up
+to sign and rotation inside a cluster of equal eigenvalues, so the bar is:
+  * eigenvalues within 1e-9 b of the oracle's (b = the spectral bound of
+    M^-1/2 L M^-1/2 that the library reports);
+  * per cluster of oracle eigenvalues, the GPU and oracle subspaces agree in
+    the M inner product: sin of the largest principal angle below
+    10 (r_gpu + r_oracle) / gap + 1e-9 (Davis-Kahan; r = residual norms of
+    the two sets measured here on the CPU with the oracle's matrices, gap =
+    the distance to the nearest eigenvalue outside the cluster);
+  * Phi^T M Phi = I within 1e-10 and the residuals below the requested target.
+At the full size of the 2.0M-face sphere the same properties are checked,
+and the 16 lowest eigenvalues against values the oracle computed once
+(tests/golden/laplace_sh_sphere_2m_first16.txt, by make_laplace_golden.py).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import laplace as LP
+from paper_2606_05581_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "laplace_sh_sphere_2m_first16.txt")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2606_05581_amd import msk
+
+    assert torch.cuda.is_available(), "GPU test needs a visible MI355X"
+    c = msk.Context(0)
+    yield c
+    c.close()
+
+
+def _residuals(L, m, Phi, lam):
+    """||A x - lambda x|| per column, A = M^-1/2 L M^-1/2, x = M^1/2 phi / |M^1/2 phi|."""
+    act = m > 0
+    sq = np.sqrt(m[act])
+    X = sq[:, None] * Phi[act]
+    nrm = np.linalg.norm(X, axis=0)
+    R = (L @ Phi)[act] / sq[:, None] - X * lam[None, :]
+    return np.linalg.norm(R, axis=0) / nrm
+
+
+def _compare(V, F, lam_g, Phi_g, info, K, label):
+    Vd = np.asarray(V, dtype=np.float32).astype(np.float64)
+    L, m, _ = LP.cotan_laplacian(Vd, F)
+    n_act = int((m > 0).sum())
+    K_more = min(K + 8, n_act - 1)
+    lam_all, Phi_all, _ = LP.laplacian_basis(Vd, F, K_more)
+    lam_o, Phi_o = lam_all[:K], Phi_all[:, :K]
+    b = info["bound"]
+    r_g = _residuals(L, m, Phi_g, lam_g)
+    r_o = _residuals(L, m, Phi_o, lam_o)
+    G = Phi_g.T @ (m[:, None] * Phi_g)
+    worst_sin, worst_tol = 0.0, 1.0
+    for a, e in LP.eigen_clusters(lam_all, rel_gap=1e-4):
+        if a >= K:
+            break
+        if e > K or (e == K and K_more == K):
+            continue  # the cut at K falls inside this cluster (or cannot be told): no unique subspace
+        outside = np.concatenate([lam_all[:a], lam_all[e:]])
+        gap = np.min(np.abs(outside[:, None] - lam_o[None, a:e])) if outside.size else np.inf
+        # sin of the largest principal angle: |M^1/2 (I - P_o) Phi_g| (P_o the M-orthogonal projector)
+        Pg, Po = Phi_g[:, a:e], Phi_o[:, a:e]
+        E = Pg - Po @ (Po.T @ (m[:, None] * Pg))
+        sin = float(np.linalg.svd(np.sqrt(m)[:, None] * E, compute_uv=False).max())
+        tol = 10 * (r_g[a:e].max() + r_o[a:e].max()) / gap + 1e-9
+        if sin / tol > worst_sin / worst_tol:
+            worst_sin, worst_tol = sin, tol
+        assert sin <= tol, (label, a, e, sin, tol)
+    dl = np.abs(lam_g - lam_o).max()
+    print(f"[laplace parity] {label}: nv={V.shape[0]} K={K} b={b:.3e} iters={info['iters']} "
+          f"spmm={info['spmm_calls']} max|dlambda|={dl:.2e} max r_gpu={r_g.max():.2e} "
+          f"worst sin/tol={worst_sin:.2e}/{worst_tol:.2e} orth={np.abs(G - np.eye(K)).max():.2e} "
+          f"total {info['total_ms']:.1f} ms", flush=True)
+    assert dl <= 1e-9 * b
+    assert np.abs(G - np.eye(K)).max() < 1e-10
+    assert r_g.max() <= 2e-12 * b
+
+
+def _jittered_sphere(level, amp, seed):
+    V, F = W.icosphere_recursive(level)
+    rng = np.random.default_rng(seed)
+    V = V * (1.0 + amp * rng.uniform(-1, 1, size=(V.shape[0], 1))) + 0.5 * amp * rng.normal(size=V.shape)
+    return V.astype(np.float32), F.astype(np.int32)
+
+
+def test_laplace_icosahedron_closed_form(ctx):
+    """12 vertices with a 64-column block: the block is rank deficient and the
+    projected problem is exact after one Rayleigh-Ritz step."""
+    V, F = W.icosahedron()
+    V32 = V.astype(np.float32)
+    bh, lam, Phi, info = ctx.basis_laplacian(V32, F.astype(np.int32), 11, block=64)
+    bh.close()
+    Vd = V32.astype(np.float64)
+    a = np.linalg.norm(Vd[F[0, 0]] - Vd[F[0, 1]])
+    s5 = math.sqrt(5)
+    want = 4 * np.array([0] + [5 - s5] * 3 + [6] * 5 + [5 + s5] * 2) / (5 * a * a)
+    print(f"[laplace icosahedron] {lam} rank drops {info['rank_drops']}", flush=True)
+    # the vertices are FP32, so the closed form holds to FP32 rounding of the geometry
+    assert np.allclose(lam, want, rtol=1e-6, atol=1e-9)
+    assert info["converged"] == 1 and info["active_vertices"] == 12
+    _compare(V32, F, lam, Phi, info, 11, "icosahedron")
+
+
+@pytest.mark.parametrize("case", ["jittered642", "icosphere2562"])
+def test_laplace_parity(ctx, case):
+    if case == "jittered642":
+        V, F, K = *_jittered_sphere(3, 0.15, 1), 40
+    else:
+        V, F = W.icosphere_recursive(4)
+        V, F, K = V.astype(np.float32), F.astype(np.int32), 64  # l <= 7: the cut falls between clusters
+    bh, lam, Phi, info = ctx.basis_laplacian(V, F, K, seed=3)
+    bh.close()
+    assert info["converged"] == 1
+    _compare(V, F, lam, Phi, info, K, case)
+
+
+def test_laplace_components_and_degenerate_faces(ctx):
+    """Three disjoint jittered spheres (three zero modes), plus a triangle with
+    a repeated vertex, a collinear one and an unreferenced vertex."""
+    parts = [_jittered_sphere(2, 0.1, s) for s in (4, 5, 6)]
+    parts = [(V + np.float32(3.0 * i), F) for i, (V, F) in enumerate(parts)]
+    V, F = W.concat_meshes(parts)
+    V = V.astype(np.float32)
+    nv0 = V.shape[0]
+    # exactly collinear in FP32: (9, 9, 9), (10, 9, 9), (9.5, 9, 9); then an unreferenced vertex
+    extra = [[9.0, 9.0, 9.0], [10.0, 9.0, 9.0], [9.5, 9.0, 9.0], [12.0, 12.0, 12.0]]
+    V2 = np.concatenate([V, extra]).astype(np.float32)
+    F2 = np.concatenate([F, [[0, 0, 5], [nv0, nv0 + 1, nv0 + 2]]]).astype(np.int32)
+    K = 24
+    bh, lam, Phi, info = ctx.basis_laplacian(V2, F2, K, seed=9)
+    bh.close()
+    assert info["skipped_faces"] == 2 and info["active_vertices"] == nv0
+    assert np.all(Phi[nv0:] == 0.0)
+    assert np.abs(lam[:3]).max() < 1e-9 * info["bound"] and lam[3] > 0.1
+    _compare(V2, F2, lam, Phi, info, K, "3 spheres + degenerate")
+
+
+def test_laplace_argument_errors(ctx):
+    from paper_2606_05581_amd import msk
+
+    V, F = W.icosphere_recursive(2)
+    V, F = V.astype(np.float32), F.astype(np.int32)
+    for kw in (dict(K=0), dict(K=600), dict(K=8, block=96), dict(K=60, block=64)):
+        K = kw.pop("K")
+        with pytest.raises(msk.MskError) as e:
+            ctx.basis_laplacian(V, F, K, **kw)
+        assert e.value.status == msk.ERR_INVALID_ARG
+    Fb = F.copy()
+    Fb[3, 1] = V.shape[0]
+    with pytest.raises(msk.MskError):
+        ctx.basis_laplacian(V, Fb, 8)
+    Vb = V.copy()
+    Vb[5, 2] = np.nan
+    with pytest.raises(msk.MskError):
+        ctx.basis_laplacian(Vb, F, 8)
+    with pytest.raises(msk.MskError) as e:  # one outer iteration cannot meet the target
+        ctx.basis_laplacian(V, F, 30, max_iters=1, degree=8)
+    assert e.value.status == msk.ERR_NOT_CONVERGED
+    bh, lam, _, info = e.value.result
+    assert info["converged"] == 0 and np.all(np.isfinite(lam))
+    bh.close()
+
+
+def test_laplace_basis_feeds_the_psd_estimator(ctx):
+    """The table basis holds the modes in the caller's vertex order: on the unit
+    sphere the degree <= 2 modes span the same space as the degree <= 2
+    spherical harmonics, so with the same rows and seed (the same walks) the
+    PSD estimate's eigenvalues match those of the harmonic basis."""
+    V, F = W.icosphere_recursive(4)
+    V = (V / np.linalg.norm(V, axis=1, keepdims=True)).astype(np.float32)
+    F = F.astype(np.int32)
+    rows = W.point_rows(V.astype(np.float64), F, 1500, np.random.default_rng(21))
+    mesh = ctx.build_bvh(V, F)
+    rh = ctx.rows(mesh, rows)
+    bl, lam, Phi, info = ctx.basis_laplacian(V, F, 9, seed=1)
+    Vd = V.astype(np.float64)
+    x, y, z = Vd[:, 0], Vd[:, 1], Vd[:, 2]
+    sh = np.stack([np.ones_like(x), y, z, x, x * y, y * z, 3 * z * z - 1, x * z, x * x - y * y], 1)
+    _, m = LP.cotan_laplacian(Vd, F)[:2]
+    Qm, _ = np.linalg.qr(np.sqrt(m)[:, None] * sh)
+    sh_on = Qm / np.sqrt(m)[:, None]  # M-orthonormal harmonics of degree <= 2
+    bs = ctx.basis(W.dense_basis(sh_on.astype(np.float32)), V.shape[0])
+    g_l = ctx.estimate_psd(mesh, rh, bl, 64, 1e-4, seed=3)
+    g_s = ctx.estimate_psd(mesh, rh, bs, 64, 1e-4, seed=3)
+    e_l = np.linalg.eigvalsh(g_l["S"])
+    e_s = np.linalg.eigvalsh(g_s["S"])
+    print(f"[laplace -> psd] eig(S) Laplacian basis {e_l.round(3)}, harmonic basis {e_s.round(3)}", flush=True)
+    assert np.abs(e_l - e_s).max() < 0.02 * e_s.max()
+    assert lam[0] == pytest.approx(0.0, abs=1e-9 * info["bound"])
+
+
+def test_laplace_full_size_sh_sphere_2m(ctx):
+    """The 2.0M-face SH-displaced sphere with K = 160 (128 modes + 32, the
+    paper's sizing): M-orthonormality, residuals measured on the CPU with the
+    oracle's matrices, ascending eigenvalues, and the 16 lowest against the
+    oracle's values."""
+    rng = np.random.default_rng(1002)
+    V, F = W.sh_displaced_sphere(316, 16, 0.05, rng)
+    V = W.normalise_unit_ball(V).astype(np.float32)
+    F = F.astype(np.int32)
+    K = 160
+    print(f"[laplace full] nv={V.shape[0]} nf={F.shape[0]} K={K}", flush=True)
+    bh, lam, Phi, info = ctx.basis_laplacian(V, F, K, seed=2)
+    bh.close()
+    print(f"[laplace full] iters={info['iters']} degree={info['degree']} spmm={info['spmm_calls']} "
+          f"b={info['bound']:.3e} filter {info['filter_ms']:.0f} ms dense {info['dense_ms']:.0f} ms "
+          f"total {info['total_ms']:.0f} ms setup {info['setup_ms']:.0f} ms", flush=True)
+    assert info["converged"] == 1
+    Vd = V.astype(np.float64)
+    L, m, _ = LP.cotan_laplacian(Vd, F)
+    r = _residuals(L, m, Phi, lam)
+    G = Phi.T @ (m[:, None] * Phi)
+    print(f"[laplace full] max residual {r.max():.2e} (b {info['bound']:.2e}), orth {np.abs(G - np.eye(K)).max():.2e}",
+          flush=True)
+    assert r.max() <= 2e-12 * info["bound"]
+    assert np.abs(G - np.eye(K)).max() < 1e-10
+    assert np.all(np.diff(lam) >= -1e-9 * info["bound"])
+    want = np.loadtxt(GOLDEN)
+    assert np.abs(lam[:16] - want).max() <= 1e-9 * info["bound"]

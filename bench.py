@@ -187,6 +187,78 @@ def psd_leg(ctx):
     }
 
 
+def _cpu_threads():
+    """Threads the oracle's scipy/BLAS calls may use (the sparse LU of the
+    shift-invert solves runs on one)."""
+    try:
+        from threadpoolctl import threadpool_info
+
+        return max([1] + [int(p.get("num_threads", 1)) for p in threadpool_info()])
+    except Exception:
+        return 1
+
+
+def laplace_leg(ctx, K=160, sample_n=48):
+    """The mesh-based Galerkin basis (Sec. 5.1): the K = 160 lowest modes of
+    the cotangent Laplacian of the 2.0M-face SH-displaced sphere (128 modes +
+    32, the paper's sizing), one untimed call on a small mesh, then one timed
+    call (host set-up, assembly, filtered subspace iteration, basis table).
+    Roofline of the filter step (sparse block product fused with the
+    recurrence) against HBM: algorithmic bytes per step = the block read once
+    (gathered rows), the previous block read and the new one written (n m 8
+    bytes each) plus the matrix (12 bytes per entry, 4 per row). The oracle
+    (shift-invert ARPACK) is timed on a bounded sample, the same family at
+    20 sample_n^2 faces, with the GPU timed on that sample too."""
+    import torch
+
+    from oracle import laplace as LP  # CPU baseline only
+    from paper_2606_05581_amd import workloads as W
+
+    Vs, Fs = W.sh_sphere_mesh(sample_n)
+    b, _, _, _ = ctx.basis_laplacian(Vs, Fs, K, want_phi=False)  # untimed warm-up
+    b.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b, _, _, info_s = ctx.basis_laplacian(Vs, Fs, K, want_phi=False)
+    torch.cuda.synchronize()
+    gpu_sample_s = time.perf_counter() - t0
+    b.close()
+    t0 = time.perf_counter()
+    LP.laplacian_basis(Vs.astype(np.float64), Fs, K)
+    cpu_sample_s = time.perf_counter() - t0
+    t = time.perf_counter()
+    V, F = W.sh_sphere_mesh()
+    log(f"[bench] laplace leg: {V.shape[0]} vertices, {F.shape[0]} faces, K={K} (mesh in "
+        f"{time.perf_counter() - t:.1f} s); sample {Vs.shape[0]} vertices: GPU {gpu_sample_s:.3f} s, "
+        f"oracle {cpu_sample_s:.2f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b, lam, _, info = ctx.basis_laplacian(V, F, K, want_phi=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    b.close()
+    n, m = V.shape[0], info["block"]
+    filter_steps = info["spmm_calls"] - 2 * (info["iters"] + 1)  # minus the two plain products per iteration
+    step_bytes = 3.0 * n * m * 8 + 12.0 * info["nnz"] + 4.0 * (n + 1)
+    step_ms = info["filter_ms"] / max(filter_steps, 1)
+    gbs = step_bytes / (step_ms * 1e-3) / 1e9
+    log(f"[bench] laplace: {el:.2f} s ({info['iters']} iterations, {filter_steps} filter steps of "
+        f"{step_ms:.3f} ms = {gbs:.0f} GB/s, dense {info['dense_ms']:.0f} ms, b {info['bound']:.3e})")
+    return {
+        "workload": "laplace_sh_sphere_2m", "vertices": int(n), "faces": int(F.shape[0]), "K": K, "block": m,
+        "value": el, "unit": "s", "higher_is_better": False, "converged": bool(info["converged"]),
+        "iters": info["iters"], "filter_steps": int(filter_steps), "last_degree": info["degree"],
+        "bound": info["bound"], "max_residual": info["max_residual"], "lambda_K": float(lam[-1]),
+        "ms": {k: info[k] for k in ("setup_ms", "assemble_ms", "filter_ms", "dense_ms", "total_ms")},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "kernel": "cheb_step_kernel", "bytes_per_step": step_bytes},
+        "sample": {"vertices": int(Vs.shape[0]), "faces": int(Fs.shape[0]), "gpu_s": gpu_sample_s,
+                   "gpu_iters": info_s["iters"]},
+        "cpu_baseline": {"value": cpu_sample_s, "unit": "s", "cores": _cpu_threads(), "kind": "oracle",
+                         "sample": f"K={K} on the {Fs.shape[0]}-face member of the same mesh family"},
+    }
+
+
 def knn_leg(ctx, walks=1024):
     """The point basis (point-based k-NN interpolator) against the per-vertex
     table on the same walks: sh_sphere_2m's 10,000 point rows, `walks` walks
@@ -275,6 +347,8 @@ def main():
     ap.add_argument("--no-psd", action="store_true", help="skip the PSD estimator (Alg. 2) leg")
     ap.add_argument("--psd-only", action="store_true", help="run only the PSD estimator leg (profiling)")
     ap.add_argument("--no-knn", action="store_true", help="skip the point-basis (k-NN) leg")
+    ap.add_argument("--no-laplace", action="store_true", help="skip the mesh Laplacian basis leg")
+    ap.add_argument("--laplace-only", action="store_true", help="run only the mesh Laplacian basis leg")
     ap.add_argument("--knn-only", action="store_true", help="run only the point-basis leg")
     ap.add_argument("--launch", default="", help="fixed launch settings instead of tuning, e.g. chunk=64,regen_min=16")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2606_05581_amd", "tune_cache.jsonl"),
@@ -298,6 +372,9 @@ def main():
         return
     if args.knn_only:
         print(json.dumps({"knn": knn_leg(msk.Context(0))}), flush=True)
+        return
+    if args.laplace_only:
+        print(json.dumps({"laplace": laplace_leg(msk.Context(0))}), flush=True)
         return
     t = time.perf_counter()
     wl = W.load(args.workload)
@@ -445,6 +522,7 @@ def main():
         "cpu_baseline": cpu,
         "psd": None if args.no_psd else psd_leg(ctx),
         "knn": None if args.no_knn else knn_leg(ctx),
+        "laplace": None if args.no_laplace else laplace_leg(ctx),
     }
     print(json.dumps(line), flush=True)
 

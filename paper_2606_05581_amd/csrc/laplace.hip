@@ -32,6 +32,8 @@
 namespace msk {
 
 bool sym_eig(int n, std::vector<double>& A, std::vector<double>& evals, std::vector<double>& V);
+bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>& evals, std::vector<double>& V,
+                      double* abs_max);
 bool cholesky_upper(int n, const std::vector<double>& A, std::vector<double>& R, double rel_tol);
 void upper_inverse(int n, const std::vector<double>& R, std::vector<double>& Ri);
 
@@ -156,6 +158,11 @@ __global__ void __launch_bounds__(256) scale_rows_kernel(const int32_t* __restri
 // One step of the filter: Z = alpha (A Y - shift Y) - beta X, one wavefront
 // per row, lane l holding columns l + 64 t (t < C, m = 64 C); beta == 0
 // reads no X. With alpha = 1, shift = beta = 0 it is the plain product A Y.
+// The rows are dealt to the eight XCDs in contiguous eighths (workgroup b
+// runs on XCD b % 8; the grid is a multiple of 8) and swept in order, so the
+// neighbour rows a row gathers, close to it in the vertex order, are read
+// through the same L2 while still there. X and Z are streamed past the caches (non-temporal), leaving them to
+// the gathered rows of Y.
 template <int C>
 __global__ void __launch_bounds__(256) cheb_step_kernel(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col,
@@ -165,13 +172,33 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(const int32_t* __restric
                                                         double beta) {
   constexpr int m = 64 * C;
   const int lane = threadIdx.x & 63;
-  const int64_t waves = (int64_t)gridDim.x * 4;
-  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < nv; i += waves) {
+  const int64_t per_xcd = gridDim.x >> 3, xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+  const int64_t chunk = (nv + 7) >> 3;
+  const int64_t lo = xcd * chunk, hi = min(nv, lo + chunk);
+  for (int64_t i = lo + j * 4 + (threadIdx.x >> 6); i < hi; i += per_xcd * 4) {
     double acc[C];
 #pragma unroll
     for (int t = 0; t < C; ++t) acc[t] = 0.0;
     const int32_t p1 = rowptr[i + 1];
-    for (int32_t p = rowptr[i]; p < p1; ++p) {
+    int32_t p = rowptr[i];
+    // four neighbour rows per batch of loads (more reads in flight per
+    // wavefront); the products are added in entry order either way
+    for (; p + 4 <= p1; p += 4) {
+      double v[4][C];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double* yr = Y + (int64_t)col[p + u] * m + lane;
+#pragma unroll
+        for (int t = 0; t < C; ++t) v[u][t] = yr[64 * t];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double a = val[p + u];
+#pragma unroll
+        for (int t = 0; t < C; ++t) acc[t] += a * v[u][t];
+      }
+    }
+    for (; p < p1; ++p) {
       const double a = val[p];
       const double* yr = Y + (int64_t)col[p] * m + lane;
 #pragma unroll
@@ -182,10 +209,12 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(const int32_t* __restric
     if (beta != 0.0) {
       const double* xi = X + i * m + lane;
 #pragma unroll
-      for (int t = 0; t < C; ++t) zi[64 * t] = alpha * (acc[t] - shift * yi[64 * t]) - beta * xi[64 * t];
+      for (int t = 0; t < C; ++t)
+        __builtin_nontemporal_store(
+            alpha * (acc[t] - shift * yi[64 * t]) - beta * __builtin_nontemporal_load(xi + 64 * t), zi + 64 * t);
     } else {
 #pragma unroll
-      for (int t = 0; t < C; ++t) zi[64 * t] = alpha * (acc[t] - shift * yi[64 * t]);
+      for (int t = 0; t < C; ++t) __builtin_nontemporal_store(alpha * (acc[t] - shift * yi[64 * t]), zi + 64 * t);
     }
   }
 }
@@ -301,7 +330,10 @@ int grid_of(int64_t n, int64_t per = 256, int64_t cap = 1 << 20) {
 
 hipError_t cheb_step(const LaplaceJob& J, const double* Y, const double* X, double* Z, double alpha, double shift,
                      double beta, hipStream_t s) {
-  const int grid = grid_of(J.n, 4, 1 << 22);
+  const int64_t chunk = (J.n + 7) / 8;
+  // one group of four rows per workgroup: each XCD's workgroups are dispatched
+  // in row order, so its rows are swept in order
+  const int grid = 8 * (int)std::max<int64_t>(1, std::min<int64_t>((chunk + 3) / 4, 1 << 27));
   const dim3 b(256);
   switch (J.m / 64) {
 #define LAP_CASE(c)                                                                                            \
@@ -554,7 +586,10 @@ int laplace_basis_device(LaplaceJob& J, std::string& err) {
     for (int i = 0; i < rank; ++i)
       for (int j = 0; j < rank; ++j)
         Hr[(size_t)i * rank + j] = 0.5 * (H[(size_t)i * m + j] + H[(size_t)j * m + i]);
-    if (!sym_eig(rank, Hr, ev, U)) {
+    // all pairs of the projected matrix: eigenvalues by implicit QR, vectors by
+    // inverse iteration on the tridiagonal form (faster than accumulating the
+    // QR rotations)
+    if (!sym_eig_smallest(rank, Hr, rank, ev, U, nullptr)) {
       err = "eigen-decomposition of the projected matrix did not converge";
       return 5;
     }

@@ -644,6 +644,15 @@ def exterior200_301k(N=20000, walks=256):
     return Workload("exterior200_301k", [case], walks=walks, modes=["exterior"], k=128)
 
 
+def sh_sphere_mesh(n=316, seed=1002):
+    """The SH-displaced sphere of sh_sphere_2m alone (20 n^2 faces; n = 316:
+    998,562 vertices, 1,997,120 faces), FP32 positions in the unit ball."""
+    rng = np.random.default_rng(seed)
+    V, F = sh_displaced_sphere(n, 16, 0.05, rng)
+    V = normalise_unit_ball(V)
+    return V.astype(np.float32), F.astype(np.int32)
+
+
 def psd_sh_sphere_2m(n=316, N=16384, pairs=320, K=128):
     """PSD estimator (Alg. 2) workload at the scale of the paper's runtime study
     (2^14 sample points, about 10M walks, the first 128 basis functions): the

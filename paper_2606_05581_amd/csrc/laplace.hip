@@ -46,6 +46,8 @@ constexpr double kDegenerateRel = 1e-12;
 // relative to the damped interval per outer iteration (larger gains make the
 // filtered block worse conditioned for the Cholesky QR)
 constexpr double kAdaptiveGain = 1e3;
+// rows a wavefront of the filter step carries at once
+constexpr int kFilterRows = 1;
 
 __device__ __forceinline__ int32_t find_col(const int32_t* __restrict__ col, int32_t lo, int32_t hi, int32_t key) {
   while (lo < hi) {
@@ -156,14 +158,40 @@ __global__ void __launch_bounds__(256) scale_rows_kernel(const int32_t* __restri
 }
 
 // One step of the filter: Z = alpha (A Y - shift Y) - beta X, one wavefront
-// per row, lane l holding columns l + 64 t (t < C, m = 64 C); beta == 0
+// per row, each lane holding C of its m = 64 C columns (lane_col); beta == 0
 // reads no X. With alpha = 1, shift = beta = 0 it is the plain product A Y.
 // The rows are dealt to the eight XCDs in contiguous eighths (workgroup b
 // runs on XCD b % 8; the grid is a multiple of 8) and swept in order, so the
 // neighbour rows a row gathers, close to it in the vertex order, are read
 // through the same L2 while still there. X and Z are streamed past the caches (non-temporal), leaving them to
 // the gathered rows of Y.
+// Lane l's share of a row of m = 64 C doubles: for even C the pairs
+// (128 s + 2 l, 128 s + 2 l + 1), s < C / 2, read as 16-byte loads (each
+// load instruction covers 1 KB of the row); for odd C the columns l + 64 t.
 template <int C>
+__device__ __forceinline__ int lane_col(int t, int lane) {
+  if constexpr (C % 2 == 0)
+    return 128 * (t >> 1) + 2 * lane + (t & 1);
+  else
+    return lane + 64 * t;
+}
+
+template <int C>
+__device__ __forceinline__ void load_lane_row(const double* __restrict__ row, int lane, double v[C]) {
+  if constexpr (C % 2 == 0) {
+#pragma unroll
+    for (int s = 0; s < C / 2; ++s) {
+      const double2 q = *reinterpret_cast<const double2*>(row + 128 * s + 2 * lane);
+      v[2 * s] = q.x;
+      v[2 * s + 1] = q.y;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < C; ++t) v[t] = row[lane + 64 * t];
+  }
+}
+
+template <int C, int R>
 __global__ void __launch_bounds__(256) cheb_step_kernel(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col,
                                                         const double* __restrict__ val, int64_t nv,
@@ -175,46 +203,68 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(const int32_t* __restric
   const int64_t per_xcd = gridDim.x >> 3, xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
   const int64_t chunk = (nv + 7) >> 3;
   const int64_t lo = xcd * chunk, hi = min(nv, lo + chunk);
-  for (int64_t i = lo + j * 4 + (threadIdx.x >> 6); i < hi; i += per_xcd * 4) {
-    double acc[C];
+  // a wavefront takes R consecutive rows and walks their neighbour lists in
+  // step, four entries of each row per batch of loads (more reads in flight);
+  // each row's products are added in entry order
+  for (int64_t i0 = lo + (j * 4 + (threadIdx.x >> 6)) * R; i0 < hi; i0 += per_xcd * 4 * R) {
+    int32_t p[R], e[R];
+    double acc[R][C];
 #pragma unroll
-    for (int t = 0; t < C; ++t) acc[t] = 0.0;
-    const int32_t p1 = rowptr[i + 1];
-    int32_t p = rowptr[i];
-    // four neighbour rows per batch of loads (more reads in flight per
-    // wavefront); the products are added in entry order either way
-    for (; p + 4 <= p1; p += 4) {
-      double v[4][C];
+    for (int r = 0; r < R; ++r) {
+      const bool ok = i0 + r < hi;
+      p[r] = ok ? rowptr[i0 + r] : 0;
+      e[r] = ok ? rowptr[i0 + r + 1] : 0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double* yr = Y + (int64_t)col[p + u] * m + lane;
+      for (int t = 0; t < C; ++t) acc[r][t] = 0.0;
+    }
+    while (true) {
+      bool any = false;
 #pragma unroll
-        for (int t = 0; t < C; ++t) v[u][t] = yr[64 * t];
-      }
+      for (int r = 0; r < R; ++r) any |= p[r] < e[r];
+      if (!any) break;
+      double v[R][4][C], a[R][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double a = val[p + u];
+      for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int t = 0; t < C; ++t) acc[t] += a * v[u][t];
+        for (int u = 0; u < 4; ++u) {
+          const int32_t q = p[r] + u;
+          if (q < e[r]) {
+            a[r][u] = val[q];
+            load_lane_row<C>(Y + (int64_t)col[q] * m, lane, v[r][u]);
+          } else {
+            a[r][u] = 0.0;
+#pragma unroll
+            for (int t = 0; t < C; ++t) v[r][u][t] = 0.0;
+          }
+        }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int t = 0; t < C; ++t) acc[r][t] += a[r][u] * v[r][u][t];
+        p[r] += 4;
       }
     }
-    for (; p < p1; ++p) {
-      const double a = val[p];
-      const double* yr = Y + (int64_t)col[p] * m + lane;
 #pragma unroll
-      for (int t = 0; t < C; ++t) acc[t] += a * yr[64 * t];
-    }
-    const double* yi = Y + i * m + lane;
-    double* zi = Z + i * m + lane;
-    if (beta != 0.0) {
-      const double* xi = X + i * m + lane;
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = i0 + r;
+      if (i >= hi) break;
+      double yv[C];
+      load_lane_row<C>(Y + i * m, lane, yv);
+      double* zi = Z + i * m;
+      if (beta != 0.0) {
+        const double* xi = X + i * m;
 #pragma unroll
-      for (int t = 0; t < C; ++t)
-        __builtin_nontemporal_store(
-            alpha * (acc[t] - shift * yi[64 * t]) - beta * __builtin_nontemporal_load(xi + 64 * t), zi + 64 * t);
-    } else {
+        for (int t = 0; t < C; ++t) {
+          const int c = lane_col<C>(t, lane);
+          __builtin_nontemporal_store(alpha * (acc[r][t] - shift * yv[t]) - beta * __builtin_nontemporal_load(xi + c),
+                                      zi + c);
+        }
+      } else {
 #pragma unroll
-      for (int t = 0; t < C; ++t) __builtin_nontemporal_store(alpha * (acc[t] - shift * yi[64 * t]), zi + 64 * t);
+        for (int t = 0; t < C; ++t) __builtin_nontemporal_store(alpha * (acc[r][t] - shift * yv[t]), zi + lane_col<C>(t, lane));
+      }
     }
   }
 }
@@ -331,15 +381,16 @@ int grid_of(int64_t n, int64_t per = 256, int64_t cap = 1 << 20) {
 hipError_t cheb_step(const LaplaceJob& J, const double* Y, const double* X, double* Z, double alpha, double shift,
                      double beta, hipStream_t s) {
   const int64_t chunk = (J.n + 7) / 8;
-  // one group of four rows per workgroup: each XCD's workgroups are dispatched
-  // in row order, so its rows are swept in order
-  const int grid = 8 * (int)std::max<int64_t>(1, std::min<int64_t>((chunk + 3) / 4, 1 << 27));
+  // one group of 4 kFilterRows rows per workgroup: each XCD's workgroups are
+  // dispatched in row order, so its rows are swept in order
+  const int64_t per = 4 * kFilterRows;
+  const int grid = 8 * (int)std::max<int64_t>(1, std::min<int64_t>((chunk + per - 1) / per, 1 << 27));
   const dim3 b(256);
   switch (J.m / 64) {
 #define LAP_CASE(c)                                                                                            \
   case c:                                                                                                      \
-    hipLaunchKernelGGL(cheb_step_kernel<c>, dim3(grid), b, 0, s, J.rowptr, J.col, J.val, J.n, Y, X, Z, alpha, \
-                       shift, beta);                                                                           \
+    hipLaunchKernelGGL((cheb_step_kernel<c, kFilterRows>), dim3(grid), b, 0, s, J.rowptr, J.col, J.val, J.n, Y, \
+                       X, Z, alpha, shift, beta);                                                              \
     break;
     LAP_CASE(1) LAP_CASE(2) LAP_CASE(3) LAP_CASE(4) LAP_CASE(5) LAP_CASE(6) LAP_CASE(7) LAP_CASE(8)
 #undef LAP_CASE

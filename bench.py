@@ -367,6 +367,13 @@ def main():
     from paper_2606_05581_amd import msk
     from paper_2606_05581_amd import workloads as W
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.psd_only:
         print(json.dumps({"psd": psd_leg(msk.Context(0))}), flush=True)
         return
@@ -383,13 +390,6 @@ def main():
     log(f"[bench] workload {wl.name}: {len(wl.cases)} mesh(es), {n_tris} triangles, {n_rows} rows x {wl.walks} "
         f"walks, {wl.modes} (inputs ready in {time.perf_counter() - t:.1f} s)")
     ctx = msk.Context(0)
-    if args.copy_calibration_mib > 0:
-        n = args.copy_calibration_mib * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
     run = Runner(ctx, wl)
     torch.cuda.synchronize()
     log("[bench] inputs on the GPU")

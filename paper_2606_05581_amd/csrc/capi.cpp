@@ -13,6 +13,7 @@
 
 #include "../../include/msk.h"
 #include "msk_internal.h"
+#include "laplace.h"
 
 using namespace msk;
 

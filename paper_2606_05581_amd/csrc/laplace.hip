@@ -27,7 +27,7 @@
 #include <string>
 #include <vector>
 
-#include "msk_internal.h"
+#include "laplace.h"
 
 namespace msk {
 

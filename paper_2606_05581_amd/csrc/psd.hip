@@ -18,6 +18,7 @@
 #include <cmath>
 
 #include "msk_internal.h"
+#include "laplace.h"
 
 namespace msk {
 

@@ -243,6 +243,24 @@ msk_status msk_basis_create_laplacian(msk_ctx* ctx, const float* V, int64_t nv, 
                                       int32_t K, const msk_laplace_opts* opts, double* evals, double* phi,
                                       msk_laplace_info* info, msk_basis** out);
 
+/* Steklov heat and heat kernel signatures (Sec. 5, eqs. steklovHeat and
+ * spectralSteklovHeat) on the vertices, from n_modes Steklov eigenpairs
+ * expressed in a table basis (for an M-orthonormal basis, the eigenpairs of
+ * the symmetrised K x K estimate of msk_estimate_psd):
+ *   psi_k(v) = sum_j Phi_vj coeffs[j][k]   (Phi: the basis table at vertex v),
+ *   hks[v][t]  = sum_k exp(-evals[k] times[t]) psi_k(v)^2,
+ *   heat[v][t] = sum_k exp(-evals[k] times[t]) a_k psi_k(v),
+ *                a_k = sum_v mass[v] u0[v] psi_k(v).
+ * Host arrays: evals (n_modes), coeffs (K x n_modes row-major, K = the
+ * basis's width), times (n_times, >= 0), mass and u0 (n_verts; needed for
+ * heat), outputs hks and heat (n_verts x n_times row-major; either may be
+ * NULL, not both). FP64 arithmetic on the FP32 table values. Errors:
+ * INVALID_ARG for a point basis, n_modes outside 1..min(512, K), n_times
+ * outside 1..4096, or non-finite inputs. */
+msk_status msk_spectral_heat(msk_ctx* ctx, const msk_basis* basis, int32_t n_modes, const double* evals,
+                             const double* coeffs, const double* times, int32_t n_times, const double* mass,
+                             const double* u0, double* hks, double* heat);
+
 /* -------------------------------------------------------------- estimate */
 
 typedef enum { MSK_INTERIOR = 0, MSK_EXTERIOR = 1 } msk_side;

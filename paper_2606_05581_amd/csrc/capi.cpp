@@ -1969,3 +1969,89 @@ extern "C" msk_status msk_basis_create_laplacian(msk_ctx* ctx, const float* V, i
   const msk_status st = rc == 1 ? MSK_ERR_INVALID_ARG : (rc == 5 ? MSK_ERR_NUMERIC : MSK_ERR_DEVICE);
   return fail(ctx, st, "Laplacian basis: " + err);
 }
+
+// ------------------------------------------------- Steklov heat and signatures
+
+extern "C" msk_status msk_spectral_heat(msk_ctx* ctx, const msk_basis* b, int32_t n_modes, const double* evals,
+                                        const double* coeffs, const double* times, int32_t n_times,
+                                        const double* mass, const double* u0, double* hks, double* heat) {
+  if (!ctx) return MSK_ERR_INVALID_ARG;
+  if (!b || !evals || !coeffs || !times) return fail(ctx, MSK_ERR_INVALID_ARG, "null basis, evals, coeffs or times");
+  if (b->knn_mesh || !b->d_rowptr) return fail(ctx, MSK_ERR_INVALID_ARG, "a table basis is required");
+  if (!hks && !heat) return fail(ctx, MSK_ERR_INVALID_ARG, "no output requested");
+  if (heat && (!mass || !u0)) return fail(ctx, MSK_ERR_INVALID_ARG, "heat needs mass and u0");
+  const int64_t K = b->K, nv = b->nv;
+  if (n_modes < 1 || n_modes > 512 || n_modes > K) return fail(ctx, MSK_ERR_INVALID_ARG, "n_modes outside 1..min(512, K)");
+  if (n_times < 1 || n_times > 4096) return fail(ctx, MSK_ERR_INVALID_ARG, "n_times outside 1..4096");
+  for (int32_t k = 0; k < n_modes; ++k)
+    if (!std::isfinite(evals[k])) return fail(ctx, MSK_ERR_INVALID_ARG, "non-finite eigenvalue");
+  for (int64_t i = 0; i < K * n_modes; ++i)
+    if (!std::isfinite(coeffs[i])) return fail(ctx, MSK_ERR_INVALID_ARG, "non-finite coefficient");
+  for (int32_t t = 0; t < n_times; ++t)
+    if (!std::isfinite(times[t]) || times[t] < 0) return fail(ctx, MSK_ERR_INVALID_ARG, "times must be finite and >= 0");
+  std::vector<double> mu0;
+  if (heat) {
+    mu0.resize(nv);
+    for (int64_t v = 0; v < nv; ++v) {
+      if (!std::isfinite(mass[v]) || !std::isfinite(u0[v])) return fail(ctx, MSK_ERR_INVALID_ARG, "non-finite mass or u0");
+      mu0[v] = mass[v] * u0[v];
+    }
+  }
+  std::vector<double> E((size_t)n_modes * n_times);
+  for (int32_t k = 0; k < n_modes; ++k)
+    for (int32_t t = 0; t < n_times; ++t) E[(size_t)k * n_times + t] = std::exp(-evals[k] * times[t]);
+  const int32_t pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((nv + 3) / 4, 1024));
+  double *d_C = nullptr, *d_W = nullptr, *d_out = nullptr, *d_mu0 = nullptr, *d_part = nullptr;
+  auto free_all = [&]() {
+    dfree(d_C);
+    dfree(d_W);
+    dfree(d_out);
+    dfree(d_mu0);
+    dfree(d_part);
+  };
+  hipError_t he;
+  if ((he = upload(ctx, &d_C, coeffs, (size_t)(K * n_modes))) != hipSuccess ||
+      (he = dalloc(&d_W, E.size())) != hipSuccess || (he = dalloc(&d_out, (size_t)(nv * n_times))) != hipSuccess ||
+      (heat && (he = upload(ctx, &d_mu0, mu0.data(), mu0.size())) != hipSuccess) ||
+      (heat && (he = dalloc(&d_part, (size_t)pgrid * n_modes)) != hipSuccess)) {
+    free_all();
+    return fail(ctx, he == hipErrorOutOfMemory ? MSK_ERR_OOM : MSK_ERR_DEVICE,
+                std::string("spectral buffers: ") + hipGetErrorString(he));
+  }
+  auto run_fields = [&](const std::vector<double>& Wh, int32_t square, double* dst) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(d_W, Wh.data(), sizeof(double) * Wh.size(), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return e;
+    e = launch_spectral_fields(b->d_rowptr, b->d_col, b->d_val, nv, d_C, n_modes, d_W, n_times, square, d_out,
+                               ctx->stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(dst, d_out, sizeof(double) * nv * n_times, hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(ctx->stream);
+  };
+  if (hks && (he = run_fields(E, 1, hks)) != hipSuccess) {
+    free_all();
+    return fail(ctx, MSK_ERR_DEVICE, std::string("heat kernel signature: ") + hipGetErrorString(he));
+  }
+  if (heat) {
+    std::vector<double> part((size_t)pgrid * n_modes), a(n_modes, 0.0);
+    if ((he = launch_spectral_coeff(b->d_rowptr, b->d_col, b->d_val, nv, d_C, n_modes, d_mu0, pgrid, d_part,
+                                    ctx->stream)) != hipSuccess ||
+        (he = hipMemcpyAsync(part.data(), d_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost,
+                             ctx->stream)) != hipSuccess ||
+        (he = hipStreamSynchronize(ctx->stream)) != hipSuccess) {
+      free_all();
+      return fail(ctx, MSK_ERR_DEVICE, std::string("heat coefficients: ") + hipGetErrorString(he));
+    }
+    for (int32_t g = 0; g < pgrid; ++g)
+      for (int32_t k = 0; k < n_modes; ++k) a[k] += part[(size_t)g * n_modes + k];
+    std::vector<double> Wh(E);
+    for (int32_t k = 0; k < n_modes; ++k)
+      for (int32_t t = 0; t < n_times; ++t) Wh[(size_t)k * n_times + t] *= a[k];
+    if ((he = run_fields(Wh, 0, heat)) != hipSuccess) {
+      free_all();
+      return fail(ctx, MSK_ERR_DEVICE, std::string("Steklov heat: ") + hipGetErrorString(he));
+    }
+  }
+  free_all();
+  return MSK_OK;
+}

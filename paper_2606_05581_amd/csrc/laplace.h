@@ -1,5 +1,6 @@
-// Declarations of the mesh Laplacian basis (laplace.hip) and of the Gram
-// product it shares with the PSD estimator (psd.hip).
+// Declarations of the mesh Laplacian basis (laplace.hip), of the Gram
+// product it shares with the PSD estimator (psd.hip), and of the spectral
+// fields built on a basis (spectral.hip).
 #pragma once
 #include "msk_internal.h"
 
@@ -46,4 +47,12 @@ struct LaplaceJob {
   LaplaceInfo info;
 };
 int laplace_basis_device(LaplaceJob& J, std::string& err);
+
+// Steklov heat and heat kernel signatures (spectral.hip)
+hipError_t launch_spectral_fields(const int32_t* rowptr, const int32_t* col, const float* val, int64_t nv,
+                                  const double* Cm, int32_t Ke, const double* W, int32_t T, int32_t square,
+                                  double* out, hipStream_t s);
+hipError_t launch_spectral_coeff(const int32_t* rowptr, const int32_t* col, const float* val, int64_t nv,
+                                 const double* Cm, int32_t Ke, const double* mu0, int32_t grid, double* part,
+                                 hipStream_t s);
 }  // namespace msk

@@ -164,6 +164,8 @@ SIGNATURES = {
     "msk_mesh_rebuild": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "msk_psd_opts_default": ([C.POINTER(PsdOpts)], None),
     "msk_laplace_opts_default": ([C.POINTER(LaplaceOpts)], None),
+    "msk_spectral_heat": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "msk_basis_create_laplacian": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
                                     C.POINTER(LaplaceOpts), C.c_void_p, C.c_void_p, C.POINTER(LaplaceInfo),
                                     C.POINTER(C.c_void_p)], C.c_int),
@@ -275,7 +277,7 @@ class Context:
         vl, pvl = _np(basis.val, np.float32)
         h = C.c_void_p()
         self._check(lib().msk_basis_create(self.h, prp, pcl, pvl, n_verts, int(basis.K), C.byref(h)))
-        return BasisHandle(self, h, int(basis.K))
+        return BasisHandle(self, h, int(basis.K), int(n_verts))
 
     def basis_knn(self, mesh, points, normals, k: int = 8, sigma: float = 0.025, tau_n: float = 0.8) -> "BasisHandle":
         """Point basis: bilateral k-NN interpolation over the sample points (K = number of points)."""
@@ -311,10 +313,31 @@ class Context:
         info = {f: getattr(inf, f) for f, _ in LaplaceInfo._fields_ if f != "reserved"}
         if st == ERR_NOT_CONVERGED and h.value:
             err = MskError(st, lib().msk_last_error(self.h).decode())
-            err.result = (BasisHandle(self, h, int(K)), ev, phi, info)
+            err.result = (BasisHandle(self, h, int(K), nv), ev, phi, info)
             raise err
         self._check(st)
-        return BasisHandle(self, h, int(K)), ev, phi, info
+        return BasisHandle(self, h, int(K), nv), ev, phi, info
+
+    def spectral_heat(self, basis, evals, coeffs, times, mass=None, u0=None, hks: bool = True):
+        """Steklov heat and heat kernel signatures on the vertices from eigenpairs
+        in a table basis (eqs. steklovHeat and spectralSteklovHeat): returns
+        (hks (nv, T) or None, heat (nv, T) or None); heat needs mass and u0."""
+        ev, pe = _np(evals, np.float64)
+        Cc, pc = _np(coeffs, np.float64)
+        tt, pt = _np(times, np.float64)
+        n_modes, T = int(ev.shape[0]), int(tt.shape[0])
+        nv = int(basis.nv)
+        out_h = np.zeros((nv, T)) if hks else None
+        out_u = None
+        pm = pu = None
+        if u0 is not None:
+            mm, pm = _np(mass, np.float64)
+            uu, pu = _np(u0, np.float64)
+            out_u = np.zeros((nv, T))
+        self._check(lib().msk_spectral_heat(self.h, basis.h, n_modes, pe, pc, pt, T, pm, pu,
+                                            out_h.ctypes.data if hks else None,
+                                            out_u.ctypes.data if out_u is not None else None))
+        return out_h, out_u
 
     def eval_knn(self, basis, Q, Nq):
         """The point basis at queries (torch tensors on the GPU, n x 3 float32): (indices, weights), n x k."""
@@ -478,9 +501,10 @@ class RowsHandle(_Handle):
 class BasisHandle(_Handle):
     _destroy = "msk_basis_destroy"
 
-    def __init__(self, ctx, h, K):
+    def __init__(self, ctx, h, K, nv=None):
         super().__init__(ctx, h)
         self.K = K
+        self.nv = nv
 
 
 _FIELD_SHAPE = {

@@ -204,9 +204,10 @@ def laplace_leg(ctx, K=160, sample_n=48):
     32, the paper's sizing), one untimed call on a small mesh, then one timed
     call (host set-up, assembly, filtered subspace iteration, basis table).
     Roofline of the filter step (sparse block product fused with the
-    recurrence) against HBM: algorithmic bytes per step = the block read once
-    (gathered rows), the previous block read and the new one written (n m 8
-    bytes each) plus the matrix (12 bytes per entry, 4 per row). The oracle
+    recurrence) against HBM: algorithmic bytes per step = the filtered columns
+    read once (gathered rows), the previous ones read and the new ones written
+    (8 bytes per vertex and column each) plus the matrix (12 bytes per entry,
+    4 per row), summed by the library over the steps. The oracle
     (shift-invert ARPACK) is timed on a bounded sample, the same family at
     20 sample_n^2 faces, with the GPU timed on that sample too."""
     import torch
@@ -239,11 +240,11 @@ def laplace_leg(ctx, K=160, sample_n=48):
     b.close()
     n, m = V.shape[0], info["block"]
     filter_steps = info["spmm_calls"] - 2 * (info["iters"] + 1)  # minus the two plain products per iteration
-    step_bytes = 3.0 * n * m * 8 + 12.0 * info["nnz"] + 4.0 * (n + 1)
     step_ms = info["filter_ms"] / max(filter_steps, 1)
-    gbs = step_bytes / (step_ms * 1e-3) / 1e9
-    log(f"[bench] laplace: {el:.2f} s ({info['iters']} iterations, {filter_steps} filter steps of "
-        f"{step_ms:.3f} ms = {gbs:.0f} GB/s, dense {info['dense_ms']:.0f} ms, b {info['bound']:.3e})")
+    gbs = info["filter_bytes"] / (info["filter_ms"] * 1e-3) / 1e9  # per-step widths shrink as columns lock
+    log(f"[bench] laplace: {el:.2f} s ({info['iters']} iterations, {filter_steps} filter steps, {step_ms:.3f} ms "
+        f"each on average, {gbs:.0f} GB/s, {info['locked']} columns locked at the end; dense "
+        f"{info['dense_ms']:.0f} ms, b {info['bound']:.3e})")
     return {
         "workload": "laplace_sh_sphere_2m", "vertices": int(n), "faces": int(F.shape[0]), "K": K, "block": m,
         "value": el, "unit": "s", "higher_is_better": False, "converged": bool(info["converged"]),
@@ -251,7 +252,8 @@ def laplace_leg(ctx, K=160, sample_n=48):
         "bound": info["bound"], "max_residual": info["max_residual"], "lambda_K": float(lam[-1]),
         "ms": {k: info[k] for k in ("setup_ms", "assemble_ms", "filter_ms", "dense_ms", "total_ms")},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "kernel": "cheb_step_kernel", "bytes_per_step": step_bytes},
+                     "frac": gbs / HBM_PEAK_GBS, "kernel": "cheb_step_kernel",
+                     "filter_bytes": info["filter_bytes"], "locked_at_end": info["locked"]},
         "sample": {"vertices": int(Vs.shape[0]), "faces": int(Fs.shape[0]), "gpu_s": gpu_sample_s,
                    "gpu_iters": info_s["iters"]},
         "cpu_baseline": {"value": cpu_sample_s, "unit": "s", "cores": _cpu_threads(), "kind": "oracle",

@@ -206,6 +206,10 @@ typedef struct {
   double tol;         /* stop when ||A x - lambda x|| <= tol * b for every wanted
                          pair (|x| = 1, b = the Gershgorin bound of A); 0 = 1e-12 */
   uint64_t seed;      /* start block                                        */
+  int32_t no_locking; /* 1: filter every column in every iteration (default 0:
+                         leading columns whose pairs meet the target, in
+                         multiples of 64, are left out of the filter)       */
+  int32_t reserved;
 } msk_laplace_opts;
 
 typedef struct {
@@ -214,7 +218,8 @@ typedef struct {
   int64_t nnz;             /* stored entries of L                            */
   int64_t spmm_calls;      /* sparse block products                          */
   int32_t block, degree, iters, converged; /* degree: the last filter's      */
-  int32_t grams, rotates, rank_drops, reserved;
+  int32_t grams, rotates, rank_drops, locked; /* locked: columns left out of the
+                                                 last filter                */
   double bound;            /* b, the Gershgorin bound of A                   */
   double filter_lower;     /* lower end of the last damped interval          */
   double max_residual;     /* max over the K pairs of ||A x - lambda x|| / b  */
@@ -223,6 +228,10 @@ typedef struct {
   double filter_ms;        /* device: the filter's sparse products           */
   double dense_ms;         /* orthonormalisation and Rayleigh-Ritz           */
   double total_ms;         /* device work from assembly to the basis table   */
+  double filter_bytes;     /* algorithmic bytes moved by the filter steps:
+                              per step the gathered columns, the previous and
+                              the new ones, 8 bytes each per vertex, plus 12
+                              bytes per entry of L and 4 per row            */
 } msk_laplace_info;
 
 void msk_laplace_opts_default(msk_laplace_opts* opts);

@@ -1841,6 +1841,8 @@ extern "C" msk_status msk_basis_create_laplacian(msk_ctx* ctx, const float* V, i
   J.n = nv;
   J.m = m;
   J.K = K;
+  J.nnz = (int64_t)col.size();
+  J.lock = o.no_locking ? 0 : 1;
   J.degree = o.degree;
   J.max_degree = o.max_degree;
   J.max_iters = o.max_iters;
@@ -1950,6 +1952,8 @@ extern "C" msk_status msk_basis_create_laplacian(msk_ctx* ctx, const float* V, i
     info->grams = J.info.grams;
     info->rotates = J.info.rotates;
     info->rank_drops = J.info.rank_drops;
+    info->locked = J.info.locked;
+    info->filter_bytes = J.info.filter_bytes;
     info->bound = J.info.bound;
     info->filter_lower = J.info.filter_lower;
     info->max_residual = J.info.max_residual;

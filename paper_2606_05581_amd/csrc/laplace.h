@@ -12,13 +12,15 @@ hipError_t launch_gram_upper(const double* A, const double* B, int64_t m, int64_
 // Mesh-based Galerkin basis (laplace.hip)
 struct LaplaceInfo {
   int64_t active_vertices = 0, skipped_faces = 0, spmm_calls = 0;
-  int32_t iters = 0, converged = 0, grams = 0, rotates = 0, rank_drops = 0, last_degree = 0;
-  double bound = 0.0, filter_lower = 0.0, max_residual = 0.0;
+  int32_t iters = 0, converged = 0, grams = 0, rotates = 0, rank_drops = 0, last_degree = 0, locked = 0;
+  double bound = 0.0, filter_lower = 0.0, max_residual = 0.0, filter_bytes = 0.0;
   double assemble_ms = 0.0, filter_ms = 0.0, dense_ms = 0.0, total_ms = 0.0;
 };
 struct LaplaceJob {
   hipStream_t stream = nullptr;
   int64_t n = 0;           // vertices (internal order)
+  int64_t nnz = 0;         // stored entries of L
+  int32_t lock = 1;        // leave converged leading columns out of the filter
   int64_t m = 0, K = 0;    // block size (multiple of 64, <= 512), wanted modes
   int32_t degree = 0, max_degree = 0, max_iters = 0;  // degree 0: adaptive, at most max_degree
   double tol = 0.0;

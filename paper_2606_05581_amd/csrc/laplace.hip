@@ -157,8 +157,9 @@ __global__ void __launch_bounds__(256) scale_rows_kernel(const int32_t* __restri
   if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
 }
 
-// One step of the filter: Z = alpha (A Y - shift Y) - beta X, one wavefront
-// per row, each lane holding C of its m = 64 C columns (lane_col); beta == 0
+// One step of the filter: Z = alpha (A Y - shift Y) - beta X on 64 C columns
+// of blocks with row stride ld, one wavefront per row, each lane holding C
+// of the columns (lane_col); beta == 0
 // reads no X. With alpha = 1, shift = beta = 0 it is the plain product A Y.
 // The rows are dealt to the eight XCDs in contiguous eighths (workgroup b
 // runs on XCD b % 8; the grid is a multiple of 8) and swept in order, so the
@@ -196,9 +197,8 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(const int32_t* __restric
                                                         const int32_t* __restrict__ col,
                                                         const double* __restrict__ val, int64_t nv,
                                                         const double* __restrict__ Y, const double* __restrict__ X,
-                                                        double* __restrict__ Z, double alpha, double shift,
-                                                        double beta) {
-  constexpr int m = 64 * C;
+                                                        double* __restrict__ Z, int64_t ld, double alpha,
+                                                        double shift, double beta) {
   const int lane = threadIdx.x & 63;
   const int64_t per_xcd = gridDim.x >> 3, xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
   const int64_t chunk = (nv + 7) >> 3;
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(const int32_t* __restric
           const int32_t q = p[r] + u;
           if (q < e[r]) {
             a[r][u] = val[q];
-            load_lane_row<C>(Y + (int64_t)col[q] * m, lane, v[r][u]);
+            load_lane_row<C>(Y + (int64_t)col[q] * ld, lane, v[r][u]);
           } else {
             a[r][u] = 0.0;
 #pragma unroll
@@ -251,10 +251,10 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(const int32_t* __restric
       const int64_t i = i0 + r;
       if (i >= hi) break;
       double yv[C];
-      load_lane_row<C>(Y + i * m, lane, yv);
-      double* zi = Z + i * m;
+      load_lane_row<C>(Y + i * ld, lane, yv);
+      double* zi = Z + i * ld;
       if (beta != 0.0) {
-        const double* xi = X + i * m;
+        const double* xi = X + i * ld;
 #pragma unroll
         for (int t = 0; t < C; ++t) {
           const int c = lane_col<C>(t, lane);
@@ -333,6 +333,15 @@ __global__ void __launch_bounds__(256) resid_kernel(const double* __restrict__ A
   for (int j = threadIdx.x; j < K; j += 256) part[(int64_t)blockIdx.x * K + j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
 }
 
+// dst[i][0, L) = src[i][0, L) for n x m blocks
+__global__ void copy_cols_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n, int32_t m,
+                                 int32_t L) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * L; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / L, j = e - (e / L) * L;
+    dst[i * m + j] = src[i * m + j];
+  }
+}
+
 // Start block: uniform values in [-1, 1) from a counter hash of (seed, the
 // vertex's original index, column), zero on vertices of zero mass, for the
 // columns [c0, m).
@@ -378,19 +387,25 @@ int grid_of(int64_t n, int64_t per = 256, int64_t cap = 1 << 20) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, cap));
 }
 
+// The step on columns [c0, m) of the n x m blocks (c0 a multiple of 64).
 hipError_t cheb_step(const LaplaceJob& J, const double* Y, const double* X, double* Z, double alpha, double shift,
-                     double beta, hipStream_t s) {
+                     double beta, hipStream_t s, int64_t c0 = 0) {
+  if (c0 > 0) {
+    Y += c0;
+    Z += c0;
+    if (X) X += c0;
+  }
   const int64_t chunk = (J.n + 7) / 8;
   // one group of 4 kFilterRows rows per workgroup: each XCD's workgroups are
   // dispatched in row order, so its rows are swept in order
   const int64_t per = 4 * kFilterRows;
   const int grid = 8 * (int)std::max<int64_t>(1, std::min<int64_t>((chunk + per - 1) / per, 1 << 27));
   const dim3 b(256);
-  switch (J.m / 64) {
+  switch ((J.m - c0) / 64) {
 #define LAP_CASE(c)                                                                                            \
   case c:                                                                                                      \
     hipLaunchKernelGGL((cheb_step_kernel<c, kFilterRows>), dim3(grid), b, 0, s, J.rowptr, J.col, J.val, J.n, Y, \
-                       X, Z, alpha, shift, beta);                                                              \
+                       X, Z, J.m, alpha, shift, beta);                                                         \
     break;
     LAP_CASE(1) LAP_CASE(2) LAP_CASE(3) LAP_CASE(4) LAP_CASE(5) LAP_CASE(6) LAP_CASE(7) LAP_CASE(8)
 #undef LAP_CASE
@@ -577,6 +592,7 @@ int laplace_basis_device(LaplaceJob& J, std::string& err) {
   double* d_part = J.part;
   double a = 0.0;           // lower end of the damped interval, from the last Rayleigh-Ritz
   int rank = m;
+  int locked = 0;  // leading columns left out of the filter
   int it = 0;
   bool converged = false;
   double* X = B0;  // current block
@@ -597,18 +613,28 @@ int laplace_basis_device(LaplaceJob& J, std::string& err) {
       J.info.last_degree = degree;
       double sig = e / (aL - c);
       const double tau = 2.0 / sig;
+      // soft locking: the leading `locked` columns (converged Ritz vectors)
+      // are not filtered; they stay in X's buffer, which the steps below
+      // touch only in columns [locked, m)
       double *Z0 = X, *Z1 = F1, *Z2 = F2;
-      LAP_TRY(cheb_step(J, Z0, nullptr, Z1, sig / e, c, 0.0, s));
+      LAP_TRY(cheb_step(J, Z0, nullptr, Z1, sig / e, c, 0.0, s, locked));
       for (int k = 2; k <= degree; ++k) {
         const double sn = 1.0 / (tau - sig);
-        LAP_TRY(cheb_step(J, Z1, Z0, Z2, 2.0 * sn / e, c, sig * sn, s));
+        LAP_TRY(cheb_step(J, Z1, Z0, Z2, 2.0 * sn / e, c, sig * sn, s, locked));
         sig = sn;
         double* t0 = Z0;
         Z0 = Z1;
         Z1 = Z2;
         Z2 = t0;
       }
+      if (locked > 0 && Z1 != X) {
+        hipLaunchKernelGGL(copy_cols_kernel, dim3(grid_of(J.n * locked)), dim3(256), 0, s, X, Z1, J.n, m, locked);
+        LAP_TRY(hipGetLastError());
+      }
       LAP_TRY(t_filter.stop());
+      const double w = (double)(m - locked);
+      J.info.filter_bytes += (double)degree * (12.0 * J.nnz + 4.0 * (J.n + 1)) +
+                             (3.0 * degree - 1.0) * (double)J.n * w * 8.0;
       J.info.spmm_calls += degree;
       Y = Z1;
       F1 = Z0;
@@ -662,11 +688,18 @@ int laplace_basis_device(LaplaceJob& J, std::string& err) {
     LAP_TRY(hipStreamSynchronize(s));
     LAP_TRY(t_dense.stop());
     double rmax = 0.0;
+    int nconv = 0;  // leading wanted pairs that meet the target
+    bool lead = true;
     for (int j = 0; j < K; ++j) {
       double acc = 0.0;
       for (int g = 0; g < rgrid; ++g) acc += part[(size_t)g * K + j];
-      rmax = std::max(rmax, std::sqrt(acc));
+      const double r = std::sqrt(acc);
+      rmax = std::max(rmax, r);
+      lead = lead && r <= J.tol * b;
+      if (lead) ++nconv;
     }
+    locked = (rank == m && J.lock) ? std::min(nconv / 64 * 64, m - 64) : 0;
+    J.info.locked = locked;
     X = Xn;
     J.info.max_residual = rmax / b;
     a = theta[rank - 1];

@@ -109,16 +109,17 @@ class PsdLog(C.Structure):
 
 class LaplaceOpts(C.Structure):
     _fields_ = [("block", C.c_int32), ("degree", C.c_int32), ("max_iters", C.c_int32), ("max_degree", C.c_int32),
-                ("tol", C.c_double), ("seed", C.c_uint64)]
+                ("tol", C.c_double), ("seed", C.c_uint64), ("no_locking", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LaplaceInfo(C.Structure):
     _fields_ = [("active_vertices", C.c_int64), ("skipped_faces", C.c_int64), ("nnz", C.c_int64),
                 ("spmm_calls", C.c_int64), ("block", C.c_int32), ("degree", C.c_int32), ("iters", C.c_int32),
                 ("converged", C.c_int32), ("grams", C.c_int32), ("rotates", C.c_int32), ("rank_drops", C.c_int32),
-                ("reserved", C.c_int32), ("bound", C.c_double), ("filter_lower", C.c_double),
+                ("locked", C.c_int32), ("bound", C.c_double), ("filter_lower", C.c_double),
                 ("max_residual", C.c_double), ("setup_ms", C.c_double), ("assemble_ms", C.c_double),
-                ("filter_ms", C.c_double), ("dense_ms", C.c_double), ("total_ms", C.c_double)]
+                ("filter_ms", C.c_double), ("dense_ms", C.c_double), ("total_ms", C.c_double),
+                ("filter_bytes", C.c_double)]
 
 
 _lib = None

@@ -586,7 +586,7 @@ int laplace_basis_device(LaplaceJob& J, std::string& err) {
                      J.seed);
   LAP_TRY(hipGetLastError());
 
-  std::vector<double> H, theta, Z, G;
+  std::vector<double> H, theta;
   std::vector<double> part;
   const int rgrid = 1024;
   double* d_part = J.part;

@@ -166,30 +166,25 @@ __global__ void __launch_bounds__(256) scale_rows_kernel(const int32_t* __restri
 // neighbour rows a row gathers, close to it in the vertex order, are read
 // through the same L2 while still there. X and Z are streamed past the caches (non-temporal), leaving them to
 // the gathered rows of Y.
-// Lane l's share of a row of m = 64 C doubles: for even C the pairs
+// Lane l's share of a row of m = 64 C doubles: the pairs
 // (128 s + 2 l, 128 s + 2 l + 1), s < C / 2, read as 16-byte loads (each
-// load instruction covers 1 KB of the row); for odd C the columns l + 64 t.
+// load instruction covers 1 KB of the row), and for odd C the last 64
+// columns as 128 (C / 2) + l.
 template <int C>
 __device__ __forceinline__ int lane_col(int t, int lane) {
-  if constexpr (C % 2 == 0)
-    return 128 * (t >> 1) + 2 * lane + (t & 1);
-  else
-    return lane + 64 * t;
+  if (t < 2 * (C / 2)) return 128 * (t >> 1) + 2 * lane + (t & 1);
+  return 128 * (C / 2) + lane;
 }
 
 template <int C>
 __device__ __forceinline__ void load_lane_row(const double* __restrict__ row, int lane, double v[C]) {
-  if constexpr (C % 2 == 0) {
 #pragma unroll
-    for (int s = 0; s < C / 2; ++s) {
-      const double2 q = *reinterpret_cast<const double2*>(row + 128 * s + 2 * lane);
-      v[2 * s] = q.x;
-      v[2 * s + 1] = q.y;
-    }
-  } else {
-#pragma unroll
-    for (int t = 0; t < C; ++t) v[t] = row[lane + 64 * t];
+  for (int s = 0; s < C / 2; ++s) {
+    const double2 q = *reinterpret_cast<const double2*>(row + 128 * s + 2 * lane);
+    v[2 * s] = q.x;
+    v[2 * s + 1] = q.y;
   }
+  if constexpr (C % 2 == 1) v[C - 1] = row[128 * (C / 2) + lane];
 }
 
 template <int C, int R>

@@ -739,7 +739,10 @@ void orc_estimate(const void* h, int mode_start, int exterior, int64_t n_rows, c
                   int32_t* log_stri, float* log_sbary,
                   /* optional point basis (point rows): points and normals in world coordinates */
                   const double* knn_x, const double* knn_n, int64_t knn_N, int knn_k, double knn_sigma,
-                  double knn_tau) {
+                  double knn_tau,
+                  /* exterior: 1 drops the killing term (Sec. 3.3, eq. exterior-dtn-beurling-deny-form; the
+                     default of Sec. 4): an escaped walk contributes nothing instead of b(s) */
+                  int jump_only) {
   const OrcScene* s = (const OrcScene*)h;
   OrcBasis B = {rowptr, col, val, K};
   OrcKnn KN = {NULL, knn_n, knn_N, knn_k, knn_sigma, knn_tau};
@@ -841,6 +844,7 @@ void orc_estimate(const void* h, int mode_start, int exterior, int64_t n_rows, c
       } else if (st != ST_ESCAPED) {
         for (int cc = 0; cc < 3; ++cc) sp_add(&c, &B, s->F[3 * tt + cc], -bt[cc]);
       }
+      if (jump_only && st == ST_ESCAPED) c.n = 0;
       for (int m = 0; m < c.n; ++m) {
         A1[c.col[m]] += c.val[m];
         A2[c.col[m]] += c.val[m] * c.val[m];

@@ -86,7 +86,7 @@ def lib():
                C.c_uint32, C.c_int]
             + [_P(C.c_double), _P(C.c_double), _P(C.c_int64), _P(C.c_int64), _P(C.c_int64), _P(C.c_int32)]
             + [_P(C.c_int32), _P(C.c_int64), _P(C.c_float), _P(C.c_int64), _P(C.c_int32), _P(C.c_float)]
-            + [_P(C.c_double), _P(C.c_double), C.c_int64, C.c_int, C.c_double, C.c_double]
+            + [_P(C.c_double), _P(C.c_double), C.c_int64, C.c_int, C.c_double, C.c_double, C.c_int]
         )
         L.orc_knn_weights.argtypes = [_P(C.c_double), _P(C.c_double), C.c_int64, C.c_int, C.c_double, C.c_double,
                                       _P(C.c_double), _P(C.c_double), _P(C.c_int32), _P(C.c_double)]
@@ -230,8 +230,12 @@ DEFAULT_MAX_STEPS = {"interior": 1024, "exterior": 8192}
 
 def estimate(scene: Scene, rows, basis, walks: int, eps: float, h: float, exterior: bool, seed: int = 0,
              w0: int = 0, rows_sel=None, kappa=2.0 ** -20, delta_rel=2.0 ** -21, max_steps=None, mesh: int = 0,
-             log: bool = False, nthreads: int = 1, knn=None):
+             log: bool = False, nthreads: int = 1, knn=None, jump_only: bool = False):
     """Accumulate the naive estimator's per-walk contributions c = b(s) - b(t).
+
+    ``jump_only`` (exterior): drop the killing term of the exterior form
+    (Sec. 3.3, eq. exterior-dtn-beurling-deny-form; the paper's default,
+    Sec. 4): an escaped walk then contributes nothing instead of b(s).
 
     ``knn`` (point rows only) replaces the per-vertex table by the point
     basis: a dict with ``points`` (N,3 world), ``normals`` (N,3 unit), ``k``,
@@ -292,7 +296,7 @@ def estimate(scene: Scene, rows, basis, walks: int, eps: float, h: float, exteri
         _ptr(lst, C.c_int32), _ptr(lsb, C.c_float),
         _ptr(kx, C.c_double), _ptr(kn, C.c_double), 0 if kx is None else kx.shape[0],
         0 if knn is None else int(knn["k"]), 0.0 if knn is None else float(knn["sigma"]),
-        0.0 if knn is None else float(knn["tau"]))
+        0.0 if knn is None else float(knn["tau"]), int(bool(jump_only)))
     out = dict(acc=acc, acc2=acc2, n_query=nq, n_escaped=nesc, n_capped=ncap, discarded=disc, walks=walks)
     if log:
         out.update(log_status=ls, log_tri=lt, log_bary=lb, log_nquery=lq, log_stri=lst, log_sbary=lsb)

@@ -340,9 +340,10 @@ def test_linear_data_point_rows_soup(oracle_mod):
     assert abs(z.mean()) < 4 / math.sqrt(z.size) + 0.05
 
 
-def _sh_coeffs_from_log(oracle_mod, sc, case, table, r, L, Wk):
+def _sh_coeffs_from_log(oracle_mod, sc, case, table, r, L, Wk, jump_only=False):
     """c_l estimates by projecting rows of M^-1 S onto Y_lm(s_i), with a
-    per-walk standard error from the walk log."""
+    per-walk standard error from the walk log (jump_only: escaped walks
+    contribute nothing)."""
     rows = case.rows
     S_dir = rows.p.astype(np.float64) / np.linalg.norm(rows.p.astype(np.float64), axis=1, keepdims=True)
     Ys = W.real_sh(L, S_dir)  # (N, K)
@@ -356,6 +357,8 @@ def _sh_coeffs_from_log(oracle_mod, sc, case, table, r, L, Wk):
     bt = np.einsum("iwc,iwck->iwk", lam, table[Fv[np.where(hit, tri, 0)]])
     bt = np.where(hit[..., None], bt, 0.0)
     C = (bs[:, None, :] - bt) / case.h  # (N, W, K) per-walk M^-1 S rows
+    if jump_only:
+        C = np.where(hit[..., None], C, 0.0)
     out = []
     col = 0
     for l in range(L + 1):
@@ -489,3 +492,48 @@ def test_steklov_modes_generalised_problem(oracle_mod):
     R = Ssym @ psi - (w[:, None] * psi) * ev[None, :]
     assert np.abs(R).max() < 1e-9
     assert np.allclose(psi.T @ (w[:, None] * psi), np.eye(10), atol=1e-10)
+
+
+def test_jump_only_exterior_sphere(oracle_mod):
+    """The exterior form without its killing term (Sec. 3.3, eq.
+    exterior-dtn-beurling-deny-form; the default of Sec. 4): the same walks,
+    escaped ones contributing nothing. On the unit sphere escape from
+    (1 + h) s has probability h / (1 + h), so the killing part of the
+    finite-h factor is 1 / (1 + h) and the jump-only factor is
+    (1 - (1 + h)^-(l+1)) / h - 1 / (1 + h) -> l (constants are in the kernel).
+    The accumulators equal the full ones less (escaped walks) x b(s)."""
+    V, F = W.icosphere_recursive(5)
+    rng = np.random.default_rng(7)
+    rows = W.point_rows(V, F, 600, rng, pool_factor=8)
+    L = 3
+    table = W.real_sh(L, V)
+    case = W.MeshCase(V=V.astype(np.float32), F=F.astype(np.int32), rows=rows, basis=W.dense_basis(table),
+                      eps=1e-3, h=0.05)
+    sc = oracle_mod.Scene(case.V, case.F, bvh=True)
+    Wk = 256
+    full = oracle_mod.estimate(sc, rows, case.basis, Wk, case.eps, case.h, exterior=True, log=True, nthreads=8)
+    jump = oracle_mod.estimate(sc, rows, case.basis, Wk, case.eps, case.h, exterior=True, log=True, nthreads=8,
+                               jump_only=True)
+    assert np.array_equal(full["log_status"], jump["log_status"]) and np.array_equal(full["log_tri"], jump["log_tri"])
+    assert np.array_equal(full["n_escaped"], jump["n_escaped"]) and full["n_escaped"].sum() > 0
+    tab32 = table.astype(np.float32).astype(np.float64)
+    bs = np.einsum("ic,ick->ik", rows.bary.astype(np.float64), tab32[F[rows.tri]])
+    assert np.allclose(jump["acc"], full["acc"] - full["n_escaped"][:, None] * bs, atol=1e-9 * Wk)
+    est = _sh_coeffs_from_log(oracle_mod, sc, case, tab32, jump, L, Wk, jump_only=True)
+    h = case.h
+    for l, (e, se) in enumerate(est):
+        tgt = (1 - (1 + h) ** -(l + 1)) / h - 1 / (1 + h)
+        assert abs(e - tgt) <= 4 * se + 0.025 * max(tgt, 1.0), (l, e, tgt, se)
+
+
+def test_jump_only_rows_sum_to_zero(oracle_mod, c1):
+    """Hat basis (a partition of unity): with the killing term dropped every
+    walk's c sums to zero, so every exterior row does."""
+    c, sc = c1
+    rows = W.point_rows(c.V.astype(np.float64), c.F, 100, np.random.default_rng(3))
+    r = oracle_mod.estimate(sc, rows, c.basis, 64, c.eps, c.h, exterior=True, jump_only=True)
+    assert r["n_escaped"].sum() > 0
+    # the samples' barycentrics are FP32: each walk's b(s) sums to 1 within about 1e-7
+    assert np.abs(r["acc"].sum(1)).max() < 1e-6 * 64
+    full = oracle_mod.estimate(sc, rows, c.basis, 64, c.eps, c.h, exterior=True)
+    assert np.abs(full["acc"].sum(1) - full["n_escaped"]).max() < 1e-6 * 64

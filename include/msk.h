@@ -298,6 +298,11 @@ typedef struct {
   int32_t accum;         /* persistent form, partial row sums of a chunk of
                             walks kept in LDS: 0 = FP64, 1 = FP32 (mixed
                             precision); rows are always accumulated in FP64  */
+  int32_t jump_only;     /* exterior, point rows: 1 drops the killing term of
+                            the exterior form (Sec. 3.3, exterior
+                            Beurling-Deny form; the paper's default exterior
+                            operator, Sec. 4): an escaped walk contributes 0
+                            instead of b(s), so constants are in the kernel */
 } msk_dtn_opts;
 
 void msk_dtn_opts_default(msk_dtn_opts* opts);

@@ -795,6 +795,8 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
   if (opts) o = *opts;
   if (o.form != MSK_FORM_PLAIN && o.form != MSK_FORM_PERSISTENT) return fail(ctx, MSK_ERR_INVALID_ARG, "bad form");
   if (o.accum != 0 && o.accum != 1) return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64) or 1 (FP32)");
+  if (o.jump_only != 0 && (o.jump_only != 1 || side != MSK_EXTERIOR || r->mode != MSK_ROWS_POINT))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "jump_only takes exterior estimates with point rows");
   if (o.collect_stats && b && b->knn_mesh)
     return fail(ctx, MSK_ERR_INVALID_ARG, "traversal statistics are not collected with the point basis");
   if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32) ||
@@ -894,7 +896,7 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
     }
     HIP_D(hipMemcpy(d->d_walks, wdone.data(), d->n * 8, hipMemcpyHostToDevice));
   }
-  HIP_D(launch_finalize(M, d->n, d->d_walks, r->d_w, d->d_S, d->d_se, ctx->stream));
+  HIP_D(launch_finalize(M, d->n, d->d_walks, r->d_w, d->d_S, d->d_se, ctx->stream, o.jump_only));
   HIP_D(launch_fill_u64(d->d_nonfinite, 1, 0, ctx->stream));
   HIP_D(launch_count_nonfinite(d->d_S, (int64_t)nk, d->d_nonfinite, ctx->stream));
   HIP_D(launch_count_nonfinite(d->d_se, (int64_t)nk, d->d_nonfinite, ctx->stream));
@@ -992,7 +994,8 @@ static hipError_t enqueue_batch(msk_batch* B, hipStream_t s, int part) {
   for (int32_t i = 0; i < B->n; ++i) {
     msk_dtn* d = B->dtns[i];
     const int64_t nk = d->n * d->K;
-    if ((e = launch_finalize(B->md[i], d->n, d->d_walks, B->rows[i]->d_w, d->d_S, d->d_se, s)) != hipSuccess ||
+    if ((e = launch_finalize(B->md[i], d->n, d->d_walks, B->rows[i]->d_w, d->d_S, d->d_se, s, B->o.jump_only)) !=
+            hipSuccess ||
         (e = launch_fill_u64(d->d_nonfinite, 1, 0, s)) != hipSuccess ||
         (e = launch_count_nonfinite(d->d_S, nk, d->d_nonfinite, s)) != hipSuccess ||
         (e = launch_count_nonfinite(d->d_se, nk, d->d_nonfinite, s)) != hipSuccess)
@@ -1020,6 +1023,8 @@ extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk
   for (int32_t i = 0; i < n_meshes; ++i) {
     if (o.collect_stats && bases[i] && bases[i]->knn_mesh)
       return fail(ctx, MSK_ERR_INVALID_ARG, "traversal statistics are not collected with the point basis");
+    if (o.jump_only != 0 && (o.jump_only != 1 || side != MSK_EXTERIOR || !rows[i] || rows[i]->mode != MSK_ROWS_POINT))
+      return fail(ctx, MSK_ERR_INVALID_ARG, "jump_only takes exterior estimates with point rows");
     msk_status st = check_problem(ctx, meshes[i], rows[i], bases[i], walks, eps[i], inset_h[i], side);
     if (st != MSK_OK) return fail(ctx, st, "mesh " + std::to_string(i) + ": " + ctx->err);
   }
@@ -1279,6 +1284,7 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   o.collect_stats = 0;
   const int64_t W = 2 * pairs;
   // the walk problem: interior walks; the inset is not used by ball starts
+  if (walk_opts && walk_opts->jump_only) return fail(ctx, MSK_ERR_INVALID_ARG, "jump_only applies to exterior estimates");
   msk_status st = check_problem(ctx, m, r, b, W, eps, 2.0 * eps, MSK_INTERIOR, false);
   if (st != MSK_OK) return st;
   double r_max = po.r_max;

@@ -168,7 +168,7 @@ hipError_t launch_knn_eval(const KnnDev& G, const double* c, const float* Q, con
 hipError_t launch_closest_points(const Node4* nodes, const TriRec* tris, float radius, const double* c, const float* Q,
                                  int64_t nq, int32_t* tri, float* d2, float* bary, hipStream_t s);
 hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walks, const double* w, double* S,
-                           double* se, hipStream_t s);
+                           double* se, hipStream_t s, int32_t jump_only = 0);
 
 // PSD estimator (psd.hip): per-pair inputs of the rank-one updates
 struct PsdGather {

@@ -1468,20 +1468,25 @@ __global__ void finalize_kernel(MeshDev M, int64_t n_rows, const int64_t* __rest
   }
 }
 
+// With jump_only (exterior), the killing term is dropped (Sec. 3.3, exterior
+// Beurling-Deny form; the paper's default exterior operator): an escaped
+// walk contributes nothing instead of b(s), so b(s) enters once per walk
+// that did not escape.
 __global__ void finalize_point_fix_kernel(MeshDev M, int64_t n_rows, const int64_t* __restrict__ walks,
-                                          const double* __restrict__ w, double* S, double* se) {
+                                          const double* __restrict__ w, double* S, double* se, int32_t jump_only) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rows || M.discarded[i]) return;
   const int32_t* f = M.faces + 3 * (int64_t)M.tri[i];
   const int32_t vv[3] = {f[0], f[1], f[2]};
   const double ww[3] = {(double)M.bary[3 * i], (double)M.bary[3 * i + 1], (double)M.bary[3 * i + 2]};
   const double Wi = (double)walks[i];
+  const double Hi = jump_only ? Wi - (double)M.row_escaped[i] : Wi;  // walks that carry b(s)
   const double scale = w[i] / M.inset_d;
   auto fix = [&](int32_t j, double bs) {
     const int64_t idx = i * M.K + j;
     const double t1 = M.acc1[idx], t2 = M.acc2[idx];
-    const double s1 = Wi * bs - t1;
-    const double s2 = Wi * bs * bs - 2.0 * bs * t1 + t2;
+    const double s1 = Hi * bs - t1;
+    const double s2 = Hi * bs * bs - 2.0 * bs * t1 + t2;
     const double mean = s1 / Wi;
     const double var = fmax(0.0, s2 / Wi - mean * mean) * (Wi / (Wi - 1.0));
     S[idx] = scale * mean;
@@ -1621,13 +1626,14 @@ hipError_t launch_closest_points(const Node4* nodes, const TriRec* tris, float r
 }
 
 hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walks, const double* w, double* S,
-                           double* se, hipStream_t s) {
+                           double* se, hipStream_t s,
+                           int32_t jump_only) {
   if (n_rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(n_rows * M.K, 256)), dim3(256), 0, s, M, n_rows, walks, w, S, se);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || M.mode != kRowsPoint) return e;
   hipLaunchKernelGGL(finalize_point_fix_kernel, dim3(blocks_for(n_rows, 128)), dim3(128), 0, s, M, n_rows, walks, w, S,
-                     se);
+                     se, jump_only);
   return hipGetLastError();
 }
 

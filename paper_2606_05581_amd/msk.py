@@ -61,7 +61,7 @@ class DtnOpts(C.Structure):
                 ("delta_rel", C.c_double), ("form", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("chunk", C.c_int32), ("regen_min", C.c_int32), ("record_log", C.c_int32), ("se_target", C.c_double),
                 ("walks_max", C.c_int64), ("collect_stats", C.c_int32), ("mesh_id", C.c_int32),
-                ("accum", C.c_int32)]
+                ("accum", C.c_int32), ("jump_only", C.c_int32)]
 
 
 class DtnInfo(C.Structure):

@@ -154,6 +154,24 @@ def test_laplace_components_and_degenerate_faces(ctx):
     _compare(V2, F2, lam, Phi, info, K, "3 spheres + degenerate")
 
 
+def test_laplace_fans_and_nonmanifold_edge(ctx):
+    """A closed double cone (apex and base centre of degree 200) with a fin of two
+    triangles on one slant edge, which that edge then shares with three faces."""
+    n = 200
+    ang = 2 * np.pi * np.arange(n) / n
+    ring = np.stack([np.cos(ang), np.sin(ang), np.zeros(n)], 1)
+    V = np.concatenate([ring, [[0.0, 0.0, 1.0], [0.0, 0.0, -0.7], [0.9, 0.4, 0.8], [1.3, 0.1, 0.3]]])
+    apex, base, f1, f2 = n, n + 1, n + 2, n + 3
+    F = [[i, (i + 1) % n, apex] for i in range(n)] + [[(i + 1) % n, i, base] for i in range(n)]
+    F += [[0, apex, f1], [0, f1, f2]]  # the fin on edge (0, apex)
+    V, F = V.astype(np.float32), np.array(F, dtype=np.int32)
+    K = 20
+    bh, lam, Phi, info = ctx.basis_laplacian(V, F, K, seed=4)
+    bh.close()
+    assert info["converged"] == 1 and info["skipped_faces"] == 0 and info["iters"] > 0
+    _compare(V, F, lam, Phi, info, K, "fans + non-manifold edge")
+
+
 def test_laplace_argument_errors(ctx):
     from paper_2606_05581_amd import msk
 

@@ -43,6 +43,22 @@ def kernel_sources_sha():
                           + open(os.path.join(csrc, "msk_internal.h"), "rb").read()).hexdigest()[:16]
 
 
+def laplace_sources_sha():
+    csrc = os.path.join(ROOT, "paper_2606_05581_amd", "csrc")
+    return hashlib.sha256(open(os.path.join(csrc, "laplace.hip"), "rb").read()
+                          + open(os.path.join(csrc, "laplace.h"), "rb").read()).hexdigest()[:16]
+
+
+def laplace_traffic():
+    """HBM bytes of all filter steps of the basis leg's full-mesh solve, from
+    the committed counter passes, if taken on the current sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_laplace_sh_sphere_2m.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    return rec["filter_traffic_bytes"] if rec.get("source_sha") == laplace_sources_sha() else None
+
+
 def measured_traffic(workload):
     """HBM bytes per walk-kernel launch from the committed rocprofv3 counter
     passes, if they were taken on the current kernel sources (else None)."""
@@ -253,7 +269,8 @@ def laplace_leg(ctx, K=160, sample_n=48):
         "ms": {k: info[k] for k in ("setup_ms", "assemble_ms", "filter_ms", "dense_ms", "total_ms")},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "kernel": "cheb_step_kernel",
-                     "filter_bytes": info["filter_bytes"], "locked_at_end": info["locked"]},
+                     "filter_bytes": info["filter_bytes"], "traffic": laplace_traffic(),
+                     "locked_at_end": info["locked"]},
         "sample": {"vertices": int(Vs.shape[0]), "faces": int(Fs.shape[0]), "gpu_s": gpu_sample_s,
                    "gpu_iters": info_s["iters"]},
         "cpu_baseline": {"value": cpu_sample_s, "unit": "s", "cores": _cpu_threads(), "kind": "oracle",

@@ -1367,33 +1367,81 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
 // d2 < B) and stops at the first triangle found with sqrt(d2) < t; when none
 // lies below B the ball is accepted. Same decisions as comparing the exact
 // nearest distance with t, with only the boxes near the ball visited.
-__global__ void tangent_ball_kernel(MeshDev M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_rows) return;
-  const float sx = M.p[3 * i], sy = M.p[3 * i + 1], sz = M.p[3 * i + 2];
-  double nx = M.n[3 * i], ny = M.n[3 * i + 1], nz = M.n[3 * i + 2];
-  const double nl = sqrt(nx * nx + ny * ny + nz * nz);
-  nx /= nl; ny /= nl; nz /= nl;
-  float lo = 0.0f, hi = r_max;
-  for (int32_t it = 0; it < iters; ++it) {
-    const float mid = 0.5f * (lo + hi);
-    const double cxd = sx - mid * nx, cyd = sy - mid * ny, czd = sz - mid * nz;
-    const float cx = (float)cxd, cy = (float)cyd, cz = (float)czd;
-    const float t = mid - fminf(tol, mid * 0x1p-10f);
-    const float bound = t > 0.0f ? (t * t) * (1.0f + 0x1p-20f) : 0.0f;
-    Nearest h;
-    h.d2 = bound; h.orig = INT_MAX; h.slot = -1;
-    TravCount cnt;
-    if (t > 0.0f) bvh_nearest<false, true>(M.nodes, M.tris, nullptr, 0, cx, cy, cz, M.radius, h, cnt, t);
-    const bool empty = h.orig == INT_MAX || sqrtf(h.d2) >= t;
-    const bool inside = empty && sqrt(cxd * cxd + cyd * cyd + czd * czd) + mid <= M.radius_d;
-    if (inside)
-      lo = mid;
-    else
-      hi = mid;
+// Whether the ball of radius r touching s from the inside is accepted (the
+// test of one bisection step).
+__device__ bool tangent_ball_inside(const MeshDev& M, float sx, float sy, float sz, double nx, double ny, double nz,
+                                    float mid, float tol) {
+  const double cxd = sx - mid * nx, cyd = sy - mid * ny, czd = sz - mid * nz;
+  const float cx = (float)cxd, cy = (float)cyd, cz = (float)czd;
+  const float t = mid - fminf(tol, mid * 0x1p-10f);
+  const float bound = t > 0.0f ? (t * t) * (1.0f + 0x1p-20f) : 0.0f;
+  Nearest h;
+  h.d2 = bound; h.orig = INT_MAX; h.slot = -1;
+  TravCount cnt;
+  if (t > 0.0f) bvh_nearest<false, true>(M.nodes, M.tris, nullptr, 0, cx, cy, cz, M.radius, h, cnt, t);
+  const bool empty = h.orig == INT_MAX || sqrtf(h.d2) >= t;
+  return empty && sqrt(cxd * cxd + cyd * cyd + czd * czd) + mid <= M.radius_d;
+}
+
+// The bisection of a row, three levels per round: the eight lanes of a row
+// evaluate the (up to) seven midpoints of the next three levels at once (lane
+// k takes heap node k of that subtree: node 1 the current midpoint, node 2k
+// and 2k + 1 the midpoints of its lower and upper halves), then all follow
+// the path the sequential bisection takes through them. Every midpoint is
+// formed by the same float operations as in the sequential loop, so the
+// radius is the same; the rounds of dependent queries drop from iters to
+// ceil(iters / 3), and eight lanes per row fill the GPU with 16,384 rows.
+// row_queries counts the iters decisions of the bisection.
+__global__ void __launch_bounds__(64) tangent_ball_kernel(MeshDev M, int64_t n_rows, float r_max, int32_t iters,
+                                                          float tol, float* radius) {
+  const int lane = threadIdx.x & 63, sub = lane & 7, gbase = lane & ~7;
+  // eight rows per 64-lane workgroup; the loop bound is uniform over the
+  // workgroup, so every lane takes part in every ballot
+  for (int64_t base = (int64_t)blockIdx.x * 8; base < n_rows; base += (int64_t)gridDim.x * 8) {
+    const int64_t i = base + (threadIdx.x >> 3);
+    const bool valid = i < n_rows;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    double nx = 0.0, ny = 0.0, nz = 1.0;
+    if (valid) {
+      sx = M.p[3 * i]; sy = M.p[3 * i + 1]; sz = M.p[3 * i + 2];
+      nx = M.n[3 * i]; ny = M.n[3 * i + 1]; nz = M.n[3 * i + 2];
+      const double nl = sqrt(nx * nx + ny * ny + nz * nz);
+      nx /= nl; ny /= nl; nz /= nl;
+    }
+    float lo = 0.0f, hi = r_max;
+    for (int32_t done = 0; done < iters;) {
+      const int levels = min(3, iters - done);
+      bool res = false;
+      if (valid && sub >= 1 && sub < (1 << levels)) {
+        float a = lo, b = hi;
+        const int depth = 31 - __clz(sub);  // bits of the node index below its leading one
+        for (int j = depth - 1; j >= 0; --j) {
+          const float m = 0.5f * (a + b);
+          if ((sub >> j) & 1)
+            a = m;
+          else
+            b = m;
+        }
+        res = tangent_ball_inside(M, sx, sy, sz, nx, ny, nz, 0.5f * (a + b), tol);
+      }
+      const unsigned long long mask = __ballot(res);  // every lane of the wavefront takes part
+      int node = 1;
+      for (int l = 0; l < levels; ++l) {
+        const float mid = 0.5f * (lo + hi);
+        const int bit = (int)((mask >> (gbase + node)) & 1ull);
+        if (bit)
+          lo = mid;
+        else
+          hi = mid;
+        node = 2 * node + bit;
+      }
+      done += levels;
+    }
+    if (valid && sub == 0) {
+      radius[i] = lo;
+      atomicAdd(M.row_queries + i, (unsigned long long)iters);
+    }
   }
-  radius[i] = lo;
-  atomicAdd(M.row_queries + i, (unsigned long long)iters);
 }
 
 __global__ void discard_kernel(MeshDev M, int64_t n_rows, int32_t* discarded) {
@@ -1611,7 +1659,7 @@ hipError_t launch_knn_eval(const KnnDev& G, const double* c, const float* Q, con
 hipError_t launch_tangent_ball(const MeshDev& M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius,
                                hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tangent_ball_kernel, dim3(blocks_for(n_rows, 64)), dim3(64), 0, s, M, n_rows, r_max, iters,
+  hipLaunchKernelGGL(tangent_ball_kernel, dim3(blocks_for(8 * n_rows, 64)), dim3(64), 0, s, M, n_rows, r_max, iters,
                      tol, radius);
   return hipGetLastError();
 }

@@ -150,7 +150,8 @@ def psd_leg(ctx):
     """The PSD estimator (Alg. 2) on its own workload: one untimed warm-up call,
     then one timed call (tangent balls, walks, gathers and products; inputs
     resident). Rooflines: the gather kernel against HBM (algorithmic bytes:
-    per pair six table rows read and five update rows written, per row three
+    per pair six table rows read (FP32) and, in the two-pass form, five FP64
+    update rows written and read back, per row three
     table rows), the symmetric rank-k products against the FP64 matrix peak
     (5 K (K+1) flops per pair)."""
     import torch
@@ -181,7 +182,8 @@ def psd_leg(ctx):
     # algorithmic bytes: per pair six table rows read (the two terminal
     # triangles) plus, in the two-pass form, five update rows written and read
     # back; per row three table rows (the sample's triangle); walk log entries
-    gbytes = n_pairs * ((6.0 if fused else 11.0) * K * 8 + 2 * 16) + n * 3.0 * K * 8
+    # (the table holds the FP32 basis values: 4 bytes per entry; update rows are FP64)
+    gbytes = n_pairs * (6.0 * K * 4 + (0.0 if fused else 10.0 * K * 8) + 2 * 16) + n * 3.0 * K * 4
     prod_tf = flops / (info["product_ms"] * 1e-3) / 1e12
     gath_ms = info["product_ms"] if fused else info["gather_ms"]
     gath = gbytes / (gath_ms * 1e-3) / 1e9

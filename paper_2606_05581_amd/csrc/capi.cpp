@@ -1312,7 +1312,8 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   const int64_t slices = std::max<int64_t>(1, std::min<int64_t>(1024, ((int64_t)1 << 28) / (nblk * 32768 * 4)));
   const int64_t n_slots = fused ? fused_slots : 4 * slices;
   float* d_rad = nullptr;
-  double *d_tab = nullptr, *d_S = nullptr, *d_Q = nullptr, *d_se = nullptr, *d_U = nullptr, *d_V = nullptr;
+  float* d_tab = nullptr;
+  double *d_S = nullptr, *d_Q = nullptr, *d_se = nullptr, *d_U = nullptr, *d_V = nullptr;
   double *d_PS = nullptr, *d_PQ = nullptr;
   hipEvent_t ev[6] = {};
   auto cleanup = [&](msk_status s) {
@@ -1352,7 +1353,7 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   for (hipEvent_t& e : ev) HIP_P(hipEventCreate(&e));
   hipStream_t s = ctx->stream;
   HIP_P(hipEventRecord(ev[0], s));
-  HIP_P(launch_fill_u64(d_tab, b->nv * K, 0, s));
+  HIP_P(launch_fill_u32(d_tab, b->nv * K, 0, s));
   HIP_P(launch_dense_table(b->d_rowptr, b->d_col, b->d_val, b->nv, K, d_tab, s));
   if (!fused) {  // the two-pass form adds into its slots call by call
     HIP_P(launch_fill_u64(d_PS, n_slots * nblk * 4096, 0, s));

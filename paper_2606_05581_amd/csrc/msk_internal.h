@@ -172,7 +172,7 @@ hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walk
 
 // PSD estimator (psd.hip): per-pair inputs of the rank-one updates
 struct PsdGather {
-  const double* tab;        // dense per-vertex basis table, n_verts x K
+  const float* tab;         // dense per-vertex basis table, n_verts x K (the basis values, FP32)
   int64_t K;
   int64_t Kp;               // row stride of the gathered update rows (K rounded up to 64)
   int64_t pairs;            // antithetic pairs per row
@@ -187,7 +187,7 @@ struct PsdGather {
   const float* log_bary;
 };
 hipError_t launch_dense_table(const int32_t* rowptr, const int32_t* col, const float* val, int64_t nv, int64_t K,
-                              double* tab, hipStream_t s);
+                              float* tab, hipStream_t s);
 hipError_t launch_psd_gather(const PsdGather& G, int64_t q0, int64_t nq, double* U, double* V, hipStream_t s);
 int64_t psd_blocks(int64_t Kp);
 // Fused gather + products (Kp <= 384): partial slots (one per workgroup column) of S and Q blocks; 0 = not available

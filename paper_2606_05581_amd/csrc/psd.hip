@@ -29,11 +29,11 @@ inline int grid_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs -
 // Dense per-vertex table (n_verts x K, zeroed beforehand) from the CSR basis:
 // one wavefront per vertex, lanes over its entries (coalesced).
 __global__ void dense_table_kernel(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                   const float* __restrict__ val, int64_t nv, int64_t K, double* __restrict__ tab) {
+                                   const float* __restrict__ val, int64_t nv, int64_t K, float* __restrict__ tab) {
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t v = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); v < nv; v += waves)
     for (int32_t e = rowptr[v] + (int32_t)(threadIdx.x & 63); e < rowptr[v + 1]; e += 64)
-      tab[v * K + col[e]] = (double)val[e];
+      tab[v * K + col[e]] = val[e];
 }
 
 // One workgroup per pair of the chunk [q0, q0 + nq); threads over columns.
@@ -332,7 +332,7 @@ __global__ void psd_se_kernel(const double* __restrict__ S, const double* __rest
 }  // namespace
 
 hipError_t launch_dense_table(const int32_t* rowptr, const int32_t* col, const float* val, int64_t nv, int64_t K,
-                              double* tab, hipStream_t s) {
+                              float* tab, hipStream_t s) {
   if (nv <= 0) return hipSuccess;
   hipLaunchKernelGGL(dense_table_kernel, dim3(grid_for(nv, 4)), dim3(256), 0, s, rowptr, col, val, nv, K, tab);
   return hipGetLastError();

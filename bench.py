@@ -38,9 +38,9 @@ def log(*a):
 
 
 def kernel_sources_sha():
-    csrc = os.path.join(ROOT, "paper_2606_05581_amd", "csrc")
-    return hashlib.sha256(open(os.path.join(csrc, "walk.hip"), "rb").read()
-                          + open(os.path.join(csrc, "msk_internal.h"), "rb").read()).hexdigest()[:16]
+    from paper_2606_05581_amd.build import walk_sources_sha
+
+    return walk_sources_sha()
 
 
 def laplace_sources_sha():
@@ -318,40 +318,67 @@ def knn_leg(ctx, walks=1024):
     return out
 
 
-def cpu_baseline(wl, target_s, max_threads=16, max_meshes=8):
-    """The oracle (FP64 walks, its own BVH) on a bounded sample of rows."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_threads():
+    """Threads the oracle may use: the process's CPU share (OMP_NUM_THREADS
+    where the host sets it, else 16), at most the CPUs it may run on."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    share = int(os.environ.get("OMP_NUM_THREADS", "16") or 16)
+    return max(1, min(share, avail)), avail
+
+
+def cpu_baseline(wl, target_s, max_meshes=8):
+    """The oracle (FP64 walks, its own BVH) on a bounded sample of rows, on
+    the process's CPU share and on one core."""
     from oracle import oracle as O
 
     O.build()
-    threads = max(1, min(max_threads, os.cpu_count() or 1))
+    threads, avail = cpu_threads()
     modes = [m == "exterior" for m in wl.modes]
     picks = np.unique(np.linspace(0, len(wl.cases) - 1, min(max_meshes, len(wl.cases))).astype(int))
     scenes = [(i, wl.cases[i], O.Scene(wl.cases[i].V, wl.cases[i].F, bvh=True)) for i in picks]
+    most = max(c.rows.n_rows for _, c, _ in scenes)
 
-    def run(rows_per_mesh):
+    def run(rows_per_mesh, nthreads):
         t0 = time.perf_counter()
         walks = 0
         for i, c, sc in scenes:
             sel = np.linspace(0, c.rows.n_rows - 1, min(rows_per_mesh, c.rows.n_rows)).astype(np.int32)
             for ext in modes:
                 r = O.estimate(sc, c.rows, c.basis, wl.walks, c.eps, c.h, exterior=ext, rows_sel=sel,
-                               nthreads=threads, mesh=int(i))
+                               nthreads=nthreads, mesh=int(i))
                 walks += int((r["discarded"] == 0).sum()) * wl.walks
         return walks, time.perf_counter() - t0
 
-    per_mesh = max(1, threads // len(scenes))
-    walks, dt = run(per_mesh)
-    # grow the sample until it takes about target_s (or covers every row)
-    while dt < 0.5 * target_s and per_mesh < max(c.rows.n_rows for _, c, _ in scenes):
-        rate = walks / max(dt, 1e-9)
-        per_mesh = int(min(max(2 * per_mesh, target_s * rate / (wl.walks * len(modes) * len(scenes))),
-                           max(c.rows.n_rows for _, c, _ in scenes)))
-        walks, dt = run(per_mesh)
+    def grow(nthreads, budget_s, per_mesh):
+        # grow the sample until it takes about budget_s (or covers every row)
+        walks, dt = run(per_mesh, nthreads)
+        while dt < 0.5 * budget_s and per_mesh < most:
+            rate = walks / max(dt, 1e-9)
+            per_mesh = int(min(max(2 * per_mesh, budget_s * rate / (wl.walks * len(modes) * len(scenes))), most))
+            walks, dt = run(per_mesh, nthreads)
+        return walks, dt, per_mesh
+
+    walks, dt, per_mesh = grow(threads, target_s, max(1, threads // len(scenes)))
+    walks1, dt1, per_mesh1 = grow(1, target_s / 3, 1)
     rows = sum(min(per_mesh, c.rows.n_rows) for _, c, _ in scenes)
+    rows1 = sum(min(per_mesh1, c.rows.n_rows) for _, c, _ in scenes)
     return {"value": walks / dt, "unit": "walks/s", "cores": threads, "kind": "oracle",
             "sample": f"{rows} rows (evenly spaced, {len(scenes)} of {len(wl.cases)} meshes) x {wl.walks} walks x "
-                      f"{len(modes)} operator(s) of {wl.name}; FP64 oracle with its BVH, {threads} OpenMP threads, "
-                      f"{dt:.1f} s"}
+                      f"{len(modes)} operator(s) of {wl.name}; FP64 oracle with its BVH, {threads} OpenMP threads "
+                      f"(the process's CPU share; {avail} CPUs visible), {dt:.1f} s",
+            "single_core": {"value": walks1 / dt1, "unit": "walks/s", "rows": rows1, "seconds": dt1},
+            "cpu_model": cpu_model(), "cpus_visible": avail,
+            "parallel_efficiency": (walks / dt) / (threads * walks1 / dt1)}
 
 
 def main():

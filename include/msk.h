@@ -296,8 +296,10 @@ typedef struct {
   int32_t mesh_id;       /* single-mesh estimates: the mesh index in the Philox
                             counter (a batch uses each mesh's position)       */
   int32_t accum;         /* persistent form, partial row sums of a chunk of
-                            walks kept in LDS: 0 = FP64, 1 = FP32 (mixed
-                            precision); rows are always accumulated in FP64  */
+                            walks kept in LDS: 0 = FP64, 1 = FP32 (plain
+                            blocked sums), 2 = compensated FP32 (a
+                            double-float pair per slot, TwoSum updates);
+                            rows are always accumulated in FP64          */
   int32_t jump_only;     /* exterior, point rows: 1 drops the killing term of
                             the exterior form (Sec. 3.3, exterior
                             Beurling-Deny form; the paper's default exterior
@@ -306,6 +308,17 @@ typedef struct {
 } msk_dtn_opts;
 
 void msk_dtn_opts_default(msk_dtn_opts* opts);
+
+/* Smallest admissible shell width for a mesh of bounding radius `radius`
+ * (msk_mesh_info.radius) under `opts` (NULL = defaults): every estimate
+ * (msk_estimate_dtn, its batched forms, msk_estimate_psd) requires
+ * eps > max(delta_rel R / (1 - kappa), 2^-18 R). Below the first term a walk
+ * at distance d < eps would take the step d (1 - kappa) - delta_rel R <= 0 and
+ * could cross the surface (Sec. 2: a WoS step stays inside the empty ball);
+ * below the second the FP32 scene-frame distance no longer resolves the
+ * shell. Host-only, no device work; NaN for radius <= 0, a non-finite radius
+ * or kappa outside [0, 1). */
+double msk_eps_floor(double radius, const msk_dtn_opts* opts);
 
 /* Estimate the DtN rows of one mesh (Alg. 1 in row form).
  *   walks:  walks per row W (the first batch when se_target > 0);
@@ -322,7 +335,8 @@ void msk_dtn_opts_default(msk_dtn_opts* opts);
  * row's predicted deficit q(1-q)/se_target^2 - W_i rounded up (at least
  * `walks`, at most doubling W_i), up to walks_max; walk indices continue
  * the row's Philox walk counter.
- * Errors: INVALID_ARG for walks < 2, eps <= 0, inset_h <= eps, or rows /
+ * Errors: INVALID_ARG for walks < 2, eps <= msk_eps_floor(R, opts),
+ * inset_h <= eps, kappa outside [0, 1/2), delta_rel outside [0, 1/4), or rows /
  * basis built for a mesh with a different vertex count. Any K is accepted
  * (K == n_rows is needed only by msk_steklov_modes). NUMERIC when an entry
  * of S or se is NaN or infinite (e.g. basis values beyond the FP32 range of
@@ -485,7 +499,9 @@ void msk_psd_opts_default(msk_psd_opts* opts);
 typedef struct {
   int64_t n_rows, K, pairs;
   int64_t walks_total;     /* walks run (2 x pairs per row with a tangent ball) */
-  int64_t queries_total;   /* bisection and walk queries                       */
+  int64_t queries_total;   /* closest-point queries issued: the bisection's
+                              bounded queries (up to 7 per round of three
+                              levels) and the walks' queries                 */
   int64_t escaped_total, capped_total;
   int64_t dropped_rows;    /* rows without a tangent ball (radius 0)           */
   double mean_radius;      /* over rows with a tangent ball                    */
@@ -526,8 +542,9 @@ typedef struct {  /* optional host walk log, n_rows x 2 pairs entries each    */
  * S = sum of X (K x K, symmetric PSD by construction) and se = its standard
  * error, the n_rows x pairs pair terms taken as independent draws:
  * se^2 = (n Q - S^2)/(n - 1), Q = sum of X*X elementwise. The sums are FP64:
- * the difference rows are gathered from a dense FP64 copy of the basis table
- * and multiplied on the matrix cores (FP64 MFMA, symmetric rank-k blocks);
+ * the difference rows are gathered from a dense FP32 copy of the basis table
+ * (promoted exactly to FP64) and multiplied on the matrix cores (FP64 MFMA,
+ * symmetric rank-k blocks);
  * for K <= 384 both happen in one kernel with the rows kept in LDS.
  *   S, se:  host, K x K doubles (se may be NULL);
  *   radius: host, n_rows floats (tangent radii, 0 = dropped) or NULL;
@@ -535,11 +552,12 @@ typedef struct {  /* optional host walk log, n_rows x 2 pairs entries each    */
  * Ball points next to s lie within eps of the surface and their walks end at
  * once, so a coarse shell biases the estimate low (on a unit sphere eps =
  * 1e-3 gives about 1% less than eps <= 1e-4): use eps well below the
- * finite-difference estimator's inset (the paper runs at 1e-6).
+ * finite-difference estimator's inset (the paper runs at 1e-6; here eps
+ * must exceed msk_eps_floor, 2^-18 R by default).
  * walk_opts: seed, max_steps, kappa, delta_rel, form, launch settings and
  * mesh_id as for msk_estimate_dtn (walk_offset, se_target, record_log and
  * collect_stats are ignored). Errors: INVALID_ARG for hat rows, pairs < 1,
- * K > 8192, eps <= 0, a basis for another vertex count or a flat mesh;
+ * K > 8192, eps <= msk_eps_floor(R, walk_opts), a basis for another vertex count or a flat mesh;
  * NUMERIC (outputs written) when an entry is not finite. */
 msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* mesh, const msk_rows* rows, const msk_basis* basis,
                             int64_t pairs, double eps, const msk_dtn_opts* walk_opts, const msk_psd_opts* opts,

@@ -1,4 +1,5 @@
 """Build libmsk.so (the HIP/gfx950 walk library) in-tree with hipcc."""
+import hashlib
 import os
 import subprocess
 import sys
@@ -21,13 +22,25 @@ HIPCC_FLAGS = [
 ]
 
 
+def walk_sources_sha() -> str:
+    """Revision of the walk kernels: a hash of their sources. Autotuner
+    results and measured traffic records are keyed by it, so that any edit
+    of the kernels invalidates them."""
+    h = hashlib.sha256()
+    for name in ("walk.hip", "msk_internal.h"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     """Compile every source into `out` (default: the in-tree libmsk.so);
     `defines` are extra NAME=VALUE macros (kernel tuning constants)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = out + ".tmp"
-    cmd = ([hipcc] + HIPCC_FLAGS + ["-D" + d for d in defines] + [os.path.join(CSRC, s) for s in SOURCES] + LIBS +
-           ["-o", tmp])
+    rev = ['-DMSK_WALK_SRC_SHA="%s"' % walk_sources_sha()]
+    cmd = ([hipcc] + HIPCC_FLAGS + rev + ["-D" + d for d in defines] + [os.path.join(CSRC, s) for s in SOURCES] +
+           LIBS + ["-o", tmp])
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -543,6 +543,17 @@ extern "C" void msk_dtn_opts_default(msk_dtn_opts* o) {
   o->accum = 0;
 }
 
+extern "C" double msk_eps_floor(double radius, const msk_dtn_opts* opts) {
+  msk_dtn_opts o;
+  msk_dtn_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(radius > 0.0) || !std::isfinite(radius) || !(o.kappa >= 0.0 && o.kappa < 1.0)) return NAN;
+  // a walk at distance d steps by d (1 - kappa) - delta_rel R, which stays
+  // positive only for d > delta_rel R / (1 - kappa); below 2^-18 R the FP32
+  // distance of the scene frame no longer resolves the shell
+  return std::max(o.delta_rel * radius / (1.0 - o.kappa), std::ldexp(radius, -18));
+}
+
 namespace {
 
 void dtn_free(msk_dtn* d) {
@@ -567,7 +578,7 @@ struct Prepared {
 };
 
 msk_status check_problem(msk_ctx* ctx, const msk_mesh* m, const msk_rows* r, const msk_basis* b, int64_t walks,
-                         double eps, double h, int32_t side, bool row_sums = true) {
+                         double eps, double h, int32_t side, const msk_dtn_opts* o, bool row_sums = true) {
   if (!m || !r || !b) return fail(ctx, MSK_ERR_INVALID_ARG, "null mesh / rows / basis");
   if (r->mesh != m) return fail(ctx, MSK_ERR_INVALID_ARG, "rows were created for another mesh");
   if (b->nv != m->nv) return fail(ctx, MSK_ERR_INVALID_ARG, "basis vertex count differs from the mesh's");
@@ -577,6 +588,13 @@ msk_status check_problem(msk_ctx* ctx, const msk_mesh* m, const msk_rows* r, con
     return fail(ctx, MSK_ERR_INVALID_ARG, "the walk estimators take at most 32 basis entries per vertex");
   if (walks < 2 || walks > INT32_MAX) return fail(ctx, MSK_ERR_INVALID_ARG, "walks must be in 2..2^31-1");
   if (!(eps > 0) || !(h > eps) || !std::isfinite(h)) return fail(ctx, MSK_ERR_INVALID_ARG, "need 0 < eps < inset_h");
+  if (o && !(o->kappa >= 0.0 && o->kappa < 0.5 && o->delta_rel >= 0.0 && o->delta_rel < 0.25))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "need 0 <= kappa < 1/2 and 0 <= delta_rel < 1/4");
+  const double floor_eps = msk_eps_floor(m->radius, o);
+  if (!(eps > floor_eps))
+    return fail(ctx, MSK_ERR_INVALID_ARG,
+                "eps must exceed " + std::to_string(floor_eps) + " for this mesh (msk_eps_floor: the step guard "
+                "delta_rel R / (1 - kappa) and the FP32 distance resolution 2^-18 R)");
   if (side != MSK_INTERIOR && side != MSK_EXTERIOR) return fail(ctx, MSK_ERR_INVALID_ARG, "side must be 0 or 1");
   return MSK_OK;
 }
@@ -717,7 +735,7 @@ static msk_status run_walks(msk_ctx* ctx, const std::vector<MeshDev>& meshes, co
   L.regen_min = std::min(64, std::max(1, o.regen_min));
   L.use_lds_top = use_lds_top;
   L.n_top = n_top;
-  L.accum_f32 = o.accum == 1 ? 1 : 0;
+  L.accum = o.accum;
   for (const MeshDev& md : meshes) L.knn |= md.knn.k > 0 ? 1 : 0;
   if (o.collect_stats) {
     HIP_TRY(ctx, dalloc(&lb.d_stats, 3));
@@ -788,13 +806,14 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
                                        const msk_dtn_opts* opts, msk_dtn** out) {
   if (!ctx || !out) return MSK_ERR_INVALID_ARG;
   *out = nullptr;
-  msk_status st = check_problem(ctx, m, r, b, walks, eps, inset_h, side);
-  if (st != MSK_OK) return st;
   msk_dtn_opts o;
   msk_dtn_opts_default(&o);
   if (opts) o = *opts;
+  msk_status st = check_problem(ctx, m, r, b, walks, eps, inset_h, side, &o);
+  if (st != MSK_OK) return st;
   if (o.form != MSK_FORM_PLAIN && o.form != MSK_FORM_PERSISTENT) return fail(ctx, MSK_ERR_INVALID_ARG, "bad form");
-  if (o.accum != 0 && o.accum != 1) return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64) or 1 (FP32)");
+  if (o.accum < 0 || o.accum > 2)
+    return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64), 1 (FP32) or 2 (compensated FP32)");
   if (o.jump_only != 0 && (o.jump_only != 1 || side != MSK_EXTERIOR || r->mode != MSK_ROWS_POINT))
     return fail(ctx, MSK_ERR_INVALID_ARG, "jump_only takes exterior estimates with point rows");
   if (o.collect_stats && b && b->knn_mesh)
@@ -984,7 +1003,7 @@ static hipError_t enqueue_batch(msk_batch* B, hipStream_t s, int part) {
     L.queue_end = B->lb.d_qend;
     L.chunk = std::max(1, B->o.chunk);
     L.regen_min = std::min(64, std::max(1, B->o.regen_min));
-    L.accum_f32 = B->o.accum == 1 ? 1 : 0;
+    L.accum = B->o.accum;
     for (const MeshDev& md : B->md) L.knn |= md.knn.k > 0 ? 1 : 0;
     for (msk_dtn* d : B->dtns) L.n_slots += d->n;
     if (B->o.collect_stats) L.stats = B->lb.d_stats;
@@ -1019,13 +1038,14 @@ extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk
   if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32) ||
       (o.se_target > 0 && o.walk_offset + o.walks_max > ((int64_t)1 << 32)))
     return fail(ctx, MSK_ERR_INVALID_ARG, "walk indices must fit in 32 bits");
-  if (o.accum != 0 && o.accum != 1) return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64) or 1 (FP32)");
+  if (o.accum < 0 || o.accum > 2)
+    return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64), 1 (FP32) or 2 (compensated FP32)");
   for (int32_t i = 0; i < n_meshes; ++i) {
     if (o.collect_stats && bases[i] && bases[i]->knn_mesh)
       return fail(ctx, MSK_ERR_INVALID_ARG, "traversal statistics are not collected with the point basis");
     if (o.jump_only != 0 && (o.jump_only != 1 || side != MSK_EXTERIOR || !rows[i] || rows[i]->mode != MSK_ROWS_POINT))
       return fail(ctx, MSK_ERR_INVALID_ARG, "jump_only takes exterior estimates with point rows");
-    msk_status st = check_problem(ctx, meshes[i], rows[i], bases[i], walks, eps[i], inset_h[i], side);
+    msk_status st = check_problem(ctx, meshes[i], rows[i], bases[i], walks, eps[i], inset_h[i], side, &o);
     if (st != MSK_OK) return fail(ctx, st, "mesh " + std::to_string(i) + ": " + ctx->err);
   }
   msk_batch* B = new msk_batch();
@@ -1285,7 +1305,7 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   const int64_t W = 2 * pairs;
   // the walk problem: interior walks; the inset is not used by ball starts
   if (walk_opts && walk_opts->jump_only) return fail(ctx, MSK_ERR_INVALID_ARG, "jump_only applies to exterior estimates");
-  msk_status st = check_problem(ctx, m, r, b, W, eps, 2.0 * eps, MSK_INTERIOR, false);
+  msk_status st = check_problem(ctx, m, r, b, W, eps, 2.0 * eps, MSK_INTERIOR, &o, false);
   if (st != MSK_OK) return st;
   double r_max = po.r_max;
   if (!(r_max > 0.0)) {  // half the shortest side of the bounding box (Appendix A, unbounded tangent balls)
@@ -1539,9 +1559,13 @@ extern "C" msk_status msk_mesh_rebuild(msk_ctx* ctx, msk_mesh* m, int32_t leaf) 
   return MSK_OK;
 }
 
-// Cached tuning results are keyed by the walk kernel's design revision, the
-// device's CU count and the workload's shape.
-constexpr const char* kTuneKernel = "stream-2";
+// Cached tuning results are keyed by the walk kernels' revision (a hash of
+// their sources, set by the build), the device's CU count and the workload's
+// shape, so an edit of the kernels forces a new search.
+#ifndef MSK_WALK_SRC_SHA
+#define MSK_WALK_SRC_SHA "unversioned"
+#endif
+constexpr const char* kTuneKernel = MSK_WALK_SRC_SHA;
 
 static std::string tune_signature(const msk_ctx* ctx, int32_t n, msk_mesh* const* meshes, const msk_rows* const* rows,
                                   int32_t side) {
@@ -1565,7 +1589,8 @@ extern "C" msk_status msk_autotune(msk_ctx* ctx, int32_t n, msk_mesh* const* mes
   if (space) sp = *space;
   if (sp.trial_walks < 2 || sp.trial_rows < 1) return fail(ctx, MSK_ERR_INVALID_ARG, "bad trial size");
   for (int32_t i = 0; i < n; ++i) {
-    msk_status st = check_problem(ctx, meshes[i], rows[i], bases[i], sp.trial_walks, eps[i], inset_h[i], side);
+    msk_status st = check_problem(ctx, meshes[i], rows[i], bases[i], sp.trial_walks, eps[i], inset_h[i], side,
+                                   nullptr);
     if (st != MSK_OK) return st;
   }
   std::memset(out, 0, sizeof(*out));

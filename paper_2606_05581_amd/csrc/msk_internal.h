@@ -143,7 +143,8 @@ struct WalkLaunch {
   int32_t use_lds_top;         // single-mesh launch: stage mesh 0's top nodes in LDS
   int32_t n_top;
   unsigned long long* stats;   // optional: [nodes visited, triangles tested, FP32 operations]
-  int32_t accum_f32;           // persistent form: FP32 partial sums in the wavefront row tables
+  int32_t accum;               // persistent form, wavefront row-table partial sums:
+                               // 0 FP64, 1 FP32, 2 compensated FP32 (double-float pairs)
   int32_t knn;                 // some mesh uses the point basis: launch the k-NN instantiations
 };
 

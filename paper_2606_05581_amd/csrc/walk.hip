@@ -740,7 +740,8 @@ __device__ void walk_finish_global(const WalkLaunch& L, const MeshDev& M, const 
 // chunk's last walk has finished, the wavefront flushes the table into the
 // FP64 row with one device atomic per distinct column. AccT = double keeps
 // the partial sums in FP64; AccT = float keeps them in FP32 (a chunk holds at
-// most `chunk` walks) and flushes them into the FP64 rows.
+// most `chunk` walks) and flushes them into the FP64 rows; AccT = CompF32
+// keeps them as compensated FP32 pairs.
 // Row-table slots per wavefront table (2^bits) and the occupancy the
 // persistent kernels are compiled for: with 64 slots, the cooperative leaf
 // scratch and 21 LDS-staged top nodes a workgroup holds 29.8 KB of LDS.
@@ -752,6 +753,51 @@ __device__ void walk_finish_global(const WalkLaunch& L, const MeshDev& M, const 
 #endif
 constexpr int kSlotBits = MSK_TABLE_SLOT_BITS, kSlots = 1 << kSlotBits, kProbes = 8, kWaves = 4;
 constexpr int32_t kEmptyKey = -1;
+
+// Compensated FP32 partial sum: the value is hi + lo, a double-float pair.
+// An addition of x = xh + xl (the FP64 contribution split into two floats)
+// forms s = fl(hi + xh) and its exact rounding error e by Knuth's TwoSum,
+// then lo += e + xl; the pair is one 64-bit LDS word replaced by
+// compare-and-swap, so concurrent lanes on one slot serialise and none is
+// lost. The sum's error is then of order u^2 n max|x| plus u |sum| for the
+// final rounding of lo, instead of u n max|x| for a plain FP32 sum (u =
+// 2^-24, n terms).
+struct CompF32 {
+  float hi, lo;
+};
+
+template <typename AccT>
+__device__ __forceinline__ AccT acc_zero() {
+  return (AccT)0;
+}
+template <>
+__device__ __forceinline__ CompF32 acc_zero<CompF32>() {
+  return CompF32{0.0f, 0.0f};
+}
+__device__ __forceinline__ double acc_value(double a) { return a; }
+__device__ __forceinline__ double acc_value(float a) { return (double)a; }
+__device__ __forceinline__ double acc_value(CompF32 a) { return (double)a.hi + (double)a.lo; }
+
+__device__ __forceinline__ void lds_acc_add(double* p, double v) { atomicAdd(p, v); }
+__device__ __forceinline__ void lds_acc_add(float* p, double v) { atomicAdd(p, (float)v); }
+__device__ __forceinline__ void lds_acc_add(CompF32* p, double v) {
+#pragma clang fp contract(off)
+  const float xh = (float)v;
+  const float xl = (float)(v - (double)xh);
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  unsigned long long old = __atomic_load_n(q, __ATOMIC_RELAXED), seen;
+  do {
+    seen = old;
+    const float hi = __uint_as_float((uint32_t)seen), lo = __uint_as_float((uint32_t)(seen >> 32));
+    const float sum = hi + xh;
+    const float bv = sum - hi;
+    const float err = (hi - (sum - bv)) + (xh - bv);
+    const float nlo = lo + (err + xl);
+    const unsigned long long nw =
+        (unsigned long long)__float_as_uint(sum) | ((unsigned long long)__float_as_uint(nlo) << 32);
+    old = atomicCAS(q, seen, nw);
+  } while (old != seen);
+}
 
 template <typename AccT>
 struct WaveTables {
@@ -770,8 +816,8 @@ __device__ __forceinline__ void table_add(WaveTables<AccT>& T, int wi, int t, in
     const uint32_t si = (h + (uint32_t)p) & (kSlots - 1);
     const int32_t old = atomicCAS(&T.key[wi][t][si], kEmptyKey, j);
     if (old == kEmptyKey || old == j) {
-      atomicAdd(&T.v1[wi][t][si], (AccT)v);
-      atomicAdd(&T.v2[wi][t][si], (AccT)(v * v));
+      lds_acc_add(&T.v1[wi][t][si], v);
+      lds_acc_add(&T.v2[wi][t][si], v * v);
       return;
     }
   }
@@ -802,11 +848,11 @@ __device__ void table_flush(const WalkLaunch& L, WaveTables<AccT>& T, int wi, in
   for (int i = (int)__lane_id(); i < kSlots; i += 64) {
     const int32_t j = T.key[wi][t][i];
     if (j != kEmptyKey) {
-      atomicAdd(a1 + j, (double)T.v1[wi][t][i]);
-      atomicAdd(a2 + j, (double)T.v2[wi][t][i]);
+      atomicAdd(a1 + j, acc_value(T.v1[wi][t][i]));
+      atomicAdd(a2 + j, acc_value(T.v2[wi][t][i]));
       T.key[wi][t][i] = kEmptyKey;
-      T.v1[wi][t][i] = (AccT)0;
-      T.v2[wi][t][i] = (AccT)0;
+      T.v1[wi][t][i] = acc_zero<AccT>();
+      T.v2[wi][t][i] = acc_zero<AccT>();
     }
   }
   if (__lane_id() == 0) {
@@ -982,8 +1028,8 @@ __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kern
   CoopScratch* W = &coop[wi];
   for (int i = threadIdx.x; i < kWaves * 2 * kSlots; i += blockDim.x) {
     (&T.key[0][0][0])[i] = kEmptyKey;
-    (&T.v1[0][0][0])[i] = (AccT)0;
-    (&T.v2[0][0][0])[i] = (AccT)0;
+    (&T.v1[0][0][0])[i] = acc_zero<AccT>();
+    (&T.v2[0][0][0])[i] = acc_zero<AccT>();
   }
   for (int i = threadIdx.x; i < kWaves * 2 * 3; i += blockDim.x) (&T.cnt[0][0][0])[i] = 0;
   int32_t n_lds = 0;
@@ -1370,7 +1416,7 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
 // Whether the ball of radius r touching s from the inside is accepted (the
 // test of one bisection step).
 __device__ bool tangent_ball_inside(const MeshDev& M, float sx, float sy, float sz, double nx, double ny, double nz,
-                                    float mid, float tol) {
+                                    float mid, float tol, uint32_t& issued) {
   const double cxd = sx - mid * nx, cyd = sy - mid * ny, czd = sz - mid * nz;
   const float cx = (float)cxd, cy = (float)cyd, cz = (float)czd;
   const float t = mid - fminf(tol, mid * 0x1p-10f);
@@ -1378,7 +1424,10 @@ __device__ bool tangent_ball_inside(const MeshDev& M, float sx, float sy, float 
   Nearest h;
   h.d2 = bound; h.orig = INT_MAX; h.slot = -1;
   TravCount cnt;
-  if (t > 0.0f) bvh_nearest<false, true>(M.nodes, M.tris, nullptr, 0, cx, cy, cz, M.radius, h, cnt, t);
+  if (t > 0.0f) {
+    bvh_nearest<false, true>(M.nodes, M.tris, nullptr, 0, cx, cy, cz, M.radius, h, cnt, t);
+    ++issued;
+  }
   const bool empty = h.orig == INT_MAX || sqrtf(h.d2) >= t;
   return empty && sqrt(cxd * cxd + cyd * cyd + czd * czd) + mid <= M.radius_d;
 }
@@ -1391,7 +1440,8 @@ __device__ bool tangent_ball_inside(const MeshDev& M, float sx, float sy, float 
 // formed by the same float operations as in the sequential loop, so the
 // radius is the same; the rounds of dependent queries drop from iters to
 // ceil(iters / 3), and eight lanes per row fill the GPU with 16,384 rows.
-// row_queries counts the iters decisions of the bisection.
+// row_queries counts the bounded queries the lanes issue (up to seven per
+// round of three levels, so more than the iters decisions they serve).
 __global__ void __launch_bounds__(64) tangent_ball_kernel(MeshDev M, int64_t n_rows, float r_max, int32_t iters,
                                                           float tol, float* radius) {
   const int lane = threadIdx.x & 63, sub = lane & 7, gbase = lane & ~7;
@@ -1409,6 +1459,7 @@ __global__ void __launch_bounds__(64) tangent_ball_kernel(MeshDev M, int64_t n_r
       nx /= nl; ny /= nl; nz /= nl;
     }
     float lo = 0.0f, hi = r_max;
+    uint32_t issued = 0;
     for (int32_t done = 0; done < iters;) {
       const int levels = min(3, iters - done);
       bool res = false;
@@ -1422,7 +1473,7 @@ __global__ void __launch_bounds__(64) tangent_ball_kernel(MeshDev M, int64_t n_r
           else
             b = m;
         }
-        res = tangent_ball_inside(M, sx, sy, sz, nx, ny, nz, 0.5f * (a + b), tol);
+        res = tangent_ball_inside(M, sx, sy, sz, nx, ny, nz, 0.5f * (a + b), tol, issued);
       }
       const unsigned long long mask = __ballot(res);  // every lane of the wavefront takes part
       int node = 1;
@@ -1437,10 +1488,8 @@ __global__ void __launch_bounds__(64) tangent_ball_kernel(MeshDev M, int64_t n_r
       }
       done += levels;
     }
-    if (valid && sub == 0) {
-      radius[i] = lo;
-      atomicAdd(M.row_queries + i, (unsigned long long)iters);
-    }
+    if (valid && sub == 0) radius[i] = lo;
+    if (valid && issued) atomicAdd(M.row_queries + i, (unsigned long long)issued);
   }
 }
 
@@ -1578,16 +1627,24 @@ hipError_t launch_walk_plain(const WalkLaunch& L, hipStream_t s) {
 
 hipError_t launch_walk_persistent(const WalkLaunch& L, int grid, hipStream_t s) {
   if (L.knn && L.stats) return hipErrorInvalidValue;  // the point basis has no counting instantiation
+  if (L.accum < 0 || L.accum > 2) return hipErrorInvalidValue;
   if (L.knn) {  // point basis: instantiations carrying the k-NN evaluation
-    if (L.accum_f32)
+    if (L.accum == 1)
       hipLaunchKernelGGL((walk_stream_kernel<false, float, true>), dim3(grid), dim3(256), 0, s, L);
+    else if (L.accum == 2)
+      hipLaunchKernelGGL((walk_stream_kernel<false, CompF32, true>), dim3(grid), dim3(256), 0, s, L);
     else
       hipLaunchKernelGGL((walk_stream_kernel<false, double, true>), dim3(grid), dim3(256), 0, s, L);
-  } else if (L.accum_f32) {
+  } else if (L.accum == 1) {
     if (L.stats)
       hipLaunchKernelGGL((walk_stream_kernel<true, float>), dim3(grid), dim3(256), 0, s, L);
     else
       hipLaunchKernelGGL((walk_stream_kernel<false, float>), dim3(grid), dim3(256), 0, s, L);
+  } else if (L.accum == 2) {
+    if (L.stats)
+      hipLaunchKernelGGL((walk_stream_kernel<true, CompF32>), dim3(grid), dim3(256), 0, s, L);
+    else
+      hipLaunchKernelGGL((walk_stream_kernel<false, CompF32>), dim3(grid), dim3(256), 0, s, L);
   } else {
     if (L.stats)
       hipLaunchKernelGGL((walk_stream_kernel<true, double>), dim3(grid), dim3(256), 0, s, L);

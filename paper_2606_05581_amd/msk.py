@@ -145,6 +145,7 @@ SIGNATURES = {
     "msk_basis_eval_knn": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
                            C.c_int),
     "msk_dtn_opts_default": ([C.POINTER(DtnOpts)], None),
+    "msk_eps_floor": ([C.c_double, C.POINTER(DtnOpts)], C.c_double),
     "msk_estimate_dtn": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_int32,
                           C.POINTER(DtnOpts), C.POINTER(C.c_void_p)], C.c_int),
     "msk_estimate_dtn_batched": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),

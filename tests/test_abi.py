@@ -56,3 +56,28 @@ def test_opts_defaults_and_errors_without_device():
     h = ctypes.c_void_p()
     assert msk.lib().msk_create(0, None, None) == msk.ERR_INVALID_ARG
     assert msk.lib().msk_estimate_dtn(None, None, None, None, 16, 1e-3, 0.05, 0, None, ctypes.byref(h)) != msk.OK
+
+
+def test_eps_floor_covers_the_step_guard_and_fp32_resolution():
+    """The shell must be wider than the step guard delta_rel R / (1 - kappa)
+    (else a walk inside the shell could take a step of negative length and
+    cross the surface) and than the FP32 resolution 2^-18 R of the scene
+    frame; the floor scales with the mesh radius."""
+    from paper_2606_05581_amd import msk
+
+    L = msk.lib()
+    o = msk.DtnOpts()
+    L.msk_dtn_opts_default(ctypes.byref(o))
+    for R in [1.0, 2.5, 1e3]:
+        f = L.msk_eps_floor(R, ctypes.byref(o))
+        assert f == max(o.delta_rel * R / (1 - o.kappa), R * 2.0 ** -18)
+        assert f == L.msk_eps_floor(R, None)
+        # a walk just outside the floor takes a positive step
+        d = f * (1 + 1e-9)
+        assert d * (1 - o.kappa) - o.delta_rel * R > 0
+    # the header's example: eps = 1e-6 is refused on a mesh of radius > 0.262
+    assert L.msk_eps_floor(0.25, None) < 1e-6 < L.msk_eps_floor(0.3, None)
+    o.delta_rel = 2.0 ** -12  # a larger guard dominates
+    assert L.msk_eps_floor(1.0, ctypes.byref(o)) == pytest.approx(2.0 ** -12 / (1 - o.kappa), rel=1e-15)
+    assert L.msk_eps_floor(0.0, None) != L.msk_eps_floor(0.0, None)  # NaN
+    assert L.msk_eps_floor(float("inf"), None) != L.msk_eps_floor(float("inf"), None)

@@ -76,5 +76,6 @@ def test_eigen_krylov_path_soup2000(ctx):
     """2,000 rows (restarted block Krylov path), k = 32."""
     wl = W.soup8_53k()
     ev, ref, err, res, st = _check(ctx, wl.cases[0], 128, 32, False, "soup8 N=2000 interior")
-    # products with C are FP32: eigenvalues to ~1e-6 |C| once converged
-    assert err < 2e-5 and res < 2e-4
+    # products with C are FP32, the basis and Rayleigh quotients FP64: eigenvalues within 1e-6 |C|
+    # of LAPACK (measured 2e-8 to 9e-8 on the full-size estimates)
+    assert err < 1e-6 and res < 2e-4

@@ -246,3 +246,55 @@ def test_nonfinite_estimate_reports_numeric(ctx):
     with pytest.raises(msk.MskError) as ee:
         ctx.steklov_modes(r, 4)
     assert ee.value.status == msk.ERR_NUMERIC
+
+
+@pytest.mark.parametrize("exterior", [False, True])
+def test_capped_walks_parity(ctx, oracle_mod, exterior):
+    """A step cap of 4 ends most walks CAPPED: each ends at the nearest surface
+    point of its last position and is counted. The GPU's capped walks, their
+    terminal triangles and query counts follow the oracle's walk for walk,
+    and the entries stay within 4 combined standard errors."""
+    wl = W.soup8_53k(N=200, walks=64)
+    case = wl.cases[0]
+    label = f"soup8 N=200 capped at 4 steps {'exterior' if exterior else 'interior'}"
+    print(f"[{label}] start", flush=True)
+    g = _gpu_estimate(ctx, case, wl.walks, exterior, max_steps=4)
+    sc = oracle_mod.Scene(case.V, case.F, bvh=True)
+    r = oracle_mod.estimate(sc, case.rows, case.basis, wl.walks, case.eps, case.h, exterior=exterior, log=True,
+                            max_steps=4)
+    S, se = oracle_mod.finalize(r["acc"], r["acc2"], case.rows.w, case.h, wl.walks, r["discarded"])
+    r.update(S=S, se=se)
+    viol, div = _parity_report(g, r, label, case)
+    ran = r["log_status"] >= 0
+    capped_o = (r["log_status"] == oracle_mod.CAPPED)[ran].mean()
+    capped_g = (g["status"] == oracle_mod.CAPPED)[ran].mean()
+    print(f"[{label}] capped walks: GPU {capped_g:.2%}, oracle {capped_o:.2%}; "
+          f"per-row counts GPU {int(g['cap'].sum())}, oracle {int(r['n_capped'].sum())}", flush=True)
+    assert capped_o > 0.3  # the cap is exercised
+    assert viol.sum() == 0
+    assert div < 0.01
+    assert abs(capped_g - capped_o) <= 0.01
+    assert int(g["cap"].sum()) == int((g["status"] == oracle_mod.CAPPED).sum())
+    # a capped walk makes exactly max_steps + 1 queries (the cap's query included)
+    assert np.all(g["nq"][g["status"] == oracle_mod.CAPPED] == 5)
+
+
+def test_eps_at_the_floor_is_refused(ctx):
+    """eps must exceed msk_eps_floor(R): at the floor a walk inside the shell
+    could take a step of non-positive length. On a sphere of radius 3 the
+    default floor is the FP32 resolution 3 * 2^-18."""
+    from paper_2606_05581_amd import msk
+
+    V, F = W.icosphere_recursive(2)
+    case = W._point_case(3.0 * V, F, 64, np.random.default_rng(5))
+    mesh = ctx.build_bvh(case.V, case.F)
+    rows = ctx.rows(mesh, case.rows)
+    basis = ctx.basis(case.basis, case.V.shape[0])
+    R = mesh.info()["radius"]
+    floor = msk.lib().msk_eps_floor(R, None)
+    assert floor == R * 2.0 ** -18
+    with pytest.raises(msk.MskError) as ei:
+        ctx.estimate_dtn(mesh, rows, basis, 8, floor, case.h)
+    assert ei.value.status == msk.ERR_INVALID_ARG and "eps must exceed" in str(ei.value)
+    d = ctx.estimate_dtn(mesh, rows, basis, 8, floor * 1.01, case.h)
+    assert d.info()["walks_total"] > 0

@@ -7,7 +7,8 @@ FP64 ones, so a few rows and walks diverge; the bar is:
   * terminal triangles of the walks identical for at least 97% of walks;
   * every entry of S within 4 combined standard errors (plus 1e-9 |S|) of the
     oracle's, S symmetric positive semidefinite;
-  * on the unit sphere, degree <= 2 harmonics match the capped Steklov form.
+  * on the unit sphere, the zero-cap limit of degree-1 harmonics matches the
+    Steklov form of linear data on the polyhedron.
 """
 import math
 
@@ -90,19 +91,52 @@ def test_psd_soup_parity(ctx, oracle_mod):
     assert g["info"]["escaped_total"] == 0
 
 
-def test_psd_unit_sphere_closed_form_and_parity(ctx, oracle_mod):
+def test_psd_unit_sphere_parity(ctx, oracle_mod):
     V, F = W.icosphere_recursive(4)
     V = V / np.linalg.norm(V, axis=1, keepdims=True)
     rows = W.point_rows(V, F, 1500, np.random.default_rng(21))
     tab, deg = _sh_l2(V)
     g, o = _run_both(ctx, oracle_mod, V.astype(np.float32), F, rows, tab, 64, 1e-4, seed=3)
     _check_parity(g, o, 1.0, "unit sphere K=9")
-    S, se = g["S"], g["se"]
-    t0 = math.radians(2.5)
-    rbar = float(np.mean(g["radius"]))
-    want = {l: l - 0.5 * math.sin(0.5 * t0) * l * (l + 1) * rbar for l in (1, 2)}
-    for i in range(1, 9):
-        assert abs(S[i, i] - want[deg[i]]) <= 4 * se[i, i] + 0.03 * want[deg[i]], (i, S[i, i], want[deg[i]])
+
+
+def test_psd_unit_sphere_zero_cap_limit(ctx):
+    """The estimate leaves out a cap about each sample; its share has no closed
+    form on a polyhedron (walks from cap points inside the domain spread their
+    exit points), but the zero-cap limit is the Steklov form. Richardson
+    extrapolation 2 S(2.5 deg) - S(5 deg) on common streams, over 64 seeds,
+    on the level-4 icosphere: the degree-1 entries equal the exact form of
+    linear data on the polyhedron, (3 / (4 pi)) Vol, within 4 standard errors
+    of the seed mean plus 0.5% for the cap's second-order term; the off-diagonal
+    entries of all nine harmonics vanish (the icosahedral group acts
+    irreducibly on each degree, so the form is diagonal there)."""
+    V, F = W.icosphere_recursive(4)
+    V = V / np.linalg.norm(V, axis=1, keepdims=True)
+    rows = W.point_rows(V, F, 1500, np.random.default_rng(21))
+    tab, deg = _sh_l2(V)
+    A, B, C = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    exact = 3.0 / (4 * math.pi) * abs(np.einsum("ij,ij->i", A, np.cross(B, C)).sum() / 6.0)
+    mesh = ctx.build_bvh(V.astype(np.float32), F)
+    rh = ctx.rows(mesh, rows)
+    bh = ctx.basis(_dense_basis(tab), V.shape[0])
+    lim = []
+    for seed in range(64):
+        a = ctx.estimate_psd(mesh, rh, bh, 256, 1e-5, seed=900 + seed, cap_deg=2.5)["S"]
+        b = ctx.estimate_psd(mesh, rh, bh, 256, 1e-5, seed=900 + seed, cap_deg=5.0)["S"]
+        lim.append(2.0 * a - b)
+    lim = np.array(lim)
+    d1 = lim[:, [1, 2, 3], [1, 2, 3]].mean(1)
+    m, sem = d1.mean(), d1.std(ddof=1) / math.sqrt(len(d1))
+    d2 = lim[:, list(range(4, 9)), list(range(4, 9))].mean(1)
+    print(f"[psd zero-cap limit] GPU, level-4 sphere: degree 1 {m:.5f} +- {sem:.5f} (exact {exact:.5f}, ratio "
+          f"{m / exact:.4f}); degree 2 {d2.mean():.5f} +- {d2.std(ddof=1) / math.sqrt(len(d2)):.5f} "
+          f"(2 on the smooth sphere)", flush=True)
+    assert abs(m - exact) <= 4 * sem + 0.005 * exact
+    off = lim.copy()
+    for i in range(9):
+        off[:, i, i] = 0.0
+    off_mean, off_sem = off.mean(0), off.std(0, ddof=1) / math.sqrt(len(off))
+    assert np.all(np.abs(off_mean) <= 4 * off_sem + 0.005 * exact)
 
 
 @pytest.mark.parametrize("K", [300, 400])
@@ -187,3 +221,49 @@ def test_psd_variance_below_finite_difference(ctx):
     # (1-(1-h)^l)/h - l below 0.3% for l <= 2) the PSD estimator's is lower
     assert var[("fd", h0 / 4)] > 2.0 * var[("fd", h0)]
     assert var[("psd", 0)] < var[("fd", h0 / 4)]
+
+
+def test_psd_sh_sphere_2m_row_subset_parity_and_full_size(ctx, oracle_mod):
+    """The benched PSD workload (2.0M-face SH sphere, K = 128 spherical
+    harmonics, 320 antithetic pairs per row, eps = 1e-5):
+      * 160 Morton-spread rows on the full mesh, GPU against the oracle (same
+        rows, same streams): the fused K = 128 kernel's entries within 4
+        combined standard errors, radii and terminal triangles as above;
+      * all 16,384 rows on the GPU, as the bench times them (2,048 partial
+        slots summed by the reduction): S symmetric positive semidefinite and
+        the constant column zero to FP32 barycentric rounding."""
+    import dataclasses
+    import time
+
+    wl = W.load("psd_sh_sphere_2m")
+    case = wl.cases[0]
+    pairs = wl.walks // 2
+    order = W.morton_order(case.rows.p)
+    sel = np.sort(order[np.linspace(0, len(order) - 1, 160).astype(np.int64)])
+    r = case.rows
+    sub = dataclasses.replace(r, w=r.w[sel], p=r.p[sel], n=r.n[sel], tri=r.tri[sel], bary=r.bary[sel])
+    tab = np.zeros((case.V.shape[0], case.basis.K))
+    rows_of = np.repeat(np.arange(case.V.shape[0]), np.diff(case.basis.rowptr))
+    tab[rows_of, case.basis.col] = case.basis.val
+    mesh = ctx.build_bvh(case.V, case.F)
+    bh = ctx.basis(case.basis, case.V.shape[0])
+    rh = ctx.rows(mesh, sub)
+    print(f"[psd full] subset of {len(sel)} rows x {pairs} pairs, K={case.basis.K}, {case.F.shape[0]} faces",
+          flush=True)
+    g = ctx.estimate_psd(mesh, rh, bh, pairs, case.eps, seed=0, log=True)
+    t = time.time()
+    sc = oracle_mod.Scene(case.V, case.F, bvh=True)
+    o = oracle_mod.psd_estimate(sc, sub, tab.astype(np.float32).astype(np.float64), pairs, case.eps, seed=0,
+                                log=True, nthreads=16)
+    print(f"[psd full] oracle on the subset: {time.time() - t:.1f} s", flush=True)
+    assert g["info"]["fused"] == 1
+    _check_parity(g, o, oracle_mod.psd_r_max(case.V), "psd_sh_sphere_2m 160-row subset, K=128")
+    rfull = ctx.rows(mesh, r)
+    f = ctx.estimate_psd(mesh, rfull, bh, pairs, case.eps, seed=0)
+    S, se = f["S"], f["se"]
+    assert np.array_equal(S, S.T)
+    lam = np.linalg.eigvalsh(S)
+    assert lam.min() >= -1e-12 * lam.max()
+    assert np.abs(S[0]).max() < 1e-6 * np.abs(S).max()
+    print(f"[psd full] 16,384 rows: {f['info']['walk_kernel_ms']:.1f} ms walks, dropped rows "
+          f"{f['info']['dropped_rows']}, smallest eigenvalue / largest {lam.min() / lam.max():.2e}", flush=True)

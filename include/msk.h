@@ -395,6 +395,30 @@ msk_status msk_dtn_get_info(const msk_dtn* dtn, msk_dtn_info* info);
  * walk launch inside the graph; total_ms = the whole graph). */
 msk_status msk_batch_get_info(const msk_batch* batch, msk_dtn_info* info);
 
+/* msk_estimate_dtn for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same walks and the same S and se as msk_estimate_dtn with
+ * these arguments, written to caller-provided device arrays, with no device
+ * allocation and no allocating library call. The accumulators, row counters
+ * and launch tables live in a fixed workspace compiled into the library: 64
+ * MiB per device (MSK_NOALLOC_WORKSPACE_BYTES), held by every device the
+ * library runs on until the process ends; about 16 n_rows K + 64 n_rows
+ * bytes are needed, so e.g. 2,000 rows x 2,000 columns fit. Every call on a
+ * device shares that device's workspace and clears what it uses first; calls
+ * that overlap on one device (other host threads, other streams) race and
+ * must be serialised by the caller.
+ *   S, se: device, n_rows x K doubles each (row i = the rows' original i).
+ *   info:  optional host copy of the counters (walk_kernel_ms and total_ms
+ *          are not measured: 0).
+ * Errors: as msk_estimate_dtn; INVALID_ARG also when the workspace is too
+ * small for n_rows x K, when S or se is NULL, or for se_target > 0,
+ * record_log or collect_stats (not available here); DEVICE when the
+ * workspace's address could not be looked up at msk_create. */
+#define MSK_NOALLOC_WORKSPACE_BYTES (64ull << 20)
+msk_status msk_estimate_dtn_noalloc(msk_ctx* ctx, const msk_mesh* mesh, const msk_rows* rows, const msk_basis* basis,
+                                    int64_t walks, double eps, double inset_h, int32_t side,
+                                    const msk_dtn_opts* opts, double* S, double* se, msk_dtn_info* info);
+
 typedef enum {
   MSK_FIELD_S = 0,          /* n_rows x K double, the estimate             */
   MSK_FIELD_SE = 1,         /* n_rows x K double, standard errors          */

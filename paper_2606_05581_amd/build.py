@@ -7,7 +7,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsk.so")
-SOURCES = ["walk.hip", "psd.hip", "laplace.hip", "spectral.hip", "eigen.hip", "capi.cpp", "bvh_build.cpp", "symeig_host.cpp"]
+SOURCES = ["walk.hip", "psd.hip", "laplace.hip", "spectral.hip", "eigen.hip", "noalloc.hip", "capi.cpp",
+           "bvh_build.cpp", "symeig_host.cpp"]
 LIBS = []
 
 HIPCC_FLAGS = [

@@ -187,6 +187,9 @@ extern "C" msk_status msk_create(int device, void* hip_stream, msk_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = prop.multiProcessorCount;
+  // the allocation-free estimate's workspace on this device (looked up once
+  // per device; a failure is reported by that entry point, not here)
+  (void)msk::noalloc_scratch_init(device);
   *out = c;
   return MSK_OK;
 }
@@ -934,6 +937,131 @@ extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const ms
 #undef HIP_D
   *out = d;
   if (d->info.nonfinite_entries > 0) return fail(ctx, MSK_ERR_NUMERIC, "non-finite entries in S or se");
+  return MSK_OK;
+}
+
+// ------------------------------------------- estimate without allocation
+
+extern "C" msk_status msk_estimate_dtn_noalloc(msk_ctx* ctx, const msk_mesh* m, const msk_rows* r,
+                                               const msk_basis* b, int64_t walks, double eps, double inset_h,
+                                               int32_t side, const msk_dtn_opts* opts, double* S, double* se,
+                                               msk_dtn_info* info) {
+  if (!ctx) return MSK_ERR_INVALID_ARG;
+  msk_dtn_opts o;
+  msk_dtn_opts_default(&o);
+  if (opts) o = *opts;
+  msk_status st = check_problem(ctx, m, r, b, walks, eps, inset_h, side, &o);
+  if (st != MSK_OK) return st;
+  if (!S || !se) return fail(ctx, MSK_ERR_INVALID_ARG, "S and se (device, n_rows x K doubles) must be given");
+  if (o.form != MSK_FORM_PLAIN && o.form != MSK_FORM_PERSISTENT) return fail(ctx, MSK_ERR_INVALID_ARG, "bad form");
+  if (o.accum < 0 || o.accum > 2)
+    return fail(ctx, MSK_ERR_INVALID_ARG, "accum must be 0 (FP64), 1 (FP32) or 2 (compensated FP32)");
+  if (o.jump_only != 0 && (o.jump_only != 1 || side != MSK_EXTERIOR || r->mode != MSK_ROWS_POINT))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "jump_only takes exterior estimates with point rows");
+  if (o.se_target > 0 || o.record_log || o.collect_stats)
+    return fail(ctx, MSK_ERR_INVALID_ARG, "the allocation-free estimate takes a fixed walk count, no log and no "
+                                          "statistics");
+  if (o.walk_offset < 0 || o.walk_offset + walks > ((int64_t)1 << 32))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "walk indices must fit in 32 bits");
+  if (o.mesh_id < 0 || o.mesh_id > 0xFFFFFF) return fail(ctx, MSK_ERR_INVALID_ARG, "mesh_id must be < 2^24");
+  const int64_t n = r->n;
+  if ((unsigned long long)n * (unsigned long long)walks >= (1ull << 62))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "too many walks");
+  // workspace layout, each part 256-byte aligned: the accumulators, the row
+  // counters, the walk-launch tables and the queue counters
+  const size_t nk = (size_t)n * (size_t)b->K;
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t off_acc1 = 0, off_acc2 = off_acc1 + up(nk * 8), off_q = off_acc2 + up(nk * 8);
+  const size_t off_esc = off_q + up((size_t)n * 8), off_cap = off_esc + up((size_t)n * 8);
+  const size_t off_walks = off_cap + up((size_t)n * 8), off_disc = off_walks + up((size_t)n * 8);
+  const size_t off_nonf = off_disc + up((size_t)n * 4), off_qn = off_nonf + 256, off_qe = off_qn + 256;
+  const size_t off_mesh = off_qe + 256, off_slots = off_mesh + up(sizeof(MeshDev));
+  const size_t need = off_slots + up((size_t)n * sizeof(RowSlot));
+  if (need > msk::kNoallocScratchBytes)
+    return fail(ctx, MSK_ERR_INVALID_ARG,
+                "the allocation-free estimate needs " + std::to_string(need) + " bytes of workspace for " +
+                    std::to_string(n) + " rows x " + std::to_string(b->K) + " columns; its fixed workspace holds " +
+                    std::to_string(msk::kNoallocScratchBytes) + " (about 16 n K + 64 n bytes are needed)");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipError_t serr = hipSuccess;
+  char* base = (char*)msk::noalloc_scratch(ctx->device, &serr);
+  if (!base) return fail(ctx, MSK_ERR_DEVICE, std::string("workspace address: ") + hipGetErrorString(serr));
+  // a stack-held result record pointing into the workspace and the caller's
+  // outputs (make_meshdev reads its pointers)
+  msk_dtn d;
+  d.ctx = ctx;
+  d.rows = r;
+  d.n = n;
+  d.K = b->K;
+  d.W = walks;
+  d.mode = r->mode;
+  d.inset = inset_h;
+  d.d_S = S;
+  d.d_se = se;
+  d.d_acc1 = (double*)(base + off_acc1);
+  d.d_acc2 = (double*)(base + off_acc2);
+  d.d_q = (unsigned long long*)(base + off_q);
+  d.d_esc = (unsigned long long*)(base + off_esc);
+  d.d_cap = (unsigned long long*)(base + off_cap);
+  d.d_walks = (int64_t*)(base + off_walks);
+  d.d_disc = (int32_t*)(base + off_disc);
+  d.d_nonfinite = (unsigned long long*)(base + off_nonf);
+  unsigned long long* d_qn = (unsigned long long*)(base + off_qn);
+  unsigned long long* d_qe = (unsigned long long*)(base + off_qe);
+  MeshDev* d_mesh = (MeshDev*)(base + off_mesh);
+  RowSlot* d_slots = (RowSlot*)(base + off_slots);
+  hipStream_t s = ctx->stream;
+  // the workspace keeps the previous call's contents: clear what accumulates
+  HIP_TRY(ctx, launch_fill_u64(d.d_acc1, (int64_t)nk, 0, s));
+  HIP_TRY(ctx, launch_fill_u64(d.d_acc2, (int64_t)nk, 0, s));
+  HIP_TRY(ctx, launch_fill_u64(d.d_q, n, 0, s));
+  HIP_TRY(ctx, launch_fill_u64(d.d_esc, n, 0, s));
+  HIP_TRY(ctx, launch_fill_u64(d.d_cap, n, 0, s));
+  HIP_TRY(ctx, launch_fill_u64(d.d_walks, n, (unsigned long long)walks, s));
+  HIP_TRY(ctx, launch_fill_u32(d.d_disc, n, 0u, s));
+  HIP_TRY(ctx, launch_fill_u64(d.d_nonfinite, 1, 0, s));
+  MeshDev M = make_meshdev(m, r, b, &d, eps, inset_h, side, o, o.mesh_id);
+  if (r->mode == MSK_ROWS_POINT) HIP_TRY(ctx, launch_discard(M, n, d.d_disc, s));
+  std::vector<RowSlot> slots(r->order.size());
+  for (size_t i = 0; i < slots.size(); ++i) slots[i] = RowSlot{0, r->order[i], 0u};
+  HIP_TRY(ctx, hipMemcpyAsync(d_mesh, &M, sizeof(MeshDev), hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipMemcpyAsync(d_slots, slots.data(), sizeof(RowSlot) * slots.size(), hipMemcpyHostToDevice, s));
+  WalkLaunch L;
+  std::memset(&L, 0, sizeof(L));
+  L.meshes = d_mesh;
+  L.slots = d_slots;
+  L.n_slots = (int64_t)slots.size();
+  L.walks_per_slot = walks;
+  L.walk_offset = o.walk_offset;
+  L.seed_lo = (uint32_t)o.seed;
+  L.seed_hi = (uint32_t)(o.seed >> 32);
+  L.queue_next = d_qn;
+  L.queue_end = d_qe;
+  L.chunk = std::max(1, o.chunk);
+  L.regen_min = std::min(64, std::max(1, o.regen_min));
+  L.use_lds_top = (o.form == MSK_FORM_PERSISTENT && m->top_nodes > 0) ? 1 : 0;
+  L.n_top = m->top_nodes;
+  L.accum = o.accum;
+  L.knn = b->knn_mesh ? 1 : 0;
+  HIP_TRY(ctx, launch_init_queues(d_qn, d_qe, make_queues(L.n_slots, walks), s));
+  if (o.form == MSK_FORM_PLAIN)
+    HIP_TRY(ctx, launch_walk_plain(L, s));
+  else
+    HIP_TRY(ctx, launch_walk_persistent(L, std::max(1, ctx->n_cu * std::max(1, o.blocks_per_cu)), s));
+  HIP_TRY(ctx, launch_finalize(M, n, d.d_walks, r->d_w, S, se, s, o.jump_only));
+  HIP_TRY(ctx, launch_count_nonfinite(S, (int64_t)nk, d.d_nonfinite, s));
+  HIP_TRY(ctx, launch_count_nonfinite(se, (int64_t)nk, d.d_nonfinite, s));
+  // the host copies above read `slots` and `M`: they are complete once the
+  // stream is
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  msk_status cs = collect_info(ctx, &d);
+  d.d_S = d.d_se = d.d_acc1 = d.d_acc2 = nullptr;  // nothing of the record is freed
+  d.d_q = d.d_esc = d.d_cap = d.d_nonfinite = nullptr;
+  d.d_walks = nullptr;
+  d.d_disc = nullptr;
+  if (cs != MSK_OK) return cs;
+  if (info) *info = d.info;
+  if (d.info.nonfinite_entries > 0) return fail(ctx, MSK_ERR_NUMERIC, "non-finite entries in S or se");
   return MSK_OK;
 }
 

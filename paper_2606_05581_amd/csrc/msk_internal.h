@@ -171,6 +171,14 @@ hipError_t launch_closest_points(const Node4* nodes, const TriRec* tris, float r
 hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walks, const double* w, double* S,
                            double* se, hipStream_t s, int32_t jump_only = 0);
 
+// Fixed workspace of the allocation-free estimate (noalloc.hip): 64 MiB per
+// device. noalloc_scratch_init looks its address up on `device` (which must
+// be current) once; noalloc_scratch returns it (nullptr if the lookup failed
+// or was not made, with the HIP error in *err).
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch(int device, hipError_t* err);
+
 // PSD estimator (psd.hip): per-pair inputs of the rank-one updates
 struct PsdGather {
   const float* tab;         // dense per-vertex basis table, n_verts x K (the basis values, FP32)

@@ -148,6 +148,8 @@ SIGNATURES = {
     "msk_eps_floor": ([C.c_double, C.POINTER(DtnOpts)], C.c_double),
     "msk_estimate_dtn": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_int32,
                           C.POINTER(DtnOpts), C.POINTER(C.c_void_p)], C.c_int),
+    "msk_estimate_dtn_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                                  C.c_int32, C.POINTER(DtnOpts), C.c_void_p, C.c_void_p, C.POINTER(DtnInfo)], C.c_int),
     "msk_estimate_dtn_batched": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                   C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int64,
                                   C.c_int32, C.POINTER(DtnOpts), C.POINTER(C.c_void_p)], C.c_int),
@@ -371,6 +373,23 @@ class Context:
             raise MskNumericError(st, lib().msk_last_error(self.h).decode(), Dtn(self, h, rows.n, basis.K, walks))
         self._check(st)
         return Dtn(self, h, rows.n, basis.K, walks)
+
+    def estimate_dtn_noalloc(self, mesh, rows, basis, walks: int, eps: float, inset_h: float, S, se,
+                             exterior: bool = False, **opts) -> dict:
+        """msk_estimate_dtn into caller-provided device arrays S and se (torch
+        CUDA float64 tensors, n_rows x K, contiguous) with no device
+        allocation; returns the counters."""
+        for t in (S, se):
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()
+                    and tuple(t.shape) == (rows.n, basis.K)):
+                raise ValueError("S and se must be contiguous float64 CUDA tensors of shape (n_rows, K)")
+        o = self.default_opts(**opts)
+        info = DtnInfo()
+        st = lib().msk_estimate_dtn_noalloc(self.h, mesh.h, rows.h, basis.h, walks, eps, inset_h,
+                                            EXTERIOR if exterior else INTERIOR, C.byref(o), C.c_void_p(S.data_ptr()),
+                                            C.c_void_p(se.data_ptr()), C.byref(info))
+        self._check(st)
+        return {f: getattr(info, f) for f, _ in DtnInfo._fields_}
 
     def estimate_dtn_batched(self, meshes, rows, bases, eps, insets, walks: int, exterior: bool = False, **opts):
         n = len(meshes)

@@ -1022,3 +1022,536 @@ void orc_psd_estimate(const void* h, int64_t n_rows, const float* p, const float
     free(Qi);
   }
 }
+
+/* ------------------------------------- Kelvin-inverted exterior (Sec. 3.3) */
+
+/* The exterior DtN form of Sec. 3.3 (eq. exterior-dtn-beurling-deny-form) is
+ * estimated in the image of the exterior under the Kelvin transform
+ * x -> x / |x|^2 about a centre o inside the shape (Sec. 3.3, "The Kelvin
+ * Transform"; Appendix, Kelvin transform): a bounded domain whose boundary
+ * is the image of the mesh, each planar triangle becoming a piece of a sphere
+ * through the origin bounded by three circular arcs (Sec. 4: spherical
+ * triangular elements with non-planar distance queries). Coordinates below
+ * are relative to o. */
+
+typedef struct {
+  int64_t nv, nf;
+  double* V;     /* (nv, 3) primal vertices relative to the inversion centre */
+  int32_t* F;
+  double o[3];   /* inversion centre (world) */
+  double lo[3], hi[3]; /* bounding box of the inverted vertices */
+  double radius; /* max |x~| over the inverted vertices and arcs (a bound of the inverted domain) */
+  /* bounding volume hierarchy over boxes that contain each inverted
+   * triangle (an acceleration of the brute-force minimum, same result) */
+  double* tlo;   /* (nf, 3) */
+  double* thi;
+  int64_t nnodes;
+  OrcNode* nodes;
+  int64_t* order;
+} OrcKelvin;
+
+static void kelvin3(const double* x, double* y) {
+  double r2 = dot3(x, x);
+  y[0] = x[0] / r2; y[1] = x[1] / r2; y[2] = x[2] / r2;
+}
+
+/* barycentrics of the projection of y onto the plane of (a, b, c) */
+static void plane_bary(const double* y, const double* a, const double* b, const double* c, double* l) {
+  double ab[3], ac[3], ay[3], n[3], x[3];
+  for (int k = 0; k < 3; ++k) { ab[k] = b[k] - a[k]; ac[k] = c[k] - a[k]; ay[k] = y[k] - a[k]; }
+  cross3(ab, ac, n);
+  double nn = dot3(n, n);
+  cross3(ay, ac, x);
+  double l1 = dot3(x, n) / nn;
+  cross3(ab, ay, x);
+  double l2 = dot3(x, n) / nn;
+  l[0] = 1 - l1 - l2; l[1] = l1; l[2] = l2;
+}
+
+/* Nearest point of the image of the segment [P0, P1] (relative to the
+ * centre, not through it) to p: the image of the line is the circle through
+ * the origin in the plane of (0, P0, P1) with diameter from 0 to the image
+ * of the line's foot point f, centre f / (2 |f|^2), radius 1 / (2 |f|); the
+ * nearest circle point to p is the radial projection of p's in-plane
+ * position; it lies on the segment's arc when its image lies between P0 and
+ * P1, else an end point is nearest. The origin itself is the image of the
+ * line's point at infinity, not of a segment point: every point of the
+ * segment's image lies at least 1 / max(|P0|, |P1|) from it, and a
+ * projection closer than that is not on the arc. A line through the centre
+ * maps to itself. Returns the squared distance, the point q and the segment
+ * parameter t of kappa(q) = P0 + t (P1 - P0). */
+static double inv_seg_d2(const double* p, const double* P0, const double* P1, double* q, double* t_out) {
+  double e[3] = {P1[0] - P0[0], P1[1] - P0[1], P1[2] - P0[2]};
+  double ee = dot3(e, e);
+  double best = INFINITY, bt = 0;
+  double k0[3], k1[3];
+  kelvin3(P0, k0);
+  kelvin3(P1, k1);
+  /* end points */
+  double dd0[3] = {p[0] - k0[0], p[1] - k0[1], p[2] - k0[2]};
+  double dd1[3] = {p[0] - k1[0], p[1] - k1[1], p[2] - k1[2]};
+  if (dot3(dd0, dd0) < best) { best = dot3(dd0, dd0); bt = 0; memcpy(q, k0, sizeof(k0)); }
+  if (dot3(dd1, dd1) < best) { best = dot3(dd1, dd1); bt = 1; memcpy(q, k1, sizeof(k1)); }
+  if (!(ee > 0)) { *t_out = bt; return best; }
+  double tf = -dot3(P0, e) / ee;
+  double f[3] = {P0[0] + tf * e[0], P0[1] + tf * e[1], P0[2] + tf * e[2]};
+  double ff = dot3(f, f);
+  double m[3];
+  cross3(P0, P1, m);
+  double mm = dot3(m, m);
+  double scale = fmax(dot3(P0, P0), dot3(P1, P1));
+  if (ff > 1e-24 * scale && mm > 0) {
+    double ml = sqrt(mm);
+    for (int k = 0; k < 3; ++k) m[k] /= ml;
+    double cc[3] = {f[0] / (2 * ff), f[1] / (2 * ff), f[2] / (2 * ff)};
+    double rho = 1.0 / (2 * sqrt(ff));
+    double mp = dot3(m, p);
+    double u[3] = {p[0] - mp * m[0] - cc[0], p[1] - mp * m[1] - cc[1], p[2] - mp * m[2] - cc[2]};
+    double ul = sqrt(dot3(u, u));
+    if (ul > 0) {
+      double e2[3] = {cc[0] + rho * u[0] / ul, cc[1] + rho * u[1] / ul, cc[2] + rho * u[2] / ul};
+      double ry = dot3(e2, e2);
+      if (ry * scale >= 1.0 - 1e-9) {
+        double y[3];
+        kelvin3(e2, y);
+        double yd[3] = {y[0] - P0[0], y[1] - P0[1], y[2] - P0[2]};
+        double t = dot3(yd, e) / ee;
+        if (t >= 0 && t <= 1) {
+          double d[3] = {p[0] - e2[0], p[1] - e2[1], p[2] - e2[2]};
+          double d2 = dot3(d, d);
+          if (d2 < best) { best = d2; bt = t; memcpy(q, e2, sizeof(e2)); }
+        }
+      }
+    }
+  } else {
+    /* the line passes through the centre: the arc is the straight segment
+     * between the images of the end points */
+    double t;
+    double d2 = seg_closest(p, k0, k1, &t);
+    if (d2 < best) {
+      best = d2;
+      for (int k = 0; k < 3; ++k) q[k] = k0[k] + t * (k1[k] - k0[k]);
+      double y[3], yd[3];
+      kelvin3(q, y);
+      for (int k = 0; k < 3; ++k) yd[k] = y[k] - P0[k];
+      bt = dot3(yd, e) / ee;
+    }
+  }
+  *t_out = bt;
+  return best;
+}
+
+/* Squared distance from p (inverted space, relative to the centre) to the
+ * image of triangle (A, B, C) (relative to the centre), the nearest point q
+ * and the barycentrics l of its image kappa(q) in (A, B, C). The plane
+ * n . y = dd of the triangle (unit n) maps to the sphere through the origin
+ * with centre n / (2 dd) and radius 1 / (2 |dd|); the nearest sphere point to
+ * p is the radial projection, written stably in terms of dd so that a plane
+ * through the centre (dd = 0: the image is that plane) is the limit; it
+ * belongs to the patch when its image lies in the triangle. Otherwise the
+ * nearest point of the patch lies on its boundary, the images of the three
+ * edges (the distance to points of a sphere grows with their angle from the
+ * radial projection). */
+double orc_kelvin_tri_d2(const double* p, const double* A, const double* B, const double* C, double* q, double* l) {
+  double best = INFINITY;
+  double ab[3], ac[3], n[3];
+  for (int k = 0; k < 3; ++k) { ab[k] = B[k] - A[k]; ac[k] = C[k] - A[k]; }
+  cross3(ab, ac, n);
+  double nl = sqrt(dot3(n, n));
+  double scale = fmax(dot3(ab, ab), dot3(ac, ac));
+  if (nl > 1e-12 * scale) {
+    for (int k = 0; k < 3; ++k) n[k] /= nl;
+    double dd = dot3(n, A);
+    double qq[3];
+    if (dd != 0.0) {
+      double sg = dd > 0 ? 1.0 : -1.0, ad = fabs(dd);
+      double v[3] = {dd * p[0] - 0.5 * n[0], dd * p[1] - 0.5 * n[1], dd * p[2] - 0.5 * n[2]};
+      double vl = sqrt(dot3(v, v));
+      double sd = (ad * dot3(p, p) - sg * dot3(n, p)) / (vl + 0.5); /* signed distance to the sphere */
+      for (int k = 0; k < 3; ++k) qq[k] = p[k] - sd * sg * v[k] / vl;
+    } else {
+      double np = dot3(n, p);
+      for (int k = 0; k < 3; ++k) qq[k] = p[k] - np * n[k];
+    }
+    double M2 = fmax(dot3(A, A), fmax(dot3(B, B), dot3(C, C)));
+    if (dot3(qq, qq) * M2 >= 1.0 - 1e-9) { /* image points lie at least 1 / max|vertex| from the origin */
+      double y[3], lb[3];
+      kelvin3(qq, y);
+      plane_bary(y, A, B, C, lb);
+      if (lb[0] >= 0 && lb[1] >= 0 && lb[2] >= 0) {
+        double d[3] = {p[0] - qq[0], p[1] - qq[1], p[2] - qq[2]};
+        best = dot3(d, d);
+        memcpy(q, qq, sizeof(qq));
+        memcpy(l, lb, sizeof(lb));
+      }
+    }
+  }
+  const double* P[3] = {A, B, C};
+  for (int e = 0; e < 3; ++e) {
+    int i0 = e, i1 = (e + 1) % 3;
+    double qe[3], t;
+    double d2 = inv_seg_d2(p, P[i0], P[i1], qe, &t);
+    if (d2 < best) {
+      best = d2;
+      memcpy(q, qe, sizeof(qe));
+      l[0] = l[1] = l[2] = 0;
+      l[i0] = 1 - t;
+      l[i1] = t;
+    }
+  }
+  return best;
+}
+
+/* A box containing the image of triangle t: each coordinate of
+ * kappa(y) = y / |y|^2 for y in the triangle is a quotient of a number in the
+ * triangle's coordinate range and one in [m2, M2], m2 the squared distance
+ * from the centre to the triangle and M2 its largest squared vertex norm. */
+static void kelvin_tri_box(const OrcKelvin* s, int64_t t, double* lo, double* hi) {
+  const double* P[3] = {s->V + 3 * (int64_t)s->F[3 * t], s->V + 3 * (int64_t)s->F[3 * t + 1],
+                        s->V + 3 * (int64_t)s->F[3 * t + 2]};
+  double l[3], z[3] = {0, 0, 0};
+  double m2 = orc_closest_tri(z, P[0], P[1], P[2], l);
+  double M2 = fmax(dot3(P[0], P[0]), fmax(dot3(P[1], P[1]), dot3(P[2], P[2])));
+  for (int k = 0; k < 3; ++k) {
+    double a = fmin(P[0][k], fmin(P[1][k], P[2][k])), b = fmax(P[0][k], fmax(P[1][k], P[2][k]));
+    if (a >= 0) { lo[k] = a / M2; hi[k] = b / m2; }
+    else if (b <= 0) { lo[k] = a / m2; hi[k] = b / M2; }
+    else { lo[k] = a / m2; hi[k] = b / m2; }
+    double pad = 1e-12 * (fabs(lo[k]) + fabs(hi[k]));
+    lo[k] -= pad; hi[k] += pad;
+  }
+}
+
+static int64_t kelvin_build(OrcKelvin* s, int64_t lo, int64_t hi, double* key) {
+  int64_t id = s->nnodes++;
+  OrcNode* n = &s->nodes[id];
+  double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int k = 0; k < 3; ++k) { n->bmin[k] = INFINITY; n->bmax[k] = -INFINITY; }
+  for (int64_t i = lo; i < hi; ++i) {
+    int64_t t = s->order[i];
+    for (int k = 0; k < 3; ++k) {
+      n->bmin[k] = fmin(n->bmin[k], s->tlo[3 * t + k]);
+      n->bmax[k] = fmax(n->bmax[k], s->thi[3 * t + k]);
+      double c = 0.5 * (s->tlo[3 * t + k] + s->thi[3 * t + k]);
+      clo[k] = fmin(clo[k], c); chi[k] = fmax(chi[k], c);
+    }
+  }
+  n->lo = lo; n->hi = hi; n->left = n->right = -1;
+  if (hi - lo <= 4) return id;
+  int ax = 0;
+  for (int k = 1; k < 3; ++k)
+    if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+  for (int64_t i = lo; i < hi; ++i) {
+    int64_t t = s->order[i];
+    key[t] = 0.5 * (s->tlo[3 * t + ax] + s->thi[3 * t + ax]);
+  }
+  g_sort_key = key;
+  qsort(s->order + lo, (size_t)(hi - lo), sizeof(int64_t), cmp_key);
+  int64_t mid = lo + (hi - lo) / 2;
+  int64_t l = kelvin_build(s, lo, mid, key);
+  int64_t r = kelvin_build(s, mid, hi, key);
+  s->nodes[id].left = l;
+  s->nodes[id].right = r;
+  return id;
+}
+
+void* orc_kelvin_create(const float* V, int64_t nv, const int32_t* F, int64_t nf, const double* centre) {
+  OrcKelvin* s = (OrcKelvin*)calloc(1, sizeof(OrcKelvin));
+  s->nv = nv; s->nf = nf;
+  s->V = (double*)malloc(sizeof(double) * 3 * nv);
+  s->F = (int32_t*)malloc(sizeof(int32_t) * 3 * nf);
+  memcpy(s->F, F, sizeof(int32_t) * 3 * nf);
+  for (int k = 0; k < 3; ++k) { s->o[k] = centre[k]; s->lo[k] = INFINITY; s->hi[k] = -INFINITY; }
+  double rmax = 0;
+  for (int64_t i = 0; i < nv; ++i) {
+    double y[3];
+    for (int k = 0; k < 3; ++k) s->V[3 * i + k] = (double)V[3 * i + k] - centre[k];
+    kelvin3(s->V + 3 * i, y);
+    for (int k = 0; k < 3; ++k) { s->lo[k] = fmin(s->lo[k], y[k]); s->hi[k] = fmax(s->hi[k], y[k]); }
+    rmax = fmax(rmax, sqrt(dot3(y, y)));
+  }
+  /* the inverted surface lies within 1 / (distance from the centre to the
+   * mesh); the inverted vertices alone may miss bulging patches */
+  double dmin = INFINITY;
+  for (int64_t t = 0; t < nf; ++t) {
+    double l[3], z[3] = {0, 0, 0};
+    double d2 = orc_closest_tri(z, s->V + 3 * (int64_t)F[3 * t], s->V + 3 * (int64_t)F[3 * t + 1],
+                                s->V + 3 * (int64_t)F[3 * t + 2], l);
+    dmin = fmin(dmin, d2);
+  }
+  s->radius = fmax(rmax, 1.0 / sqrt(dmin));
+  s->tlo = (double*)malloc(sizeof(double) * 3 * (size_t)nf);
+  s->thi = (double*)malloc(sizeof(double) * 3 * (size_t)nf);
+  for (int64_t t = 0; t < nf; ++t) kelvin_tri_box(s, t, s->tlo + 3 * t, s->thi + 3 * t);
+  s->nodes = (OrcNode*)malloc(sizeof(OrcNode) * (size_t)(2 * nf + 1));
+  s->order = (int64_t*)malloc(sizeof(int64_t) * (size_t)nf);
+  double* key = (double*)malloc(sizeof(double) * (size_t)nf);
+  for (int64_t i = 0; i < nf; ++i) s->order[i] = i;
+  kelvin_build(s, 0, nf, key);
+  free(key);
+  return s;
+}
+
+void orc_kelvin_destroy(void* h) {
+  OrcKelvin* s = (OrcKelvin*)h;
+  free(s->V); free(s->F); free(s->tlo); free(s->thi); free(s->nodes); free(s->order); free(s);
+}
+
+void orc_kelvin_info(const void* h, double* lo, double* hi, double* radius) {
+  const OrcKelvin* s = (const OrcKelvin*)h;
+  for (int k = 0; k < 3; ++k) { lo[k] = s->lo[k]; hi[k] = s->hi[k]; }
+  *radius = s->radius;
+}
+
+/* Nearest inverted triangle by brute force: minimum of (squared distance,
+ * index) over all triangles; q = nearest point (inverted space), l = primal
+ * barycentrics of its image. */
+static double kelvin_tri(const OrcKelvin* s, int64_t t, const double* p, double* q, double* l) {
+  return orc_kelvin_tri_d2(p, s->V + 3 * (int64_t)s->F[3 * t], s->V + 3 * (int64_t)s->F[3 * t + 1],
+                           s->V + 3 * (int64_t)s->F[3 * t + 2], q, l);
+}
+
+static double kelvin_nearest_brute(const OrcKelvin* s, const double* p, int64_t* tri, double* q, double* l) {
+  double best = INFINITY;
+  *tri = -1;
+  for (int64_t t = 0; t < s->nf; ++t) {
+    double qq[3], ll[3];
+    double d2 = kelvin_tri(s, t, p, qq, ll);
+    if (d2 < best) {
+      best = d2; *tri = t;
+      memcpy(q, qq, sizeof(qq));
+      memcpy(l, ll, sizeof(ll));
+    }
+  }
+  return best;
+}
+
+/* The same minimum, visiting only boxes that can hold a closer image. */
+static double kelvin_nearest(const OrcKelvin* s, const double* p, int64_t* tri, double* q, double* l) {
+  double best = INFINITY;
+  int64_t bi = -1;
+  int64_t stack[256];
+  int sp = 0;
+  stack[sp++] = 0;
+  while (sp > 0) {
+    const OrcNode* n = &s->nodes[stack[--sp]];
+    if (box_d2(n, p) > best * (1.0 + 1e-12)) continue;
+    if (n->left < 0) {
+      for (int64_t i = n->lo; i < n->hi; ++i) {
+        int64_t t = s->order[i];
+        double qq[3], ll[3];
+        double d = kelvin_tri(s, t, p, qq, ll);
+        if (d < best || (d == best && t < bi)) {
+          best = d; bi = t;
+          memcpy(q, qq, sizeof(qq));
+          memcpy(l, ll, sizeof(ll));
+        }
+      }
+    } else {
+      double da = box_d2(&s->nodes[n->left], p), db = box_d2(&s->nodes[n->right], p);
+      if (da <= db) { stack[sp++] = n->right; stack[sp++] = n->left; }
+      else { stack[sp++] = n->left; stack[sp++] = n->right; }
+      if (sp > 250) abort();
+    }
+  }
+  *tri = bi;
+  return best;
+}
+
+void orc_kelvin_nearest(const void* h, const double* Q, int64_t nq, int use_bvh, int64_t* tri, double* d2,
+                        double* qpt, double* bary) {
+  const OrcKelvin* s = (const OrcKelvin*)h;
+  for (int64_t i = 0; i < nq; ++i)
+    d2[i] = use_bvh ? kelvin_nearest(s, Q + 3 * i, tri + i, qpt + 3 * i, bary + 3 * i)
+                    : kelvin_nearest_brute(s, Q + 3 * i, tri + i, qpt + 3 * i, bary + 3 * i);
+}
+
+/* Walk-on-Spheres in the inverted exterior from x (inverted space, relative
+ * to the centre): a bounded domain, so every walk ends in the eps-shell (or
+ * at the step cap). Same step rule and streams as the primal walks. */
+static int kelvin_walk(const OrcKelvin* s, const OrcWalkParams* P, uint32_t row, uint32_t wk, double* x,
+                       int64_t* tri, double* q, double* l, int64_t* nquery) {
+  double eps2 = P->eps * P->eps;
+  for (int64_t k = 0; k < P->max_steps; ++k) {
+    double d2 = kelvin_nearest(s, x, tri, q, l);
+    if (d2 < eps2) { *nquery = k + 1; return ST_HIT; }
+    double u[4];
+    draw4(P->seed, row, wk, (uint32_t)k, PURPOSE_STEP, P->mesh, u);
+    double r = sqrt(d2) * (1.0 - P->kappa) - P->delta;
+    double z = 1.0 - 2.0 * u[0];
+    double rxy = 2.0 * sqrt(u[0] * (1.0 - u[0]));
+    double phi = 2.0 * M_PI * u[1];
+    x[0] += r * rxy * cos(phi);
+    x[1] += r * rxy * sin(phi);
+    x[2] += r * z;
+  }
+  kelvin_nearest(s, x, tri, q, l);
+  *nquery = P->max_steps + 1;
+  return ST_CAPPED;
+}
+
+/* Largest ball in the inverted exterior touching the inverted surface at
+ * s~ (relative to the centre), with n~ its unit normal pointing out of the
+ * inverted exterior: bisection as for the interior balls, a radius accepted
+ * when the centre c = s~ - r n~ is at least r - min(tol, r/1024) from the
+ * inverted surface and the ball lies within the inverted domain's bound. */
+double orc_kelvin_tangent_ball(const void* h, const double* st, const double* nt, double r_max, int iters,
+                               double tol) {
+  const OrcKelvin* s = (const OrcKelvin*)h;
+  double lo = 0.0, hi = r_max;
+  for (int it = 0; it < iters; ++it) {
+    double mid = 0.5 * (lo + hi);
+    double c[3] = {st[0] - mid * nt[0], st[1] - mid * nt[1], st[2] - mid * nt[2]};
+    int64_t tt;
+    double qq[3], ll[3];
+    double d = sqrt(kelvin_nearest(s, c, &tt, qq, ll));
+    double t = mid - fmin(tol, mid * TANGENT_REL_TOL);
+    if (d >= t && sqrt(dot3(c, c)) + mid <= s->radius) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+/* The point s~ = kappa(s) and the unit normal n~ there pointing out of the
+ * inverted exterior: the Kelvin Jacobian maps n_s to -|s~|^2 n~ (Appendix,
+ * normal inversion), and it is |s~|^2 times the reflection H = I - 2 s^ s^T,
+ * so n~ = -H n_s (s relative to the centre, n_s the outward unit normal). */
+void orc_kelvin_point_normal(const double* s, const double* ns, double* st, double* nt) {
+  double r = sqrt(dot3(s, s));
+  double sh[3] = {s[0] / r, s[1] / r, s[2] / r};
+  double sn = dot3(sh, ns);
+  kelvin3(s, st);
+  for (int k = 0; k < 3; ++k) nt[k] = -(ns[k] - 2.0 * sn * sh[k]);
+}
+
+/* The exterior estimate (Sec. 3.3, eq. main-exterior-estimator) over point
+ * rows: row i's sample s_i (primal face, barycentrics, outward normal,
+ * weight w_i) maps to s~_i; its tangent ball in the inverted exterior (radius
+ * r_i, centre c~_i) gets `pairs` antithetic pairs of ball points drawn
+ * proportionally to the ball's jump kernel outside the cap (as for the
+ * interior PSD estimator), and a walk from each in the inverted exterior ends
+ * at t~, whose image t is a primal surface point with basis values b(t). Per
+ * pair p of row i the jump term adds
+ *   X_p = alpha_i (d_1 d_1^T / |t~_1| + d_2 d_2^T / |t~_2|) / 2,
+ *   alpha_i = w_i |s~_i|^3 Z_i / (2 pairs), d = b(s_i) - b(t),
+ * (the exterior jump kernel |s~|^3 |t~|^3 J~(s~, t~), eq.
+ * exterior-jump-kernel-final, with the surface element of the inverted
+ * boundary |t~|^-4 times the primal one). The killing term (eq.
+ * killing-measure-poisson-kernel) runs kill_walks walks from the origin of
+ * the inverted space (the image of infinity); walk k (Philox row
+ * 0xFFFFFFFF, walk k) ends at t~_0 and adds
+ *   Y_k = (4 pi / |t~_0|) b(t_0) b(t_0)^T / kill_walks.
+ * Outputs: Sj, Qj (sum of X and of X*X), Sk, Qk (same for Y), K x K each; per
+ * row radius and Z; queries per row (bisection and walks) and of the killing
+ * walks. */
+void orc_kelvin_estimate(const void* h, int64_t n_rows, const float* p, const float* nrm, const int32_t* tri,
+                         const float* bary, const double* w, const double* tab, int64_t K, int64_t pairs,
+                         int64_t kill_walks, double theta0, double r_max, int bisect_iters, double eps, double kappa,
+                         double delta, int64_t max_steps, uint64_t seed, uint32_t mesh, int nthreads, double* Sj,
+                         double* Qj, double* Sk, double* Qk, double* radius, double* Zout, int64_t* n_query,
+                         int64_t* kill_query, int32_t* log_status, int64_t* log_tri, float* log_bary) {
+  const OrcKelvin* sc = (const OrcKelvin*)h;
+  OrcWalkParams P = {eps, kappa, delta, max_steps, seed, mesh};
+  memset(Sj, 0, sizeof(double) * K * K);
+  memset(Qj, 0, sizeof(double) * K * K);
+  memset(Sk, 0, sizeof(double) * K * K);
+  memset(Qk, 0, sizeof(double) * K * K);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+  for (int64_t i = 0; i < n_rows; ++i) {
+    double s[3], n[3], st[3], nt[3];
+    for (int k = 0; k < 3; ++k) {
+      s[k] = (double)p[3 * i + k] - sc->o[k];
+      n[k] = nrm[3 * i + k];
+    }
+    double nl = sqrt(dot3(n, n));
+    for (int k = 0; k < 3; ++k) n[k] /= nl;
+    orc_kelvin_point_normal(s, n, st, nt);
+    double r = orc_kelvin_tangent_ball(h, st, nt, r_max, bisect_iters, 0.5 * eps);
+    radius[i] = r;
+    Zout[i] = r > 0 ? orc_ball_jump_mass(r, theta0) : 0.0;
+    n_query[i] = bisect_iters;
+    if (r <= 0) continue;
+    double c[3] = {st[0] - r * nt[0], st[1] - r * nt[1], st[2] - r * nt[2]};
+    double sl = sqrt(dot3(st, st));
+    double alpha = w[i] * sl * sl * sl * Zout[i] / (2.0 * (double)pairs);
+    double* bs = (double*)calloc(K, sizeof(double));
+    double* d = (double*)malloc(sizeof(double) * 2 * K);
+    double* Si = (double*)calloc(K * K, sizeof(double));
+    double* Qi = (double*)calloc(K * K, sizeof(double));
+    for (int cc = 0; cc < 3; ++cc) {
+      int64_t v = sc->F[3 * (int64_t)tri[i] + cc];
+      for (int64_t k = 0; k < K; ++k) bs[k] += (double)bary[3 * i + cc] * tab[v * K + k];
+    }
+    for (int64_t j = 0; j < pairs; ++j) {
+      double u[4], g[2];
+      draw4(seed, (uint32_t)i, (uint32_t)j, 0, PURPOSE_BALL, mesh, u);
+      for (int a = 0; a < 2; ++a) {
+        double x[3], q[3], l[3];
+        orc_ball_point(c, r, nt, theta0, u[0], u[1], a, x);
+        int64_t tt = -1, nq = 0;
+        int stt = kelvin_walk(sc, &P, (uint32_t)i, (uint32_t)(2 * j + a), x, &tt, q, l, &nq);
+        n_query[i] += nq;
+        g[a] = 1.0 / sqrt(dot3(q, q));
+        for (int64_t k = 0; k < K; ++k) {
+          double b = 0.0;
+          for (int cc = 0; cc < 3; ++cc) b += l[cc] * tab[(int64_t)sc->F[3 * tt + cc] * K + k];
+          d[a * K + k] = bs[k] - b;
+        }
+        if (log_status) {
+          int64_t li = i * 2 * pairs + 2 * j + a;
+          log_status[li] = stt;
+          log_tri[li] = tt;
+          log_bary[2 * li] = (float)l[1];
+          log_bary[2 * li + 1] = (float)l[2];
+        }
+      }
+      for (int64_t k = 0; k < K; ++k)
+        for (int64_t m = 0; m < K; ++m) {
+          double xv = 0.5 * alpha * (g[0] * d[k] * d[m] + g[1] * d[K + k] * d[K + m]);
+          Si[k * K + m] += xv;
+          Qi[k * K + m] += xv * xv;
+        }
+    }
+#pragma omp critical
+    {
+      for (int64_t e = 0; e < K * K; ++e) { Sj[e] += Si[e]; Qj[e] += Qi[e]; }
+    }
+    free(bs); free(d); free(Si); free(Qi);
+  }
+  /* killing term: walks from the image of infinity */
+  int64_t kq = 0;
+  if (kill_walks > 0) {
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+      double* b = (double*)malloc(sizeof(double) * K);
+      double* Sl = (double*)calloc(K * K, sizeof(double));
+      double* Ql = (double*)calloc(K * K, sizeof(double));
+      int64_t ql = 0;
+#pragma omp for schedule(dynamic, 64)
+      for (int64_t k = 0; k < kill_walks; ++k) {
+        double x[3] = {0, 0, 0}, q[3], l[3];
+        int64_t tt = -1, nq = 0;
+        kelvin_walk(sc, &P, 0xFFFFFFFFu, (uint32_t)k, x, &tt, q, l, &nq);
+        ql += nq;
+        double g = 4.0 * M_PI / sqrt(dot3(q, q)) / (double)kill_walks;
+        for (int64_t a = 0; a < K; ++a) {
+          b[a] = 0.0;
+          for (int cc = 0; cc < 3; ++cc) b[a] += l[cc] * tab[(int64_t)sc->F[3 * tt + cc] * K + a];
+        }
+        for (int64_t a = 0; a < K; ++a)
+          for (int64_t m = 0; m < K; ++m) {
+            double yv = g * b[a] * b[m];
+            Sl[a * K + m] += yv;
+            Ql[a * K + m] += yv * yv;
+          }
+      }
+#pragma omp critical
+      {
+        for (int64_t e = 0; e < K * K; ++e) { Sk[e] += Sl[e]; Qk[e] += Ql[e]; }
+        kq += ql;
+      }
+      free(b); free(Sl); free(Ql);
+    }
+  }
+  *kill_query = kq;
+}

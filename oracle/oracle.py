@@ -17,7 +17,10 @@ definition:
   smallest k eigenpairs of M^-1/2 (S + S^T)/2 M^-1/2 by LAPACK (numpy.eigh),
   eigenvectors mapped back by M^-1/2;
 * ``psd_estimate`` -- the PSD estimator of Sec. 3.2 (Alg. 2), run in
-  ``oracle.c``, with ``psd_standard_error`` for its entries.
+  ``oracle.c``, with ``psd_standard_error`` for its entries;
+* ``kelvin_estimate`` -- the exterior estimator of Sec. 3.3 in the
+  Kelvin-inverted exterior (jump term from tangent balls, killing term from
+  walks started at the image of infinity), run in ``oracle.c``.
 """
 from __future__ import annotations
 
@@ -103,6 +106,24 @@ def lib():
              C.c_double, C.c_double, C.c_int64, C.c_uint64, C.c_uint32, C.c_int]
             + [_P(C.c_double), _P(C.c_double), _P(C.c_double), _P(C.c_double), _P(C.c_int64)]
             + [_P(C.c_int32), _P(C.c_int64), _P(C.c_float), _P(C.c_int64)]
+        )
+        L.orc_kelvin_tri_d2.argtypes = [_P(C.c_double)] * 6
+        L.orc_kelvin_tri_d2.restype = C.c_double
+        L.orc_kelvin_create.argtypes = [_P(C.c_float), C.c_int64, _P(C.c_int32), C.c_int64, _P(C.c_double)]
+        L.orc_kelvin_create.restype = C.c_void_p
+        L.orc_kelvin_destroy.argtypes = [C.c_void_p]
+        L.orc_kelvin_info.argtypes = [C.c_void_p, _P(C.c_double), _P(C.c_double), _P(C.c_double)]
+        L.orc_kelvin_nearest.argtypes = [C.c_void_p, _P(C.c_double), C.c_int64, C.c_int, _P(C.c_int64),
+                                         _P(C.c_double), _P(C.c_double), _P(C.c_double)]
+        L.orc_kelvin_tangent_ball.argtypes = [C.c_void_p, _P(C.c_double), _P(C.c_double), C.c_double, C.c_int,
+                                              C.c_double]
+        L.orc_kelvin_tangent_ball.restype = C.c_double
+        L.orc_kelvin_point_normal.argtypes = [_P(C.c_double)] * 4
+        L.orc_kelvin_estimate.argtypes = (
+            [C.c_void_p, C.c_int64, _P(C.c_float), _P(C.c_float), _P(C.c_int32), _P(C.c_float), _P(C.c_double),
+             _P(C.c_double), C.c_int64, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_int, C.c_double,
+             C.c_double, C.c_double, C.c_int64, C.c_uint64, C.c_uint32, C.c_int]
+            + [_P(C.c_double)] * 6 + [_P(C.c_int64), _P(C.c_int64), _P(C.c_int32), _P(C.c_int64), _P(C.c_float)]
         )
         _lib = L
     return _lib
@@ -426,6 +447,121 @@ def psd_standard_error(S, Q, n_pairs):
     """Standard error of S = sum_p X_p over n_pairs pair terms, the pairs taken as
     independent draws of n_pairs X_p: se^2 = (n_pairs Q - S^2) / (n_pairs - 1)."""
     return np.sqrt(np.maximum(0.0, n_pairs * Q - S * S) / (n_pairs - 1.0))
+
+
+# ------------------------------------- Kelvin-inverted exterior (Sec. 3.3)
+
+
+def kelvin(x):
+    """Kelvin transform about the origin, x -> x / |x|^2 (Sec. 3.3, The Kelvin Transform)."""
+    x = np.asarray(x, dtype=np.float64)
+    return x / np.sum(x * x, axis=-1, keepdims=True)
+
+
+def kelvin_tri_d2(p, a, b, c):
+    """Squared distance from p to the image of triangle abc under the Kelvin
+    transform (all relative to the inversion centre), the nearest point q
+    and the barycentrics of its image in abc."""
+    args = [np.ascontiguousarray(x, dtype=np.float64) for x in (p, a, b, c)]
+    q, l = np.zeros(3), np.zeros(3)
+    d2 = lib().orc_kelvin_tri_d2(*[_ptr(x, C.c_double) for x in args], _ptr(q, C.c_double), _ptr(l, C.c_double))
+    return d2, q, l
+
+
+def kelvin_point_normal(s, ns):
+    """s~ = kappa(s) and the unit normal there pointing out of the inverted
+    exterior (s relative to the centre, ns the primal outward unit normal)."""
+    s, ns = _c(s, np.float64), _c(ns, np.float64)
+    st, nt = np.zeros(3), np.zeros(3)
+    lib().orc_kelvin_point_normal(_ptr(s, C.c_double), _ptr(ns, C.c_double), _ptr(st, C.c_double),
+                                  _ptr(nt, C.c_double))
+    return st, nt
+
+
+class KelvinScene:
+    """A mesh seen through the Kelvin transform about a centre inside it: the
+    inverted exterior, bounded by the images of the triangles (spherical
+    patches), with brute-force nearest-patch queries."""
+
+    def __init__(self, V, F, centre):
+        self.V = _c(V, np.float32)
+        self.F = _c(F, np.int32)
+        self.centre = _c(centre, np.float64)
+        self.h = lib().orc_kelvin_create(_ptr(self.V, C.c_float), self.V.shape[0], _ptr(self.F, C.c_int32),
+                                         self.F.shape[0], _ptr(self.centre, C.c_double))
+        lo, hi, r = np.zeros(3), np.zeros(3), np.zeros(1)
+        lib().orc_kelvin_info(self.h, _ptr(lo, C.c_double), _ptr(hi, C.c_double), _ptr(r, C.c_double))
+        self.lo, self.hi, self.radius = lo, hi, float(r[0])
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_kelvin_destroy(self.h)
+            self.h = None
+
+    def nearest(self, Q, bvh: bool = True):
+        """Nearest inverted triangle of points Q (inverted space, relative to
+        the centre): (index, squared distance, nearest point, primal
+        barycentrics); the BVH returns the brute-force minimum."""
+        Q = _c(Q, np.float64).reshape(-1, 3)
+        n = Q.shape[0]
+        tri, d2, q, l = np.zeros(n, dtype=np.int64), np.zeros(n), np.zeros((n, 3)), np.zeros((n, 3))
+        lib().orc_kelvin_nearest(self.h, _ptr(Q, C.c_double), n, int(bvh), _ptr(tri, C.c_int64),
+                                 _ptr(d2, C.c_double), _ptr(q, C.c_double), _ptr(l, C.c_double))
+        return tri, d2, q, l
+
+    def r_max(self):
+        """Largest tangent-ball radius: half the shortest side of the inverted
+        surface's bounding box (Appendix, unbounded tangent balls, for the
+        exterior), here the box of the inverted vertices."""
+        return 0.5 * float((self.hi - self.lo).min())
+
+
+def kelvin_estimate(ks: KelvinScene, rows, table, pairs: int, kill_walks: int, eps: float, seed: int = 0,
+                    cap_deg=PSD_CAP_DEG, r_max=None, bisect_iters=PSD_BISECT_ITERS, kappa=2.0 ** -20,
+                    delta_rel=2.0 ** -21, max_steps=None, mesh: int = 0, log: bool = False, nthreads: int = 1):
+    """The exterior estimate of Sec. 3.3 (eq. main-exterior-estimator) in the
+    Kelvin-inverted exterior, over point rows with a dense per-vertex table.
+    eps is the shell width in inverted-space units; the step guard is
+    delta_rel times the inverted domain's bound. Returns the jump term
+    ``S_jump`` and the killing term ``S_kill`` (K x K each) with their standard
+    errors, the full operator ``S = S_jump + S_kill``, per-row radii and query
+    counts."""
+    if rows.mode != "point":
+        raise ValueError("the exterior estimator takes point rows")
+    if max_steps is None:
+        max_steps = DEFAULT_MAX_STEPS["interior"]
+    if r_max is None:
+        r_max = ks.r_max()
+    tab = _c(table, np.float64)
+    K = tab.shape[1]
+    n = rows.n_rows
+    Sj, Qj, Sk, Qk = (np.zeros((K, K)) for _ in range(4))
+    rad, Z = np.zeros(n), np.zeros(n)
+    nq = np.zeros(n, dtype=np.int64)
+    kq = np.zeros(1, dtype=np.int64)
+    if log:
+        ls = np.full((n, 2 * pairs), -1, dtype=np.int32)
+        lt = np.full((n, 2 * pairs), -1, dtype=np.int64)
+        lb = np.zeros((n, 2 * pairs, 2), dtype=np.float32)
+    else:
+        ls = lt = lb = None
+    p, nn, tri, bary = (_c(rows.p, np.float32), _c(rows.n, np.float32), _c(rows.tri, np.int32),
+                        _c(rows.bary, np.float32))
+    w = _c(rows.w, np.float64)
+    lib().orc_kelvin_estimate(ks.h, n, _ptr(p, C.c_float), _ptr(nn, C.c_float), _ptr(tri, C.c_int32),
+                              _ptr(bary, C.c_float), _ptr(w, C.c_double), _ptr(tab, C.c_double), K, pairs,
+                              kill_walks, np.deg2rad(cap_deg), r_max, bisect_iters, eps, kappa,
+                              delta_rel * ks.radius, max_steps, C.c_uint64(seed), mesh, nthreads,
+                              _ptr(Sj, C.c_double), _ptr(Qj, C.c_double), _ptr(Sk, C.c_double), _ptr(Qk, C.c_double),
+                              _ptr(rad, C.c_double), _ptr(Z, C.c_double), _ptr(nq, C.c_int64), _ptr(kq, C.c_int64),
+                              _ptr(ls, C.c_int32), _ptr(lt, C.c_int64), _ptr(lb, C.c_float))
+    se_j = psd_standard_error(Sj, Qj, n * pairs)
+    se_k = psd_standard_error(Sk, Qk, kill_walks) if kill_walks > 1 else np.zeros_like(Sk)
+    out = dict(S_jump=Sj, se_jump=se_j, S_kill=Sk, se_kill=se_k, S=Sj + Sk, se=np.sqrt(se_j ** 2 + se_k ** 2),
+               radius=rad, Z=Z, n_query=nq, kill_queries=int(kq[0]), pairs=pairs, kill_walks=kill_walks)
+    if log:
+        out.update(log_status=ls, log_tri=lt, log_bary=lb)
+    return out
 
 
 # ------------------------------------------------------- point basis (k-NN)

@@ -587,6 +587,96 @@ msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* mesh, const msk_rows* 
                             int64_t pairs, double eps, const msk_dtn_opts* walk_opts, const msk_psd_opts* opts,
                             double* S, double* se, float* radius, const msk_psd_log* log, msk_psd_info* info);
 
+/* ---------------------------------------- Kelvin-inverted exterior (f2) */
+
+/* The exterior DtN form of Sec. 3.3 (eq. exterior-dtn-beurling-deny-form:
+ * a jump term and a killing term) estimated in the image of the exterior
+ * under the Kelvin transform x -> x / |x|^2 about a centre inside the shape
+ * (Sec. 3.3, The Kelvin Transform; Appendix, Kelvin transform): a bounded
+ * domain, bounded by the images of the triangles, each a piece of a sphere
+ * through the origin cut by three circular arcs (Sec. 4: spherical
+ * triangular elements with non-planar distance queries).
+ * msk_kelvin_create copies the mesh's triangles relative to `centre` (world,
+ * 3 doubles; it must lie inside the shape, off the surface) and builds a
+ * 4-wide hierarchy over boxes that contain their images (leaf_size 1..8, 0 =
+ * 4). Errors: INVALID_ARG for a centre on the surface or at a vertex, or a
+ * non-finite centre. All geometry of this path is FP64. */
+typedef struct msk_kelvin msk_kelvin;
+typedef struct {
+  double centre[3];     /* inversion centre (world)                         */
+  double radius;        /* bound of the inverted domain: max |x~| over its boundary */
+  double box_lo[3], box_hi[3]; /* box of the inverted vertices               */
+  double r_max;         /* default tangent-ball bound: half its shortest side */
+  int64_t n_tris, n_nodes;
+  int32_t depth, leaf_size;
+} msk_kelvin_info;
+msk_status msk_kelvin_create(msk_ctx* ctx, const msk_mesh* mesh, const double* centre, int32_t leaf_size,
+                             msk_kelvin** out);
+msk_status msk_kelvin_get_info(const msk_kelvin* kelvin, msk_kelvin_info* info);
+void msk_kelvin_destroy(msk_kelvin* kelvin);
+
+/* Exact nearest inverted element of each query point: lexicographic minimum
+ * of (FP64 squared distance, original index).
+ *   Q:    device, nq x 3 doubles, inverted space relative to the centre;
+ *   tri:  device, nq int32 original triangle index;
+ *   d2:   device, nq doubles, squared distance;
+ *   qpt:  device, nq x 3 doubles, the nearest point (inverted space);
+ *   bary: device, nq x 3 doubles, barycentrics of the nearest point's image
+ *         in the original triangle. */
+msk_status msk_kelvin_closest_points(msk_ctx* ctx, const msk_kelvin* kelvin, const double* Q, int64_t nq,
+                                     int32_t* tri, double* d2, double* qpt, double* bary);
+
+typedef struct {  /* optional host walk log, n_rows x 2 pairs jump walks then kill_walks */
+  int32_t* status;  /* 0 hit, 2 capped, -1 not run (row without a tangent ball) */
+  int32_t* tri;     /* terminal original triangle                           */
+  float* bary;      /* barycentrics of its vertices 1 and 2 at the terminal point's image (2 per walk) */
+  int32_t* queries;
+} msk_kelvin_log;
+
+typedef struct {
+  int64_t n_rows, K, pairs, kill_walks;
+  int64_t walks_total, queries_total, kill_queries, dropped_rows, capped_total;
+  double mean_radius, r_max;  /* inverted units                              */
+  double tangent_ms, walk_kernel_ms, product_ms;
+  int64_t nonfinite_entries;
+} msk_kelvin_est_info;
+
+/* The exterior estimate (Sec. 3.3, eq. main-exterior-estimator; Appendix,
+ * exterior jump kernel and killing measure) over point rows of the mesh:
+ *   - jump term: row i's sample s_i maps to s~_i = kappa(s_i - centre), with
+ *     the unit normal n~_i = -(n - 2 (s^ . n) s^) pointing out of the
+ *     inverted domain (n the outward normal); its tangent ball in the
+ *     inverted domain (bisection as for msk_estimate_psd: bound opts.r_max,
+ *     0 = half the shortest side of the inverted vertices' box; tolerance
+ *     min(eps/2, r/1024)) gets `pairs` antithetic pairs of ball points drawn
+ *     by the ball jump kernel outside the cap (Philox (row, pair, 0, purpose
+ *     4 << 24 | mesh_id)); walk 2j + a runs Walk-on-Spheres in the inverted
+ *     domain with the step streams of that walk index, ends at t~ in the
+ *     eps-shell (inverted units) and adds, per pair,
+ *       X_p = alpha_i (d_1 d_1^T / |t~_1| + d_2 d_2^T / |t~_2|) / 2,
+ *       alpha_i = w_i |s~_i|^3 Z_i / (2 pairs), d = b(s_i) - b(kappa(t~)),
+ *     Z_i = (1/(2 r_i)) (1/sin(cap/2) - 1) (eq. exterior-jump-kernel-final);
+ *   - killing term: kill_walks walks (even) start at the origin of the
+ *     inverted space (the image of infinity; Philox row 0xFFFFFFFF, walk k)
+ *     and add (4 pi / |t~_0|) b(t_0) b(t_0)^T / kill_walks (eq.
+ *     killing-measure-poisson-kernel).
+ * The full exterior form is S_jump + S_kill; the paper's default drops the
+ * killing term (Sec. 4). Standard errors: the pair terms (and the pairs of
+ * killing walks) taken as independent draws, se^2 = (n Q - S^2)/(n - 1).
+ *   S_jump, se_jump, S_kill, se_kill: host K x K doubles (se may be NULL;
+ *     S_kill NULL only with kill_walks = 0);
+ *   radius: host n_rows doubles (inverted tangent radii, 0 = dropped) or NULL;
+ *   log, info: optional.
+ * walk_opts: seed, max_steps (0 = 1024), kappa, delta_rel (the guard is
+ * delta_rel times the inverted domain's bound), mesh_id. Errors: INVALID_ARG
+ * for rows of another mesh, hat rows, a point basis, K > 8192, pairs < 1, an
+ * odd kill_walks, or eps at or below max(delta_rel R~ / (1 - kappa),
+ * 2^-40 R~); NUMERIC when an entry is not finite (outputs written). */
+msk_status msk_estimate_kelvin(msk_ctx* ctx, const msk_kelvin* kelvin, const msk_rows* rows, const msk_basis* basis,
+                               int64_t pairs, int64_t kill_walks, double eps, const msk_dtn_opts* walk_opts,
+                               const msk_psd_opts* opts, double* S_jump, double* se_jump, double* S_kill,
+                               double* se_kill, double* radius, const msk_kelvin_log* log, msk_kelvin_est_info* info);
+
 #ifdef __cplusplus
 }
 #endif

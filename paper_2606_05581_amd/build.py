@@ -7,8 +7,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsk.so")
-SOURCES = ["walk.hip", "psd.hip", "laplace.hip", "spectral.hip", "eigen.hip", "noalloc.hip", "capi.cpp",
-           "bvh_build.cpp", "symeig_host.cpp"]
+SOURCES = ["walk.hip", "psd.hip", "laplace.hip", "spectral.hip", "eigen.hip", "noalloc.hip", "kelvin.hip",
+           "capi.cpp", "bvh_build.cpp", "symeig_host.cpp"]
 LIBS = []
 
 HIPCC_FLAGS = [
@@ -28,7 +28,7 @@ def walk_sources_sha() -> str:
     results and measured traffic records are keyed by it, so that any edit
     of the kernels invalidates them."""
     h = hashlib.sha256()
-    for name in ("walk.hip", "msk_internal.h"):
+    for name in ("walk.hip", "msk_internal.h", "philox.h"):
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -155,60 +155,17 @@ struct Builder {
 
 }  // namespace
 
-std::string build_bvh_host(const float* V, int64_t nv, const int32_t* F, int64_t nf, int leaf_size, HostBvh& out) {
-  if (nv < 3 || nf < 1) return "mesh needs at least 3 vertices and 1 triangle";
-  // the walk kernel packs a triangle slot and a lane into one 32-bit word
-  if (nf >= (int64_t)1 << 26) return "too many triangles (a mesh holds at most 2^26 - 1)";
+std::string build_bvh_boxes(const std::vector<Box3f>& boxes, const std::vector<float>& cen, int leaf_size,
+                            std::vector<Node4>& nodes_out, std::vector<int32_t>& leaf_order, int& depth) {
+  if (boxes.empty()) return "no elements";
   if (leaf_size < 1 || leaf_size > 8) return "leaf_size must be in 1..8";
-  out.leaf_size = leaf_size;
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int64_t i = 0; i < nv; ++i)
+  std::vector<Box> tb(boxes.size());
+  for (size_t i = 0; i < boxes.size(); ++i)
     for (int k = 0; k < 3; ++k) {
-      double x = V[3 * i + k];
-      if (!std::isfinite(x)) return "vertex coordinates must be finite";
-      lo[k] = std::min(lo[k], x);
-      hi[k] = std::max(hi[k], x);
+      tb[i].lo[k] = boxes[i].lo[k];
+      tb[i].hi[k] = boxes[i].hi[k];
     }
-  for (int k = 0; k < 3; ++k) out.centre[k] = 0.5 * (lo[k] + hi[k]);
-  double r2 = 0;
-  for (int64_t i = 0; i < nv; ++i) {
-    double d0 = V[3 * i] - out.centre[0], d1 = V[3 * i + 1] - out.centre[1], d2 = V[3 * i + 2] - out.centre[2];
-    r2 = std::max(r2, d0 * d0 + d1 * d1 + d2 * d2);
-  }
-  out.radius = (1.0 + std::ldexp(1.0, -20)) * std::sqrt(r2);
-  std::vector<float> Vr((size_t)nv * 3);
-  for (int64_t i = 0; i < nv; ++i)
-    for (int k = 0; k < 3; ++k) Vr[3 * i + k] = (float)((double)V[3 * i + k] - out.centre[k]);
-
-  std::vector<Box> tb((size_t)nf);
-  std::vector<float> cen((size_t)nf * 3);
-  double area = 0;
-  for (int64_t t = 0; t < nf; ++t) {
-    tb[t].reset();
-    double c[3] = {0, 0, 0}, P[3][3];
-    for (int j = 0; j < 3; ++j) {
-      int64_t v = F[3 * t + j];
-      if (v < 0 || v >= nv) return "face index out of range";
-      for (int k = 0; k < 3; ++k) {
-        float x = Vr[3 * v + k];
-        tb[t].lo[k] = std::min(tb[t].lo[k], x);
-        tb[t].hi[k] = std::max(tb[t].hi[k], x);
-        c[k] += x;
-        P[j][k] = V[3 * v + k];
-      }
-    }
-    for (int k = 0; k < 3; ++k) cen[3 * t + k] = (float)(c[k] / 3.0);
-    double e1[3], e2[3];
-    for (int k = 0; k < 3; ++k) {
-      e1[k] = P[1][k] - P[0][k];
-      e2[k] = P[2][k] - P[0][k];
-    }
-    double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2], cz = e1[0] * e2[1] - e1[1] * e2[0];
-    area += 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
-  }
-  if (!(area > 0)) return "mesh has zero total area";
-  out.area = area;
-
+  const int64_t nf = (int64_t)tb.size();
   std::vector<int32_t> order((size_t)nf);
   for (int64_t i = 0; i < nf; ++i) order[i] = (int32_t)i;
   Builder bld(tb, cen, order, leaf_size);
@@ -220,16 +177,15 @@ std::string build_bvh_host(const float* V, int64_t nv, const int32_t* F, int64_t
   // four binary descendants by repeatedly opening the largest inner child.
   struct WItem { int32_t bin; int32_t depth; };
   std::vector<WItem> queue;
-  out.nodes.clear();
+  nodes_out.clear();
   std::vector<int32_t> wide_of;  // queue index == wide node index
   queue.push_back({0, 1});
   size_t head = 0;
   int maxdepth = 0;
   std::vector<int32_t> leaf_first, leaf_count;
   // leaf order assigned in BFS order of leaves
-  std::vector<TriRec> tris;
-  tris.reserve((size_t)nf);
-  out.slot_of_tri.assign((size_t)nf, -1);
+  leaf_order.clear();
+  leaf_order.reserve((size_t)nf);
   while (head < queue.size()) {
     WItem it = queue[head++];
     maxdepth = std::max(maxdepth, it.depth);
@@ -267,19 +223,8 @@ std::string build_bvh_host(const float* V, int64_t nv, const int32_t* F, int64_t
       w.lox[k] = c.box.lo[0]; w.loy[k] = c.box.lo[1]; w.loz[k] = c.box.lo[2];
       w.hix[k] = c.box.hi[0]; w.hiy[k] = c.box.hi[1]; w.hiz[k] = c.box.hi[2];
       if (c.left < 0) {
-        int32_t first = (int32_t)tris.size();
-        for (int32_t i = c.first; i < c.first + c.count; ++i) {
-          int32_t t = order[i];
-          TriRec r;
-          const int32_t* f = F + 3 * (int64_t)t;
-          r.a = make_float4(Vr[3 * f[0]], Vr[3 * f[0] + 1], Vr[3 * f[0] + 2], 0.f);
-          r.b = make_float4(Vr[3 * f[1]], Vr[3 * f[1] + 1], Vr[3 * f[1] + 2], 0.f);
-          r.c = make_float4(Vr[3 * f[2]], Vr[3 * f[2] + 1], Vr[3 * f[2] + 2], 0.f);
-          int32_t ti = t;
-          std::memcpy(&r.a.w, &ti, 4);
-          out.slot_of_tri[t] = (int32_t)tris.size();
-          tris.push_back(r);
-        }
+        int32_t first = (int32_t)leaf_order.size();
+        for (int32_t i = c.first; i < c.first + c.count; ++i) leaf_order.push_back(order[i]);
         w.child[k] = -first - 1;
         w.count[k] = c.count;
       } else {
@@ -287,13 +232,91 @@ std::string build_bvh_host(const float* V, int64_t nv, const int32_t* F, int64_t
         queue.push_back({kids[k], it.depth + 1});
       }
     }
-    out.nodes.push_back(w);
+    nodes_out.push_back(w);
   }
-  out.tris.swap(tris);
-  out.depth = maxdepth;
-  if ((int64_t)out.tris.size() != nf) return "internal error: triangle count mismatch";
+  depth = maxdepth;
+  if (leaf_order.size() != tb.size()) return "internal error: element count mismatch";
   // traversal stack: at most 3 pending siblings per level (with margin)
   if (3 * maxdepth + 5 > kStackDepth) return "BVH too deep for the traversal stack";
+  return "";
+}
+
+std::string build_bvh_host(const float* V, int64_t nv, const int32_t* F, int64_t nf, int leaf_size, HostBvh& out) {
+  if (nv < 3 || nf < 1) return "mesh needs at least 3 vertices and 1 triangle";
+  // the walk kernel packs a triangle slot and a lane into one 32-bit word
+  if (nf >= (int64_t)1 << 26) return "too many triangles (a mesh holds at most 2^26 - 1)";
+  if (leaf_size < 1 || leaf_size > 8) return "leaf_size must be in 1..8";
+  out.leaf_size = leaf_size;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = 0; i < nv; ++i)
+    for (int k = 0; k < 3; ++k) {
+      double x = V[3 * i + k];
+      if (!std::isfinite(x)) return "vertex coordinates must be finite";
+      lo[k] = std::min(lo[k], x);
+      hi[k] = std::max(hi[k], x);
+    }
+  for (int k = 0; k < 3; ++k) out.centre[k] = 0.5 * (lo[k] + hi[k]);
+  double r2 = 0;
+  for (int64_t i = 0; i < nv; ++i) {
+    double d0 = V[3 * i] - out.centre[0], d1 = V[3 * i + 1] - out.centre[1], d2 = V[3 * i + 2] - out.centre[2];
+    r2 = std::max(r2, d0 * d0 + d1 * d1 + d2 * d2);
+  }
+  out.radius = (1.0 + std::ldexp(1.0, -20)) * std::sqrt(r2);
+  std::vector<float> Vr((size_t)nv * 3);
+  for (int64_t i = 0; i < nv; ++i)
+    for (int k = 0; k < 3; ++k) Vr[3 * i + k] = (float)((double)V[3 * i + k] - out.centre[k]);
+
+  std::vector<Box3f> tb((size_t)nf);
+  std::vector<float> cen((size_t)nf * 3);
+  double area = 0;
+  for (int64_t t = 0; t < nf; ++t) {
+    for (int k = 0; k < 3; ++k) {
+      tb[t].lo[k] = std::numeric_limits<float>::infinity();
+      tb[t].hi[k] = -std::numeric_limits<float>::infinity();
+    }
+    double c[3] = {0, 0, 0}, P[3][3];
+    for (int j = 0; j < 3; ++j) {
+      int64_t v = F[3 * t + j];
+      if (v < 0 || v >= nv) return "face index out of range";
+      for (int k = 0; k < 3; ++k) {
+        float x = Vr[3 * v + k];
+        tb[t].lo[k] = std::min(tb[t].lo[k], x);
+        tb[t].hi[k] = std::max(tb[t].hi[k], x);
+        c[k] += x;
+        P[j][k] = V[3 * v + k];
+      }
+    }
+    for (int k = 0; k < 3; ++k) cen[3 * t + k] = (float)(c[k] / 3.0);
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+      e1[k] = P[1][k] - P[0][k];
+      e2[k] = P[2][k] - P[0][k];
+    }
+    double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2], cz = e1[0] * e2[1] - e1[1] * e2[0];
+    area += 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+  }
+  if (!(area > 0)) return "mesh has zero total area";
+  out.area = area;
+
+  std::vector<int32_t> leaf_order;
+  std::string err = build_bvh_boxes(tb, cen, leaf_size, out.nodes, leaf_order, out.depth);
+  if (!err.empty()) return err;
+  std::vector<TriRec> tris(leaf_order.size());
+  out.slot_of_tri.assign((size_t)nf, -1);
+  for (size_t slot = 0; slot < leaf_order.size(); ++slot) {
+    const int32_t t = leaf_order[slot];
+    TriRec r;
+    const int32_t* f = F + 3 * (int64_t)t;
+    r.a = make_float4(Vr[3 * f[0]], Vr[3 * f[0] + 1], Vr[3 * f[0] + 2], 0.f);
+    r.b = make_float4(Vr[3 * f[1]], Vr[3 * f[1] + 1], Vr[3 * f[1] + 2], 0.f);
+    r.c = make_float4(Vr[3 * f[2]], Vr[3 * f[2] + 1], Vr[3 * f[2] + 2], 0.f);
+    int32_t ti = t;
+    std::memcpy(&r.a.w, &ti, 4);
+    out.slot_of_tri[t] = (int32_t)slot;
+    tris[slot] = r;
+  }
+  out.tris.swap(tris);
+  if ((int64_t)out.tris.size() != nf) return "internal error: triangle count mismatch";
   return "";
 }
 

@@ -46,6 +46,7 @@ struct msk_rows {
   int64_t n = 0;
   std::vector<double> w;
   std::vector<int32_t> order;    // Z-order of the rows
+  std::vector<float> p_world, n_world;  // point rows: host copies of the samples and normals
   double* d_w = nullptr;
   float* d_p = nullptr;
   float* d_n = nullptr;
@@ -307,6 +308,8 @@ extern "C" msk_status msk_rows_create(msk_ctx* ctx, const msk_mesh* m, const msk
       }
       for (int k = 0; k < 3; ++k) pos[3 * i + k] = (float)((double)d->p[3 * i + k] - m->centre[k]);
     }
+    r->p_world.assign(d->p, d->p + 3 * n);
+    r->n_world.assign(d->n, d->n + 3 * n);
     if ((he = upload(ctx, &r->d_p, pos.data(), pos.size())) != hipSuccess ||
         (he = upload(ctx, &r->d_n, d->n, (size_t)n * 3)) != hipSuccess ||
         (he = upload(ctx, &r->d_tri, d->tri, (size_t)n)) != hipSuccess ||
@@ -1535,7 +1538,7 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   }
   HIP_P(hipEventRecord(ev[2], s));
   // rank-one updates: gather a chunk of pairs, then S += U^T U, Q += V^T V
-  PsdGather G;
+  PsdGather G{};
   G.tab = d_tab;
   G.K = K;
   G.Kp = Kp;
@@ -1634,6 +1637,463 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   const bool bad = I.nonfinite_entries > 0;
   cleanup(MSK_OK);
   if (bad) return fail(ctx, MSK_ERR_NUMERIC, "non-finite entries in S or se");
+  return MSK_OK;
+}
+
+// ------------------------------------------- Kelvin-inverted exterior
+
+struct msk_kelvin {
+  msk_ctx* ctx = nullptr;
+  const msk_mesh* mesh = nullptr;
+  double centre[3] = {0, 0, 0};
+  double radius = 0;                // bound of the inverted domain
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // box of the inverted vertices
+  int32_t depth = 0, leaf_size = 4;
+  int64_t n_nodes = 0;
+  Node4* d_nodes = nullptr;
+  KelvinTri* d_tris = nullptr;
+};
+
+namespace {
+
+double dot3d(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Squared distance from the origin to triangle (A, B, C): the nearest point
+// of the plane if it lies inside, else of the three edges.
+double origin_tri_d2(const double* A, const double* B, const double* C) {
+  const double* P[3] = {A, B, C};
+  double best = INFINITY;
+  for (int e = 0; e < 3; ++e) {
+    const double* p0 = P[e];
+    const double* p1 = P[(e + 1) % 3];
+    double d[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+    const double dd = dot3d(d, d);
+    double t = dd > 0 ? -dot3d(p0, d) / dd : 0.0;
+    t = std::min(1.0, std::max(0.0, t));
+    const double q[3] = {p0[0] + t * d[0], p0[1] + t * d[1], p0[2] + t * d[2]};
+    best = std::min(best, dot3d(q, q));
+  }
+  const double ab[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]}, ac[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+  const double n[3] = {ab[1] * ac[2] - ab[2] * ac[1], ab[2] * ac[0] - ab[0] * ac[2], ab[0] * ac[1] - ab[1] * ac[0]};
+  const double nn = dot3d(n, n);
+  if (nn > 0) {
+    const double t = dot3d(n, A) / nn;  // foot of the origin on the plane: t n
+    const double f[3] = {t * n[0], t * n[1], t * n[2]};
+    // inside test by the signs of the sub-triangle areas
+    auto side = [&](const double* u, const double* v) {
+      const double a[3] = {u[0] - f[0], u[1] - f[1], u[2] - f[2]}, b[3] = {v[0] - f[0], v[1] - f[1], v[2] - f[2]};
+      const double c[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+      return dot3d(c, n);
+    };
+    const double s0 = side(A, B), s1 = side(B, C), s2 = side(C, A);
+    if ((s0 >= 0 && s1 >= 0 && s2 >= 0) || (s0 <= 0 && s1 <= 0 && s2 <= 0)) best = std::min(best, dot3d(f, f));
+  }
+  return best;
+}
+
+float round_down(double x) {
+  float f = (float)x;
+  return (double)f > x ? std::nextafter(f, -INFINITY) : f;
+}
+float round_up(double x) {
+  float f = (float)x;
+  return (double)f < x ? std::nextafter(f, INFINITY) : f;
+}
+
+}  // namespace
+
+extern "C" msk_status msk_kelvin_create(msk_ctx* ctx, const msk_mesh* m, const double* centre, int32_t leaf_size,
+                                        msk_kelvin** out) {
+  if (!ctx || !out) return MSK_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!m || !centre) return fail(ctx, MSK_ERR_INVALID_ARG, "null mesh or centre");
+  if (!std::isfinite(centre[0]) || !std::isfinite(centre[1]) || !std::isfinite(centre[2]))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "the inversion centre must be finite");
+  if (leaf_size == 0) leaf_size = 4;
+  if (leaf_size < 1 || leaf_size > 8) return fail(ctx, MSK_ERR_INVALID_ARG, "leaf_size must be in 1..8");
+  const int64_t nf = m->nf;
+  std::vector<KelvinTri> rec((size_t)nf);
+  std::vector<Box3f> boxes((size_t)nf);
+  std::vector<float> cen((size_t)nf * 3);
+  double dmin = INFINITY, lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double rmax = 0;
+  for (int64_t v = 0; v < m->nv; ++v) {
+    double x[3];
+    for (int k = 0; k < 3; ++k) x[k] = (double)m->vworld[3 * v + k] - centre[k];
+    const double r2 = dot3d(x, x);
+    if (!(r2 > 0)) return fail(ctx, MSK_ERR_INVALID_ARG, "the inversion centre is a mesh vertex");
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], x[k] / r2);
+      hi[k] = std::max(hi[k], x[k] / r2);
+    }
+    rmax = std::max(rmax, 1.0 / std::sqrt(r2));
+  }
+  for (int64_t t = 0; t < nf; ++t) {
+    KelvinTri& T = rec[t];
+    double* P[3] = {T.a, T.b, T.c};
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) P[j][k] = (double)m->vworld[3 * (int64_t)m->faces[3 * t + j] + k] - centre[k];
+    T.orig = (int32_t)t;
+    T.pad = 0;
+    // a box containing the image: each coordinate of y / |y|^2 over the
+    // triangle is a quotient of a value in the coordinate's range by one in
+    // [m2, M2] (squared distances from the centre)
+    const double m2 = origin_tri_d2(T.a, T.b, T.c);
+    const double M2 = std::max(dot3d(T.a, T.a), std::max(dot3d(T.b, T.b), dot3d(T.c, T.c)));
+    dmin = std::min(dmin, m2);
+    if (!(m2 > 0)) return fail(ctx, MSK_ERR_INVALID_ARG, "the inversion centre lies on the surface (triangle " +
+                                                          std::to_string(t) + ")");
+    for (int k = 0; k < 3; ++k) {
+      const double a = std::min(T.a[k], std::min(T.b[k], T.c[k])), b = std::max(T.a[k], std::max(T.b[k], T.c[k]));
+      double l, h;
+      if (a >= 0) { l = a / M2; h = b / m2; }
+      else if (b <= 0) { l = a / m2; h = b / M2; }
+      else { l = a / m2; h = b / m2; }
+      const double pad = 1e-12 * (std::fabs(l) + std::fabs(h));
+      boxes[t].lo[k] = round_down(l - pad);
+      boxes[t].hi[k] = round_up(h + pad);
+      cen[3 * t + k] = (float)(0.5 * (l + h));
+    }
+  }
+  std::vector<Node4> nodes;
+  std::vector<int32_t> leaf_order;
+  int depth = 0;
+  std::string err = build_bvh_boxes(boxes, cen, leaf_size, nodes, leaf_order, depth);
+  if (!err.empty()) return fail(ctx, MSK_ERR_INVALID_ARG, "inverted BVH: " + err);
+  std::vector<KelvinTri> ordered(leaf_order.size());
+  for (size_t i = 0; i < leaf_order.size(); ++i) ordered[i] = rec[leaf_order[i]];
+  msk_kelvin* K = new msk_kelvin();
+  K->ctx = ctx;
+  K->mesh = m;
+  for (int k = 0; k < 3; ++k) {
+    K->centre[k] = centre[k];
+    K->lo[k] = lo[k];
+    K->hi[k] = hi[k];
+  }
+  K->radius = std::max(rmax, 1.0 / std::sqrt(dmin));
+  K->depth = depth;
+  K->leaf_size = leaf_size;
+  K->n_nodes = (int64_t)nodes.size();
+  hipError_t he;
+  if ((he = upload(ctx, &K->d_nodes, nodes.data(), nodes.size())) != hipSuccess ||
+      (he = upload(ctx, &K->d_tris, ordered.data(), ordered.size())) != hipSuccess) {
+    msk_kelvin_destroy(K);
+    return fail(ctx, he == hipErrorOutOfMemory ? MSK_ERR_OOM : MSK_ERR_DEVICE,
+                std::string("inverted mesh upload: ") + hipGetErrorString(he));
+  }
+  *out = K;
+  return MSK_OK;
+}
+
+extern "C" msk_status msk_kelvin_get_info(const msk_kelvin* K, msk_kelvin_info* info) {
+  if (!K || !info) return MSK_ERR_INVALID_ARG;
+  std::memset(info, 0, sizeof(*info));
+  for (int k = 0; k < 3; ++k) {
+    info->centre[k] = K->centre[k];
+    info->box_lo[k] = K->lo[k];
+    info->box_hi[k] = K->hi[k];
+  }
+  info->radius = K->radius;
+  info->r_max = 0.5 * std::min(K->hi[0] - K->lo[0], std::min(K->hi[1] - K->lo[1], K->hi[2] - K->lo[2]));
+  info->n_tris = K->mesh->nf;
+  info->n_nodes = K->n_nodes;
+  info->depth = K->depth;
+  info->leaf_size = K->leaf_size;
+  return MSK_OK;
+}
+
+extern "C" void msk_kelvin_destroy(msk_kelvin* K) {
+  if (!K) return;
+  dfree(K->d_nodes);
+  dfree(K->d_tris);
+  delete K;
+}
+
+static KelvinDev kelvin_dev(const msk_kelvin* K, double eps, const msk_dtn_opts& o) {
+  KelvinDev D;
+  std::memset(&D, 0, sizeof(D));
+  D.nodes = K->d_nodes;
+  D.tris = K->d_tris;
+  D.n_tris = K->mesh->nf;
+  D.radius = K->radius;
+  D.eps2 = eps * eps;
+  D.kappa = o.kappa;
+  D.delta = o.delta_rel * K->radius;
+  D.max_steps = o.max_steps > 0 ? o.max_steps : 1024;
+  D.mesh_id = (uint32_t)o.mesh_id;
+  D.seed_lo = (uint32_t)o.seed;
+  D.seed_hi = (uint32_t)(o.seed >> 32);
+  return D;
+}
+
+extern "C" msk_status msk_kelvin_closest_points(msk_ctx* ctx, const msk_kelvin* K, const double* Q, int64_t nq,
+                                                int32_t* tri, double* d2, double* qpt, double* bary) {
+  if (!ctx || !K) return MSK_ERR_INVALID_ARG;
+  if (nq < 0 || (nq > 0 && (!Q || !tri || !d2 || !qpt || !bary)))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "bad query arrays");
+  if (nq == 0) return MSK_OK;
+  msk_dtn_opts o;
+  msk_dtn_opts_default(&o);
+  HIP_TRY(ctx, launch_kelvin_closest(kelvin_dev(K, 0.0, o), Q, nq, tri, d2, qpt, bary, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MSK_OK;
+}
+
+extern "C" msk_status msk_estimate_kelvin(msk_ctx* ctx, const msk_kelvin* K, const msk_rows* r, const msk_basis* b,
+                                          int64_t pairs, int64_t kill_walks, double eps,
+                                          const msk_dtn_opts* walk_opts, const msk_psd_opts* opts, double* S_jump,
+                                          double* se_jump, double* S_kill, double* se_kill, double* radius_out,
+                                          const msk_kelvin_log* log_out, msk_kelvin_est_info* info) {
+  if (!ctx) return MSK_ERR_INVALID_ARG;
+  if (!K || !r || !b) return fail(ctx, MSK_ERR_INVALID_ARG, "null inverted mesh, rows or basis");
+  if (!S_jump) return fail(ctx, MSK_ERR_INVALID_ARG, "S_jump must be given");
+  if (r->mesh != K->mesh) return fail(ctx, MSK_ERR_INVALID_ARG, "rows were created for another mesh");
+  if (r->mode != MSK_ROWS_POINT) return fail(ctx, MSK_ERR_INVALID_ARG, "the exterior estimator takes point rows");
+  if (b->knn_mesh || !b->d_rowptr) return fail(ctx, MSK_ERR_INVALID_ARG, "a per-vertex table basis is required");
+  if (b->nv != K->mesh->nv) return fail(ctx, MSK_ERR_INVALID_ARG, "basis vertex count differs from the mesh's");
+  if (b->K > 8192) return fail(ctx, MSK_ERR_INVALID_ARG, "K <= 8192 basis functions");
+  if (pairs < 1 || 2 * pairs > ((int64_t)1 << 31) || r->n * 2 * pairs >= ((int64_t)1 << 40))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "need 1 <= pairs and fewer than 2^40 walks");
+  if (kill_walks < 0 || kill_walks % 2 != 0 || kill_walks > ((int64_t)1 << 31))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "kill_walks must be even, in 0..2^31");
+  if (kill_walks > 0 && !S_kill) return fail(ctx, MSK_ERR_INVALID_ARG, "S_kill must be given with kill_walks > 0");
+  msk_psd_opts po;
+  msk_psd_opts_default(&po);
+  if (opts) po = *opts;
+  if (!(po.cap_deg > 0.0 && po.cap_deg < 180.0)) return fail(ctx, MSK_ERR_INVALID_ARG, "cap_deg must be in (0, 180)");
+  if (po.bisect_iters < 1 || po.bisect_iters > 40) return fail(ctx, MSK_ERR_INVALID_ARG, "bisect_iters in 1..40");
+  msk_dtn_opts o;
+  msk_dtn_opts_default(&o);
+  if (walk_opts) o = *walk_opts;
+  if (!(o.kappa >= 0.0 && o.kappa < 0.5 && o.delta_rel >= 0.0 && o.delta_rel < 0.25))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "need 0 <= kappa < 1/2 and 0 <= delta_rel < 1/4");
+  if (o.mesh_id < 0 || o.mesh_id > 0xFFFFFF) return fail(ctx, MSK_ERR_INVALID_ARG, "mesh_id must be < 2^24");
+  // the step guard and the FP64 resolution of the inverted scene bound the shell
+  const double eps_floor = std::max(o.delta_rel * K->radius / (1.0 - o.kappa), std::ldexp(K->radius, -40));
+  if (!(eps > eps_floor) || !std::isfinite(eps))
+    return fail(ctx, MSK_ERR_INVALID_ARG, "eps must exceed " + std::to_string(eps_floor) +
+                                              " (inverted units: the step guard and the FP64 resolution)");
+  const int64_t n = r->n, K_ = b->K, Kp = (K_ + 63) / 64 * 64;
+  const int64_t n_jump = n * 2 * pairs, n_walk = n_jump + kill_walks;
+  double r_max = po.r_max;
+  if (!(r_max > 0.0)) r_max = 0.5 * std::min(K->hi[0] - K->lo[0], std::min(K->hi[1] - K->lo[1], K->hi[2] - K->lo[2]));
+  if (!(r_max > 0.0)) return fail(ctx, MSK_ERR_INVALID_ARG, "flat inverted surface: no tangent balls");
+  // samples and image normals (host, FP64, relative to the centre)
+  std::vector<double> st((size_t)n * 3), nt((size_t)n * 3), s3((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    double s[3], nn[3];
+    for (int k = 0; k < 3; ++k) {
+      s[k] = (double)r->p_world[3 * i + k] - K->centre[k];
+      nn[k] = r->n_world[3 * i + k];
+    }
+    const double sl = std::sqrt(dot3d(s, s)), nl = std::sqrt(dot3d(nn, nn));
+    if (!(sl > 0) || !(nl > 0)) return fail(ctx, MSK_ERR_INVALID_ARG, "row " + std::to_string(i) + " at the centre");
+    const double sh[3] = {s[0] / sl, s[1] / sl, s[2] / sl};
+    for (int k = 0; k < 3; ++k) nn[k] /= nl;
+    const double sn = dot3d(sh, nn);
+    for (int k = 0; k < 3; ++k) {
+      st[3 * i + k] = s[k] / (sl * sl);
+      nt[3 * i + k] = -(nn[k] - 2.0 * sn * sh[k]);
+    }
+    s3[i] = 1.0 / (sl * sl * sl);
+  }
+  const double u0 = std::sin(0.5 * po.cap_deg * M_PI / 180.0);
+  double *d_st = nullptr, *d_nt = nullptr, *d_rad = nullptr, *d_g = nullptr, *d_alpha = nullptr, *d_kalpha = nullptr;
+  int32_t *d_ls = nullptr, *d_lt = nullptr, *d_lq = nullptr, *d_ktri = nullptr;
+  float *d_lb = nullptr, *d_tab = nullptr, *d_kbary = nullptr;
+  unsigned long long *d_rq = nullptr, *d_tq = nullptr, *d_kq = nullptr, *d_nonf = nullptr;
+  double *d_S = nullptr, *d_Q = nullptr, *d_se = nullptr, *d_PS = nullptr, *d_PQ = nullptr, *d_U = nullptr,
+         *d_V = nullptr;
+  hipEvent_t ev[5] = {};
+  auto cleanup = [&](msk_status s_) {
+    dfree(d_st); dfree(d_nt); dfree(d_rad); dfree(d_g); dfree(d_alpha); dfree(d_kalpha);
+    dfree(d_ls); dfree(d_lt); dfree(d_lq); dfree(d_ktri); dfree(d_lb); dfree(d_tab); dfree(d_kbary);
+    dfree(d_rq); dfree(d_tq); dfree(d_kq); dfree(d_nonf);
+    dfree(d_S); dfree(d_Q); dfree(d_se); dfree(d_PS); dfree(d_PQ); dfree(d_U); dfree(d_V);
+    for (hipEvent_t& e : ev) {
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;
+    }
+    return s_;
+  };
+#define HIP_K(expr)                                                                                   \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess)                                                                             \
+      return cleanup(fail(ctx, e_ == hipErrorOutOfMemory ? MSK_ERR_OOM : MSK_ERR_DEVICE,             \
+                          std::string(#expr) + ": " + hipGetErrorString(e_)));                        \
+  } while (0)
+  hipStream_t s = ctx->stream;
+  for (hipEvent_t& e : ev) HIP_K(hipEventCreate(&e));
+  HIP_K(upload(ctx, &d_st, st.data(), st.size()));
+  HIP_K(upload(ctx, &d_nt, nt.data(), nt.size()));
+  HIP_K(dalloc(&d_rad, n));
+  HIP_K(dalloc(&d_tq, n));
+  HIP_K(dalloc(&d_rq, n));
+  HIP_K(dalloc(&d_kq, 1));
+  HIP_K(dalloc(&d_nonf, 1));
+  HIP_K(dalloc(&d_g, n_walk));
+  HIP_K(dalloc(&d_ls, n_walk));
+  HIP_K(dalloc(&d_lt, n_walk));
+  HIP_K(dalloc(&d_lq, n_walk));
+  HIP_K(dalloc(&d_lb, 2 * n_walk));
+  HIP_K(dalloc(&d_tab, b->nv * K_));
+  HIP_K(dalloc(&d_S, K_ * K_));
+  HIP_K(dalloc(&d_Q, K_ * K_));
+  HIP_K(dalloc(&d_se, K_ * K_));
+  HIP_K(hipEventRecord(ev[0], s));
+  HIP_K(launch_fill_u32(d_tab, b->nv * K_, 0, s));
+  HIP_K(launch_dense_table(b->d_rowptr, b->d_col, b->d_val, b->nv, K_, d_tab, s));
+  HIP_K(launch_fill_u64(d_rq, n, 0, s));
+  HIP_K(launch_fill_u64(d_kq, 1, 0, s));
+  const KelvinDev D = kelvin_dev(K, eps, o);
+  HIP_K(launch_kelvin_tangent(D, d_st, d_nt, n, r_max, po.bisect_iters, 0.5 * eps, d_rad, d_tq, s));
+  HIP_K(hipEventRecord(ev[1], s));
+  HIP_K(launch_kelvin_walks(D, d_st, d_nt, d_rad, n, pairs, u0, kill_walks, d_ls, d_lt, d_lb, d_lq, d_g, d_rq, d_kq,
+                            s));
+  HIP_K(hipEventRecord(ev[2], s));
+  std::vector<double> rad((size_t)n);
+  HIP_K(hipMemcpyAsync(rad.data(), d_rad, n * 8, hipMemcpyDeviceToHost, s));
+  HIP_K(hipStreamSynchronize(s));
+  // alpha_i = w_i |s~_i|^3 Z_i / (2 pairs), Z_i = (1 / (2 r_i)) (1 / u0 - 1)
+  std::vector<double> alpha((size_t)n, 0.0);
+  int64_t dropped = 0;
+  double rsum = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (rad[i] > 0) {
+      alpha[i] = r->w[i] * s3[i] * (1.0 / (2.0 * rad[i])) * (1.0 / u0 - 1.0) / (2.0 * (double)pairs);
+      rsum += rad[i];
+    } else {
+      ++dropped;
+    }
+  }
+  HIP_K(upload(ctx, &d_alpha, alpha.data(), alpha.size()));
+  // products of one term: fused (K <= 384) or gathered in chunks, then the
+  // partial slots reduced into S and Q, and the standard error
+  float prod_ms_total = 0;
+  auto products = [&](const PsdGather& G, int64_t n_pairs, double* S_host, double* se_host) -> msk_status {
+    const int64_t nblk = psd_blocks(Kp);
+    const int64_t fused_slots = psd_fused_slots(Kp, n_pairs);
+    const bool fused = fused_slots > 0;
+    const int64_t chunk = std::min<int64_t>(std::max<int64_t>(1, po.chunk_pairs), n_pairs);
+    const int64_t slices = std::max<int64_t>(1, std::min<int64_t>(1024, ((int64_t)1 << 28) / (nblk * 32768 * 4)));
+    const int64_t n_slots = fused ? fused_slots : 4 * slices;
+    dfree(d_PS); dfree(d_PQ); dfree(d_U); dfree(d_V);
+    HIP_K(dalloc(&d_PS, n_slots * nblk * 4096));
+    HIP_K(dalloc(&d_PQ, n_slots * nblk * 4096));
+    HIP_K(hipEventRecord(ev[3], s));
+    if (fused) {
+      HIP_K(launch_psd_fused(G, n_pairs, n_slots, d_PS, d_PQ, s));
+    } else {
+      HIP_K(dalloc(&d_U, 2 * chunk * Kp));
+      HIP_K(dalloc(&d_V, 3 * chunk * Kp));
+      HIP_K(launch_fill_u64(d_PS, n_slots * nblk * 4096, 0, s));
+      HIP_K(launch_fill_u64(d_PQ, n_slots * nblk * 4096, 0, s));
+      for (int64_t q0 = 0; q0 < n_pairs; q0 += chunk) {
+        const int64_t nq = std::min(chunk, n_pairs - q0);
+        HIP_K(launch_psd_gather(G, q0, nq, d_U, d_V, s));
+        HIP_K(launch_psd_syrk(d_U, 2 * nq, Kp, slices, d_PS, s));
+        HIP_K(launch_psd_syrk(d_V, 3 * nq, Kp, slices, d_PQ, s));
+      }
+    }
+    HIP_K(launch_psd_reduce(d_PS, n_slots, K_, Kp, d_S, s));
+    HIP_K(launch_psd_reduce(d_PQ, n_slots, K_, Kp, d_Q, s));
+    HIP_K(launch_psd_se(d_S, d_Q, K_ * K_, (double)n_pairs, d_se, s));
+    HIP_K(launch_count_nonfinite(d_S, K_ * K_, d_nonf, s));
+    HIP_K(launch_count_nonfinite(d_se, K_ * K_, d_nonf, s));
+    HIP_K(hipEventRecord(ev[4], s));
+    HIP_K(hipEventSynchronize(ev[4]));
+    float ms = 0;
+    HIP_K(hipEventElapsedTime(&ms, ev[3], ev[4]));
+    prod_ms_total += ms;
+    HIP_K(hipMemcpy(S_host, d_S, K_ * K_ * 8, hipMemcpyDeviceToHost));
+    if (se_host) HIP_K(hipMemcpy(se_host, d_se, K_ * K_ * 8, hipMemcpyDeviceToHost));
+    return MSK_OK;
+  };
+  HIP_K(launch_fill_u64(d_nonf, 1, 0, s));
+  PsdGather G{};
+  G.tab = d_tab;
+  G.K = K_;
+  G.Kp = Kp;
+  G.pairs = pairs;
+  G.faces = K->mesh->d_faces;
+  G.tri = r->d_tri;
+  G.bary = r->d_bary;
+  G.w = r->d_w;
+  G.u0 = u0;
+  G.log_status = d_ls;
+  G.log_tri = d_lt;
+  G.log_bary = d_lb;
+  G.alpha_row = d_alpha;
+  G.walk_g = d_g;
+  {
+    msk_status ps = products(G, n * pairs, S_jump, se_jump);
+    if (ps != MSK_OK) return cleanup(ps);
+  }
+  if (kill_walks > 0) {
+    // killing walks as pairs of walks from a virtual sample with b(s) = 0:
+    // X_p = alpha (g_1 b_1 b_1^T + g_2 b_2 b_2^T) / 2 with alpha = 8 pi / N0
+    const int64_t nk = kill_walks / 2;
+    std::vector<double> ka((size_t)nk, 8.0 * M_PI / (double)kill_walks);
+    HIP_K(upload(ctx, &d_kalpha, ka.data(), ka.size()));
+    HIP_K(dalloc(&d_ktri, nk));
+    HIP_K(dalloc(&d_kbary, 3 * nk));
+    HIP_K(launch_fill_u32(d_ktri, nk, 0u, s));
+    HIP_K(launch_fill_u32(d_kbary, 3 * nk, 0u, s));
+    PsdGather Gk = G;
+    Gk.pairs = 1;
+    Gk.tri = d_ktri;
+    Gk.bary = d_kbary;
+    Gk.w = nullptr;
+    Gk.alpha_row = d_kalpha;
+    Gk.log_status = d_ls + n_jump;
+    Gk.log_tri = d_lt + n_jump;
+    Gk.log_bary = d_lb + 2 * n_jump;
+    Gk.walk_g = d_g + n_jump;
+    msk_status ps = products(Gk, nk, S_kill, se_kill);
+    if (ps != MSK_OK) return cleanup(ps);
+  }
+  // logs, counters and timings
+  if (radius_out) std::memcpy(radius_out, rad.data(), n * 8);
+  if (log_out) {
+    if (log_out->status) HIP_K(hipMemcpy(log_out->status, d_ls, n_walk * 4, hipMemcpyDeviceToHost));
+    if (log_out->tri) HIP_K(hipMemcpy(log_out->tri, d_lt, n_walk * 4, hipMemcpyDeviceToHost));
+    if (log_out->bary) HIP_K(hipMemcpy(log_out->bary, d_lb, n_walk * 8, hipMemcpyDeviceToHost));
+    if (log_out->queries) HIP_K(hipMemcpy(log_out->queries, d_lq, n_walk * 4, hipMemcpyDeviceToHost));
+  }
+  std::vector<unsigned long long> rq((size_t)n), tq((size_t)n);
+  unsigned long long kq = 0, nonf = 0;
+  HIP_K(hipMemcpy(rq.data(), d_rq, n * 8, hipMemcpyDeviceToHost));
+  HIP_K(hipMemcpy(tq.data(), d_tq, n * 8, hipMemcpyDeviceToHost));
+  HIP_K(hipMemcpy(&kq, d_kq, 8, hipMemcpyDeviceToHost));
+  HIP_K(hipMemcpy(&nonf, d_nonf, 8, hipMemcpyDeviceToHost));
+  std::vector<int32_t> ls((size_t)n_walk);
+  HIP_K(hipMemcpy(ls.data(), d_ls, n_walk * 4, hipMemcpyDeviceToHost));
+  float t_tan = 0, t_walk = 0;
+  HIP_K(hipEventElapsedTime(&t_tan, ev[0], ev[1]));
+  HIP_K(hipEventElapsedTime(&t_walk, ev[1], ev[2]));
+  msk_kelvin_est_info I;
+  std::memset(&I, 0, sizeof(I));
+  I.n_rows = n;
+  I.K = K_;
+  I.pairs = pairs;
+  I.kill_walks = kill_walks;
+  I.dropped_rows = dropped;
+  I.walks_total = (n - dropped) * 2 * pairs + kill_walks;
+  for (int64_t i = 0; i < n; ++i) I.queries_total += (int64_t)(rq[i] + tq[i]);
+  I.kill_queries = (int64_t)kq;
+  I.queries_total += I.kill_queries;
+  for (int64_t w = 0; w < n_walk; ++w) I.capped_total += ls[w] == kCapped ? 1 : 0;
+  I.mean_radius = n > dropped ? rsum / (double)(n - dropped) : 0.0;
+  I.r_max = r_max;
+  I.tangent_ms = t_tan;
+  I.walk_kernel_ms = t_walk;
+  I.product_ms = prod_ms_total;
+  I.nonfinite_entries = (int64_t)nonf;
+  if (info) *info = I;
+#undef HIP_K
+  cleanup(MSK_OK);
+  if (I.nonfinite_entries > 0) return fail(ctx, MSK_ERR_NUMERIC, "non-finite entries in the estimate");
   return MSK_OK;
 }
 

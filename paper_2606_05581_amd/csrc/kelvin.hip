@@ -1,0 +1,446 @@
+// The exterior estimate in the Kelvin-inverted domain (Sec. 3.3, The Kelvin
+// Transform; eqs. exterior-jump-kernel-final, killing-measure-poisson-kernel,
+// main-exterior-estimator; Sec. 4, spherical triangular elements).
+//
+// Coordinates are relative to an inversion centre inside the shape. The map
+// x -> x / |x|^2 sends the unbounded exterior to a bounded domain whose
+// boundary is the image of the mesh: each planar triangle becomes a piece of
+// a sphere through the origin (or of the plane itself when it passes through
+// the centre), bounded by three circular arcs, the images of its edges. Walks
+// in that domain always end, so Walk-on-Spheres applies with the exact
+// distance to these curved elements. Everything here is FP64: element
+// spheres of triangles whose planes pass near the centre have huge radii,
+// and the distance is written stably in that limit.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "msk_internal.h"
+#include "philox.h"
+
+namespace msk {
+
+namespace {
+
+__host__ __device__ __forceinline__ double dot(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__host__ __device__ __forceinline__ void invert(const double x[3], double y[3]) {
+  const double s = 1.0 / dot(x, x);
+  y[0] = x[0] * s; y[1] = x[1] * s; y[2] = x[2] * s;
+}
+
+__host__ __device__ __forceinline__ void cross(const double u[3], const double v[3], double o[3]) {
+  o[0] = u[1] * v[2] - u[2] * v[1];
+  o[1] = u[2] * v[0] - u[0] * v[2];
+  o[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+// Offer a candidate point q at squared distance d2 with barycentrics l.
+struct Best {
+  double d2;
+  double q[3];
+  double l[3];
+};
+__host__ __device__ __forceinline__ void offer(Best& b, double d2, const double q[3], double l0, double l1, double l2) {
+  if (d2 < b.d2) {
+    b.d2 = d2;
+    b.q[0] = q[0]; b.q[1] = q[1]; b.q[2] = q[2];
+    b.l[0] = l0; b.l[1] = l1; b.l[2] = l2;
+  }
+}
+
+// The image of the edge [P, Q] (primal, relative to the centre): end points,
+// and the nearest point of the arc. The line through P and Q, at foot point f
+// from the centre, maps to the circle through the origin in the plane of
+// (0, P, Q) with centre f / (2 |f|^2) and radius 1 / (2 |f|); the circle
+// point nearest to x is the radial projection of x's in-plane position, and
+// it lies on the edge's arc when its image is between P and Q. A line
+// through the centre maps to itself: the arc is then the straight segment
+// between the end points' images. (ia, ib) are the edge's vertex slots.
+__host__ __device__ void edge_image(const double x[3], const double P[3], const double Q[3], int ia, int ib, Best& b) {
+#pragma clang fp contract(off)
+  double kp[3], kq[3], d[3];
+  invert(P, kp);
+  invert(Q, kq);
+  double l[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < 3; ++k) d[k] = x[k] - kp[k];
+  l[ia] = 1.0;
+  offer(b, dot(d, d), kp, l[0], l[1], l[2]);
+  for (int k = 0; k < 3; ++k) d[k] = x[k] - kq[k];
+  l[ia] = 0.0; l[ib] = 1.0;
+  offer(b, dot(d, d), kq, l[0], l[1], l[2]);
+  const double e[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
+  const double ee = dot(e, e);
+  if (!(ee > 0.0)) return;
+  const double tf = -dot(P, e) / ee;
+  const double f[3] = {P[0] + tf * e[0], P[1] + tf * e[1], P[2] + tf * e[2]};
+  const double ff = dot(f, f);
+  double m[3];
+  cross(P, Q, m);
+  const double mm = dot(m, m);
+  if (ff > 1e-24 * fmax(dot(P, P), dot(Q, Q)) && mm > 0.0) {
+    const double ml = 1.0 / sqrt(mm);
+    for (int k = 0; k < 3; ++k) m[k] *= ml;
+    const double c[3] = {f[0] / (2.0 * ff), f[1] / (2.0 * ff), f[2] / (2.0 * ff)};
+    const double rho = 1.0 / (2.0 * sqrt(ff));
+    const double mx = dot(m, x);
+    const double u[3] = {x[0] - mx * m[0] - c[0], x[1] - mx * m[1] - c[1], x[2] - mx * m[2] - c[2]};
+    const double ul = sqrt(dot(u, u));
+    if (!(ul > 0.0)) return;
+    const double pt[3] = {c[0] + rho * u[0] / ul, c[1] + rho * u[1] / ul, c[2] + rho * u[2] / ul};
+    // the origin is the image of the line's point at infinity: every point of
+    // the segment's image lies at least 1 / max(|P|, |Q|) from it
+    if (!(dot(pt, pt) * fmax(dot(P, P), dot(Q, Q)) >= 1.0 - 1e-9)) return;
+    double y[3];
+    invert(pt, y);
+    const double yd[3] = {y[0] - P[0], y[1] - P[1], y[2] - P[2]};
+    const double t = dot(yd, e) / ee;
+    if (t >= 0.0 && t <= 1.0) {
+      for (int k = 0; k < 3; ++k) d[k] = x[k] - pt[k];
+      l[ia] = 1.0 - t; l[ib] = t;
+      offer(b, dot(d, d), pt, l[0], l[1], l[2]);
+    }
+  } else {
+    const double g[3] = {kq[0] - kp[0], kq[1] - kp[1], kq[2] - kp[2]};
+    const double gg = dot(g, g);
+    double s = gg > 0.0 ? ((x[0] - kp[0]) * g[0] + (x[1] - kp[1]) * g[1] + (x[2] - kp[2]) * g[2]) / gg : 0.0;
+    s = fmin(1.0, fmax(0.0, s));
+    const double pt[3] = {kp[0] + s * g[0], kp[1] + s * g[1], kp[2] + s * g[2]};
+    double y[3];
+    invert(pt, y);
+    const double yd[3] = {y[0] - P[0], y[1] - P[1], y[2] - P[2]};
+    const double t = dot(yd, e) / ee;
+    for (int k = 0; k < 3; ++k) d[k] = x[k] - pt[k];
+    l[ia] = 1.0 - t; l[ib] = t;
+    offer(b, dot(d, d), pt, l[0], l[1], l[2]);
+  }
+}
+
+}  // namespace
+
+// Squared distance from x to the image of triangle T, its nearest point and
+// the barycentrics of that point's image in T. The triangle's plane
+// n . y = c maps to the sphere through the origin with centre n / (2c) and
+// radius 1 / (2|c|); with v = c x - n/2 the signed distance of x to it is
+// (|c| |x|^2 - sign(c) n . x) / (|v| + 1/2) and the radial projection moves x
+// by that distance along sign(c) v / |v|, which tends to the plane's own
+// projection as c -> 0. The projection belongs to the patch when its image
+// lies in T; otherwise the nearest point is on the patch's boundary (distance
+// to a sphere's points grows with their angle from the radial projection).
+__host__ __device__ double kelvin_tri_d2(const double x[3], const KelvinTri& T, double q[3], double l[3]) {
+#pragma clang fp contract(off)
+  Best b;
+  b.d2 = INFINITY;
+  double ab[3], ac[3], n[3];
+  for (int k = 0; k < 3; ++k) {
+    ab[k] = T.b[k] - T.a[k];
+    ac[k] = T.c[k] - T.a[k];
+  }
+  cross(ab, ac, n);
+  const double nl = sqrt(dot(n, n));
+  if (nl > 1e-12 * fmax(dot(ab, ab), dot(ac, ac))) {
+    for (int k = 0; k < 3; ++k) n[k] /= nl;
+    const double c = dot(n, T.a);
+    double p[3];
+    if (c != 0.0) {
+      const double sg = c > 0.0 ? 1.0 : -1.0;
+      const double v[3] = {c * x[0] - 0.5 * n[0], c * x[1] - 0.5 * n[1], c * x[2] - 0.5 * n[2]};
+      const double vl = sqrt(dot(v, v));
+      const double sd = (fabs(c) * dot(x, x) - sg * dot(n, x)) / (vl + 0.5);
+      for (int k = 0; k < 3; ++k) p[k] = x[k] - sd * sg * v[k] / vl;
+    } else {
+      const double nx = dot(n, x);
+      for (int k = 0; k < 3; ++k) p[k] = x[k] - nx * n[k];
+    }
+    const double M2 = fmax(dot(T.a, T.a), fmax(dot(T.b, T.b), dot(T.c, T.c)));
+    if (dot(p, p) * M2 >= 1.0 - 1e-9) {  // image points lie at least 1 / max|vertex| from the origin
+      double y[3], ay[3], w[3];
+      invert(p, y);
+      for (int k = 0; k < 3; ++k) ay[k] = y[k] - T.a[k];
+      // barycentrics of y's projection on the plane, n unit
+      cross(ay, ac, w);
+      const double l1 = dot(w, n) / nl;
+      cross(ab, ay, w);
+      const double l2 = dot(w, n) / nl;
+      const double l0 = 1.0 - l1 - l2;
+      if (l0 >= 0.0 && l1 >= 0.0 && l2 >= 0.0) {
+        const double d[3] = {x[0] - p[0], x[1] - p[1], x[2] - p[2]};
+        offer(b, dot(d, d), p, l0, l1, l2);
+      }
+    }
+  }
+  edge_image(x, T.a, T.b, 0, 1, b);
+  edge_image(x, T.b, T.c, 1, 2, b);
+  edge_image(x, T.c, T.a, 2, 0, b);
+  q[0] = b.q[0]; q[1] = b.q[1]; q[2] = b.q[2];
+  l[0] = b.l[0]; l[1] = b.l[1]; l[2] = b.l[2];
+  return b.d2;
+}
+
+// Exact nearest inverted element: lexicographic minimum of (squared distance,
+// original index), depth first over the 4-wide hierarchy of boxes that
+// contain the elements (FP32 boxes rounded outward; their FP64 lower bounds
+// are within the boxes' own rounding of the true distance, hence the small
+// relative margin).
+__host__ __device__ double kelvin_nearest(const KelvinDev& K, const double x[3], int32_t& orig, double q[3], double l[3]) {
+  double best = INFINITY;
+  orig = INT_MAX;
+  int32_t stk[kStackDepth];
+  double stl[kStackDepth];
+  int sp = 0;
+  int32_t node = 0;
+  while (true) {
+    const Node4& N = K.nodes[node];
+    double lb[4];
+    int32_t cc[4], cn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double gx = fmax(fmax((double)N.lox[k] - x[0], x[0] - (double)N.hix[k]), 0.0);
+      const double gy = fmax(fmax((double)N.loy[k] - x[1], x[1] - (double)N.hiy[k]), 0.0);
+      const double gz = fmax(fmax((double)N.loz[k] - x[2], x[2] - (double)N.hiz[k]), 0.0);
+      lb[k] = gx * gx + gy * gy + gz * gz;
+      cc[k] = N.child[k];
+      cn[k] = N.count[k];
+    }
+    // nearest first
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+      for (int j = i; j > 0 && lb[j] < lb[j - 1]; --j) {
+        const double t = lb[j]; lb[j] = lb[j - 1]; lb[j - 1] = t;
+        const int32_t a = cc[j]; cc[j] = cc[j - 1]; cc[j - 1] = a;
+        const int32_t c = cn[j]; cn[j] = cn[j - 1]; cn[j - 1] = c;
+      }
+    int32_t next = -1;
+    double next_lb = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      if (!(lb[k] <= best * (1.0 + 1e-12))) continue;
+      if (cc[k] < 0 && cn[k] > 0) {
+        const int32_t first = -cc[k] - 1;
+        for (int32_t s = first; s < first + cn[k]; ++s) {
+          const KelvinTri& T = K.tris[s];
+          double qq[3], ll[3];
+          const double d = kelvin_tri_d2(x, T, qq, ll);
+          if (d < best || (d == best && T.orig < orig)) {
+            best = d;
+            orig = T.orig;
+            q[0] = qq[0]; q[1] = qq[1]; q[2] = qq[2];
+            l[0] = ll[0]; l[1] = ll[1]; l[2] = ll[2];
+          }
+        }
+      }
+    }
+    // the nearest surviving inner child is next, the others wait on the
+    // stack (farthest first) with their bounds
+    for (int k = 3; k >= 0; --k) {
+      if (cc[k] >= 0 && lb[k] <= best * (1.0 + 1e-12)) {
+        if (next >= 0 && sp < kStackDepth) {
+          stk[sp] = next;
+          stl[sp] = next_lb;
+          ++sp;
+        }
+        next = cc[k];
+        next_lb = lb[k];
+      }
+    }
+    if (next >= 0) {
+      node = next;
+      continue;
+    }
+    node = -1;
+    while (sp > 0) {
+      --sp;
+      if (stl[sp] <= best * (1.0 + 1e-12)) {
+        node = stk[sp];
+        break;
+      }
+    }
+    if (node < 0) break;
+  }
+  return best;
+}
+
+namespace {
+
+__device__ __forceinline__ void frame(const double n[3], double e1[3], double e2[3]) {
+  const double sg = n[2] >= 0.0 ? 1.0 : -1.0;
+  const double a = -1.0 / (sg + n[2]);
+  const double b = n[0] * n[1] * a;
+  e1[0] = 1.0 + sg * n[0] * n[0] * a; e1[1] = sg * b; e1[2] = -sg * n[0];
+  e2[0] = b; e2[1] = sg + n[1] * n[1] * a; e2[2] = -n[1];
+}
+
+// Walk-on-Spheres in the inverted domain from x: step k draws the Philox
+// block (row, walk, k, step purpose), the same streams as the oracle. Ends
+// in the eps-shell (hit) or at the step cap (nearest point of the last
+// position). Returns the status; orig, q and l describe the terminal point.
+__device__ int32_t kelvin_walk(const KelvinDev& K, uint32_t row, uint32_t walk, double x[3], int32_t& orig,
+                               double q[3], double l[3], int32_t& queries) {
+  for (int64_t k = 0; k < K.max_steps; ++k) {
+    const double d2 = kelvin_nearest(K, x, orig, q, l);
+    if (d2 < K.eps2) {
+      queries = (int32_t)(k + 1);
+      return kHit;
+    }
+    const uint4 u = philox10(make_uint4(row, walk, (uint32_t)k, (kPurposeStep << 24) | (K.mesh_id & 0xFFFFFFu)),
+                             K.seed_lo, K.seed_hi);
+    const double u0 = unit_f(u.x), u1 = unit_f(u.y);
+    const double r = sqrt(d2) * (1.0 - K.kappa) - K.delta;
+    const double z = 1.0 - 2.0 * u0;
+    const double rxy = 2.0 * sqrt(u0 * (1.0 - u0));
+    double sp, cp;
+    sincospi(2.0 * u1, &sp, &cp);
+    x[0] += r * rxy * cp;
+    x[1] += r * rxy * sp;
+    x[2] += r * z;
+  }
+  kelvin_nearest(K, x, orig, q, l);
+  queries = (int32_t)(K.max_steps + 1);
+  return kCapped;
+}
+
+}  // namespace
+
+// Largest ball in the inverted domain touching its boundary at s~_i (unit
+// normal n~_i pointing out of the domain): bisection over [0, r_max], a
+// radius accepted when the centre c = s~ - r n~ is at least r - min(tol,
+// r/1024) from the inverted surface and the ball lies within the domain's
+// bound. One lane per row; every step is an exact nearest query.
+__global__ void kelvin_tangent_kernel(KelvinDev K, const double* __restrict__ st, const double* __restrict__ nt,
+                                      int64_t n_rows, double r_max, int32_t iters, double tol,
+                                      double* __restrict__ radius, unsigned long long* __restrict__ queries) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows) return;
+  const double s[3] = {st[3 * i], st[3 * i + 1], st[3 * i + 2]};
+  const double n[3] = {nt[3 * i], nt[3 * i + 1], nt[3 * i + 2]};
+  double lo = 0.0, hi = r_max;
+  for (int32_t it = 0; it < iters; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double c[3] = {s[0] - mid * n[0], s[1] - mid * n[1], s[2] - mid * n[2]};
+    int32_t o;
+    double q[3], l[3];
+    const double d = sqrt(kelvin_nearest(K, c, o, q, l));
+    const double t = mid - fmin(tol, mid * (1.0 / 1024.0));
+    if (d >= t && sqrt(dot(c, c)) + mid <= K.radius)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  radius[i] = lo;
+  queries[i] = (unsigned long long)iters;
+}
+
+// One lane per walk. Walks [0, n_rows 2 pairs) are the jump term's: walk
+// 2j + a of row i starts at point a of antithetic pair j on the row's tangent
+// ball, drawn with density proportional to the ball jump kernel outside the
+// cap (u = sin(theta/2) with density ~ 1/u^2 on [u0, 1], inverted in closed
+// form; azimuth uniform, + pi for the partner). The next n_kill walks are the
+// killing term's, from the origin (the image of infinity), with Philox row
+// 0xFFFFFFFF and walk index k. Each walk logs its status, terminal original
+// triangle, the barycentrics of that triangle's vertices 1 and 2 at the
+// terminal point's image, its query count, and the factor g = 1/|t~| of its
+// rank-one update.
+__global__ void kelvin_walk_kernel(KelvinDev K, const double* __restrict__ st, const double* __restrict__ nt,
+                                   const double* __restrict__ radius, int64_t n_rows, int64_t pairs, double u0,
+                                   int64_t n_kill, int32_t* __restrict__ log_status, int32_t* __restrict__ log_tri,
+                                   float* __restrict__ log_bary, int32_t* __restrict__ log_q, double* __restrict__ g,
+                                   unsigned long long* __restrict__ row_queries, unsigned long long* kill_queries) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_jump = n_rows * 2 * pairs;
+  if (id >= n_jump + n_kill) return;
+  double x[3] = {0.0, 0.0, 0.0};
+  uint32_t row = 0xFFFFFFFFu, walk;
+  int64_t i = -1;
+  if (id < n_jump) {
+    i = id / (2 * pairs);
+    const int64_t w = id - i * 2 * pairs;
+    const double r = radius[i];
+    if (!(r > 0.0)) {
+      log_status[id] = -1;
+      log_tri[id] = -1;
+      log_bary[2 * id] = log_bary[2 * id + 1] = 0.0f;
+      log_q[id] = 0;
+      g[id] = 0.0;
+      return;
+    }
+    row = (uint32_t)i;
+    walk = (uint32_t)w;
+    const uint4 u = philox10(make_uint4(row, (uint32_t)(w >> 1), 0u, (kPurposeBall << 24) | (K.mesh_id & 0xFFFFFFu)),
+                             K.seed_lo, K.seed_hi);
+    const double xi = unit_f(u.x), eta = unit_f(u.y);
+    const double su = 1.0 / (1.0 / u0 - xi * (1.0 / u0 - 1.0));
+    const double ct = 1.0 - 2.0 * su * su, sn = 2.0 * su * sqrt(fmax(0.0, 1.0 - su * su));
+    double sp, cp;
+    sincospi(2.0 * eta + ((w & 1) ? 1.0 : 0.0), &sp, &cp);
+    const double n[3] = {nt[3 * i], nt[3 * i + 1], nt[3 * i + 2]};
+    double e1[3], e2[3];
+    frame(n, e1, e2);
+    for (int k = 0; k < 3; ++k) {
+      const double c = st[3 * i + k] - r * n[k];
+      x[k] = c + r * (ct * n[k] + sn * (cp * e1[k] + sp * e2[k]));
+    }
+  } else {
+    walk = (uint32_t)(id - n_jump);
+  }
+  int32_t orig = -1, nq = 0;
+  double q[3], l[3];
+  const int32_t status = kelvin_walk(K, row, walk, x, orig, q, l, nq);
+  log_status[id] = status;
+  log_tri[id] = orig;
+  log_bary[2 * id] = (float)l[1];
+  log_bary[2 * id + 1] = (float)l[2];
+  log_q[id] = nq;
+  g[id] = 1.0 / sqrt(dot(q, q));
+  if (i >= 0)
+    atomicAdd(row_queries + i, (unsigned long long)nq);
+  else
+    atomicAdd(kill_queries, (unsigned long long)nq);
+}
+
+// Nearest inverted element of each query point (inverted space, relative to
+// the centre).
+__global__ void kelvin_closest_kernel(KelvinDev K, const double* __restrict__ Q, int64_t nq, int32_t* __restrict__ tri,
+                                      double* __restrict__ d2, double* __restrict__ qpt, double* __restrict__ bary) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const double x[3] = {Q[3 * i], Q[3 * i + 1], Q[3 * i + 2]};
+  int32_t o;
+  double q[3], l[3];
+  d2[i] = kelvin_nearest(K, x, o, q, l);
+  tri[i] = o;
+  for (int k = 0; k < 3; ++k) {
+    qpt[3 * i + k] = q[k];
+    bary[3 * i + k] = l[k];
+  }
+}
+
+hipError_t launch_kelvin_tangent(const KelvinDev& K, const double* st, const double* nt, int64_t n_rows, double r_max,
+                                 int32_t iters, double tol, double* radius, unsigned long long* queries,
+                                 hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kelvin_tangent_kernel, dim3((unsigned)((n_rows + 63) / 64)), dim3(64), 0, s, K, st, nt, n_rows,
+                     r_max, iters, tol, radius, queries);
+  return hipGetLastError();
+}
+
+hipError_t launch_kelvin_walks(const KelvinDev& K, const double* st, const double* nt, const double* radius,
+                               int64_t n_rows, int64_t pairs, double u0, int64_t n_kill, int32_t* log_status,
+                               int32_t* log_tri, float* log_bary, int32_t* log_q, double* g,
+                               unsigned long long* row_queries, unsigned long long* kill_queries, hipStream_t s) {
+  const int64_t n = n_rows * 2 * pairs + n_kill;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kelvin_walk_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, K, st, nt, radius,
+                     n_rows, pairs, u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries);
+  return hipGetLastError();
+}
+
+hipError_t launch_kelvin_closest(const KelvinDev& K, const double* Q, int64_t nq, int32_t* tri, double* d2,
+                                 double* qpt, double* bary, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kelvin_closest_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, K, Q, nq, tri, d2,
+                     qpt, bary);
+  return hipGetLastError();
+}
+
+}  // namespace msk

@@ -47,6 +47,15 @@ struct HostBvh {
 // centre. Returns an empty string on success, else an error message.
 std::string build_bvh_host(const float* V, int64_t nv, const int32_t* F, int64_t nf, int leaf_size, HostBvh& out);
 
+// The same binned-SAH build and 4-wide collapse over any elements given by
+// their boxes and centroids (n x 3 floats): the nodes in breadth-first order
+// and the element order of the leaf slots.
+struct Box3f {
+  float lo[3], hi[3];
+};
+std::string build_bvh_boxes(const std::vector<Box3f>& boxes, const std::vector<float>& cen, int leaf_size,
+                            std::vector<Node4>& nodes_out, std::vector<int32_t>& leaf_order, int& depth);
+
 // ------------------------------------------------------------ kernel ABI
 
 enum RowMode : int32_t { kRowsPoint = 0, kRowsHatRing = 1 };
@@ -194,7 +203,41 @@ struct PsdGather {
   const int32_t* log_status;  // walk log, n_rows x 2 pairs
   const int32_t* log_tri;
   const float* log_bary;
+  // optional (null = the interior estimator's): per-row alpha replacing
+  // w Z(r) / (2 pairs), and a per-walk factor g of its rank-one update
+  // (X_p = alpha (g_1 d_1 d_1^T + g_2 d_2 d_2^T) / 2), both FP64
+  const double* alpha_row;
+  const double* walk_g;
 };
+// Exterior estimate in the Kelvin-inverted domain (kelvin.hip): an element is
+// a mesh triangle given by its vertices relative to the inversion centre
+// (FP64), in BVH leaf order, with its original index.
+struct KelvinTri {
+  double a[3], b[3], c[3];
+  int32_t orig;
+  int32_t pad;
+};
+static_assert(sizeof(KelvinTri) == 80, "inverted element record must be 80 bytes");
+struct KelvinDev {
+  const Node4* nodes;      // 4-wide hierarchy over boxes containing the inverted elements
+  const KelvinTri* tris;
+  int64_t n_tris;
+  double radius;           // bound of the inverted domain (max |x~| on its boundary)
+  double eps2;             // shell width squared (inverted units)
+  double kappa, delta;     // step radius d (1 - kappa) - delta
+  int64_t max_steps;
+  uint32_t mesh_id, seed_lo, seed_hi;
+};
+hipError_t launch_kelvin_tangent(const KelvinDev& K, const double* st, const double* nt, int64_t n_rows, double r_max,
+                                 int32_t iters, double tol, double* radius, unsigned long long* queries,
+                                 hipStream_t s);
+hipError_t launch_kelvin_walks(const KelvinDev& K, const double* st, const double* nt, const double* radius,
+                               int64_t n_rows, int64_t pairs, double u0, int64_t n_kill, int32_t* log_status,
+                               int32_t* log_tri, float* log_bary, int32_t* log_q, double* g,
+                               unsigned long long* row_queries, unsigned long long* kill_queries, hipStream_t s);
+hipError_t launch_kelvin_closest(const KelvinDev& K, const double* Q, int64_t nq, int32_t* tri, double* d2,
+                                 double* qpt, double* bary, hipStream_t s);
+
 hipError_t launch_dense_table(const int32_t* rowptr, const int32_t* col, const float* val, int64_t nv, int64_t K,
                               float* tab, hipStream_t s);
 hipError_t launch_psd_gather(const PsdGather& G, int64_t q0, int64_t nq, double* U, double* V, hipStream_t s);

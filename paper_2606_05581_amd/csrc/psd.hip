@@ -5,7 +5,10 @@
 // radius r_i) with walks ending at t_1, t_2, the boxed estimator with s
 // stratified over rows and z drawn in proportion to the ball jump kernel
 // gives X_p = alpha_i (d_1 d_1^T + d_2 d_2^T) / 2, d = b(s_i) - b(t),
-// alpha_i = w_i Z_i / (2 P), Z_i the kernel's mass outside the cap. The sums
+// alpha_i = w_i Z_i / (2 P), Z_i the kernel's mass outside the cap (the
+// exterior estimate in the Kelvin-inverted domain passes its own alpha_i and
+// a factor g per walk: X_p = alpha_i (g_1 d_1 d_1^T + g_2 d_2 d_2^T) / 2,
+// and the rows below scale accordingly). The sums
 // S = sum_p X_p and Q = sum_p X_p * X_p (elementwise, for standard errors)
 // are symmetric rank-k updates S += U^T U, Q += V^T V over rows
 //   U: sqrt(alpha/2) d_1, sqrt(alpha/2) d_2;
@@ -36,6 +39,14 @@ __global__ void dense_table_kernel(const int32_t* __restrict__ rowptr, const int
       tab[v * K + col[e]] = val[e];
 }
 
+// alpha_i of row i: given per row, or w_i Z(r_i) / (2 pairs) (0 for a row
+// without a tangent ball).
+__device__ __forceinline__ double pair_alpha(const PsdGather& G, int64_t i) {
+  if (G.alpha_row) return G.alpha_row[i];
+  const double r = (double)G.radius[i];
+  return r > 0.0 ? G.w[i] * (1.0 / (2.0 * r)) * (1.0 / G.u0 - 1.0) / (2.0 * (double)G.pairs) : 0.0;
+}
+
 // One workgroup per pair of the chunk [q0, q0 + nq); threads over columns.
 __global__ void __launch_bounds__(256) psd_gather_kernel(PsdGather G, int64_t q0, int64_t nq, double* __restrict__ U,
                                                          double* __restrict__ V) {
@@ -44,8 +55,9 @@ __global__ void __launch_bounds__(256) psd_gather_kernel(PsdGather G, int64_t q0
     const int64_t q = q0 + qq;
     const int64_t i = q / G.pairs;
     const int64_t j = q - i * G.pairs;
-    const double r = (double)G.radius[i];
-    const double alpha = r > 0.0 ? G.w[i] * (1.0 / (2.0 * r)) * (1.0 / G.u0 - 1.0) / (2.0 * (double)G.pairs) : 0.0;
+    const double alpha = pair_alpha(G, i);
+    const double g1 = G.walk_g ? G.walk_g[i * 2 * G.pairs + 2 * j] : 1.0;
+    const double g2 = G.walk_g ? G.walk_g[i * 2 * G.pairs + 2 * j + 1] : 1.0;
     // sample: face and barycentrics of s_i
     const int32_t* fs = G.faces + 3 * (int64_t)G.tri[i];
     const double ls[3] = {G.bary[3 * i], G.bary[3 * i + 1], G.bary[3 * i + 2]};
@@ -62,7 +74,8 @@ __global__ void __launch_bounds__(256) psd_gather_kernel(PsdGather G, int64_t q0
       lt[a][2] = l2;
       for (int c = 0; c < 3; ++c) ft[a][c] = has_t ? G.faces[3 * (int64_t)t + c] : 0;
     }
-    const double su = sqrt(0.5 * alpha), sv = 0.5 * alpha, sv2 = sqrt(2.0) * 0.5 * alpha;
+    const double su1 = sqrt(0.5 * alpha * g1), su2 = sqrt(0.5 * alpha * g2);
+    const double sv1 = 0.5 * alpha * g1, sv2 = 0.5 * alpha * g2, sv12 = sqrt(2.0) * 0.5 * alpha * sqrt(g1 * g2);
     double* u = U + 2 * qq * Kp;
     double* v = V + 3 * qq * Kp;
     for (int64_t k = K + threadIdx.x; k < Kp; k += blockDim.x) {  // padding columns
@@ -79,11 +92,11 @@ __global__ void __launch_bounds__(256) psd_gather_kernel(PsdGather G, int64_t q0
       const double b2 = lt[1][0] * G.tab[ft[1][0] * K + k] + lt[1][1] * G.tab[ft[1][1] * K + k] +
                         lt[1][2] * G.tab[ft[1][2] * K + k];
       const double d1 = bs - b1, d2 = bs - b2;
-      u[k] = su * d1;
-      u[Kp + k] = su * d2;
-      v[k] = sv * d1 * d1;
-      v[Kp + k] = sv * d2 * d2;
-      v[2 * Kp + k] = sv2 * d1 * d2;
+      u[k] = su1 * d1;
+      u[Kp + k] = su2 * d2;
+      v[k] = sv1 * d1 * d1;
+      v[Kp + k] = sv2 * d2 * d2;
+      v[2 * Kp + k] = sv12 * d1 * d2;
     }
   }
 }
@@ -175,14 +188,15 @@ __global__ void __launch_bounds__(256) syrk_blocks_kernel(const double* __restri
 // into the workgroup's slot (slot = blockIdx.x; no other workgroup writes it).
 struct PairMeta {
   double alpha;
+  double g[2];
   double ls[3], lt[2][3];
   int32_t fs[3], ft[2][3];
 };
 
 __device__ void pair_meta(const PsdGather& G, int64_t q, PairMeta& m) {
   const int64_t i = q / G.pairs, j = q - (q / G.pairs) * G.pairs;
-  const double r = (double)G.radius[i];
-  m.alpha = r > 0.0 ? G.w[i] * (1.0 / (2.0 * r)) * (1.0 / G.u0 - 1.0) / (2.0 * (double)G.pairs) : 0.0;
+  m.alpha = pair_alpha(G, i);
+  for (int a = 0; a < 2; ++a) m.g[a] = G.walk_g ? G.walk_g[i * 2 * G.pairs + 2 * j + a] : 1.0;
   const int32_t* fs = G.faces + 3 * (int64_t)G.tri[i];
   for (int c = 0; c < 3; ++c) {
     m.fs[c] = fs[c];
@@ -238,6 +252,7 @@ __global__ void __launch_bounds__(512) psd_fused_kernel(PsdGather G, int64_t n_p
       } else {
         PairMeta& m = meta[threadIdx.x];
         m.alpha = 0.0;
+        m.g[0] = m.g[1] = 1.0;
         for (int c = 0; c < 3; ++c) {
           m.fs[c] = m.ft[0][c] = m.ft[1][c] = 0;
           m.ls[c] = m.lt[0][c] = m.lt[1][c] = 0.0;
@@ -259,12 +274,14 @@ __global__ void __launch_bounds__(512) psd_fused_kernel(PsdGather G, int64_t n_p
         d1 = bs - b1;
         d2 = bs - b2;
       }
-      const double su = sqrt(0.5 * m.alpha), sv = 0.5 * m.alpha, sv2 = sqrt(2.0) * 0.5 * m.alpha;
-      Ur[(2 * pp) * stride + k] = su * d1;
-      Ur[(2 * pp + 1) * stride + k] = su * d2;
-      Vr[(3 * pp) * stride + k] = sv * d1 * d1;
-      Vr[(3 * pp + 1) * stride + k] = sv * d2 * d2;
-      Vr[(3 * pp + 2) * stride + k] = sv2 * d1 * d2;
+      const double su1 = sqrt(0.5 * m.alpha * m.g[0]), su2 = sqrt(0.5 * m.alpha * m.g[1]);
+      const double sv1 = 0.5 * m.alpha * m.g[0], sv2 = 0.5 * m.alpha * m.g[1];
+      const double sv12 = sqrt(2.0) * 0.5 * m.alpha * sqrt(m.g[0] * m.g[1]);
+      Ur[(2 * pp) * stride + k] = su1 * d1;
+      Ur[(2 * pp + 1) * stride + k] = su2 * d2;
+      Vr[(3 * pp) * stride + k] = sv1 * d1 * d1;
+      Vr[(3 * pp + 1) * stride + k] = sv2 * d2 * d2;
+      Vr[(3 * pp + 2) * stride + k] = sv12 * d1 * d2;
     }
     __syncthreads();
     if (active) {

@@ -107,6 +107,24 @@ class PsdLog(C.Structure):
     _fields_ = [("status", C.c_void_p), ("tri", C.c_void_p), ("bary", C.c_void_p), ("queries", C.c_void_p)]
 
 
+class KelvinInfo(C.Structure):
+    _fields_ = [("centre", C.c_double * 3), ("radius", C.c_double), ("box_lo", C.c_double * 3),
+                ("box_hi", C.c_double * 3), ("r_max", C.c_double), ("n_tris", C.c_int64), ("n_nodes", C.c_int64),
+                ("depth", C.c_int32), ("leaf_size", C.c_int32)]
+
+
+class KelvinLog(C.Structure):
+    _fields_ = [("status", C.c_void_p), ("tri", C.c_void_p), ("bary", C.c_void_p), ("queries", C.c_void_p)]
+
+
+class KelvinEstInfo(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("K", C.c_int64), ("pairs", C.c_int64), ("kill_walks", C.c_int64),
+                ("walks_total", C.c_int64), ("queries_total", C.c_int64), ("kill_queries", C.c_int64),
+                ("dropped_rows", C.c_int64), ("capped_total", C.c_int64), ("mean_radius", C.c_double),
+                ("r_max", C.c_double), ("tangent_ms", C.c_double), ("walk_kernel_ms", C.c_double),
+                ("product_ms", C.c_double), ("nonfinite_entries", C.c_int64)]
+
+
 class LaplaceOpts(C.Structure):
     _fields_ = [("block", C.c_int32), ("degree", C.c_int32), ("max_iters", C.c_int32), ("max_degree", C.c_int32),
                 ("tol", C.c_double), ("seed", C.c_uint64), ("no_locking", C.c_int32), ("reserved", C.c_int32)]
@@ -176,6 +194,14 @@ SIGNATURES = {
     "msk_estimate_psd": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.POINTER(DtnOpts),
                           C.POINTER(PsdOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PsdLog),
                           C.POINTER(PsdInfo)], C.c_int),
+    "msk_kelvin_create": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
+    "msk_kelvin_get_info": ([C.c_void_p, C.POINTER(KelvinInfo)], C.c_int),
+    "msk_kelvin_destroy": ([C.c_void_p], None),
+    "msk_kelvin_closest_points": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p], C.c_int),
+    "msk_estimate_kelvin": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_double,
+                             C.POINTER(DtnOpts), C.POINTER(PsdOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.POINTER(KelvinLog), C.POINTER(KelvinEstInfo)], C.c_int),
     "msk_autotune": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.POINTER(TuneSpace),
                       C.POINTER(TuneResult)], C.c_int),
@@ -440,6 +466,60 @@ class Context:
                                        C.byref(res)))
         return {f: getattr(res, f) for f, _ in TuneResult._fields_}
 
+    # -- exterior in the Kelvin-inverted domain
+    def kelvin(self, mesh, centre, leaf_size: int = 0) -> "Kelvin":
+        """The mesh seen through the Kelvin transform about `centre` (world, inside the shape)."""
+        c = (C.c_double * 3)(*[float(x) for x in centre])
+        h = C.c_void_p()
+        self._check(lib().msk_kelvin_create(self.h, mesh.h, c, leaf_size, C.byref(h)))
+        return Kelvin(self, h)
+
+    def kelvin_closest_points(self, kv, Q):
+        """Nearest inverted elements of Q (torch float64 CUDA tensor, n x 3, inverted space):
+        (tri, d2, nearest point, barycentrics of its image) as CUDA tensors."""
+        import torch
+
+        Q = Q.contiguous()
+        n = Q.shape[0]
+        tri = torch.empty(n, dtype=torch.int32, device=Q.device)
+        d2 = torch.empty(n, dtype=torch.float64, device=Q.device)
+        qp = torch.empty((n, 3), dtype=torch.float64, device=Q.device)
+        bary = torch.empty((n, 3), dtype=torch.float64, device=Q.device)
+        self._check(lib().msk_kelvin_closest_points(self.h, kv.h, Q.data_ptr(), n, tri.data_ptr(), d2.data_ptr(),
+                                                    qp.data_ptr(), bary.data_ptr()))
+        return tri, d2, qp, bary
+
+    def estimate_kelvin(self, kv, rows, basis, pairs: int, kill_walks: int, eps: float, cap_deg: float = 2.5,
+                        bisect_iters: int = 10, r_max: float = 0.0, chunk_pairs: int = 262144, log: bool = False,
+                        **walk_opts) -> dict:
+        """The exterior estimate in the Kelvin-inverted domain: jump and killing terms (K x K)
+        with standard errors, inverted tangent radii, info and optionally the walk log."""
+        o = self.default_opts(**walk_opts)
+        po = PsdOpts()
+        lib().msk_psd_opts_default(C.byref(po))
+        po.cap_deg, po.bisect_iters, po.r_max, po.chunk_pairs = cap_deg, bisect_iters, r_max, chunk_pairs
+        K, n = int(basis.K), int(rows.n)
+        nw = n * 2 * int(pairs) + int(kill_walks)
+        Sj, sej, Sk, sek = (np.zeros((K, K)) for _ in range(4))
+        rad = np.zeros(n)
+        info = KelvinEstInfo()
+        lg = None
+        out = {}
+        if log:
+            out = dict(status=np.zeros(nw, dtype=np.int32), tri=np.zeros(nw, dtype=np.int32),
+                       bary=np.zeros((nw, 2), dtype=np.float32), nq=np.zeros(nw, dtype=np.int32))
+            lg = KelvinLog(out["status"].ctypes.data, out["tri"].ctypes.data, out["bary"].ctypes.data,
+                           out["nq"].ctypes.data)
+        st = lib().msk_estimate_kelvin(self.h, kv.h, rows.h, basis.h, pairs, kill_walks, eps, C.byref(o),
+                                       C.byref(po), Sj.ctypes.data, sej.ctypes.data,
+                                       Sk.ctypes.data if kill_walks > 0 else None,
+                                       sek.ctypes.data if kill_walks > 0 else None, rad.ctypes.data,
+                                       C.byref(lg) if lg is not None else None, C.byref(info))
+        self._check(st)
+        res = dict(S_jump=Sj, se_jump=sej, S_kill=Sk, se_kill=sek, S=Sj + Sk, se=np.sqrt(sej ** 2 + sek ** 2),
+                   radius=rad, info={f: getattr(info, f) for f, _ in KelvinEstInfo._fields_}, **out)
+        return res
+
     def estimate_psd(self, mesh, rows, basis, pairs: int, eps: float, cap_deg: float = 2.5, bisect_iters: int = 10,
                      r_max: float = 0.0, chunk_pairs: int = 262144, log: bool = False, **walk_opts) -> dict:
         """The PSD estimator (Alg. 2) over point rows: S, se (K x K), tangent radii, info and optionally the walk log."""
@@ -509,6 +589,16 @@ class Mesh(_Handle):
         i = MeshInfo()
         self.ctx._check(lib().msk_mesh_get_info(self.h, C.byref(i)))
         return {f: (list(getattr(i, f)) if f == "centre" else getattr(i, f)) for f, _ in MeshInfo._fields_}
+
+
+class Kelvin(_Handle):
+    _destroy = "msk_kelvin_destroy"
+
+    def info(self) -> dict:
+        i = KelvinInfo()
+        self.ctx._check(lib().msk_kelvin_get_info(self.h, C.byref(i)))
+        return {f: (list(getattr(i, f)) if f in ("centre", "box_lo", "box_hi") else getattr(i, f))
+                for f, _ in KelvinInfo._fields_}
 
 
 class RowsHandle(_Handle):

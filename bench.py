@@ -156,10 +156,8 @@ def psd_leg(ctx):
     (5 K (K+1) flops per pair)."""
     import torch
 
-    from paper_2606_05581_amd import workloads as W
-
     t = time.perf_counter()
-    wl = W.load("psd_sh_sphere_2m", cache=False)
+    wl = _psd_workload()
     case = wl.cases[0]
     pairs = wl.walks // 2
     mesh = ctx.build_bvh(case.V, case.F)
@@ -202,6 +200,64 @@ def psd_leg(ctx):
             "gather": {"bound": "hbm", "achieved": gath, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": gath / HBM_PEAK_GBS, "kernel": "psd_fused_kernel" if fused else "psd_gather_kernel"},
         },
+    }
+
+
+_PSD_WL = {}
+
+
+def _psd_workload():
+    """The 2M-face SH-sphere PSD workload, built once for the PSD and Kelvin legs."""
+    from paper_2606_05581_amd import workloads as W
+
+    if "wl" not in _PSD_WL:
+        _PSD_WL["wl"] = W.load("psd_sh_sphere_2m", cache=False)
+    return _PSD_WL["wl"]
+
+
+def kelvin_leg(ctx, pairs=64, kill_walks=1 << 20):
+    """The exterior estimate in the Kelvin-inverted domain (Sec. 3.3) on the
+    SH-displaced sphere of the PSD workload (2.0M faces, 16,384 point rows,
+    K = 128), inverted about the origin (inside the shape): one untimed
+    warm-up call, then one timed call with inputs resident (inverted tangent
+    balls, jump walks from ball points, killing walks from the origin,
+    gathers and FP64 products). The build of the inverted hierarchy is timed
+    apart."""
+    import torch
+
+    wl = _psd_workload()
+    case = wl.cases[0]
+    mesh = ctx.build_bvh(case.V, case.F)
+    rh = ctx.rows(mesh, case.rows)
+    bh = ctx.basis(case.basis, case.V.shape[0])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    kv = ctx.kelvin(mesh, np.zeros(3))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    ki = kv.info()
+    eps = 1e-5 * ki["radius"]
+    log(f"[bench] kelvin workload: {case.F.shape[0]} triangles inverted in {build_s:.2f} s (depth {ki['depth']}), "
+        f"{case.rows.n_rows} rows x {pairs} pairs + {kill_walks} killing walks, K={case.basis.K}")
+    ctx.estimate_kelvin(kv, rh, bh, 2, 1024, eps)  # untimed warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.estimate_kelvin(kv, rh, bh, pairs, kill_walks, eps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = r["info"]
+    q = info["queries_total"] + info["kill_queries"]
+    log(f"[bench] kelvin: {info['walks_total'] / el:.3e} walks/s, {q / el:.3e} queries/s; tangent balls "
+        f"{info['tangent_ms']:.1f} ms, walks {info['walk_kernel_ms']:.1f} ms, products {info['product_ms']:.1f} ms")
+    return {
+        "workload": wl.name + " exterior (Kelvin-inverted)", "rows": int(info["n_rows"]), "pairs_per_row": pairs,
+        "kill_walks": kill_walks, "K": int(info["K"]), "triangles": int(case.F.shape[0]),
+        "value": info["walks_total"] / el, "unit": "walks/s", "queries_per_s": q / el, "seconds": el,
+        "inverted_build_s": build_s, "inverted_depth": int(ki["depth"]),
+        "ms": {k: info[k] for k in ("tangent_ms", "walk_kernel_ms", "product_ms")},
+        "mean_radius": info["mean_radius"], "dropped_rows": info["dropped_rows"],
+        "capped_total": info["capped_total"], "steps_per_walk": q / max(info["walks_total"], 1),
+        "S_trace": float(np.trace(r["S"])), "S_kill_trace": float(np.trace(r["S_kill"])),
     }
 
 
@@ -318,6 +374,116 @@ def knn_leg(ctx, walks=1024):
     return out
 
 
+def _roofs(per_q, queries, ms):
+    """Both rooflines of one walk launch from its algorithmic work per query."""
+    if not per_q or ms <= 0:
+        return None
+    flops = queries * per_q["fp32_ops"] / (ms * 1e-3) / 1e12
+    gbs = queries * per_q["bytes"] / (ms * 1e-3) / 1e9
+    return {"alu": {"achieved": flops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": flops / FP32_VECTOR_PEAK_TFLOPS},
+            "hbm_bytes_touched": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS},
+            "per_query": per_q}
+
+
+def config_leg(ctx, name, accum_forms=(0,), se_target=0.0, eigen=True):
+    """One of the other configurations at its full size in the persistent
+    single-mesh form: walks/s and queries/s of each operator (after an
+    untimed warm-up), per-query work from the counting kernel (untimed), the
+    eigen step's time for the workload's k, and for several accumulation
+    forms their rates and their difference from the FP64 form on the same
+    walks."""
+    import torch
+
+    from paper_2606_05581_amd import msk
+    from paper_2606_05581_amd import workloads as W
+
+    t = time.perf_counter()
+    wl = W.load(name)
+    c = wl.cases[0]
+    mesh = ctx.build_bvh(c.V, c.F)
+    rows = ctx.rows(mesh, c.rows)
+    basis = ctx.basis(c.basis, c.V.shape[0])
+    torch.cuda.synchronize()
+    prep = time.perf_counter() - t
+    out = {"workload": name, "triangles": int(c.F.shape[0]), "rows": int(c.rows.n_rows), "walks_per_row": wl.walks,
+           "operators": {}}
+    kw = {"se_target": se_target} if se_target > 0 else {}
+    for mode in wl.modes:
+        ext = mode == "exterior"
+        st = ctx.estimate_dtn(mesh, rows, basis, wl.walks, c.eps, c.h, exterior=ext, collect_stats=1, **kw)
+        si = st.info()
+        st.close()
+        q = max(si["queries_total"], 1)
+        per_q = {"nodes": si["nodes_visited"] / q, "triangles": si["tris_tested"] / q,
+                 "fp32_ops": si["valu_flops"] / q}
+        per_q["bytes"] = per_q["nodes"] * NODE_BYTES + per_q["triangles"] * TRI_BYTES
+        forms = {}
+        S0 = None
+        for a in accum_forms:
+            ctx.estimate_dtn(mesh, rows, basis, wl.walks, c.eps, c.h, exterior=ext, accum=a, **kw).close()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            d = ctx.estimate_dtn(mesh, rows, basis, wl.walks, c.eps, c.h, exterior=ext, accum=a, **kw)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            inf = d.info()
+            rec = {"walks_per_s": inf["walks_total"] / el, "queries_per_s": inf["queries_total"] / el,
+                   "steps_per_walk": inf["queries_total"] / max(inf["walks_total"], 1), "seconds": el,
+                   "walk_kernel_ms": inf["walk_kernel_ms"], "walk_launches": inf["walk_launches"],
+                   "walks_total": inf["walks_total"],
+                   "roofline": _roofs(per_q, inf["queries_total"] / max(inf["walk_launches"], 1),
+                                      inf["walk_kernel_ms"] / max(inf["walk_launches"], 1))}
+            S = d.get(msk.FIELD_S)
+            if S0 is None:
+                S0 = S
+            else:
+                rec["max_abs_diff_vs_f64_rel"] = float(np.abs(S - S0).max() / np.abs(S0).max())
+            if eigen and wl.k > 0 and c.basis.K == c.rows.n_rows:
+                t1 = time.perf_counter()
+                ev, _, est = ctx.steklov_modes(d, wl.k, vectors=False)
+                rec["eigen"] = {"k": wl.k, "seconds": time.perf_counter() - t1, "lanczos_ms": est["lanczos_ms"],
+                                "converged": bool(est["converged"]), "cycles": est["iterations"]}
+                if a != accum_forms[0] and "ev0" in forms.get("_", {}):
+                    rec["eigen"]["max_abs_diff_vs_f64_rel"] = float(np.abs(ev - forms["_"]["ev0"]).max() /
+                                                                    np.abs(forms["_"]["ev0"]).max())
+                forms.setdefault("_", {}).setdefault("ev0", ev)
+            d.close()
+            forms[{0: "f64", 1: "f32", 2: "compensated_f32"}[a]] = rec
+            log(f"[bench] {name} {mode} accum={a}: {rec['walks_per_s']:.3e} walks/s, "
+                f"{rec['queries_per_s']:.3e} queries/s")
+        forms.pop("_", None)
+        out["operators"][mode] = forms
+    out["inputs_s"] = prep
+    for h in (basis, rows, mesh):
+        h.close()
+    return out
+
+
+def plain_leaf_sweep(run, leaves=(2, 4, 8)):
+    """The plain form (one lane per walk, one launch per mesh) at each BVH
+    leaf width, meshes rebuilt in place; returns the rates and the best."""
+    import torch
+
+    from paper_2606_05581_amd import msk
+
+    res = {}
+    for leaf in leaves:
+        for h in run.handles:
+            h[1].rebuild(leaf)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        pr = run.step(with_eigen=False, form=msk.FORM_PLAIN)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp
+        res[leaf] = {"walks_per_s": sum(r["walks_total"] for r in pr) / tp,
+                     "walks_per_s_walk_kernels": sum(r["walks_total"] for r in pr) / (
+                         sum(r["walk_kernel_ms"] for r in pr) * 1e-3)}
+        log(f"[bench] plain form, leaf {leaf}: {res[leaf]['walks_per_s']:.3e} walks/s")
+    best = max(res, key=lambda k: res[k]["walks_per_s"])
+    return res, best
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -392,12 +558,17 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (unit sphere, soup, 2M-face sphere, exterior scene)")
+    ap.add_argument("--configs-only", action="store_true", help="run only the other configurations")
     ap.add_argument("--no-psd", action="store_true", help="skip the PSD estimator (Alg. 2) leg")
     ap.add_argument("--psd-only", action="store_true", help="run only the PSD estimator leg (profiling)")
     ap.add_argument("--no-knn", action="store_true", help="skip the point-basis (k-NN) leg")
     ap.add_argument("--no-laplace", action="store_true", help="skip the mesh Laplacian basis leg")
     ap.add_argument("--laplace-only", action="store_true", help="run only the mesh Laplacian basis leg")
     ap.add_argument("--knn-only", action="store_true", help="run only the point-basis leg")
+    ap.add_argument("--no-kelvin", action="store_true", help="skip the Kelvin-inverted exterior leg")
+    ap.add_argument("--kelvin-only", action="store_true", help="run only the Kelvin-inverted exterior leg")
     ap.add_argument("--launch", default="", help="fixed launch settings instead of tuning, e.g. chunk=64,regen_min=16")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2606_05581_amd", "tune_cache.jsonl"),
                     help="autotuner results (JSON lines); a stored entry for this workload is reused, else the "
@@ -425,11 +596,22 @@ def main():
     if args.psd_only:
         print(json.dumps({"psd": psd_leg(msk.Context(0))}), flush=True)
         return
+    if args.kelvin_only:
+        print(json.dumps({"kelvin": kelvin_leg(msk.Context(0))}), flush=True)
+        return
     if args.knn_only:
         print(json.dumps({"knn": knn_leg(msk.Context(0))}), flush=True)
         return
     if args.laplace_only:
         print(json.dumps({"laplace": laplace_leg(msk.Context(0))}), flush=True)
+        return
+    if args.configs_only:
+        c0 = msk.Context(0)
+        print(json.dumps({"configs": {
+            "unit_sphere_320": config_leg(c0, "unit_sphere_320"),
+            "soup8_53k": config_leg(c0, "soup8_53k"),
+            "sh_sphere_2m": config_leg(c0, "sh_sphere_2m", accum_forms=(0, 1, 2)),
+            "exterior200_301k": config_leg(c0, "exterior200_301k", se_target=1e-3)}}), flush=True)
         return
     t = time.perf_counter()
     wl = W.load(args.workload)
@@ -494,20 +676,17 @@ def main():
 
     plain = None
     if not args.no_plain:
-        torch.cuda.synchronize()
-        tp = time.perf_counter()
-        pr = run.step(with_eigen=False, form=msk.FORM_PLAIN)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - tp
         se_plain = {}
-        run.step(with_eigen=False, form=msk.FORM_PLAIN, se_out=se_plain)  # untimed
-        plain = {"walks_per_s": sum(r["walks_total"] for r in pr) / tp,
-                 "walks_per_s_walk_kernels": sum(r["walks_total"] for r in pr) / (
-                     sum(r["walk_kernel_ms"] for r in pr) * 1e-3),
-                 "launches": sum(r["walk_launches"] for r in pr),
+        run.step(with_eigen=False, form=msk.FORM_PLAIN, se_out=se_plain)  # untimed: same walks, same se
+        # the plain form at its own best BVH leaf width (the walks do not depend on it)
+        sweep, best = plain_leaf_sweep(run)
+        plain = {"walks_per_s": sweep[best]["walks_per_s"],
+                 "walks_per_s_walk_kernels": sweep[best]["walks_per_s_walk_kernels"],
+                 "leaf": best, "leaf_sweep": {str(k): v for k, v in sweep.items()},
+                 "launches": len(run.handles) * len(wl.modes),
                  "median_se_ratio": float(np.median([se_batched[k] / se_plain[k] for k in se_plain
                                                      if se_plain[k] > 0]))}
-        log(f"[bench] plain form: {plain['walks_per_s']:.3e} walks/s ({plain['launches']} launches)")
+        log(f"[bench] plain form at its best leaf width {best}: {plain['walks_per_s']:.3e} walks/s")
 
     cpu = None
     if not args.no_cpu:
@@ -568,7 +747,14 @@ def main():
         "vs_plain_walk_kernels": (walks / (kern_ms * 1e-3) / plain["walks_per_s_walk_kernels"]) if plain else None,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "configs": None if args.no_configs else {
+            "unit_sphere_320": config_leg(ctx, "unit_sphere_320"),
+            "soup8_53k": config_leg(ctx, "soup8_53k"),
+            "sh_sphere_2m": config_leg(ctx, "sh_sphere_2m", accum_forms=(0, 1, 2)),
+            "exterior200_301k": config_leg(ctx, "exterior200_301k", se_target=1e-3),
+        },
         "psd": None if args.no_psd else psd_leg(ctx),
+        "kelvin": None if args.no_kelvin else kelvin_leg(ctx),
         "knn": None if args.no_knn else knn_leg(ctx),
         "laplace": None if args.no_laplace else laplace_leg(ctx),
     }

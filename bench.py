@@ -27,8 +27,10 @@ sys.path.insert(0, ROOT)
 
 KERNEL_NAME = "walk_stream_kernel"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+CLOCK_GHZ = 2.4                  # MI355X peak engine clock
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz
 FP64_MATRIX_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix-core peak
+FP32_MATRIX_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix-core peak
 NODE_BYTES, TRI_BYTES = 128, 48
 DEFAULT_WORKLOAD = "batch64_mixed"
 
@@ -72,6 +74,20 @@ def measured_traffic(workload):
 def traffic_record(workload):
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     return json.load(open(path)) if os.path.exists(path) else None
+
+
+def issue_record(workload):
+    """VALU issue of the walk kernel from the committed counter passes
+    (instructions and active lanes per launch), if taken on the current
+    kernel sources (else None)."""
+    rec = traffic_record(workload)
+    if not rec or rec.get("source_sha") != kernel_sources_sha() or "valu_insts_per_launch" not in rec:
+        return None
+    issue_peak = 1024 * CLOCK_GHZ * 1e9 / 4  # 1,024 SIMDs, one wave64 VALU instruction per 4 cycles
+    ips = rec["valu_insts_per_launch"] / (rec["launch_ms"] * 1e-3)
+    return {"achieved": ips, "peak": issue_peak, "unit": "wave64 VALU instructions/s", "frac": ips / issue_peak,
+            "active_lanes": rec["active_lanes_per_valu"], "lane_frac": rec["active_lanes_per_valu"] / 64.0,
+            "source": f"profiles/traffic_{workload}.json"}
 
 
 class Runner:
@@ -443,7 +459,8 @@ def config_leg(ctx, name, accum_forms=(0,), se_target=0.0, eigen=True):
                 t1 = time.perf_counter()
                 ev, _, est = ctx.steklov_modes(d, wl.k, vectors=False)
                 rec["eigen"] = {"k": wl.k, "seconds": time.perf_counter() - t1, "lanczos_ms": est["lanczos_ms"],
-                                "converged": bool(est["converged"]), "cycles": est["iterations"]}
+                                "converged": bool(est["converged"]), "cycles": est["iterations"],
+                                "roofline": _eigen_roofs(est)}
                 if a != accum_forms[0] and "ev0" in forms.get("_", {}):
                     rec["eigen"]["max_abs_diff_vs_f64_rel"] = float(np.abs(ev - forms["_"]["ev0"]).max() /
                                                                     np.abs(forms["_"]["ev0"]).max())
@@ -457,6 +474,19 @@ def config_leg(ctx, name, accum_forms=(0,), se_target=0.0, eigen=True):
     out["inputs_s"] = prep
     for h in (basis, rows, mesh):
         h.close()
+    return out
+
+
+def _eigen_roofs(est):
+    """Rooflines of the eigen step's dense products from the library's event
+    sums: the FP32 products with C against the FP32 matrix peak, the FP64
+    basis products against the FP64 matrix peak (algorithmic flops 2 M N K)."""
+    out = {}
+    for key, peak in (("fp32", FP32_MATRIX_PEAK_TFLOPS), ("fp64", FP64_MATRIX_PEAK_TFLOPS)):
+        ms, fl, n = est[key + "_product_ms"], est[key + "_product_flops"], est[key + "_products"]
+        tf = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        out[key] = {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+                    "products": int(n), "ms": ms, "dtype": "f32" if key == "fp32" else "f64"}
     return out
 
 
@@ -703,13 +733,17 @@ def main():
                "frac": bytes_ach / HBM_PEAK_GBS}
         alu = {"bound": "alu", "achieved": flops_ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                "frac": flops_ach / FP32_VECTOR_PEAK_TFLOPS}
-        main_, other = (mem, alu) if mem["frac"] >= alu["frac"] else (alu, mem)
-        roof = dict(main_)
+        # the kernel is bound by VALU issue at a third of the lanes (counters),
+        # so the headline is the arithmetic roofline of its algorithmic work;
+        # the bytes it touches per query (mostly served by LDS, L2 and MALL)
+        # and the measured HBM traffic stand beside it
+        roof = dict(alu)
         tr = traffic_record(wl.name)
         roof.update({"traffic": measured_traffic(wl.name), "kernel": KERNEL_NAME, "per_query": per_q,
                      "traffic_source": ({"launch_ms": tr.get("launch_ms"), "launch": tr.get("launch"),
                                          "profile": f"profiles/traffic_{wl.name}.json"} if tr else None),
-                     "queries_per_launch": q_per_launch, "launch_ms": avg_ms, "other": other})
+                     "queries_per_launch": q_per_launch, "launch_ms": avg_ms, "bytes_touched": mem,
+                     "valu_issue": issue_record(wl.name)})
     eig = [r["eigen_ms"] for r in recs if "eigen_ms" in r]
     line = {
         "metric": "DtN walks/sec + closest-point queries/sec at fixed std-error; batched vs plain",

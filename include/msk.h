@@ -485,13 +485,20 @@ typedef struct {
   int32_t iterations;   /* block-Lanczos steps taken                      */
   int32_t block;        /* block size                                      */
   double max_residual;  /* max_j |C v_j - lambda_j v_j| / |C|_est          */
-  double lanczos_ms;
+  double lanczos_ms;    /* the whole call (events)                          */
+  /* dense products on the matrix cores: count, summed kernel time (events
+   * around each) and algorithmic flops (2 M N K each); FP32 = the products
+   * with C, FP64 = the basis products and the final Rayleigh quotients */
+  int64_t fp32_products;
+  double fp32_product_ms, fp32_product_flops;
+  int64_t fp64_products;
+  double fp64_product_ms, fp64_product_flops;
 } msk_eig_stats;
 
 /* Smallest k eigenpairs of the symmetrised, mass-scaled estimate
  * C = M^-1/2 (S + S^T)/2 M^-1/2, M = diag(w) over the rows that were not
  * discarded (Sec. 2, eq. steklov-eigenproblem; Alg. 1 symmetrisation),
- * by block Lanczos on the GPU: FP32 products with C, FP64 full
+ * by block Lanczos on the GPU: FP32 products with C on the matrix cores, FP64 full
  * re-orthogonalisation and Rayleigh quotients, the projected problem solved
  * in FP64 on the host. Requires K == n_rows.
  *   evals: host, k doubles, ascending.

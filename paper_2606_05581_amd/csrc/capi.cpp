@@ -1367,7 +1367,7 @@ extern "C" void msk_dtn_destroy(msk_dtn* d) {
 namespace msk {
 int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const std::vector<double>& w,
                          const std::vector<int32_t>& discarded, int k, double* evals, double* evecs, int* iters,
-                         int* block_out, double* max_res, double* ms_out, std::string& err);
+                         int* block_out, double* max_res, double* ms_out, EigGemmTimes* gt, std::string& err);
 }
 
 extern "C" msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* d, int32_t k, double* evals, double* evecs,
@@ -1380,13 +1380,20 @@ extern "C" msk_status msk_steklov_modes(msk_ctx* ctx, const msk_dtn* d, int32_t 
   int iters = 0, block = 0;
   double res = 0, ms = 0;
   std::string err;
+  EigGemmTimes gt;
   int rc = steklov_modes_device(ctx->stream, d->d_S, d->n, d->rows->w, disc, k, evals, evecs, &iters, &block, &res,
-                                &ms, err);
+                                &ms, stats ? &gt : nullptr, err);
   if (stats) {
     stats->iterations = iters;
     stats->block = block;
     stats->max_residual = res;
     stats->lanczos_ms = ms;
+    stats->fp32_products = gt.fp32_products;
+    stats->fp32_product_ms = gt.fp32_ms;
+    stats->fp32_product_flops = gt.fp32_flops;
+    stats->fp64_products = gt.fp64_products;
+    stats->fp64_product_ms = gt.fp64_ms;
+    stats->fp64_product_flops = gt.fp64_flops;
   }
   if (rc == 1) return fail(ctx, MSK_ERR_INVALID_ARG, err);
   if (rc == 3) return fail(ctx, MSK_ERR_DEVICE, err);

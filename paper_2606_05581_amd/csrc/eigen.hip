@@ -2,7 +2,7 @@
 // symmetrised, mass-scaled estimate C = M^-1/2 (S + S^T)/2 M^-1/2 (Alg. 1's
 // symmetrisation; Sec. 2 eq. steklov-eigenproblem) by a thick-restarted
 // block Krylov (block Lanczos) Rayleigh-Ritz method:
-//   - products with C in FP32 (tiled GEMM kernel, C stored in FP32),
+//   - products with C in FP32 on the matrix cores (C stored in FP32),
 //   - basis kept in FP64 with full re-orthogonalisation (classical
 //     Gram-Schmidt twice + Cholesky QR) on the GPU,
 //   - the small projected problem solved in FP64 on the host,
@@ -75,99 +75,188 @@ __global__ void copy_block_f64_to_f32_kernel(const double* __restrict__ x, int64
   }
 }
 
-// Row-major GEMM: C = alpha op(A) op(B) + beta C, op(A) M x K, op(B) K x N.
-// A is M x K (lda) or, transposed, K x M; B is K x N (ldb) or N x K.
-// 64 x 64 output tile per 256-thread workgroup, 4 x 4 per thread, K in steps
-// of 16 through LDS.
+// Row-major GEMM on the matrix cores: C = alpha op(A) op(B) + beta C, op(A)
+// M x K, op(B) K x N; A is M x K (lda) or, transposed, K x M; B is K x N
+// (ldb) or N x K. A 256-thread workgroup computes a 64 x 64 tile: each
+// wavefront a 32 x 32 quarter as 2 x 2 blocks of the 16 x 16 x 4 MFMA (FP64
+// or FP32, accumulating in the same precision), K in steps of 16 staged
+// through LDS. The K range may be split over blockIdx.z (the long inner
+// dimension of the Gram products Q^T X): each slice then writes its partial
+// tile to `part` (splits x M x N) and splitk_reduce_kernel sums them in a
+// fixed order.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mfma;
+// Operands: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]. Results:
+// accumulator item e of lane l is column l % 16 and row 4 e + l / 16 (FP64)
+// or row 4 (l / 16) + e (FP32) of the 16 x 16 block (measured on gfx950).
+template <>
+struct Mfma<double> {
+  typedef mfma_d4 V;
+  __device__ static V step(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int e) { return 4 * e + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+  typedef mfma_f4 V;
+  __device__ static V step(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
+
 template <typename T, bool TA, bool TB>
-__global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t K, T alpha, const T* __restrict__ A,
-                                                   int64_t lda, const T* __restrict__ B, int64_t ldb, T beta, T* Cm,
-                                                   int64_t ldc) {
+__global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk, T alpha,
+                                                   const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                                                   int64_t ldb, T beta, T* Cm, int64_t ldc, T* __restrict__ part) {
   constexpr int BM = 64, BN = 64, BK = 16;
-  __shared__ T As[BK][BM + 1];
-  __shared__ T Bs[BK][BN + 1];
-  const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;
+  __shared__ T As[BK][BM + 4];
+  __shared__ T Bs[BK][BN + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
-  T acc[4][4];
+  const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  const int wm = 32 * (wv >> 1), wn = 32 * (wv & 1);
+  typename Mfma<T>::V acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
-  for (int64_t k0 = 0; k0 < K; k0 += BK) {
-    // load A tile: BM x BK elements, 256 threads x 4
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = tid + r * 256;  // 0..1023
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = T(0);
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {  // A tile: BM x BK, 4 elements per thread
+      const int e = tid + r * 256;
       int mm, kk;
-      if (TA) {  // A stored K x M: contiguous along m
+      if (TA) {  // stored K x M: contiguous along m
         kk = e / BM;
         mm = e % BM;
-      } else {  // A stored M x K: contiguous along k
+      } else {  // stored M x K: contiguous along k
         mm = e / BK;
         kk = e % BK;
       }
       const int64_t gm = m0 + mm, gk = k0 + kk;
       T v = T(0);
-      if (gm < M && gk < K) v = TA ? A[gk * lda + gm] : A[gm * lda + gk];
+      if (gm < M && gk < ke) v = TA ? A[gk * lda + gm] : A[gm * lda + gk];
       As[kk][mm] = v;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 4; ++r) {  // B tile: BK x BN
       const int e = tid + r * 256;
       int nn, kk;
-      if (TB) {  // B stored N x K: contiguous along k
+      if (TB) {  // stored N x K: contiguous along k
         nn = e / BK;
         kk = e % BK;
-      } else {  // B stored K x N: contiguous along n
+      } else {  // stored K x N: contiguous along n
         kk = e / BN;
         nn = e % BN;
       }
       const int64_t gn = n0 + nn, gk = k0 + kk;
       T v = T(0);
-      if (gn < N && gk < K) v = TB ? B[gn * ldb + gk] : B[gk * ldb + gn];
+      if (gn < N && gk < ke) v = TB ? B[gn * ldb + gk] : B[gk * ldb + gn];
       Bs[kk][nn] = v;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      T a[4], b[4];
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      T a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
+      for (int i = 0; i < 2; ++i) a[i] = As[kk][wm + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc * 4 + j];
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kk][wn + 16 * j + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::step(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t gm = m0 + tr * 4 + i;
-    if (gm >= M) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t gn = n0 + tc * 4 + j;
-      if (gn >= N) continue;
-      T* c = Cm + gm * ldc + gn;
-      *c = alpha * acc[i][j] + (beta == T(0) ? T(0) : beta * *c);
-    }
-  }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t gm = m0 + wm + 16 * i + Mfma<T>::row(lane, e), gn = n0 + wn + 16 * j + (lane & 15);
+        if (gm >= M || gn >= N) continue;
+        if (part) {
+          part[((int64_t)blockIdx.z * M + gm) * N + gn] = acc[i][j][e];
+        } else {
+          T* c = Cm + gm * ldc + gn;
+          *c = alpha * acc[i][j][e] + (beta == T(0) ? T(0) : beta * *c);
+        }
+      }
+}
+
+// C = alpha sum_z part[z] + beta C (z ascending: a fixed order)
+template <typename T>
+__global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, T alpha, const T* __restrict__ part, T beta,
+                                     T* Cm, int64_t ldc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M * N) return;
+  T acc = T(0);
+  for (int z = 0; z < splits; ++z) acc += part[(int64_t)z * M * N + i];
+  const int64_t r = i / N, c = i % N;
+  T* o = Cm + r * ldc + c;
+  *o = alpha * acc + (beta == T(0) ? T(0) : beta * *o);
 }
 
 namespace {
 
 int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 1 << 16); }
 
+// Split-K workspace of the products (device memory owned by the caller) and,
+// optionally, event pairs around each product for the per-precision sums of
+// kernel time and algorithmic flops.
+struct GemmWs {
+  void* p = nullptr;
+  size_t bytes = 0;
+  struct Mark {
+    hipEvent_t a, b;
+    int fp32;
+    double flops;
+  };
+  std::vector<Mark>* marks = nullptr;
+};
+
+// Splits the K range over enough slices for about 512 workgroups (two per
+// compute unit) when the output has few tiles, within the workspace.
 template <typename T, bool TA, bool TB>
-hipError_t gemm(hipStream_t s, int64_t M, int64_t N, int64_t K, T alpha, const T* A, int64_t lda, const T* B,
-                int64_t ldb, T beta, T* C, int64_t ldc) {
+hipError_t gemm(hipStream_t s, const GemmWs& ws, int64_t M, int64_t N, int64_t K, T alpha, const T* A, int64_t lda,
+                const T* B, int64_t ldb, T beta, T* C, int64_t ldc) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
-  hipLaunchKernelGGL((gemm_kernel<T, TA, TB>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
-  return hipGetLastError();
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int64_t splits = 1;
+  if (K >= 512) splits = std::min<int64_t>((512 + tiles - 1) / tiles, (K + 255) / 256);
+  splits = std::min<int64_t>(splits, (int64_t)(ws.bytes / (sizeof(T) * (size_t)M * (size_t)N)));
+  splits = std::max<int64_t>(1, std::min<int64_t>(splits, 65535));
+  int64_t kchunk = ((K + splits - 1) / splits + 15) / 16 * 16;
+  if (kchunk < 16) kchunk = 16;
+  splits = std::max<int64_t>(1, (K + kchunk - 1) / kchunk);
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)splits);
+  T* part = splits > 1 ? (T*)ws.p : nullptr;
+  GemmWs::Mark mk{nullptr, nullptr, sizeof(T) == 4 ? 1 : 0, 2.0 * (double)M * (double)N * (double)K};
+  if (ws.marks) {
+    hipError_t e;
+    if ((e = hipEventCreate(&mk.a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&mk.b)) != hipSuccess) {
+      (void)hipEventDestroy(mk.a);
+      return e;
+    }
+    ws.marks->push_back(mk);
+    if ((e = hipEventRecord(mk.a, s)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((gemm_kernel<T, TA, TB>), grid, dim3(256), 0, s, M, N, std::max<int64_t>(K, 0), kchunk, alpha, A,
+                     lda, B, ldb, beta, C, ldc, part);
+  if (splits > 1) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, s, M, N,
+                       (int)splits, alpha, part, beta, C, ldc);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && ws.marks) e = hipEventRecord(mk.b, s);
+  return e;
 }
 
 struct DevBuf {
@@ -196,7 +285,7 @@ struct DevBuf {
 // 1 on bad arguments, 3 on a device error (message in err).
 int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const std::vector<double>& w,
                          const std::vector<int32_t>& discarded, int k, double* evals, double* evecs, int* iters,
-                         int* block_out, double* max_res, double* ms_out, std::string& err) {
+                         int* block_out, double* max_res, double* ms_out, EigGemmTimes* gt, std::string& err) {
   hipEvent_t e0, e1;
   EIG_TRY(hipEventCreate(&e0));
   EIG_TRY(hipEventCreate(&e1));
@@ -216,6 +305,22 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
   EIG_TRY(hipMalloc(&dm.p, n * 8));
   EIG_TRY(hipMalloc(&dC64.p, (size_t)n * n * 8));
   EIG_TRY(hipMalloc(&dC32.p, (size_t)n * n * 4));
+  // split-K partial tiles: at most about 1,024 tiles of 64 x 64 FP64
+  DevBuf dWs;
+  GemmWs ws;
+  ws.bytes = (size_t)32 << 20;
+  EIG_TRY(hipMalloc(&dWs.p, ws.bytes));
+  ws.p = dWs.p;
+  struct Marks {
+    std::vector<GemmWs::Mark> v;
+    ~Marks() {
+      for (auto& m : v) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+      }
+    }
+  } marks;
+  if (gt) ws.marks = &marks.v;
   EIG_TRY(hipMemcpyAsync(dkeep.p, keep.data(), n * 4, hipMemcpyHostToDevice, s));
   EIG_TRY(hipMemcpyAsync(dm.p, m.data(), n * 8, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(assemble_c_kernel, dim3(blocks_for(n * n)), dim3(256), 0, s, dS, n_rows, dkeep.as<int32_t>(),
@@ -272,17 +377,17 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
       std::vector<double> G((size_t)b * b), R, Ri;
       for (int pass = 0; pass < 2; ++pass) {
         if (cur > 0) {  // X -= Q (Q^T X)
-          EIG_TRY((gemm<double, true, false>(s, cur, b, n, 1.0, Q, cap, X, b, 0.0, dG.as<double>(), b)));
-          EIG_TRY((gemm<double, false, false>(s, n, b, cur, -1.0, Q, cap, dG.as<double>(), b, 1.0, X, b)));
+          EIG_TRY((gemm<double, true, false>(s, ws, cur, b, n, 1.0, Q, cap, X, b, 0.0, dG.as<double>(), b)));
+          EIG_TRY((gemm<double, false, false>(s, ws, n, b, cur, -1.0, Q, cap, dG.as<double>(), b, 1.0, X, b)));
         }
-        EIG_TRY((gemm<double, true, false>(s, b, b, n, 1.0, X, b, X, b, 0.0, dT.as<double>(), b)));
+        EIG_TRY((gemm<double, true, false>(s, ws, b, b, n, 1.0, X, b, X, b, 0.0, dT.as<double>(), b)));
         EIG_TRY(hipMemcpyAsync(G.data(), dT.p, (size_t)b * b * 8, hipMemcpyDeviceToHost, s));
         EIG_TRY(hipStreamSynchronize(s));
         if (!cholesky_upper(b, G, R, 1e-24)) return 0;
         upper_inverse(b, R, Ri);
         EIG_TRY(hipMemcpyAsync(dT.p, Ri.data(), (size_t)b * b * 8, hipMemcpyHostToDevice, s));
         // X = X R^-1 (through a temporary: dQ2's first n*b entries)
-        EIG_TRY((gemm<double, false, false>(s, n, b, b, 1.0, X, b, dT.as<double>(), b, 0.0, dQ2.as<double>(), b)));
+        EIG_TRY((gemm<double, false, false>(s, ws, n, b, b, 1.0, X, b, dT.as<double>(), b, 0.0, dQ2.as<double>(), b)));
         EIG_TRY(hipMemcpyAsync(X, dQ2.p, (size_t)n * b * 8, hipMemcpyDeviceToDevice, s));
       }
       // append X to Q, C X (FP32 product) to W
@@ -290,7 +395,7 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
                          (int64_t)cap, n, (int64_t)b);
       hipLaunchKernelGGL(copy_block_f64_to_f32_kernel, dim3(blocks_for(n * b)), dim3(256), 0, s, X, (int64_t)b,
                          dX32.as<float>(), (int64_t)b, n, (int64_t)b);
-      EIG_TRY((gemm<float, false, false>(s, n, b, n, 1.0f, dC32.as<float>(), n, dX32.as<float>(), b, 0.0f,
+      EIG_TRY((gemm<float, false, false>(s, ws, n, b, n, 1.0f, dC32.as<float>(), n, dX32.as<float>(), b, 0.0f,
                                          dY32.as<float>(), b)));
       hipLaunchKernelGGL(copy_block_f32_to_f64_kernel, dim3(blocks_for(n * b)), dim3(256), 0, s, dY32.as<float>(),
                          (int64_t)b, Wm + cur, (int64_t)cap, n, (int64_t)b);
@@ -329,7 +434,7 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
         if (!ok) break;
       }
       // Rayleigh-Ritz on span(Q[:, :cur])
-      EIG_TRY((gemm<double, true, false>(s, cur, cur, n, 1.0, Q, cap, Wm, cap, 0.0, dT.as<double>(), cur)));
+      EIG_TRY((gemm<double, true, false>(s, ws, cur, cur, n, 1.0, Q, cap, Wm, cap, 0.0, dT.as<double>(), cur)));
       T.assign((size_t)cur * cur, 0.0);
       EIG_TRY(hipMemcpyAsync(T.data(), dT.p, T.size() * 8, hipMemcpyDeviceToHost, s));
       EIG_TRY(hipStreamSynchronize(s));
@@ -345,8 +450,8 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
       cnorm = std::max(cnorm, tmax);
       // Ritz vectors V = Q Y[:, :kk], CV = W Y[:, :kk] (Y is cur x kk)
       EIG_TRY(hipMemcpyAsync(dY.p, Y.data(), (size_t)cur * kk * 8, hipMemcpyHostToDevice, s));
-      EIG_TRY((gemm<double, false, false>(s, n, kk, cur, 1.0, Q, cap, dY.as<double>(), kk, 0.0, dQ2.as<double>(), kk)));
-      EIG_TRY((gemm<double, false, false>(s, n, kk, cur, 1.0, Wm, cap, dY.as<double>(), kk, 0.0, dW2.as<double>(), kk)));
+      EIG_TRY((gemm<double, false, false>(s, ws, n, kk, cur, 1.0, Q, cap, dY.as<double>(), kk, 0.0, dQ2.as<double>(), kk)));
+      EIG_TRY((gemm<double, false, false>(s, ws, n, kk, cur, 1.0, Wm, cap, dY.as<double>(), kk, 0.0, dW2.as<double>(), kk)));
       // residual norms of the first k Ritz pairs: |CV_j - theta_j V_j|
       std::vector<double> V2((size_t)n * kk), CV2((size_t)n * kk);
       EIG_TRY(hipMemcpyAsync(V2.data(), dQ2.p, V2.size() * 8, hipMemcpyDeviceToHost, s));
@@ -410,7 +515,7 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
     EIG_TRY(hipMalloc(&dV.p, (size_t)n * k * 8));
     EIG_TRY(hipMalloc(&dCV.p, (size_t)n * k * 8));
     EIG_TRY(hipMemcpyAsync(dV.p, Vk.data(), Vk.size() * 8, hipMemcpyHostToDevice, s));
-    EIG_TRY((gemm<double, false, false>(s, n, k, n, 1.0, dC64.as<double>(), n, dV.as<double>(), k, 0.0,
+    EIG_TRY((gemm<double, false, false>(s, ws, n, k, n, 1.0, dC64.as<double>(), n, dV.as<double>(), k, 0.0,
                                         dCV.as<double>(), k)));
     std::vector<double> CV((size_t)n * k);
     EIG_TRY(hipMemcpyAsync(CV.data(), dCV.p, CV.size() * 8, hipMemcpyDeviceToHost, s));
@@ -449,6 +554,22 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
   float f = 0;
   EIG_TRY(hipEventElapsedTime(&f, e0, e1));
   *ms_out = f;
+  if (gt) {
+    *gt = EigGemmTimes{};
+    for (const auto& m : marks.v) {
+      float g = 0;
+      EIG_TRY(hipEventElapsedTime(&g, m.a, m.b));
+      if (m.fp32) {
+        ++gt->fp32_products;
+        gt->fp32_ms += g;
+        gt->fp32_flops += m.flops;
+      } else {
+        ++gt->fp64_products;
+        gt->fp64_ms += g;
+        gt->fp64_flops += m.flops;
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return status;

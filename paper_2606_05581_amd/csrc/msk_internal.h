@@ -250,4 +250,12 @@ hipError_t launch_psd_fused(const PsdGather& G, int64_t n_pairs, int64_t n_slots
 hipError_t launch_psd_syrk(const double* A, int64_t m, int64_t Kp, int64_t slices, double* P, hipStream_t s);
 hipError_t launch_psd_reduce(const double* P, int64_t n_slots, int64_t K, int64_t Kp, double* C, hipStream_t s);
 hipError_t launch_psd_se(const double* S, const double* Q, int64_t n, double n_pairs, double* se, hipStream_t s);
+// Summed kernel time and algorithmic flops of the eigen step's dense
+// products, by precision (FP32: the products with C; FP64: the basis
+// products and the final Rayleigh quotients).
+struct EigGemmTimes {
+  int64_t fp32_products = 0, fp64_products = 0;
+  double fp32_ms = 0, fp32_flops = 0, fp64_ms = 0, fp64_flops = 0;
+};
+
 }  // namespace msk

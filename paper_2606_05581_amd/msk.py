@@ -74,7 +74,9 @@ class DtnInfo(C.Structure):
 
 class EigStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("block", C.c_int32), ("max_residual", C.c_double),
-                ("lanczos_ms", C.c_double)]
+                ("lanczos_ms", C.c_double), ("fp32_products", C.c_int64), ("fp32_product_ms", C.c_double),
+                ("fp32_product_flops", C.c_double), ("fp64_products", C.c_int64), ("fp64_product_ms", C.c_double),
+                ("fp64_product_flops", C.c_double)]
 
 
 class TuneSpace(C.Structure):
@@ -556,8 +558,7 @@ class Context:
                                      evecs.ctypes.data if vectors else None, C.byref(stats))
         if st not in (OK, ERR_NOT_CONVERGED):
             self._check(st)
-        return evals, evecs, dict(converged=st == OK, iterations=stats.iterations, block=stats.block,
-                                  max_residual=stats.max_residual, lanczos_ms=stats.lanczos_ms)
+        return evals, evecs, dict(converged=st == OK, **{f: getattr(stats, f) for f, _ in EigStats._fields_})
 
 
 class _Handle:

@@ -79,3 +79,13 @@ def test_eigen_krylov_path_soup2000(ctx):
     # products with C are FP32, the basis and Rayleigh quotients FP64: eigenvalues within 1e-6 |C|
     # of LAPACK (measured 2e-8 to 9e-8 on the full-size estimates)
     assert err < 1e-6 and res < 2e-4
+    # the library's product accounting: every FP32 product is C (n x n) times one block (n x b)
+    assert st["fp32_products"] >= st["iterations"] and st["fp64_products"] > 0
+    assert st["fp32_product_ms"] > 0 and st["fp64_product_ms"] > 0
+    per = st["fp32_product_flops"] / st["fp32_products"]
+    nk = np.sqrt(per / (2 * st["block"]))
+    assert per == pytest.approx(2 * round(nk) ** 2 * st["block"], rel=1e-12)
+    print(f"[soup8 N=2000 interior] products with C: {st['fp32_products']} in {st['fp32_product_ms']:.2f} ms "
+          f"({st['fp32_product_flops'] / st['fp32_product_ms'] / 1e9:.1f} TFLOP/s FP32); FP64 products: "
+          f"{st['fp64_products']} in {st['fp64_product_ms']:.2f} ms "
+          f"({st['fp64_product_flops'] / st['fp64_product_ms'] / 1e9:.1f} TFLOP/s)", flush=True)

@@ -962,7 +962,9 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 #ifndef MSK_LDS_TOP_NODES
 #define MSK_LDS_TOP_NODES 21
 #endif
-// top BVH nodes staged in LDS by the persistent kernel (at most kMaxTop)
+// top BVH nodes staged in LDS by the persistent kernel in single-mesh
+// launches (at most kMaxTop), in dynamic LDS: batched launches, whose lanes
+// work on many meshes at once, reserve none
 constexpr int kLdsTop = MSK_LDS_TOP_NODES < kMaxTop ? MSK_LDS_TOP_NODES : kMaxTop;
 #ifndef MSK_PERSISTENT_WAVES_PER_EU
 #define MSK_PERSISTENT_WAVES_PER_EU 4
@@ -1000,7 +1002,7 @@ __device__ unsigned long long g_phase_cycles[16];
 // walks, their queries and their results are those of the other forms.
 template <bool kStats, typename AccT, bool kKnn = false>
 __global__ void __launch_bounds__(256) MSK_PERSISTENT_OCCUPANCY walk_stream_kernel(WalkLaunch L) {
-  __shared__ Node4 top[kLdsTop > 0 ? kLdsTop : 1];
+  extern __shared__ Node4 top[];  // kLdsTop nodes when L.use_lds_top, else none
   __shared__ WaveTables<AccT> T;
   __shared__ CoopScratch coop[kWaves];
   const int wi = threadIdx.x >> 6;
@@ -1607,28 +1609,29 @@ hipError_t launch_walk_plain(const WalkLaunch& L, hipStream_t s) {
 hipError_t launch_walk_persistent(const WalkLaunch& L, int grid, hipStream_t s) {
   if (L.knn && L.stats) return hipErrorInvalidValue;  // the point basis has no counting instantiation
   if (L.accum < 0 || L.accum > 2) return hipErrorInvalidValue;
+  const size_t lds = L.use_lds_top && kLdsTop > 0 ? sizeof(Node4) * kLdsTop : 0;
   if (L.knn) {  // point basis: instantiations carrying the k-NN evaluation
     if (L.accum == 1)
-      hipLaunchKernelGGL((walk_stream_kernel<false, float, true>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<false, float, true>), dim3(grid), dim3(256), lds, s, L);
     else if (L.accum == 2)
-      hipLaunchKernelGGL((walk_stream_kernel<false, CompF32, true>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<false, CompF32, true>), dim3(grid), dim3(256), lds, s, L);
     else
-      hipLaunchKernelGGL((walk_stream_kernel<false, double, true>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<false, double, true>), dim3(grid), dim3(256), lds, s, L);
   } else if (L.accum == 1) {
     if (L.stats)
-      hipLaunchKernelGGL((walk_stream_kernel<true, float>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<true, float>), dim3(grid), dim3(256), lds, s, L);
     else
-      hipLaunchKernelGGL((walk_stream_kernel<false, float>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<false, float>), dim3(grid), dim3(256), lds, s, L);
   } else if (L.accum == 2) {
     if (L.stats)
-      hipLaunchKernelGGL((walk_stream_kernel<true, CompF32>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<true, CompF32>), dim3(grid), dim3(256), lds, s, L);
     else
-      hipLaunchKernelGGL((walk_stream_kernel<false, CompF32>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<false, CompF32>), dim3(grid), dim3(256), lds, s, L);
   } else {
     if (L.stats)
-      hipLaunchKernelGGL((walk_stream_kernel<true, double>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<true, double>), dim3(grid), dim3(256), lds, s, L);
     else
-      hipLaunchKernelGGL((walk_stream_kernel<false, double>), dim3(grid), dim3(256), 0, s, L);
+      hipLaunchKernelGGL((walk_stream_kernel<false, double>), dim3(grid), dim3(256), lds, s, L);
   }
   return hipGetLastError();
 }

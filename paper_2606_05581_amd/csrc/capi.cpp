@@ -1741,22 +1741,52 @@ extern "C" msk_status msk_kelvin_create(msk_ctx* ctx, const msk_mesh* m, const d
     for (int j = 0; j < 3; ++j)
       for (int k = 0; k < 3; ++k) P[j][k] = (double)m->vworld[3 * (int64_t)m->faces[3 * t + j] + k] - centre[k];
     T.orig = (int32_t)t;
-    T.pad = 0;
+    T.has_plane = kelvin_plane(T.a, T.b, T.c, T.n, T.cpl) ? 1 : 0;
+    if (!T.has_plane) T.n[0] = T.n[1] = T.n[2] = T.cpl = 0.0;
+    T.M2 = std::max(dot3d(T.a, T.a), std::max(dot3d(T.b, T.b), dot3d(T.c, T.c)));
     // a box containing the image: each coordinate of y / |y|^2 over the
     // triangle is a quotient of a value in the coordinate's range by one in
     // [m2, M2] (squared distances from the centre)
     const double m2 = origin_tri_d2(T.a, T.b, T.c);
-    const double M2 = std::max(dot3d(T.a, T.a), std::max(dot3d(T.b, T.b), dot3d(T.c, T.c)));
+    const double M2 = T.M2;
     dmin = std::min(dmin, m2);
     if (!(m2 > 0)) return fail(ctx, MSK_ERR_INVALID_ARG, "the inversion centre lies on the surface (triangle " +
                                                           std::to_string(t) + ")");
+    // a second enclosure, tight for small elements: kappa(y) = kappa(a) +
+    // J(a) (y - a) + R with J(a) = (I - 2 a^ a^T) / |a|^2 and the Taylor
+    // remainder |R| <= |y - a|^2 / rmin^3 (|D^2 kappa(x)[h, h]| = 2 |h|^2 /
+    // |x|^3, and the segment's points are at least rmin = sqrt(m2) from the
+    // centre): the affine image of the triangle, padded by twice that bound
+    double p3[3][3];
+    {
+      const double aa = dot3d(T.a, T.a);
+      const double e1[3] = {T.b[0] - T.a[0], T.b[1] - T.a[1], T.b[2] - T.a[2]};
+      const double e2[3] = {T.c[0] - T.a[0], T.c[1] - T.a[1], T.c[2] - T.a[2]};
+      const double ae1 = dot3d(T.a, e1), ae2 = dot3d(T.a, e2);
+      for (int k = 0; k < 3; ++k) {
+        p3[0][k] = T.a[k] / aa;
+        p3[1][k] = p3[0][k] + (e1[k] - 2.0 * T.a[k] * ae1 / aa) / aa;
+        p3[2][k] = p3[0][k] + (e2[k] - 2.0 * T.a[k] * ae2 / aa) / aa;
+      }
+    }
+    double h2 = 0.0;
+    for (const double* v : {T.b, T.c}) {
+      const double e[3] = {v[0] - T.a[0], v[1] - T.a[1], v[2] - T.a[2]};
+      h2 = std::max(h2, dot3d(e, e));
+    }
+    const double rem = 2.0 * h2 / (m2 * std::sqrt(m2));
     for (int k = 0; k < 3; ++k) {
       const double a = std::min(T.a[k], std::min(T.b[k], T.c[k])), b = std::max(T.a[k], std::max(T.b[k], T.c[k]));
       double l, h;
       if (a >= 0) { l = a / M2; h = b / m2; }
       else if (b <= 0) { l = a / m2; h = b / M2; }
       else { l = a / m2; h = b / m2; }
-      const double pad = 1e-12 * (std::fabs(l) + std::fabs(h));
+      // the intersection of the two enclosures
+      const double l2 = std::min(p3[0][k], std::min(p3[1][k], p3[2][k])) - rem;
+      const double u2 = std::max(p3[0][k], std::max(p3[1][k], p3[2][k])) + rem;
+      l = std::max(l, l2);
+      h = std::min(h, u2);
+      const double pad = 1e-12 * (std::fabs(l) + std::fabs(h)) + 1e-15 * std::sqrt(1.0 / m2);
       boxes[t].lo[k] = round_down(l - pad);
       boxes[t].hi[k] = round_up(h + pad);
       cen[3 * t + k] = (float)(0.5 * (l + h));
@@ -1908,14 +1938,14 @@ extern "C" msk_status msk_estimate_kelvin(msk_ctx* ctx, const msk_kelvin* K, con
   double *d_st = nullptr, *d_nt = nullptr, *d_rad = nullptr, *d_g = nullptr, *d_alpha = nullptr, *d_kalpha = nullptr;
   int32_t *d_ls = nullptr, *d_lt = nullptr, *d_lq = nullptr, *d_ktri = nullptr;
   float *d_lb = nullptr, *d_tab = nullptr, *d_kbary = nullptr;
-  unsigned long long *d_rq = nullptr, *d_tq = nullptr, *d_kq = nullptr, *d_nonf = nullptr;
+  unsigned long long *d_rq = nullptr, *d_tq = nullptr, *d_kq = nullptr, *d_nonf = nullptr, *d_next = nullptr;
   double *d_S = nullptr, *d_Q = nullptr, *d_se = nullptr, *d_PS = nullptr, *d_PQ = nullptr, *d_U = nullptr,
          *d_V = nullptr;
   hipEvent_t ev[5] = {};
   auto cleanup = [&](msk_status s_) {
     dfree(d_st); dfree(d_nt); dfree(d_rad); dfree(d_g); dfree(d_alpha); dfree(d_kalpha);
     dfree(d_ls); dfree(d_lt); dfree(d_lq); dfree(d_ktri); dfree(d_lb); dfree(d_tab); dfree(d_kbary);
-    dfree(d_rq); dfree(d_tq); dfree(d_kq); dfree(d_nonf);
+    dfree(d_rq); dfree(d_tq); dfree(d_kq); dfree(d_nonf); dfree(d_next);
     dfree(d_S); dfree(d_Q); dfree(d_se); dfree(d_PS); dfree(d_PQ); dfree(d_U); dfree(d_V);
     for (hipEvent_t& e : ev) {
       if (e) (void)hipEventDestroy(e);
@@ -1938,6 +1968,7 @@ extern "C" msk_status msk_estimate_kelvin(msk_ctx* ctx, const msk_kelvin* K, con
   HIP_K(dalloc(&d_tq, n));
   HIP_K(dalloc(&d_rq, n));
   HIP_K(dalloc(&d_kq, 1));
+  HIP_K(dalloc(&d_next, 1));
   HIP_K(dalloc(&d_nonf, 1));
   HIP_K(dalloc(&d_g, n_walk));
   HIP_K(dalloc(&d_ls, n_walk));
@@ -1956,8 +1987,33 @@ extern "C" msk_status msk_estimate_kelvin(msk_ctx* ctx, const msk_kelvin* K, con
   const KelvinDev D = kelvin_dev(K, eps, o);
   HIP_K(launch_kelvin_tangent(D, d_st, d_nt, n, r_max, po.bisect_iters, 0.5 * eps, d_rad, d_tq, s));
   HIP_K(hipEventRecord(ev[1], s));
-  HIP_K(launch_kelvin_walks(D, d_st, d_nt, d_rad, n, pairs, u0, kill_walks, d_ls, d_lt, d_lb, d_lq, d_g, d_rq, d_kq,
-                            s));
+  KelvinDev DW = D;
+  if (kill_walks > 0) {  // the origin's nearest element, shared by the first steps of all killing walks
+    double* d_o = nullptr;
+    int32_t* d_ot = nullptr;
+    HIP_K(dalloc(&d_o, 10));
+    hipError_t e1 = dalloc(&d_ot, 1);
+    double ho[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int32_t hot = -1;
+    if (e1 == hipSuccess) e1 = hipMemcpyAsync(d_o, ho, sizeof(ho), hipMemcpyHostToDevice, s);
+    if (e1 == hipSuccess) e1 = launch_kelvin_closest(D, d_o, 1, d_ot, d_o + 3, d_o + 4, d_o + 7, s);
+    if (e1 == hipSuccess) e1 = hipMemcpyAsync(ho, d_o, sizeof(ho), hipMemcpyDeviceToHost, s);
+    if (e1 == hipSuccess) e1 = hipMemcpyAsync(&hot, d_ot, sizeof(hot), hipMemcpyDeviceToHost, s);
+    if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
+    dfree(d_o);
+    dfree(d_ot);
+    HIP_K(e1);
+    DW.origin_known = 1;
+    DW.origin_orig = hot;
+    DW.origin_d2 = ho[3];
+    for (int c = 0; c < 3; ++c) {
+      DW.origin_q[c] = ho[4 + c];
+      DW.origin_l[c] = ho[7 + c];
+    }
+  }
+  HIP_K(launch_fill_u64(d_next, 1, 0, s));
+  HIP_K(launch_kelvin_walks(DW, d_st, d_nt, d_rad, n, pairs, u0, kill_walks, d_ls, d_lt, d_lb, d_lq, d_g, d_rq,
+                            d_kq, d_next, std::max(1, ctx->n_cu * 4), s));
   HIP_K(hipEventRecord(ev[2], s));
   std::vector<double> rad((size_t)n);
   HIP_K(hipMemcpyAsync(rad.data(), d_rad, n * 8, hipMemcpyDeviceToHost, s));

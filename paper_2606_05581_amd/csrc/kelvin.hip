@@ -13,10 +13,16 @@
 // and the distance is written stably in that limit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "msk_internal.h"
 #include "philox.h"
+
+// wavefronts per SIMD the persistent walk kernel is compiled for
+#ifndef MSK_KELVIN_WAVES_PER_EU
+#define MSK_KELVIN_WAVES_PER_EU 4
+#endif
 
 namespace msk {
 
@@ -120,6 +126,24 @@ __host__ __device__ void edge_image(const double x[3], const double P[3], const 
 
 }  // namespace
 
+// The plane of triangle (a, b, c) as used by the distance below: unit normal
+// n and offset cpl = n . a, or false for a (numerically) degenerate triangle.
+__host__ __device__ bool kelvin_plane(const double a[3], const double b[3], const double c[3], double n[3],
+                                      double& cpl) {
+#pragma clang fp contract(off)
+  double ab[3], ac[3];
+  for (int k = 0; k < 3; ++k) {
+    ab[k] = b[k] - a[k];
+    ac[k] = c[k] - a[k];
+  }
+  cross(ab, ac, n);
+  const double nl = sqrt(dot(n, n));
+  if (!(nl > 1e-12 * fmax(dot(ab, ab), dot(ac, ac)))) return false;
+  for (int k = 0; k < 3; ++k) n[k] /= nl;
+  cpl = dot(n, a);
+  return true;
+}
+
 // Squared distance from x to the image of triangle T, its nearest point and
 // the barycentrics of that point's image in T. The triangle's plane
 // n . y = c maps to the sphere through the origin with centre n / (2c) and
@@ -129,37 +153,42 @@ __host__ __device__ void edge_image(const double x[3], const double P[3], const 
 // projection as c -> 0. The projection belongs to the patch when its image
 // lies in T; otherwise the nearest point is on the patch's boundary (distance
 // to a sphere's points grows with their angle from the radial projection).
-__host__ __device__ double kelvin_tri_d2(const double x[3], const KelvinTri& T, double q[3], double l[3]) {
+// Every point of the patch lies on that sphere (or plane), so its distance
+// bounds the patch's from below: when its square exceeds `bound` (with a
+// relative margin for rounding) the element cannot come nearer than bound and
+// INFINITY is returned without the boundary arcs.
+__host__ __device__ double kelvin_tri_d2(const double x[3], const KelvinTri& T, double q[3], double l[3],
+                                         double bound) {
 #pragma clang fp contract(off)
   Best b;
   b.d2 = INFINITY;
-  double ab[3], ac[3], n[3];
-  for (int k = 0; k < 3; ++k) {
-    ab[k] = T.b[k] - T.a[k];
-    ac[k] = T.c[k] - T.a[k];
-  }
-  cross(ab, ac, n);
-  const double nl = sqrt(dot(n, n));
-  if (nl > 1e-12 * fmax(dot(ab, ab), dot(ac, ac))) {
-    for (int k = 0; k < 3; ++k) n[k] /= nl;
-    const double c = dot(n, T.a);
+  if (T.has_plane) {
+    const double* n = T.n;
+    const double c = T.cpl;
     double p[3];
     if (c != 0.0) {
       const double sg = c > 0.0 ? 1.0 : -1.0;
       const double v[3] = {c * x[0] - 0.5 * n[0], c * x[1] - 0.5 * n[1], c * x[2] - 0.5 * n[2]};
       const double vl = sqrt(dot(v, v));
       const double sd = (fabs(c) * dot(x, x) - sg * dot(n, x)) / (vl + 0.5);
+      if (sd * sd > bound * (1.0 + 1e-9)) return INFINITY;
       for (int k = 0; k < 3; ++k) p[k] = x[k] - sd * sg * v[k] / vl;
     } else {
       const double nx = dot(n, x);
+      if (nx * nx > bound * (1.0 + 1e-9)) return INFINITY;
       for (int k = 0; k < 3; ++k) p[k] = x[k] - nx * n[k];
     }
-    const double M2 = fmax(dot(T.a, T.a), fmax(dot(T.b, T.b), dot(T.c, T.c)));
-    if (dot(p, p) * M2 >= 1.0 - 1e-9) {  // image points lie at least 1 / max|vertex| from the origin
-      double y[3], ay[3], w[3];
+    if (dot(p, p) * T.M2 >= 1.0 - 1e-9) {  // image points lie at least 1 / max|vertex| from the origin
+      double y[3], ay[3], w[3], ab[3], ac[3], nn[3];
       invert(p, y);
-      for (int k = 0; k < 3; ++k) ay[k] = y[k] - T.a[k];
-      // barycentrics of y's projection on the plane, n unit
+      for (int k = 0; k < 3; ++k) {
+        ay[k] = y[k] - T.a[k];
+        ab[k] = T.b[k] - T.a[k];
+        ac[k] = T.c[k] - T.a[k];
+      }
+      // barycentrics of y's projection on the plane
+      cross(ab, ac, nn);
+      const double nl = dot(nn, n);
       cross(ay, ac, w);
       const double l1 = dot(w, n) / nl;
       cross(ab, ay, w);
@@ -221,7 +250,7 @@ __host__ __device__ double kelvin_nearest(const KelvinDev& K, const double x[3],
         for (int32_t s = first; s < first + cn[k]; ++s) {
           const KelvinTri& T = K.tris[s];
           double qq[3], ll[3];
-          const double d = kelvin_tri_d2(x, T, qq, ll);
+          const double d = kelvin_tri_d2(x, T, qq, ll, best);
           if (d < best || (d == best && T.orig < orig)) {
             best = d;
             orig = T.orig;
@@ -261,6 +290,43 @@ __host__ __device__ double kelvin_nearest(const KelvinDev& K, const double x[3],
   return best;
 }
 
+
+// Whether some inverted element lies nearer to x than t (its distance, the
+// square root of the exact squared distance, below t): the decision the
+// tangent-ball bisection needs, equal to comparing the nearest element's
+// distance with t. Boxes and element spheres farther than t (with a small
+// relative margin for their own rounding) are skipped, and the search stops
+// at the first element found, so a point far from every element costs a few
+// box tests instead of a full nearest search.
+__host__ __device__ bool kelvin_any_within(const KelvinDev& K, const double x[3], double t) {
+  if (!(t > 0.0)) return false;
+  const double t2 = t * t * (1.0 + 1e-9);
+  int32_t stk[kStackDepth];
+  int sp = 0;
+  int32_t node = 0;
+  while (true) {
+    const Node4& N = K.nodes[node];
+    for (int k = 0; k < 4; ++k) {
+      const double gx = fmax(fmax((double)N.lox[k] - x[0], x[0] - (double)N.hix[k]), 0.0);
+      const double gy = fmax(fmax((double)N.loy[k] - x[1], x[1] - (double)N.hiy[k]), 0.0);
+      const double gz = fmax(fmax((double)N.loz[k] - x[2], x[2] - (double)N.hiz[k]), 0.0);
+      if (!(gx * gx + gy * gy + gz * gz <= t2)) continue;
+      const int32_t cc = N.child[k], cn = N.count[k];
+      if (cc < 0) {
+        const int32_t first = -cc - 1;
+        for (int32_t e = first; e < first + cn; ++e) {
+          double qq[3], ll[3];
+          const double d2 = kelvin_tri_d2(x, K.tris[e], qq, ll, t2);
+          if (sqrt(d2) < t) return true;
+        }
+      } else if (sp < kStackDepth) {
+        stk[sp++] = cc;
+      }
+    }
+    if (sp == 0) return false;
+    node = stk[--sp];
+  }
+}
 namespace {
 
 __device__ __forceinline__ void frame(const double n[3], double e1[3], double e2[3]) {
@@ -271,33 +337,36 @@ __device__ __forceinline__ void frame(const double n[3], double e1[3], double e2
   e2[0] = b; e2[1] = sg + n[1] * n[1] * a; e2[2] = -n[1];
 }
 
-// Walk-on-Spheres in the inverted domain from x: step k draws the Philox
-// block (row, walk, k, step purpose), the same streams as the oracle. Ends
-// in the eps-shell (hit) or at the step cap (nearest point of the last
-// position). Returns the status; orig, q and l describe the terminal point.
-__device__ int32_t kelvin_walk(const KelvinDev& K, uint32_t row, uint32_t walk, double x[3], int32_t& orig,
-                               double q[3], double l[3], int32_t& queries) {
-  for (int64_t k = 0; k < K.max_steps; ++k) {
-    const double d2 = kelvin_nearest(K, x, orig, q, l);
-    if (d2 < K.eps2) {
-      queries = (int32_t)(k + 1);
-      return kHit;
+// One step of Walk-on-Spheres in the inverted domain at x: the exact
+// nearest element; in the eps-shell the walk has hit (true), else x moves to
+// a uniform point of the sphere of radius d (1 - kappa) - delta, drawn from
+// the Philox block (row, walk, k, step purpose), the oracle's streams.
+__device__ bool kelvin_step(const KelvinDev& K, uint32_t row, uint32_t walk, int64_t k, double x[3], int32_t& orig,
+                            double q[3], double l[3], bool at_origin) {
+  double d2;
+  if (at_origin) {  // the first step of a killing walk: the shared answer
+    d2 = K.origin_d2;
+    orig = K.origin_orig;
+    for (int c = 0; c < 3; ++c) {
+      q[c] = K.origin_q[c];
+      l[c] = K.origin_l[c];
     }
-    const uint4 u = philox10(make_uint4(row, walk, (uint32_t)k, (kPurposeStep << 24) | (K.mesh_id & 0xFFFFFFu)),
-                             K.seed_lo, K.seed_hi);
-    const double u0 = unit_f(u.x), u1 = unit_f(u.y);
-    const double r = sqrt(d2) * (1.0 - K.kappa) - K.delta;
-    const double z = 1.0 - 2.0 * u0;
-    const double rxy = 2.0 * sqrt(u0 * (1.0 - u0));
-    double sp, cp;
-    sincospi(2.0 * u1, &sp, &cp);
-    x[0] += r * rxy * cp;
-    x[1] += r * rxy * sp;
-    x[2] += r * z;
+  } else {
+    d2 = kelvin_nearest(K, x, orig, q, l);
   }
-  kelvin_nearest(K, x, orig, q, l);
-  queries = (int32_t)(K.max_steps + 1);
-  return kCapped;
+  if (d2 < K.eps2) return true;
+  const uint4 u = philox10(make_uint4(row, walk, (uint32_t)k, (kPurposeStep << 24) | (K.mesh_id & 0xFFFFFFu)),
+                           K.seed_lo, K.seed_hi);
+  const double u0 = unit_f(u.x), u1 = unit_f(u.y);
+  const double r = sqrt(d2) * (1.0 - K.kappa) - K.delta;
+  const double z = 1.0 - 2.0 * u0;
+  const double rxy = 2.0 * sqrt(u0 * (1.0 - u0));
+  double sp, cp;
+  sincospi(2.0 * u1, &sp, &cp);
+  x[0] += r * rxy * cp;
+  x[1] += r * rxy * sp;
+  x[2] += r * z;
+  return false;
 }
 
 }  // namespace
@@ -318,11 +387,8 @@ __global__ void kelvin_tangent_kernel(KelvinDev K, const double* __restrict__ st
   for (int32_t it = 0; it < iters; ++it) {
     const double mid = 0.5 * (lo + hi);
     const double c[3] = {s[0] - mid * n[0], s[1] - mid * n[1], s[2] - mid * n[2]};
-    int32_t o;
-    double q[3], l[3];
-    const double d = sqrt(kelvin_nearest(K, c, o, q, l));
     const double t = mid - fmin(tol, mid * (1.0 / 1024.0));
-    if (d >= t && sqrt(dot(c, c)) + mid <= K.radius)
+    if (sqrt(dot(c, c)) + mid <= K.radius && !kelvin_any_within(K, c, t))
       lo = mid;
     else
       hi = mid;
@@ -331,71 +397,101 @@ __global__ void kelvin_tangent_kernel(KelvinDev K, const double* __restrict__ st
   queries[i] = (unsigned long long)iters;
 }
 
-// One lane per walk. Walks [0, n_rows 2 pairs) are the jump term's: walk
-// 2j + a of row i starts at point a of antithetic pair j on the row's tangent
-// ball, drawn with density proportional to the ball jump kernel outside the
-// cap (u = sin(theta/2) with density ~ 1/u^2 on [u0, 1], inverted in closed
-// form; azimuth uniform, + pi for the partner). The next n_kill walks are the
+// Walks [0, n_rows 2 pairs) are the jump term's: walk 2j + a of row i starts
+// at point a of antithetic pair j on the row's tangent ball, drawn with
+// density proportional to the ball jump kernel outside the cap
+// (u = sin(theta/2) with density ~ 1/u^2 on [u0, 1], inverted in closed form;
+// azimuth uniform, + pi for the partner). The next n_kill walks are the
 // killing term's, from the origin (the image of infinity), with Philox row
-// 0xFFFFFFFF and walk index k. Each walk logs its status, terminal original
+// 0xFFFFFFFF and walk index k. The launch is persistent: every lane claims
+// walks one at a time from a counter and advances its walk by one step per
+// loop trip, so a lane whose walk ends takes the next one at once instead of
+// idling until the longest walk of its wavefront ends; each walk's result
+// depends on its index only. Each walk logs its status, terminal original
 // triangle, the barycentrics of that triangle's vertices 1 and 2 at the
 // terminal point's image, its query count, and the factor g = 1/|t~| of its
 // rank-one update.
-__global__ void kelvin_walk_kernel(KelvinDev K, const double* __restrict__ st, const double* __restrict__ nt,
-                                   const double* __restrict__ radius, int64_t n_rows, int64_t pairs, double u0,
-                                   int64_t n_kill, int32_t* __restrict__ log_status, int32_t* __restrict__ log_tri,
-                                   float* __restrict__ log_bary, int32_t* __restrict__ log_q, double* __restrict__ g,
-                                   unsigned long long* __restrict__ row_queries, unsigned long long* kill_queries) {
-  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n_jump = n_rows * 2 * pairs;
-  if (id >= n_jump + n_kill) return;
-  double x[3] = {0.0, 0.0, 0.0};
-  uint32_t row = 0xFFFFFFFFu, walk;
-  int64_t i = -1;
-  if (id < n_jump) {
-    i = id / (2 * pairs);
-    const int64_t w = id - i * 2 * pairs;
-    const double r = radius[i];
-    if (!(r > 0.0)) {
-      log_status[id] = -1;
-      log_tri[id] = -1;
-      log_bary[2 * id] = log_bary[2 * id + 1] = 0.0f;
-      log_q[id] = 0;
-      g[id] = 0.0;
-      return;
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MSK_KELVIN_WAVES_PER_EU)))
+kelvin_walk_kernel(
+    KelvinDev K, const double* __restrict__ st, const double* __restrict__ nt, const double* __restrict__ radius,
+    int64_t n_rows, int64_t pairs, double u0, int64_t n_kill, int32_t* __restrict__ log_status,
+    int32_t* __restrict__ log_tri, float* __restrict__ log_bary, int32_t* __restrict__ log_q, double* __restrict__ g,
+    unsigned long long* __restrict__ row_queries, unsigned long long* kill_queries, unsigned long long* next_walk) {
+  const int64_t n_jump = n_rows * 2 * pairs, total = n_jump + n_kill;
+  int64_t id = -1, i = -1, k = 0;
+  uint32_t row = 0, walk = 0;
+  double x[3] = {0.0, 0.0, 0.0}, q[3] = {0.0, 0.0, 0.0}, l[3] = {0.0, 0.0, 0.0};
+  int32_t orig = -1;
+  while (true) {
+    if (id < 0) {  // claim the next walk
+      id = (int64_t)atomicAdd(next_walk, 1ull);
+      if (id >= total) break;
+      k = 0;
+      orig = -1;
+      if (id < n_jump) {
+        i = id / (2 * pairs);
+        const int64_t w = id - i * 2 * pairs;
+        const double r = radius[i];
+        if (!(r > 0.0)) {
+          log_status[id] = -1;
+          log_tri[id] = -1;
+          log_bary[2 * id] = log_bary[2 * id + 1] = 0.0f;
+          log_q[id] = 0;
+          g[id] = 0.0;
+          id = -1;
+          continue;
+        }
+        row = (uint32_t)i;
+        walk = (uint32_t)w;
+        const uint4 u = philox10(
+            make_uint4(row, (uint32_t)(w >> 1), 0u, (kPurposeBall << 24) | (K.mesh_id & 0xFFFFFFu)), K.seed_lo,
+            K.seed_hi);
+        const double xi = unit_f(u.x), eta = unit_f(u.y);
+        const double su = 1.0 / (1.0 / u0 - xi * (1.0 / u0 - 1.0));
+        const double ct = 1.0 - 2.0 * su * su, sn = 2.0 * su * sqrt(fmax(0.0, 1.0 - su * su));
+        double sp, cp;
+        sincospi(2.0 * eta + ((w & 1) ? 1.0 : 0.0), &sp, &cp);
+        const double n[3] = {nt[3 * i], nt[3 * i + 1], nt[3 * i + 2]};
+        double e1[3], e2[3];
+        frame(n, e1, e2);
+        for (int c3 = 0; c3 < 3; ++c3) {
+          const double c = st[3 * i + c3] - r * n[c3];
+          x[c3] = c + r * (ct * n[c3] + sn * (cp * e1[c3] + sp * e2[c3]));
+        }
+      } else {
+        i = -1;
+        row = 0xFFFFFFFFu;
+        walk = (uint32_t)(id - n_jump);
+        x[0] = x[1] = x[2] = 0.0;
+      }
     }
-    row = (uint32_t)i;
-    walk = (uint32_t)w;
-    const uint4 u = philox10(make_uint4(row, (uint32_t)(w >> 1), 0u, (kPurposeBall << 24) | (K.mesh_id & 0xFFFFFFu)),
-                             K.seed_lo, K.seed_hi);
-    const double xi = unit_f(u.x), eta = unit_f(u.y);
-    const double su = 1.0 / (1.0 / u0 - xi * (1.0 / u0 - 1.0));
-    const double ct = 1.0 - 2.0 * su * su, sn = 2.0 * su * sqrt(fmax(0.0, 1.0 - su * su));
-    double sp, cp;
-    sincospi(2.0 * eta + ((w & 1) ? 1.0 : 0.0), &sp, &cp);
-    const double n[3] = {nt[3 * i], nt[3 * i + 1], nt[3 * i + 2]};
-    double e1[3], e2[3];
-    frame(n, e1, e2);
-    for (int k = 0; k < 3; ++k) {
-      const double c = st[3 * i + k] - r * n[k];
-      x[k] = c + r * (ct * n[k] + sn * (cp * e1[k] + sp * e2[k]));
+    int32_t status = -1, nq = 0;
+    if (k < K.max_steps) {
+      if (kelvin_step(K, row, walk, k, x, orig, q, l, i < 0 && k == 0 && K.origin_known)) {
+        status = kHit;
+        nq = (int32_t)(k + 1);
+      } else {
+        ++k;
+      }
+    } else {  // step cap: the nearest point of the last position
+      kelvin_nearest(K, x, orig, q, l);
+      status = kCapped;
+      nq = (int32_t)(K.max_steps + 1);
     }
-  } else {
-    walk = (uint32_t)(id - n_jump);
+    if (status >= 0) {
+      log_status[id] = status;
+      log_tri[id] = orig;
+      log_bary[2 * id] = (float)l[1];
+      log_bary[2 * id + 1] = (float)l[2];
+      log_q[id] = nq;
+      g[id] = 1.0 / sqrt(dot(q, q));
+      if (i >= 0)
+        atomicAdd(row_queries + i, (unsigned long long)nq);
+      else
+        atomicAdd(kill_queries, (unsigned long long)nq);
+      id = -1;
+    }
   }
-  int32_t orig = -1, nq = 0;
-  double q[3], l[3];
-  const int32_t status = kelvin_walk(K, row, walk, x, orig, q, l, nq);
-  log_status[id] = status;
-  log_tri[id] = orig;
-  log_bary[2 * id] = (float)l[1];
-  log_bary[2 * id + 1] = (float)l[2];
-  log_q[id] = nq;
-  g[id] = 1.0 / sqrt(dot(q, q));
-  if (i >= 0)
-    atomicAdd(row_queries + i, (unsigned long long)nq);
-  else
-    atomicAdd(kill_queries, (unsigned long long)nq);
 }
 
 // Nearest inverted element of each query point (inverted space, relative to
@@ -427,11 +523,14 @@ hipError_t launch_kelvin_tangent(const KelvinDev& K, const double* st, const dou
 hipError_t launch_kelvin_walks(const KelvinDev& K, const double* st, const double* nt, const double* radius,
                                int64_t n_rows, int64_t pairs, double u0, int64_t n_kill, int32_t* log_status,
                                int32_t* log_tri, float* log_bary, int32_t* log_q, double* g,
-                               unsigned long long* row_queries, unsigned long long* kill_queries, hipStream_t s) {
+                               unsigned long long* row_queries, unsigned long long* kill_queries,
+                               unsigned long long* next_walk, int grid, hipStream_t s) {
   const int64_t n = n_rows * 2 * pairs + n_kill;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kelvin_walk_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, K, st, nt, radius,
-                     n_rows, pairs, u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries);
+  if (grid < 1) return hipErrorInvalidValue;
+  const int64_t blocks = std::min<int64_t>(grid, (n + 255) / 256);
+  hipLaunchKernelGGL(kelvin_walk_kernel, dim3((unsigned)blocks), dim3(256), 0, s, K, st, nt, radius, n_rows, pairs,
+                     u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries, next_walk);
   return hipGetLastError();
 }
 

@@ -1716,7 +1716,7 @@ extern "C" msk_status msk_kelvin_create(msk_ctx* ctx, const msk_mesh* m, const d
   if (!m || !centre) return fail(ctx, MSK_ERR_INVALID_ARG, "null mesh or centre");
   if (!std::isfinite(centre[0]) || !std::isfinite(centre[1]) || !std::isfinite(centre[2]))
     return fail(ctx, MSK_ERR_INVALID_ARG, "the inversion centre must be finite");
-  if (leaf_size == 0) leaf_size = 4;
+  if (leaf_size == 0) leaf_size = 1;
   if (leaf_size < 1 || leaf_size > 8) return fail(ctx, MSK_ERR_INVALID_ARG, "leaf_size must be in 1..8");
   const int64_t nf = m->nf;
   std::vector<KelvinTri> rec((size_t)nf);

@@ -246,3 +246,51 @@ def test_kelvin_agrees_with_the_escape_estimator_on_an_ellipsoid(ctx):
           f"finite difference {np.round(np.diag(Ff), 4)} +- {np.round(np.diag(Fse), 4)}", flush=True)
     tol = 4 * np.sqrt(Kse ** 2 + Fse ** 2) + 0.02 * np.abs(np.diag(Ff)).max()
     assert np.all(np.abs(Kf - Ff) <= tol)
+
+
+def test_kelvin_sh_sphere_2m_row_subset_parity_and_full_size(ctx, oracle_mod):
+    """The benched Kelvin configuration (the 2.0M-face SH sphere inverted about
+    the origin, K = 128 spherical harmonics, eps = 1e-5 R~):
+      * 160 Morton-spread rows x 64 pairs and 4,096 killing walks on the full
+        mesh, GPU against the oracle (same rows, same streams): radii,
+        terminal triangles and both terms as above;
+      * all 16,384 rows x 64 pairs and 2^20 killing walks on the GPU, as the
+        bench times them: both terms symmetric positive semidefinite, the jump
+        term's constant row zero to FP32 table rounding (b(s) - b(t) vanishes
+        for a constant), the killing term's constant entry positive."""
+    import dataclasses
+    import time
+
+    wl = W.load("psd_sh_sphere_2m")
+    case = wl.cases[0]
+    order = W.morton_order(case.rows.p)
+    sel = np.sort(order[np.linspace(0, len(order) - 1, 160).astype(np.int64)])
+    r = case.rows
+    sub = dataclasses.replace(r, w=r.w[sel], p=r.p[sel], n=r.n[sel], tri=r.tri[sel], bary=r.bary[sel])
+    tab = np.zeros((case.V.shape[0], case.basis.K))
+    rows_of = np.repeat(np.arange(case.V.shape[0]), np.diff(case.basis.rowptr))
+    tab[rows_of, case.basis.col] = case.basis.val
+    mesh = ctx.build_bvh(case.V, case.F)
+    bh = ctx.basis(case.basis, case.V.shape[0])
+    kv = ctx.kelvin(mesh, np.zeros(3))
+    eps = 1e-5 * kv.info()["radius"]
+    print(f"[kelvin full] subset of {len(sel)} rows x 64 pairs + 4096 killing walks, K={case.basis.K}, "
+          f"{case.F.shape[0]} faces, R~ = {kv.info()['radius']:.3f}", flush=True)
+    g = ctx.estimate_kelvin(kv, ctx.rows(mesh, sub), bh, 64, 4096, eps, seed=0, log=True)
+    t = time.time()
+    ks = oracle_mod.KelvinScene(case.V, case.F, np.zeros(3))
+    assert ks.radius == pytest.approx(kv.info()["radius"], rel=1e-12)
+    o = oracle_mod.kelvin_estimate(ks, sub, tab.astype(np.float32).astype(np.float64), 64, 4096, eps, seed=0,
+                                   log=True, nthreads=16)
+    print(f"[kelvin full] oracle on the subset: {time.time() - t:.1f} s", flush=True)
+    _check(g, o, ks.r_max(), "psd_sh_sphere_2m exterior, 160-row subset, K=128")
+    f = ctx.estimate_kelvin(kv, ctx.rows(mesh, r), bh, 64, 1 << 20, eps, seed=0)
+    for key in ("jump", "kill"):
+        S = f["S_" + key]
+        assert np.array_equal(S, S.T)
+        lam = np.linalg.eigvalsh(S)
+        assert lam.min() >= -1e-12 * lam.max()
+    assert np.abs(f["S_jump"][0]).max() < 1e-6 * np.abs(f["S_jump"]).max()
+    assert f["S_kill"][0, 0] > 0
+    print(f"[kelvin full] 16,384 rows x 64 pairs + 2^20 killing walks: walks {f['info']['walk_kernel_ms']:.1f} ms, "
+          f"dropped rows {f['info']['dropped_rows']}, capped {f['info']['capped_total']}", flush=True)

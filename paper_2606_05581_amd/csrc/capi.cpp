@@ -13,6 +13,9 @@
 
 #include "../../include/msk.h"
 #include "msk_internal.h"
+#include "eigen.h"
+#include "kelvin.h"
+#include "psd.h"
 #include "laplace.h"
 
 using namespace msk;

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "msk_internal.h"
+#include "eigen.h"
 
 namespace msk {
 

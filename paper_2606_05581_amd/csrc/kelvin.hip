@@ -17,6 +17,7 @@
 #include <cmath>
 
 #include "msk_internal.h"
+#include "kelvin.h"
 #include "philox.h"
 
 // wavefronts per SIMD the persistent walk kernel is compiled for

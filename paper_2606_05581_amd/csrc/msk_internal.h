@@ -180,6 +180,13 @@ hipError_t launch_closest_points(const Node4* nodes, const TriRec* tris, float r
 hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walks, const double* w, double* S,
                            double* se, hipStream_t s, int32_t jump_only = 0);
 
+// Blocked symmetric products shared by the PSD estimator and the mesh basis
+// (psd.hip):
+int64_t psd_blocks(int64_t Kp);
+// Partial 64 x 64 upper blocks of A^T A (A: m x Kp row-major) into P: slices x 4 slots of psd_blocks(Kp) blocks
+hipError_t launch_psd_syrk(const double* A, int64_t m, int64_t Kp, int64_t slices, double* P, hipStream_t s);
+hipError_t launch_psd_reduce(const double* P, int64_t n_slots, int64_t K, int64_t Kp, double* C, hipStream_t s);
+
 // Fixed workspace of the allocation-free estimate (noalloc.hip): 64 MiB per
 // device. noalloc_scratch_init looks its address up on `device` (which must
 // be current) once; noalloc_scratch returns it (nullptr if the lookup failed
@@ -187,88 +194,5 @@ hipError_t launch_finalize(const MeshDev& M, int64_t n_rows, const int64_t* walk
 constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
 hipError_t noalloc_scratch_init(int device);
 void* noalloc_scratch(int device, hipError_t* err);
-
-// PSD estimator (psd.hip): per-pair inputs of the rank-one updates
-struct PsdGather {
-  const float* tab;         // dense per-vertex basis table, n_verts x K (the basis values, FP32)
-  int64_t K;
-  int64_t Kp;               // row stride of the gathered update rows (K rounded up to 64)
-  int64_t pairs;            // antithetic pairs per row
-  const int32_t* faces;     // original faces (n_tris x 3)
-  const int32_t* tri;       // sample face per row
-  const float* bary;        // sample barycentrics per row (n x 3)
-  const double* w;          // row weights
-  const float* radius;      // tangent-ball radius per row (0 = dropped)
-  double u0;                // sin(theta0 / 2)
-  const int32_t* log_status;  // walk log, n_rows x 2 pairs
-  const int32_t* log_tri;
-  const float* log_bary;
-  // optional (null = the interior estimator's): per-row alpha replacing
-  // w Z(r) / (2 pairs), and a per-walk factor g of its rank-one update
-  // (X_p = alpha (g_1 d_1 d_1^T + g_2 d_2 d_2^T) / 2), both FP64
-  const double* alpha_row;
-  const double* walk_g;
-};
-// Exterior estimate in the Kelvin-inverted domain (kelvin.hip): an element is
-// a mesh triangle given by its vertices relative to the inversion centre
-// (FP64), in BVH leaf order, with its original index.
-struct KelvinTri {
-  double a[3], b[3], c[3];  // vertices relative to the inversion centre
-  double n[3];              // unit normal of the triangle's plane n . y = cpl (if has_plane)
-  double cpl;
-  double M2;                // largest squared vertex norm
-  int32_t orig;
-  int32_t has_plane;        // 0 for a (numerically) degenerate triangle: arcs only
-};
-static_assert(sizeof(KelvinTri) == 120, "inverted element record must be 120 bytes");
-struct KelvinDev {
-  const Node4* nodes;      // 4-wide hierarchy over boxes containing the inverted elements
-  const KelvinTri* tris;
-  int64_t n_tris;
-  double radius;           // bound of the inverted domain (max |x~| on its boundary)
-  double eps2;             // shell width squared (inverted units)
-  double kappa, delta;     // step radius d (1 - kappa) - delta
-  int64_t max_steps;
-  uint32_t mesh_id, seed_lo, seed_hi;
-  // the nearest element of the origin, where every killing walk starts (one
-  // query for all of them; near the middle of a round shape every element is
-  // almost equally near and that query visits most of the hierarchy)
-  int32_t origin_known, origin_orig;
-  double origin_d2, origin_q[3], origin_l[3];
-};
-hipError_t launch_kelvin_tangent(const KelvinDev& K, const double* st, const double* nt, int64_t n_rows, double r_max,
-                                 int32_t iters, double tol, double* radius, unsigned long long* queries,
-                                 hipStream_t s);
-hipError_t launch_kelvin_walks(const KelvinDev& K, const double* st, const double* nt, const double* radius,
-                               int64_t n_rows, int64_t pairs, double u0, int64_t n_kill, int32_t* log_status,
-                               int32_t* log_tri, float* log_bary, int32_t* log_q, double* g,
-                               unsigned long long* row_queries, unsigned long long* kill_queries,
-                               unsigned long long* next_walk, int grid, hipStream_t s);
-// Plane of a triangle for its inverted element (unit normal n, offset n . a);
-// false for a numerically degenerate triangle.
-__host__ __device__ bool kelvin_plane(const double a[3], const double b[3], const double c[3], double n[3],
-                                      double& cpl);
-hipError_t launch_kelvin_closest(const KelvinDev& K, const double* Q, int64_t nq, int32_t* tri, double* d2,
-                                 double* qpt, double* bary, hipStream_t s);
-
-hipError_t launch_dense_table(const int32_t* rowptr, const int32_t* col, const float* val, int64_t nv, int64_t K,
-                              float* tab, hipStream_t s);
-hipError_t launch_psd_gather(const PsdGather& G, int64_t q0, int64_t nq, double* U, double* V, hipStream_t s);
-int64_t psd_blocks(int64_t Kp);
-// Fused gather + products (Kp <= 384): partial slots (one per workgroup column) of S and Q blocks; 0 = not available
-int64_t psd_fused_slots(int64_t Kp, int64_t n_pairs);
-hipError_t launch_psd_fused(const PsdGather& G, int64_t n_pairs, int64_t n_slots, double* PS, double* PQ,
-                            hipStream_t s);
-// Partial 64 x 64 upper blocks of A^T A (A: m x Kp row-major) into P: slices x 4 slots of psd_blocks(Kp) blocks
-hipError_t launch_psd_syrk(const double* A, int64_t m, int64_t Kp, int64_t slices, double* P, hipStream_t s);
-hipError_t launch_psd_reduce(const double* P, int64_t n_slots, int64_t K, int64_t Kp, double* C, hipStream_t s);
-hipError_t launch_psd_se(const double* S, const double* Q, int64_t n, double n_pairs, double* se, hipStream_t s);
-// Summed kernel time and algorithmic flops of the eigen step's dense
-// products, by precision (FP32: the products with C; FP64: the basis
-// products and the final Rayleigh quotients).
-struct EigGemmTimes {
-  int64_t fp32_products = 0, fp64_products = 0;
-  double fp32_ms = 0, fp32_flops = 0, fp64_ms = 0, fp64_flops = 0;
-};
 
 }  // namespace msk

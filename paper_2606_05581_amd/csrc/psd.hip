@@ -21,6 +21,7 @@
 #include <cmath>
 
 #include "msk_internal.h"
+#include "psd.h"
 #include "laplace.h"
 
 namespace msk {

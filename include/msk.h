@@ -608,8 +608,9 @@ msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* mesh, const msk_rows* 
  * 4-wide hierarchy over boxes that contain their images (leaf_size 1..8, 0 =
  * 1: one element per leaf, the fastest on MI355X since an element's exact
  * distance costs far more than a box test). Errors: INVALID_ARG for a centre
- * on the surface or at a vertex, or a
- * non-finite centre. All geometry of this path is FP64. */
+ * at a vertex or on the surface (nearer to a triangle than 1e-9 times its
+ * largest vertex distance), or a non-finite centre. All geometry of this
+ * path is FP64. */
 typedef struct msk_kelvin msk_kelvin;
 typedef struct {
   double centre[3];     /* inversion centre (world)                         */

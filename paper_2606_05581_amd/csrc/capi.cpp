@@ -1726,12 +1726,13 @@ extern "C" msk_status msk_kelvin_create(msk_ctx* ctx, const msk_mesh* m, const d
   std::vector<Box3f> boxes((size_t)nf);
   std::vector<float> cen((size_t)nf * 3);
   double dmin = INFINITY, lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  double rmax = 0;
+  double rmax = 0, far2 = 0;
   for (int64_t v = 0; v < m->nv; ++v) {
     double x[3];
     for (int k = 0; k < 3; ++k) x[k] = (double)m->vworld[3 * v + k] - centre[k];
     const double r2 = dot3d(x, x);
     if (!(r2 > 0)) return fail(ctx, MSK_ERR_INVALID_ARG, "the inversion centre is a mesh vertex");
+    far2 = std::max(far2, r2);
     for (int k = 0; k < 3; ++k) {
       lo[k] = std::min(lo[k], x[k] / r2);
       hi[k] = std::max(hi[k], x[k] / r2);
@@ -1753,8 +1754,11 @@ extern "C" msk_status msk_kelvin_create(msk_ctx* ctx, const msk_mesh* m, const d
     const double m2 = origin_tri_d2(T.a, T.b, T.c);
     const double M2 = T.M2;
     dmin = std::min(dmin, m2);
-    if (!(m2 > 0)) return fail(ctx, MSK_ERR_INVALID_ARG, "the inversion centre lies on the surface (triangle " +
-                                                          std::to_string(t) + ")");
+    // a centre within 1e-9 of the mesh's extent from a triangle makes the
+    // inverted domain ~1e9 times larger than its elements: refused as on it
+    if (!(m2 > 1e-18 * far2))
+      return fail(ctx, MSK_ERR_INVALID_ARG, "the inversion centre lies on the surface (triangle " + std::to_string(t) +
+                                                ", within 1e-9 of the mesh's extent)");
     // a second enclosure, tight for small elements: kappa(y) = kappa(a) +
     // J(a) (y - a) + R with J(a) = (I - 2 a^ a^T) / |a|^2 and the Taylor
     // remainder |R| <= |y - a|^2 / rmin^3 (|D^2 kappa(x)[h, h]| = 2 |h|^2 /

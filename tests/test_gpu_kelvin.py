@@ -294,3 +294,42 @@ def test_kelvin_sh_sphere_2m_row_subset_parity_and_full_size(ctx, oracle_mod):
     assert f["S_kill"][0, 0] > 0
     print(f"[kelvin full] 16,384 rows x 64 pairs + 2^20 killing walks: walks {f['info']['walk_kernel_ms']:.1f} ms, "
           f"dropped rows {f['info']['dropped_rows']}, capped {f['info']['capped_total']}", flush=True)
+
+
+def test_kelvin_argument_errors(ctx):
+    """The inverted mesh and its estimate refuse what the method excludes,
+    with INVALID_ARG and a message, and the context stays usable: a centre
+    at a vertex or on a triangle (the inversion is undefined there), a
+    non-finite centre, a leaf width out of range; hat rows, a point basis,
+    no pairs, an odd number of killing walks, eps at or below the floor."""
+    from paper_2606_05581_amd import msk
+
+    V, F, tab = _sphere(2)
+    mesh = ctx.build_bvh(V.astype(np.float32), F)
+
+    def refused(fn, words):
+        with pytest.raises(msk.MskError) as ei:
+            fn()
+        assert ei.value.status == msk.ERR_INVALID_ARG and words in str(ei.value), str(ei.value)
+
+    Vf = V.astype(np.float32).astype(np.float64)
+    refused(lambda: ctx.kelvin(mesh, Vf[7]), "vertex")
+    refused(lambda: ctx.kelvin(mesh, Vf[F[3]].mean(0)), "surface")
+    refused(lambda: ctx.kelvin(mesh, np.array([0.0, np.nan, 0.0])), "finite")
+    refused(lambda: ctx.kelvin(mesh, np.zeros(3), leaf_size=9), "leaf_size")
+    kv = ctx.kelvin(mesh, np.zeros(3))
+    eps = 1e-5 * kv.info()["radius"]
+    rows = W.point_rows(V, F, 50, np.random.default_rng(2))
+    rh = ctx.rows(mesh, rows)
+    bh = ctx.basis(W.dense_basis(tab.astype(np.float32)), V.shape[0])
+    hat = ctx.rows(mesh, W.hat_rows(V, F))
+    refused(lambda: ctx.estimate_kelvin(kv, hat, bh, 4, 0, eps), "point rows")
+    knn = ctx.basis_knn(mesh, rows.p, rows.n, k=4)
+    refused(lambda: ctx.estimate_kelvin(kv, rh, knn, 4, 0, eps), "table basis")
+    refused(lambda: ctx.estimate_kelvin(kv, rh, bh, 0, 0, eps), "pairs")
+    refused(lambda: ctx.estimate_kelvin(kv, rh, bh, 4, 101, eps), "even")
+    floor = max(2.0 ** -21 * kv.info()["radius"] / (1 - 2.0 ** -20), 2.0 ** -40 * kv.info()["radius"])
+    refused(lambda: ctx.estimate_kelvin(kv, rh, bh, 4, 0, 0.5 * floor), "eps must exceed")
+    r = ctx.estimate_kelvin(kv, rh, bh, 4, 0, eps)  # no killing walks: the jump term alone
+    assert np.all(r["S_kill"] == 0) and np.all(np.isfinite(r["S_jump"]))
+    assert r["info"]["kill_walks"] == 0 and r["info"]["walks_total"] == 50 * 8 - 8 * r["info"]["dropped_rows"]

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <condition_variable>
 #include <cstdint>
+#include <cfloat>
 #include <cmath>
 #include <functional>
 #include <mutex>
@@ -250,28 +251,92 @@ bool sym_eig(int n, std::vector<double>& A, std::vector<double>& evals, std::vec
 
 namespace {
 
-// Eigenvalues of the symmetric tridiagonal (d, e) by implicit QR without
-// vectors; false if QR did not settle.
-bool tridiag_eigenvalues(int n, std::vector<double> d, std::vector<double> e, std::vector<double>& out) {
-  std::vector<double> none;
-  const double tol = 4e-16;
-  int hi = n - 1;
-  long iters = 0;
-  while (hi > 0) {
-    if (std::fabs(e[hi - 1]) <= tol * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
-      e[hi - 1] = 0.0;
-      --hi;
-      continue;
-    }
-    int lo = hi - 1;
-    while (lo > 0 && std::fabs(e[lo - 1]) > tol * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
-    if (lo > 0) e[lo - 1] = 0.0;
-    qr_step(n, lo, hi, d, e, none);
-    if (++iters > 60L * n + 100) return false;
+// Numbers of eigenvalues of the symmetric tridiagonal (d, e) below each of
+// B points x: the negative pivots of the LDL^T factorisation of T - x I
+// (Sylvester's law of inertia; Golub & Van Loan 8.4.1), e2[i] = e[i]^2, a
+// pivot smaller than pivmin in magnitude replaced by -pivmin. The B
+// recurrences are independent; interleaving them hides the divisions'
+// latency.
+template <int B>
+void sturm_counts(int n, const double* d, const double* e2, const double* x, double pivmin, int* c) {
+  double q[B];
+  for (int b = 0; b < B; ++b) {
+    q[b] = d[0] - x[b];
+    if (std::fabs(q[b]) < pivmin) q[b] = -pivmin;
+    c[b] = q[b] < 0.0;
   }
-  out = d;
+  for (int i = 1; i < n; ++i) {
+    for (int b = 0; b < B; ++b) {
+      q[b] = (d[i] - x[b]) - e2[i - 1] / q[b];
+      if (std::fabs(q[b]) < pivmin) q[b] = -pivmin;
+      c[b] += q[b] < 0.0;
+    }
+  }
+}
+
+// The m smallest eigenvalues of the symmetric tridiagonal (d, e), ascending,
+// and the largest, each by bisection on the Sturm count inside the
+// Gershgorin interval to an absolute width of 4 eps |T| (eigenvalues are
+// independent: four bisections advance together, groups are pool tasks).
+void tridiag_smallest(int n, const std::vector<double>& d, const std::vector<double>& e, int m,
+                      std::vector<double>& out, double& largest) {
+  std::vector<double> e2(std::max(n - 1, 1), 0.0);
+  double glo = INFINITY, ghi = -INFINITY, emax2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+    glo = std::min(glo, d[i] - r);
+    ghi = std::max(ghi, d[i] + r);
+    if (i + 1 < n) {
+      e2[i] = e[i] * e[i];
+      emax2 = std::max(emax2, e2[i]);
+    }
+  }
+  const double tnorm = std::max(std::fabs(glo), std::fabs(ghi));
+  const double eps = std::ldexp(1.0, -52);
+  const double pivmin = DBL_MIN * std::max(1.0, emax2);
+  const double atol = 4.0 * eps * std::max(tnorm, DBL_MIN);
+  glo -= 2.0 * atol + pivmin;
+  ghi += 2.0 * atol + pivmin;
+  // targets: indices 0..m-1 and n-1 (the largest), in groups of four
+  std::vector<int> idx(m + 1);
+  for (int j = 0; j < m; ++j) idx[j] = j;
+  idx[m] = n - 1;
+  std::vector<double> val(m + 1, 0.0);
+  constexpr int kB = 4;
+  const int groups = (m + 1 + kB - 1) / kB;
+  parallel_rows(groups, 1, [&](int g0, int g1) {
+    for (int g = g0; g < g1; ++g) {
+      double lo[kB], hi[kB], mid[kB];
+      int j[kB], c[kB];
+      for (int b = 0; b < kB; ++b) {
+        const int t = std::min(g * kB + b, m);  // a short last group repeats the last target
+        j[b] = idx[t];
+        lo[b] = glo;
+        hi[b] = ghi;
+      }
+      for (int it = 0; it < 200; ++it) {
+        bool open = false;
+        for (int b = 0; b < kB; ++b) {
+          mid[b] = 0.5 * (lo[b] + hi[b]);
+          open = open || hi[b] - lo[b] > atol;
+        }
+        if (!open) break;
+        sturm_counts<kB>(n, d.data(), e2.data(), mid, pivmin, c);
+        for (int b = 0; b < kB; ++b) {
+          if (!(hi[b] - lo[b] > atol)) continue;
+          if (c[b] <= j[b])
+            lo[b] = mid[b];
+          else
+            hi[b] = mid[b];
+        }
+      }
+      for (int b = 0; b < kB; ++b)
+        if (g * kB + b <= m) val[g * kB + b] = 0.5 * (lo[b] + hi[b]);
+    }
+  });
+  out.assign(val.begin(), val.begin() + m);
+  largest = val[m];
   std::sort(out.begin(), out.end());
-  return true;
 }
 
 // LU factorisation with partial pivoting of the tridiagonal T - sigma I
@@ -342,10 +407,9 @@ bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>&
   if (m > n) m = n;
   std::vector<double> d, e, Qdummy, H, betas;
   tridiagonalise(n, A, Qdummy, d, e, false, &H, &betas);
-  std::vector<double> all;
-  if (!tridiag_eigenvalues(n, d, e, all)) return false;
-  if (abs_max) *abs_max = std::max(std::fabs(all.front()), std::fabs(all.back()));
-  evals.assign(all.begin(), all.begin() + m);
+  double largest = 0.0;
+  tridiag_smallest(n, d, e, m, evals, largest);
+  if (abs_max) *abs_max = std::max(std::fabs(evals.front()), std::fabs(largest));
   double tnorm = 0.0;
   for (int i = 0; i < n; ++i)
     tnorm = std::max(tnorm, std::fabs(d[i]) + (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0));
@@ -406,20 +470,40 @@ bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>&
     }
     std::copy(y.begin(), y.end(), Xc.begin() + (size_t)j * n);
   }
-  // back-transform each vector: H_0 H_1 ... H_{n-3} x (last reflector first)
-  parallel_rows(m, 8, [&](int lo, int hi) {
-    for (int j = lo; j < hi; ++j) {
-      double* xj = &Xc[(size_t)j * n];
-      for (int k = n - 3; k >= 0; --k) {
-        const double beta = betas[k];
-        if (beta == 0.0) continue;
-        const double* v = &H[(size_t)k * n];  // v[k+1] = 1, v[k+2..] stored
-        double s = xj[k + 1];
-        for (int r = k + 2; r < n; ++r) s += v[r] * xj[r];
-        s *= beta;
-        xj[k + 1] -= s;
-        for (int r = k + 2; r < n; ++r) xj[r] -= v[r] * s;
+  // back-transform each vector: H_0 H_1 ... H_{n-3} x (last reflector first),
+  // four vectors at a time: each reflector is read once per four, and the
+  // four dot products are independent chains (every vector still sees the
+  // same operations in the same order)
+  auto apply4 = [&](double* x0, double* x1, double* x2, double* x3) {
+    for (int k = n - 3; k >= 0; --k) {
+      const double beta = betas[k];
+      if (beta == 0.0) continue;
+      const double* v = &H[(size_t)k * n];  // v[k+1] = 1, v[k+2..] stored
+      double s0 = x0[k + 1], s1 = x1[k + 1], s2 = x2[k + 1], s3 = x3[k + 1];
+      for (int r = k + 2; r < n; ++r) {
+        const double vr = v[r];
+        s0 += vr * x0[r];
+        s1 += vr * x1[r];
+        s2 += vr * x2[r];
+        s3 += vr * x3[r];
       }
+      s0 *= beta; s1 *= beta; s2 *= beta; s3 *= beta;
+      x0[k + 1] -= s0; x1[k + 1] -= s1; x2[k + 1] -= s2; x3[k + 1] -= s3;
+      for (int r = k + 2; r < n; ++r) {
+        const double vr = v[r];
+        x0[r] -= vr * s0;
+        x1[r] -= vr * s1;
+        x2[r] -= vr * s2;
+        x3[r] -= vr * s3;
+      }
+    }
+  };
+  std::vector<double> spare((size_t)3 * n, 0.0);  // stand-ins for a short last group
+  parallel_rows((m + 3) / 4, 1, [&](int g0, int g1) {
+    for (int g = g0; g < g1; ++g) {
+      double* xs[4];
+      for (int b = 0; b < 4; ++b) xs[b] = 4 * g + b < m ? &Xc[(size_t)(4 * g + b) * n] : &spare[(size_t)(b - 1) * n];
+      apply4(xs[0], xs[1], xs[2], xs[3]);
     }
   });
   std::vector<double> X((size_t)n * m);

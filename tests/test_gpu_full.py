@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 from paper_2606_05581_amd import workloads as W
-from parity_util import parity_report
+from parity_util import check_log_reconstruction, parity_report
 
 pytestmark = pytest.mark.gpu
 
@@ -141,6 +141,12 @@ def test_sh_sphere_2m_full_and_modes(ctx, oracle_mod):
     viol, div = parity_report(g, o, label, case)
     assert viol.sum() == 0
     assert div < 0.01
+    import dataclasses
+
+    rs = case.rows
+    sub = dataclasses.replace(case, rows=dataclasses.replace(rs, w=rs.w[sel], p=rs.p[sel], n=rs.n[sel],
+                                                             tri=rs.tri[sel], bary=rs.bary[sel]))
+    check_log_reconstruction(oracle_mod, sub, g, o, False, label)
     qg, qo = d.get(msk.FIELD_ROW_QUERIES)[sel].sum(), o["n_query"].sum()
     assert abs(qg - qo) <= 0.01 * qo  # walks agree up to rare FP32 / FP64 path splits
     assert esc.sum() == 0 and cap.sum() == 0
@@ -238,6 +244,12 @@ def test_exterior200_full_adaptive_and_modes(ctx, oracle_mod):
     # scene), so FP32 positions drift from the oracle's FP64 ones for more
     # steps before a near-tie decision can flip: measured 3.1%
     assert div0 < 0.05
+    import dataclasses
+
+    rs = case.rows
+    sub = dataclasses.replace(case, rows=dataclasses.replace(rs, w=rs.w[sel], p=rs.p[sel], n=rs.n[sel],
+                                                             tri=rs.tri[sel], bary=rs.bary[sel]))
+    check_log_reconstruction(oracle_mod, sub, g0, o0, True, f"{label}, first {wl.walks} walks")
     d0.close()
     # eigen step: 128 smallest modes; reference eigenvalues from the FP64
     # symmetric eigensolver that torch calls on the same matrix
@@ -322,6 +334,13 @@ def test_batch64_mixed_full(ctx, oracle_mod):
         viol, div = parity_report(g, o, f"batch64_mixed member {i}", c)
         assert viol.sum() == 0
         divs.append(div)
+        # each side's S on the logged rows is its own walk log summed
+        import dataclasses
+
+        rs = c.rows
+        sub = dataclasses.replace(c, rows=dataclasses.replace(rs, w=rs.w[sel], p=rs.p[sel], n=rs.n[sel],
+                                                              tri=rs.tri[sel], bary=rs.bary[sel]))
+        check_log_reconstruction(oracle_mod, sub, g, o, False, f"batch64_mixed member {i}")
         one.close()
     print(f"[batch64_mixed full] divergent walks over the 16 logged rows: mean {np.mean(divs):.4%}, "
           f"max {np.max(divs):.4%}", flush=True)

@@ -71,6 +71,67 @@ def _run_both(ctx, oracle_mod, V, F, centre, rows, tab, pairs, kill, eps_rel, se
     return g, o, kv, ks
 
 
+def _kelvin_from_log(V, F, centre, rows, tab, status, tri, bary, radius, pairs, n_kill, cap_deg=2.5):
+    """Both terms rebuilt on the CPU from a walk log alone (rows x 2 pairs jump
+    walks, then the killing walks): t = the terminal point's image in its
+    triangle (barycentrics), |t~| = 1 / |t - centre|, s~ likewise.
+    Jump: alpha_i (g_1 d_1 d_1^T + g_2 d_2 d_2^T) / 2 per pair with
+    alpha_i = w_i |s~_i|^3 Z_i / (2 pairs), Z_i = (1 / (2 r_i)) (1 / sin(theta0/2) - 1),
+    g = 1 / |t~|, d = b(s) - b(t). Killing: (4 pi / N0) g b(t) b(t)^T per walk."""
+    tab = np.asarray(tab, dtype=np.float64)
+    F = np.asarray(F, dtype=np.int64)
+    Vc = V.astype(np.float32).astype(np.float64) - centre
+    n = rows.n_rows
+    W2 = 2 * pairs
+    u0 = math.sin(0.5 * math.radians(cap_deg))
+    r = np.asarray(radius, dtype=np.float64)
+    s = rows.p.astype(np.float64) - centre
+    s3 = 1.0 / np.linalg.norm(s, axis=1) ** 3
+    alpha = np.where(r > 0, rows.w * s3 * (1.0 / (2.0 * np.where(r > 0, r, 1.0))) * (1.0 / u0 - 1.0) / (2.0 * pairs),
+                     0.0)
+
+    def terminal(st, tr, ba):
+        l1, l2 = ba[..., 0].astype(np.float64), ba[..., 1].astype(np.float64)
+        lam = np.stack([1.0 - l1 - l2, l1, l2], -1)
+        ok = (st == 0) | (st == 2)
+        t = np.where(ok, tr, 0).astype(np.int64)
+        bt = np.einsum("...c,...ck->...k", lam, tab[F[t]]) * ok[..., None]
+        pt = np.einsum("...c,...ck->...k", lam, Vc[F[t]])
+        g = np.where(ok, np.linalg.norm(pt, axis=-1), 0.0)  # 1 / |t~| = |t|
+        return bt, g
+
+    bs = np.einsum("rc,rck->rk", rows.bary.astype(np.float64), tab[F[rows.tri]])
+    bt, g = terminal(status[: n * W2].reshape(n, W2), tri[: n * W2].reshape(n, W2),
+                     bary[: n * W2].reshape(n, W2, 2))
+    D = (bs[:, None, :] - bt).reshape(n * W2, -1)
+    a = np.repeat(alpha, W2) * g.reshape(-1) * 0.5
+    Sj = D.T @ (a[:, None] * D)
+    Sk = None
+    if n_kill > 0 and len(status) > n * W2:
+        btk, gk = terminal(status[n * W2:], tri[n * W2:], bary[n * W2:])
+        Sk = btk.T @ ((4.0 * math.pi / n_kill) * gk[:, None] * btk)
+    return Sj, Sk
+
+
+def _check_log_sum(V, F, centre, rows, tab, g, o, pairs, n_kill, label):
+    """Each side's terms equal its own walk log summed on the CPU (the GPU's
+    jump and killing terms; the oracle's jump term, whose log holds the jump
+    walks only). The GPU's weights g come from its FP64 nearest point, the
+    rebuilt ones from the logged FP32 barycentrics: the bar is 1e-6 of the
+    largest entry."""
+    Sj_g, Sk_g = _kelvin_from_log(V, F, centre, rows, tab, g["status"], g["tri"], g["bary"], g["radius"], pairs,
+                                  n_kill)
+    nw = rows.n_rows * 2 * pairs
+    Sj_o, _ = _kelvin_from_log(V, F, centre, rows, tab, o["log_status"].reshape(-1), o["log_tri"].reshape(-1),
+                               o["log_bary"].reshape(nw, 2), o["radius"], pairs, 0)
+    dj = np.abs(g["S_jump"] - Sj_g).max() / np.abs(g["S_jump"]).max()
+    do = np.abs(o["S_jump"] - Sj_o).max() / np.abs(o["S_jump"]).max()
+    dk = np.abs(g["S_kill"] - Sk_g).max() / np.abs(g["S_kill"]).max() if Sk_g is not None else 0.0
+    print(f"[kelvin parity] {label}: terms rebuilt from the walk log: GPU jump within {dj:.2e}, killing within "
+          f"{dk:.2e}; oracle jump within {do:.2e} of the largest entry", flush=True)
+    assert dj <= 1e-6 and dk <= 1e-6 and do <= 1e-6
+
+
 def _check(g, o, r_max, label):
     step = r_max / 2 ** 10
     same_r = np.abs(g["radius"] - o["radius"]) <= 2 * step
@@ -135,15 +196,19 @@ def test_kelvin_closest_points_match_the_oracle(ctx, oracle_mod):
 def test_kelvin_parity_unit_sphere(ctx, oracle_mod):
     V, F, tab = _sphere(3)
     rows = W.point_rows(V, F, 300, np.random.default_rng(21))
-    g, o, kv, ks = _run_both(ctx, oracle_mod, V, F, np.array([0.2, -0.1, 0.05]), rows, tab, 32, 20000, 1e-5, seed=5)
+    c = np.array([0.2, -0.1, 0.05])
+    g, o, kv, ks = _run_both(ctx, oracle_mod, V, F, c, rows, tab, 32, 20000, 1e-5, seed=5)
     _check(g, o, ks.r_max(), "unit sphere, centre (0.2, -0.1, 0.05)")
+    _check_log_sum(V, F, c, rows, np.asarray(tab, np.float32), g, o, 32, 20000, "unit sphere")
 
 
 def test_kelvin_parity_two_bodies(ctx, oracle_mod):
     V, F, tab = _two_bodies()
     rows = W.point_rows(V, F, 400, np.random.default_rng(23))
-    g, o, kv, ks = _run_both(ctx, oracle_mod, V, F, np.array([0.1, 0.2, -0.1]), rows, tab, 16, 20000, 1e-5, seed=9)
+    c = np.array([0.1, 0.2, -0.1])
+    g, o, kv, ks = _run_both(ctx, oracle_mod, V, F, c, rows, tab, 16, 20000, 1e-5, seed=9)
     _check(g, o, ks.r_max(), "sphere and ellipsoid, K=10")
+    _check_log_sum(V, F, c, rows, np.asarray(tab, np.float32), g, o, 16, 20000, "sphere and ellipsoid")
 
 
 @pytest.fixture(scope="module")

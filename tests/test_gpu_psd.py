@@ -59,6 +59,43 @@ def _run_both(ctx, oracle_mod, V, F, rows, tab, pairs, eps, seed, **kw):
     return g, o
 
 
+def _psd_from_log(rows, F, tab, status, tri, bary, radius, pairs, cap_deg=2.5):
+    """Alg. 2's S rebuilt on the CPU from a walk log alone: per row i with a
+    tangent ball of radius r_i, alpha_i = w_i Z_i / (2 pairs) with
+    Z_i = (1 / (2 r_i)) (1 / sin(theta0 / 2) - 1), and per pair
+    alpha_i (d_1 d_1^T + d_2 d_2^T) / 2, d = b(s) - b(t) (b(t) = 0 for a walk
+    that escaped); the sum as one product D^T diag(alpha / 2) D."""
+    tab = np.asarray(tab, dtype=np.float64)
+    F = np.asarray(F, dtype=np.int64)
+    n, W2 = status.shape
+    r = np.asarray(radius, dtype=np.float64)
+    u0 = math.sin(0.5 * math.radians(cap_deg))
+    alpha = np.where(r > 0, rows.w * (1.0 / (2.0 * np.where(r > 0, r, 1.0))) * (1.0 / u0 - 1.0) / (2.0 * pairs), 0.0)
+    bs = np.einsum("rc,rck->rk", rows.bary.astype(np.float64), tab[F[rows.tri]])
+    l1, l2 = bary[..., 0].astype(np.float64), bary[..., 1].astype(np.float64)
+    lam = np.stack([1.0 - l1 - l2, l1, l2], -1)
+    ended = (status == 0) | (status == 2)
+    t = np.where(ended, tri, 0).astype(np.int64)
+    bt = np.einsum("rwc,rwck->rwk", lam, tab[F[t]]) * ended[..., None]
+    D = (bs[:, None, :] - bt).reshape(n * W2, -1)
+    a = np.repeat(np.where((status >= 0).any(1), alpha, 0.0), W2) * 0.5
+    return D.T @ (a[:, None] * D)
+
+
+def _check_log_sum(rows, F, tab, g, o, pairs, label):
+    """Each side's S equals its own walk log summed on the CPU: the GPU's
+    gathers, matrix-core products and reduction to FP64 rounding (1e-12 of
+    the largest entry), the oracle's to the FP32 rounding of its logged
+    barycentrics (1e-7)."""
+    scale = np.abs(o["S"]).max()
+    Sg = _psd_from_log(rows, F, tab, g["status"], g["tri"], g["bary"], g["radius"], pairs)
+    So = _psd_from_log(rows, F, tab, o["log_status"], o["log_tri"], o["log_bary"], o["radius"], pairs)
+    dg, do = np.abs(g["S"] - Sg).max() / scale, np.abs(o["S"] - So).max() / scale
+    print(f"[psd parity] {label}: S rebuilt from the walk log: GPU within {dg:.2e}, oracle within {do:.2e} of the "
+          f"largest entry", flush=True)
+    assert dg <= 1e-12 and do <= 1e-7
+
+
 def _check_parity(g, o, r_max, label):
     step = r_max / 2 ** 10
     same_r = np.abs(g["radius"].astype(np.float64) - o["radius"]) <= 2 * step
@@ -88,6 +125,7 @@ def test_psd_soup_parity(ctx, oracle_mod):
                     P[:, 2] ** 2 - P[:, 0] ** 2, np.sin(3 * P[:, 0]), np.cos(2 * P[:, 1] + P[:, 2])], 1)
     g, o = _run_both(ctx, oracle_mod, case.V, case.F, case.rows, tab, 32, case.eps, seed=7)
     _check_parity(g, o, oracle_mod.psd_r_max(case.V), "soup8 K=9")
+    _check_log_sum(case.rows, case.F, tab.astype(np.float32), g, o, 32, "soup8 K=9")
     assert g["info"]["escaped_total"] == 0
 
 
@@ -258,6 +296,7 @@ def test_psd_sh_sphere_2m_row_subset_parity_and_full_size(ctx, oracle_mod):
     print(f"[psd full] oracle on the subset: {time.time() - t:.1f} s", flush=True)
     assert g["info"]["fused"] == 1
     _check_parity(g, o, oracle_mod.psd_r_max(case.V), "psd_sh_sphere_2m 160-row subset, K=128")
+    _check_log_sum(sub, case.F, tab.astype(np.float32), g, o, pairs, "psd_sh_sphere_2m 160-row subset, K=128")
     rfull = ctx.rows(mesh, r)
     f = ctx.estimate_psd(mesh, rfull, bh, pairs, case.eps, seed=0)
     S, se = f["S"], f["se"]

@@ -183,6 +183,9 @@ def psd_leg(ctx):
     log(f"[bench] psd workload: {case.F.shape[0]} triangles, {case.rows.n_rows} rows x {pairs} pairs, "
         f"K={case.basis.K} (inputs ready in {time.perf_counter() - t:.1f} s)")
     ctx.estimate_psd(mesh, rh, bh, 4, case.eps)  # untimed warm-up
+    # untimed: the same walks through the counting kernel, for the walk
+    # kernel's algorithmic work (box nodes, triangle tests, FP32 operations)
+    st = ctx.estimate_psd(mesh, rh, bh, pairs, case.eps, collect_stats=1)["info"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = ctx.estimate_psd(mesh, rh, bh, pairs, case.eps)
@@ -199,6 +202,8 @@ def psd_leg(ctx):
     # (the table holds the FP32 basis values: 4 bytes per entry; update rows are FP64)
     gbytes = n_pairs * (6.0 * K * 4 + (0.0 if fused else 10.0 * K * 8) + 2 * 16) + n * 3.0 * K * 4
     prod_tf = flops / (info["product_ms"] * 1e-3) / 1e12
+    walk_tf = st["valu_flops"] / (info["walk_kernel_ms"] * 1e-3) / 1e12
+    walk_q = max(st["walks_total"], 1)
     gath_ms = info["product_ms"] if fused else info["gather_ms"]
     gath = gbytes / (gath_ms * 1e-3) / 1e9
     log(f"[bench] psd: {info['walks_total'] / el:.3e} walks/s; tangent balls {info['tangent_ms']:.1f} ms, walks "
@@ -215,6 +220,13 @@ def psd_leg(ctx):
                         "frac": prod_tf / FP64_MATRIX_PEAK_TFLOPS, "dtype": "f64"},
             "gather": {"bound": "hbm", "achieved": gath, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": gath / HBM_PEAK_GBS, "kernel": "psd_fused_kernel" if fused else "psd_gather_kernel"},
+            # the leg's dominant kernel: the ball-start walks, bound like the
+            # main walk kernel by VALU issue; its algorithmic FP32 work from
+            # the counting pass over the same walks
+            "walk": {"bound": "alu", "achieved": walk_tf, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": walk_tf / FP32_VECTOR_PEAK_TFLOPS, "kernel": "walk_stream_kernel",
+                     "per_walk": {"nodes": st["nodes_visited"] / walk_q, "triangles": st["tris_tested"] / walk_q,
+                                  "fp32_ops": st["valu_flops"] / walk_q}},
         },
     }
 

@@ -545,6 +545,10 @@ typedef struct {
   double total_ms;
   int64_t nonfinite_entries;
   int32_t fused;           /* 1: K <= 384, gathers and products in one kernel  */
+  /* the walk launch's traversal work, counted when walk_opts->collect_stats
+   * (a separately compiled counting kernel): box-node visits, triangle tests
+   * and algorithmic FP32 operations; 0 otherwise                            */
+  int64_t nodes_visited, tris_tested, valu_flops;
 } msk_psd_info;
 
 typedef struct {  /* optional host walk log, n_rows x 2 pairs entries each    */
@@ -586,8 +590,9 @@ typedef struct {  /* optional host walk log, n_rows x 2 pairs entries each    */
  * finite-difference estimator's inset (the paper runs at 1e-6; here eps
  * must exceed msk_eps_floor, 2^-18 R by default).
  * walk_opts: seed, max_steps, kappa, delta_rel, form, launch settings and
- * mesh_id as for msk_estimate_dtn (walk_offset, se_target, record_log and
- * collect_stats are ignored). Errors: INVALID_ARG for hat rows, pairs < 1,
+ * mesh_id as for msk_estimate_dtn (walk_offset, se_target and record_log
+ * are ignored; collect_stats runs the counting kernel and fills the info's
+ * traversal counts). Errors: INVALID_ARG for hat rows, pairs < 1,
  * K > 8192, eps <= msk_eps_floor(R, walk_opts), a basis for another vertex count or a flat mesh;
  * NUMERIC (outputs written) when an entry is not finite. */
 msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* mesh, const msk_rows* rows, const msk_basis* basis,

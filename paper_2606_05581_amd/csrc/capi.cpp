@@ -1441,8 +1441,7 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   if (o.mesh_id < 0 || o.mesh_id > 0xFFFFFF) return fail(ctx, MSK_ERR_INVALID_ARG, "mesh_id must be < 2^24");
   o.se_target = 0;
   o.walk_offset = 0;
-  o.record_log = 1;
-  o.collect_stats = 0;
+  o.record_log = 1;  // collect_stats is the caller's (the counting kernel; reported in the info)
   const int64_t W = 2 * pairs;
   // the walk problem: interior walks; the inset is not used by ball starts
   if (walk_opts && walk_opts->jump_only) return fail(ctx, MSK_ERR_INVALID_ARG, "jump_only applies to exterior estimates");
@@ -1642,6 +1641,9 @@ extern "C" msk_status msk_estimate_psd(msk_ctx* ctx, const msk_mesh* m, const ms
   I.total_ms = tot;
   I.nonfinite_entries = d->info.nonfinite_entries;
   I.fused = fused ? 1 : 0;
+  I.nodes_visited = stats[0];
+  I.tris_tested = stats[1];
+  I.valu_flops = stats[2];
   if (info) *info = I;
 #undef HIP_P
   const bool bad = I.nonfinite_entries > 0;

@@ -102,7 +102,8 @@ class PsdInfo(C.Structure):
                 ("dropped_rows", C.c_int64), ("mean_radius", C.c_double), ("r_max", C.c_double),
                 ("tangent_ms", C.c_double), ("walk_kernel_ms", C.c_double), ("gather_ms", C.c_double),
                 ("product_ms", C.c_double), ("total_ms", C.c_double), ("nonfinite_entries", C.c_int64),
-                ("fused", C.c_int32)]
+                ("fused", C.c_int32), ("nodes_visited", C.c_int64), ("tris_tested", C.c_int64),
+                ("valu_flops", C.c_int64)]
 
 
 class PsdLog(C.Structure):

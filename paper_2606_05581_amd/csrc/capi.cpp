@@ -810,6 +810,18 @@ static msk_status collect_info(msk_ctx* ctx, msk_dtn* d) {
   return MSK_OK;
 }
 
+// The same summary from totals summed on the device (launch_row_totals).
+static void info_from_totals(msk_dtn* d, const unsigned long long t[6]) {
+  d->info.n_rows = d->n;
+  d->info.K = d->K;
+  d->info.queries_total = (int64_t)t[0];
+  d->info.escaped_total = (int64_t)t[1];
+  d->info.capped_total = (int64_t)t[2];
+  d->info.discarded_rows = (int64_t)t[3];
+  d->info.walks_total = (int64_t)t[4];
+  d->info.nonfinite_entries = (int64_t)t[5];
+}
+
 extern "C" msk_status msk_estimate_dtn(msk_ctx* ctx, const msk_mesh* m, const msk_rows* r, const msk_basis* b,
                                        int64_t walks, double eps, double inset_h, int32_t side,
                                        const msk_dtn_opts* opts, msk_dtn** out) {
@@ -1080,6 +1092,13 @@ struct msk_batch {
   std::vector<MeshDev> md;
   std::vector<const msk_rows*> rows;
   LaunchBuffers lb;
+  // the discard pass over every mesh's point rows in one launch
+  RowRange* d_ranges = nullptr;
+  int32_t n_ranges = 0;
+  int64_t n_point_rows = 0;
+  // per-estimate totals of the row counters, summed on the device
+  RowCounters* d_counters = nullptr;
+  unsigned long long* d_totals = nullptr;
   // three captured graphs replayed back to back: prepare (zeroing, discard
   // pass, queues), the one persistent walk launch, finalisation
   hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
@@ -1093,6 +1112,9 @@ struct msk_batch {
     }
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
+    dfree(d_ranges);
+    dfree(d_counters);
+    dfree(d_totals);
     for (msk_dtn* d : dtns)
       if (d) {
         dtn_free(d);
@@ -1115,8 +1137,9 @@ static hipError_t enqueue_batch(msk_batch* B, hipStream_t s, int part) {
       if ((e = launch_fill_u64(d->d_cap, d->n, 0, s)) != hipSuccess) return e;
       if ((e = launch_fill_u64(d->d_walks, d->n, (unsigned long long)B->W, s)) != hipSuccess) return e;
       if ((e = launch_fill_u32(d->d_disc, d->n, 0u, s)) != hipSuccess) return e;
-      if (B->md[i].mode == kRowsPoint && (e = launch_discard(B->md[i], d->n, d->d_disc, s)) != hipSuccess) return e;
     }
+    if ((e = launch_discard_batch(B->lb.d_meshes, B->d_ranges, B->n_ranges, B->n_point_rows, s)) != hipSuccess)
+      return e;
     int64_t n_slots = 0;
     for (msk_dtn* d : B->dtns) n_slots += d->n;
     if ((e = launch_init_queues(B->lb.d_qnext, B->lb.d_qend, make_queues(n_slots, B->W), s)) != hipSuccess)
@@ -1154,7 +1177,7 @@ static hipError_t enqueue_batch(msk_batch* B, hipStream_t s, int part) {
         (e = launch_count_nonfinite(d->d_se, nk, d->d_nonfinite, s)) != hipSuccess)
       return e;
   }
-  return hipSuccess;
+  return launch_row_totals(B->d_counters, B->n, B->d_totals, s);
 }
 
 extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk_mesh* const* meshes,
@@ -1208,9 +1231,23 @@ extern "C" msk_status msk_batch_create(msk_ctx* ctx, int32_t n_meshes, const msk
   std::vector<RowSlot> slots;
   for (int32_t i : mo)
     for (int32_t r : rows[i]->order) slots.push_back(RowSlot{i, r, 0u});
+  std::vector<RowRange> ranges;
+  std::vector<RowCounters> counters;
+  for (int32_t i = 0; i < n_meshes; ++i) {
+    msk_dtn* d = B->dtns[i];
+    if (B->md[i].mode == kRowsPoint && d->n > 0) {
+      ranges.push_back(RowRange{B->n_point_rows, i, d->d_disc});
+      B->n_point_rows += d->n;
+    }
+    counters.push_back(RowCounters{d->d_q, d->d_esc, d->d_cap, d->d_disc, d->d_walks, d->d_nonfinite, d->n});
+  }
+  B->n_ranges = (int32_t)ranges.size();
   hipError_t he;
   if ((he = upload(ctx, &B->lb.d_meshes, B->md.data(), B->md.size())) != hipSuccess ||
       (he = upload(ctx, &B->lb.d_slots, slots.data(), slots.size())) != hipSuccess ||
+      (he = upload(ctx, &B->d_ranges, ranges.data(), ranges.size())) != hipSuccess ||
+      (he = upload(ctx, &B->d_counters, counters.data(), counters.size())) != hipSuccess ||
+      (he = dalloc(&B->d_totals, 6 * (size_t)n_meshes)) != hipSuccess ||
       (he = dalloc(&B->lb.d_qnext, 8)) != hipSuccess || (he = dalloc(&B->lb.d_qend, 8)) != hipSuccess ||
       (he = dalloc(&B->lb.d_stats, 3)) != hipSuccess) {
     delete B;
@@ -1262,11 +1299,12 @@ extern "C" msk_status msk_batch_run(msk_batch* B) {
   float tot = 0, wk = 0;
   HIP_TRY(ctx, hipEventElapsedTime(&tot, B->ev[0], B->ev[3]));
   HIP_TRY(ctx, hipEventElapsedTime(&wk, B->ev[1], B->ev[2]));
+  std::vector<unsigned long long> tot6(6 * (size_t)B->n);
+  HIP_TRY(ctx, hipMemcpy(tot6.data(), B->d_totals, tot6.size() * 8, hipMemcpyDeviceToHost));
   msk_dtn_info T{};
   for (int32_t i = 0; i < B->n; ++i) {
     msk_dtn* d = B->dtns[i];
-    msk_status st = collect_info(ctx, d);
-    if (st != MSK_OK) return st;
+    info_from_totals(d, &tot6[6 * (size_t)i]);
     d->info.walk_kernel_ms = wk;  // one shared launch
     d->info.total_ms = tot;
     d->info.walk_launches = 1;

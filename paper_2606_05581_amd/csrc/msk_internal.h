@@ -157,6 +157,24 @@ struct WalkLaunch {
   int32_t knn;                 // some mesh uses the point basis: launch the k-NN instantiations
 };
 
+// One mesh's point rows in a discard pass over the rows of several meshes.
+struct RowRange {
+  int64_t first;         // launch index of the mesh's row 0 (ascending over the ranges)
+  int32_t mesh;          // index into the launch's MeshDev array
+  int32_t* discarded;    // the mesh's discard flags (written)
+};
+
+// The per-row counters of one estimate, summed by launch_row_totals.
+struct RowCounters {
+  const unsigned long long* queries;
+  const unsigned long long* escaped;
+  const unsigned long long* capped;
+  const int32_t* discarded;
+  const int64_t* walks;
+  const unsigned long long* nonfinite;  // one count
+  int64_t n;
+};
+
 }  // namespace msk
 
 namespace msk {
@@ -173,6 +191,10 @@ hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_tangent_ball(const MeshDev& M, int64_t n_rows, float r_max, int32_t iters, float tol, float* radius,
                                hipStream_t s);
 hipError_t launch_discard(const MeshDev& M, int64_t n_rows, int32_t* discarded, hipStream_t s);
+hipError_t launch_discard_batch(const MeshDev* meshes, const RowRange* ranges, int32_t n_ranges, int64_t n_total,
+                                hipStream_t s);
+// out: 6 x n_sets counts (queries, escaped, capped, discarded rows, walks of kept rows, non-finite entries)
+hipError_t launch_row_totals(const RowCounters* sets, int32_t n_sets, unsigned long long* out, hipStream_t s);
 hipError_t launch_knn_eval(const KnnDev& G, const double* c, const float* Q, const float* Nq, int64_t n, int32_t* idx,
                            float* w, hipStream_t s);
 hipError_t launch_closest_points(const Node4* nodes, const TriRec* tris, float radius, const double* c, const float* Q,

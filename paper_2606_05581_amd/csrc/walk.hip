@@ -1474,9 +1474,7 @@ __global__ void __launch_bounds__(64) tangent_ball_kernel(MeshDev M, int64_t n_r
   }
 }
 
-__global__ void discard_kernel(MeshDev M, int64_t n_rows, int32_t* discarded) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_rows) return;
+__device__ __forceinline__ void discard_row(const MeshDev& M, int64_t i, int32_t* discarded) {
   const float sgn = M.side ? 1.0f : -1.0f;
   const float x = M.p[3 * i] + sgn * M.inset * M.n[3 * i];
   const float y = M.p[3 * i + 1] + sgn * M.inset * M.n[3 * i + 1];
@@ -1487,6 +1485,30 @@ __global__ void discard_kernel(MeshDev M, int64_t n_rows, int32_t* discarded) {
   bvh_nearest<false>(M.nodes, M.tris, nullptr, 0, x, y, z, M.radius, h, cnt);
   discarded[i] = h.d2 < 0.25f * M.inset * M.inset ? 1 : 0;
   atomicAdd(M.row_queries + i, 1ull);
+}
+
+__global__ void discard_kernel(MeshDev M, int64_t n_rows, int32_t* discarded) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_rows) discard_row(M, i, discarded);
+}
+
+// The discard pass over the point rows of several meshes in one launch:
+// launch index j belongs to the last range k with R[k].first <= j, as row
+// j - R[k].first of mesh R[k].mesh.
+__global__ void discard_batch_kernel(const MeshDev* __restrict__ meshes, const RowRange* __restrict__ R,
+                                     int32_t n_ranges, int64_t n_total) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_total) return;
+  int32_t lo = 0, hi = n_ranges - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (R[mid].first <= j)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const RowRange r = R[lo];
+  discard_row(meshes[r.mesh], j - r.first, r.discarded);
 }
 
 __global__ void knn_eval_kernel(KnnDev G, double cx, double cy, double cz, const float* __restrict__ Q,
@@ -1657,6 +1679,33 @@ __global__ void count_nonfinite_kernel(const double* __restrict__ a, int64_t n, 
   if (__lane_id() == 0 && c) atomicAdd(count, c);
 }
 
+// Per-estimate totals of the per-row counters, one workgroup per estimate:
+// out[6 k + 0..5] = queries, escaped walks, capped walks, discarded rows,
+// walks of the kept rows, non-finite entries.
+__global__ void row_totals_kernel(const RowCounters* __restrict__ sets, unsigned long long* __restrict__ out) {
+  const RowCounters C = sets[blockIdx.x];
+  __shared__ unsigned long long acc[5];
+  if (threadIdx.x < 5) acc[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned long long v[5] = {0, 0, 0, 0, 0};
+  for (int64_t i = threadIdx.x; i < C.n; i += blockDim.x) {
+    v[0] += C.queries[i];
+    v[1] += C.escaped[i];
+    v[2] += C.capped[i];
+    const bool dropped = C.discarded[i] != 0;
+    v[3] += dropped ? 1ull : 0ull;
+    v[4] += dropped ? 0ull : (unsigned long long)C.walks[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if (__lane_id() == 0 && v[k]) atomicAdd(&acc[k], v[k]);
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) out[6 * blockIdx.x + threadIdx.x] = acc[threadIdx.x];
+  if (threadIdx.x == 5) out[6 * blockIdx.x + 5] = *C.nonfinite;
+}
+
 hipError_t launch_count_nonfinite(const double* a, int64_t n, unsigned long long* count, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
@@ -1684,6 +1733,20 @@ hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s) {
 hipError_t launch_discard(const MeshDev& M, int64_t n_rows, int32_t* discarded, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(discard_kernel, dim3(blocks_for(n_rows, 128)), dim3(128), 0, s, M, n_rows, discarded);
+  return hipGetLastError();
+}
+
+hipError_t launch_discard_batch(const MeshDev* meshes, const RowRange* ranges, int32_t n_ranges, int64_t n_total,
+                                hipStream_t s) {
+  if (n_ranges <= 0 || n_total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(discard_batch_kernel, dim3(blocks_for(n_total, 128)), dim3(128), 0, s, meshes, ranges, n_ranges,
+                     n_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_totals(const RowCounters* sets, int32_t n_sets, unsigned long long* out, hipStream_t s) {
+  if (n_sets <= 0) return hipSuccess;
+  hipLaunchKernelGGL(row_totals_kernel, dim3(n_sets), dim3(256), 0, s, sets, out);
   return hipGetLastError();
 }
 

@@ -354,7 +354,7 @@ def laplace_leg(ctx, K=160, sample_n=48):
         "bound": info["bound"], "max_residual": info["max_residual"], "lambda_K": float(lam[-1]),
         "ms": {k: info[k] for k in ("setup_ms", "assemble_ms", "filter_ms", "dense_ms", "total_ms")},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "kernel": "cheb_step_kernel",
+                     "frac": gbs / HBM_PEAK_GBS, "kernel": "cheb_gather_kernel",
                      "filter_bytes": info["filter_bytes"], "traffic": laplace_traffic(),
                      "locked_at_end": info["locked"]},
         "sample": {"vertices": int(Vs.shape[0]), "faces": int(Fs.shape[0]), "gpu_s": gpu_sample_s,

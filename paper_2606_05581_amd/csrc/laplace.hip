@@ -48,6 +48,12 @@ constexpr double kDegenerateRel = 1e-12;
 constexpr double kAdaptiveGain = 1e3;
 // rows a wavefront of the filter step carries at once
 constexpr int kFilterRows = 1;
+// the step reads each row's neighbour list at once, kFilterBatch entries
+// per round (0: the four-entry batches of cheb_step_kernel)
+#ifndef MSK_FILTER_BATCH
+#define MSK_FILTER_BATCH 8
+#endif
+constexpr int kFilterBatch = MSK_FILTER_BATCH;
 
 __device__ __forceinline__ int32_t find_col(const int32_t* __restrict__ col, int32_t lo, int32_t hi, int32_t key) {
   while (lo < hi) {
@@ -187,6 +193,31 @@ __device__ __forceinline__ void load_lane_row(const double* __restrict__ row, in
   if constexpr (C % 2 == 1) v[C - 1] = row[128 * (C / 2) + lane];
 }
 
+// Non-temporal forms of the same layout: whole 16-byte pairs per lane, so
+// each instruction reads or writes 1 KB of the row in full cache lines.
+typedef double lap_d2 __attribute__((ext_vector_type(2)));
+
+template <int C>
+__device__ __forceinline__ void load_lane_row_nt(const double* __restrict__ row, int lane, double v[C]) {
+#pragma unroll
+  for (int s = 0; s < C / 2; ++s) {
+    const lap_d2 q = __builtin_nontemporal_load(reinterpret_cast<const lap_d2*>(row + 128 * s + 2 * lane));
+    v[2 * s] = q.x;
+    v[2 * s + 1] = q.y;
+  }
+  if constexpr (C % 2 == 1) v[C - 1] = __builtin_nontemporal_load(row + 128 * (C / 2) + lane);
+}
+
+template <int C>
+__device__ __forceinline__ void store_lane_row_nt(double* __restrict__ row, int lane, const double v[C]) {
+#pragma unroll
+  for (int s = 0; s < C / 2; ++s) {
+    const lap_d2 q = {v[2 * s], v[2 * s + 1]};
+    __builtin_nontemporal_store(q, reinterpret_cast<lap_d2*>(row + 128 * s + 2 * lane));
+  }
+  if constexpr (C % 2 == 1) __builtin_nontemporal_store(v[C - 1], row + 128 * (C / 2) + lane);
+}
+
 template <int C, int R>
 __global__ void __launch_bounds__(256) cheb_step_kernel(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col,
@@ -261,6 +292,64 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(const int32_t* __restric
         for (int t = 0; t < C; ++t) __builtin_nontemporal_store(alpha * (acc[r][t] - shift * yv[t]), zi + lane_col<C>(t, lane));
       }
     }
+  }
+}
+
+// The same step with the neighbour list of a row read at once: the
+// wavefront's lanes k < U load entries p + k of the list, and the gathers of
+// all U entries are issued together (lanes take each entry's column index
+// and value from lane k), so a row costs three dependent memory round trips
+// (row pointers, list, gathered rows) instead of two per four entries. The
+// row's own block row and the row of X, which do not depend on the list, are
+// read before it. Products are still added in entry order.
+template <int C, int U>
+__global__ void __launch_bounds__(256) cheb_gather_kernel(const int32_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const double* __restrict__ val, int64_t nv,
+                                                          const double* __restrict__ Y, const double* __restrict__ X,
+                                                          double* __restrict__ Z, int64_t ld, double alpha,
+                                                          double shift, double beta) {
+  static_assert(U >= 1 && U <= 64, "a batch holds at most one entry per lane");
+  const int lane = threadIdx.x & 63;
+  const int64_t per_xcd = gridDim.x >> 3, xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+  const int64_t chunk = (nv + 7) >> 3;
+  const int64_t lo = xcd * chunk, hi = min(nv, lo + chunk);
+  for (int64_t i = lo + j * 4 + (threadIdx.x >> 6); i < hi; i += per_xcd * 4) {
+    const int32_t p0 = rowptr[i], p1 = rowptr[i + 1];
+    double yv[C], xv[C];
+    load_lane_row<C>(Y + i * ld, lane, yv);
+    if (beta != 0.0) load_lane_row_nt<C>(X + i * ld, lane, xv);
+    double acc[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) acc[t] = 0.0;
+    for (int32_t p = p0; p < p1; p += U) {
+      const int32_t q = p + lane;
+      const bool mine = lane < U && q < p1;
+      const int32_t cq = mine ? col[q] : 0;
+      const double aq = mine ? val[q] : 0.0;
+      double v[U][C];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t cu = __shfl(cq, u);
+        if (p + u < p1) {
+          load_lane_row<C>(Y + (int64_t)cu * ld, lane, v[u]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < C; ++t) v[u][t] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double au = __shfl(aq, u);
+#pragma unroll
+        for (int t = 0; t < C; ++t) acc[t] += au * v[u][t];
+      }
+    }
+    double zv[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t)
+      zv[t] = beta != 0.0 ? alpha * (acc[t] - shift * yv[t]) - beta * xv[t] : alpha * (acc[t] - shift * yv[t]);
+    store_lane_row_nt<C>(Z + i * ld, lane, zv);
   }
 }
 
@@ -393,14 +482,18 @@ hipError_t cheb_step(const LaplaceJob& J, const double* Y, const double* X, doub
   const int64_t chunk = (J.n + 7) / 8;
   // one group of 4 kFilterRows rows per workgroup: each XCD's workgroups are
   // dispatched in row order, so its rows are swept in order
-  const int64_t per = 4 * kFilterRows;
+  const int64_t per = 4 * (kFilterBatch > 0 ? 1 : kFilterRows);
   const int grid = 8 * (int)std::max<int64_t>(1, std::min<int64_t>((chunk + per - 1) / per, 1 << 27));
   const dim3 b(256);
   switch ((J.m - c0) / 64) {
 #define LAP_CASE(c)                                                                                            \
   case c:                                                                                                      \
-    hipLaunchKernelGGL((cheb_step_kernel<c, kFilterRows>), dim3(grid), b, 0, s, J.rowptr, J.col, J.val, J.n, Y, \
-                       X, Z, J.m, alpha, shift, beta);                                                         \
+    if constexpr (kFilterBatch > 0)                                                                            \
+      hipLaunchKernelGGL((cheb_gather_kernel<c, (kFilterBatch > 0 ? kFilterBatch : 1)>), dim3(grid), b, 0, s,  \
+                         J.rowptr, J.col, J.val, J.n, Y, X, Z, J.m, alpha, shift, beta);                       \
+    else                                                                                                       \
+      hipLaunchKernelGGL((cheb_step_kernel<c, kFilterRows>), dim3(grid), b, 0, s, J.rowptr, J.col, J.val, J.n, \
+                         Y, X, Z, J.m, alpha, shift, beta);                                                    \
     break;
     LAP_CASE(1) LAP_CASE(2) LAP_CASE(3) LAP_CASE(4) LAP_CASE(5) LAP_CASE(6) LAP_CASE(7) LAP_CASE(8)
 #undef LAP_CASE

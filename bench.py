@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 CLOCK_GHZ = 2.4                  # MI355X peak engine clock
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz
 FP64_MATRIX_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix-core peak
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_MATRIX_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix-core peak
 NODE_BYTES, TRI_BYTES = 128, 48
 DEFAULT_WORKLOAD = "batch64_mixed"
@@ -250,7 +251,10 @@ def kelvin_leg(ctx, pairs=64, kill_walks=1 << 20):
     warm-up call, then one timed call with inputs resident (inverted tangent
     balls, jump walks from ball points, killing walks from the origin,
     gathers and FP64 products). The build of the inverted hierarchy is timed
-    apart."""
+    apart. An untimed pass of the counting walk kernel (the same walks)
+    tallies the nearest searches' node visits, element tests and FP64
+    operations, for the walk kernel's arithmetic roofline against the FP64
+    vector peak and its bytes touched (128 B per node, 120 B per element)."""
     import torch
 
     wl = _psd_workload()
@@ -274,9 +278,23 @@ def kelvin_leg(ctx, pairs=64, kill_walks=1 << 20):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     info = r["info"]
-    q = info["queries_total"] + info["kill_queries"]
+    q = info["queries_total"]  # tangent-ball bisection steps, jump walks and killing walks
+    q_walk = q - int(info["n_rows"]) * 10  # less the bisection's 10 steps per row
     log(f"[bench] kelvin: {info['walks_total'] / el:.3e} walks/s, {q / el:.3e} queries/s; tangent balls "
         f"{info['tangent_ms']:.1f} ms, walks {info['walk_kernel_ms']:.1f} ms, products {info['product_ms']:.1f} ms")
+    cs = ctx.estimate_kelvin(kv, rh, bh, pairs, kill_walks, eps, collect_stats=1)["info"]  # untimed: counting kernel
+    wk_s = info["walk_kernel_ms"] * 1e-3
+    tf = cs["fp64_ops"] / wk_s / 1e12
+    gbs = (128 * cs["nodes_visited"] + 120 * cs["elements_tested"]) / wk_s / 1e9
+    roof = {"bound": "alu", "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "dtype": "f64", "kernel": "kelvin_walk_kernel",
+            "per_query": {"nodes": cs["nodes_visited"] / q_walk, "elements": cs["elements_tested"] / q_walk,
+                          "fp64_ops": cs["fp64_ops"] / q_walk},
+            "bytes_touched": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": gbs / HBM_PEAK_GBS}}
+    log(f"[bench] kelvin walk kernel: {tf:.3f} TFLOP/s FP64 ({roof['frac']:.4f} of peak); per query "
+        f"{roof['per_query']['nodes']:.1f} nodes, {roof['per_query']['elements']:.1f} elements, "
+        f"{roof['per_query']['fp64_ops']:.0f} FP64 ops")
     return {
         "workload": wl.name + " exterior (Kelvin-inverted)", "rows": int(info["n_rows"]), "pairs_per_row": pairs,
         "kill_walks": kill_walks, "K": int(info["K"]), "triangles": int(case.F.shape[0]),
@@ -284,8 +302,8 @@ def kelvin_leg(ctx, pairs=64, kill_walks=1 << 20):
         "inverted_build_s": build_s, "inverted_depth": int(ki["depth"]),
         "ms": {k: info[k] for k in ("tangent_ms", "walk_kernel_ms", "product_ms")},
         "mean_radius": info["mean_radius"], "dropped_rows": info["dropped_rows"],
-        "capped_total": info["capped_total"], "steps_per_walk": q / max(info["walks_total"], 1),
-        "S_trace": float(np.trace(r["S"])), "S_kill_trace": float(np.trace(r["S_kill"])),
+        "capped_total": info["capped_total"], "steps_per_walk": q_walk / max(info["walks_total"], 1),
+        "S_trace": float(np.trace(r["S"])), "S_kill_trace": float(np.trace(r["S_kill"])), "roofline": roof,
     }
 
 

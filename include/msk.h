@@ -650,10 +650,18 @@ typedef struct {  /* optional host walk log, n_rows x 2 pairs jump walks then ki
 
 typedef struct {
   int64_t n_rows, K, pairs, kill_walks;
+  /* queries_total: nearest-element queries of the tangent-ball bisection
+   * (bisect_iters per row), the jump walks and the killing walks;
+   * kill_queries: those of the killing walks (part of queries_total) */
   int64_t walks_total, queries_total, kill_queries, dropped_rows, capped_total;
   double mean_radius, r_max;  /* inverted units                              */
   double tangent_ms, walk_kernel_ms, product_ms;
   int64_t nonfinite_entries;
+  /* with walk_opts.collect_stats: the walks run in a counting build of the
+   * walk kernel (same walks, not the timed one) whose nearest searches tally
+   * their box-node visits, element tests and FP64 operations (additions,
+   * multiplications, divisions and square roots, one each); else 0 */
+  int64_t nodes_visited, elements_tested, fp64_ops;
 } msk_kelvin_est_info;
 
 /* The exterior estimate (Sec. 3.3, eq. main-exterior-estimator; Appendix,
@@ -683,7 +691,8 @@ typedef struct {
  *   radius: host n_rows doubles (inverted tangent radii, 0 = dropped) or NULL;
  *   log, info: optional.
  * walk_opts: seed, max_steps (0 = 1024), kappa, delta_rel (the guard is
- * delta_rel times the inverted domain's bound), mesh_id. Errors: INVALID_ARG
+ * delta_rel times the inverted domain's bound), mesh_id, collect_stats (the
+ * counting walk kernel; info's work tallies). Errors: INVALID_ARG
  * for rows of another mesh, hat rows, a point basis, K > 8192, pairs < 1, an
  * odd kill_walks, or eps at or below max(delta_rel R~ / (1 - kappa),
  * 2^-40 R~); NUMERIC when an entry is not finite (outputs written). */

@@ -1985,14 +1985,15 @@ extern "C" msk_status msk_estimate_kelvin(msk_ctx* ctx, const msk_kelvin* K, con
   double *d_st = nullptr, *d_nt = nullptr, *d_rad = nullptr, *d_g = nullptr, *d_alpha = nullptr, *d_kalpha = nullptr;
   int32_t *d_ls = nullptr, *d_lt = nullptr, *d_lq = nullptr, *d_ktri = nullptr;
   float *d_lb = nullptr, *d_tab = nullptr, *d_kbary = nullptr;
-  unsigned long long *d_rq = nullptr, *d_tq = nullptr, *d_kq = nullptr, *d_nonf = nullptr, *d_next = nullptr;
+  unsigned long long *d_rq = nullptr, *d_tq = nullptr, *d_kq = nullptr, *d_nonf = nullptr, *d_next = nullptr,
+                     *d_wstats = nullptr;
   double *d_S = nullptr, *d_Q = nullptr, *d_se = nullptr, *d_PS = nullptr, *d_PQ = nullptr, *d_U = nullptr,
          *d_V = nullptr;
   hipEvent_t ev[5] = {};
   auto cleanup = [&](msk_status s_) {
     dfree(d_st); dfree(d_nt); dfree(d_rad); dfree(d_g); dfree(d_alpha); dfree(d_kalpha);
     dfree(d_ls); dfree(d_lt); dfree(d_lq); dfree(d_ktri); dfree(d_lb); dfree(d_tab); dfree(d_kbary);
-    dfree(d_rq); dfree(d_tq); dfree(d_kq); dfree(d_nonf); dfree(d_next);
+    dfree(d_rq); dfree(d_tq); dfree(d_kq); dfree(d_nonf); dfree(d_next); dfree(d_wstats);
     dfree(d_S); dfree(d_Q); dfree(d_se); dfree(d_PS); dfree(d_PQ); dfree(d_U); dfree(d_V);
     for (hipEvent_t& e : ev) {
       if (e) (void)hipEventDestroy(e);
@@ -2059,8 +2060,12 @@ extern "C" msk_status msk_estimate_kelvin(msk_ctx* ctx, const msk_kelvin* K, con
     }
   }
   HIP_K(launch_fill_u64(d_next, 1, 0, s));
+  if (o.collect_stats) {  // the counting instantiation: same walks, work tallied
+    HIP_K(dalloc(&d_wstats, 3));
+    HIP_K(launch_fill_u64(d_wstats, 3, 0, s));
+  }
   HIP_K(launch_kelvin_walks(DW, d_st, d_nt, d_rad, n, pairs, u0, kill_walks, d_ls, d_lt, d_lb, d_lq, d_g, d_rq,
-                            d_kq, d_next, std::max(1, ctx->n_cu * 4), s));
+                            d_kq, d_next, d_wstats, std::max(1, ctx->n_cu * 4), s));
   HIP_K(hipEventRecord(ev[2], s));
   std::vector<double> rad((size_t)n);
   HIP_K(hipMemcpyAsync(rad.data(), d_rad, n * 8, hipMemcpyDeviceToHost, s));
@@ -2200,6 +2205,13 @@ extern "C" msk_status msk_estimate_kelvin(msk_ctx* ctx, const msk_kelvin* K, con
   I.walk_kernel_ms = t_walk;
   I.product_ms = prod_ms_total;
   I.nonfinite_entries = (int64_t)nonf;
+  if (d_wstats) {
+    unsigned long long w3[3];
+    HIP_K(hipMemcpy(w3, d_wstats, sizeof(w3), hipMemcpyDeviceToHost));
+    I.nodes_visited = (int64_t)w3[0];
+    I.elements_tested = (int64_t)w3[1];
+    I.fp64_ops = (int64_t)w3[2];
+  }
   if (info) *info = I;
 #undef HIP_K
   cleanup(MSK_OK);

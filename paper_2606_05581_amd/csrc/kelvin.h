@@ -38,7 +38,9 @@ hipError_t launch_kelvin_walks(const KelvinDev& K, const double* st, const doubl
                                int64_t n_rows, int64_t pairs, double u0, int64_t n_kill, int32_t* log_status,
                                int32_t* log_tri, float* log_bary, int32_t* log_q, double* g,
                                unsigned long long* row_queries, unsigned long long* kill_queries,
-                               unsigned long long* next_walk, int grid, hipStream_t s);
+                               unsigned long long* next_walk, unsigned long long* stats, int grid, hipStream_t s);
+// stats: null for the timed kernel, else 3 counters that the counting
+// instantiation adds its node visits, element tests and FP64 operations to
 // Plane of a triangle for its inverted element (unit normal n, offset n . a);
 // false for a numerically degenerate triangle.
 __host__ __device__ bool kelvin_plane(const double a[3], const double b[3], const double c[3], double n[3],

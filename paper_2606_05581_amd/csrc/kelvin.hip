@@ -29,16 +29,22 @@ namespace msk {
 
 namespace {
 
+// The element distance is evaluated exactly as written, with no fused
+// multiply-adds, in these helpers as in the functions that use them: the
+// result then does not depend on how the compiler inlines them.
 __host__ __device__ __forceinline__ double dot(const double a[3], const double b[3]) {
+#pragma clang fp contract(off)
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
 __host__ __device__ __forceinline__ void invert(const double x[3], double y[3]) {
+#pragma clang fp contract(off)
   const double s = 1.0 / dot(x, x);
   y[0] = x[0] * s; y[1] = x[1] * s; y[2] = x[2] * s;
 }
 
 __host__ __device__ __forceinline__ void cross(const double u[3], const double v[3], double o[3]) {
+#pragma clang fp contract(off)
   o[0] = u[1] * v[2] - u[2] * v[1];
   o[1] = u[2] * v[0] - u[0] * v[2];
   o[2] = u[0] * v[1] - u[1] * v[0];
@@ -66,7 +72,12 @@ __host__ __device__ __forceinline__ void offer(Best& b, double d2, const double 
 // it lies on the edge's arc when its image is between P and Q. A line
 // through the centre maps to itself: the arc is then the straight segment
 // between the end points' images. (ia, ib) are the edge's vertex slots.
-__host__ __device__ void edge_image(const double x[3], const double P[3], const double Q[3], int ia, int ib, Best& b) {
+// FP64 operations are counted (kCount) as additions, multiplications,
+// divisions and square roots, one each, up to each exit: dot 5, cross 9,
+// inversion 9.
+template <bool kCount>
+__host__ __device__ void edge_image(const double x[3], const double P[3], const double Q[3], int ia, int ib, Best& b,
+                                    uint64_t& ops) {
 #pragma clang fp contract(off)
   double kp[3], kq[3], d[3];
   invert(P, kp);
@@ -80,6 +91,7 @@ __host__ __device__ void edge_image(const double x[3], const double P[3], const 
   offer(b, dot(d, d), kq, l[0], l[1], l[2]);
   const double e[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
   const double ee = dot(e, e);
+  if constexpr (kCount) ops += 42;
   if (!(ee > 0.0)) return;
   const double tf = -dot(P, e) / ee;
   const double f[3] = {P[0] + tf * e[0], P[1] + tf * e[1], P[2] + tf * e[2]};
@@ -87,6 +99,7 @@ __host__ __device__ void edge_image(const double x[3], const double P[3], const 
   double m[3];
   cross(P, Q, m);
   const double mm = dot(m, m);
+  if constexpr (kCount) ops += 42;
   if (ff > 1e-24 * fmax(dot(P, P), dot(Q, Q)) && mm > 0.0) {
     const double ml = 1.0 / sqrt(mm);
     for (int k = 0; k < 3; ++k) m[k] *= ml;
@@ -95,16 +108,20 @@ __host__ __device__ void edge_image(const double x[3], const double P[3], const 
     const double mx = dot(m, x);
     const double u[3] = {x[0] - mx * m[0] - c[0], x[1] - mx * m[1] - c[1], x[2] - mx * m[2] - c[2]};
     const double ul = sqrt(dot(u, u));
+    if constexpr (kCount) ops += 32;
     if (!(ul > 0.0)) return;
     const double pt[3] = {c[0] + rho * u[0] / ul, c[1] + rho * u[1] / ul, c[2] + rho * u[2] / ul};
     // the origin is the image of the line's point at infinity: every point of
     // the segment's image lies at least 1 / max(|P|, |Q|) from it
+    if constexpr (kCount) ops += 15;
     if (!(dot(pt, pt) * fmax(dot(P, P), dot(Q, Q)) >= 1.0 - 1e-9)) return;
     double y[3];
     invert(pt, y);
     const double yd[3] = {y[0] - P[0], y[1] - P[1], y[2] - P[2]};
     const double t = dot(yd, e) / ee;
+    if constexpr (kCount) ops += 18;
     if (t >= 0.0 && t <= 1.0) {
+      if constexpr (kCount) ops += 9;
       for (int k = 0; k < 3; ++k) d[k] = x[k] - pt[k];
       l[ia] = 1.0 - t; l[ib] = t;
       offer(b, dot(d, d), pt, l[0], l[1], l[2]);
@@ -122,6 +139,7 @@ __host__ __device__ void edge_image(const double x[3], const double P[3], const 
     for (int k = 0; k < 3; ++k) d[k] = x[k] - pt[k];
     l[ia] = 1.0 - t; l[ib] = t;
     offer(b, dot(d, d), pt, l[0], l[1], l[2]);
+    if constexpr (kCount) ops += 50;
   }
 }
 
@@ -158,8 +176,9 @@ __host__ __device__ bool kelvin_plane(const double a[3], const double b[3], cons
 // bounds the patch's from below: when its square exceeds `bound` (with a
 // relative margin for rounding) the element cannot come nearer than bound and
 // INFINITY is returned without the boundary arcs.
-__host__ __device__ double kelvin_tri_d2(const double x[3], const KelvinTri& T, double q[3], double l[3],
-                                         double bound) {
+template <bool kCount>
+__host__ __device__ double kelvin_tri_d2_t(const double x[3], const KelvinTri& T, double q[3], double l[3],
+                                           double bound, uint64_t& ops) {
 #pragma clang fp contract(off)
   Best b;
   b.d2 = INFINITY;
@@ -172,13 +191,18 @@ __host__ __device__ double kelvin_tri_d2(const double x[3], const KelvinTri& T, 
       const double v[3] = {c * x[0] - 0.5 * n[0], c * x[1] - 0.5 * n[1], c * x[2] - 0.5 * n[2]};
       const double vl = sqrt(dot(v, v));
       const double sd = (fabs(c) * dot(x, x) - sg * dot(n, x)) / (vl + 0.5);
+      if constexpr (kCount) ops += 32;
       if (sd * sd > bound * (1.0 + 1e-9)) return INFINITY;
       for (int k = 0; k < 3; ++k) p[k] = x[k] - sd * sg * v[k] / vl;
+      if constexpr (kCount) ops += 10;
     } else {
       const double nx = dot(n, x);
+      if constexpr (kCount) ops += 7;
       if (nx * nx > bound * (1.0 + 1e-9)) return INFINITY;
       for (int k = 0; k < 3; ++k) p[k] = x[k] - nx * n[k];
+      if constexpr (kCount) ops += 6;
     }
+    if constexpr (kCount) ops += 6;
     if (dot(p, p) * T.M2 >= 1.0 - 1e-9) {  // image points lie at least 1 / max|vertex| from the origin
       double y[3], ay[3], w[3], ab[3], ac[3], nn[3];
       invert(p, y);
@@ -195,28 +219,54 @@ __host__ __device__ double kelvin_tri_d2(const double x[3], const KelvinTri& T, 
       cross(ab, ay, w);
       const double l2 = dot(w, n) / nl;
       const double l0 = 1.0 - l1 - l2;
+      if constexpr (kCount) ops += 64;
       if (l0 >= 0.0 && l1 >= 0.0 && l2 >= 0.0) {
         const double d[3] = {x[0] - p[0], x[1] - p[1], x[2] - p[2]};
         offer(b, dot(d, d), p, l0, l1, l2);
+        if constexpr (kCount) ops += 8;
       }
     }
   }
-  edge_image(x, T.a, T.b, 0, 1, b);
-  edge_image(x, T.b, T.c, 1, 2, b);
-  edge_image(x, T.c, T.a, 2, 0, b);
+  edge_image<kCount>(x, T.a, T.b, 0, 1, b, ops);
+  edge_image<kCount>(x, T.b, T.c, 1, 2, b, ops);
+  edge_image<kCount>(x, T.c, T.a, 2, 0, b, ops);
   q[0] = b.q[0]; q[1] = b.q[1]; q[2] = b.q[2];
   l[0] = b.l[0]; l[1] = b.l[1]; l[2] = b.l[2];
   return b.d2;
 }
 
+__host__ __device__ double kelvin_tri_d2(const double x[3], const KelvinTri& T, double q[3], double l[3],
+                                         double bound) {
+  uint64_t none = 0;
+  return kelvin_tri_d2_t<false>(x, T, q, l, bound, none);
+}
+
+// Work of the counting instantiation of the nearest search.
+struct KelvinWork {
+  uint64_t nodes = 0, elements = 0, ops = 0;
+};
+
 // Exact nearest inverted element: lexicographic minimum of (squared distance,
 // original index), depth first over the 4-wide hierarchy of boxes that
 // contain the elements (FP32 boxes rounded outward; their FP64 lower bounds
 // are within the boxes' own rounding of the true distance, hence the small
-// relative margin).
-__host__ __device__ double kelvin_nearest(const KelvinDev& K, const double x[3], int32_t& orig, double q[3], double l[3]) {
+// relative margin). `slot` names a candidate element on entry (warm start:
+// a walk's previous nearest, tested first so that the search starts with a
+// finite bound; -1 for none) and receives the nearest one's slot. The
+// minimum, and the element that attains it, do not depend on the candidate.
+template <bool kCount>
+__host__ __device__ double kelvin_nearest_t(const KelvinDev& K, const double x[3], int32_t& orig, double q[3],
+                                            double l[3], KelvinWork& work, int32_t& slot) {
   double best = INFINITY;
   orig = INT_MAX;
+  int32_t best_slot = -1;
+  if (slot >= 0) {
+    const KelvinTri& T = K.tris[slot];
+    if constexpr (kCount) ++work.elements;
+    best = kelvin_tri_d2_t<kCount>(x, T, q, l, best, work.ops);
+    orig = T.orig;
+    best_slot = slot;
+  }
   int32_t stk[kStackDepth];
   double stl[kStackDepth];
   int sp = 0;
@@ -225,6 +275,10 @@ __host__ __device__ double kelvin_nearest(const KelvinDev& K, const double x[3],
     const Node4& N = K.nodes[node];
     double lb[4];
     int32_t cc[4], cn[4];
+    if constexpr (kCount) {  // four box lower bounds: 6 differences, 6 maxima, 3 products, 2 sums each
+      ++work.nodes;
+      work.ops += 4 * 17;
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const double gx = fmax(fmax((double)N.lox[k] - x[0], x[0] - (double)N.hix[k]), 0.0);
@@ -251,10 +305,12 @@ __host__ __device__ double kelvin_nearest(const KelvinDev& K, const double x[3],
         for (int32_t s = first; s < first + cn[k]; ++s) {
           const KelvinTri& T = K.tris[s];
           double qq[3], ll[3];
-          const double d = kelvin_tri_d2(x, T, qq, ll, best);
+          if constexpr (kCount) ++work.elements;
+          const double d = kelvin_tri_d2_t<kCount>(x, T, qq, ll, best, work.ops);
           if (d < best || (d == best && T.orig < orig)) {
             best = d;
             orig = T.orig;
+            best_slot = s;
             q[0] = qq[0]; q[1] = qq[1]; q[2] = qq[2];
             l[0] = ll[0]; l[1] = ll[1]; l[2] = ll[2];
           }
@@ -288,7 +344,14 @@ __host__ __device__ double kelvin_nearest(const KelvinDev& K, const double x[3],
     }
     if (node < 0) break;
   }
+  slot = best_slot;
   return best;
+}
+
+__host__ __device__ double kelvin_nearest(const KelvinDev& K, const double x[3], int32_t& orig, double q[3], double l[3]) {
+  KelvinWork none;
+  int32_t cold = -1;
+  return kelvin_nearest_t<false>(K, x, orig, q, l, none, cold);
 }
 
 
@@ -342,8 +405,9 @@ __device__ __forceinline__ void frame(const double n[3], double e1[3], double e2
 // nearest element; in the eps-shell the walk has hit (true), else x moves to
 // a uniform point of the sphere of radius d (1 - kappa) - delta, drawn from
 // the Philox block (row, walk, k, step purpose), the oracle's streams.
+template <bool kCount>
 __device__ bool kelvin_step(const KelvinDev& K, uint32_t row, uint32_t walk, int64_t k, double x[3], int32_t& orig,
-                            double q[3], double l[3], bool at_origin) {
+                            double q[3], double l[3], bool at_origin, KelvinWork& work, int32_t& warm) {
   double d2;
   if (at_origin) {  // the first step of a killing walk: the shared answer
     d2 = K.origin_d2;
@@ -353,7 +417,7 @@ __device__ bool kelvin_step(const KelvinDev& K, uint32_t row, uint32_t walk, int
       l[c] = K.origin_l[c];
     }
   } else {
-    d2 = kelvin_nearest(K, x, orig, q, l);
+    d2 = kelvin_nearest_t<kCount>(K, x, orig, q, l, work, warm);
   }
   if (d2 < K.eps2) return true;
   const uint4 u = philox10(make_uint4(row, walk, (uint32_t)k, (kPurposeStep << 24) | (K.mesh_id & 0xFFFFFFu)),
@@ -412,13 +476,20 @@ __global__ void kelvin_tangent_kernel(KelvinDev K, const double* __restrict__ st
 // triangle, the barycentrics of that triangle's vertices 1 and 2 at the
 // terminal point's image, its query count, and the factor g = 1/|t~| of its
 // rank-one update.
+// The counting instantiation (kCount) runs the same walks and adds the
+// nearest searches' node visits, element tests and FP64 operations to
+// stats[0..2].
+template <bool kCount>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MSK_KELVIN_WAVES_PER_EU)))
 kelvin_walk_kernel(
     KelvinDev K, const double* __restrict__ st, const double* __restrict__ nt, const double* __restrict__ radius,
     int64_t n_rows, int64_t pairs, double u0, int64_t n_kill, int32_t* __restrict__ log_status,
     int32_t* __restrict__ log_tri, float* __restrict__ log_bary, int32_t* __restrict__ log_q, double* __restrict__ g,
-    unsigned long long* __restrict__ row_queries, unsigned long long* kill_queries, unsigned long long* next_walk) {
+    unsigned long long* __restrict__ row_queries, unsigned long long* kill_queries, unsigned long long* next_walk,
+    unsigned long long* __restrict__ stats) {
   const int64_t n_jump = n_rows * 2 * pairs, total = n_jump + n_kill;
+  KelvinWork work;
+  int32_t warm = -1;  // slot of the walk's previous nearest element
   int64_t id = -1, i = -1, k = 0;
   uint32_t row = 0, walk = 0;
   double x[3] = {0.0, 0.0, 0.0}, q[3] = {0.0, 0.0, 0.0}, l[3] = {0.0, 0.0, 0.0};
@@ -429,6 +500,7 @@ kelvin_walk_kernel(
       if (id >= total) break;
       k = 0;
       orig = -1;
+      warm = -1;
       if (id < n_jump) {
         i = id / (2 * pairs);
         const int64_t w = id - i * 2 * pairs;
@@ -468,14 +540,14 @@ kelvin_walk_kernel(
     }
     int32_t status = -1, nq = 0;
     if (k < K.max_steps) {
-      if (kelvin_step(K, row, walk, k, x, orig, q, l, i < 0 && k == 0 && K.origin_known)) {
+      if (kelvin_step<kCount>(K, row, walk, k, x, orig, q, l, i < 0 && k == 0 && K.origin_known, work, warm)) {
         status = kHit;
         nq = (int32_t)(k + 1);
       } else {
         ++k;
       }
     } else {  // step cap: the nearest point of the last position
-      kelvin_nearest(K, x, orig, q, l);
+      kelvin_nearest_t<kCount>(K, x, orig, q, l, work, warm);
       status = kCapped;
       nq = (int32_t)(K.max_steps + 1);
     }
@@ -492,6 +564,11 @@ kelvin_walk_kernel(
         atomicAdd(kill_queries, (unsigned long long)nq);
       id = -1;
     }
+  }
+  if constexpr (kCount) {
+    atomicAdd(stats, (unsigned long long)work.nodes);
+    atomicAdd(stats + 1, (unsigned long long)work.elements);
+    atomicAdd(stats + 2, (unsigned long long)work.ops);
   }
 }
 
@@ -525,13 +602,19 @@ hipError_t launch_kelvin_walks(const KelvinDev& K, const double* st, const doubl
                                int64_t n_rows, int64_t pairs, double u0, int64_t n_kill, int32_t* log_status,
                                int32_t* log_tri, float* log_bary, int32_t* log_q, double* g,
                                unsigned long long* row_queries, unsigned long long* kill_queries,
-                               unsigned long long* next_walk, int grid, hipStream_t s) {
+                               unsigned long long* next_walk, unsigned long long* stats, int grid, hipStream_t s) {
   const int64_t n = n_rows * 2 * pairs + n_kill;
   if (n <= 0) return hipSuccess;
   if (grid < 1) return hipErrorInvalidValue;
   const int64_t blocks = std::min<int64_t>(grid, (n + 255) / 256);
-  hipLaunchKernelGGL(kelvin_walk_kernel, dim3((unsigned)blocks), dim3(256), 0, s, K, st, nt, radius, n_rows, pairs,
-                     u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries, next_walk);
+  if (stats)
+    hipLaunchKernelGGL(kelvin_walk_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, K, st, nt, radius, n_rows,
+                       pairs, u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries,
+                       next_walk, stats);
+  else
+    hipLaunchKernelGGL(kelvin_walk_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, K, st, nt, radius, n_rows,
+                       pairs, u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries,
+                       next_walk, stats);
   return hipGetLastError();
 }
 

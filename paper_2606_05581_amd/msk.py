@@ -125,7 +125,8 @@ class KelvinEstInfo(C.Structure):
                 ("walks_total", C.c_int64), ("queries_total", C.c_int64), ("kill_queries", C.c_int64),
                 ("dropped_rows", C.c_int64), ("capped_total", C.c_int64), ("mean_radius", C.c_double),
                 ("r_max", C.c_double), ("tangent_ms", C.c_double), ("walk_kernel_ms", C.c_double),
-                ("product_ms", C.c_double), ("nonfinite_entries", C.c_int64)]
+                ("product_ms", C.c_double), ("nonfinite_entries", C.c_int64), ("nodes_visited", C.c_int64),
+                ("elements_tested", C.c_int64), ("fp64_ops", C.c_int64)]
 
 
 class LaplaceOpts(C.Structure):

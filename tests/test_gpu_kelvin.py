@@ -202,6 +202,38 @@ def test_kelvin_parity_unit_sphere(ctx, oracle_mod):
     _check_log_sum(V, F, c, rows, np.asarray(tab, np.float32), g, o, 32, 20000, "unit sphere")
 
 
+def test_kelvin_counting_kernel_runs_the_same_walks(ctx):
+    """The counting build of the walk kernel (walk option collect_stats) runs
+    the same walks, so logs and estimates are identical; its tallies agree
+    with the walks: every nearest search visits the root and tests at least
+    one element (the killing walks' first queries share one search made before
+    the launch and are not tallied), and an element test costs between 7 and
+    594 FP64 operations (its shortest and longest exit paths) on top of 4 x 17
+    per node visited."""
+    V, F, tab = _sphere(3)
+    rows = W.point_rows(V, F, 200, np.random.default_rng(23))
+    mesh = ctx.build_bvh(V.astype(np.float32), F)
+    rh = ctx.rows(mesh, rows)
+    bh = ctx.basis(W.dense_basis(np.asarray(tab, dtype=np.float32)), V.shape[0])
+    kv = ctx.kelvin(mesh, np.array([0.2, -0.1, 0.05]))
+    eps = 1e-5 * kv.info()["radius"]
+    pairs, kill = 16, 4096
+    a = ctx.estimate_kelvin(kv, rh, bh, pairs, kill, eps, seed=9, log=True)
+    b = ctx.estimate_kelvin(kv, rh, bh, pairs, kill, eps, seed=9, log=True, collect_stats=1)
+    for k in ("status", "tri", "bary", "nq", "radius", "S_jump", "S_kill", "se_jump", "se_kill"):
+        d = float(np.abs(np.asarray(a[k], np.float64) - np.asarray(b[k], np.float64)).max())
+        print(f"[kelvin counting] {k}: max difference {d:.3e}", flush=True)
+        assert np.array_equal(a[k], b[k]), k
+    ia, ib = a["info"], b["info"]
+    assert ia["nodes_visited"] == ia["elements_tested"] == ia["fp64_ops"] == 0
+    searches = ib["queries_total"] - rows.n_rows * 10 - kill
+    nodes, elems, ops = ib["nodes_visited"], ib["elements_tested"], ib["fp64_ops"]
+    print(f"[kelvin counting] {searches} searches: {nodes} nodes, {elems} elements, {ops} FP64 operations "
+          f"({nodes / searches:.1f}, {elems / searches:.1f}, {ops / searches:.0f} per search)", flush=True)
+    assert nodes >= searches and elems >= searches
+    assert 68 * nodes + 7 * elems <= ops <= 68 * nodes + 594 * elems
+
+
 def test_kelvin_parity_two_bodies(ctx, oracle_mod):
     V, F, tab = _two_bodies()
     rows = W.point_rows(V, F, 400, np.random.default_rng(23))

@@ -26,6 +26,12 @@ bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>&
                       double* abs_max);
 bool cholesky_upper(int n, const std::vector<double>& A, std::vector<double>& R, double rel_tol);
 void upper_inverse(int n, const std::vector<double>& R, std::vector<double>& Ri);
+bool tridiag_smallest_pairs(int n, const std::vector<double>& d, const std::vector<double>& e, int m,
+                            std::vector<double>& evals, std::vector<double>& Xc, double* abs_max);
+void bisect_setup(int n, const std::vector<double>& d, const std::vector<double>& e, std::vector<double>& e2,
+                  double& glo, double& ghi, double& pivmin, double& atol);
+bool tridiag_vectors(int n, const std::vector<double>& d, const std::vector<double>& e,
+                     const std::vector<double>& evals, std::vector<double>& Xc);
 
 // ------------------------------------------------------------- kernels
 
@@ -202,6 +208,227 @@ __global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, T alpha, 
   *o = alpha * acc + (beta == T(0) ? T(0) : beta * *o);
 }
 
+// ------------------------------------- projected eigenproblem on the device
+// Householder tridiagonalisation (Golub & Van Loan, Alg. 8.3.1) of the
+// symmetric n x n row-major A, in place, one launch pair per step k < n - 2:
+// the reflector P = I - beta v v^T (v[0] = 1) with P x = mu e1 for
+// x = A[k+1:, k], then p = beta A22 v, w = p - (beta p.v / 2) v and
+// A22 -= v w^T + w v^T on the trailing (n-k-1)^2 block, kept in full storage
+// (so row k holds x). Each workgroup of a step forms the same v from the
+// same sums in the same order; workgroup 0 records v[1:] in row k of H
+// (columns k+2..n-1), beta[k], d[k] = A[k][k] and e[k] = mu.
+constexpr int kProjMax = 2048;  // largest projected problem solved on the device
+
+// Sum over a 256-thread workgroup; every thread receives the same bits.
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void __launch_bounds__(256) house_symv_kernel(const double* __restrict__ A, int n, int k,
+                                                         double* __restrict__ H, double* __restrict__ betas,
+                                                         double* __restrict__ d, double* __restrict__ e,
+                                                         double* __restrict__ p) {
+  __shared__ double vs[kProjMax];
+  __shared__ double red[4];
+  const int m = n - k - 1;
+  const double* x = A + (size_t)k * n + (k + 1);  // row k = column k below the diagonal
+  double s = 0.0;
+  for (int i = 1 + (int)threadIdx.x; i < m; i += 256) s += x[i] * x[i];
+  const double sigma = block_sum256(s, red);
+  const double x0 = x[0];
+  double beta = 0.0, mu = x0, v0 = 1.0;
+  if (sigma != 0.0) {
+    mu = sqrt(x0 * x0 + sigma);
+    v0 = x0 <= 0.0 ? x0 - mu : -sigma / (x0 + mu);
+    beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
+  }
+  for (int i = threadIdx.x; i < m; i += 256) vs[i] = i == 0 ? 1.0 : (sigma != 0.0 ? x[i] / v0 : 0.0);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      betas[k] = beta;
+      d[k] = A[(size_t)k * n + k];
+      e[k] = mu;
+    }
+    for (int i = 1 + (int)threadIdx.x; i < m; i += 256) H[(size_t)k * n + k + 1 + i] = vs[i];
+  }
+  if (sigma == 0.0) return;  // already reduced in this column
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int r = blockIdx.x * 4 + wave; r < m; r += gridDim.x * 4) {
+    const double* row = A + (size_t)(k + 1 + r) * n + (k + 1);
+    double acc = 0.0;
+    for (int c = lane; c < m; c += 64) acc += row[c] * vs[c];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) p[r] = beta * acc;
+  }
+}
+
+__global__ void __launch_bounds__(256) house_update_kernel(double* __restrict__ A, int n, int k,
+                                                           const double* __restrict__ H,
+                                                           const double* __restrict__ betas,
+                                                           const double* __restrict__ p) {
+#pragma clang fp contract(off)  // (r, c) and (c, r) get the same bits: A stays symmetric
+  __shared__ double vs[kProjMax], ws[kProjMax];
+  __shared__ double red[4];
+  const double beta = betas[k];
+  if (beta == 0.0) return;
+  const int m = n - k - 1;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const double v = i == 0 ? 1.0 : H[(size_t)k * n + k + 1 + i];
+    vs[i] = v;
+    s += p[i] * v;
+  }
+  const double half = 0.5 * beta * block_sum256(s, red);
+  for (int i = threadIdx.x; i < m; i += 256) ws[i] = p[i] - half * vs[i];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int r = blockIdx.x * 4 + wave; r < m; r += gridDim.x * 4) {
+    double* row = A + (size_t)(k + 1 + r) * n + (k + 1);
+    const double vr = vs[r], wr = ws[r];
+    for (int c = lane; c < m; c += 64) row[c] -= vr * ws[c] + wr * vs[c];
+  }
+}
+
+// The last 2 x 2 block of the reduced matrix.
+__global__ void house_tail_kernel(const double* __restrict__ A, int n, double* d, double* e) {
+  if (threadIdx.x == 0) {
+    d[n - 2] = A[(size_t)(n - 2) * n + (n - 2)];
+    d[n - 1] = A[(size_t)(n - 1) * n + (n - 1)];
+    e[n - 2] = A[(size_t)(n - 1) * n + (n - 2)];
+    e[n - 1] = 0.0;
+  }
+}
+
+// Eigenvalue number j (ascending) of the symmetric tridiagonal (d, e2 = e^2)
+// by bisection on the Sturm count (the negative pivots of the LDL^T
+// factorisation of T - x I; a pivot below pivmin in magnitude taken as
+// -pivmin) until the interval is at most atol wide; one thread per target:
+// targets 0..m-1, and target m is the largest (index n - 1). The host's
+// bisection performs the same operations.
+__global__ void sturm_bisect_kernel(int n, const double* __restrict__ d, const double* __restrict__ e2, int m,
+                                    double glo, double ghi, double atol, double pivmin, double* __restrict__ out) {
+#pragma clang fp contract(off)
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > m) return;
+  const int j = t < m ? t : n - 1;
+  double lo = glo, hi = ghi;
+  for (int it = 0; it < 200 && hi - lo > atol; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    double q = d[0] - mid;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int c = q < 0.0;
+    for (int i = 1; i < n; ++i) {
+      q = (d[i] - mid) - e2[i - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      c += q < 0.0;
+    }
+    if (c <= j)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  out[t] = 0.5 * (lo + hi);
+}
+
+// Partial sums of the squared Ritz residuals: part[g][j] = sum over the rows
+// r of group g (rows g, g + G, ...) of (CV[r][j] - theta[j] V[r][j])^2, for
+// the n x m row-major V and CV; the groups are then added in order.
+__global__ void ritz_residual_kernel(const double* __restrict__ V, const double* __restrict__ CV,
+                                     const double* __restrict__ theta, int64_t n, int m, double* __restrict__ part) {
+  const int g = blockIdx.x, G = gridDim.x;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const double th = theta[j];
+    double s = 0.0;
+    for (int64_t r = g; r < n; r += G) {
+      const double dlt = CV[r * m + j] - th * V[r * m + j];
+      s += dlt * dlt;
+    }
+    part[(int64_t)g * m + j] = s;
+  }
+}
+
+__global__ void sum_groups_kernel(const double* __restrict__ part, int G, int m, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double s = 0.0;
+  for (int g = 0; g < G; ++g) s += part[(int64_t)g * m + j];
+  out[j] = s;
+}
+
+// The restart block: X[r][i] = CV[r][pick[i]] - theta[pick[i]] V[r][pick[i]]
+// for i < npick, 0 for npick <= i < b (V, CV n x m; X n x b).
+__global__ void restart_block_kernel(const double* __restrict__ V, const double* __restrict__ CV,
+                                     const double* __restrict__ theta, const int32_t* __restrict__ pick, int npick,
+                                     int64_t n, int m, int b, double* __restrict__ X) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * b; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / b;
+    const int i = (int)(t % b);
+    double x = 0.0;
+    if (i < npick) {
+      const int j = pick[i];
+      x = CV[r * m + j] - theta[j] * V[r * m + j];
+    }
+    X[t] = x;
+  }
+}
+
+// A <- (A + A^T) / 2 for the n x n row-major A.
+__global__ void symmetrise_kernel(double* A, int n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t % n);
+  if (j <= i) return;
+  const double a = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+  A[(size_t)i * n + j] = a;
+  A[(size_t)j * n + i] = a;
+}
+
+// Y = H_0 H_1 ... H_{n-3} X: one wavefront per vector (X vector-major, vector
+// j at X[j n ..]; Y n x m row-major), the reflectors applied last first; the
+// vector lives in registers, entry r = lane + 64 t in slot t < T (n <= 64 T).
+template <int T>
+__global__ void __launch_bounds__(256) house_back_kernel(const double* __restrict__ H,
+                                                         const double* __restrict__ betas, int n, int m,
+                                                         const double* __restrict__ X, double* __restrict__ Y) {
+  static_assert(64 * T <= kProjMax, "at most kProjMax entries per vector");
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= m) return;
+  double x[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int r = lane + 64 * t;
+    x[t] = r < n ? X[(size_t)j * n + r] : 0.0;
+  }
+  for (int k = n - 3; k >= 0; --k) {
+    const double beta = betas[k];
+    if (beta == 0.0) continue;
+    const double* v = H + (size_t)k * n;  // v[k+1] = 1, v[k+2..n-1] stored
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int r = lane + 64 * t;
+      if (r >= k + 1 && r < n) s += (r == k + 1 ? 1.0 : v[r]) * x[t];
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    s *= beta;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int r = lane + 64 * t;
+      if (r >= k + 1 && r < n) x[t] -= (r == k + 1 ? 1.0 : v[r]) * s;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int r = lane + 64 * t;
+    if (r < n) Y[(size_t)r * m + j] = x[t];
+  }
+}
+
 namespace {
 
 int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 1 << 16); }
@@ -356,7 +583,7 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
     // residual target above the floor of FP32 products with C
     const double tol = std::max(1e-5, 16.0 * std::sqrt((double)n) * std::ldexp(1.0, -24));
     *block_out = b;
-    DevBuf dQ, dW, dX, dX32, dY32, dT, dG, dY, dQ2, dW2;
+    DevBuf dQ, dW, dX, dX32, dY32, dT, dG, dY, dQ2, dW2, dH, dBeta, dD, dE, dP, dXc, dEv, dTh, dPart, dRes, dPick;
     EIG_TRY(hipMalloc(&dQ.p, (size_t)n * cap * 8));
     EIG_TRY(hipMalloc(&dW.p, (size_t)n * cap * 8));
     EIG_TRY(hipMalloc(&dX.p, (size_t)n * b * 8));
@@ -367,6 +594,19 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
     EIG_TRY(hipMalloc(&dY.p, (size_t)cap * cap * 8));
     EIG_TRY(hipMalloc(&dQ2.p, (size_t)n * cap * 8));
     EIG_TRY(hipMalloc(&dW2.p, (size_t)n * cap * 8));
+    if (cap <= kProjMax) {  // the device's projected eigensolve
+      EIG_TRY(hipMalloc(&dH.p, (size_t)cap * cap * 8));
+      EIG_TRY(hipMalloc(&dBeta.p, (size_t)cap * 8));
+      EIG_TRY(hipMalloc(&dD.p, (size_t)cap * 8));
+      EIG_TRY(hipMalloc(&dE.p, (size_t)cap * 8));
+      EIG_TRY(hipMalloc(&dP.p, (size_t)cap * 8));
+      EIG_TRY(hipMalloc(&dXc.p, (size_t)cap * keep_n * 8));
+      EIG_TRY(hipMalloc(&dEv.p, (size_t)(keep_n + 1) * 8));
+    }
+    EIG_TRY(hipMalloc(&dTh.p, (size_t)keep_n * 8));
+    EIG_TRY(hipMalloc(&dPart.p, (size_t)256 * keep_n * 8));
+    EIG_TRY(hipMalloc(&dRes.p, (size_t)keep_n * 8));
+    EIG_TRY(hipMalloc(&dPick.p, (size_t)b * 4));
     double* Q = dQ.as<double>();
     double* Wm = dW.as<double>();
     double* X = dX.as<double>();
@@ -436,42 +676,102 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
       }
       // Rayleigh-Ritz on span(Q[:, :cur])
       EIG_TRY((gemm<double, true, false>(s, ws, cur, cur, n, 1.0, Q, cap, Wm, cap, 0.0, dT.as<double>(), cur)));
-      T.assign((size_t)cur * cur, 0.0);
-      EIG_TRY(hipMemcpyAsync(T.data(), dT.p, T.size() * 8, hipMemcpyDeviceToHost, s));
-      EIG_TRY(hipStreamSynchronize(s));
-      for (int i = 0; i < cur; ++i)
-        for (int j = i + 1; j < cur; ++j) T[(size_t)i * cur + j] = T[(size_t)j * cur + i] =
-            0.5 * (T[(size_t)i * cur + j] + T[(size_t)j * cur + i]);
       const int kk = std::min(keep_n, cur);
       double tmax = 0.0;
-      if (!sym_eig_smallest(cur, T, kk, th, Y, &tmax)) {
-        err = "projected eigensolve did not converge";
-        return 4;
+      if (cur >= 3 && cur <= kProjMax) {
+        // on the device: symmetrise, tridiagonalise; the tridiagonal's kk
+        // smallest pairs on the host; back through the reflectors into dY
+        double* A = dT.as<double>();
+        hipLaunchKernelGGL(symmetrise_kernel, dim3(blocks_for((int64_t)cur * cur)), dim3(256), 0, s, A, cur);
+        for (int kx = 0; kx + 2 < cur; ++kx) {
+          const int g = std::min(256, (cur - kx - 1 + 3) / 4);
+          hipLaunchKernelGGL(house_symv_kernel, dim3(g), dim3(256), 0, s, (const double*)A, cur, kx,
+                             dH.as<double>(), dBeta.as<double>(), dD.as<double>(), dE.as<double>(), dP.as<double>());
+          hipLaunchKernelGGL(house_update_kernel, dim3(g), dim3(256), 0, s, A, cur, kx, (const double*)dH.as<double>(),
+                             (const double*)dBeta.as<double>(), (const double*)dP.as<double>());
+        }
+        hipLaunchKernelGGL(house_tail_kernel, dim3(1), dim3(64), 0, s, (const double*)A, cur, dD.as<double>(),
+                           dE.as<double>());
+        EIG_TRY(hipGetLastError());
+        std::vector<double> td(cur), te(cur), e2, Xc;
+        EIG_TRY(hipMemcpyAsync(td.data(), dD.p, (size_t)cur * 8, hipMemcpyDeviceToHost, s));
+        EIG_TRY(hipMemcpyAsync(te.data(), dE.p, (size_t)cur * 8, hipMemcpyDeviceToHost, s));
+        EIG_TRY(hipStreamSynchronize(s));
+        // the kk smallest eigenvalues and the largest: bisection, one thread each
+        double glo, ghi, pivmin, atol;
+        bisect_setup(cur, td, te, e2, glo, ghi, pivmin, atol);
+        EIG_TRY(hipMemcpyAsync(dP.p, e2.data(), e2.size() * 8, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(sturm_bisect_kernel, dim3((kk + 1 + 63) / 64), dim3(64), 0, s, cur,
+                           (const double*)dD.as<double>(), (const double*)dP.as<double>(), kk, glo, ghi, atol, pivmin,
+                           dEv.as<double>());
+        EIG_TRY(hipGetLastError());
+        std::vector<double> ev((size_t)kk + 1);
+        EIG_TRY(hipMemcpyAsync(ev.data(), dEv.p, ev.size() * 8, hipMemcpyDeviceToHost, s));
+        EIG_TRY(hipStreamSynchronize(s));
+        th.assign(ev.begin(), ev.begin() + kk);
+        std::sort(th.begin(), th.end());
+        tmax = std::max(std::fabs(th.front()), std::fabs(ev[kk]));
+        if (!tridiag_vectors(cur, td, te, th, Xc)) {
+          err = "projected eigensolve did not converge";
+          return 4;
+        }
+        EIG_TRY(hipMemcpyAsync(dXc.p, Xc.data(), Xc.size() * 8, hipMemcpyHostToDevice, s));
+        const dim3 gb((kk + 3) / 4);
+        const double* Hc = dH.as<double>();
+        const double* Bc = dBeta.as<double>();
+        const double* Xd = dXc.as<double>();
+        if (cur <= 512)
+          hipLaunchKernelGGL(house_back_kernel<8>, gb, dim3(256), 0, s, Hc, Bc, cur, kk, Xd, dY.as<double>());
+        else if (cur <= 1024)
+          hipLaunchKernelGGL(house_back_kernel<16>, gb, dim3(256), 0, s, Hc, Bc, cur, kk, Xd, dY.as<double>());
+        else
+          hipLaunchKernelGGL(house_back_kernel<32>, gb, dim3(256), 0, s, Hc, Bc, cur, kk, Xd, dY.as<double>());
+        EIG_TRY(hipGetLastError());
+      } else {
+        T.assign((size_t)cur * cur, 0.0);
+        EIG_TRY(hipMemcpyAsync(T.data(), dT.p, T.size() * 8, hipMemcpyDeviceToHost, s));
+        EIG_TRY(hipStreamSynchronize(s));
+        for (int i = 0; i < cur; ++i)
+          for (int j = i + 1; j < cur; ++j) T[(size_t)i * cur + j] = T[(size_t)j * cur + i] =
+              0.5 * (T[(size_t)i * cur + j] + T[(size_t)j * cur + i]);
+        if (!sym_eig_smallest(cur, T, kk, th, Y, &tmax)) {
+          err = "projected eigensolve did not converge";
+          return 4;
+        }
+        EIG_TRY(hipMemcpyAsync(dY.p, Y.data(), (size_t)cur * kk * 8, hipMemcpyHostToDevice, s));
       }
       cnorm = std::max(cnorm, tmax);
       // Ritz vectors V = Q Y[:, :kk], CV = W Y[:, :kk] (Y is cur x kk)
-      EIG_TRY(hipMemcpyAsync(dY.p, Y.data(), (size_t)cur * kk * 8, hipMemcpyHostToDevice, s));
       EIG_TRY((gemm<double, false, false>(s, ws, n, kk, cur, 1.0, Q, cap, dY.as<double>(), kk, 0.0, dQ2.as<double>(), kk)));
       EIG_TRY((gemm<double, false, false>(s, ws, n, kk, cur, 1.0, Wm, cap, dY.as<double>(), kk, 0.0, dW2.as<double>(), kk)));
-      // residual norms of the first k Ritz pairs: |CV_j - theta_j V_j|
-      std::vector<double> V2((size_t)n * kk), CV2((size_t)n * kk);
-      EIG_TRY(hipMemcpyAsync(V2.data(), dQ2.p, V2.size() * 8, hipMemcpyDeviceToHost, s));
-      EIG_TRY(hipMemcpyAsync(CV2.data(), dW2.p, CV2.size() * 8, hipMemcpyDeviceToHost, s));
-      EIG_TRY(hipStreamSynchronize(s));
+      // squared residual norms of the kk Ritz pairs, |CV_j - theta_j V_j|^2,
+      // on the device (the row groups added in a fixed order)
+      constexpr int kResGroups = 256;
+      EIG_TRY(hipMemcpyAsync(dTh.p, th.data(), (size_t)kk * 8, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(ritz_residual_kernel, dim3(kResGroups), dim3(256), 0, s, (const double*)dQ2.as<double>(),
+                         (const double*)dW2.as<double>(), (const double*)dTh.as<double>(), n, kk, dPart.as<double>());
+      hipLaunchKernelGGL(sum_groups_kernel, dim3((kk + 255) / 256), dim3(256), 0, s, (const double*)dPart.as<double>(),
+                         kResGroups, kk, dRes.as<double>());
+      EIG_TRY(hipGetLastError());
       res.assign(kk, 0.0);
-      for (int64_t r = 0; r < n; ++r)
-        for (int j = 0; j < kk; ++j) {
-          const double d = CV2[(size_t)r * kk + j] - th[j] * V2[(size_t)r * kk + j];
-          res[j] += d * d;
-        }
-      worst = 0.0;
-      for (int j = 0; j < k; ++j) worst = std::max(worst, std::sqrt(res[j]) / std::max(cnorm, 1e-300));
-      const bool done = worst <= tol || cur >= n;
-      if (done || cycle + 1 == max_cycles) {
+      EIG_TRY(hipMemcpyAsync(res.data(), dRes.p, (size_t)kk * 8, hipMemcpyDeviceToHost, s));
+      EIG_TRY(hipStreamSynchronize(s));
+      // the first k Ritz vectors on the host, once the iteration ends
+      auto take_vectors = [&]() -> int {
+        std::vector<double> V2((size_t)n * kk);
+        EIG_TRY(hipMemcpyAsync(V2.data(), dQ2.p, V2.size() * 8, hipMemcpyDeviceToHost, s));
+        EIG_TRY(hipStreamSynchronize(s));
         theta.assign(th.begin(), th.begin() + k);
         Vk.assign((size_t)n * k, 0.0);
         for (int64_t r = 0; r < n; ++r)
           for (int j = 0; j < k; ++j) Vk[(size_t)r * k + j] = V2[(size_t)r * kk + j];
+        return 0;
+      };
+      worst = 0.0;
+      for (int j = 0; j < k; ++j) worst = std::max(worst, std::sqrt(res[j]) / std::max(cnorm, 1e-300));
+      const bool done = worst <= tol || cur >= n;
+      if (done || cycle + 1 == max_cycles) {
+        if (int rc = take_vectors()) return rc;
         if (!done) status = 4;
         break;
       }
@@ -489,21 +789,17 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
         if (std::sqrt(res[j]) > tol * cnorm) pick.push_back(j);
       for (int j = 0; j < kk && (int)pick.size() < b; ++j)
         if (!(std::sqrt(res[j]) > tol * cnorm)) pick.push_back(j);
-      std::vector<double> Rb((size_t)n * b, 0.0);
-      for (int64_t r = 0; r < n; ++r)
-        for (int i = 0; i < (int)pick.size(); ++i) {
-          const int j = pick[i];
-          Rb[(size_t)r * b + i] = CV2[(size_t)r * kk + j] - th[j] * V2[(size_t)r * kk + j];
-        }
-      EIG_TRY(hipMemcpyAsync(X, Rb.data(), Rb.size() * 8, hipMemcpyHostToDevice, s));
+      EIG_TRY(hipMemcpyAsync(dPick.p, pick.data(), pick.size() * 4, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(restart_block_kernel, dim3(blocks_for(n * b)), dim3(256), 0, s,
+                         (const double*)dQ2.as<double>(), (const double*)dW2.as<double>(),
+                         (const double*)dTh.as<double>(), (const int32_t*)dPick.as<int32_t>(), (int)pick.size(), n, kk,
+                         b, X);
+      EIG_TRY(hipGetLastError());
       bool ok;
       int rc = add_block(ok);
       if (rc) return rc;
       if (!ok) {  // residual block already in the span: cannot improve
-        theta.assign(th.begin(), th.begin() + k);
-        Vk.assign((size_t)n * k, 0.0);
-        for (int64_t r = 0; r < n; ++r)
-          for (int j = 0; j < k; ++j) Vk[(size_t)r * k + j] = V2[(size_t)r * kk + j];
+        if (int rc2 = take_vectors()) return rc2;
         status = worst <= tol ? 0 : 4;
         break;
       }

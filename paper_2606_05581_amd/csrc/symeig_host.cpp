@@ -278,10 +278,16 @@ void sturm_counts(int n, const double* d, const double* e2, const double* x, dou
 // and the largest, each by bisection on the Sturm count inside the
 // Gershgorin interval to an absolute width of 4 eps |T| (eigenvalues are
 // independent: four bisections advance together, groups are pool tasks).
-void tridiag_smallest(int n, const std::vector<double>& d, const std::vector<double>& e, int m,
-                      std::vector<double>& out, double& largest) {
-  std::vector<double> e2(std::max(n - 1, 1), 0.0);
-  double glo = INFINITY, ghi = -INFINITY, emax2 = 0.0;
+}  // namespace
+
+// The bisection's set-up: e2[i] = e[i]^2, the widened Gershgorin interval
+// [glo, ghi], the pivot floor and the absolute width at which it stops.
+void bisect_setup(int n, const std::vector<double>& d, const std::vector<double>& e, std::vector<double>& e2,
+                  double& glo, double& ghi, double& pivmin, double& atol) {
+  e2.assign(std::max(n - 1, 1), 0.0);
+  glo = INFINITY;
+  ghi = -INFINITY;
+  double emax2 = 0.0;
   for (int i = 0; i < n; ++i) {
     const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
     glo = std::min(glo, d[i] - r);
@@ -293,10 +299,19 @@ void tridiag_smallest(int n, const std::vector<double>& d, const std::vector<dou
   }
   const double tnorm = std::max(std::fabs(glo), std::fabs(ghi));
   const double eps = std::ldexp(1.0, -52);
-  const double pivmin = DBL_MIN * std::max(1.0, emax2);
-  const double atol = 4.0 * eps * std::max(tnorm, DBL_MIN);
+  pivmin = DBL_MIN * std::max(1.0, emax2);
+  atol = 4.0 * eps * std::max(tnorm, DBL_MIN);
   glo -= 2.0 * atol + pivmin;
   ghi += 2.0 * atol + pivmin;
+}
+
+namespace {
+
+void tridiag_smallest(int n, const std::vector<double>& d, const std::vector<double>& e, int m,
+                      std::vector<double>& out, double& largest) {
+  std::vector<double> e2;
+  double glo, ghi, pivmin, atol;
+  bisect_setup(n, d, e, e2, glo, ghi, pivmin, atol);
   // targets: indices 0..m-1 and n-1 (the largest), in groups of four
   std::vector<int> idx(m + 1);
   for (int j = 0; j < m; ++j) idx[j] = j;
@@ -396,27 +411,42 @@ void tridiag_solve(int n, const TriLU& f, std::vector<double>& y) {
 
 }  // namespace
 
-// The m smallest eigenpairs of a symmetric A (n x n, row-major; destroyed):
-// Householder tridiagonalisation, all eigenvalues of T by implicit QR without
-// vectors, eigenvectors of T for the m smallest by inverse iteration (with
-// Gram-Schmidt inside clusters of close eigenvalues, as in LAPACK's xSTEIN),
-// then back through the reflectors. evals ascending; V is n x m row-major;
-// abs_max (optional) receives the largest eigenvalue magnitude.
-bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>& evals, std::vector<double>& V,
-                      double* abs_max) {
+bool tridiag_vectors(int n, const std::vector<double>& d, const std::vector<double>& e,
+                     const std::vector<double>& evals, std::vector<double>& Xc);
+
+// The m smallest eigenpairs of the symmetric tridiagonal (d, e): the
+// eigenvalues by Sturm-count bisection (ascending), the vectors by inverse
+// iteration (with Gram-Schmidt inside clusters of close eigenvalues, as in
+// LAPACK's xSTEIN), vector j at Xc[j n .. j n + n); abs_max (optional)
+// receives the largest eigenvalue magnitude.
+bool tridiag_smallest_pairs(int n, const std::vector<double>& d, const std::vector<double>& e, int m,
+                            std::vector<double>& evals, std::vector<double>& Xc, double* abs_max) {
   if (m > n) m = n;
-  std::vector<double> d, e, Qdummy, H, betas;
-  tridiagonalise(n, A, Qdummy, d, e, false, &H, &betas);
   double largest = 0.0;
   tridiag_smallest(n, d, e, m, evals, largest);
   if (abs_max) *abs_max = std::max(std::fabs(evals.front()), std::fabs(largest));
+  return tridiag_vectors(n, d, e, evals, Xc);
+}
+
+// Eigenvectors of the symmetric tridiagonal (d, e) for the ascending
+// eigenvalues evals, by inverse iteration, vector j at Xc[j n .. j n + n).
+bool tridiag_vectors(int n, const std::vector<double>& d, const std::vector<double>& e,
+                     const std::vector<double>& evals, std::vector<double>& Xc) {
+  const int m = (int)evals.size();
   double tnorm = 0.0;
   for (int i = 0; i < n; ++i)
     tnorm = std::max(tnorm, std::fabs(d[i]) + (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0));
   if (tnorm == 0.0) tnorm = 1.0;
   const double eps = std::ldexp(1.0, -52);
-  const double ortol = 1e-3 * tnorm;  // eigenvalues closer than this form a cluster
-  std::vector<double> Xc((size_t)n * m, 0.0);  // eigenvectors of T, vector j at Xc[j * n + r]
+  // eigenvalues closer than ortol form a cluster, whose vectors are kept
+  // orthogonal by Gram-Schmidt. Outside a cluster, inverse iteration from
+  // shifts accurate to about eps |T| leaves a neighbour at gap g >= ortol a
+  // component of about eps |T| / g <= 2.2e-10 per step, so the vectors come
+  // out orthogonal to that level without it. (LAPACK's xSTEIN takes
+  // 1e-3 |T|, which on the densely spaced low end of a Steklov spectrum
+  // makes the whole requested range one cluster and the work k^2 n.)
+  const double ortol = 1e-6 * tnorm;
+  Xc.assign((size_t)n * m, 0.0);  // eigenvectors of T, vector j at Xc[j * n + r]
   std::vector<double> y(n), x(n), dots;
   TriLU f;
   uint64_t seed = 0x9E3779B97F4A7C15ull;
@@ -470,6 +500,19 @@ bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>&
     }
     std::copy(y.begin(), y.end(), Xc.begin() + (size_t)j * n);
   }
+  return true;
+}
+
+// The m smallest eigenpairs of a symmetric A (n x n, row-major; destroyed):
+// Householder tridiagonalisation, the tridiagonal's m smallest pairs, then
+// back through the reflectors. evals ascending; V is n x m row-major;
+// abs_max (optional) receives the largest eigenvalue magnitude.
+bool sym_eig_smallest(int n, std::vector<double>& A, int m, std::vector<double>& evals, std::vector<double>& V,
+                      double* abs_max) {
+  if (m > n) m = n;
+  std::vector<double> d, e, Qdummy, H, betas, Xc;
+  tridiagonalise(n, A, Qdummy, d, e, false, &H, &betas);
+  if (!tridiag_smallest_pairs(n, d, e, m, evals, Xc, abs_max)) return false;
   // back-transform each vector: H_0 H_1 ... H_{n-3} x (last reflector first),
   // four vectors at a time: each reflector is read once per four, and the
   // four dot products are independent chains (every vector still sees the

@@ -89,3 +89,14 @@ def test_eigen_krylov_path_soup2000(ctx):
           f"({st['fp32_product_flops'] / st['fp32_product_ms'] / 1e9:.1f} TFLOP/s FP32); FP64 products: "
           f"{st['fp64_products']} in {st['fp64_product_ms']:.2f} ms "
           f"({st['fp64_product_flops'] / st['fp64_product_ms'] / 1e9:.1f} TFLOP/s)", flush=True)
+
+
+@pytest.mark.parametrize("k", [200, 270])
+def test_eigen_projected_problem_paths(ctx, k):
+    """The projected problem of each restart (cap = max(512, 8k) columns) is
+    solved on the device up to 2,048 columns (k = 200: cap 1,600) and on the
+    host above (k = 270: cap 2,160); both paths against LAPACK on the same
+    3,000-row estimate."""
+    wl = W.soup8_53k(N=3000, walks=64)
+    ev, ref, err, res, st = _check(ctx, wl.cases[0], 64, k, False, f"soup8 N=3000 interior, cap {max(512, 8 * k)}")
+    assert st["converged"] and err < 1e-6 and res < 2e-4

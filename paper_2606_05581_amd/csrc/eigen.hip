@@ -210,13 +210,13 @@ __global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, T alpha, 
 
 // ------------------------------------- projected eigenproblem on the device
 // Householder tridiagonalisation (Golub & Van Loan, Alg. 8.3.1) of the
-// symmetric n x n row-major A, in place, one launch pair per step k < n - 2:
-// the reflector P = I - beta v v^T (v[0] = 1) with P x = mu e1 for
-// x = A[k+1:, k], then p = beta A22 v, w = p - (beta p.v / 2) v and
-// A22 -= v w^T + w v^T on the trailing (n-k-1)^2 block, kept in full storage
-// (so row k holds x). Each workgroup of a step forms the same v from the
-// same sums in the same order; workgroup 0 records v[1:] in row k of H
-// (columns k+2..n-1), beta[k], d[k] = A[k][k] and e[k] = mu.
+// symmetric n x n row-major A, in place, steps k < n - 2: the reflector
+// P = I - beta v v^T (v[0] = 1) with P x = mu e1 for x = A[k+1:, k], then
+// p = beta A22 v, w = p - (beta p.v / 2) v and A22 -= v w^T + w v^T on the
+// trailing (n-k-1)^2 block, kept in full storage (so row k holds x). Each
+// workgroup of a step forms the same v from the same sums in the same order;
+// workgroup 0 records v[1:] in row k of H (columns k+2..n-1), beta[k],
+// d[k] = A[k][k] and e[k] = mu.
 constexpr int kProjMax = 2048;  // largest projected problem solved on the device
 
 // Sum over a 256-thread workgroup; every thread receives the same bits.
@@ -228,80 +228,108 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void __launch_bounds__(256) house_symv_kernel(const double* __restrict__ A, int n, int k,
-                                                         double* __restrict__ H, double* __restrict__ betas,
-                                                         double* __restrict__ d, double* __restrict__ e,
-                                                         double* __restrict__ p) {
-  __shared__ double vs[kProjMax];
+// One launch per step: step k's kernel applies step k - 1's rank-2 update
+// (w from p_{k-1} and v_{k-1}, formed by every workgroup) to the rows of its
+// own block while it computes p_k from them. Row k, the only row of step
+// k - 1's block that step k reads beyond its own, is updated on the fly, not
+// in memory (rows and columns <= k are not read again); the last update, of
+// the final 2 x 2 block, is left to house_tail2_kernel. Contraction is off,
+// so entries (r, c) and (c, r) of an update get the same bits.
+__global__ void __launch_bounds__(256) house_step_kernel(double* __restrict__ A, int n, int k, double* __restrict__ H,
+                                                         double* __restrict__ betas, double* __restrict__ d,
+                                                         double* __restrict__ e, const double* __restrict__ p_prev,
+                                                         double* __restrict__ p_out) {
+#pragma clang fp contract(off)
+  __shared__ double vp[kProjMax], wp[kProjMax], vs[kProjMax];
   __shared__ double red[4];
-  const int m = n - k - 1;
-  const double* x = A + (size_t)k * n + (k + 1);  // row k = column k below the diagonal
+  const int m = n - k - 1;      // step k's block: rows and columns k+1..n-1
+  const int mp = m + 1;         // step k-1's block: k..n-1
+  const double bp = k > 0 ? betas[k - 1] : 0.0;
+  // step k-1's v and w over its block (index 0 is row k)
+  if (bp != 0.0) {
+    double sv = 0.0;
+    for (int i = threadIdx.x; i < mp; i += 256) {
+      const double v = i == 0 ? 1.0 : H[(size_t)(k - 1) * n + k + i];
+      vp[i] = v;
+      sv += p_prev[i] * v;
+    }
+    const double half = 0.5 * bp * block_sum256(sv, red);
+    for (int i = threadIdx.x; i < mp; i += 256) wp[i] = p_prev[i] - half * vp[i];
+    __syncthreads();
+  }
+  // row k after step k-1's update: x = A[k][k+1..], d[k] = A[k][k]
+  const double* rk = A + (size_t)k * n + (k + 1);
   double s = 0.0;
-  for (int i = 1 + (int)threadIdx.x; i < m; i += 256) s += x[i] * x[i];
-  const double sigma = block_sum256(s, red);
-  const double x0 = x[0];
+  for (int i = threadIdx.x; i < m; i += 256) {
+    double x = rk[i];
+    if (bp != 0.0) x -= vp[0] * wp[1 + i] + wp[0] * vp[1 + i];
+    vs[i] = x;
+    if (i >= 1) s += x * x;
+  }
+  const double sigma = block_sum256(s, red);  // (its barrier also publishes vs)
+  const double x0 = vs[0];
   double beta = 0.0, mu = x0, v0 = 1.0;
   if (sigma != 0.0) {
     mu = sqrt(x0 * x0 + sigma);
     v0 = x0 <= 0.0 ? x0 - mu : -sigma / (x0 + mu);
     beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
   }
-  for (int i = threadIdx.x; i < m; i += 256) vs[i] = i == 0 ? 1.0 : (sigma != 0.0 ? x[i] / v0 : 0.0);
+  __syncthreads();  // every thread has read vs[0]
+  for (int i = threadIdx.x; i < m; i += 256) vs[i] = i == 0 ? 1.0 : (sigma != 0.0 ? vs[i] / v0 : 0.0);
   __syncthreads();
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) {
+      double akk = A[(size_t)k * n + k];
+      if (bp != 0.0) akk -= vp[0] * wp[0] + wp[0] * vp[0];
       betas[k] = beta;
-      d[k] = A[(size_t)k * n + k];
+      d[k] = akk;
       e[k] = mu;
     }
     for (int i = 1 + (int)threadIdx.x; i < m; i += 256) H[(size_t)k * n + k + 1 + i] = vs[i];
   }
-  if (sigma == 0.0) return;  // already reduced in this column
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int r = blockIdx.x * 4 + wave; r < m; r += gridDim.x * 4) {
-    const double* row = A + (size_t)(k + 1 + r) * n + (k + 1);
-    double acc = 0.0;
-    for (int c = lane; c < m; c += 64) acc += row[c] * vs[c];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) p[r] = beta * acc;
-  }
-}
-
-__global__ void __launch_bounds__(256) house_update_kernel(double* __restrict__ A, int n, int k,
-                                                           const double* __restrict__ H,
-                                                           const double* __restrict__ betas,
-                                                           const double* __restrict__ p) {
-#pragma clang fp contract(off)  // (r, c) and (c, r) get the same bits: A stays symmetric
-  __shared__ double vs[kProjMax], ws[kProjMax];
-  __shared__ double red[4];
-  const double beta = betas[k];
-  if (beta == 0.0) return;
-  const int m = n - k - 1;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < m; i += 256) {
-    const double v = i == 0 ? 1.0 : H[(size_t)k * n + k + 1 + i];
-    vs[i] = v;
-    s += p[i] * v;
-  }
-  const double half = 0.5 * beta * block_sum256(s, red);
-  for (int i = threadIdx.x; i < m; i += 256) ws[i] = p[i] - half * vs[i];
-  __syncthreads();
+  // rows of step k's block: step k-1's update, then p_k = beta A22 v
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int r = blockIdx.x * 4 + wave; r < m; r += gridDim.x * 4) {
     double* row = A + (size_t)(k + 1 + r) * n + (k + 1);
-    const double vr = vs[r], wr = ws[r];
-    for (int c = lane; c < m; c += 64) row[c] -= vr * ws[c] + wr * vs[c];
+    double acc = 0.0;
+    if (bp != 0.0) {
+      const double vr = vp[1 + r], wr = wp[1 + r];
+      for (int c = lane; c < m; c += 64) {
+        const double a = row[c] - (vr * wp[1 + c] + wr * vp[1 + c]);
+        row[c] = a;
+        acc += a * vs[c];
+      }
+    } else {
+      for (int c = lane; c < m; c += 64) acc += row[c] * vs[c];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) p_out[r] = beta * acc;
   }
 }
 
-// The last 2 x 2 block of the reduced matrix.
-__global__ void house_tail_kernel(const double* __restrict__ A, int n, double* d, double* e) {
-  if (threadIdx.x == 0) {
-    d[n - 2] = A[(size_t)(n - 2) * n + (n - 2)];
-    d[n - 1] = A[(size_t)(n - 1) * n + (n - 1)];
-    e[n - 2] = A[(size_t)(n - 1) * n + (n - 2)];
-    e[n - 1] = 0.0;
+// After the last step (k = n - 3): its update of the final 2 x 2 block, and
+// that block's entries.
+__global__ void house_tail2_kernel(const double* __restrict__ A, int n, const double* __restrict__ H,
+                                   const double* __restrict__ betas, const double* __restrict__ p, double* d,
+                                   double* e) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0) return;
+  const int k = n - 3;
+  double a00 = A[(size_t)(n - 2) * n + (n - 2)], a11 = A[(size_t)(n - 1) * n + (n - 1)];
+  double a10 = A[(size_t)(n - 1) * n + (n - 2)];
+  const double b = k >= 0 ? betas[k] : 0.0;
+  if (b != 0.0) {
+    const double v0 = 1.0, v1 = H[(size_t)k * n + k + 2];
+    const double half = 0.5 * b * (p[0] * v0 + p[1] * v1);
+    const double w0 = p[0] - half * v0, w1 = p[1] - half * v1;
+    a00 -= v0 * w0 + w0 * v0;
+    a11 -= v1 * w1 + w1 * v1;
+    a10 -= v1 * w0 + w1 * v0;
   }
+  d[n - 2] = a00;
+  d[n - 1] = a11;
+  e[n - 2] = a10;
+  e[n - 1] = 0.0;
 }
 
 // Eigenvalue number j (ascending) of the symmetric tridiagonal (d, e2 = e^2)
@@ -599,7 +627,7 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
       EIG_TRY(hipMalloc(&dBeta.p, (size_t)cap * 8));
       EIG_TRY(hipMalloc(&dD.p, (size_t)cap * 8));
       EIG_TRY(hipMalloc(&dE.p, (size_t)cap * 8));
-      EIG_TRY(hipMalloc(&dP.p, (size_t)cap * 8));
+      EIG_TRY(hipMalloc(&dP.p, (size_t)2 * cap * 8));
       EIG_TRY(hipMalloc(&dXc.p, (size_t)cap * keep_n * 8));
       EIG_TRY(hipMalloc(&dEv.p, (size_t)(keep_n + 1) * 8));
     }
@@ -683,15 +711,16 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
         // smallest pairs on the host; back through the reflectors into dY
         double* A = dT.as<double>();
         hipLaunchKernelGGL(symmetrise_kernel, dim3(blocks_for((int64_t)cur * cur)), dim3(256), 0, s, A, cur);
+        double* pb[2] = {dP.as<double>(), dP.as<double>() + cap};  // p_{k-1} and p_k, alternating
         for (int kx = 0; kx + 2 < cur; ++kx) {
           const int g = std::min(256, (cur - kx - 1 + 3) / 4);
-          hipLaunchKernelGGL(house_symv_kernel, dim3(g), dim3(256), 0, s, (const double*)A, cur, kx,
-                             dH.as<double>(), dBeta.as<double>(), dD.as<double>(), dE.as<double>(), dP.as<double>());
-          hipLaunchKernelGGL(house_update_kernel, dim3(g), dim3(256), 0, s, A, cur, kx, (const double*)dH.as<double>(),
-                             (const double*)dBeta.as<double>(), (const double*)dP.as<double>());
+          hipLaunchKernelGGL(house_step_kernel, dim3(g), dim3(256), 0, s, A, cur, kx, dH.as<double>(),
+                             dBeta.as<double>(), dD.as<double>(), dE.as<double>(), (const double*)pb[(kx + 1) & 1],
+                             pb[kx & 1]);
         }
-        hipLaunchKernelGGL(house_tail_kernel, dim3(1), dim3(64), 0, s, (const double*)A, cur, dD.as<double>(),
-                           dE.as<double>());
+        hipLaunchKernelGGL(house_tail2_kernel, dim3(1), dim3(64), 0, s, (const double*)A, cur,
+                           (const double*)dH.as<double>(), (const double*)dBeta.as<double>(),
+                           (const double*)pb[(cur - 3) & 1], dD.as<double>(), dE.as<double>());
         EIG_TRY(hipGetLastError());
         std::vector<double> td(cur), te(cur), e2, Xc;
         EIG_TRY(hipMemcpyAsync(td.data(), dD.p, (size_t)cur * 8, hipMemcpyDeviceToHost, s));

@@ -1702,6 +1702,7 @@ struct msk_kelvin {
   int64_t n_nodes = 0;
   Node4* d_nodes = nullptr;
   KelvinTri* d_tris = nullptr;
+  KelvinPre* d_pre = nullptr;
 };
 
 namespace {
@@ -1860,7 +1861,10 @@ extern "C" msk_status msk_kelvin_create(msk_ctx* ctx, const msk_mesh* m, const d
   K->n_nodes = (int64_t)nodes.size();
   hipError_t he;
   if ((he = upload(ctx, &K->d_nodes, nodes.data(), nodes.size())) != hipSuccess ||
-      (he = upload(ctx, &K->d_tris, ordered.data(), ordered.size())) != hipSuccess) {
+      (he = upload(ctx, &K->d_tris, ordered.data(), ordered.size())) != hipSuccess ||
+      (he = dalloc(&K->d_pre, ordered.size())) != hipSuccess ||
+      (he = launch_kelvin_prepare(K->d_tris, (int64_t)ordered.size(), K->d_pre, ctx->stream)) != hipSuccess ||
+      (he = hipStreamSynchronize(ctx->stream)) != hipSuccess) {
     msk_kelvin_destroy(K);
     return fail(ctx, he == hipErrorOutOfMemory ? MSK_ERR_OOM : MSK_ERR_DEVICE,
                 std::string("inverted mesh upload: ") + hipGetErrorString(he));
@@ -1890,6 +1894,7 @@ extern "C" void msk_kelvin_destroy(msk_kelvin* K) {
   if (!K) return;
   dfree(K->d_nodes);
   dfree(K->d_tris);
+  dfree(K->d_pre);
   delete K;
 }
 
@@ -1898,6 +1903,7 @@ static KelvinDev kelvin_dev(const msk_kelvin* K, double eps, const msk_dtn_opts&
   std::memset(&D, 0, sizeof(D));
   D.nodes = K->d_nodes;
   D.tris = K->d_tris;
+  D.pre = K->d_pre;
   D.n_tris = K->mesh->nf;
   D.radius = K->radius;
   D.eps2 = eps * eps;

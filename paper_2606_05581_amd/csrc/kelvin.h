@@ -16,9 +16,32 @@ struct KelvinTri {
   int32_t has_plane;        // 0 for a (numerically) degenerate triangle: arcs only
 };
 static_assert(sizeof(KelvinTri) == 120, "inverted element record must be 120 bytes");
+// The part of an element's distance that does not depend on the query point,
+// per edge (a, b), (b, c), (c, a) from P to Q: e = Q - P, ee = |e|^2,
+// pqmax = max(|P|^2, |Q|^2), and by kind: 1, an arc (the line misses the
+// centre): m the unit normal of the plane (0, P, Q), c and rho the image
+// circle's centre and radius; 2, a straight segment (the line through the
+// centre): m = image(Q) - image(P), rho = |m|^2; 0, a degenerate edge (its
+// end points only).
+struct KelvinEdge {
+  double e[3];
+  double ee;
+  double m[3];
+  double c[3];
+  double rho;
+  double pqmax;
+  int32_t kind;
+  int32_t pad;
+};
+struct KelvinPre {
+  double k[3][3];       // images of the vertices a, b, c
+  KelvinEdge edge[3];
+};
+static_assert(sizeof(KelvinPre) == 384, "prepared element record must be 384 bytes");
 struct KelvinDev {
   const Node4* nodes;      // 4-wide hierarchy over boxes containing the inverted elements
   const KelvinTri* tris;
+  const KelvinPre* pre;    // prepared records, same order as tris
   int64_t n_tris;
   double radius;           // bound of the inverted domain (max |x~| on its boundary)
   double eps2;             // shell width squared (inverted units)
@@ -45,6 +68,8 @@ hipError_t launch_kelvin_walks(const KelvinDev& K, const double* st, const doubl
 // false for a numerically degenerate triangle.
 __host__ __device__ bool kelvin_plane(const double a[3], const double b[3], const double c[3], double n[3],
                                       double& cpl);
+// The prepared records of n elements (device arrays, leaf order).
+hipError_t launch_kelvin_prepare(const KelvinTri* tris, int64_t n, KelvinPre* pre, hipStream_t s);
 hipError_t launch_kelvin_closest(const KelvinDev& K, const double* Q, int64_t nq, int32_t* tri, double* d2,
                                  double* qpt, double* bary, hipStream_t s);
 

@@ -71,17 +71,49 @@ __host__ __device__ __forceinline__ void offer(Best& b, double d2, const double 
 // point nearest to x is the radial projection of x's in-plane position, and
 // it lies on the edge's arc when its image is between P and Q. A line
 // through the centre maps to itself: the arc is then the straight segment
-// between the end points' images. (ia, ib) are the edge's vertex slots.
-// FP64 operations are counted (kCount) as additions, multiplications,
-// divisions and square roots, one each, up to each exit: dot 5, cross 9,
-// inversion 9.
-template <bool kCount>
-__host__ __device__ void edge_image(const double x[3], const double P[3], const double Q[3], int ia, int ib, Best& b,
-                                    uint64_t& ops) {
+// between the end points' images. Everything that does not depend on x is
+// computed once per inverted mesh (edge_prepare, kelvin_prepare_kernel);
+// edge_eval does the rest, with the same operations in the same order as
+// one function evaluating both would. (ia, ib) are the edge's vertex slots.
+__host__ __device__ void edge_prepare(const double P[3], const double Q[3], KelvinEdge& E) {
 #pragma clang fp contract(off)
-  double kp[3], kq[3], d[3];
+  double kp[3], kq[3];
   invert(P, kp);
   invert(Q, kq);
+  for (int k = 0; k < 3; ++k) E.e[k] = Q[k] - P[k];
+  E.ee = dot(E.e, E.e);
+  E.kind = 0;
+  E.pad = 0;
+  for (int k = 0; k < 3; ++k) E.m[k] = E.c[k] = 0.0;
+  E.rho = 0.0;
+  E.pqmax = fmax(dot(P, P), dot(Q, Q));
+  if (!(E.ee > 0.0)) return;
+  const double tf = -dot(P, E.e) / E.ee;
+  const double f[3] = {P[0] + tf * E.e[0], P[1] + tf * E.e[1], P[2] + tf * E.e[2]};
+  const double ff = dot(f, f);
+  double m[3];
+  cross(P, Q, m);
+  const double mm = dot(m, m);
+  if (ff > 1e-24 * E.pqmax && mm > 0.0) {
+    E.kind = 1;
+    const double ml = 1.0 / sqrt(mm);
+    for (int k = 0; k < 3; ++k) E.m[k] = m[k] * ml;
+    for (int k = 0; k < 3; ++k) E.c[k] = f[k] / (2.0 * ff);
+    E.rho = 1.0 / (2.0 * sqrt(ff));
+  } else {
+    E.kind = 2;
+    for (int k = 0; k < 3; ++k) E.m[k] = kq[k] - kp[k];  // the segment's direction g
+    E.rho = dot(E.m, E.m);                               // |g|^2
+  }
+}
+
+// FP64 operations are counted (kCount) as additions, multiplications,
+// divisions and square roots, one each, up to each exit: dot 5, inversion 9.
+template <bool kCount>
+__host__ __device__ void edge_eval(const double x[3], const double P[3], const double kp[3], const double kq[3],
+                                   const KelvinEdge& E, int ia, int ib, Best& b, uint64_t& ops) {
+#pragma clang fp contract(off)
+  double d[3];
   double l[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < 3; ++k) d[k] = x[k] - kp[k];
   l[ia] = 1.0;
@@ -89,36 +121,25 @@ __host__ __device__ void edge_image(const double x[3], const double P[3], const 
   for (int k = 0; k < 3; ++k) d[k] = x[k] - kq[k];
   l[ia] = 0.0; l[ib] = 1.0;
   offer(b, dot(d, d), kq, l[0], l[1], l[2]);
-  const double e[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
-  const double ee = dot(e, e);
-  if constexpr (kCount) ops += 42;
-  if (!(ee > 0.0)) return;
-  const double tf = -dot(P, e) / ee;
-  const double f[3] = {P[0] + tf * e[0], P[1] + tf * e[1], P[2] + tf * e[2]};
-  const double ff = dot(f, f);
-  double m[3];
-  cross(P, Q, m);
-  const double mm = dot(m, m);
-  if constexpr (kCount) ops += 42;
-  if (ff > 1e-24 * fmax(dot(P, P), dot(Q, Q)) && mm > 0.0) {
-    const double ml = 1.0 / sqrt(mm);
-    for (int k = 0; k < 3; ++k) m[k] *= ml;
-    const double c[3] = {f[0] / (2.0 * ff), f[1] / (2.0 * ff), f[2] / (2.0 * ff)};
-    const double rho = 1.0 / (2.0 * sqrt(ff));
+  if constexpr (kCount) ops += 16;
+  if (E.kind == 0) return;
+  if (E.kind == 1) {
+    const double* m = E.m;
+    const double* c = E.c;
     const double mx = dot(m, x);
     const double u[3] = {x[0] - mx * m[0] - c[0], x[1] - mx * m[1] - c[1], x[2] - mx * m[2] - c[2]};
     const double ul = sqrt(dot(u, u));
-    if constexpr (kCount) ops += 32;
+    if constexpr (kCount) ops += 20;
     if (!(ul > 0.0)) return;
-    const double pt[3] = {c[0] + rho * u[0] / ul, c[1] + rho * u[1] / ul, c[2] + rho * u[2] / ul};
+    const double pt[3] = {c[0] + E.rho * u[0] / ul, c[1] + E.rho * u[1] / ul, c[2] + E.rho * u[2] / ul};
     // the origin is the image of the line's point at infinity: every point of
     // the segment's image lies at least 1 / max(|P|, |Q|) from it
     if constexpr (kCount) ops += 15;
-    if (!(dot(pt, pt) * fmax(dot(P, P), dot(Q, Q)) >= 1.0 - 1e-9)) return;
+    if (!(dot(pt, pt) * E.pqmax >= 1.0 - 1e-9)) return;
     double y[3];
     invert(pt, y);
     const double yd[3] = {y[0] - P[0], y[1] - P[1], y[2] - P[2]};
-    const double t = dot(yd, e) / ee;
+    const double t = dot(yd, E.e) / E.ee;
     if constexpr (kCount) ops += 18;
     if (t >= 0.0 && t <= 1.0) {
       if constexpr (kCount) ops += 9;
@@ -127,19 +148,19 @@ __host__ __device__ void edge_image(const double x[3], const double P[3], const 
       offer(b, dot(d, d), pt, l[0], l[1], l[2]);
     }
   } else {
-    const double g[3] = {kq[0] - kp[0], kq[1] - kp[1], kq[2] - kp[2]};
-    const double gg = dot(g, g);
+    const double* g = E.m;
+    const double gg = E.rho;
     double s = gg > 0.0 ? ((x[0] - kp[0]) * g[0] + (x[1] - kp[1]) * g[1] + (x[2] - kp[2]) * g[2]) / gg : 0.0;
     s = fmin(1.0, fmax(0.0, s));
     const double pt[3] = {kp[0] + s * g[0], kp[1] + s * g[1], kp[2] + s * g[2]};
     double y[3];
     invert(pt, y);
     const double yd[3] = {y[0] - P[0], y[1] - P[1], y[2] - P[2]};
-    const double t = dot(yd, e) / ee;
+    const double t = dot(yd, E.e) / E.ee;
     for (int k = 0; k < 3; ++k) d[k] = x[k] - pt[k];
     l[ia] = 1.0 - t; l[ib] = t;
     offer(b, dot(d, d), pt, l[0], l[1], l[2]);
-    if constexpr (kCount) ops += 50;
+    if constexpr (kCount) ops += 42;
   }
 }
 
@@ -177,8 +198,8 @@ __host__ __device__ bool kelvin_plane(const double a[3], const double b[3], cons
 // relative margin for rounding) the element cannot come nearer than bound and
 // INFINITY is returned without the boundary arcs.
 template <bool kCount>
-__host__ __device__ double kelvin_tri_d2_t(const double x[3], const KelvinTri& T, double q[3], double l[3],
-                                           double bound, uint64_t& ops) {
+__host__ __device__ double kelvin_tri_d2_t(const double x[3], const KelvinTri& T, const KelvinPre& R, double q[3],
+                                           double l[3], double bound, uint64_t& ops) {
 #pragma clang fp contract(off)
   Best b;
   b.d2 = INFINITY;
@@ -227,18 +248,34 @@ __host__ __device__ double kelvin_tri_d2_t(const double x[3], const KelvinTri& T
       }
     }
   }
-  edge_image<kCount>(x, T.a, T.b, 0, 1, b, ops);
-  edge_image<kCount>(x, T.b, T.c, 1, 2, b, ops);
-  edge_image<kCount>(x, T.c, T.a, 2, 0, b, ops);
+  edge_eval<kCount>(x, T.a, R.k[0], R.k[1], R.edge[0], 0, 1, b, ops);
+  edge_eval<kCount>(x, T.b, R.k[1], R.k[2], R.edge[1], 1, 2, b, ops);
+  edge_eval<kCount>(x, T.c, R.k[2], R.k[0], R.edge[2], 2, 0, b, ops);
   q[0] = b.q[0]; q[1] = b.q[1]; q[2] = b.q[2];
   l[0] = b.l[0]; l[1] = b.l[1]; l[2] = b.l[2];
   return b.d2;
 }
 
-__host__ __device__ double kelvin_tri_d2(const double x[3], const KelvinTri& T, double q[3], double l[3],
-                                         double bound) {
+__host__ __device__ double kelvin_tri_d2(const double x[3], const KelvinTri& T, const KelvinPre& R, double q[3],
+                                         double l[3], double bound) {
   uint64_t none = 0;
-  return kelvin_tri_d2_t<false>(x, T, q, l, bound, none);
+  return kelvin_tri_d2_t<false>(x, T, R, q, l, bound, none);
+}
+
+// The point-independent part of every element (leaf order): the images of
+// its vertices and its edges' constants.
+__global__ void kelvin_prepare_kernel(const KelvinTri* __restrict__ tris, int64_t n, KelvinPre* __restrict__ pre) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const KelvinTri& T = tris[s];
+  KelvinPre R;
+  invert(T.a, R.k[0]);
+  invert(T.b, R.k[1]);
+  invert(T.c, R.k[2]);
+  edge_prepare(T.a, T.b, R.edge[0]);
+  edge_prepare(T.b, T.c, R.edge[1]);
+  edge_prepare(T.c, T.a, R.edge[2]);
+  pre[s] = R;
 }
 
 // Work of the counting instantiation of the nearest search.
@@ -263,7 +300,7 @@ __host__ __device__ double kelvin_nearest_t(const KelvinDev& K, const double x[3
   if (slot >= 0) {
     const KelvinTri& T = K.tris[slot];
     if constexpr (kCount) ++work.elements;
-    best = kelvin_tri_d2_t<kCount>(x, T, q, l, best, work.ops);
+    best = kelvin_tri_d2_t<kCount>(x, T, K.pre[slot], q, l, best, work.ops);
     orig = T.orig;
     best_slot = slot;
   }
@@ -306,7 +343,7 @@ __host__ __device__ double kelvin_nearest_t(const KelvinDev& K, const double x[3
           const KelvinTri& T = K.tris[s];
           double qq[3], ll[3];
           if constexpr (kCount) ++work.elements;
-          const double d = kelvin_tri_d2_t<kCount>(x, T, qq, ll, best, work.ops);
+          const double d = kelvin_tri_d2_t<kCount>(x, T, K.pre[s], qq, ll, best, work.ops);
           if (d < best || (d == best && T.orig < orig)) {
             best = d;
             orig = T.orig;
@@ -380,7 +417,7 @@ __host__ __device__ bool kelvin_any_within(const KelvinDev& K, const double x[3]
         const int32_t first = -cc - 1;
         for (int32_t e = first; e < first + cn; ++e) {
           double qq[3], ll[3];
-          const double d2 = kelvin_tri_d2(x, K.tris[e], qq, ll, t2);
+          const double d2 = kelvin_tri_d2(x, K.tris[e], K.pre[e], qq, ll, t2);
           if (sqrt(d2) < t) return true;
         }
       } else if (sp < kStackDepth) {
@@ -615,6 +652,12 @@ hipError_t launch_kelvin_walks(const KelvinDev& K, const double* st, const doubl
     hipLaunchKernelGGL(kelvin_walk_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, K, st, nt, radius, n_rows,
                        pairs, u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries,
                        next_walk, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_kelvin_prepare(const KelvinTri* tris, int64_t n, KelvinPre* pre, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kelvin_prepare_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, tris, n, pre);
   return hipGetLastError();
 }
 

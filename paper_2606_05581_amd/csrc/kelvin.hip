@@ -24,6 +24,11 @@
 #ifndef MSK_KELVIN_WAVES_PER_EU
 #define MSK_KELVIN_WAVES_PER_EU 4
 #endif
+// the walks' launch: streaming (one hierarchy node per loop trip, 1) or one
+// whole search per loop trip (0)
+#ifndef MSK_KELVIN_STREAM
+#define MSK_KELVIN_STREAM 1
+#endif
 
 namespace msk {
 
@@ -438,6 +443,25 @@ __device__ __forceinline__ void frame(const double n[3], double e1[3], double e2
   e2[0] = b; e2[1] = sg + n[1] * n[1] * a; e2[2] = -n[1];
 }
 
+// The move of step k from x at squared distance d2 to the surface: a uniform
+// point of the sphere of radius d (1 - kappa) - delta, drawn from the Philox
+// block (row, walk, k, step purpose).
+__device__ __forceinline__ void kelvin_move(const KelvinDev& K, uint32_t row, uint32_t walk, int64_t k, double d2,
+                                            double x[3]) {
+#pragma clang fp contract(off)
+  const uint4 u = philox10(make_uint4(row, walk, (uint32_t)k, (kPurposeStep << 24) | (K.mesh_id & 0xFFFFFFu)),
+                           K.seed_lo, K.seed_hi);
+  const double u0 = unit_f(u.x), u1 = unit_f(u.y);
+  const double r = sqrt(d2) * (1.0 - K.kappa) - K.delta;
+  const double z = 1.0 - 2.0 * u0;
+  const double rxy = 2.0 * sqrt(u0 * (1.0 - u0));
+  double sp, cp;
+  sincospi(2.0 * u1, &sp, &cp);
+  x[0] += r * rxy * cp;
+  x[1] += r * rxy * sp;
+  x[2] += r * z;
+}
+
 // One step of Walk-on-Spheres in the inverted domain at x: the exact
 // nearest element; in the eps-shell the walk has hit (true), else x moves to
 // a uniform point of the sphere of radius d (1 - kappa) - delta, drawn from
@@ -457,17 +481,7 @@ __device__ bool kelvin_step(const KelvinDev& K, uint32_t row, uint32_t walk, int
     d2 = kelvin_nearest_t<kCount>(K, x, orig, q, l, work, warm);
   }
   if (d2 < K.eps2) return true;
-  const uint4 u = philox10(make_uint4(row, walk, (uint32_t)k, (kPurposeStep << 24) | (K.mesh_id & 0xFFFFFFu)),
-                           K.seed_lo, K.seed_hi);
-  const double u0 = unit_f(u.x), u1 = unit_f(u.y);
-  const double r = sqrt(d2) * (1.0 - K.kappa) - K.delta;
-  const double z = 1.0 - 2.0 * u0;
-  const double rxy = 2.0 * sqrt(u0 * (1.0 - u0));
-  double sp, cp;
-  sincospi(2.0 * u1, &sp, &cp);
-  x[0] += r * rxy * cp;
-  x[1] += r * rxy * sp;
-  x[2] += r * z;
+  kelvin_move(K, row, walk, k, d2, x);
   return false;
 }
 
@@ -609,6 +623,220 @@ kelvin_walk_kernel(
   }
 }
 
+// Streaming form of the same walks: every loop trip advances each searching
+// lane by one node of the hierarchy (the node's leaf elements tested by that
+// lane), so a lane whose search is long does not hold the others; a lane
+// whose search ends finishes its step at once (or its walk, logged as above,
+// and claims the next one). Each search visits the same nodes in the same
+// order as kelvin_nearest_t, from the same warm candidate, so walks and logs
+// are those of kelvin_walk_kernel.
+template <bool kCount>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MSK_KELVIN_WAVES_PER_EU)))
+kelvin_stream_kernel(
+    KelvinDev K, const double* __restrict__ st, const double* __restrict__ nt, const double* __restrict__ radius,
+    int64_t n_rows, int64_t pairs, double u0, int64_t n_kill, int32_t* __restrict__ log_status,
+    int32_t* __restrict__ log_tri, float* __restrict__ log_bary, int32_t* __restrict__ log_q, double* __restrict__ g,
+    unsigned long long* __restrict__ row_queries, unsigned long long* kill_queries, unsigned long long* next_walk,
+    unsigned long long* __restrict__ stats) {
+  const int64_t n_jump = n_rows * 2 * pairs, total = n_jump + n_kill;
+  KelvinWork work;
+  int64_t id = -1, i = -1, k = 0;
+  uint32_t row = 0, walk = 0;
+  double x[3] = {0.0, 0.0, 0.0}, q[3] = {0.0, 0.0, 0.0}, l[3] = {0.0, 0.0, 0.0};
+  int32_t orig = -1, warm = -1;
+  bool done = false;
+  // the search in progress (node < 0: none)
+  int32_t stk[kStackDepth];
+  double stl[kStackDepth];
+  int sp = 0;
+  int32_t node = -1, best_slot = -1;
+  double best = INFINITY;
+  auto search_begin = [&]() {
+    best = INFINITY;
+    orig = INT_MAX;
+    best_slot = -1;
+    if (warm >= 0) {
+      const KelvinTri& T = K.tris[warm];
+      if constexpr (kCount) ++work.elements;
+      best = kelvin_tri_d2_t<kCount>(x, T, K.pre[warm], q, l, best, work.ops);
+      orig = T.orig;
+      best_slot = warm;
+    }
+    sp = 0;
+    node = 0;
+  };
+  auto log_walk = [&](int32_t status, int32_t nq) {
+    log_status[id] = status;
+    log_tri[id] = orig;
+    log_bary[2 * id] = (float)l[1];
+    log_bary[2 * id + 1] = (float)l[2];
+    log_q[id] = nq;
+    g[id] = 1.0 / sqrt(dot(q, q));
+    if (i >= 0)
+      atomicAdd(row_queries + i, (unsigned long long)nq);
+    else
+      atomicAdd(kill_queries, (unsigned long long)nq);
+    id = -1;
+  };
+  // the answer of step k's search (squared distance d2): the walk hits, or
+  // moves and starts the next search (the step cap's final search at
+  // k = max_steps)
+  auto step_done = [&](double d2) {
+    if (k >= K.max_steps) {  // the cap's search
+      log_walk(kCapped, (int32_t)(K.max_steps + 1));
+      return;
+    }
+    if (d2 < K.eps2) {
+      log_walk(kHit, (int32_t)(k + 1));
+      return;
+    }
+    kelvin_move(K, row, walk, k, d2, x);
+    ++k;
+    search_begin();
+  };
+  while (true) {
+    // lanes without a walk claim the next one
+    while (id < 0 && !done) {
+      id = (int64_t)atomicAdd(next_walk, 1ull);
+      if (id >= total) {
+        id = -1;
+        done = true;
+        break;
+      }
+      k = 0;
+      orig = -1;
+      warm = -1;
+      if (id < n_jump) {
+        i = id / (2 * pairs);
+        const int64_t w = id - i * 2 * pairs;
+        const double r = radius[i];
+        if (!(r > 0.0)) {
+          log_status[id] = -1;
+          log_tri[id] = -1;
+          log_bary[2 * id] = log_bary[2 * id + 1] = 0.0f;
+          log_q[id] = 0;
+          g[id] = 0.0;
+          id = -1;
+          continue;
+        }
+        row = (uint32_t)i;
+        walk = (uint32_t)w;
+        const uint4 u = philox10(
+            make_uint4(row, (uint32_t)(w >> 1), 0u, (kPurposeBall << 24) | (K.mesh_id & 0xFFFFFFu)), K.seed_lo,
+            K.seed_hi);
+        const double xi = unit_f(u.x), eta = unit_f(u.y);
+        const double su = 1.0 / (1.0 / u0 - xi * (1.0 / u0 - 1.0));
+        const double ct = 1.0 - 2.0 * su * su, sn = 2.0 * su * sqrt(fmax(0.0, 1.0 - su * su));
+        double sp2, cp;
+        sincospi(2.0 * eta + ((w & 1) ? 1.0 : 0.0), &sp2, &cp);
+        const double n[3] = {nt[3 * i], nt[3 * i + 1], nt[3 * i + 2]};
+        double e1[3], e2[3];
+        frame(n, e1, e2);
+        for (int c3 = 0; c3 < 3; ++c3) {
+          const double c = st[3 * i + c3] - r * n[c3];
+          x[c3] = c + r * (ct * n[c3] + sn * (cp * e1[c3] + sp2 * e2[c3]));
+        }
+        search_begin();
+      } else {
+        i = -1;
+        row = 0xFFFFFFFFu;
+        walk = (uint32_t)(id - n_jump);
+        x[0] = x[1] = x[2] = 0.0;
+        if (K.origin_known && K.max_steps > 0) {  // the first step's shared answer
+          orig = K.origin_orig;
+          for (int c = 0; c < 3; ++c) {
+            q[c] = K.origin_q[c];
+            l[c] = K.origin_l[c];
+          }
+          best_slot = -1;
+          step_done(K.origin_d2);  // logs, or starts step 1's search
+        } else {
+          search_begin();
+        }
+      }
+    }
+    if (__ballot(id >= 0) == 0) break;  // no lane of the wavefront has a walk left
+    if (id < 0) continue;
+    // one node of this lane's search
+    {
+      const Node4& N = K.nodes[node];
+      double lb[4];
+      int32_t cc[4], cn[4];
+      if constexpr (kCount) {
+        ++work.nodes;
+        work.ops += 4 * 17;
+      }
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) {
+        const double gx = fmax(fmax((double)N.lox[c4] - x[0], x[0] - (double)N.hix[c4]), 0.0);
+        const double gy = fmax(fmax((double)N.loy[c4] - x[1], x[1] - (double)N.hiy[c4]), 0.0);
+        const double gz = fmax(fmax((double)N.loz[c4] - x[2], x[2] - (double)N.hiz[c4]), 0.0);
+        lb[c4] = gx * gx + gy * gy + gz * gz;
+        cc[c4] = N.child[c4];
+        cn[c4] = N.count[c4];
+      }
+#pragma unroll
+      for (int a = 1; a < 4; ++a)
+        for (int b = a; b > 0 && lb[b] < lb[b - 1]; --b) {
+          const double t = lb[b]; lb[b] = lb[b - 1]; lb[b - 1] = t;
+          const int32_t t1 = cc[b]; cc[b] = cc[b - 1]; cc[b - 1] = t1;
+          const int32_t t2 = cn[b]; cn[b] = cn[b - 1]; cn[b - 1] = t2;
+        }
+      int32_t next = -1;
+      double next_lb = 0.0;
+      for (int c4 = 0; c4 < 4; ++c4) {
+        if (!(lb[c4] <= best * (1.0 + 1e-12))) continue;
+        if (cc[c4] < 0 && cn[c4] > 0) {
+          const int32_t first = -cc[c4] - 1;
+          for (int32_t e = first; e < first + cn[c4]; ++e) {
+            const KelvinTri& T = K.tris[e];
+            double qq[3], ll[3];
+            if constexpr (kCount) ++work.elements;
+            const double d = kelvin_tri_d2_t<kCount>(x, T, K.pre[e], qq, ll, best, work.ops);
+            if (d < best || (d == best && T.orig < orig)) {
+              best = d;
+              orig = T.orig;
+              best_slot = e;
+              q[0] = qq[0]; q[1] = qq[1]; q[2] = qq[2];
+              l[0] = ll[0]; l[1] = ll[1]; l[2] = ll[2];
+            }
+          }
+        }
+      }
+      for (int c4 = 3; c4 >= 0; --c4) {
+        if (cc[c4] >= 0 && lb[c4] <= best * (1.0 + 1e-12)) {
+          if (next >= 0 && sp < kStackDepth) {
+            stk[sp] = next;
+            stl[sp] = next_lb;
+            ++sp;
+          }
+          next = cc[c4];
+          next_lb = lb[c4];
+        }
+      }
+      if (next < 0) {
+        while (sp > 0) {
+          --sp;
+          if (stl[sp] <= best * (1.0 + 1e-12)) {
+            next = stk[sp];
+            break;
+          }
+        }
+      }
+      node = next;
+    }
+    if (node < 0) {  // the search is answered
+      warm = best_slot;
+      step_done(best);
+    }
+  }
+  if constexpr (kCount) {
+    atomicAdd(stats, (unsigned long long)work.nodes);
+    atomicAdd(stats + 1, (unsigned long long)work.elements);
+    atomicAdd(stats + 2, (unsigned long long)work.ops);
+  }
+}
+
 // Nearest inverted element of each query point (inverted space, relative to
 // the centre).
 __global__ void kelvin_closest_kernel(KelvinDev K, const double* __restrict__ Q, int64_t nq, int32_t* __restrict__ tri,
@@ -644,6 +872,16 @@ hipError_t launch_kelvin_walks(const KelvinDev& K, const double* st, const doubl
   if (n <= 0) return hipSuccess;
   if (grid < 1) return hipErrorInvalidValue;
   const int64_t blocks = std::min<int64_t>(grid, (n + 255) / 256);
+#if MSK_KELVIN_STREAM
+  if (stats)
+    hipLaunchKernelGGL(kelvin_stream_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, K, st, nt, radius, n_rows,
+                       pairs, u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries,
+                       next_walk, stats);
+  else
+    hipLaunchKernelGGL(kelvin_stream_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, K, st, nt, radius,
+                       n_rows, pairs, u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries,
+                       next_walk, stats);
+#else
   if (stats)
     hipLaunchKernelGGL(kelvin_walk_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, K, st, nt, radius, n_rows,
                        pairs, u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries,
@@ -652,6 +890,7 @@ hipError_t launch_kelvin_walks(const KelvinDev& K, const double* st, const doubl
     hipLaunchKernelGGL(kelvin_walk_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, K, st, nt, radius, n_rows,
                        pairs, u0, n_kill, log_status, log_tri, log_bary, log_q, g, row_queries, kill_queries,
                        next_walk, stats);
+#endif
   return hipGetLastError();
 }
 

@@ -29,6 +29,11 @@
 #ifndef MSK_KELVIN_STREAM
 #define MSK_KELVIN_STREAM 1
 #endif
+// the streaming launch's leaf elements: tested across the wavefront (1) or
+// by each lane for its own search (0)
+#ifndef MSK_KELVIN_COOP
+#define MSK_KELVIN_COOP 1
+#endif
 
 namespace msk {
 
@@ -204,8 +209,9 @@ __host__ __device__ bool kelvin_plane(const double a[3], const double b[3], cons
 // INFINITY is returned without the boundary arcs.
 template <bool kCount>
 __host__ __device__ double kelvin_tri_d2_t(const double x[3], const KelvinTri& T, const KelvinPre& R, double q[3],
-                                           double l[3], double bound, uint64_t& ops) {
+                                           double l[3], double bound, uint64_t& ops, double* skip2 = nullptr) {
 #pragma clang fp contract(off)
+  if (skip2) *skip2 = -INFINITY;  // no plane: never skipped
   Best b;
   b.d2 = INFINITY;
   if (T.has_plane) {
@@ -218,12 +224,14 @@ __host__ __device__ double kelvin_tri_d2_t(const double x[3], const KelvinTri& T
       const double vl = sqrt(dot(v, v));
       const double sd = (fabs(c) * dot(x, x) - sg * dot(n, x)) / (vl + 0.5);
       if constexpr (kCount) ops += 32;
+      if (skip2) *skip2 = sd * sd;  // the value compared with the bound
       if (sd * sd > bound * (1.0 + 1e-9)) return INFINITY;
       for (int k = 0; k < 3; ++k) p[k] = x[k] - sd * sg * v[k] / vl;
       if constexpr (kCount) ops += 10;
     } else {
       const double nx = dot(n, x);
       if constexpr (kCount) ops += 7;
+      if (skip2) *skip2 = nx * nx;
       if (nx * nx > bound * (1.0 + 1e-9)) return INFINITY;
       for (int k = 0; k < 3; ++k) p[k] = x[k] - nx * n[k];
       if constexpr (kCount) ops += 6;
@@ -623,6 +631,40 @@ kelvin_walk_kernel(
   }
 }
 
+// The leaf elements a wavefront's searches reach in one loop trip, tested 64
+// at a time across its lanes: the list (element slot, owner lane), each
+// owner's query point and bound, and each test's result, in LDS.
+struct KelvinCoop {
+  double x[64][3];
+  double bound[64];
+  int32_t slot[64];
+  int32_t owner[64];
+  double rd[64], rk[64];  // distance, and the value its sphere (plane) skip compares with the bound
+  int32_t ro[64], rs[64];
+  double rq[64][3], rl[64][3];
+};
+
+// Orders a wavefront's LDS accesses as written (the hardware executes one
+// wavefront's LDS instructions in issue order; only the compiler must not
+// move them).
+__device__ __forceinline__ void kelvin_lds_order() { __asm__ __volatile__("" ::: "memory"); }
+
+// Exclusive prefix sum over the wavefront of a count below 64 (bit-sliced
+// ballots); `total` receives the wavefront's sum.
+__device__ __forceinline__ uint32_t kelvin_wave_prefix(uint32_t v, uint32_t& total) {
+  const uint32_t lane = __lane_id();
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    const uint64_t m = __ballot((v >> b) & 1u);
+    pre += (uint32_t)__popcll(m & below) << b;
+    tot += (uint32_t)__popcll(m) << b;
+  }
+  total = tot;
+  return pre;
+}
+
 // Streaming form of the same walks: every loop trip advances each searching
 // lane by one node of the hierarchy (the node's leaf elements tested by that
 // lane), so a lane whose search is long does not hold the others; a lane
@@ -639,6 +681,9 @@ kelvin_stream_kernel(
     unsigned long long* __restrict__ row_queries, unsigned long long* kill_queries, unsigned long long* next_walk,
     unsigned long long* __restrict__ stats) {
   const int64_t n_jump = n_rows * 2 * pairs, total = n_jump + n_kill;
+  __shared__ KelvinCoop coop[4];
+  KelvinCoop* C = &coop[threadIdx.x >> 6];
+  const uint32_t lane = __lane_id();
   KelvinWork work;
   int64_t id = -1, i = -1, k = 0;
   uint32_t row = 0, walk = 0;
@@ -756,12 +801,12 @@ kelvin_stream_kernel(
       }
     }
     if (__ballot(id >= 0) == 0) break;  // no lane of the wavefront has a walk left
-    if (id < 0) continue;
-    // one node of this lane's search
-    {
+    const bool srch = id >= 0;
+    // one node of each searching lane's search: its four child boxes, nearest first
+    double lb[4] = {0.0, 0.0, 0.0, 0.0};
+    int32_t cc[4] = {0, 0, 0, 0}, cn[4] = {0, 0, 0, 0};
+    if (srch) {
       const Node4& N = K.nodes[node];
-      double lb[4];
-      int32_t cc[4], cn[4];
       if constexpr (kCount) {
         ++work.nodes;
         work.ops += 4 * 17;
@@ -782,8 +827,100 @@ kelvin_stream_kernel(
           const int32_t t1 = cc[b]; cc[b] = cc[b - 1]; cc[b - 1] = t1;
           const int32_t t2 = cn[b]; cn[b] = cn[b - 1]; cn[b - 1] = t2;
         }
-      int32_t next = -1;
-      double next_lb = 0.0;
+    }
+#if MSK_KELVIN_COOP
+    // the leaf elements within the bound (the trip's starting bound: a test
+    // that a tighter bound would have cut short cannot win either), listed in
+    // the lane's order and tested 64 at a time by the whole wavefront; each
+    // owner then folds its results in that order
+    {
+      // the children listed, fixed before any fold tightens the bound
+      uint32_t nu = 0, qmask = 0;
+      if (srch)
+        for (int c4 = 0; c4 < 4; ++c4)
+          if (lb[c4] <= best * (1.0 + 1e-12) && cc[c4] < 0 && cn[c4] > 0) {
+            nu += (uint32_t)cn[c4];
+            qmask |= 1u << c4;
+          }
+      uint32_t total;
+      const uint32_t pre = kelvin_wave_prefix(nu, total);
+      bool child_ok = false;  // the fold's current child (carried over a round boundary)
+      if (total > 0) {
+        C->x[lane][0] = x[0];
+        C->x[lane][1] = x[1];
+        C->x[lane][2] = x[2];
+        C->bound[lane] = best;
+        for (uint32_t base = 0; base < total; base += 64) {
+          if (nu > 0) {
+            uint32_t pos = pre;
+            for (int c4 = 0; c4 < 4; ++c4) {
+              if (!((qmask >> c4) & 1u)) continue;
+              const int32_t first = -cc[c4] - 1;
+              for (int32_t e = first; e < first + cn[c4]; ++e, ++pos)
+                if (pos >= base && pos < base + 64) {
+                  C->slot[pos - base] = e;
+                  C->owner[pos - base] = (int32_t)lane;
+                }
+            }
+          }
+          kelvin_lds_order();
+          if (base + lane < total) {
+            const int32_t e = C->slot[lane];
+            const int32_t o = C->owner[lane];
+            const double xo[3] = {C->x[o][0], C->x[o][1], C->x[o][2]};
+            const KelvinTri& T = K.tris[e];
+            double qq[3], ll[3];
+            if constexpr (kCount) ++work.elements;
+            double k2;
+            const double d = kelvin_tri_d2_t<kCount>(xo, T, K.pre[e], qq, ll, C->bound[o], work.ops, &k2);
+            C->rd[lane] = d;
+            C->rk[lane] = k2;
+            C->ro[lane] = T.orig;
+            C->rs[lane] = e;
+            for (int c = 0; c < 3; ++c) {
+              C->rq[lane][c] = qq[c];
+              C->rl[lane][c] = ll[c];
+            }
+          }
+          kelvin_lds_order();
+          if (nu > 0) {
+            // the owner replays its lane-private order on these results: a
+            // child is entered only if its box is still within the bound, an
+            // element counts only if its sphere (plane) is (the tests ran with
+            // the trip's starting bound, which is never tighter), so the
+            // updates are exactly those of the lane-private search
+            uint32_t pos = pre;
+            for (int c4 = 0; c4 < 4; ++c4) {
+              if (!((qmask >> c4) & 1u)) continue;
+              const int32_t first = -cc[c4] - 1;
+              for (int32_t e = first; e < first + cn[c4]; ++e, ++pos) {
+                if (pos < base || pos >= base + 64) continue;
+                if (e == first) child_ok = lb[c4] <= best * (1.0 + 1e-12);
+                if (!child_ok) continue;
+                const uint32_t r = pos - base;
+                if (C->rk[r] > best * (1.0 + 1e-9)) continue;  // the lane-private test would have returned INFINITY
+                const double d = C->rd[r];
+                const int32_t o2 = C->ro[r];
+                if (d < best || (d == best && o2 < orig)) {
+                  best = d;
+                  orig = o2;
+                  best_slot = C->rs[r];
+                  for (int c = 0; c < 3; ++c) {
+                    q[c] = C->rq[r][c];
+                    l[c] = C->rl[r][c];
+                  }
+                }
+              }
+            }
+          }
+          kelvin_lds_order();
+        }
+      }
+    }
+#endif
+    if (!srch) continue;
+    {
+#if !MSK_KELVIN_COOP
       for (int c4 = 0; c4 < 4; ++c4) {
         if (!(lb[c4] <= best * (1.0 + 1e-12))) continue;
         if (cc[c4] < 0 && cn[c4] > 0) {
@@ -803,6 +940,9 @@ kelvin_stream_kernel(
           }
         }
       }
+#endif
+      int32_t next = -1;
+      double next_lb = 0.0;
       for (int c4 = 3; c4 >= 0; --c4) {
         if (cc[c4] >= 0 && lb[c4] <= best * (1.0 + 1e-12)) {
           if (next >= 0 && sp < kStackDepth) {

@@ -235,6 +235,30 @@ def test_kelvin_counting_kernel_runs_the_same_walks(ctx):
     assert 68 * nodes + 7 * elems <= ops <= 68 * nodes + 354 * elems
 
 
+def test_kelvin_leaf_width_changes_no_walk(ctx):
+    """The nearest-element search is exact, so the inverted hierarchy's leaf
+    width (elements per leaf) changes which nodes are visited but no walk: at
+    8 elements per leaf the wavefront's shared element tests list several
+    elements per child and often need more than one round of 64 per loop trip,
+    and the owners' replay must still give the one-element-per-leaf walks."""
+    V, F, tab = _sphere(3)
+    rows = W.point_rows(V, F, 200, np.random.default_rng(29))
+    mesh = ctx.build_bvh(V.astype(np.float32), F)
+    rh = ctx.rows(mesh, rows)
+    bh = ctx.basis(W.dense_basis(np.asarray(tab, dtype=np.float32)), V.shape[0])
+    c = np.array([0.15, 0.1, -0.05])
+    res = []
+    for leaf in (1, 8):
+        kv = ctx.kelvin(mesh, c, leaf_size=leaf)
+        eps = 1e-5 * kv.info()["radius"]
+        res.append(ctx.estimate_kelvin(kv, rh, bh, 16, 4096, eps, seed=13, log=True, collect_stats=1))
+    a, b = res
+    print(f"[kelvin leaf width] leaf 1: {a['info']['elements_tested']} element tests, leaf 8: "
+          f"{b['info']['elements_tested']}", flush=True)
+    for k in ("status", "tri", "bary", "nq", "radius", "S_jump", "S_kill"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_kelvin_parity_two_bodies(ctx, oracle_mod):
     V, F, tab = _two_bodies()
     rows = W.point_rows(V, F, 400, np.random.default_rng(23))

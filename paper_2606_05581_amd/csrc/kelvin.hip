@@ -499,26 +499,69 @@ __device__ bool kelvin_step(const KelvinDev& K, uint32_t row, uint32_t walk, int
 // normal n~_i pointing out of the domain): bisection over [0, r_max], a
 // radius accepted when the centre c = s~ - r n~ is at least r - min(tol,
 // r/1024) from the inverted surface and the ball lies within the domain's
-// bound. One lane per row; every step is an exact nearest query.
-__global__ void kelvin_tangent_kernel(KelvinDev K, const double* __restrict__ st, const double* __restrict__ nt,
-                                      int64_t n_rows, double r_max, int32_t iters, double tol,
-                                      double* __restrict__ radius, unsigned long long* __restrict__ queries) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_rows) return;
-  const double s[3] = {st[3 * i], st[3 * i + 1], st[3 * i + 2]};
-  const double n[3] = {nt[3 * i], nt[3 * i + 1], nt[3 * i + 2]};
-  double lo = 0.0, hi = r_max;
-  for (int32_t it = 0; it < iters; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    const double c[3] = {s[0] - mid * n[0], s[1] - mid * n[1], s[2] - mid * n[2]};
-    const double t = mid - fmin(tol, mid * (1.0 / 1024.0));
-    if (sqrt(dot(c, c)) + mid <= K.radius && !kelvin_any_within(K, c, t))
-      lo = mid;
-    else
-      hi = mid;
+// bound. Three levels per round: the eight lanes of a row evaluate the (up
+// to) seven midpoints of the next three levels at once (lane k takes heap
+// node k of that subtree: node 1 the current midpoint, nodes 2k and 2k + 1
+// the midpoints of its halves), then all follow the path the sequential
+// bisection takes through them. Every midpoint is formed by the operations of
+// the sequential loop, so the radius is that loop's; the rounds of dependent
+// searches drop from iters to ceil(iters / 3), and eight lanes per row fill
+// the GPU. queries[i] counts the iters decisions.
+__global__ void __launch_bounds__(64) kelvin_tangent_kernel(KelvinDev K, const double* __restrict__ st,
+                                                            const double* __restrict__ nt, int64_t n_rows,
+                                                            double r_max, int32_t iters, double tol,
+                                                            double* __restrict__ radius,
+                                                            unsigned long long* __restrict__ queries) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & 63, sub = lane & 7, gbase = lane & ~7;
+  // eight rows per 64-lane workgroup; the loop bound is uniform over the
+  // workgroup, so every lane takes part in every ballot
+  for (int64_t base = (int64_t)blockIdx.x * 8; base < n_rows; base += (int64_t)gridDim.x * 8) {
+    const int64_t i = base + (threadIdx.x >> 3);
+    const bool valid = i < n_rows;
+    double s[3] = {0.0, 0.0, 0.0}, n[3] = {0.0, 0.0, 0.0};
+    if (valid)
+      for (int c = 0; c < 3; ++c) {
+        s[c] = st[3 * i + c];
+        n[c] = nt[3 * i + c];
+      }
+    double lo = 0.0, hi = r_max;
+    for (int32_t done = 0; done < iters;) {
+      const int levels = min(3, iters - done);
+      bool res = false;
+      if (valid && sub >= 1 && sub < (1 << levels)) {
+        double a = lo, b = hi;
+        const int depth = 31 - __clz(sub);  // bits of the node index below its leading one
+        for (int j = depth - 1; j >= 0; --j) {
+          const double m = 0.5 * (a + b);
+          if ((sub >> j) & 1)
+            a = m;
+          else
+            b = m;
+        }
+        const double mid = 0.5 * (a + b);
+        const double c[3] = {s[0] - mid * n[0], s[1] - mid * n[1], s[2] - mid * n[2]};
+        const double t = mid - fmin(tol, mid * (1.0 / 1024.0));
+        res = sqrt(dot(c, c)) + mid <= K.radius && !kelvin_any_within(K, c, t);
+      }
+      const unsigned long long mask = __ballot(res);  // every lane of the wavefront takes part
+      int node = 1;
+      for (int l = 0; l < levels; ++l) {
+        const double mid = 0.5 * (lo + hi);
+        const int bit = (int)((mask >> (gbase + node)) & 1ull);
+        if (bit)
+          lo = mid;
+        else
+          hi = mid;
+        node = 2 * node + bit;
+      }
+      done += levels;
+    }
+    if (valid && sub == 0) {
+      radius[i] = lo;
+      queries[i] = (unsigned long long)iters;
+    }
   }
-  radius[i] = lo;
-  queries[i] = (unsigned long long)iters;
 }
 
 // Walks [0, n_rows 2 pairs) are the jump term's: walk 2j + a of row i starts
@@ -998,8 +1041,9 @@ hipError_t launch_kelvin_tangent(const KelvinDev& K, const double* st, const dou
                                  int32_t iters, double tol, double* radius, unsigned long long* queries,
                                  hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kelvin_tangent_kernel, dim3((unsigned)((n_rows + 63) / 64)), dim3(64), 0, s, K, st, nt, n_rows,
-                     r_max, iters, tol, radius, queries);
+  const int64_t blocks = std::min<int64_t>((n_rows + 7) / 8, 1 << 20);  // eight rows per 64-lane workgroup
+  hipLaunchKernelGGL(kelvin_tangent_kernel, dim3((unsigned)blocks), dim3(64), 0, s, K, st, nt, n_rows, r_max, iters,
+                     tol, radius, queries);
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@
 
 #include "msk_internal.h"
 #include "eigen.h"
+#include "philox.h"
 
 namespace msk {
 
@@ -442,32 +443,71 @@ __global__ void house_tail2_kernel(const double* __restrict__ A, int n, const do
 // Eigenvalue number j (ascending) of the symmetric tridiagonal (d, e2 = e^2)
 // by bisection on the Sturm count (the negative pivots of the LDL^T
 // factorisation of T - x I; a pivot below pivmin in magnitude taken as
-// -pivmin) until the interval is at most atol wide; one thread per target:
-// targets 0..m-1, and target m is the largest (index n - 1). The host's
-// bisection performs the same operations.
-__global__ void sturm_bisect_kernel(int n, const double* __restrict__ d, const double* __restrict__ e2, int m,
-                                    double glo, double ghi, double atol, double pivmin, double* __restrict__ out) {
+// -pivmin) until the interval is at most atol wide; targets 0..m-1, and
+// target m is the largest (index n - 1). Eight lanes per target, three
+// levels per round: lane k (1..7) counts at heap node k's midpoint of the
+// next three levels (formed by the sequential loop's operations), then the
+// group follows the sequential bisection's path through them, stopping where
+// it would. So the result is the host's bisection's, with a third of the
+// dependent counts.
+__global__ void __launch_bounds__(64) sturm_bisect_kernel(int n, const double* __restrict__ d,
+                                                          const double* __restrict__ e2, int m, double glo, double ghi,
+                                                          double atol, double pivmin, double* __restrict__ out) {
 #pragma clang fp contract(off)
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > m) return;
+  const int lane = threadIdx.x & 63, sub = lane & 7, gbase = lane & ~7;
+  const int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
+  const bool valid = t <= m;
   const int j = t < m ? t : n - 1;
   double lo = glo, hi = ghi;
-  for (int it = 0; it < 200 && hi - lo > atol; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    double q = d[0] - mid;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int c = q < 0.0;
-    for (int i = 1; i < n; ++i) {
-      q = (d[i] - mid) - e2[i - 1] / q;
+  for (int it = 0; it < 200;) {
+    // uniform over the wavefront: every lane takes part in every ballot
+    if (__ballot(valid && hi - lo > atol) == 0) break;
+    bool res = false;
+    if (valid && sub >= 1 && hi - lo > atol) {
+      double a = lo, b = hi;
+      const int depth = 31 - __clz(sub);
+      for (int k = depth - 1; k >= 0; --k) {
+        const double mm = 0.5 * (a + b);
+        if ((sub >> k) & 1)
+          a = mm;
+        else
+          b = mm;
+      }
+      const double mid = 0.5 * (a + b);
+      double q = d[0] - mid;
       if (fabs(q) < pivmin) q = -pivmin;
-      c += q < 0.0;
+      int c = q < 0.0;
+      for (int i = 1; i < n; ++i) {
+        q = (d[i] - mid) - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0;
+      }
+      res = c <= j;  // the sequential step would move lo up to this midpoint
     }
-    if (c <= j)
-      lo = mid;
-    else
-      hi = mid;
+    const unsigned long long mask = __ballot(res);
+    int node = 1;
+    for (int l = 0; l < 3 && it < 200 && hi - lo > atol; ++l, ++it) {
+      const double mid = 0.5 * (lo + hi);
+      const int bit = (int)((mask >> (gbase + node)) & 1ull);
+      if (bit)
+        lo = mid;
+      else
+        hi = mid;
+      node = 2 * node + bit;
+    }
   }
-  out[t] = 0.5 * (lo + hi);
+  if (valid && sub == 0) out[t] = 0.5 * (lo + hi);
+}
+
+// A block of standard normal numbers for the Krylov start: entry t from
+// the Philox block (t lo, t hi, 0, 7 << 24) of the key (seed lo, seed hi),
+// its first two words as uniforms of (0, 1) by Box-Muller.
+__global__ void normal_block_kernel(double* __restrict__ X, int64_t count, uint32_t seed_lo, uint32_t seed_hi) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+    const uint4 r = philox10(make_uint4((uint32_t)t, (uint32_t)((uint64_t)t >> 32), 0u, 7u << 24), seed_lo, seed_hi);
+    const double u1 = ((double)r.x + 0.5) * 0x1p-32, u2 = ((double)r.y + 0.5) * 0x1p-32;
+    X[t] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+  }
 }
 
 // Partial sums of the squared Ritz residuals: part[g][j] = sum over the rows
@@ -795,13 +835,10 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
       ok = true;
       return 0;
     };
-    // random start block (host RNG, fixed seed)
+    // random start block (on the device, fixed seed)
     {
-      std::mt19937_64 rng(12345);
-      std::normal_distribution<double> nd;
-      std::vector<double> X0((size_t)n * b);
-      for (auto& x : X0) x = nd(rng);
-      EIG_TRY(hipMemcpyAsync(X, X0.data(), X0.size() * 8, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(normal_block_kernel, dim3(blocks_for(n * b)), dim3(256), 0, s, X, n * (int64_t)b, 12345u, 0u);
+      EIG_TRY(hipGetLastError());
       bool ok;
       int rc = add_block(ok);
       if (rc) return rc;
@@ -852,7 +889,7 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
         double glo, ghi, pivmin, atol;
         bisect_setup(cur, td, te, e2, glo, ghi, pivmin, atol);
         EIG_TRY(hipMemcpyAsync(dP.p, e2.data(), e2.size() * 8, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(sturm_bisect_kernel, dim3((kk + 1 + 63) / 64), dim3(64), 0, s, cur,
+        hipLaunchKernelGGL(sturm_bisect_kernel, dim3((8 * (kk + 1) + 63) / 64), dim3(64), 0, s, cur,
                            (const double*)dD.as<double>(), (const double*)dP.as<double>(), kk, glo, ghi, atol, pivmin,
                            dEv.as<double>());
         EIG_TRY(hipGetLastError());

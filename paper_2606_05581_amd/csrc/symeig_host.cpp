@@ -447,60 +447,69 @@ bool tridiag_vectors(int n, const std::vector<double>& d, const std::vector<doub
   // makes the whole requested range one cluster and the work k^2 n.)
   const double ortol = 1e-6 * tnorm;
   Xc.assign((size_t)n * m, 0.0);  // eigenvectors of T, vector j at Xc[j * n + r]
-  std::vector<double> y(n), x(n), dots;
-  TriLU f;
-  uint64_t seed = 0x9E3779B97F4A7C15ull;
-  int cluster_start = 0;
-  double sigma_prev = 0.0;
-  for (int j = 0; j < m; ++j) {
-    if (j > 0 && evals[j] - evals[j - 1] > ortol) cluster_start = j;
-    // separate equal shifts inside a cluster slightly
-    double sigma = evals[j];
-    if (j > cluster_start && sigma <= sigma_prev + 10.0 * eps * tnorm) sigma = sigma_prev + 10.0 * eps * tnorm;
-    sigma_prev = sigma;
-    tridiag_lu(n, d, e, sigma, eps * tnorm, f);
-    for (int r = 0; r < n; ++r) {  // pseudo-random start
-      seed ^= seed << 13; seed ^= seed >> 7; seed ^= seed << 17;
-      y[r] = (double)(seed >> 11) * 0x1p-53 - 0.5;
-    }
-    for (int it = 0; it < 4; ++it) {
-      x = y;
-      tridiag_solve(n, f, x);
-      // classical Gram-Schmidt inside the cluster, twice: the projections
-      // are independent (a pool task each), then one update per entry
-      const int nc = j - cluster_start;
-      for (int pass = 0; pass < 2 && nc > 0; ++pass) {
-        dots.assign(nc, 0.0);
-        parallel_rows(nc, 16, [&](int lo, int hi) {
-          for (int i = lo; i < hi; ++i) {
-            const double* xi = &Xc[(size_t)(cluster_start + i) * n];
-            double s0 = 0.0, s1 = 0.0;
-            int r = 0;
-            for (; r + 1 < n; r += 2) {
-              s0 += xi[r] * x[r];
-              s1 += xi[r + 1] * x[r + 1];
+  // clusters [cs[c], cs[c + 1]): independent of each other, so they are pool
+  // tasks; each vector's pseudo-random start depends on its index only
+  std::vector<int> cs(1, 0);
+  for (int j = 1; j < m; ++j)
+    if (evals[j] - evals[j - 1] > ortol) cs.push_back(j);
+  cs.push_back(m);
+  const int ncl = (int)cs.size() - 1;
+  std::atomic<bool> good{true};
+  parallel_rows(ncl, 1, [&](int c0, int c1) {
+    std::vector<double> y(n), x(n), dots;
+    TriLU f;
+    for (int cl = c0; cl < c1 && good.load(); ++cl) {
+      const int cluster_start = cs[cl];
+      double sigma_prev = 0.0;
+      for (int j = cluster_start; j < cs[cl + 1]; ++j) {
+        // separate equal shifts inside a cluster slightly
+        double sigma = evals[j];
+        if (j > cluster_start && sigma <= sigma_prev + 10.0 * eps * tnorm) sigma = sigma_prev + 10.0 * eps * tnorm;
+        sigma_prev = sigma;
+        tridiag_lu(n, d, e, sigma, eps * tnorm, f);
+        uint64_t seed = 0x9E3779B97F4A7C15ull * (uint64_t)(j + 1) + 0xD1B54A32D192ED03ull;
+        for (int r = 0; r < n; ++r) {  // pseudo-random start (xorshift)
+          seed ^= seed << 13; seed ^= seed >> 7; seed ^= seed << 17;
+          y[r] = (double)(seed >> 11) * 0x1p-53 - 0.5;
+        }
+        for (int it = 0; it < 4; ++it) {
+          x = y;
+          tridiag_solve(n, f, x);
+          // classical Gram-Schmidt against the cluster's earlier vectors, twice
+          const int nc = j - cluster_start;
+          for (int pass = 0; pass < 2 && nc > 0; ++pass) {
+            dots.assign(nc, 0.0);
+            for (int i = 0; i < nc; ++i) {
+              const double* xi = &Xc[(size_t)(cluster_start + i) * n];
+              double s0 = 0.0, s1 = 0.0;
+              int r = 0;
+              for (; r + 1 < n; r += 2) {
+                s0 += xi[r] * x[r];
+                s1 += xi[r + 1] * x[r + 1];
+              }
+              for (; r < n; ++r) s0 += xi[r] * x[r];
+              dots[i] = s0 + s1;
             }
-            for (; r < n; ++r) s0 += xi[r] * x[r];
-            dots[i] = s0 + s1;
+            for (int i = 0; i < nc; ++i) {
+              const double* xi = &Xc[(size_t)(cluster_start + i) * n];
+              const double dt = dots[i];
+              for (int r = 0; r < n; ++r) x[r] -= dt * xi[r];
+            }
           }
-        });
-        parallel_rows(n, 256, [&](int lo, int hi) {
-          for (int i = 0; i < nc; ++i) {
-            const double* xi = &Xc[(size_t)(cluster_start + i) * n];
-            const double dt = dots[i];
-            for (int r = lo; r < hi; ++r) x[r] -= dt * xi[r];
+          double nrm = 0.0;
+          for (double t : x) nrm += t * t;
+          nrm = std::sqrt(nrm);
+          if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+            good.store(false);
+            return;
           }
-        });
+          for (int r = 0; r < n; ++r) y[r] = x[r] / nrm;
+        }
+        std::copy(y.begin(), y.end(), Xc.begin() + (size_t)j * n);
       }
-      double nrm = 0.0;
-      for (double t : x) nrm += t * t;
-      nrm = std::sqrt(nrm);
-      if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
-      for (int r = 0; r < n; ++r) y[r] = x[r] / nrm;
     }
-    std::copy(y.begin(), y.end(), Xc.begin() + (size_t)j * n);
-  }
-  return true;
+  });
+  return good.load();
 }
 
 // The m smallest eigenpairs of a symmetric A (n x n, row-major; destroyed):

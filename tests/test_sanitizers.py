@@ -3,7 +3,7 @@
 The oracle (oracle/oracle.c) and the library's host-side code that runs
 without a device (the BVH builder, the dense symmetric eigensolvers of the
 eigen step) are compiled with gcc/g++ -fsanitize=address,undefined and
-driven on small inputs by tests/sanitize/*; any report aborts the driver.
+driven on small inputs by tests/sanitize/*; any report aborts the test program.
 The library's C ABI itself (capi.cpp) needs a device for nearly every call
 and is not covered here."""
 import os

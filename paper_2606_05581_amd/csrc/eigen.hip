@@ -196,61 +196,112 @@ __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t
       }
 }
 
-// The tall, skinny FP32 product of the Krylov steps, A (M x K, row-major: the
-// FP32 copy of C) times B (K x N, row-major, N <= 64: a block of vectors):
-// a 128 x 64 output tile per workgroup (4 wavefronts of 32 rows, each 2 x 4
-// blocks of the 16x16x4 MFMA), K in steps of 32 read with 16-byte loads
-// (lda, ldb and N multiples of 4, A and B 16-byte aligned); the next step's
-// tiles are fetched into registers while the current ones are multiplied
-// out of LDS. Output as gemm_kernel's (split-K partials or C).
-__global__ void __launch_bounds__(256) gemm_tall_f32_kernel(int64_t M, int N, int64_t K, int64_t kchunk, float alpha,
-                                                            const float* __restrict__ A, int64_t lda,
-                                                            const float* __restrict__ B, int64_t ldb, float beta,
-                                                            float* Cm, int64_t ldc, float* __restrict__ part) {
-  constexpr int BM = 128, BK = 32;
-  __shared__ __align__(16) float As[BK][BM + 4];
-  __shared__ __align__(16) float Bs[BK][64 + 4];  // rows of 272 B: 16-byte stores stay aligned
+// Tall products of the Krylov steps on the matrix cores: A (M x K, or K x M
+// when TA) times B (K x N, row-major) with large M and K. A 128 x 64 output
+// tile per workgroup (4 wavefronts of 32 rows, each 2 x 4 blocks of the
+// 16x16x4 MFMA); K in steps of 32 (FP32) or 16 (FP64) read with 16-byte
+// loads (leading dimensions multiples of 16 bytes, A and B 16-byte aligned);
+// the next step's tiles are fetched into registers while the current ones
+// are multiplied out of LDS. Output as gemm_kernel's (split-K partials or C).
+template <typename T>
+struct TallCfg;
+template <>
+struct TallCfg<float> {
+  typedef float4 Vec;  // 16-byte load
+  static constexpr int kW = 4, kBK = 32, kPad = 4;
+};
+template <>
+struct TallCfg<double> {
+  typedef double2 Vec;
+  static constexpr int kW = 2, kBK = 16, kPad = 2;
+};
+
+template <typename T>
+__device__ __forceinline__ T vec_get(const typename TallCfg<T>::Vec& v, int c);
+template <>
+__device__ __forceinline__ float vec_get<float>(const float4& v, int c) {
+  return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
+template <>
+__device__ __forceinline__ double vec_get<double>(const double2& v, int c) {
+  return c == 0 ? v.x : v.y;
+}
+
+template <typename T, bool TA>
+__global__ void __launch_bounds__(256) gemm_tall_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk, T alpha,
+                                                        const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                                                        int64_t ldb, T beta, T* Cm, int64_t ldc, T* __restrict__ part) {
+  typedef typename TallCfg<T>::Vec Vec;
+  constexpr int W = TallCfg<T>::kW, BK = TallCfg<T>::kBK, PAD = TallCfg<T>::kPad, BM = 128, BN = 64;
+  // per thread: 4 vectors of the A tile (BM x BK) and 2 of the B tile (BK x BN)
+  static_assert(BM * BK == 4 * 256 * W && BK * BN == 2 * 256 * W, "tile loads");
+  __shared__ __align__(16) T As[BK][BM + PAD];
+  __shared__ __align__(16) T Bs[BK][BN + PAD];  // rows a multiple of 16 bytes: vector stores stay aligned
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
   const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   const int wm = 32 * wv;
-  mfma_f4 acc[2][4];
+  typename Mfma<T>::V acc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.0f;
-  float4 ra[4], rb[2];
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = T(0);
+  Vec ra[4], rb[2];
+  // which tile entries a thread's vector r holds
+  auto a_pos = [&](int r, int& mm, int& kk) {
+    const int idx = tid + 256 * r;
+    if (TA) {  // rows of k, BM / W vectors each
+      kk = idx / (BM / W);
+      mm = W * (idx % (BM / W));
+    } else {  // rows of m, BK / W vectors each
+      mm = idx / (BK / W);
+      kk = W * (idx % (BK / W));
+    }
+  };
+  auto b_pos = [&](int r, int& kk, int& nn) {
+    const int idx = tid + 256 * r;
+    kk = idx / (BN / W);
+    nn = W * (idx % (BN / W));
+  };
   auto fetch = [&](int64_t k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {  // A: 128 rows x 8 quads of k
-      const int idx = tid + 256 * r, m = idx >> 3, kq = idx & 7;
-      const int64_t gm = m0 + m, gk = k0 + 4 * kq;
-      if (gm < M && gk + 3 < ke) {
-        ra[r] = *reinterpret_cast<const float4*>(A + gm * lda + gk);
-      } else {
-        const float* a = A + gm * lda;
-        ra[r].x = gm < M && gk < ke ? a[gk] : 0.0f;
-        ra[r].y = gm < M && gk + 1 < ke ? a[gk + 1] : 0.0f;
-        ra[r].z = gm < M && gk + 2 < ke ? a[gk + 2] : 0.0f;
-        ra[r].w = gm < M && gk + 3 < ke ? a[gk + 3] : 0.0f;
+    for (int r = 0; r < 4; ++r) {
+      int mm, kk;
+      a_pos(r, mm, kk);
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      T v[W];
+      if (TA) {  // W consecutive m of row gk
+        if (gk < ke && gm + W - 1 < M) {
+          ra[r] = *reinterpret_cast<const Vec*>(A + gk * lda + gm);
+          continue;
+        }
+#pragma unroll
+        for (int c = 0; c < W; ++c) v[c] = gk < ke && gm + c < M ? A[gk * lda + gm + c] : T(0);
+      } else {  // W consecutive k of row gm
+        if (gm < M && gk + W - 1 < ke) {
+          ra[r] = *reinterpret_cast<const Vec*>(A + gm * lda + gk);
+          continue;
+        }
+#pragma unroll
+        for (int c = 0; c < W; ++c) v[c] = gm < M && gk + c < ke ? A[gm * lda + gk + c] : T(0);
       }
+      ra[r] = *reinterpret_cast<const Vec*>(v);
     }
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {  // B: 32 rows of k x 16 quads of n
-      const int idx = tid + 256 * r, kk = idx >> 4, nq = idx & 15;
-      const int64_t gk = k0 + kk;
-      const int gn = 4 * nq;
-      if (gk < ke && gn + 3 < N) {
-        rb[r] = *reinterpret_cast<const float4*>(B + gk * ldb + gn);
-      } else {
-        const float* b = B + gk * ldb;
-        rb[r].x = gk < ke && gn < N ? b[gn] : 0.0f;
-        rb[r].y = gk < ke && gn + 1 < N ? b[gn + 1] : 0.0f;
-        rb[r].z = gk < ke && gn + 2 < N ? b[gn + 2] : 0.0f;
-        rb[r].w = gk < ke && gn + 3 < N ? b[gn + 3] : 0.0f;
+    for (int r = 0; r < 2; ++r) {
+      int kk, nn;
+      b_pos(r, kk, nn);
+      const int64_t gk = k0 + kk, gn = n0 + nn;
+      if (gk < ke && gn + W - 1 < N) {
+        rb[r] = *reinterpret_cast<const Vec*>(B + gk * ldb + gn);
+        continue;
       }
+      T v[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) v[c] = gk < ke && gn + c < N ? B[gk * ldb + gn + c] : T(0);
+      rb[r] = *reinterpret_cast<const Vec*>(v);
     }
   };
   if (kb < ke) fetch(kb);
@@ -258,23 +309,27 @@ __global__ void __launch_bounds__(256) gemm_tall_f32_kernel(int64_t M, int N, in
     __syncthreads();  // the previous step's reads of As and Bs are done
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int idx = tid + 256 * r, m = idx >> 3, kq = idx & 7;
-      As[4 * kq][m] = ra[r].x;
-      As[4 * kq + 1][m] = ra[r].y;
-      As[4 * kq + 2][m] = ra[r].z;
-      As[4 * kq + 3][m] = ra[r].w;
+      int mm, kk;
+      a_pos(r, mm, kk);
+      if (TA) {
+        *reinterpret_cast<Vec*>(&As[kk][mm]) = ra[r];
+      } else {
+#pragma unroll
+        for (int c = 0; c < W; ++c) As[kk + c][mm] = vec_get<T>(ra[r], c);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      const int idx = tid + 256 * r, kk = idx >> 4, nq = idx & 15;
-      *reinterpret_cast<float4*>(&Bs[kk][4 * nq]) = rb[r];
+      int kk, nn;
+      b_pos(r, kk, nn);
+      *reinterpret_cast<Vec*>(&Bs[kk][nn]) = rb[r];
     }
     __syncthreads();
     if (k0 + BK < ke) fetch(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kk = ks + (lane >> 4);
-      float a[2], b[4];
+      T a[2], b[4];
 #pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = As[kk][wm + 16 * i + (lane & 15)];
 #pragma unroll
@@ -282,7 +337,7 @@ __global__ void __launch_bounds__(256) gemm_tall_f32_kernel(int64_t M, int N, in
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<float>::step(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::step(a[i], b[j], acc[i][j]);
     }
   }
 #pragma unroll
@@ -291,14 +346,13 @@ __global__ void __launch_bounds__(256) gemm_tall_f32_kernel(int64_t M, int N, in
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t gm = m0 + wm + 16 * i + Mfma<float>::row(lane, e);
-        const int gn = 16 * j + (lane & 15);
+        const int64_t gm = m0 + wm + 16 * i + Mfma<T>::row(lane, e), gn = n0 + 16 * j + (lane & 15);
         if (gm >= M || gn >= N) continue;
         if (part) {
           part[((int64_t)blockIdx.z * M + gm) * N + gn] = acc[i][j][e];
         } else {
-          float* c = Cm + gm * ldc + gn;
-          *c = alpha * acc[i][j][e] + (beta == 0.0f ? 0.0f : beta * *c);
+          T* c = Cm + gm * ldc + gn;
+          *c = alpha * acc[i][j][e] + (beta == T(0) ? T(0) : beta * *c);
         }
       }
 }
@@ -628,17 +682,19 @@ template <typename T, bool TA, bool TB>
 hipError_t gemm(hipStream_t s, const GemmWs& ws, int64_t M, int64_t N, int64_t K, T alpha, const T* A, int64_t lda,
                 const T* B, int64_t ldb, T beta, T* C, int64_t ldc) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  // the Krylov steps' FP32 products with C: the tall, skinny kernel
-  constexpr bool kTallType = sizeof(T) == 4 && !TA && !TB;
-  const bool tall = kTallType && N <= 64 && N % 4 == 0 && lda % 4 == 0 && ldb % 4 == 0 &&
-                    ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
+  // products with more than one 64-row tile and 16-byte aligned rows: the
+  // tall kernel
+  constexpr bool kTallType = !TB;
+  constexpr int64_t kW = 16 / (int64_t)sizeof(T);
+  const bool tall = kTallType && M > 64 && lda % kW == 0 && ldb % kW == 0 && ((uintptr_t)A & 15) == 0 &&
+                    ((uintptr_t)B & 15) == 0;
   const int64_t BMx = tall ? 128 : 64;
   const int64_t tiles = ((M + BMx - 1) / BMx) * ((N + 63) / 64);
   int64_t splits = 1;
   if (K >= 512) splits = std::min<int64_t>((512 + tiles - 1) / tiles, (K + 255) / 256);
   splits = std::min<int64_t>(splits, (int64_t)(ws.bytes / (sizeof(T) * (size_t)M * (size_t)N)));
   splits = std::max<int64_t>(1, std::min<int64_t>(splits, 65535));
-  int64_t kchunk = ((K + splits - 1) / splits + 31) / 32 * 32;
+  int64_t kchunk = ((K + splits - 1) / splits + 31) / 32 * 32;  // a multiple of every kernel's K step
   if (kchunk < 32) kchunk = 32;
   splits = std::max<int64_t>(1, (K + kchunk - 1) / kchunk);
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + BMx - 1) / BMx), (unsigned)splits);
@@ -656,9 +712,8 @@ hipError_t gemm(hipStream_t s, const GemmWs& ws, int64_t M, int64_t N, int64_t K
   }
   if constexpr (kTallType) {
     if (tall)
-      hipLaunchKernelGGL(gemm_tall_f32_kernel, grid, dim3(256), 0, s, M, (int)N, std::max<int64_t>(K, 0), kchunk,
-                         (float)alpha, (const float*)A, lda, (const float*)B, ldb, (float)beta, (float*)C, ldc,
-                         (float*)part);
+      hipLaunchKernelGGL((gemm_tall_kernel<T, TA>), grid, dim3(256), 0, s, M, N, std::max<int64_t>(K, 0), kchunk,
+                         alpha, A, lda, B, ldb, beta, C, ldc, part);
     else
       hipLaunchKernelGGL((gemm_kernel<T, TA, TB>), grid, dim3(256), 0, s, M, N, std::max<int64_t>(K, 0), kchunk, alpha,
                          A, lda, B, ldb, beta, C, ldc, part);

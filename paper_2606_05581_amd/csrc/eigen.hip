@@ -404,29 +404,51 @@ __global__ void __launch_bounds__(256) house_step_kernel(double* __restrict__ A,
 #pragma clang fp contract(off)
   __shared__ double vp[kProjMax], wp[kProjMax], vs[kProjMax];
   __shared__ double red[4];
+  constexpr int S = kProjMax / 256;  // entries per thread of a length-n vector
   const int m = n - k - 1;      // step k's block: rows and columns k+1..n-1
   const int mp = m + 1;         // step k-1's block: k..n-1
   const double bp = k > 0 ? betas[k - 1] : 0.0;
-  // step k-1's v and w over its block (index 0 is row k)
+  // every load of the prologue issued at once: row k (x = A[k][k+1..]), and
+  // step k-1's v and p over its block (index 0 is row k)
+  const double* rk = A + (size_t)k * n + (k + 1);
+  double xr[S], hv[S], pv[S];
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const int i = threadIdx.x + 256 * t;
+    xr[t] = i < m ? rk[i] : 0.0;
+    hv[t] = bp != 0.0 && i < mp ? (i == 0 ? 1.0 : H[(size_t)(k - 1) * n + k + i]) : 0.0;
+    pv[t] = bp != 0.0 && i < mp ? p_prev[i] : 0.0;
+  }
+  // step k-1's w = p - (beta p.v / 2) v
   if (bp != 0.0) {
     double sv = 0.0;
-    for (int i = threadIdx.x; i < mp; i += 256) {
-      const double v = i == 0 ? 1.0 : H[(size_t)(k - 1) * n + k + i];
-      vp[i] = v;
-      sv += p_prev[i] * v;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int i = threadIdx.x + 256 * t;
+      if (i < mp) {
+        vp[i] = hv[t];
+        sv += pv[t] * hv[t];
+      }
     }
     const double half = 0.5 * bp * block_sum256(sv, red);
-    for (int i = threadIdx.x; i < mp; i += 256) wp[i] = p_prev[i] - half * vp[i];
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int i = threadIdx.x + 256 * t;
+      if (i < mp) wp[i] = pv[t] - half * hv[t];
+    }
     __syncthreads();
   }
-  // row k after step k-1's update: x = A[k][k+1..], d[k] = A[k][k]
-  const double* rk = A + (size_t)k * n + (k + 1);
+  // row k after step k-1's update, d[k] = A[k][k]
   double s = 0.0;
-  for (int i = threadIdx.x; i < m; i += 256) {
-    double x = rk[i];
-    if (bp != 0.0) x -= vp[0] * wp[1 + i] + wp[0] * vp[1 + i];
-    vs[i] = x;
-    if (i >= 1) s += x * x;
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const int i = threadIdx.x + 256 * t;
+    if (i < m) {
+      double x = xr[t];
+      if (bp != 0.0) x -= vp[0] * wp[1 + i] + wp[0] * vp[1 + i];
+      vs[i] = x;
+      if (i >= 1) s += x * x;
+    }
   }
   const double sigma = block_sum256(s, red);  // (its barrier also publishes vs)
   const double x0 = vs[0];
@@ -451,18 +473,29 @@ __global__ void __launch_bounds__(256) house_step_kernel(double* __restrict__ A,
   }
   // rows of step k's block: step k-1's update, then p_k = beta A22 v
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int U = 8;  // row entries per lane loaded together
   for (int r = blockIdx.x * 4 + wave; r < m; r += gridDim.x * 4) {
     double* row = A + (size_t)(k + 1 + r) * n + (k + 1);
     double acc = 0.0;
-    if (bp != 0.0) {
-      const double vr = vp[1 + r], wr = wp[1 + r];
-      for (int c = lane; c < m; c += 64) {
-        const double a = row[c] - (vr * wp[1 + c] + wr * vp[1 + c]);
-        row[c] = a;
-        acc += a * vs[c];
+    const double vr = bp != 0.0 ? vp[1 + r] : 0.0, wr = bp != 0.0 ? wp[1 + r] : 0.0;
+    for (int c0 = 0; c0 < m; c0 += 64 * U) {
+      double a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + lane + 64 * u;
+        a[u] = c < m ? row[c] : 0.0;
       }
-    } else {
-      for (int c = lane; c < m; c += 64) acc += row[c] * vs[c];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + lane + 64 * u;
+        if (c < m) {
+          if (bp != 0.0) {
+            a[u] = a[u] - (vr * wp[1 + c] + wr * vp[1 + c]);
+            row[c] = a[u];
+          }
+          acc += a[u] * vs[c];
+        }
+      }
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) p_out[r] = beta * acc;
@@ -620,11 +653,15 @@ __global__ void symmetrise_kernel(double* A, int n) {
 // Y = H_0 H_1 ... H_{n-3} X: one wavefront per vector (X vector-major, vector
 // j at X[j n ..]; Y n x m row-major), the reflectors applied last first; the
 // vector lives in registers, entry r = lane + 64 t in slot t < T (n <= 64 T).
+// The reflectors are loaded C = 64 / T at a time (v zero outside its support
+// k+1 .. n-1, so the extra terms add exact zeros and the sums are those of the
+// support alone, in the same order): one memory latency per C reflectors.
 template <int T>
 __global__ void __launch_bounds__(256) house_back_kernel(const double* __restrict__ H,
                                                          const double* __restrict__ betas, int n, int m,
                                                          const double* __restrict__ X, double* __restrict__ Y) {
   static_assert(64 * T <= kProjMax, "at most kProjMax entries per vector");
+  constexpr int C = 64 / T;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (j >= m) return;
   double x[T];
@@ -633,22 +670,29 @@ __global__ void __launch_bounds__(256) house_back_kernel(const double* __restric
     const int r = lane + 64 * t;
     x[t] = r < n ? X[(size_t)j * n + r] : 0.0;
   }
-  for (int k = n - 3; k >= 0; --k) {
-    const double beta = betas[k];
-    if (beta == 0.0) continue;
-    const double* v = H + (size_t)k * n;  // v[k+1] = 1, v[k+2..n-1] stored
-    double s = 0.0;
+  for (int k = n - 3; k >= 0; k -= C) {
+    double v[C][T], beta[C];
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int r = lane + 64 * t;
-      if (r >= k + 1 && r < n) s += (r == k + 1 ? 1.0 : v[r]) * x[t];
+    for (int c = 0; c < C; ++c) {
+      const int kc = k - c;  // v[kc+1] = 1, v[kc+2..n-1] stored in row kc
+      beta[c] = kc >= 0 ? betas[kc] : 0.0;
+      const double* h = H + (size_t)(kc >= 0 ? kc : 0) * n;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int r = lane + 64 * t;
+        v[c][t] = kc >= 0 && r >= kc + 2 && r < n ? h[r] : (kc >= 0 && r == kc + 1 ? 1.0 : 0.0);
+      }
     }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    s *= beta;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int r = lane + 64 * t;
-      if (r >= k + 1 && r < n) x[t] -= (r == k + 1 ? 1.0 : v[r]) * s;
+    for (int c = 0; c < C; ++c) {
+      if (beta[c] == 0.0) continue;
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) s += v[c][t] * x[t];
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      s *= beta[c];
+#pragma unroll
+      for (int t = 0; t < T; ++t) x[t] -= v[c][t] * s;
     }
   }
 #pragma unroll

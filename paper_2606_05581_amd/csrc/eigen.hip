@@ -531,18 +531,23 @@ __global__ void house_tail2_kernel(const double* __restrict__ A, int n, const do
 // by bisection on the Sturm count (the negative pivots of the LDL^T
 // factorisation of T - x I; a pivot below pivmin in magnitude taken as
 // -pivmin) until the interval is at most atol wide; targets 0..m-1, and
-// target m is the largest (index n - 1). Eight lanes per target, three
-// levels per round: lane k (1..7) counts at heap node k's midpoint of the
-// next three levels (formed by the sequential loop's operations), then the
-// group follows the sequential bisection's path through them, stopping where
-// it would. So the result is the host's bisection's, with a third of the
-// dependent counts.
+// target m is the largest (index n - 1). 2^L lanes per target, L levels
+// per round: lane k (1 .. 2^L - 1) counts at heap node k's midpoint of the
+// next L levels (formed by the sequential loop's operations), then the group
+// follows the sequential bisection's path through them, stopping where it
+// would. So the result is the host's bisection's, with 1/L of the dependent
+// counts.
+constexpr int kBisectLevels = 6;  // a wavefront per eigenvalue
+
+template <int L>
 __global__ void __launch_bounds__(64) sturm_bisect_kernel(int n, const double* __restrict__ d,
                                                           const double* __restrict__ e2, int m, double glo, double ghi,
                                                           double atol, double pivmin, double* __restrict__ out) {
 #pragma clang fp contract(off)
-  const int lane = threadIdx.x & 63, sub = lane & 7, gbase = lane & ~7;
-  const int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
+  static_assert(L >= 1 && L <= 6, "a group within one wavefront");
+  constexpr int G = 1 << L;
+  const int lane = threadIdx.x & 63, sub = lane & (G - 1), gbase = lane & ~(G - 1);
+  const int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> L);
   const bool valid = t <= m;
   const int j = t < m ? t : n - 1;
   double lo = glo, hi = ghi;
@@ -573,7 +578,7 @@ __global__ void __launch_bounds__(64) sturm_bisect_kernel(int n, const double* _
     }
     const unsigned long long mask = __ballot(res);
     int node = 1;
-    for (int l = 0; l < 3 && it < 200 && hi - lo > atol; ++l, ++it) {
+    for (int l = 0; l < L && it < 200 && hi - lo > atol; ++l, ++it) {
       const double mid = 0.5 * (lo + hi);
       const int bit = (int)((mask >> (gbase + node)) & 1ull);
       if (bit)
@@ -984,11 +989,12 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
         EIG_TRY(hipMemcpyAsync(td.data(), dD.p, (size_t)cur * 8, hipMemcpyDeviceToHost, s));
         EIG_TRY(hipMemcpyAsync(te.data(), dE.p, (size_t)cur * 8, hipMemcpyDeviceToHost, s));
         EIG_TRY(hipStreamSynchronize(s));
-        // the kk smallest eigenvalues and the largest: bisection, one thread each
+        // the kk smallest eigenvalues and the largest: bisection, a wavefront each
         double glo, ghi, pivmin, atol;
         bisect_setup(cur, td, te, e2, glo, ghi, pivmin, atol);
         EIG_TRY(hipMemcpyAsync(dP.p, e2.data(), e2.size() * 8, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(sturm_bisect_kernel, dim3((8 * (kk + 1) + 63) / 64), dim3(64), 0, s, cur,
+        hipLaunchKernelGGL(sturm_bisect_kernel<kBisectLevels>, dim3((((kk + 1) << kBisectLevels) + 63) / 64), dim3(64),
+                           0, s, cur,
                            (const double*)dD.as<double>(), (const double*)dP.as<double>(), kk, glo, ghi, atol, pivmin,
                            dEv.as<double>());
         EIG_TRY(hipGetLastError());

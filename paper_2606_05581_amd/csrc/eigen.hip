@@ -781,6 +781,15 @@ hipError_t gemm(hipStream_t s, const GemmWs& ws, int64_t M, int64_t N, int64_t K
   return e;
 }
 
+// Page-locked host memory: copies from and to it are queued without a
+// staging pass, so the launch that follows a small upload is not held back.
+struct PinBuf {
+  void* p = nullptr;
+  ~PinBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
 struct DevBuf {
   void* p = nullptr;
   ~DevBuf() {
@@ -901,6 +910,10 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
     EIG_TRY(hipMalloc(&dPart.p, (size_t)256 * keep_n * 8));
     EIG_TRY(hipMalloc(&dRes.p, (size_t)keep_n * 8));
     EIG_TRY(hipMalloc(&dPick.p, (size_t)b * 4));
+    PinBuf hGram;  // the b x b Gram matrix down, R^-1 up
+    EIG_TRY(hipHostMalloc(&hGram.p, (size_t)2 * b * b * 8, hipHostMallocDefault));
+    double* const pinG = (double*)hGram.p;
+    double* const pinRi = pinG + (size_t)b * b;
     double* Q = dQ.as<double>();
     double* Wm = dW.as<double>();
     double* X = dX.as<double>();
@@ -916,11 +929,13 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
           EIG_TRY((gemm<double, false, false>(s, ws, n, b, cur, -1.0, Q, cap, dG.as<double>(), b, 1.0, X, b)));
         }
         EIG_TRY((gemm<double, true, false>(s, ws, b, b, n, 1.0, X, b, X, b, 0.0, dT.as<double>(), b)));
-        EIG_TRY(hipMemcpyAsync(G.data(), dT.p, (size_t)b * b * 8, hipMemcpyDeviceToHost, s));
-        EIG_TRY(hipStreamSynchronize(s));
+        EIG_TRY(hipMemcpyAsync(pinG, dT.p, (size_t)b * b * 8, hipMemcpyDeviceToHost, s));
+        EIG_TRY(hipStreamSynchronize(s));  // (also ends the previous upload from pinRi)
+        std::copy(pinG, pinG + (size_t)b * b, G.begin());
         if (!cholesky_upper(b, G, R, 1e-24)) return 0;
         upper_inverse(b, R, Ri);
-        EIG_TRY(hipMemcpyAsync(dT.p, Ri.data(), (size_t)b * b * 8, hipMemcpyHostToDevice, s));
+        std::copy(Ri.begin(), Ri.begin() + (size_t)b * b, pinRi);
+        EIG_TRY(hipMemcpyAsync(dT.p, pinRi, (size_t)b * b * 8, hipMemcpyHostToDevice, s));
         // X = X R^-1 (through a temporary: dQ2's first n*b entries)
         EIG_TRY((gemm<double, false, false>(s, ws, n, b, b, 1.0, X, b, dT.as<double>(), b, 0.0, dQ2.as<double>(), b)));
         EIG_TRY(hipMemcpyAsync(X, dQ2.p, (size_t)n * b * 8, hipMemcpyDeviceToDevice, s));

@@ -395,7 +395,7 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
 // own block while it computes p_k from them. Row k, the only row of step
 // k - 1's block that step k reads beyond its own, is updated on the fly, not
 // in memory (rows and columns <= k are not read again); the last update, of
-// the final 2 x 2 block, is left to house_tail2_kernel. Contraction is off,
+// the final 2 x 2 block, is left to house_tail_kernel. Contraction is off,
 // so entries (r, c) and (c, r) of an update get the same bits.
 __global__ void __launch_bounds__(256) house_step_kernel(double* __restrict__ A, int n, int k, double* __restrict__ H,
                                                          double* __restrict__ betas, double* __restrict__ d,
@@ -502,29 +502,138 @@ __global__ void __launch_bounds__(256) house_step_kernel(double* __restrict__ A,
   }
 }
 
-// After the last step (k = n - 3): its update of the final 2 x 2 block, and
-// that block's entries.
-__global__ void house_tail2_kernel(const double* __restrict__ A, int n, const double* __restrict__ H,
-                                   const double* __restrict__ betas, const double* __restrict__ p, double* d,
-                                   double* e) {
+// The last steps in one launch: steps k0 .. n-3 and step n-3's update of the
+// final 2 x 2 block with that block's entries, by a single workgroup of 1024 threads
+// holding step k0 - 1's block (rows and columns k0..n-1, n - k0 <= kTailMax + 1)
+// in LDS, a barrier between steps instead of a kernel boundary. The vector
+// work runs on the first 256 threads with house_step_kernel's sums in its
+// order, and each row's product is reduced within one wavefront as there, so
+// the results are the per-step launches' bit for bit.
+constexpr int kTailMax = 84;  // (85^2 + 6 * 85) doubles: under 64 KB of LDS
+
+// block_sum256 over the first 256 threads of a larger workgroup (every
+// thread takes part in the barriers and receives the sum).
+__device__ __forceinline__ double first256_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0 && threadIdx.x < 256) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void __launch_bounds__(1024) house_tail_kernel(const double* __restrict__ A, int n, int k0,
+                                                          double* __restrict__ H, double* __restrict__ betas,
+                                                          double* __restrict__ d, double* __restrict__ e,
+                                                          const double* __restrict__ p_in) {
 #pragma clang fp contract(off)
-  if (threadIdx.x != 0) return;
-  const int k = n - 3;
-  double a00 = A[(size_t)(n - 2) * n + (n - 2)], a11 = A[(size_t)(n - 1) * n + (n - 1)];
-  double a10 = A[(size_t)(n - 1) * n + (n - 2)];
-  const double b = k >= 0 ? betas[k] : 0.0;
-  if (b != 0.0) {
-    const double v0 = 1.0, v1 = H[(size_t)k * n + k + 2];
-    const double half = 0.5 * b * (p[0] * v0 + p[1] * v1);
-    const double w0 = p[0] - half * v0, w1 = p[1] - half * v1;
-    a00 -= v0 * w0 + w0 * v0;
-    a11 -= v1 * w1 + w1 * v1;
-    a10 -= v1 * w0 + w1 * v0;
+  constexpr int TB = kTailMax + 1;
+  __shared__ double As[TB * TB];
+  __shared__ double vq[TB], pq[TB];  // step k-1's v and p over its block (index 0 is row k)
+  __shared__ double vp[TB], wp[TB], vs[TB], pc[TB];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int mb = n - k0;  // rows and columns k0..n-1
+  for (int i = tid; i < mb * mb; i += 1024) As[i] = A[(size_t)(k0 + i / mb) * n + k0 + i % mb];
+  double bp = k0 > 0 ? betas[k0 - 1] : 0.0;
+  for (int i = tid; i < mb; i += 1024) {
+    vq[i] = bp != 0.0 ? (i == 0 ? 1.0 : H[(size_t)(k0 - 1) * n + k0 + i]) : 0.0;
+    pq[i] = bp != 0.0 ? p_in[i] : 0.0;
   }
-  d[n - 2] = a00;
-  d[n - 1] = a11;
-  e[n - 2] = a10;
-  e[n - 1] = 0.0;
+  __syncthreads();
+  double beta = 0.0;
+  int k = k0;
+  for (; k + 2 < n; ++k) {
+    const int m = n - k - 1, mp = m + 1, o = k - k0;  // o: row / column k in As
+    // step k-1's w = p - (beta p.v / 2) v (one entry per thread, i = tid)
+    if (bp != 0.0) {
+      double sv = 0.0;
+      if (tid < mp) {
+        vp[tid] = vq[tid];
+        sv += pq[tid] * vq[tid];
+      }
+      const double half = 0.5 * bp * first256_sum(sv, red);
+      if (tid < mp) wp[tid] = pq[tid] - half * vq[tid];
+      __syncthreads();
+    }
+    // row k after step k-1's update
+    double s = 0.0;
+    if (tid < m) {
+      double x = As[o * mb + o + 1 + tid];
+      if (bp != 0.0) x -= vp[0] * wp[1 + tid] + wp[0] * vp[1 + tid];
+      vs[tid] = x;
+      if (tid >= 1) s += x * x;
+    }
+    const double sigma = first256_sum(s, red);
+    const double x0 = vs[0];
+    double mu = x0, v0 = 1.0;
+    beta = 0.0;
+    if (sigma != 0.0) {
+      mu = sqrt(x0 * x0 + sigma);
+      v0 = x0 <= 0.0 ? x0 - mu : -sigma / (x0 + mu);
+      beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
+    }
+    __syncthreads();  // every thread has read vs[0]
+    if (tid < m) vs[tid] = tid == 0 ? 1.0 : (sigma != 0.0 ? vs[tid] / v0 : 0.0);
+    __syncthreads();
+    if (tid == 0) {
+      double akk = As[o * mb + o];
+      if (bp != 0.0) akk -= vp[0] * wp[0] + wp[0] * vp[0];
+      betas[k] = beta;
+      d[k] = akk;
+      e[k] = mu;
+    }
+    if (tid >= 1 && tid < m) H[(size_t)k * n + k + 1 + tid] = vs[tid];
+    // rows of step k's block: step k-1's update, then p_k = beta A22 v
+    for (int r = wave; r < m; r += 16) {
+      double* row = As + (o + 1 + r) * mb + (o + 1);
+      double acc = 0.0;
+      const double vr = bp != 0.0 ? vp[1 + r] : 0.0, wr = bp != 0.0 ? wp[1 + r] : 0.0;
+      double a[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int c = lane + 64 * u;
+        a[u] = c < m ? row[c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int c = lane + 64 * u;
+        if (c < m) {
+          if (bp != 0.0) {
+            a[u] = a[u] - (vr * wp[1 + c] + wr * vp[1 + c]);
+            row[c] = a[u];
+          }
+          acc += a[u] * vs[c];
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if (lane == 0) pc[r] = beta * acc;
+    }
+    __syncthreads();
+    if (tid < m) {
+      vq[tid] = vs[tid];
+      pq[tid] = pc[tid];
+    }
+    bp = beta;
+    __syncthreads();
+  }
+  // step n-3's update of the final 2 x 2 block, and that block's entries
+  if (tid == 0) {
+    const int o = n - 2 - k0;
+    double a00 = As[o * mb + o], a11 = As[(o + 1) * mb + o + 1];
+    double a10 = As[(o + 1) * mb + o];
+    if (bp != 0.0) {
+      const double v0 = 1.0, v1 = vq[1];
+      const double half = 0.5 * bp * (pq[0] * v0 + pq[1] * v1);
+      const double w0 = pq[0] - half * v0, w1 = pq[1] - half * v1;
+      a00 -= v0 * w0 + w0 * v0;
+      a11 -= v1 * w1 + w1 * v1;
+      a10 -= v1 * w0 + w1 * v0;
+    }
+    d[n - 2] = a00;
+    d[n - 1] = a11;
+    e[n - 2] = a10;
+    e[n - 1] = 0.0;
+  }
 }
 
 // Eigenvalue number j (ascending) of the symmetric tridiagonal (d, e2 = e^2)
@@ -990,15 +1099,17 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
         double* A = dT.as<double>();
         hipLaunchKernelGGL(symmetrise_kernel, dim3(blocks_for((int64_t)cur * cur)), dim3(256), 0, s, A, cur);
         double* pb[2] = {dP.as<double>(), dP.as<double>() + cap};  // p_{k-1} and p_k, alternating
-        for (int kx = 0; kx + 2 < cur; ++kx) {
+        // a launch per step while step kx's block is larger than kTailMax,
+        // then the rest in one launch from LDS
+        int kx = 0;
+        for (; kx + 2 < cur && cur - kx - 1 > kTailMax; ++kx) {
           const int g = std::min(256, (cur - kx - 1 + 3) / 4);
           hipLaunchKernelGGL(house_step_kernel, dim3(g), dim3(256), 0, s, A, cur, kx, dH.as<double>(),
                              dBeta.as<double>(), dD.as<double>(), dE.as<double>(), (const double*)pb[(kx + 1) & 1],
                              pb[kx & 1]);
         }
-        hipLaunchKernelGGL(house_tail2_kernel, dim3(1), dim3(64), 0, s, (const double*)A, cur,
-                           (const double*)dH.as<double>(), (const double*)dBeta.as<double>(),
-                           (const double*)pb[(cur - 3) & 1], dD.as<double>(), dE.as<double>());
+        hipLaunchKernelGGL(house_tail_kernel, dim3(1), dim3(1024), 0, s, (const double*)A, cur, kx, dH.as<double>(),
+                           dBeta.as<double>(), dD.as<double>(), dE.as<double>(), (const double*)pb[(kx + 1) & 1]);
         EIG_TRY(hipGetLastError());
         std::vector<double> td(cur), te(cur), e2, Xc;
         EIG_TRY(hipMemcpyAsync(td.data(), dD.p, (size_t)cur * 8, hipMemcpyDeviceToHost, s));

@@ -831,7 +831,58 @@ struct GemmWs {
     int fp32;
     double flops;
   };
-  std::vector<Mark>* marks = nullptr;
+  // Per-product timings: marks still in flight, events free for reuse and the
+  // sums over the marks already read. A mark is read as soon as its end event
+  // has completed and its events are reused, because creating an event is a
+  // driver call that takes longer than a short product, and the device would
+  // wait for it.
+  struct Timing {
+    std::vector<Mark> live;
+    std::vector<hipEvent_t> spare;
+    EigGemmTimes sum;
+    hipError_t take(hipEvent_t& ev) {
+      if (!spare.empty()) {
+        ev = spare.back();
+        spare.pop_back();
+        return hipSuccess;
+      }
+      return hipEventCreate(&ev);
+    }
+    // read the completed marks, in order (all of them once the stream is idle)
+    hipError_t harvest() {
+      size_t i = 0;
+      for (; i < live.size(); ++i) {
+        const Mark& m = live[i];
+        const hipError_t q = hipEventQuery(m.b);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) return q;
+        float g = 0;
+        const hipError_t e = hipEventElapsedTime(&g, m.a, m.b);
+        if (e != hipSuccess) return e;
+        if (m.fp32) {
+          ++sum.fp32_products;
+          sum.fp32_ms += g;
+          sum.fp32_flops += m.flops;
+        } else {
+          ++sum.fp64_products;
+          sum.fp64_ms += g;
+          sum.fp64_flops += m.flops;
+        }
+        spare.push_back(m.a);
+        spare.push_back(m.b);
+      }
+      live.erase(live.begin(), live.begin() + i);
+      return hipSuccess;
+    }
+    ~Timing() {
+      for (auto& m : live) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+      }
+      for (auto& ev : spare) (void)hipEventDestroy(ev);
+    }
+  };
+  Timing* timing = nullptr;
 };
 
 // Splits the K range over enough slices for about 512 workgroups (two per
@@ -858,14 +909,15 @@ hipError_t gemm(hipStream_t s, const GemmWs& ws, int64_t M, int64_t N, int64_t K
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + BMx - 1) / BMx), (unsigned)splits);
   T* part = splits > 1 ? (T*)ws.p : nullptr;
   GemmWs::Mark mk{nullptr, nullptr, sizeof(T) == 4 ? 1 : 0, 2.0 * (double)M * (double)N * (double)K};
-  if (ws.marks) {
+  if (ws.timing) {
     hipError_t e;
-    if ((e = hipEventCreate(&mk.a)) != hipSuccess) return e;
-    if ((e = hipEventCreate(&mk.b)) != hipSuccess) {
-      (void)hipEventDestroy(mk.a);
+    if ((e = ws.timing->harvest()) != hipSuccess) return e;
+    if ((e = ws.timing->take(mk.a)) != hipSuccess) return e;
+    if ((e = ws.timing->take(mk.b)) != hipSuccess) {
+      ws.timing->spare.push_back(mk.a);
       return e;
     }
-    ws.marks->push_back(mk);
+    ws.timing->live.push_back(mk);
     if ((e = hipEventRecord(mk.a, s)) != hipSuccess) return e;
   }
   if constexpr (kTallType) {
@@ -886,7 +938,7 @@ hipError_t gemm(hipStream_t s, const GemmWs& ws, int64_t M, int64_t N, int64_t K
                        (int)splits, alpha, part, beta, C, ldc);
   }
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess && ws.marks) e = hipEventRecord(mk.b, s);
+  if (e == hipSuccess && ws.timing) e = hipEventRecord(mk.b, s);
   return e;
 }
 
@@ -951,16 +1003,8 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
   ws.bytes = (size_t)32 << 20;
   EIG_TRY(hipMalloc(&dWs.p, ws.bytes));
   ws.p = dWs.p;
-  struct Marks {
-    std::vector<GemmWs::Mark> v;
-    ~Marks() {
-      for (auto& m : v) {
-        (void)hipEventDestroy(m.a);
-        (void)hipEventDestroy(m.b);
-      }
-    }
-  } marks;
-  if (gt) ws.marks = &marks.v;
+  GemmWs::Timing timing;
+  if (gt) ws.timing = &timing;
   EIG_TRY(hipMemcpyAsync(dkeep.p, keep.data(), n * 4, hipMemcpyHostToDevice, s));
   EIG_TRY(hipMemcpyAsync(dm.p, m.data(), n * 8, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(assemble_c_kernel, dim3(blocks_for(n * n)), dim3(256), 0, s, dS, n_rows, dkeep.as<int32_t>(),
@@ -1271,20 +1315,12 @@ int steklov_modes_device(hipStream_t s, const double* dS, int64_t n_rows, const 
   EIG_TRY(hipEventElapsedTime(&f, e0, e1));
   *ms_out = f;
   if (gt) {
-    *gt = EigGemmTimes{};
-    for (const auto& m : marks.v) {
-      float g = 0;
-      EIG_TRY(hipEventElapsedTime(&g, m.a, m.b));
-      if (m.fp32) {
-        ++gt->fp32_products;
-        gt->fp32_ms += g;
-        gt->fp32_flops += m.flops;
-      } else {
-        ++gt->fp64_products;
-        gt->fp64_ms += g;
-        gt->fp64_flops += m.flops;
-      }
+    EIG_TRY(timing.harvest());  // the stream is idle: every mark is read
+    if (!timing.live.empty()) {
+      err = "product timing events still pending after the stream finished";
+      return 4;
     }
+    *gt = timing.sum;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
